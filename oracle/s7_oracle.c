@@ -1,0 +1,269 @@
+/*
+ * FP64 CPU oracle for BiCGStab on the 7-point variable-coefficient stencil
+ * system.  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU
+ * baseline of the benchmark call it; the GPU library never does, and the two
+ * share no code.
+ *
+ * What it computes (paper: "Fast Stencil-Code Computation on a Wafer-Scale
+ * Processor", SC20):
+ *   - the linear system A x = b of Eq. (1), section III;
+ *   - A is the 7-point stencil operator on an X x Y x Z mesh (section IV,
+ *     "SpMV (3D)"): row (i,j,k) has the main diagonal and the six
+ *     direction-named off-diagonals xm, xp, ym, yp, zm, zp, where xp
+ *     multiplies the value at (i+1,j,k) and xm the value at (i-1,j,k), and
+ *     likewise in y and z.  Neighbours outside the mesh are zero (Dirichlet);
+ *     their coefficients are not entered in the matrix;
+ *   - optional diagonal (Jacobi) preconditioning, which the paper applies so
+ *     that the main diagonal becomes all ones (section IV, first
+ *     paragraph): row i and b_i are divided by a_ii;
+ *   - the "Standard BiCGStab" iteration of Algorithm 1, with the readings
+ *     listed below, in FP64 with plain left-to-right loops.
+ *
+ * Readings of Algorithm 1 (the paper is silent or garbled on these):
+ *   - r_0 = b - A x_0 (the listing writes r_0 := b, i.e. x_0 = 0);
+ *   - the shadow vector r_hat = r_0 is fixed for the whole solve;
+ *   - the solution update writes x_{i+1} (the listing overwrites x_i);
+ *   - stopping: after the q-step, if ||q||/||b|| <= tol then x += alpha p
+ *     and stop ("half-step" exit); after the full step, stop if
+ *     ||r_{i+1}||/||b|| <= tol, or when max_iter full iterations are done;
+ *   - breakdown: (r_hat, s) == 0, (y, y) == 0 or (r_hat, r_{i+1}) == 0
+ *     exactly, or a non-finite scalar.
+ * The CSR uses ascending column order; all sums run left to right.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_NOT_CONVERGED 1
+#define OR_BREAKDOWN 2
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+
+#define OR_REASON_NONE 0
+#define OR_REASON_RHO_ZERO 1
+#define OR_REASON_RS_ZERO 2
+#define OR_REASON_YY_ZERO 3
+#define OR_REASON_NONFINITE 4
+
+typedef struct {
+    double rho;     /* (r_hat, r_i) */
+    double alpha;
+    double omega;
+    double beta;
+    double sigma;   /* (r_hat, s_i) */
+    double nb;      /* ||b|| */
+    double tol;
+    double res_rec; /* last recurrence residual ||r||/||b|| (or ||q||/||b|| at a half-step exit) */
+    int64_t iter;   /* full iterations done (a half-step exit counts as one) */
+    int64_t max_iter;
+    int32_t status;
+    int32_t reason;
+    int32_t done;
+    int32_t half_exit;
+} oracle_bicg;
+
+/* Number of stored entries of the CSR of the nx x ny x nz stencil. */
+int64_t oracle_csr_nnz(int32_t nx, int32_t ny, int32_t nz) {
+    int64_t n = (int64_t)nx * ny * nz;
+    int64_t nnz = n;                          /* diagonal */
+    nnz += 2 * (int64_t)(nx - 1) * ny * nz;   /* x links */
+    nnz += 2 * (int64_t)nx * (ny - 1) * nz;   /* y links */
+    nnz += 2 * (int64_t)nx * ny * (nz - 1);   /* z links */
+    return nnz;
+}
+
+/*
+ * Assemble the CSR of A from the seven coefficient arrays
+ * (diag, xm, xp, ym, yp, zm, zp; each nx*ny*nz floats, x fastest).
+ * Values are the FP32 inputs widened exactly to FP64.
+ */
+int64_t oracle_build_csr(int32_t nx, int32_t ny, int32_t nz,
+                         const float *diag, const float *xm, const float *xp,
+                         const float *ym, const float *yp,
+                         const float *zm, const float *zp,
+                         int64_t *rowptr, int64_t *col, double *val) {
+    const int64_t sx = 1, sy = nx, sz = (int64_t)nx * ny;
+    int64_t e = 0;
+    rowptr[0] = 0;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                int64_t c = i + nx * (j + ny * k);
+                /* ascending column order: z-, y-, x-, centre, x+, y+, z+ */
+                if (k > 0)      { col[e] = c - sz; val[e] = (double)zm[c]; ++e; }
+                if (j > 0)      { col[e] = c - sy; val[e] = (double)ym[c]; ++e; }
+                if (i > 0)      { col[e] = c - sx; val[e] = (double)xm[c]; ++e; }
+                col[e] = c; val[e] = (double)diag[c]; ++e;
+                if (i < nx - 1) { col[e] = c + sx; val[e] = (double)xp[c]; ++e; }
+                if (j < ny - 1) { col[e] = c + sy; val[e] = (double)yp[c]; ++e; }
+                if (k < nz - 1) { col[e] = c + sz; val[e] = (double)zp[c]; ++e; }
+                rowptr[c + 1] = e;
+            }
+    return e;
+}
+
+/* y = A x, each row summed left to right over its entries. */
+void oracle_spmv(int64_t n, const int64_t *rowptr, const int64_t *col,
+                 const double *val, const double *x, double *y) {
+    for (int64_t r = 0; r < n; ++r) {
+        double acc = 0.0;
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) acc += val[e] * x[col[e]];
+        y[r] = acc;
+    }
+}
+
+/* Rows [r0, r1) only: y[r - r0] = (A x)_r. */
+void oracle_spmv_rows(int64_t r0, int64_t r1, const int64_t *rowptr, const int64_t *col,
+                      const double *val, const double *x, double *y) {
+    for (int64_t r = r0; r < r1; ++r) {
+        double acc = 0.0;
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) acc += val[e] * x[col[e]];
+        y[r - r0] = acc;
+    }
+}
+
+double oracle_dot(int64_t n, const double *a, const double *b) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc += a[i] * b[i];
+    return acc;
+}
+
+/* Left diagonal scaling: row r of A and b_r divided by a_rr.  Returns -1 if a_rr == 0. */
+int oracle_jacobi_scale(int64_t n, const int64_t *rowptr, const int64_t *col,
+                        double *val, double *b) {
+    for (int64_t r = 0; r < n; ++r) {
+        double d = 0.0;
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+            if (col[e] == r) d = val[e];
+        if (d == 0.0) return -1;
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) val[e] = val[e] / d;
+        if (b) b[r] = b[r] / d;
+    }
+    return 0;
+}
+
+/*
+ * Start of Algorithm 1: r = b - A x0, r_hat = r, p = r, rho = (r_hat, r),
+ * nb = ||b||.  Decides the trivial exits (b = 0, already converged,
+ * max_iter = 0).
+ */
+int oracle_bicgstab_init(int64_t n, const int64_t *rowptr, const int64_t *col,
+                         const double *val, const double *b, double *x,
+                         double *r, double *rhat, double *p, double tol,
+                         int64_t max_iter, oracle_bicg *st) {
+    memset(st, 0, sizeof(*st));
+    st->tol = tol;
+    st->max_iter = max_iter;
+    st->nb = sqrt(oracle_dot(n, b, b));
+    if (st->nb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; r[i] = 0.0; rhat[i] = 0.0; p[i] = 0.0; }
+        st->status = OR_OK;
+        st->done = 1;
+        return st->status;
+    }
+    oracle_spmv(n, rowptr, col, val, x, r);
+    for (int64_t i = 0; i < n; ++i) {
+        r[i] = b[i] - r[i];
+        rhat[i] = r[i];
+        p[i] = r[i];
+    }
+    st->rho = oracle_dot(n, rhat, r);
+    st->res_rec = sqrt(oracle_dot(n, r, r)) / st->nb;
+    if (!isfinite(st->res_rec)) {
+        st->status = OR_BREAKDOWN; st->reason = OR_REASON_NONFINITE; st->done = 1;
+    } else if (st->res_rec <= tol) {
+        st->status = OR_OK; st->done = 1;
+    } else if (max_iter <= 0) {
+        st->status = OR_NOT_CONVERGED; st->done = 1;
+    }
+    return st->status;
+}
+
+static void set_breakdown(oracle_bicg *st, int32_t reason) {
+    st->status = OR_BREAKDOWN;
+    st->reason = reason;
+    st->done = 1;
+}
+
+/* One iteration of Algorithm 1 (s, alpha, q, y, omega, x, r, beta, p). */
+int oracle_bicgstab_step(int64_t n, const int64_t *rowptr, const int64_t *col,
+                         const double *val, double *x, double *r, const double *rhat,
+                         double *p, double *s, double *q, double *y, oracle_bicg *st) {
+    if (st->done) return st->status;
+    /* s_i = A p_i ; alpha_i = (r0, r_i) / (r0, s_i) */
+    oracle_spmv(n, rowptr, col, val, p, s);
+    st->sigma = oracle_dot(n, rhat, s);
+    if (st->sigma == 0.0) { set_breakdown(st, OR_REASON_RS_ZERO); return st->status; }
+    st->alpha = st->rho / st->sigma;
+    if (!isfinite(st->alpha)) { set_breakdown(st, OR_REASON_NONFINITE); return st->status; }
+    /* q_i = r_i - alpha_i s_i */
+    for (int64_t i = 0; i < n; ++i) q[i] = r[i] - st->alpha * s[i];
+    double qn = sqrt(oracle_dot(n, q, q)) / st->nb;
+    if (qn <= st->tol) {
+        /* half-step exit: x_{i+1} = x_i + alpha_i p_i, residual is q_i */
+        for (int64_t i = 0; i < n; ++i) { x[i] = x[i] + st->alpha * p[i]; r[i] = q[i]; }
+        st->omega = 0.0;
+        st->iter += 1;
+        st->res_rec = qn;
+        st->half_exit = 1;
+        st->status = OR_OK;
+        st->done = 1;
+        return st->status;
+    }
+    /* y_i = A q_i ; omega_i = (q_i, y_i) / (y_i, y_i) */
+    oracle_spmv(n, rowptr, col, val, q, y);
+    double yy = oracle_dot(n, y, y);
+    if (yy == 0.0) { set_breakdown(st, OR_REASON_YY_ZERO); return st->status; }
+    st->omega = oracle_dot(n, q, y) / yy;
+    if (!isfinite(st->omega)) { set_breakdown(st, OR_REASON_NONFINITE); return st->status; }
+    /* x_{i+1} = x_i + alpha_i p_i + omega_i q_i ; r_{i+1} = q_i - omega_i y_i */
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = x[i] + st->alpha * p[i] + st->omega * q[i];
+        r[i] = q[i] - st->omega * y[i];
+    }
+    st->iter += 1;
+    double rho_new = oracle_dot(n, rhat, r);
+    st->res_rec = sqrt(oracle_dot(n, r, r)) / st->nb;
+    if (!isfinite(st->res_rec)) { set_breakdown(st, OR_REASON_NONFINITE); return st->status; }
+    if (st->res_rec <= st->tol) { st->status = OR_OK; st->done = 1; st->rho = rho_new; return st->status; }
+    if (st->iter >= st->max_iter) { st->status = OR_NOT_CONVERGED; st->done = 1; st->rho = rho_new; return st->status; }
+    if (rho_new == 0.0) { set_breakdown(st, OR_REASON_RHO_ZERO); return st->status; }
+    /* beta_i = (alpha_i / omega_i) (r0, r_{i+1}) / (r0, r_i) ; p_{i+1} = r_{i+1} + beta_i (p_i - omega_i s_i) */
+    st->beta = (st->alpha / st->omega) * (rho_new / st->rho);
+    if (!isfinite(st->beta)) { set_breakdown(st, OR_REASON_NONFINITE); return st->status; }
+    for (int64_t i = 0; i < n; ++i) p[i] = r[i] + st->beta * (p[i] - st->omega * s[i]);
+    st->rho = rho_new;
+    return st->status;
+}
+
+/*
+ * Whole solve.  x holds x0 on entry and the last iterate on exit.  If
+ * ntrace > 0, alpha/omega/rho (rho = (r0, r_i) at the start of iteration i)
+ * and the recurrence residual after each iteration are recorded for the
+ * first ntrace iterations.
+ */
+int oracle_bicgstab(int64_t n, const int64_t *rowptr, const int64_t *col,
+                    const double *val, const double *b, double *x, double tol,
+                    int64_t max_iter, oracle_bicg *st, int64_t ntrace,
+                    double *tr_rho, double *tr_alpha, double *tr_omega, double *tr_res) {
+    double *buf = (double *)malloc(sizeof(double) * (size_t)n * 6);
+    if (!buf) return OR_ENOMEM;
+    double *r = buf, *rhat = buf + n, *p = buf + 2 * n, *s = buf + 3 * n,
+           *q = buf + 4 * n, *y = buf + 5 * n;
+    oracle_bicgstab_init(n, rowptr, col, val, b, x, r, rhat, p, tol, max_iter, st);
+    while (!st->done) {
+        int64_t it = st->iter;
+        double rho = st->rho;
+        oracle_bicgstab_step(n, rowptr, col, val, x, r, rhat, p, s, q, y, st);
+        if (it < ntrace) {
+            if (tr_rho) tr_rho[it] = rho;
+            if (tr_alpha) tr_alpha[it] = st->alpha;
+            if (tr_omega) tr_omega[it] = st->omega;
+            if (tr_res) tr_res[it] = st->res_rec;
+        }
+    }
+    free(buf);
+    return st->status;
+}
