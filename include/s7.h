@@ -1,0 +1,234 @@
+/*
+ * s7: BiCGStab for 7-point variable-coefficient stencil systems on MI355X.
+ *
+ * C ABI of libs7.so.  Plain pointers and sizes only.
+ *
+ * The problem (paper: "Fast Stencil-Code Computation on a Wafer-Scale
+ * Processor", SC20).  Eq. (1), section III: solve A x = b.  A is the 7-point
+ * finite-difference operator on an nx x ny x nz structured mesh (section IV,
+ * "SpMV (3D)").  Each row has a main diagonal and six off-diagonals named by
+ * direction and sign, as the paper names its coefficient vectors:
+ *
+ *   (A v)(i,j,k) = diag v(i,j,k)
+ *                + xm v(i-1,j,k) + xp v(i+1,j,k)
+ *                + ym v(i,j-1,k) + yp v(i,j+1,k)
+ *                + zm v(i,j,k-1) + zp v(i,j,k+1).
+ *
+ * Values outside the mesh are zero (Dirichlet ghosts).  The coefficients of
+ * those outward links are ignored, whatever their values.
+ *
+ * Layout.  Every per-cell array is [nz][ny][nx], x fastest: cell (i,j,k) is
+ * element i + nx*(j + ny*k).  Coefficients come as seven arrays in the order
+ * {diag, xm, xp, ym, yp, zm, zp}.  N = nx*ny*nz must be below 2^31.
+ *
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller, for
+ * example a PyTorch tensor.  The library allocates no device memory of its
+ * own.  Scratch comes from a caller-provided workspace of the size that
+ * s7_workspace_bytes() reports, 256-byte aligned.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void*; 0 means the null
+ * stream.  s7_stencil_apply is asynchronous on it.  The solvers are
+ * synchronous: they return when the result is in x.
+ *
+ * Errors.  Every function returns an s7_status.  No function aborts or
+ * throws across the ABI.  s7_last_error() gives a message for the calling
+ * thread's last failure.
+ */
+#ifndef S7_H
+#define S7_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t nx, ny, nz;
+} s7_dims;
+
+enum s7_status {
+    S7_OK = 0,
+    S7_NOT_CONVERGED = 1, /* iteration cap reached; x holds the last iterate */
+    S7_BREAKDOWN = 2,     /* see s7_info.reason; x holds the last iterate */
+    S7_EINVAL = -1,       /* null pointer, dim < 1, N >= 2^31, rtol <= 0 or NaN,
+                             max_iter < 0, workspace too small or misaligned */
+    S7_ENOMEM = -2,       /* request larger than the whole queue arena */
+    S7_EHIP = -3,         /* HIP runtime error (message in s7_last_error) */
+    S7_EAGAIN = -4,       /* poll: not finished yet; submit: queue full */
+    S7_ENOTFOUND = -5     /* unknown ticket */
+};
+
+/* Breakdown reasons.  Each test is exact, with no threshold. */
+enum s7_reason {
+    S7_REASON_NONE = 0,
+    S7_REASON_RHO_ZERO = 1, /* (r0, r_{i+1}) == 0 */
+    S7_REASON_RS_ZERO = 2,  /* (r0, s_i) == 0 */
+    S7_REASON_YY_ZERO = 3,  /* (y_i, y_i) == 0 */
+    S7_REASON_NONFINITE = 4 /* a scalar became Inf or NaN */
+};
+
+/*
+ * Precision of the inner iteration.
+ * S7_FP32: coefficients and Krylov vectors are stored and computed in FP32.
+ *   Inner products accumulate FP32 products in FP64.  b and x are FP64 at
+ *   the boundary.
+ * S7_BF16_IR and S7_FP16_IR: coefficients and Krylov vectors are stored in
+ *   BF16 or FP16 and computed in FP32, with FP64 inner products.  This is the
+ *   paper's mixed 16/32-bit scheme (section IV "AllReduce"; Table I).  It
+ *   runs inside an FP64 iterative-refinement loop, the correction scheme the
+ *   paper names (section VI-B).  Each outer step forms the true residual
+ *   r = b - A x in FP64 with the exact FP32 coefficients, solves
+ *   A d = r / scale to the inner tolerance, and updates x += scale * d in FP64.
+ */
+enum s7_prec { S7_FP32 = 0, S7_BF16_IR = 1, S7_FP16_IR = 2 };
+
+typedef struct {
+    int32_t jacobi;         /* 1 (default): left diagonal (Jacobi) scaling, so the
+                               iterated matrix has a unit diagonal (section IV,
+                               first paragraph); 0: iterate on A as given */
+    int32_t graph_iters;    /* iterations per captured hipGraph launch; 0 = auto */
+    int32_t rows_per_wave;  /* stencil tile rows per wavefront (4 or 8); 0 = auto */
+    int32_t zchunk;         /* z-planes per tile; 0 = auto */
+    int32_t profile;        /* 1: launch without graphs, time every pass with HIP
+                               events into s7_info.pass_ms */
+    int32_t inner_max_iter; /* IR: inner iteration cap per outer step; 0 = 100 */
+    int32_t outer_max_iter; /* IR: outer step cap; 0 = 30 */
+    int32_t reserved0;
+    double inner_rtol;      /* IR: inner relative tolerance; 0 = 1e-2 (BF16), 5e-3 (FP16) */
+} s7_options;
+
+typedef struct {
+    int32_t iters;       /* BiCGStab iterations; for IR, summed over outer steps */
+    int32_t outer_iters; /* IR outer steps (1 for S7_FP32) */
+    int32_t status;      /* s7_status of this solve */
+    int32_t reason;      /* s7_reason when status == S7_BREAKDOWN */
+    double rel_res_rec;  /* recurrence residual ||r_i|| / ||b|| of the iterated
+                            (scaled) system at exit */
+    double rel_res_true; /* ||b - A x|| / ||b|| of the unscaled system, FP64, at exit */
+    double t_ms;         /* solver wall time (queue: submit to completion) */
+    double t_wait_ms;    /* queue: submit to admission; 0 otherwise */
+    double pass_ms[4];   /* profile: summed time of P1, P2, P3, all other kernels */
+    int32_t pass_count[4];
+} s7_info;
+
+/* Fills *opt with the defaults described above. */
+void s7_default_options(s7_options *opt);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *s7_last_error(void);
+
+/* ABI version: 0x010000 * major + 0x100 * minor. */
+int32_t s7_version(void);
+
+/*
+ * u = A v.  This is the SpMV of section IV, "SpMV (3D)": six coefficient
+ * times neighbour products plus the diagonal term.  Here the diagonal is
+ * explicit: no unit-diagonal assumption.
+ * coef: 7 device pointers {diag, xm, xp, ym, yp, zm, zp}, N floats each.
+ * v: N floats in.  u: N floats out.  u must not alias v.
+ * FP32 arithmetic with a fixed summation order:
+ *   diag v + xm v(i-1) + xp v(i+1) + ym v(j-1) + yp v(j+1) + zm v(k-1) + zp v(k+1).
+ * Asynchronous on `stream`.
+ */
+int s7_stencil_apply(s7_dims d, const float *const coef[7], const float *v, float *u,
+                     void *stream);
+
+/*
+ * Bytes of workspace s7_bicgstab_solve needs for these dims, precision and
+ * options.  opt may be NULL for the defaults.  Returns 0 for invalid dims.
+ */
+size_t s7_workspace_bytes(s7_dims d, int32_t prec, const s7_options *opt);
+
+/*
+ * Solves A x = b by BiCGStab.  This is Algorithm 1 ("Standard BiCGStab")
+ * with r0 = b - A x0 and the shadow vector r0 fixed.  Optional Jacobi
+ * scaling is applied (section IV).
+ *   coef  7 device float arrays (see layout above), not modified.
+ *   b     N device doubles.
+ *   x     N device doubles: x0 on entry, the solution (or last iterate) on exit.
+ *   rtol  relative tolerance, > 0.  The iteration stops when the recurrence
+ *         residual ||r||/||b|| of the iterated system is <= rtol.  That is
+ *         checked after each full step, and on ||q|| after the q-step.  For
+ *         the IR precisions the outer loop stops on the true FP64 residual.
+ *   max_iter  cap on BiCGStab iterations (>= 0).  For IR it caps the inner
+ *         iterations summed over the outer steps.
+ *   ws, ws_bytes  caller workspace, at least s7_workspace_bytes(), 256-byte
+ *         aligned.  Its contents are scratch.
+ *   opt   NULL for defaults.  info: optional, filled on return.
+ * b == 0 gives x = 0, 0 iterations, S7_OK.  max_iter == 0 leaves x = x0 and
+ * returns S7_NOT_CONVERGED, unless x0 already meets rtol.
+ */
+int s7_bicgstab_solve(s7_dims d, const float *const coef[7], const double *b, double *x,
+                      double rtol, int32_t max_iter, int32_t prec, void *ws, size_t ws_bytes,
+                      const s7_options *opt, s7_info *info, void *stream);
+
+/* Workspace for s7_bicgstab_solve_batched over these nsys systems. */
+size_t s7_batched_workspace_bytes(int32_t nsys, const s7_dims *d, int32_t prec,
+                                  const s7_options *opt);
+
+/*
+ * Solves nsys independent systems, of uneven mesh sizes, together in one
+ * persistent launch.  This is the "many compact problems" use of section
+ * VIII-B.  Per-system arguments are host arrays of length nsys:
+ *   d[s]; coef[7*s + c], device float arrays in the order above; b[s] and x[s],
+ *   device doubles; rtol[s]; max_iter[s].
+ * info, if not NULL, is an array of nsys and receives each system's result.
+ * Each system's iterates depend only on that system and its tile shape, never
+ * on the rest of the batch.  Returns the worst status: a negative error, or
+ * else the largest of S7_OK, S7_NOT_CONVERGED and S7_BREAKDOWN.
+ */
+int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims *d, const float *const *coef,
+                              const double *const *b, double *const *x, const double *rtol,
+                              const int32_t *max_iter, int32_t prec, void *ws, size_t ws_bytes,
+                              const s7_options *opt, s7_info *info, void *stream);
+
+/*
+ * Request queue with continuous batching (serving form; section VIII-A names
+ * the real-time use).  The caller supplies the device arena, which is the HBM
+ * budget.  A request is admitted when its workspace fits in the arena.
+ * Admitted requests join the resident batch between persistent-kernel
+ * epochs.  Their Krylov state stays on the device until they finish.
+ */
+typedef struct s7_queue s7_queue;
+
+typedef struct {
+    s7_dims d;
+    const float *coef[7]; /* device arrays, kept alive by the caller until done */
+    const double *b;      /* device */
+    double *x;            /* device; x0 on submit, solution when done */
+    double rtol;
+    int32_t max_iter;
+    int32_t prec;         /* s7_prec */
+} s7_request;
+
+/* Creates a queue over the caller's device arena (256-byte aligned). */
+int s7_queue_create(s7_queue **q, void *arena, size_t arena_bytes, const s7_options *opt);
+/* Copies the descriptor and returns a ticket.  S7_ENOMEM if it can never fit. */
+int s7_queue_submit(s7_queue *q, const s7_request *req, uint64_t *ticket);
+/* Non-blocking.  S7_EAGAIN while running; else the request's status, with *info filled. */
+int s7_queue_poll(s7_queue *q, uint64_t ticket, s7_info *info);
+/* Blocks until the request is done. */
+int s7_queue_wait(s7_queue *q, uint64_t ticket, s7_info *info);
+/* Finishes the outstanding work, then releases the queue. */
+int s7_queue_destroy(s7_queue *q);
+
+/*
+ * Synthetic problem generator, for benchmarks and tests on meshes too large
+ * to build on the host.  It writes the seven coefficient arrays and x*, and
+ * b = A x* in FP64.  Recipe: recipe 0 draws i.i.d. off-diagonals in
+ * [-1, -0.5) and sets diag = fl32(sum|off| + 0.1).  Recipe 1 also scales
+ * zm and zp by 1 + 9 s(k), a centred z-slab with smoothstep edges.  The
+ * random numbers come from SplitMix64 (Steele, Lea, Flood 2014), indexed
+ * by (seed, array, cell).  Any of coef[c], xstar and b may be NULL to skip it.
+ * b needs all seven coef arrays and xstar.
+ */
+int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float *const coef[7],
+                        double *xstar, double *b, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S7_H */

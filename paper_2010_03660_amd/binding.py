@@ -1,1 +1,259 @@
-"""ctypes binding of libs7.so (filled in with the library)."""
+"""ctypes binding of libs7.so: argument marshalling only.
+
+Every entry point has the name of its C function without the ``s7_`` prefix.
+Arrays are torch CUDA tensors, or raw device addresses as ints.  Streams are
+``torch.cuda.Stream`` objects, raw ``hipStream_t`` ints, or None for torch's
+current stream.  If the library is missing, the first call raises
+RuntimeError.  There is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libs7.so")
+
+OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+EINVAL, ENOMEM, EHIP, EAGAIN, ENOTFOUND = -1, -2, -3, -4, -5
+REASON_NONE, REASON_RHO_ZERO, REASON_RS_ZERO, REASON_YY_ZERO, REASON_NONFINITE = range(5)
+FP32, BF16_IR, FP16_IR = 0, 1, 2
+PREC_NAMES = {"fp32": FP32, "bf16_ir": BF16_IR, "fp16_ir": FP16_IR}
+
+__all__ = [
+    "Dims", "Options", "Info", "Request", "lib", "default_options", "last_error", "version",
+    "stencil_apply", "workspace_bytes", "bicgstab_solve", "batched_workspace_bytes",
+    "bicgstab_solve_batched", "queue_create", "queue_submit", "queue_poll", "queue_wait",
+    "queue_destroy", "generate_problem", "S7Error",
+    "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
+    "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
+    "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
+]
+
+
+class Dims(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
+
+
+class Options(C.Structure):
+    _fields_ = [("jacobi", C.c_int32), ("graph_iters", C.c_int32), ("rows_per_wave", C.c_int32),
+                ("zchunk", C.c_int32), ("profile", C.c_int32), ("inner_max_iter", C.c_int32),
+                ("outer_max_iter", C.c_int32), ("reserved0", C.c_int32),
+                ("inner_rtol", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32), ("status", C.c_int32),
+                ("reason", C.c_int32), ("rel_res_rec", C.c_double), ("rel_res_true", C.c_double),
+                ("t_ms", C.c_double), ("t_wait_ms", C.c_double), ("pass_ms", C.c_double * 4),
+                ("pass_count", C.c_int32 * 4)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "outer_iters": self.outer_iters, "status": self.status,
+                "reason": self.reason, "rel_res_rec": self.rel_res_rec,
+                "rel_res_true": self.rel_res_true, "t_ms": self.t_ms, "t_wait_ms": self.t_wait_ms,
+                "pass_ms": list(self.pass_ms), "pass_count": list(self.pass_count)}
+
+
+class Request(C.Structure):
+    _fields_ = [("d", Dims), ("coef", C.c_void_p * 7), ("b", C.c_void_p), ("x", C.c_void_p),
+                ("rtol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32)]
+
+
+class S7Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"s7 error {code}: {msg}")
+        self.code = code
+
+
+_vp = C.c_void_p
+EXPORTS = {
+    "s7_default_options": (None, [C.POINTER(Options)]),
+    "s7_last_error": (C.c_char_p, []),
+    "s7_version": (C.c_int32, []),
+    "s7_stencil_apply": (C.c_int, [Dims, C.POINTER(_vp), _vp, _vp, _vp]),
+    "s7_workspace_bytes": (C.c_size_t, [Dims, C.c_int32, C.POINTER(Options)]),
+    "s7_bicgstab_solve": (C.c_int, [Dims, C.POINTER(_vp), _vp, _vp, C.c_double, C.c_int32, C.c_int32,
+                                    _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info), _vp]),
+    "s7_batched_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(Dims), C.c_int32,
+                                                C.POINTER(Options)]),
+    "s7_bicgstab_solve_batched": (C.c_int, [C.c_int32, C.POINTER(Dims), C.POINTER(_vp),
+                                            C.POINTER(_vp), C.POINTER(_vp),
+                                            C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32,
+                                            _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info),
+                                            _vp]),
+    "s7_queue_create": (C.c_int, [C.POINTER(_vp), _vp, C.c_size_t, C.POINTER(Options)]),
+    "s7_queue_submit": (C.c_int, [_vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "s7_queue_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(Info)]),
+    "s7_queue_wait": (C.c_int, [_vp, C.c_uint64, C.POINTER(Info)]),
+    "s7_queue_destroy": (C.c_int, [_vp]),
+    "s7_generate_problem": (C.c_int, [Dims, C.c_uint64, C.c_int32, C.POINTER(_vp), _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library.  Raises RuntimeError if libs7.so is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2010_03660_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().s7_last_error().decode()
+
+
+def version() -> int:
+    return lib().s7_version()
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().s7_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dims(d) -> Dims:
+    return d if isinstance(d, Dims) else Dims(*[int(v) for v in d])
+
+
+def _coef(coef: Sequence) -> C.Array:
+    if len(coef) != 7:
+        raise ValueError("need 7 coefficient arrays: diag, xm, xp, ym, yp, zm, zp")
+    return (_vp * 7)(*[_ptr(c) for c in coef])
+
+
+def _check(rc: int, allow=(OK, NOT_CONVERGED, BREAKDOWN)) -> int:
+    if rc not in allow:
+        raise S7Error(rc, last_error())
+    return rc
+
+
+def stencil_apply(dims, coef, v, u, stream=None) -> None:
+    _check(lib().s7_stencil_apply(_dims(dims), _coef(coef), _ptr(v), _ptr(u), _stream(stream)),
+           allow=(OK,))
+
+
+def workspace_bytes(dims, prec=FP32, opt: Options | None = None) -> int:
+    return int(lib().s7_workspace_bytes(_dims(dims), int(prec), C.byref(opt) if opt else None))
+
+
+def _workspace(nbytes: int, ws):
+    if ws is not None:
+        return ws
+    import torch
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+
+
+def bicgstab_solve(dims, coef, b, x, rtol, max_iter, prec=FP32, ws=None,
+                   opt: Options | None = None, stream=None) -> Info:
+    """Solves A x = b in place in x (x0 on entry).  Returns the Info record; raises on error codes < 0."""
+    info = Info()
+    nbytes = workspace_bytes(dims, prec, opt)
+    ws = _workspace(nbytes, ws)
+    wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
+    rc = lib().s7_bicgstab_solve(_dims(dims), _coef(coef), _ptr(b), _ptr(x), float(rtol),
+                                 int(max_iter), int(prec), _ptr(ws), wsb,
+                                 C.byref(opt) if opt else None, C.byref(info), _stream(stream))
+    _check(rc)
+    return info
+
+
+def batched_workspace_bytes(dims_list, prec=FP32, opt: Options | None = None) -> int:
+    n = len(dims_list)
+    arr = (Dims * n)(*[_dims(d) for d in dims_list])
+    return int(lib().s7_batched_workspace_bytes(n, arr, int(prec), C.byref(opt) if opt else None))
+
+
+def bicgstab_solve_batched(dims_list, coefs, bs, xs, rtols, max_iters, prec=FP32, ws=None,
+                           opt: Options | None = None, stream=None):
+    """Solves len(dims_list) systems in one persistent launch.  Returns (status, [Info])."""
+    n = len(dims_list)
+    arr = (Dims * n)(*[_dims(d) for d in dims_list])
+    cp = (_vp * (7 * n))(*[_ptr(c) for cs in coefs for c in cs])
+    bp = (_vp * n)(*[_ptr(b) for b in bs])
+    xp = (_vp * n)(*[_ptr(x) for x in xs])
+    rt = (C.c_double * n)(*[float(r) for r in rtols])
+    mi = (C.c_int32 * n)(*[int(m) for m in max_iters])
+    infos = (Info * n)()
+    nbytes = batched_workspace_bytes(dims_list, prec, opt)
+    ws = _workspace(nbytes, ws)
+    wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
+    rc = lib().s7_bicgstab_solve_batched(n, arr, cp, bp, xp, rt, mi, int(prec), _ptr(ws), wsb,
+                                         C.byref(opt) if opt else None, infos, _stream(stream))
+    _check(rc)
+    return rc, list(infos)
+
+
+def queue_create(arena, arena_bytes: int | None = None, opt: Options | None = None) -> int:
+    q = _vp()
+    nbytes = arena_bytes if arena_bytes is not None else arena.numel() * arena.element_size()
+    _check(lib().s7_queue_create(C.byref(q), _ptr(arena), nbytes, C.byref(opt) if opt else None),
+           allow=(OK,))
+    return q.value
+
+
+def queue_submit(q: int, dims, coef, b, x, rtol, max_iter, prec=FP32) -> int:
+    req = Request(_dims(dims), (_vp * 7)(*[_ptr(c) for c in coef]), _ptr(b), _ptr(x), float(rtol),
+                  int(max_iter), int(prec))
+    t = C.c_uint64()
+    _check(lib().s7_queue_submit(q, C.byref(req), C.byref(t)), allow=(OK,))
+    return t.value
+
+
+def queue_poll(q: int, ticket: int):
+    """(status or EAGAIN, Info)."""
+    info = Info()
+    rc = lib().s7_queue_poll(q, ticket, C.byref(info))
+    _check(rc, allow=(OK, NOT_CONVERGED, BREAKDOWN, EAGAIN))
+    return rc, info
+
+
+def queue_wait(q: int, ticket: int):
+    info = Info()
+    rc = lib().s7_queue_wait(q, ticket, C.byref(info))
+    _check(rc)
+    return rc, info
+
+
+def queue_destroy(q: int) -> None:
+    _check(lib().s7_queue_destroy(q), allow=(OK,))
+
+
+def generate_problem(dims, seed: int, recipe: int, coef=None, xstar=None, b=None, stream=None):
+    cp = _coef(coef) if coef is not None else None
+    _check(lib().s7_generate_problem(_dims(dims), int(seed), int(recipe), cp, _ptr(xstar), _ptr(b),
+                                     _stream(stream)), allow=(OK,))

@@ -1,0 +1,70 @@
+// Host-side helpers shared by the s7 translation units: error reporting,
+// argument checks, workspace layout and tile choice.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/s7.h"
+#include "s7_device.hpp"
+
+namespace s7 {
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define S7_HIP(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::s7::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                            __LINE__);                                                    \
+            return S7_EHIP;                                                               \
+        }                                                                                 \
+    } while (0)
+
+#define S7_CHECK_LAUNCH() S7_HIP(hipGetLastError())
+
+inline bool dims_ok(s7_dims d) {
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return false;
+    long long n = (long long)d.nx * d.ny * d.nz;
+    return n < (1ll << 31);
+}
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+inline size_t elt_size(int prec) { return prec == S7_FP32 ? 4 : 2; }
+
+// Tile shape of the z-march kernels for a mesh.  rows_per_wave and zchunk
+// come from the options, the tuning cache, or these defaults.
+struct TileChoice {
+    int R;
+    int zc;
+};
+
+TileChoice choose_tiles(s7_dims d, const s7_options& o, int prec);
+
+inline int stream_blocks_for(long long n) {
+    long long b = (n + kThreads * 8 - 1) / (kThreads * 8);
+    if (b < 1) b = 1;
+    if (b > 2048) b = 2048;
+    return (int)b;
+}
+
+// Workspace of one system: [State][partials][coef copies][7 vectors of T][d: FP32].
+struct Layout {
+    size_t off_state, off_partials, off_coef, off_vec, off_d, bytes;
+    int ncoef;
+    size_t elt;
+    size_t nparts;  // doubles of partials
+    size_t n;
+};
+
+Layout make_layout(s7_dims d, int prec, int jacobi, TileChoice tc);
+
+void options_or_default(const s7_options* in, s7_options& out);
+
+}  // namespace s7

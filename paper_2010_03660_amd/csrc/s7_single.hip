@@ -1,0 +1,838 @@
+// Single-system path of the s7 library: stencil apply, the generator, and the
+// BiCGStab solve (FP32, and BF16/FP16 inside FP64 iterative refinement).
+//
+// Per iteration, Algorithm 1 runs as three fused passes with a device-side
+// scalar step at the end of each:
+//   P1  p_i = r_i + beta (p_{i-1} - omega s_{i-1}), formed on the fly (also
+//       at halo cells); s_i = A p_i; partial (r0, s_i)    -> alpha_i
+//   P2  q_i = r_i - alpha s_i on the fly; y_i = A q_i;
+//       partials (q,y), (y,y), (q,q)                     -> omega_i, half-step test
+//   P3  x += alpha p + omega q; r_{i+1} = q - omega y;
+//       partials (r0,r), (r,r)                           -> beta_i, stopping tests
+// p and s are ping-pong buffers, so halo reads of the old values never race
+// with writes of the new ones.  The scalars stay on the device.  The host
+// reads only the `done` word, once per captured graph of K iterations.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "s7_host.hpp"
+
+namespace s7 {
+
+// ============================================================== error state
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+void clear_error() { g_err.clear(); }
+
+void options_or_default(const s7_options* in, s7_options& out) {
+    if (in) {
+        out = *in;
+    } else {
+        s7_default_options(&out);
+    }
+}
+
+TileChoice choose_tiles(s7_dims d, const s7_options& o, int prec) {
+    (void)prec;
+    TileChoice tc;
+    tc.R = (o.rows_per_wave == 4 || o.rows_per_wave == 8) ? o.rows_per_wave : (d.ny >= 32 ? 8 : 4);
+    if (o.zchunk > 0) {
+        tc.zc = o.zchunk;
+    } else {
+        int zc = 64;
+        Mesh m{d.nx, d.ny, d.nz};
+        while (zc > 8 && make_ztiles(m, tc.R, zc).nblocks < 2048) zc /= 2;
+        tc.zc = zc;
+    }
+    if (tc.zc > d.nz) tc.zc = d.nz;
+    return tc;
+}
+
+Layout make_layout(s7_dims d, int prec, int jacobi, TileChoice tc) {
+    Layout L;
+    Mesh m{d.nx, d.ny, d.nz};
+    L.n = (size_t)d.nx * d.ny * d.nz;
+    L.elt = elt_size(prec);
+    L.ncoef = jacobi ? 6 : 7;
+    size_t nb = (size_t)make_ztiles(m, tc.R, tc.zc).nblocks;
+    size_t nb4 = (size_t)make_ztiles(m, 4, tc.zc).nblocks;
+    if (nb4 > nb) nb = nb4;
+    size_t sb = (size_t)stream_blocks_for((long long)L.n);
+    if (sb > nb) nb = sb;
+    L.nparts = nb * kMaxDots;
+    size_t off = 0;
+    L.off_state = off;
+    off = align256(off + sizeof(State));
+    L.off_partials = off;
+    off = align256(off + L.nparts * sizeof(double));
+    L.off_coef = off;
+    off = align256(off + (size_t)L.ncoef * align256(L.n * L.elt));
+    L.off_vec = off;
+    off = align256(off + (size_t)7 * align256(L.n * L.elt));
+    L.off_d = off;
+    off = align256(off + L.n * sizeof(float));
+    L.bytes = off;
+    return L;
+}
+
+template <class T>
+static SysView<T> make_view(s7_dims d, const Layout& L, TileChoice tc, int jacobi, char* ws) {
+    SysView<T> S;
+    S.m = Mesh{d.nx, d.ny, d.nz};
+    S.zt = make_ztiles(S.m, tc.R, tc.zc);
+    S.n = (int)L.n;
+    S.unit = jacobi ? 1 : 0;
+    const size_t span = align256(L.n * L.elt);
+    const int first = jacobi ? 1 : 0;
+    for (int a = 0; a < 7; ++a)
+        S.c[a] = a < first ? nullptr : reinterpret_cast<const T*>(ws + L.off_coef + (a - first) * span);
+    auto vec = [&](int i) { return reinterpret_cast<T*>(ws + L.off_vec + i * span); };
+    S.r = vec(0);
+    S.rhat = vec(1);
+    S.p[0] = vec(2);
+    S.p[1] = vec(3);
+    S.s[0] = vec(4);
+    S.s[1] = vec(5);
+    S.y = vec(6);
+    S.d = reinterpret_cast<float*>(ws + L.off_d);
+    S.st = reinterpret_cast<State*>(ws + L.off_state);
+    S.partials = reinterpret_cast<double*>(ws + L.off_partials);
+    S.stream_blocks = stream_blocks_for((long long)L.n);
+    return S;
+}
+
+// ============================================================== kernels
+struct Coef7 {
+    const float* c[7];
+};
+
+// Working-precision coefficient copies.  jacobi: c[a] / diag for a = 1..6 (unit
+// diagonal).  Otherwise all seven.  Outward links on the boundary faces are
+// zeroed, so the iteration never needs face tests.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_prep_coef(Coef7 src, T* dst0, size_t span_elems,
+                                                        Mesh m, int jacobi) {
+    const int first = jacobi ? 1 : 0;
+    const int n = m.nx * m.ny * m.nz;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        const int x = i % m.nx;
+        const int rest = i / m.nx;
+        const int y = rest % m.ny;
+        const int k = rest / m.ny;
+        const bool in[7] = {true, x > 0, x < m.nx - 1, y > 0, y < m.ny - 1, k > 0, k < m.nz - 1};
+        const float dg = src.c[0][i];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) {
+            if (a < first) continue;
+            float v = in[a] ? src.c[a][i] : 0.0f;
+            if (jacobi) v = v / dg;
+            dst0[(size_t)(a - first) * span_elems + i] = from_f32<T>(v);
+        }
+    }
+}
+
+// r0 = b - A x0 in FP64 with the caller's FP32 coefficients.  Optionally
+// Jacobi-scaled.  Rounded to FP32 into r and r_hat, and d = 0.  Partials:
+// ||b_s||^2, (r,r) of the rounded r, ||b||^2 unscaled.
+struct OutInitF32 {
+    const double* b;
+    const float* diag;
+    float *r, *rhat, *d;
+    int jacobi;
+    double acc[3];
+    __device__ __forceinline__ void emit(int idx, double, double ax) {
+        const double bi = b[idx];
+        double r0 = bi - ax, bs = bi;
+        if (jacobi) {
+            const double dg = (double)diag[idx];
+            r0 = r0 / dg;
+            bs = bs / dg;
+        }
+        const float rf = (float)r0;
+        r[idx] = rf;
+        rhat[idx] = rf;
+        d[idx] = 0.0f;
+        acc[0] = fma(bs, bs, acc[0]);
+        acc[1] = fma((double)rf, (double)rf, acc[1]);
+        acc[2] = fma(bi, bi, acc[2]);
+    }
+};
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_init_f32(Coef7 cf, const double* b, const double* x0,
+                                                       SysView<float> S, int jacobi, double tol,
+                                                       int max_iter) {
+    const int L = xcd_remap(blockIdx.x, S.zt.nblocks);
+    int tx, ty, k0, k1;
+    OutInitF32 out{b, cf.c[0], S.r, S.rhat, S.d, jacobi, {0.0, 0.0, 0.0}};
+    if (wave_tile(S.zt, S.m, L, tx, ty, k0, k1)) {
+        SrcLoadF64 src{x0};
+        StencilOp<float, double, false, true> op{{cf.c[0], cf.c[1], cf.c[2], cf.c[3], cf.c[4], cf.c[5], cf.c[6]}, S.m};
+        zmarch<R>(S.m, tx, ty, k0, k1, src, op, out);
+    }
+    double tot[3];
+    if (reduce_partials<3>(out.acc, S.partials, &S.st->ticket, S.zt.nblocks, blockIdx.x, tot) &&
+        threadIdx.x == 0) {
+        tail_init(S.st, tot[0], tot[1], tol, max_iter);
+        S.st->bb_true = tot[2];
+        S.st->scale = 1.0;
+    }
+}
+
+// True residual r = b - A x in FP64 (caller's coefficients, unscaled).
+// Partials: ||b||^2, ||r||^2, max |r_s| (r_s = r / diag with Jacobi).  With
+// store != 0, r_s goes to dst as FP32: the right-hand side of the next
+// refinement step.
+struct OutResid {
+    const double* b;
+    const float* diag;
+    float* dst;
+    int jacobi;
+    int store;
+    double acc[3];
+    __device__ __forceinline__ void emit(int idx, double, double ax) {
+        const double bi = b[idx];
+        const double r0 = bi - ax;
+        acc[0] = fma(bi, bi, acc[0]);
+        acc[1] = fma(r0, r0, acc[1]);
+        const double rs = jacobi ? r0 / (double)diag[idx] : r0;
+        const float rf = (float)rs;
+        if (store) dst[idx] = rf;
+        acc[2] = fmax(acc[2], (double)fabsf(rf));
+    }
+};
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_resid(Coef7 cf, const double* b, const double* x,
+                                                    float* dst, Mesh m, ZTiles zt, State* st,
+                                                    double* partials, int jacobi, int store) {
+    const int L = xcd_remap(blockIdx.x, zt.nblocks);
+    int tx, ty, k0, k1;
+    OutResid out{b, cf.c[0], dst, jacobi, store, {0.0, 0.0, 0.0}};
+    if (wave_tile(zt, m, L, tx, ty, k0, k1)) {
+        SrcLoadF64 src{x};
+        StencilOp<float, double, false, true> op{{cf.c[0], cf.c[1], cf.c[2], cf.c[3], cf.c[4], cf.c[5], cf.c[6]}, m};
+        zmarch<R>(m, tx, ty, k0, k1, src, op, out);
+    }
+    double tot[3];
+    if (reduce_partials<3, 4u>(out.acc, partials, &st->ticket, zt.nblocks, blockIdx.x, tot) &&
+        threadIdx.x == 0) {
+        st->bb_true = tot[0];
+        st->rr_true = tot[1];
+        st->rmax = tot[2];
+    }
+}
+
+// Start of an inner solve of the refinement: r = r_hat = fl_T(rs / scale)
+// from the FP32 residual in d, then d = 0.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_ir_init(SysView<T> S, float inv_scale, double tol,
+                                                      int max_iter) {
+    int i0, i1;
+    stream_range(S.n, S.stream_blocks, blockIdx.x, i0, i1);
+    double acc[1] = {0.0};
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += kThreads) {
+        const T rt = from_f32<T>(S.d[i] * inv_scale);
+        S.r[i] = rt;
+        S.rhat[i] = rt;
+        S.d[i] = 0.0f;
+        const double v = (double)to_f32(rt);
+        acc[0] = fma(v, v, acc[0]);
+    }
+    double tot[1];
+    if (reduce_partials<1>(acc, S.partials, &S.st->ticket, S.stream_blocks, blockIdx.x, tot) &&
+        threadIdx.x == 0) {
+        tail_init(S.st, tot[0], tot[0], tol, max_iter);
+    }
+}
+
+// x += scale * d (FP64), or x = 0 when b = 0.
+__global__ __launch_bounds__(kThreads) void k_update_x(double* x, const float* d, int n,
+                                                       double scale, const State* st) {
+    const bool zero = st->nbzero != 0;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+        x[i] = zero ? 0.0 : fma(scale, (double)d[i], x[i]);
+}
+
+// Clears the solver state, including the reduction ticket (a kernel rather
+// than a memset, so that the same clear is valid inside captured graphs).
+__global__ __launch_bounds__(64) void k_zero_state(State* st) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(st);
+    for (int i = threadIdx.x; i < (int)(sizeof(State) / 4); i += 64) w[i] = 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill0(double* x, int n) {
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) x[i] = 0.0;
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(kThreads) void k_p1(SysView<T> S, int par) {
+    if (S.st->done) return;
+    const int L = xcd_remap(blockIdx.x, S.zt.nblocks);
+    double acc[1];
+    wg_p1<T, R>(S, L, par, acc);
+    double tot[1];
+    if (reduce_partials<1>(acc, S.partials, &S.st->ticket, S.zt.nblocks, blockIdx.x, tot) &&
+        threadIdx.x == 0)
+        tail_p1(S.st, tot);
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(kThreads) void k_p2(SysView<T> S, int par) {
+    if (S.st->done) return;
+    const int L = xcd_remap(blockIdx.x, S.zt.nblocks);
+    double acc[3];
+    wg_p2<T, R>(S, L, par, acc);
+    double tot[3];
+    if (reduce_partials<3>(acc, S.partials, &S.st->ticket, S.zt.nblocks, blockIdx.x, tot) &&
+        threadIdx.x == 0)
+        tail_p2(S.st, tot);
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_p3(SysView<T> S, int par) {
+    if (S.st->done) return;
+    double acc[2];
+    chunk_p3<T>(S, blockIdx.x, par, acc);
+    double tot[2];
+    if (reduce_partials<2>(acc, S.partials, &S.st->ticket, S.stream_blocks, blockIdx.x, tot) &&
+        threadIdx.x == 0)
+        tail_p3(S.st, tot);
+}
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_stencil_apply(Coef7 cf, const float* v, float* u,
+                                                            Mesh m, ZTiles zt) {
+    const int L = xcd_remap(blockIdx.x, zt.nblocks);
+    int tx, ty, k0, k1;
+    if (!wave_tile(zt, m, L, tx, ty, k0, k1)) return;
+    SrcLoad<float> src{v};
+    StencilOp<float, float, false, true> op{{cf.c[0], cf.c[1], cf.c[2], cf.c[3], cf.c[4], cf.c[5], cf.c[6]}, m};
+    OutStore<float> out{u};
+    zmarch<R>(m, tx, ty, k0, k1, src, op, out);
+}
+
+// ---- generator (recipe of the synthetic inputs; see s7.h)
+__device__ __forceinline__ uint64_t gen_hash(uint64_t seed, int aid, uint64_t cell) {
+    const uint64_t key = splitmix64(seed ^ ((uint64_t)aid << 56));
+    return splitmix64(key ^ cell);
+}
+
+__device__ __forceinline__ double smooth01(double t) {
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    return __dmul_rn(__dmul_rn(t, t), __dsub_rn(3.0, __dmul_rn(2.0, t)));
+}
+
+__global__ __launch_bounds__(kThreads) void k_gen_coef(Coef7 out, double* xstar, Mesh m,
+                                                       uint64_t seed, int recipe) {
+    const int n = m.nx * m.ny * m.nz;
+    float* c[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) c[a] = const_cast<float*>(out.c[a]);
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        const int k = i / (m.nx * m.ny);
+        double f = 1.0;
+        if (recipe == 1) {
+            const double lo = (double)(m.nz / 4), hi = (double)((3 * m.nz) / 4), w = 4.0;
+            const double kd = (double)k;
+            const double s = __dmul_rn(smooth01(__ddiv_rn(__dsub_rn(kd, __dsub_rn(lo, w)), w)),
+                                       smooth01(__ddiv_rn(__dsub_rn(__dadd_rn(__dsub_rn(hi, 1.0), w), kd), w)));
+            f = __dadd_rn(1.0, __dmul_rn(9.0, s));
+        }
+        double sum = 0.0;
+        float off[6];
+#pragma unroll
+        for (int a = 1; a <= 6; ++a) {
+            const uint64_t h = gen_hash(seed, a, (uint64_t)i);
+            const double mm = (double)(h >> 41);
+            float v = (float)(-(__dadd_rn(0.5, __dmul_rn(mm, 0x1p-24))));
+            if (recipe == 1 && a >= 5) v = (float)__dmul_rn((double)v, f);
+            off[a - 1] = v;
+            sum = __dadd_rn(sum, fabs((double)v));
+        }
+        const float dg = (float)__dadd_rn(sum, 0.1);
+        if (c[0]) c[0][i] = dg;
+#pragma unroll
+        for (int a = 1; a <= 6; ++a)
+            if (c[a]) c[a][i] = off[a - 1];
+        if (xstar) {
+            const uint64_t h = gen_hash(seed, 7, (uint64_t)i);
+            xstar[i] = __dadd_rn(-1.0, __dmul_rn((double)(h >> 40), 0x1p-23));
+        }
+    }
+}
+
+struct OutF64 {
+    double* u;
+    __device__ __forceinline__ void emit(int idx, double, double av) { u[idx] = av; }
+};
+
+template <int R>
+__global__ __launch_bounds__(kThreads) void k_apply_f64(Coef7 cf, const double* v, double* u,
+                                                        Mesh m, ZTiles zt) {
+    const int L = xcd_remap(blockIdx.x, zt.nblocks);
+    int tx, ty, k0, k1;
+    if (!wave_tile(zt, m, L, tx, ty, k0, k1)) return;
+    SrcLoadF64 src{v};
+    StencilOp<float, double, false, true> op{{cf.c[0], cf.c[1], cf.c[2], cf.c[3], cf.c[4], cf.c[5], cf.c[6]}, m};
+    OutF64 out{u};
+    zmarch<R>(m, tx, ty, k0, k1, src, op, out);
+}
+
+// ============================================================== graph cache
+namespace {
+
+struct GraphEntry {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec;
+};
+
+std::mutex g_graph_mu;
+std::list<GraphEntry> g_graphs;
+constexpr size_t kMaxGraphs = 32;
+hipStream_t g_capture_stream[16] = {};
+
+int capture_stream(hipStream_t* out) {
+    int dev = 0;
+    S7_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 16) {
+        set_error("device index %d out of range", dev);
+        return S7_EINVAL;
+    }
+    if (!g_capture_stream[dev]) S7_HIP(hipStreamCreateWithFlags(&g_capture_stream[dev], hipStreamNonBlocking));
+    *out = g_capture_stream[dev];
+    return S7_OK;
+}
+
+}  // namespace
+
+// Returns a cached executable graph for `key`, capturing `body` on first use.
+template <class F>
+static int cached_graph(const std::vector<uintptr_t>& key, F body, hipGraphExec_t* out) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
+        if (it->key == key) {
+            g_graphs.splice(g_graphs.begin(), g_graphs, it);
+            *out = g_graphs.front().exec;
+            return S7_OK;
+        }
+    }
+    hipStream_t cs;
+    int rc = capture_stream(&cs);
+    if (rc) return rc;
+    hipGraph_t graph;
+    S7_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    body(cs);
+    hipError_t le = hipGetLastError();
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        set_error("graph capture failed: %s / %s", hipGetErrorString(le), hipGetErrorString(ce));
+        return S7_EHIP;
+    }
+    hipGraphExec_t exec;
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+        return S7_EHIP;
+    }
+    if (g_graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(g_graphs.back().exec);
+        g_graphs.pop_back();
+    }
+    g_graphs.push_front(GraphEntry{key, exec});
+    *out = exec;
+    return S7_OK;
+}
+
+// ============================================================== drivers
+static int auto_graph_iters(size_t n, int elt) {
+    const double us = (double)n * (elt == 4 ? 116.0 : 60.0) / 5.0e6 + 15.0;
+    int k = (int)(2000.0 / us);
+    if (k < 2) k = 2;
+    if (k > 64) k = 64;
+    return k & ~1;
+}
+
+template <class T, int R>
+static void launch_iteration(const SysView<T>& S, int par, hipStream_t s) {
+    hipLaunchKernelGGL((k_p1<T, R>), dim3(S.zt.nblocks), dim3(kThreads), 0, s, S, par);
+    hipLaunchKernelGGL((k_p2<T, R>), dim3(S.zt.nblocks), dim3(kThreads), 0, s, S, par);
+    hipLaunchKernelGGL((k_p3<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S, par);
+}
+
+static const size_t kStateHead = offsetof(State, pad);
+
+static int read_state(const State* dst, State* host, hipStream_t s) {
+    S7_HIP(hipMemcpyAsync(host, dst, kStateHead, hipMemcpyDeviceToHost, s));
+    S7_HIP(hipStreamSynchronize(s));
+    return S7_OK;
+}
+
+// Runs BiCGStab iterations from an initialised state until the device says done.
+template <class T, int R>
+static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t stream,
+                          State* host, s7_info* info) {
+    int rc = read_state(S.st, host, stream);
+    if (rc) return rc;
+    if (host->done) return S7_OK;
+    int K = o.graph_iters > 0 ? o.graph_iters : auto_graph_iters((size_t)S.n, (int)sizeof(T));
+    K = (K + 1) & ~1;
+    const long long max_launches = (long long)host->max_iter / K + 3;
+    if (o.profile) {
+        std::vector<hipEvent_t> ev((size_t)4 * K);
+        for (auto& e : ev) S7_HIP(hipEventCreate(&e));
+        for (long long l = 0; l < max_launches; ++l) {
+            const int it0 = host->iter;
+            for (int j = 0; j < K; ++j) {
+                const int par = j & 1;
+                S7_HIP(hipEventRecord(ev[4 * j + 0], stream));
+                hipLaunchKernelGGL((k_p1<T, R>), dim3(S.zt.nblocks), dim3(kThreads), 0, stream, S, par);
+                S7_HIP(hipEventRecord(ev[4 * j + 1], stream));
+                hipLaunchKernelGGL((k_p2<T, R>), dim3(S.zt.nblocks), dim3(kThreads), 0, stream, S, par);
+                S7_HIP(hipEventRecord(ev[4 * j + 2], stream));
+                hipLaunchKernelGGL((k_p3<T>), dim3(S.stream_blocks), dim3(kThreads), 0, stream, S, par);
+                S7_HIP(hipEventRecord(ev[4 * j + 3], stream));
+            }
+            S7_CHECK_LAUNCH();
+            rc = read_state(S.st, host, stream);
+            if (rc) return rc;
+            const int ran = host->iter - it0;
+            if (info) {
+                for (int j = 0; j < K && j < ran; ++j) {
+                    for (int p = 0; p < 3; ++p) {
+                        float ms = 0.f;
+                        S7_HIP(hipEventElapsedTime(&ms, ev[4 * j + p], ev[4 * j + p + 1]));
+                        info->pass_ms[p] += ms;
+                        info->pass_count[p] += 1;
+                    }
+                }
+            }
+            if (host->done) break;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+    } else {
+        std::vector<uintptr_t> key = {0x51u, (uintptr_t)sizeof(T), (uintptr_t)R, (uintptr_t)K,
+                                      (uintptr_t)S.m.nx, (uintptr_t)S.m.ny, (uintptr_t)S.m.nz,
+                                      (uintptr_t)S.zt.zc, (uintptr_t)S.unit, (uintptr_t)S.st,
+                                      (uintptr_t)S.partials, (uintptr_t)S.r, (uintptr_t)S.c[0],
+                                      (uintptr_t)S.d, (uintptr_t)S.stream_blocks};
+        hipGraphExec_t g;
+        rc = cached_graph(key, [&](hipStream_t cs) {
+            for (int j = 0; j < K; ++j) launch_iteration<T, R>(S, j & 1, cs);
+        }, &g);
+        if (rc) return rc;
+        for (long long l = 0; l < max_launches; ++l) {
+            S7_HIP(hipGraphLaunch(g, stream));
+            rc = read_state(S.st, host, stream);
+            if (rc) return rc;
+            if (host->done) break;
+        }
+    }
+    if (!host->done) {
+        set_error("iteration driver did not reach a final state");
+        return S7_EHIP;
+    }
+    return S7_OK;
+}
+
+static int grid_for(size_t n) {
+    size_t g = (n + kThreads - 1) / kThreads;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+template <int R>
+static int resid_launch(const Coef7& cf, const double* b, const double* x, float* dst, Mesh m,
+                        int zc, State* st, double* partials, int jacobi, int store, hipStream_t s) {
+    ZTiles zt = make_ztiles(m, R, zc);
+    hipLaunchKernelGGL((k_resid<R>), dim3(zt.nblocks), dim3(kThreads), 0, s, cf, b, x, dst, m, zt,
+                       st, partials, jacobi, store);
+    S7_CHECK_LAUNCH();
+    return S7_OK;
+}
+
+template <class T>
+static int prep_coef(const Coef7& cf, const SysView<T>& S, size_t span_elems, int jacobi,
+                     hipStream_t s) {
+    hipLaunchKernelGGL((k_prep_coef<T>), dim3(grid_for(S.n)), dim3(kThreads), 0, s, cf,
+                       const_cast<T*>(S.c[jacobi ? 1 : 0]), span_elems, S.m, jacobi);
+    S7_CHECK_LAUNCH();
+    return S7_OK;
+}
+
+static void fill_info_from_state(const State& h, s7_info* info) {
+    if (!info) return;
+    info->status = h.status;
+    info->reason = h.reason;
+    info->rel_res_rec = h.res_rec;
+}
+
+template <int R>
+static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol,
+                      int max_iter, char* ws, const Layout& Lo, TileChoice tc,
+                      const s7_options& o, s7_info* info, hipStream_t s) {
+    SysView<float> S = make_view<float>(d, Lo, tc, o.jacobi, ws);
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, S.st);
+    int rc = prep_coef<float>(cf, S, align256(Lo.n * Lo.elt) / Lo.elt, o.jacobi, s);
+    if (rc) return rc;
+    auto t0 = std::chrono::steady_clock::now();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipLaunchKernelGGL((k_init_f32<R>), dim3(S.zt.nblocks), dim3(kThreads), 0, s, cf, b, x, S,
+                       o.jacobi, rtol, max_iter);
+    S7_CHECK_LAUNCH();
+    State h;
+    rc = run_iterations<float, R>(S, o, s, &h, info);
+    if (rc) return rc;
+    if (o.profile) {
+        S7_HIP(hipEventCreate(&e0));
+        S7_HIP(hipEventCreate(&e1));
+        S7_HIP(hipEventRecord(e0, s));
+    }
+    hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, x, S.d, S.n, 1.0, S.st);
+    S7_CHECK_LAUNCH();
+    rc = resid_launch<R>(cf, b, x, nullptr, S.m, tc.zc, S.st, S.partials, o.jacobi, 0, s);
+    if (rc) return rc;
+    if (o.profile) S7_HIP(hipEventRecord(e1, s));
+    rc = read_state(S.st, &h, s);
+    if (rc) return rc;
+    auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        fill_info_from_state(h, info);
+        info->iters = h.iter;
+        info->outer_iters = 1;
+        info->rel_res_true = h.bb_true > 0 ? sqrt(h.rr_true / h.bb_true) : 0.0;
+        info->t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        if (o.profile) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            info->pass_ms[3] += ms;
+            info->pass_count[3] += 1;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return h.status;
+}
+
+template <class T, int R>
+static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol,
+                    int max_iter, char* ws, const Layout& Lo, TileChoice tc, const s7_options& o,
+                    s7_info* info, hipStream_t s, int prec) {
+    SysView<T> S = make_view<T>(d, Lo, tc, o.jacobi, ws);
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, S.st);
+    int rc = prep_coef<T>(cf, S, align256(Lo.n * Lo.elt) / Lo.elt, o.jacobi, s);
+    if (rc) return rc;
+    auto t0 = std::chrono::steady_clock::now();
+    const double inner_tol = o.inner_rtol > 0 ? o.inner_rtol : (prec == S7_FP16_IR ? 5e-3 : 1e-2);
+    const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : 100;
+    const int outer_cap = o.outer_max_iter > 0 ? o.outer_max_iter : 30;
+    int total = 0, outer = 0, status = S7_NOT_CONVERGED, reason = 0;
+    double rel = INFINITY, inner_res = 0.0;
+    int stall = 0;
+    State h;
+    for (;;) {
+        rc = resid_launch<R>(cf, b, x, S.d, S.m, tc.zc, S.st, S.partials, o.jacobi, 1, s);
+        if (rc) return rc;
+        rc = read_state(S.st, &h, s);
+        if (rc) return rc;
+        if (h.bb_true == 0.0) {
+            hipLaunchKernelGGL(k_fill0, dim3(grid_for(S.n)), dim3(kThreads), 0, s, x, S.n);
+            S7_CHECK_LAUNCH();
+            rel = 0.0;
+            status = S7_OK;
+            break;
+        }
+        const double nrel = sqrt(h.rr_true / h.bb_true);
+        if (!std::isfinite(nrel)) {
+            status = S7_BREAKDOWN;
+            reason = S7_REASON_NONFINITE;
+            rel = nrel;
+            break;
+        }
+        stall = (nrel > 0.5 * rel) ? stall + 1 : 0;
+        rel = nrel;
+        if (rel <= rtol) {
+            status = S7_OK;
+            break;
+        }
+        if (outer >= outer_cap || total >= max_iter || stall >= 3) {
+            status = S7_NOT_CONVERGED;
+            break;
+        }
+        // power-of-two scale: the inner right-hand side has max |.| in (0.5, 1]
+        double scale = h.rmax > 0 ? exp2(ceil(log2(h.rmax))) : 1.0;
+        hipLaunchKernelGGL((k_ir_init<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S,
+                           (float)(1.0 / scale), inner_tol,
+                           inner_cap < max_iter - total ? inner_cap : max_iter - total);
+        S7_CHECK_LAUNCH();
+        rc = run_iterations<T, R>(S, o, s, &h, info);
+        if (rc) return rc;
+        total += h.iter;
+        outer += 1;
+        inner_res = h.res_rec;
+        if (h.status == S7_BREAKDOWN && h.iter == 0) {
+            status = S7_BREAKDOWN;
+            reason = h.reason;
+            break;
+        }
+        hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, x, S.d, S.n,
+                           scale, S.st);
+        S7_CHECK_LAUNCH();
+    }
+    S7_HIP(hipStreamSynchronize(s));
+    auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->status = status;
+        info->reason = reason;
+        info->iters = total;
+        info->outer_iters = outer;
+        info->rel_res_true = rel;
+        info->rel_res_rec = inner_res;
+        info->t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    return status;
+}
+
+}  // namespace s7
+
+// ============================================================== C ABI
+using namespace s7;
+
+extern "C" {
+
+void s7_default_options(s7_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->jacobi = 1;
+}
+
+const char* s7_last_error(void) { return g_err.c_str(); }
+
+int32_t s7_version(void) { return 0x010000; }
+
+static bool coef_ok(const float* const coef[7]) {
+    if (!coef) return false;
+    for (int a = 0; a < 7; ++a)
+        if (!coef[a]) return false;
+    return true;
+}
+
+int s7_stencil_apply(s7_dims d, const float* const coef[7], const float* v, float* u, void* stream) {
+    clear_error();
+    if (!dims_ok(d) || !coef_ok(coef) || !v || !u || v == u) {
+        set_error("s7_stencil_apply: invalid argument");
+        return S7_EINVAL;
+    }
+    Mesh m{d.nx, d.ny, d.nz};
+    Coef7 cf;
+    for (int a = 0; a < 7; ++a) cf.c[a] = coef[a];
+    s7_options o;
+    s7_default_options(&o);
+    TileChoice tc = choose_tiles(d, o, S7_FP32);
+    hipStream_t s = (hipStream_t)stream;
+    if (tc.R == 8) {
+        ZTiles zt = make_ztiles(m, 8, tc.zc);
+        hipLaunchKernelGGL((k_stencil_apply<8>), dim3(zt.nblocks), dim3(kThreads), 0, s, cf, v, u, m, zt);
+    } else {
+        ZTiles zt = make_ztiles(m, 4, tc.zc);
+        hipLaunchKernelGGL((k_stencil_apply<4>), dim3(zt.nblocks), dim3(kThreads), 0, s, cf, v, u, m, zt);
+    }
+    S7_CHECK_LAUNCH();
+    return S7_OK;
+}
+
+size_t s7_workspace_bytes(s7_dims d, int32_t prec, const s7_options* opt) {
+    if (!dims_ok(d) || prec < S7_FP32 || prec > S7_FP16_IR) return 0;
+    s7_options o;
+    options_or_default(opt, o);
+    return make_layout(d, prec, o.jacobi, choose_tiles(d, o, prec)).bytes;
+}
+
+int s7_bicgstab_solve(s7_dims d, const float* const coef[7], const double* b, double* x,
+                      double rtol, int32_t max_iter, int32_t prec, void* ws, size_t ws_bytes,
+                      const s7_options* opt, s7_info* info, void* stream) {
+    clear_error();
+    if (info) std::memset(info, 0, sizeof(*info));
+    s7_options o;
+    options_or_default(opt, o);
+    if (!dims_ok(d) || !coef_ok(coef) || !b || !x || !ws || !(rtol > 0.0) || max_iter < 0 ||
+        prec < S7_FP32 || prec > S7_FP16_IR || ((uintptr_t)ws & 255u) != 0) {
+        set_error("s7_bicgstab_solve: invalid argument");
+        return S7_EINVAL;
+    }
+    TileChoice tc = choose_tiles(d, o, prec);
+    Layout Lo = make_layout(d, prec, o.jacobi, tc);
+    if (ws_bytes < Lo.bytes) {
+        set_error("s7_bicgstab_solve: workspace too small (%zu < %zu)", ws_bytes, Lo.bytes);
+        return S7_EINVAL;
+    }
+    Coef7 cf;
+    for (int a = 0; a < 7; ++a) cf.c[a] = coef[a];
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)ws;
+    int rc;
+    if (prec == S7_FP32) {
+        rc = tc.R == 8 ? solve_fp32<8>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s)
+                       : solve_fp32<4>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s);
+    } else if (prec == S7_BF16_IR) {
+        rc = tc.R == 8 ? solve_ir<bf16, 8>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s, prec)
+                       : solve_ir<bf16, 4>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s, prec);
+    } else {
+        rc = tc.R == 8 ? solve_ir<f16, 8>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s, prec)
+                       : solve_ir<f16, 4>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s, prec);
+    }
+    return rc;
+}
+
+int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float* const coef[7],
+                        double* xstar, double* b, void* stream) {
+    clear_error();
+    if (!dims_ok(d) || (recipe != 0 && recipe != 1)) {
+        set_error("s7_generate_problem: invalid argument");
+        return S7_EINVAL;
+    }
+    Mesh m{d.nx, d.ny, d.nz};
+    Coef7 cf;
+    bool all = coef != nullptr;
+    for (int a = 0; a < 7; ++a) {
+        cf.c[a] = coef ? coef[a] : nullptr;
+        all = all && cf.c[a];
+    }
+    if (b && (!all || !xstar)) {
+        set_error("s7_generate_problem: b needs all coefficient arrays and xstar");
+        return S7_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    hipLaunchKernelGGL(k_gen_coef, dim3(grid_for(n)), dim3(kThreads), 0, s, cf, xstar, m, seed, recipe);
+    S7_CHECK_LAUNCH();
+    if (b) {
+        s7_options o;
+        s7_default_options(&o);
+        TileChoice tc = choose_tiles(d, o, S7_FP32);
+        ZTiles zt = make_ztiles(m, 4, tc.zc);
+        hipLaunchKernelGGL((k_apply_f64<4>), dim3(zt.nblocks), dim3(kThreads), 0, s, cf,
+                           (const double*)xstar, b, m, zt);
+        S7_CHECK_LAUNCH();
+    }
+    return S7_OK;
+}
+
+}  // extern "C"

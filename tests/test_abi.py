@@ -1,0 +1,82 @@
+"""The C-ABI library loads without a GPU and exports every function include/s7.h declares,
+with struct layouts that match the binding."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "s7.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(s7_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_lists_the_boundary():
+    fns = declared_functions()
+    for f in ("s7_stencil_apply", "s7_bicgstab_solve", "s7_bicgstab_solve_batched",
+              "s7_queue_submit", "s7_queue_poll", "s7_workspace_bytes"):
+        assert f in fns
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2010_03660_amd import binding
+    lib = binding.lib()
+    for f in declared_functions():
+        assert hasattr(lib, f), f
+    assert set(declared_functions()) == set(binding.EXPORTS)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    from paper_2010_03660_amd import binding
+    src = tmp_path / "sz.c"
+    src.write_text('#include "s7.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(s7_options),'
+                   ' sizeof(s7_info), sizeof(s7_request), offsetof(s7_info, pass_ms),'
+                   ' offsetof(s7_request, rtol), sizeof(s7_dims)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(binding.Options), C.sizeof(binding.Info), C.sizeof(binding.Request),
+            binding.Info.pass_ms.offset, binding.Request.rtol.offset, C.sizeof(binding.Dims)]
+    assert got == want
+
+
+def test_host_side_argument_checks():
+    """Calls that fail validation return before touching the GPU."""
+    from paper_2010_03660_amd import binding as B
+    lib = B.lib()
+    assert lib.s7_version() == 0x010000
+    o = B.default_options()
+    assert o.jacobi == 1
+    assert lib.s7_workspace_bytes(B.Dims(0, 4, 4), 0, None) == 0
+    assert lib.s7_workspace_bytes(B.Dims(2048, 2048, 1024), 0, None) == 0  # N >= 2^31
+    assert lib.s7_workspace_bytes(B.Dims(8, 8, 8), 0, None) > 0
+    coef = (C.c_void_p * 7)(*([256] * 7))
+    info = B.Info()
+    bad = [
+        (B.Dims(8, 8, 8), -1.0, 10),       # rtol <= 0
+        (B.Dims(8, 8, 8), float("nan"), 10),
+        (B.Dims(8, 8, 8), 1e-6, -1),       # max_iter < 0
+        (B.Dims(0, 8, 8), 1e-6, 10),
+    ]
+    for d, rtol, mi in bad:
+        rc = lib.s7_bicgstab_solve(d, coef, 256, 512, rtol, mi, 0, 1024, 1 << 20, None,
+                                   C.byref(info), 0)
+        assert rc == B.EINVAL, (d.nx, rtol, mi)
+        assert "invalid" in B.last_error()
+    # workspace too small, or not 256-byte aligned
+    rc = lib.s7_bicgstab_solve(B.Dims(8, 8, 8), coef, 256, 512, 1e-6, 10, 0, 1024, 16, None,
+                               C.byref(info), 0)
+    assert rc == B.EINVAL and "workspace" in B.last_error()
+    rc = lib.s7_bicgstab_solve(B.Dims(8, 8, 8), coef, 256, 512, 1e-6, 10, 0, 1032, 1 << 30, None,
+                               C.byref(info), 0)
+    assert rc == B.EINVAL
+    # u aliasing v
+    rc = lib.s7_stencil_apply(B.Dims(8, 8, 8), coef, 4096, 4096, 0)
+    assert rc == B.EINVAL
