@@ -39,6 +39,23 @@ __device__ __forceinline__ float to_f32(float v) { return v; }
 __device__ __forceinline__ float to_f32(bf16 v) { return __uint_as_float(((uint32_t)v.u) << 16); }
 __device__ __forceinline__ float to_f32(f16 v) { return (float)v; }
 
+// Type tag of a storage type: part of every cache key that depends on it
+// (BF16 and FP16 have the same size).
+template <class T>
+struct TypeTag;
+template <>
+struct TypeTag<float> {
+    static constexpr int value = 0;
+};
+template <>
+struct TypeTag<bf16> {
+    static constexpr int value = 1;
+};
+template <>
+struct TypeTag<f16> {
+    static constexpr int value = 2;
+};
+
 template <class T>
 __device__ __forceinline__ T from_f32(float f);
 template <>

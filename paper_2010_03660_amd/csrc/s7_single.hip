@@ -527,7 +527,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
         }
         for (auto& e : ev) (void)hipEventDestroy(e);
     } else {
-        std::vector<uintptr_t> key = {0x51u, (uintptr_t)sizeof(T), (uintptr_t)R, (uintptr_t)K,
+        std::vector<uintptr_t> key = {0x51u, (uintptr_t)TypeTag<T>::value, (uintptr_t)R, (uintptr_t)K,
                                       (uintptr_t)S.m.nx, (uintptr_t)S.m.ny, (uintptr_t)S.m.nz,
                                       (uintptr_t)S.zt.zc, (uintptr_t)S.unit, (uintptr_t)S.st,
                                       (uintptr_t)S.partials, (uintptr_t)S.r, (uintptr_t)S.c[0],
