@@ -227,6 +227,22 @@ int s7_queue_destroy(s7_queue *q);
 int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float *const coef[7],
                         double *xstar, double *b, void *stream);
 
+/*
+ * Bandwidth probe (diagnostic).  These are STREAM-style kernels (McCalpin):
+ * they measure the HBM rate that plain streaming code reaches, which is the
+ * practical ceiling for the solver's roofline fractions.  n floats per buffer,
+ * a multiple of 8, with 16-byte aligned device buffers.
+ *   kind 0: read-only sum of a.  kind 1: c = a (copy).  kind 2: c = a + 0.5 b
+ *   (triad).  kind 3: six n/2-float read streams (the halves of a, b and c) and
+ *   two write streams (a, b updated in place).  This is the access pattern of
+ *   the BiCGStab x/r update.
+ * Add 4 to kind for non-temporal stores, 8 for non-temporal loads.
+ * width: floats per access (1, 2 or 4).  blocks: grid size (256 threads each).
+ * Asynchronous on `stream`.
+ */
+int s7_bandwidth_probe(int32_t kind, int32_t width, float *a, float *b, float *c, size_t n,
+                       int32_t blocks, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ __all__ = [
     "Dims", "Options", "Info", "Request", "lib", "default_options", "last_error", "version",
     "stencil_apply", "workspace_bytes", "bicgstab_solve", "batched_workspace_bytes",
     "bicgstab_solve_batched", "queue_create", "queue_submit", "queue_poll", "queue_wait",
-    "queue_destroy", "generate_problem", "S7Error",
+    "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
     "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
@@ -89,6 +89,7 @@ EXPORTS = {
     "s7_queue_wait": (C.c_int, [_vp, C.c_uint64, C.POINTER(Info)]),
     "s7_queue_destroy": (C.c_int, [_vp]),
     "s7_generate_problem": (C.c_int, [Dims, C.c_uint64, C.c_int32, C.POINTER(_vp), _vp, _vp, _vp]),
+    "s7_bandwidth_probe": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_size_t, C.c_int32, _vp]),
 }
 
 _lib = None
@@ -257,3 +258,8 @@ def generate_problem(dims, seed: int, recipe: int, coef=None, xstar=None, b=None
     cp = _coef(coef) if coef is not None else None
     _check(lib().s7_generate_problem(_dims(dims), int(seed), int(recipe), cp, _ptr(xstar), _ptr(b),
                                      _stream(stream)), allow=(OK,))
+
+
+def bandwidth_probe(kind: int, width: int, a, b, c, n: int, blocks: int, stream=None) -> None:
+    _check(lib().s7_bandwidth_probe(int(kind), int(width), _ptr(a), _ptr(b), _ptr(c), int(n),
+                                    int(blocks), _stream(stream)), allow=(OK,))

@@ -98,6 +98,70 @@ __device__ __forceinline__ double lane_next(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// ---------------------------------------------------------------- streaming access
+// Non-temporal loads and stores for data touched once per pass (coefficients,
+// r0, and the vectors a pass writes).  The cached path is kept for operands
+// whose halo neighbours re-read them.
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ f16 ld_nt(const f16* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ bf16 ld_nt(const bf16* p) {
+    bf16 r;
+    r.u = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
+    return r;
+}
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(f16* p, f16 v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(bf16* p, bf16 v) {
+    __builtin_nontemporal_store(v.u, reinterpret_cast<uint16_t*>(p));
+}
+
+// Four consecutive elements (8- or 16-byte aligned) as FP32, and back.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void ld4_nt(const float* p, float (&v)[4]) {
+    const f32x4 a = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+}
+__device__ __forceinline__ void ld4_nt(const bf16* p, float (&v)[4]) {
+    const u16x4 a = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
+    v[0] = __uint_as_float((uint32_t)a.x << 16);
+    v[1] = __uint_as_float((uint32_t)a.y << 16);
+    v[2] = __uint_as_float((uint32_t)a.z << 16);
+    v[3] = __uint_as_float((uint32_t)a.w << 16);
+}
+__device__ __forceinline__ void ld4_nt(const f16* p, float (&v)[4]) {
+    const u16x4 a = __builtin_nontemporal_load(reinterpret_cast<const u16x4*>(p));
+    const uint16_t u[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = (float)__builtin_bit_cast(f16, u[i]);
+}
+__device__ __forceinline__ void st4_nt(float* p, const float (&v)[4]) {
+    f32x4 a;
+    a.x = v[0];
+    a.y = v[1];
+    a.z = v[2];
+    a.w = v[3];
+    __builtin_nontemporal_store(a, reinterpret_cast<f32x4*>(p));
+}
+template <class T>
+__device__ __forceinline__ uint16_t bits16(T v);
+template <>
+__device__ __forceinline__ uint16_t bits16<bf16>(bf16 v) { return v.u; }
+template <>
+__device__ __forceinline__ uint16_t bits16<f16>(f16 v) { return __builtin_bit_cast(uint16_t, v); }
+template <class T>
+__device__ __forceinline__ void st4_nt(T* p, const T (&v)[4]) {
+    u16x4 a;
+    a.x = bits16(v[0]);
+    a.y = bits16(v[1]);
+    a.z = bits16(v[2]);
+    a.w = bits16(v[3]);
+    __builtin_nontemporal_store(a, reinterpret_cast<u16x4*>(p));
+}
+
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -255,20 +319,26 @@ __device__ bool reduce_partials(double (&acc)[ND], double* partials, uint32_t* t
 // the arithmetic type.  UNIT: the diagonal is one (Jacobi-scaled system), so
 // only six arrays exist: c[1..6].  MASK: force outward coefficients on the
 // boundary faces to 0, so caller data there (even Inf/NaN) never enters.
-// Summation order: diag v, then xm, xp, ym, yp, zm, zp, by fused multiply-add.
+// load() fetches the raw coefficients of a cell.  apply() forms
+// diag v + xm w + xp e + ym s + yp n + zm b + zp t, in that order, by FMA.
 template <class CT, class V, bool UNIT, bool MASK>
 struct StencilOp {
     const CT* c[7];
     Mesh m;
-    __device__ __forceinline__ V ld(int a, int idx) const { return (V)to_f32v(c[a][idx]); }
-    __device__ __forceinline__ static float to_f32v(float v) { return v; }
-    __device__ __forceinline__ static float to_f32v(bf16 v) { return to_f32(v); }
-    __device__ __forceinline__ static float to_f32v(f16 v) { return to_f32(v); }
-    __device__ __forceinline__ V apply(int idx, int x, int y, int k, V v, V w, V e, V s, V n,
-                                       V b, V t) const {
-        V acc = UNIT ? v : ld(0, idx) * v;
-        V cxm = ld(1, idx), cxp = ld(2, idx), cym = ld(3, idx), cyp = ld(4, idx);
-        V czm = ld(5, idx), czp = ld(6, idx);
+    struct Raw {
+        CT a[7];
+    };
+    __device__ __forceinline__ Raw load(int idx) const {
+        Raw r;
+#pragma unroll
+        for (int a = UNIT ? 1 : 0; a < 7; ++a) r.a[a] = c[a][idx];
+        return r;
+    }
+    __device__ __forceinline__ V apply(const Raw& r, int x, int y, int k, V v, V w, V e, V s,
+                                       V n, V b, V t) const {
+        V acc = UNIT ? v : (V)to_f32(r.a[0]) * v;
+        V cxm = (V)to_f32(r.a[1]), cxp = (V)to_f32(r.a[2]), cym = (V)to_f32(r.a[3]);
+        V cyp = (V)to_f32(r.a[4]), czm = (V)to_f32(r.a[5]), czp = (V)to_f32(r.a[6]);
         if (MASK) {
             cxm = (x > 0) ? cxm : (V)0;
             cxp = (x < m.nx - 1) ? cxp : (V)0;
@@ -290,59 +360,81 @@ struct StencilOp {
 // ---------------------------------------------------------------- z-march engine
 // One wavefront: tile columns x = tx*62-1 .. tx*62+62 (lane = x - tx*62 + 1),
 // rows y = ty*R-1 .. ty*R+R, planes k0-1 .. k1 (k1 exclusive end of the owned
-// chunk).  src.get(idx, own) returns the operand value at a cell; own is true
-// exactly once per owned cell (interior lane, interior row, owned plane).  The
-// source may write its value there (P1 stores p_new).  out.emit(idx, v, Av)
-// runs for every owned cell, planes in order, rows in order.
+// chunk).  Each z-step first issues every load it needs: the operand of plane
+// k+1 on all R+2 rows, and the coefficients and sink inputs of plane k.  Loads
+// go to clamped, in-mesh addresses and are masked afterwards with selects.  So
+// no load waits behind a branch or behind a store that might alias it.  Only
+// stores are predicated.
+//   Src: Raw load(idx); V value(raw, idx, valid, own).  own is true exactly once
+//     per owned cell (interior lane, interior row, owned plane); the source may
+//     then store its value there (P1 stores p_new).
+//   Op:  Raw load(idx); V apply(raw, x, y, k, v, w, e, s, n, b, t).
+//   Out: Raw load(idx); void emit(raw, idx, own, v, Av); acts only where own.
+// Owned cells are visited plane by plane, rows in order.
 template <int R, class Src, class Op, class Out>
 __device__ __forceinline__ void zmarch(const Mesh m, int tx, int ty, int k0, int k1, Src& src,
                                        const Op& op, Out& out) {
     using V = typename Src::V;
+    using SR = typename Src::Raw;
+    using CR = typename Op::Raw;
+    using OR = typename Out::Raw;
     const int lane = threadIdx.x & (kWave - 1);
     const int x = tx * kTileX - 1 + lane;
     const bool xin = (unsigned)x < (unsigned)m.nx;
     const bool xown = xin && lane >= 1 && lane <= kTileX;
+    const int xc = min(max(x, 0), m.nx - 1);
     const int y0 = ty * R - 1;
     const int plane = m.nx * m.ny;
     bool yin[R + 2];
     int rowidx[R + 2];
 #pragma unroll
     for (int t = 0; t < R + 2; ++t) {
-        yin[t] = xin && ((unsigned)(y0 + t) < (unsigned)m.ny);
-        rowidx[t] = x + m.nx * (y0 + t);
+        const int y = y0 + t;
+        yin[t] = xin && ((unsigned)y < (unsigned)m.ny);
+        rowidx[t] = xc + m.nx * min(max(y, 0), m.ny - 1);
     }
     V zlo[R], cur[R + 2], nxt[R + 2];
-    // plane k0 - 1 (halo plane, interior rows only)
+    SR sr[R + 2];
+    {  // planes k0 - 1 (halo plane, interior rows only) and k0 (owned)
+        const int kk = max(k0 - 1, 0);
 #pragma unroll
-    for (int t = 1; t <= R; ++t) {
-        zlo[t - 1] = (V)0;
-        if (k0 > 0 && yin[t]) zlo[t - 1] = src.get(rowidx[t] + plane * (k0 - 1), false);
-    }
-    // plane k0 (owned)
+        for (int t = 1; t <= R; ++t) sr[t] = src.load(rowidx[t] + plane * kk);
 #pragma unroll
-    for (int t = 0; t < R + 2; ++t) {
-        cur[t] = (V)0;
-        if (yin[t]) cur[t] = src.get(rowidx[t] + plane * k0, xown && t >= 1 && t <= R);
+        for (int t = 1; t <= R; ++t)
+            zlo[t - 1] = src.value(sr[t], rowidx[t] + plane * kk, k0 > 0 && yin[t], false);
+#pragma unroll
+        for (int t = 0; t < R + 2; ++t) sr[t] = src.load(rowidx[t] + plane * k0);
+#pragma unroll
+        for (int t = 0; t < R + 2; ++t)
+            cur[t] = src.value(sr[t], rowidx[t] + plane * k0, yin[t],
+                               xown && yin[t] && t >= 1 && t <= R);
     }
     for (int k = k0; k < k1; ++k) {
         const int kn = k + 1;
         const bool kin = kn < m.nz;
         const bool kown = kn < k1;
+        const int kc = kin ? kn : k;
+        CR cr[R];
+        OR orr[R];
+        // ---- loads
 #pragma unroll
-        for (int t = 0; t < R + 2; ++t) {
-            nxt[t] = (V)0;
-            if (kin && yin[t]) nxt[t] = src.get(rowidx[t] + plane * kn, kown && xown && t >= 1 && t <= R);
-        }
+        for (int t = 0; t < R + 2; ++t) sr[t] = src.load(rowidx[t] + plane * kc);
+#pragma unroll
+        for (int t = 1; t <= R; ++t) cr[t - 1] = op.load(rowidx[t] + plane * k);
+#pragma unroll
+        for (int t = 1; t <= R; ++t) orr[t - 1] = out.load(rowidx[t] + plane * k);
+        // ---- compute and stores
+#pragma unroll
+        for (int t = 0; t < R + 2; ++t)
+            nxt[t] = src.value(sr[t], rowidx[t] + plane * kc, kin && yin[t],
+                               kown && xown && yin[t] && t >= 1 && t <= R);
 #pragma unroll
         for (int t = 1; t <= R; ++t) {
             const V w = lane_prev(cur[t]);
             const V e = lane_next(cur[t]);
-            if (xown && yin[t]) {
-                const int idx = rowidx[t] + plane * k;
-                const V av = op.apply(idx, x, y0 + t, k, cur[t], w, e, cur[t - 1], cur[t + 1],
-                                      zlo[t - 1], nxt[t]);
-                out.emit(idx, cur[t], av);
-            }
+            const V av = op.apply(cr[t - 1], x, y0 + t, k, cur[t], w, e, cur[t - 1], cur[t + 1],
+                                  zlo[t - 1], nxt[t]);
+            out.emit(orr[t - 1], rowidx[t] + plane * k, xown && yin[t], cur[t], av);
         }
 #pragma unroll
         for (int t = 1; t <= R; ++t) zlo[t - 1] = cur[t];
@@ -366,39 +458,51 @@ __device__ __forceinline__ bool wave_tile(const ZTiles& zt, const Mesh& m, int L
 }
 
 // ---------------------------------------------------------------- sources and sinks
+struct NoRaw {};
+
 template <class T>
 struct SrcLoad {  // plain operand v
     using V = float;
+    using Raw = T;
     const T* v;
-    __device__ __forceinline__ float get(int idx, bool) const { return to_f32(v[idx]); }
+    __device__ __forceinline__ T load(int idx) const { return v[idx]; }
+    __device__ __forceinline__ float value(T a, int, bool valid, bool) const {
+        return valid ? to_f32(a) : 0.0f;
+    }
 };
 
 struct SrcLoadF64 {
     using V = double;
+    using Raw = double;
     const double* v;
-    __device__ __forceinline__ double get(int idx, bool) const { return v[idx]; }
+    __device__ __forceinline__ double load(int idx) const { return v[idx]; }
+    __device__ __forceinline__ double value(double a, int, bool valid, bool) const {
+        return valid ? a : 0.0;
+    }
 };
 
 // P1 operand: p_{i} = r_i + beta_{i-1} (p_{i-1} - omega_{i-1} s_{i-1}) (Algorithm 1,
 // last update of the previous iteration); p_0 = r_0.  Rounded to the storage
-// type, stored once per owned cell, and applied in its rounded form.
+// type, stored once per owned cell, and applied in its rounded form.  p_old and
+// s_old are read in the first iteration too (and ignored), so the loads never
+// sit behind a branch.
 template <class T>
 struct SrcP1 {
     using V = float;
+    struct Raw {
+        T r, p, s;
+    };
     const T *r, *p_old, *s_old;
     T* p_new;
     float beta, omega;
     bool first;
-    __device__ __forceinline__ float get(int idx, bool own) const {
-        float v;
-        if (first) {
-            v = to_f32(r[idx]);
-        } else {
-            v = fmaT(beta, fmaT(-omega, to_f32(s_old[idx]), to_f32(p_old[idx])), to_f32(r[idx]));
-        }
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{r[idx], p_old[idx], s_old[idx]}; }
+    __device__ __forceinline__ float value(const Raw& a, int idx, bool valid, bool own) const {
+        const float rv = to_f32(a.r);
+        const float v = first ? rv : fmaT(beta, fmaT(-omega, to_f32(a.s), to_f32(a.p)), rv);
         const T vt = from_f32<T>(v);
         if (own) p_new[idx] = vt;
-        return to_f32(vt);
+        return valid ? to_f32(vt) : 0.0f;
     }
 };
 
@@ -406,41 +510,54 @@ struct SrcP1 {
 template <class T>
 struct SrcP2 {
     using V = float;
+    struct Raw {
+        T r, s;
+    };
     const T *r, *s;
     float alpha;
-    __device__ __forceinline__ float get(int idx, bool) const {
-        return fmaT(-alpha, to_f32(s[idx]), to_f32(r[idx]));
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{r[idx], s[idx]}; }
+    __device__ __forceinline__ float value(const Raw& a, int, bool valid, bool) const {
+        const float q = fmaT(-alpha, to_f32(a.s), to_f32(a.r));
+        return valid ? q : 0.0f;
     }
 };
 
 template <class T>
 struct OutStore {
+    using Raw = NoRaw;
     T* u;
-    __device__ __forceinline__ void emit(int idx, float, float av) { u[idx] = from_f32<T>(av); }
+    __device__ __forceinline__ NoRaw load(int) const { return NoRaw{}; }
+    __device__ __forceinline__ void emit(NoRaw, int idx, bool own, float, float av) {
+        if (own) u[idx] = from_f32<T>(av);
+    }
 };
 
 // P1 sink: s_i = A p_i stored; accumulates (r0, s_i).
 template <class T>
 struct OutP1 {
+    using Raw = T;
     T* s;
     const T* rhat;
     double acc[1];
-    __device__ __forceinline__ void emit(int idx, float, float av) {
+    __device__ __forceinline__ T load(int idx) const { return rhat[idx]; }
+    __device__ __forceinline__ void emit(T rh, int idx, bool own, float, float av) {
         const T st = from_f32<T>(av);
-        s[idx] = st;
-        acc[0] = fma((double)to_f32(rhat[idx]), (double)to_f32(st), acc[0]);
+        if (own) s[idx] = st;
+        acc[0] = fma(own ? (double)to_f32(rh) : 0.0, (double)to_f32(st), acc[0]);
     }
 };
 
 // P2 sink: y_i = A q_i stored; accumulates (q, y), (y, y), (q, q).
 template <class T>
 struct OutP2 {
+    using Raw = NoRaw;
     T* y;
     double acc[3];
-    __device__ __forceinline__ void emit(int idx, float q, float av) {
+    __device__ __forceinline__ NoRaw load(int) const { return NoRaw{}; }
+    __device__ __forceinline__ void emit(NoRaw, int idx, bool own, float q, float av) {
         const T yt = from_f32<T>(av);
-        y[idx] = yt;
-        const double yd = (double)to_f32(yt), qd = (double)q;
+        if (own) y[idx] = yt;
+        const double yd = own ? (double)to_f32(yt) : 0.0, qd = own ? (double)q : 0.0;
         acc[0] = fma(qd, yd, acc[0]);
         acc[1] = fma(yd, yd, acc[1]);
         acc[2] = fma(qd, qd, acc[2]);
@@ -515,7 +632,24 @@ __device__ __forceinline__ void wg_p2(const SysView<T>& S, int L, int par, doubl
 
 // P3 over one contiguous chunk: q = r - alpha s; d += alpha p + omega q;
 // r = q - omega y.  Accumulates (r0, r_{i+1}) and (r_{i+1}, r_{i+1}).  In place is
-// safe: every cell reads and writes only itself.
+// safe: every cell reads and writes only itself.  Four consecutive cells per
+// thread and step, with 16-byte (FP32) or 8-byte (16-bit) non-temporal accesses.
+// Chunk bounds are multiples of 8 cells except at the end of the array, so the
+// vector accesses stay aligned; the last chunk's tail (< 4 cells) is scalar.
+template <class T>
+__device__ __forceinline__ void p3_cell(const SysView<T>& S, int i, float alpha, float omega,
+                                        int par, double& a0, double& a1) {
+    const T* p = S.p[par ^ 1];
+    const T* s = S.s[par ^ 1];
+    const float q = fmaT(-alpha, to_f32(s[i]), to_f32(S.r[i]));
+    S.d[i] = fmaT(omega, q, fmaT(alpha, to_f32(p[i]), S.d[i]));
+    const T rn = from_f32<T>(fmaT(-omega, to_f32(S.y[i]), q));
+    S.r[i] = rn;
+    const double rd = (double)to_f32(rn);
+    a0 = fma((double)to_f32(S.rhat[i]), rd, a0);
+    a1 = fma(rd, rd, a1);
+}
+
 template <class T>
 __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, int par, double (&acc)[2]) {
     int i0, i1;
@@ -528,15 +662,32 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, int par, do
     T* __restrict__ r = S.r;
     float* __restrict__ d = S.d;
     double a0 = 0.0, a1 = 0.0;
-    for (int i = i0 + (int)threadIdx.x; i < i1; i += kThreads) {
-        const float q = fmaT(-alpha, to_f32(s[i]), to_f32(r[i]));
-        d[i] = fmaT(omega, q, fmaT(alpha, to_f32(p[i]), d[i]));
-        const T rn = from_f32<T>(fmaT(-omega, to_f32(y[i]), q));
-        r[i] = rn;
-        const double rd = (double)to_f32(rn);
-        a0 = fma((double)to_f32(rh[i]), rd, a0);
-        a1 = fma(rd, rd, a1);
+    const int nv = (i1 - i0) / 4;
+    for (int v = (int)threadIdx.x; v < nv; v += kThreads) {
+        const int i = i0 + 4 * v;
+        float pv[4], sv[4], yv[4], rv[4], hv[4], dv[4];
+        ld4_nt(p + i, pv);
+        ld4_nt(s + i, sv);
+        ld4_nt(y + i, yv);
+        ld4_nt(r + i, rv);
+        ld4_nt(rh + i, hv);
+        ld4_nt(d + i, dv);
+        T rn[4];
+        float rnf[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float q = fmaT(-alpha, sv[j], rv[j]);
+            dv[j] = fmaT(omega, q, fmaT(alpha, pv[j], dv[j]));
+            rn[j] = from_f32<T>(fmaT(-omega, yv[j], q));
+            rnf[j] = to_f32(rn[j]);
+            const double rd = (double)rnf[j];
+            a0 = fma((double)hv[j], rd, a0);
+            a1 = fma(rd, rd, a1);
+        }
+        st4_nt(d + i, dv);
+        st4_nt(r + i, rn);
     }
+    for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads) p3_cell(S, i, alpha, omega, par, a0, a1);
     acc[0] = a0;
     acc[1] = a1;
 }

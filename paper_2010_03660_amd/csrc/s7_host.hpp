@@ -47,10 +47,13 @@ struct TileChoice {
 
 TileChoice choose_tiles(s7_dims d, const s7_options& o, int prec);
 
+// Workgroups of the streaming pass: at most 1024 (mixed read/write streams
+// reach a higher HBM rate with fewer concurrent streams), at least one per
+// 2048 cells.
 inline int stream_blocks_for(long long n) {
     long long b = (n + kThreads * 8 - 1) / (kThreads * 8);
     if (b < 1) b = 1;
-    if (b > 2048) b = 2048;
+    if (b > 1024) b = 1024;
     return (int)b;
 }
 

@@ -150,23 +150,30 @@ __global__ __launch_bounds__(kThreads) void k_prep_coef(Coef7 src, T* dst0, size
 // Jacobi-scaled.  Rounded to FP32 into r and r_hat, and d = 0.  Partials:
 // ||b_s||^2, (r,r) of the rounded r, ||b||^2 unscaled.
 struct OutInitF32 {
+    struct Raw {
+        double b;
+        float dg;
+    };
     const double* b;
     const float* diag;
     float *r, *rhat, *d;
     int jacobi;
     double acc[3];
-    __device__ __forceinline__ void emit(int idx, double, double ax) {
-        const double bi = b[idx];
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{b[idx], diag[idx]}; }
+    __device__ __forceinline__ void emit(const Raw& in, int idx, bool own, double, double ax) {
+        const double bi = own ? in.b : 0.0;
         double r0 = bi - ax, bs = bi;
         if (jacobi) {
-            const double dg = (double)diag[idx];
+            const double dg = own ? (double)in.dg : 1.0;
             r0 = r0 / dg;
             bs = bs / dg;
         }
-        const float rf = (float)r0;
-        r[idx] = rf;
-        rhat[idx] = rf;
-        d[idx] = 0.0f;
+        const float rf = own ? (float)r0 : 0.0f;
+        if (own) {
+            r[idx] = rf;
+            rhat[idx] = rf;
+            d[idx] = 0.0f;
+        }
         acc[0] = fma(bs, bs, acc[0]);
         acc[1] = fma((double)rf, (double)rf, acc[1]);
         acc[2] = fma(bi, bi, acc[2]);
@@ -199,18 +206,24 @@ __global__ __launch_bounds__(kThreads) void k_init_f32(Coef7 cf, const double* b
 // store != 0, r_s goes to dst as FP32: the right-hand side of the next
 // refinement step.
 struct OutResid {
+    struct Raw {
+        double b;
+        float dg;
+    };
     const double* b;
     const float* diag;
     float* dst;
     int jacobi;
     int store;
     double acc[3];
-    __device__ __forceinline__ void emit(int idx, double, double ax) {
-        const double bi = b[idx];
+    __device__ __forceinline__ Raw load(int idx) const { return Raw{b[idx], diag[idx]}; }
+    __device__ __forceinline__ void emit(const Raw& in, int idx, bool own, double, double ax) {
+        if (!own) return;
+        const double bi = in.b;
         const double r0 = bi - ax;
         acc[0] = fma(bi, bi, acc[0]);
         acc[1] = fma(r0, r0, acc[1]);
-        const double rs = jacobi ? r0 / (double)diag[idx] : r0;
+        const double rs = jacobi ? r0 / (double)in.dg : r0;
         const float rf = (float)rs;
         if (store) dst[idx] = rf;
         acc[2] = fmax(acc[2], (double)fabsf(rf));
@@ -378,8 +391,12 @@ __global__ __launch_bounds__(kThreads) void k_gen_coef(Coef7 out, double* xstar,
 }
 
 struct OutF64 {
+    using Raw = NoRaw;
     double* u;
-    __device__ __forceinline__ void emit(int idx, double, double av) { u[idx] = av; }
+    __device__ __forceinline__ NoRaw load(int) const { return NoRaw{}; }
+    __device__ __forceinline__ void emit(NoRaw, int idx, bool own, double, double av) {
+        if (own) u[idx] = av;
+    }
 };
 
 template <int R>
