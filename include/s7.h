@@ -89,8 +89,9 @@ typedef struct {
                                iterated matrix has a unit diagonal (section IV,
                                first paragraph); 0: iterate on A as given */
     int32_t graph_iters;    /* iterations per captured hipGraph launch; 0 = auto */
-    int32_t rows_per_wave;  /* stencil tile rows per wavefront (4 or 8); 0 = auto */
-    int32_t zchunk;         /* z-planes per tile; 0 = auto */
+    int32_t stream_blocks;  /* workgroups of the streaming pass; 0 = auto (at most 1024);
+                               capped at 4096 */
+    int32_t reserved1;
     int32_t profile;        /* 1: launch without graphs, time every pass with HIP
                                events into s7_info.pass_ms */
     int32_t inner_max_iter; /* IR: inner iteration cap per outer step; 0 = 100 */

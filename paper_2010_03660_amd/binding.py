@@ -37,8 +37,8 @@ class Dims(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("jacobi", C.c_int32), ("graph_iters", C.c_int32), ("rows_per_wave", C.c_int32),
-                ("zchunk", C.c_int32), ("profile", C.c_int32), ("inner_max_iter", C.c_int32),
+    _fields_ = [("jacobi", C.c_int32), ("graph_iters", C.c_int32), ("stream_blocks", C.c_int32),
+                ("reserved1", C.c_int32), ("profile", C.c_int32), ("inner_max_iter", C.c_int32),
                 ("outer_max_iter", C.c_int32), ("reserved0", C.c_int32),
                 ("inner_rtol", C.c_double)]
 

@@ -1,20 +1,23 @@
 // Device-side building blocks of the s7 library (gfx950, wave64).
 //
 // * Storage types and round-to-nearest-even conversions (FP32, BF16, FP16).
-// * The z-marching tile engine: one wavefront owns a 62-column x R-row tile
-//   of an x-y plane and marches through a chunk of z-planes.  The planes k-1,
-//   k and k+1 stay in registers.  x-neighbours come from the adjacent lane
-//   (DPP wavefront shift).  y-neighbours come from the adjacent register row.
-//   Lanes 0 and 63 and rows 0 and R+1 hold the tile's x/y halo.  Their values
-//   are computed but never written.
-// * The fused BiCGStab passes over one workgroup tile (4 wavefronts):
-//   P1 (p update on the fly + s = A p + (r0,s)), P2 (q on the fly + y = A q +
-//   three dots) and the streaming P3 (x, r updates + two dots).
-// * Deterministic two-level reductions: FP64 per lane, a fixed wavefront
-//   butterfly, a fixed wave order in LDS, per-workgroup partials, and a final
-//   fixed-order sum by the last workgroup to arrive (atomic ticket).
+// * The cell-parallel stencil: one thread per cell, cells in their natural
+//   x-fastest order, so a workgroup covers 256 consecutive cells.  All seven
+//   operand values and the coefficients are loaded straight from memory.  The
+//   neighbour re-reads (x+-1, y+-1, z+-1) are served by L1, L2 and the
+//   Infinity Cache; HBM sees each array about once.  Loads are branch-free:
+//   an off-mesh neighbour reads the cell itself, and a zero coefficient
+//   cancels it.
+// * The fused BiCGStab passes: P1 (s = A p and (r0,s)), P2 (q on the fly at
+//   all seven positions, y = A q and five dots) and the streaming P3 (x, r
+//   and p updates and two dots).
+// * Deterministic hierarchical reductions: FP64 per lane, a fixed wavefront
+//   butterfly, a fixed wave order in LDS, and per-workgroup partials.  The
+//   last workgroup of each group of 1024 sums the group's partials, and the
+//   last group sums the group partials.  "Last" is decided by atomic tickets,
+//   and every sum runs in a fixed index order.
 // * The scalar steps of Algorithm 1 (alpha, omega, beta, stopping and
-//   breakdown tests), run by one thread of that last workgroup.
+//   breakdown tests), run by one thread of the last workgroup.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,10 +27,10 @@
 namespace s7 {
 
 constexpr int kWave = 64;
-constexpr int kTileX = 62;  // output columns per wavefront: lanes 1..62
-constexpr int kWaves = 4;   // wavefronts per workgroup, stacked in y
+constexpr int kWaves = 4;  // wavefronts per workgroup
 constexpr int kThreads = kWave * kWaves;
-constexpr int kMaxDots = 4;
+constexpr int kMaxDots = 6;
+constexpr int kGroup = 1024;  // workgroups per first-level reduction group
 
 // ---------------------------------------------------------------- types
 struct bf16 {
@@ -75,28 +78,6 @@ __device__ __forceinline__ bf16 from_f32<bf16>(float f) {
 }
 template <>
 __device__ __forceinline__ f16 from_f32<f16>(float f) { return (f16)f; }  // RNE
-
-// ---------------------------------------------------------------- lane shifts
-// DPP wavefront shifts (GFX9 wave_shr:1 / wave_shl:1).  All 64 lanes must be
-// active; lanes with no source read 0.
-__device__ __forceinline__ float lane_prev(float v) {  // value held by lane - 1
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float lane_next(float v) {  // value held by lane + 1
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
-__device__ __forceinline__ double lane_prev(double v) {
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double lane_next(double v) {
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
 
 // ---------------------------------------------------------------- streaming access
 // Non-temporal loads and stores for data touched once per pass (coefficients,
@@ -170,48 +151,100 @@ struct Mesh {
     int nx, ny, nz;
 };
 
-struct ZTiles {
-    int R;         // rows per wavefront tile
-    int zc;        // z-planes per tile
-    int tiles_x;   // ceil(nx / 62)
-    int tiles_y;   // ceil(ny / R)
-    int groups_y;  // ceil(tiles_y / 4): workgroup rows
-    int chunks;    // ceil(nz / zc)
-    int nblocks;   // tiles_x * groups_y * chunks
+// One cell of the mesh and the offsets of its six neighbours.  An off-mesh
+// neighbour gets offset 0: it reads the cell itself, and its coefficient is
+// zero or masked.  Threads past the end take the last cell and own nothing.
+struct Cell {
+    int idx;
+    bool own;
+    int dw, de, ds, dn, db, dt;
 };
 
-__host__ __device__ inline ZTiles make_ztiles(Mesh m, int R, int zc) {
-    ZTiles t;
-    t.R = R;
-    t.zc = zc;
-    t.tiles_x = (m.nx + kTileX - 1) / kTileX;
-    t.tiles_y = (m.ny + R - 1) / R;
-    t.groups_y = (t.tiles_y + kWaves - 1) / kWaves;
-    t.chunks = (m.nz + zc - 1) / zc;
-    t.nblocks = t.tiles_x * t.groups_y * t.chunks;
-    return t;
+__device__ __forceinline__ Cell cell_at(int g, const Mesh& m, int n) {
+    Cell c;
+    c.own = g < n;
+    c.idx = c.own ? g : n - 1;
+    const int plane = m.nx * m.ny;
+    const int k = c.idx / plane;
+    const int rem = c.idx - k * plane;
+    const int j = rem / m.nx;
+    const int i = rem - j * m.nx;
+    c.dw = i > 0 ? -1 : 0;
+    c.de = i < m.nx - 1 ? 1 : 0;
+    c.ds = j > 0 ? -m.nx : 0;
+    c.dn = j < m.ny - 1 ? m.nx : 0;
+    c.db = k > 0 ? -plane : 0;
+    c.dt = k < m.nz - 1 ? plane : 0;
+    return c;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Renumber so that each XCD receives one contiguous run of logical tiles.  The
-// tiles of a run are x-y neighbours, which share halo lines in that L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-    const int nx = 8;
-    const int per = nblocks / nx, rem = nblocks % nx;
-    const int xcd = bid % nx, slot = bid / nx;
-    return (xcd < rem) ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+// The seven operand values of a cell: centre, west, east, south, north,
+// below, above.
+template <class V>
+struct Nbr {
+    V c, w, e, s, n, b, t;
+};
+
+template <class T>
+__device__ __forceinline__ Nbr<T> load_nbr(const T* v, const Cell& c) {
+    const T* p = v + c.idx;
+    return Nbr<T>{p[0], p[c.dw], p[c.de], p[c.ds], p[c.dn], p[c.db], p[c.dt]};
+}
+
+template <class T>
+__device__ __forceinline__ Nbr<float> nbr_f32(const Nbr<T>& a) {
+    return Nbr<float>{to_f32(a.c), to_f32(a.w), to_f32(a.e), to_f32(a.s),
+                      to_f32(a.n), to_f32(a.b), to_f32(a.t)};
+}
+
+// Coefficients of a cell.  UNIT: unit diagonal (Jacobi-scaled copies, c[0]
+// unused).  MASK: zero the coefficient of every off-mesh neighbour, so caller
+// data on the boundary faces (even Inf/NaN) never enters.
+template <class CT, bool UNIT>
+struct Coefs {
+    CT a[7];
+};
+
+template <class CT, bool UNIT>
+__device__ __forceinline__ Coefs<CT, UNIT> load_coefs(const CT* const* c, int idx) {
+    Coefs<CT, UNIT> r;
+#pragma unroll
+    for (int a = UNIT ? 1 : 0; a < 7; ++a) r.a[a] = c[a][idx];
+    return r;
+}
+
+// diag v + xm w + xp e + ym s + yp n + zm b + zp t, in that order, by FMA.
+template <class V, class CT, bool UNIT, bool MASK>
+__device__ __forceinline__ V apply7(const Coefs<CT, UNIT>& k, const Nbr<V>& v, const Cell& c) {
+    V cw = (V)to_f32(k.a[1]), ce = (V)to_f32(k.a[2]), cs = (V)to_f32(k.a[3]);
+    V cn = (V)to_f32(k.a[4]), cb = (V)to_f32(k.a[5]), ct = (V)to_f32(k.a[6]);
+    if (MASK) {
+        cw = c.dw ? cw : (V)0;
+        ce = c.de ? ce : (V)0;
+        cs = c.ds ? cs : (V)0;
+        cn = c.dn ? cn : (V)0;
+        cb = c.db ? cb : (V)0;
+        ct = c.dt ? ct : (V)0;
+    }
+    V acc = UNIT ? v.c : (V)to_f32(k.a[0]) * v.c;
+    acc = fmaT(cw, v.w, acc);
+    acc = fmaT(ce, v.e, acc);
+    acc = fmaT(cs, v.s, acc);
+    acc = fmaT(cn, v.n, acc);
+    acc = fmaT(cb, v.b, acc);
+    acc = fmaT(ct, v.t, acc);
+    return acc;
 }
 
 // ---------------------------------------------------------------- solver state
 struct State {
-    double rho, alpha, omega, beta;  // (r0, r_i), alpha_i, omega_i, beta_{i-1}
-    double sigma, qy, yy, qq;        // (r0, s), (q, y), (y, y), (q, q)
-    double rr, nb, tol, res_rec;     // (r, r), ||b|| of the iterated system, rtol, last ||r||/||b||
-    double bb_true, rr_true, rmax, scale;  // unscaled ||b||^2, ||b - A x||^2, max |r|, IR scale
+    double rho, alpha, omega, beta;   // (r0, r_i), alpha_i, omega_i, beta_i
+    double sigma, qy, yy, qq;         // (r0, s), (q, y), (y, y), (q, q)
+    double rq, ry, rr, nb;            // (r0, q), (r0, y), (r, r), ||b|| of the iterated system
+    double tol, res_rec, bb_true, rr_true;  // rtol, last ||r||/||b||, unscaled ||b||^2, ||b - A x||^2
+    double rmax, scale, pad_d[2];     // max |r_s| of the last residual pass, IR scale
     int32_t iter, max_iter, done, status;
-    int32_t reason, half, first, nbzero;
-    int32_t pad[8];
-    alignas(256) uint32_t ticket;  // arrival counter of the last-block reduction
+    int32_t reason, half, beta_bad, nbzero;
 };
 
 enum : int32_t { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2 };
@@ -224,17 +257,27 @@ __device__ __forceinline__ void set_breakdown(State* st, int32_t reason) {
 }
 
 // ---------------------------------------------------------------- reductions
-template <int ND>
-__device__ __forceinline__ void wave_sum(double (&a)[ND]) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int j = 0; j < ND; ++j) {
-            double o = __shfl_xor(a[j], off, kWave);
-            a[j] = a[j] + o;
-        }
-    }
-}
+// Reduction scratch of one system: per-workgroup partials, second-level
+// partials and one arrival counter (zero between uses).
+//
+// A grid-wide sum ends in a "last workgroup" step, decided by an atomic ticket
+// after a release fence.  On this multi-XCD device an agent-scope release
+// fence writes back the XCD's L2, which is cheap a few thousand times per
+// pass but ruinous millions of times.  So passes with at most kSingleMax
+// workgroups finish their sums in-kernel.  Larger passes only store their
+// workgroup partials, and a second kernel (k_finish) sums them in blocks of
+// kGroup, then finishes with the ticket among its own workgroups.  Every sum
+// runs in a fixed index order, so the result never depends on arrival order.
+struct Red {
+    double* part;
+    double* gpart;
+    uint32_t* cnt;
+};
+
+constexpr int kSingleMax = 4096;
+
+__host__ __device__ inline int red_groups(int nblocks) { return (nblocks + kGroup - 1) / kGroup; }
+__host__ __device__ inline bool red_split(int nblocks) { return nblocks > kSingleMax; }
 
 // Values j with bit j of MAXMASK set reduce with max, the others with +.
 template <int ND, unsigned MAXMASK>
@@ -249,19 +292,20 @@ __device__ __forceinline__ void wave_reduce(double (&a)[ND]) {
     }
 }
 
-// Block partial of this workgroup -> partials[slot*ND + j].  Then the arrival
-// ticket.  The last workgroup to arrive reduces every partial in a fixed
-// order into tot[] (valid in thread 0) and resets the ticket.  Returns true in
-// all threads of that workgroup.  The result does not depend on which
-// workgroup arrives last.
-template <int ND, unsigned MAXMASK = 0u>
-__device__ bool reduce_partials(double (&acc)[ND], double* partials, uint32_t* ticket,
-                                int nslots, int slot, double (&tot)[ND]) {
+template <int ND, unsigned MAXMASK>
+__device__ __forceinline__ double comb(int j, double a, double b) {
+    return ((MAXMASK >> j) & 1u) ? fmax(a, b) : a + b;
+}
+
+// Workgroup sum of acc (fixed butterfly, then waves in order).  out is written
+// in thread 0 only; the other threads' out is left as it was.
+template <int ND, unsigned MAXMASK>
+__device__ __forceinline__ void block_reduce(double (&acc)[ND], double (&out)[ND]) {
     __shared__ double sm[kWaves][kMaxDots];
-    __shared__ int last;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     wave_reduce<ND, MAXMASK>(acc);
+    __syncthreads();
     if (lane == 0) {
 #pragma unroll
         for (int j = 0; j < ND; ++j) sm[wave][j] = acc[j];
@@ -272,313 +316,100 @@ __device__ bool reduce_partials(double (&acc)[ND], double* partials, uint32_t* t
         for (int j = 0; j < ND; ++j) {
             double v = sm[0][j];
 #pragma unroll
-            for (int w = 1; w < kWaves; ++w)
-                v = ((MAXMASK >> j) & 1u) ? fmax(v, sm[w][j]) : v + sm[w][j];
-            partials[(size_t)slot * ND + j] = v;
+            for (int w = 1; w < kWaves; ++w) v = comb<ND, MAXMASK>(j, v, sm[w][j]);
+            out[j] = v;
         }
-        __threadfence();
-        uint32_t t = atomicAdd(ticket, 1u);
-        last = (t == (uint32_t)(nslots - 1));
     }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+}
+
+// Sums src[i*ND + j] for i in [i0, i1) into out (thread 0), in a fixed order.
+template <int ND, unsigned MAXMASK>
+__device__ __forceinline__ void sum_range(const double* src, int i0, int i1, double (&out)[ND]) {
     double s[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) s[j] = 0.0;
-    for (int b = threadIdx.x; b < nslots; b += kThreads) {
+    for (int b = i0 + (int)threadIdx.x; b < i1; b += kThreads) {
 #pragma unroll
-        for (int j = 0; j < ND; ++j) {
-            double v = __builtin_nontemporal_load(&partials[(size_t)b * ND + j]);
-            s[j] = ((MAXMASK >> j) & 1u) ? fmax(s[j], v) : s[j] + v;
-        }
+        for (int j = 0; j < ND; ++j)
+            s[j] = comb<ND, MAXMASK>(j, s[j], __builtin_nontemporal_load(&src[(size_t)b * ND + j]));
     }
-    wave_reduce<ND, MAXMASK>(s);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < ND; ++j) sm[wave][j] = s[j];
-    }
-    __syncthreads();
+    block_reduce<ND, MAXMASK>(s, out);
+}
+
+// In-kernel completion: the workgroup sum goes to part[bid]; the last of nblocks
+// workgroups to arrive sums part[0..nblocks) into tot (thread 0) and returns
+// true in all its threads.
+template <int ND, unsigned MAXMASK = 0u>
+__device__ bool reduce_ticket(double (&acc)[ND], double* part, uint32_t* cnt, int nblocks, int bid,
+                              double (&tot)[ND]) {
+    __shared__ int flag;
+    double bsum[ND];
+    block_reduce<ND, MAXMASK>(acc, bsum);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int j = 0; j < ND; ++j) {
-            double v = sm[0][j];
-#pragma unroll
-            for (int w = 1; w < kWaves; ++w)
-                v = ((MAXMASK >> j) & 1u) ? fmax(v, sm[w][j]) : v + sm[w][j];
-            tot[j] = v;
-        }
-        *ticket = 0u;
+        for (int j = 0; j < ND; ++j) part[(size_t)bid * ND + j] = bsum[j];
+        __threadfence();
+        flag = (atomicAdd(cnt, 1u) == (uint32_t)(nblocks - 1));
     }
+    __syncthreads();
+    if (!flag) return false;
+    __threadfence();
+    sum_range<ND, MAXMASK>(part, 0, nblocks, tot);
+    if (threadIdx.x == 0) *cnt = 0u;
     return true;
 }
 
-// ---------------------------------------------------------------- stencil operator
-// Coefficient access for the z-march.  CT is the stored coefficient type.  V is
-// the arithmetic type.  UNIT: the diagonal is one (Jacobi-scaled system), so
-// only six arrays exist: c[1..6].  MASK: force outward coefficients on the
-// boundary faces to 0, so caller data there (even Inf/NaN) never enters.
-// load() fetches the raw coefficients of a cell.  apply() forms
-// diag v + xm w + xp e + ym s + yp n + zm b + zp t, in that order, by FMA.
-template <class CT, class V, bool UNIT, bool MASK>
-struct StencilOp {
-    const CT* c[7];
-    Mesh m;
-    struct Raw {
-        CT a[7];
-    };
-    __device__ __forceinline__ Raw load(int idx) const {
-        Raw r;
+// Split completion, first half: store the workgroup sum only.
+template <int ND, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void reduce_store(double (&acc)[ND], double* part, int bid) {
+    double bsum[ND];
+    block_reduce<ND, MAXMASK>(acc, bsum);
+    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int a = UNIT ? 1 : 0; a < 7; ++a) r.a[a] = c[a][idx];
-        return r;
-    }
-    __device__ __forceinline__ V apply(const Raw& r, int x, int y, int k, V v, V w, V e, V s,
-                                       V n, V b, V t) const {
-        V acc = UNIT ? v : (V)to_f32(r.a[0]) * v;
-        V cxm = (V)to_f32(r.a[1]), cxp = (V)to_f32(r.a[2]), cym = (V)to_f32(r.a[3]);
-        V cyp = (V)to_f32(r.a[4]), czm = (V)to_f32(r.a[5]), czp = (V)to_f32(r.a[6]);
-        if (MASK) {
-            cxm = (x > 0) ? cxm : (V)0;
-            cxp = (x < m.nx - 1) ? cxp : (V)0;
-            cym = (y > 0) ? cym : (V)0;
-            cyp = (y < m.ny - 1) ? cyp : (V)0;
-            czm = (k > 0) ? czm : (V)0;
-            czp = (k < m.nz - 1) ? czp : (V)0;
-        }
-        acc = fmaT(cxm, w, acc);
-        acc = fmaT(cxp, e, acc);
-        acc = fmaT(cym, s, acc);
-        acc = fmaT(cyp, n, acc);
-        acc = fmaT(czm, b, acc);
-        acc = fmaT(czp, t, acc);
-        return acc;
-    }
-};
-
-// ---------------------------------------------------------------- z-march engine
-// One wavefront: tile columns x = tx*62-1 .. tx*62+62 (lane = x - tx*62 + 1),
-// rows y = ty*R-1 .. ty*R+R, planes k0-1 .. k1 (k1 exclusive end of the owned
-// chunk).  Each z-step first issues every load it needs: the operand of plane
-// k+1 on all R+2 rows, and the coefficients and sink inputs of plane k.  Loads
-// go to clamped, in-mesh addresses and are masked afterwards with selects.  So
-// no load waits behind a branch or behind a store that might alias it.  Only
-// stores are predicated.
-//   Src: Raw load(idx); V value(raw, idx, valid, own).  own is true exactly once
-//     per owned cell (interior lane, interior row, owned plane); the source may
-//     then store its value there (P1 stores p_new).
-//   Op:  Raw load(idx); V apply(raw, x, y, k, v, w, e, s, n, b, t).
-//   Out: Raw load(idx); void emit(raw, idx, own, v, Av); acts only where own.
-// Owned cells are visited plane by plane, rows in order.
-template <int R, class Src, class Op, class Out>
-__device__ __forceinline__ void zmarch(const Mesh m, int tx, int ty, int k0, int k1, Src& src,
-                                       const Op& op, Out& out) {
-    using V = typename Src::V;
-    using SR = typename Src::Raw;
-    using CR = typename Op::Raw;
-    using OR = typename Out::Raw;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int x = tx * kTileX - 1 + lane;
-    const bool xin = (unsigned)x < (unsigned)m.nx;
-    const bool xown = xin && lane >= 1 && lane <= kTileX;
-    const int xc = min(max(x, 0), m.nx - 1);
-    const int y0 = ty * R - 1;
-    const int plane = m.nx * m.ny;
-    bool yin[R + 2];
-    int rowidx[R + 2];
-#pragma unroll
-    for (int t = 0; t < R + 2; ++t) {
-        const int y = y0 + t;
-        yin[t] = xin && ((unsigned)y < (unsigned)m.ny);
-        rowidx[t] = xc + m.nx * min(max(y, 0), m.ny - 1);
-    }
-    V zlo[R], cur[R + 2], nxt[R + 2];
-    SR sr[R + 2];
-    {  // planes k0 - 1 (halo plane, interior rows only) and k0 (owned)
-        const int kk = max(k0 - 1, 0);
-#pragma unroll
-        for (int t = 1; t <= R; ++t) sr[t] = src.load(rowidx[t] + plane * kk);
-#pragma unroll
-        for (int t = 1; t <= R; ++t)
-            zlo[t - 1] = src.value(sr[t], rowidx[t] + plane * kk, k0 > 0 && yin[t], false);
-#pragma unroll
-        for (int t = 0; t < R + 2; ++t) sr[t] = src.load(rowidx[t] + plane * k0);
-#pragma unroll
-        for (int t = 0; t < R + 2; ++t)
-            cur[t] = src.value(sr[t], rowidx[t] + plane * k0, yin[t],
-                               xown && yin[t] && t >= 1 && t <= R);
-    }
-    for (int k = k0; k < k1; ++k) {
-        const int kn = k + 1;
-        const bool kin = kn < m.nz;
-        const bool kown = kn < k1;
-        const int kc = kin ? kn : k;
-        CR cr[R];
-        OR orr[R];
-        // ---- loads
-#pragma unroll
-        for (int t = 0; t < R + 2; ++t) sr[t] = src.load(rowidx[t] + plane * kc);
-#pragma unroll
-        for (int t = 1; t <= R; ++t) cr[t - 1] = op.load(rowidx[t] + plane * k);
-#pragma unroll
-        for (int t = 1; t <= R; ++t) orr[t - 1] = out.load(rowidx[t] + plane * k);
-        // ---- compute and stores
-#pragma unroll
-        for (int t = 0; t < R + 2; ++t)
-            nxt[t] = src.value(sr[t], rowidx[t] + plane * kc, kin && yin[t],
-                               kown && xown && yin[t] && t >= 1 && t <= R);
-#pragma unroll
-        for (int t = 1; t <= R; ++t) {
-            const V w = lane_prev(cur[t]);
-            const V e = lane_next(cur[t]);
-            const V av = op.apply(cr[t - 1], x, y0 + t, k, cur[t], w, e, cur[t - 1], cur[t + 1],
-                                  zlo[t - 1], nxt[t]);
-            out.emit(orr[t - 1], rowidx[t] + plane * k, xown && yin[t], cur[t], av);
-        }
-#pragma unroll
-        for (int t = 1; t <= R; ++t) zlo[t - 1] = cur[t];
-#pragma unroll
-        for (int t = 0; t < R + 2; ++t) cur[t] = nxt[t];
+        for (int j = 0; j < ND; ++j) part[(size_t)bid * ND + j] = bsum[j];
     }
 }
 
-// Decode a (remapped) workgroup index into this wavefront's tile.  Returns
-// false if the wavefront has no rows (the last workgroup row may be short).
-__device__ __forceinline__ bool wave_tile(const ZTiles& zt, const Mesh& m, int L, int& tx, int& ty,
-                                          int& k0, int& k1) {
-    tx = L % zt.tiles_x;
-    int rest = L / zt.tiles_x;
-    const int gy = rest % zt.groups_y;
-    const int tz = rest / zt.groups_y;
-    ty = gy * kWaves + (int)(threadIdx.x / kWave);
-    k0 = tz * zt.zc;
-    k1 = min(m.nz, k0 + zt.zc);
-    return ty < zt.tiles_y;
+// Grid-wide sum: in-kernel for small grids (returns true in the completing
+// workgroup), or the first half of a split sum (returns false; k_finish ends it).
+template <int ND, unsigned MAXMASK = 0u>
+__device__ __forceinline__ bool grid_reduce(double (&acc)[ND], const Red& red, int nblocks, int bid,
+                                            double (&tot)[ND]) {
+    if (red_split(nblocks)) {
+        reduce_store<ND, MAXMASK>(acc, red.part, bid);
+        return false;
+    }
+    return reduce_ticket<ND, MAXMASK>(acc, red.part, red.cnt, nblocks, bid, tot);
 }
 
-// ---------------------------------------------------------------- sources and sinks
-struct NoRaw {};
-
-template <class T>
-struct SrcLoad {  // plain operand v
-    using V = float;
-    using Raw = T;
-    const T* v;
-    __device__ __forceinline__ T load(int idx) const { return v[idx]; }
-    __device__ __forceinline__ float value(T a, int, bool valid, bool) const {
-        return valid ? to_f32(a) : 0.0f;
-    }
-};
-
-struct SrcLoadF64 {
-    using V = double;
-    using Raw = double;
-    const double* v;
-    __device__ __forceinline__ double load(int idx) const { return v[idx]; }
-    __device__ __forceinline__ double value(double a, int, bool valid, bool) const {
-        return valid ? a : 0.0;
-    }
-};
-
-// P1 operand: p_{i} = r_i + beta_{i-1} (p_{i-1} - omega_{i-1} s_{i-1}) (Algorithm 1,
-// last update of the previous iteration); p_0 = r_0.  Rounded to the storage
-// type, stored once per owned cell, and applied in its rounded form.  p_old and
-// s_old are read in the first iteration too (and ignored), so the loads never
-// sit behind a branch.
-template <class T>
-struct SrcP1 {
-    using V = float;
-    struct Raw {
-        T r, p, s;
-    };
-    const T *r, *p_old, *s_old;
-    T* p_new;
-    float beta, omega;
-    bool first;
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{r[idx], p_old[idx], s_old[idx]}; }
-    __device__ __forceinline__ float value(const Raw& a, int idx, bool valid, bool own) const {
-        const float rv = to_f32(a.r);
-        const float v = first ? rv : fmaT(beta, fmaT(-omega, to_f32(a.s), to_f32(a.p)), rv);
-        const T vt = from_f32<T>(v);
-        if (own) p_new[idx] = vt;
-        return valid ? to_f32(vt) : 0.0f;
-    }
-};
-
-// P2 operand: q_i = r_i - alpha_i s_i, formed in FP32 and never stored.
-template <class T>
-struct SrcP2 {
-    using V = float;
-    struct Raw {
-        T r, s;
-    };
-    const T *r, *s;
-    float alpha;
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{r[idx], s[idx]}; }
-    __device__ __forceinline__ float value(const Raw& a, int, bool valid, bool) const {
-        const float q = fmaT(-alpha, to_f32(a.s), to_f32(a.r));
-        return valid ? q : 0.0f;
-    }
-};
-
-template <class T>
-struct OutStore {
-    using Raw = NoRaw;
-    T* u;
-    __device__ __forceinline__ NoRaw load(int) const { return NoRaw{}; }
-    __device__ __forceinline__ void emit(NoRaw, int idx, bool own, float, float av) {
-        if (own) u[idx] = from_f32<T>(av);
-    }
-};
-
-// P1 sink: s_i = A p_i stored; accumulates (r0, s_i).
-template <class T>
-struct OutP1 {
-    using Raw = T;
-    T* s;
-    const T* rhat;
-    double acc[1];
-    __device__ __forceinline__ T load(int idx) const { return rhat[idx]; }
-    __device__ __forceinline__ void emit(T rh, int idx, bool own, float, float av) {
-        const T st = from_f32<T>(av);
-        if (own) s[idx] = st;
-        acc[0] = fma(own ? (double)to_f32(rh) : 0.0, (double)to_f32(st), acc[0]);
-    }
-};
-
-// P2 sink: y_i = A q_i stored; accumulates (q, y), (y, y), (q, q).
-template <class T>
-struct OutP2 {
-    using Raw = NoRaw;
-    T* y;
-    double acc[3];
-    __device__ __forceinline__ NoRaw load(int) const { return NoRaw{}; }
-    __device__ __forceinline__ void emit(NoRaw, int idx, bool own, float q, float av) {
-        const T yt = from_f32<T>(av);
-        if (own) y[idx] = yt;
-        const double yd = own ? (double)to_f32(yt) : 0.0, qd = own ? (double)q : 0.0;
-        acc[0] = fma(qd, yd, acc[0]);
-        acc[1] = fma(yd, yd, acc[1]);
-        acc[2] = fma(qd, qd, acc[2]);
-    }
-};
+// Split completion, second half, run by the finishing kernel's workgroups:
+// workgroup g sums part[g*kGroup .. ) and the last one sums those sums.
+template <int ND, unsigned MAXMASK = 0u>
+__device__ __forceinline__ bool finish_split(const Red& red, int nblocks, double (&tot)[ND]) {
+    // The group sum lands in thread 0 only; the other threads contribute zeros
+    // (the identity of both + and max over non-negative values) to the ticket sum.
+    double gs[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) gs[j] = 0.0;
+    const int g = blockIdx.x;
+    sum_range<ND, MAXMASK>(red.part, g * kGroup, min(nblocks, (g + 1) * kGroup), gs);
+    return reduce_ticket<ND, MAXMASK>(gs, red.gpart, red.cnt, (int)gridDim.x, g, tot);
+}
 
 // ---------------------------------------------------------------- system view
 // Everything one BiCGStab system needs on the device.  coef: 6 (unit
-// diagonal) or 7 working-precision arrays with outward links zeroed.
+// diagonal, c[1..6]) or 7 working-precision arrays with outward links zeroed.
 template <class T>
 struct SysView {
     Mesh m;
-    ZTiles zt;
     int n;
-    int unit;          // 1: Jacobi-scaled (unit diagonal, c[1..6] used)
+    int unit;          // 1: Jacobi-scaled (unit diagonal)
     const T* c[7];
-    T *r, *rhat, *y;
-    T *p[2], *s[2];
+    T *r, *rhat, *p, *s, *y;
     float* d;          // FP32 correction accumulated by the iteration
     State* st;
-    double* partials;
+    Red red;
+    int cell_blocks;   // workgroups of the cell-parallel passes: ceil(n / 256)
     int stream_blocks; // workgroups of the streaming pass
 };
 
@@ -591,72 +422,68 @@ __host__ __device__ inline void stream_range(int n, int nb, int b, int& i0, int&
     i1 = min(n, (b + 1) * per * 8);
 }
 
-// P1 over one workgroup tile.  Returns the partial (r0, s) in acc[0].
-template <class T, int R>
-__device__ __forceinline__ void wg_p1(const SysView<T>& S, int L, int par, double (&acc)[1]) {
-    int tx, ty, k0, k1;
-    acc[0] = 0.0;
-    if (!wave_tile(S.zt, S.m, L, tx, ty, k0, k1)) return;
-    SrcP1<T> src{S.r, S.p[par], S.s[par], S.p[par ^ 1], (float)S.st->beta, (float)S.st->omega,
-                 S.st->first != 0};
-    OutP1<T> out{S.s[par ^ 1], S.rhat, {0.0}};
-    if (S.unit) {
-        StencilOp<T, float, true, false> op{{S.c[0], S.c[1], S.c[2], S.c[3], S.c[4], S.c[5], S.c[6]}, S.m};
-        zmarch<R>(S.m, tx, ty, k0, k1, src, op, out);
-    } else {
-        StencilOp<T, float, false, false> op{{S.c[0], S.c[1], S.c[2], S.c[3], S.c[4], S.c[5], S.c[6]}, S.m};
-        zmarch<R>(S.m, tx, ty, k0, k1, src, op, out);
-    }
-    acc[0] = out.acc[0];
+// P1 at one cell: s = A p; partial (r0, s).
+template <class T, bool UNIT>
+__device__ __forceinline__ void cell_p1(const SysView<T>& S, int g, double (&acc)[1]) {
+    const Cell c = cell_at(g, S.m, S.n);
+    const Nbr<float> pv = nbr_f32(load_nbr(S.p, c));
+    const Coefs<T, UNIT> k = load_coefs<T, UNIT>(S.c, c.idx);
+    const T rh = S.rhat[c.idx];
+    const T sv = from_f32<T>(apply7<float, T, UNIT, false>(k, pv, c));
+    if (c.own) S.s[c.idx] = sv;
+    acc[0] = c.own ? (double)to_f32(rh) * (double)to_f32(sv) : 0.0;
 }
 
-// P2 over one workgroup tile (reads s of parity par^1, the one P1 wrote).
-template <class T, int R>
-__device__ __forceinline__ void wg_p2(const SysView<T>& S, int L, int par, double (&acc)[3]) {
-    int tx, ty, k0, k1;
-    acc[0] = acc[1] = acc[2] = 0.0;
-    if (!wave_tile(S.zt, S.m, L, tx, ty, k0, k1)) return;
-    SrcP2<T> src{S.r, S.s[par ^ 1], (float)S.st->alpha};
-    OutP2<T> out{S.y, {0.0, 0.0, 0.0}};
-    if (S.unit) {
-        StencilOp<T, float, true, false> op{{S.c[0], S.c[1], S.c[2], S.c[3], S.c[4], S.c[5], S.c[6]}, S.m};
-        zmarch<R>(S.m, tx, ty, k0, k1, src, op, out);
-    } else {
-        StencilOp<T, float, false, false> op{{S.c[0], S.c[1], S.c[2], S.c[3], S.c[4], S.c[5], S.c[6]}, S.m};
-        zmarch<R>(S.m, tx, ty, k0, k1, src, op, out);
-    }
-    acc[0] = out.acc[0];
-    acc[1] = out.acc[1];
-    acc[2] = out.acc[2];
+// P2 at one cell: q = r - alpha s at all seven positions (FP32, never stored),
+// y = A q stored; partials (q,y), (y,y), (q,q), (r0,q), (r0,y).
+template <class T, bool UNIT>
+__device__ __forceinline__ void cell_p2(const SysView<T>& S, int g, float alpha, double (&acc)[5]) {
+    const Cell c = cell_at(g, S.m, S.n);
+    const Nbr<float> rv = nbr_f32(load_nbr(S.r, c));
+    const Nbr<float> sv = nbr_f32(load_nbr(S.s, c));
+    const Coefs<T, UNIT> k = load_coefs<T, UNIT>(S.c, c.idx);
+    const double rh = (double)to_f32(S.rhat[c.idx]);
+    Nbr<float> q;
+    q.c = fmaT(-alpha, sv.c, rv.c);
+    q.w = fmaT(-alpha, sv.w, rv.w);
+    q.e = fmaT(-alpha, sv.e, rv.e);
+    q.s = fmaT(-alpha, sv.s, rv.s);
+    q.n = fmaT(-alpha, sv.n, rv.n);
+    q.b = fmaT(-alpha, sv.b, rv.b);
+    q.t = fmaT(-alpha, sv.t, rv.t);
+    const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k, q, c));
+    if (c.own) S.y[c.idx] = yt;
+    const double yd = c.own ? (double)to_f32(yt) : 0.0;
+    const double qd = c.own ? (double)q.c : 0.0;
+    acc[0] = qd * yd;
+    acc[1] = yd * yd;
+    acc[2] = qd * qd;
+    acc[3] = rh * qd;
+    acc[4] = rh * yd;
 }
 
 // P3 over one contiguous chunk: q = r - alpha s; d += alpha p + omega q;
-// r = q - omega y.  Accumulates (r0, r_{i+1}) and (r_{i+1}, r_{i+1}).  In place is
-// safe: every cell reads and writes only itself.  Four consecutive cells per
-// thread and step, with 16-byte (FP32) or 8-byte (16-bit) non-temporal accesses.
-// Chunk bounds are multiples of 8 cells except at the end of the array, so the
-// vector accesses stay aligned; the last chunk's tail (< 4 cells) is scalar.
+// r = q - omega y; p = r + beta (p - omega s).  Accumulates (r0, r_{i+1}) and
+// (r_{i+1}, r_{i+1}).  In place is safe: every cell reads and writes only
+// itself.  Four consecutive cells per thread and step, with 16-byte (FP32) or
+// 8-byte (16-bit) non-temporal accesses.  Chunk bounds are multiples of 8
+// cells except at the end of the array; the last chunk's tail is scalar.
 template <class T>
-__device__ __forceinline__ void p3_cell(const SysView<T>& S, int i, float alpha, float omega,
-                                        int par, double& a0, double& a1) {
-    const T* p = S.p[par ^ 1];
-    const T* s = S.s[par ^ 1];
-    const float q = fmaT(-alpha, to_f32(s[i]), to_f32(S.r[i]));
-    S.d[i] = fmaT(omega, q, fmaT(alpha, to_f32(p[i]), S.d[i]));
-    const T rn = from_f32<T>(fmaT(-omega, to_f32(S.y[i]), q));
-    S.r[i] = rn;
-    const double rd = (double)to_f32(rn);
-    a0 = fma((double)to_f32(S.rhat[i]), rd, a0);
-    a1 = fma(rd, rd, a1);
+__device__ __forceinline__ void p3_math(float alpha, float omega, float beta, float pv, float sv,
+                                        float yv, float rv, float& dv, T& rn, T& pn) {
+    const float q = fmaT(-alpha, sv, rv);
+    dv = fmaT(omega, q, fmaT(alpha, pv, dv));
+    rn = from_f32<T>(fmaT(-omega, yv, q));
+    pn = from_f32<T>(fmaT(beta, fmaT(-omega, sv, pv), to_f32(rn)));
 }
 
 template <class T>
-__device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, int par, double (&acc)[2]) {
+__device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&acc)[2]) {
     int i0, i1;
     stream_range(S.n, S.stream_blocks, b, i0, i1);
-    const float alpha = (float)S.st->alpha, omega = (float)S.st->omega;
-    const T* __restrict__ p = S.p[par ^ 1];
-    const T* __restrict__ s = S.s[par ^ 1];
+    const float alpha = (float)S.st->alpha, omega = (float)S.st->omega, beta = (float)S.st->beta;
+    T* __restrict__ p = S.p;
+    const T* __restrict__ s = S.s;
     const T* __restrict__ y = S.y;
     const T* __restrict__ rh = S.rhat;
     T* __restrict__ r = S.r;
@@ -672,22 +499,30 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, int par, do
         ld4_nt(r + i, rv);
         ld4_nt(rh + i, hv);
         ld4_nt(d + i, dv);
-        T rn[4];
-        float rnf[4];
+        T rn[4], pn[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const float q = fmaT(-alpha, sv[j], rv[j]);
-            dv[j] = fmaT(omega, q, fmaT(alpha, pv[j], dv[j]));
-            rn[j] = from_f32<T>(fmaT(-omega, yv[j], q));
-            rnf[j] = to_f32(rn[j]);
-            const double rd = (double)rnf[j];
+            p3_math<T>(alpha, omega, beta, pv[j], sv[j], yv[j], rv[j], dv[j], rn[j], pn[j]);
+            const double rd = (double)to_f32(rn[j]);
             a0 = fma((double)hv[j], rd, a0);
             a1 = fma(rd, rd, a1);
         }
         st4_nt(d + i, dv);
         st4_nt(r + i, rn);
+        st4_nt(p + i, pn);
     }
-    for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads) p3_cell(S, i, alpha, omega, par, a0, a1);
+    for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads) {
+        float dv = d[i];
+        T rn, pn;
+        p3_math<T>(alpha, omega, beta, to_f32(p[i]), to_f32(s[i]), to_f32(y[i]), to_f32(r[i]), dv,
+                   rn, pn);
+        d[i] = dv;
+        r[i] = rn;
+        p[i] = pn;
+        const double rd = (double)to_f32(rn);
+        a0 = fma((double)to_f32(rh[i]), rd, a0);
+        a1 = fma(rd, rd, a1);
+    }
     acc[0] = a0;
     acc[1] = a1;
 }
@@ -709,11 +544,19 @@ __device__ __forceinline__ void tail_p1(State* st, const double (&tot)[1]) {
     st->alpha = a;
 }
 
-// After P2: half-step test on ||q||, else omega_i = (q, y) / (y, y).
-__device__ __forceinline__ void tail_p2(State* st, const double (&tot)[3]) {
+// After P2: half-step test on ||q||, else omega_i = (q, y) / (y, y), and
+// beta_i = (alpha_i / omega_i) rho_{i+1} / rho_i with rho_{i+1} = (r0, r_{i+1})
+// expanded as (r0, q_i) - omega_i (r0, y_i), so that P3 can form p_{i+1} in the
+// same pass as r_{i+1}.  P3 also computes (r0, r_{i+1}) directly.  That exact
+// value becomes rho for the next iteration and drives the breakdown test.
+__device__ __forceinline__ void tail_p2(State* st, const double (&tot)[5]) {
     st->qy = tot[0];
     st->yy = tot[1];
     st->qq = tot[2];
+    st->rq = tot[3];
+    st->ry = tot[4];
+    st->beta = 0.0;
+    st->beta_bad = RS_NONE;
     const double qn = sqrt(tot[2]) / st->nb;
     if (qn <= st->tol) {
         st->omega = 0.0;  // P3 then adds alpha p only and sets r = q
@@ -730,9 +573,18 @@ __device__ __forceinline__ void tail_p2(State* st, const double (&tot)[3]) {
         return;
     }
     st->omega = w;
+    const double rho_next = tot[3] - w * tot[4];
+    const double beta = (st->alpha / w) * (rho_next / st->rho);
+    if (rho_next == 0.0) {
+        st->beta_bad = RS_RHO_ZERO;
+    } else if (!isfinite(beta)) {
+        st->beta_bad = RS_NONFINITE;
+    } else {
+        st->beta = beta;
+    }
 }
 
-// After P3: stopping tests, then beta_i = (alpha/omega) (r0, r_{i+1}) / (r0, r_i).
+// After P3: stopping tests, then the breakdown tests on rho_{i+1}.
 __device__ __forceinline__ void tail_p3(State* st, const double (&tot)[2]) {
     st->iter += 1;
     st->rr = tot[1];
@@ -762,14 +614,11 @@ __device__ __forceinline__ void tail_p3(State* st, const double (&tot)[2]) {
         set_breakdown(st, RS_RHO_ZERO);
         return;
     }
-    const double beta = (st->alpha / st->omega) * (rho_new / st->rho);
-    if (!isfinite(beta)) {
-        set_breakdown(st, RS_NONFINITE);
+    if (st->beta_bad) {
+        set_breakdown(st, st->beta_bad);
         return;
     }
-    st->beta = beta;
     st->rho = rho_new;
-    st->first = 0;
 }
 
 // Start of a (sub)solve: r0 in place, nb^2, (r0, r0) known.
@@ -782,7 +631,7 @@ __device__ __forceinline__ void tail_init(State* st, double nb2, double rr, doub
     st->status = ST_OK;
     st->reason = RS_NONE;
     st->half = 0;
-    st->first = 1;
+    st->beta_bad = RS_NONE;
     st->alpha = st->omega = st->beta = 0.0;
     st->nb = sqrt(nb2);
     st->rho = rr;

@@ -38,35 +38,31 @@ inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 inline size_t elt_size(int prec) { return prec == S7_FP32 ? 4 : 2; }
 
-// Tile shape of the z-march kernels for a mesh.  rows_per_wave and zchunk
-// come from the options, the tuning cache, or these defaults.
-struct TileChoice {
-    int R;
-    int zc;
-};
+inline int cell_blocks_for(long long n) { return (int)((n + kThreads - 1) / kThreads); }
 
-TileChoice choose_tiles(s7_dims d, const s7_options& o, int prec);
-
-// Workgroups of the streaming pass: at most 1024 (mixed read/write streams
-// reach a higher HBM rate with fewer concurrent streams), at least one per
-// 2048 cells.
-inline int stream_blocks_for(long long n) {
+// Workgroups of the streaming pass: at most 1024 by default (mixed read/write
+// streams reach a higher HBM rate with fewer concurrent streams), at least
+// one per 2048 cells.
+inline int stream_blocks_for(long long n, int cap) {
     long long b = (n + kThreads * 8 - 1) / (kThreads * 8);
     if (b < 1) b = 1;
-    if (b > 1024) b = 1024;
+    if (cap <= 0) cap = 1024;
+    if (cap > kSingleMax) cap = kSingleMax;  // the streaming passes always finish in-kernel
+    if (b > cap) b = cap;
     return (int)b;
 }
 
-// Workspace of one system: [State][partials][coef copies][7 vectors of T][d: FP32].
+// Workspace of one system:
+// [State][partials][group partials][counters][coef copies][5 vectors of T][d: FP32].
 struct Layout {
-    size_t off_state, off_partials, off_coef, off_vec, off_d, bytes;
+    size_t off_state, off_part, off_gpart, off_cnt, off_coef, off_vec, off_d, bytes;
     int ncoef;
+    int cell_blocks, stream_blocks, groups;
     size_t elt;
-    size_t nparts;  // doubles of partials
     size_t n;
 };
 
-Layout make_layout(s7_dims d, int prec, int jacobi, TileChoice tc);
+Layout make_layout(s7_dims d, int prec, const s7_options& o);
 
 void options_or_default(const s7_options* in, s7_options& out);
 

@@ -1,17 +1,16 @@
 // Single-system path of the s7 library: stencil apply, the generator, and the
 // BiCGStab solve (FP32, and BF16/FP16 inside FP64 iterative refinement).
 //
-// Per iteration, Algorithm 1 runs as three fused passes with a device-side
-// scalar step at the end of each:
-//   P1  p_i = r_i + beta (p_{i-1} - omega s_{i-1}), formed on the fly (also
-//       at halo cells); s_i = A p_i; partial (r0, s_i)    -> alpha_i
+// Per iteration, Algorithm 1 runs as three passes.  Each ends in a device-side
+// scalar step:
+//   P1  s_i = A p_i; partial (r0, s_i)                               -> alpha_i
 //   P2  q_i = r_i - alpha s_i on the fly; y_i = A q_i;
-//       partials (q,y), (y,y), (q,q)                     -> omega_i, half-step test
+//       partials (q,y), (y,y), (q,q), (r0,q), (r0,y)    -> omega_i, beta_i, half-step test
 //   P3  x += alpha p + omega q; r_{i+1} = q - omega y;
-//       partials (r0,r), (r,r)                           -> beta_i, stopping tests
-// p and s are ping-pong buffers, so halo reads of the old values never race
-// with writes of the new ones.  The scalars stay on the device.  The host
-// reads only the `done` word, once per captured graph of K iterations.
+//       p_{i+1} = r_{i+1} + beta (p_i - omega s_i); partials (r0,r), (r,r) -> stopping tests
+// P1 and P2 are cell-parallel stencils; P3 streams.  The scalars stay on the
+// device.  The host reads only the `done` word, once per captured graph of K
+// iterations.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -47,43 +46,28 @@ void options_or_default(const s7_options* in, s7_options& out) {
     }
 }
 
-TileChoice choose_tiles(s7_dims d, const s7_options& o, int prec) {
-    (void)prec;
-    TileChoice tc;
-    tc.R = (o.rows_per_wave == 4 || o.rows_per_wave == 8) ? o.rows_per_wave : (d.ny >= 32 ? 8 : 4);
-    if (o.zchunk > 0) {
-        tc.zc = o.zchunk;
-    } else {
-        int zc = 64;
-        Mesh m{d.nx, d.ny, d.nz};
-        while (zc > 8 && make_ztiles(m, tc.R, zc).nblocks < 2048) zc /= 2;
-        tc.zc = zc;
-    }
-    if (tc.zc > d.nz) tc.zc = d.nz;
-    return tc;
-}
-
-Layout make_layout(s7_dims d, int prec, int jacobi, TileChoice tc) {
+Layout make_layout(s7_dims d, int prec, const s7_options& o) {
     Layout L;
-    Mesh m{d.nx, d.ny, d.nz};
     L.n = (size_t)d.nx * d.ny * d.nz;
     L.elt = elt_size(prec);
-    L.ncoef = jacobi ? 6 : 7;
-    size_t nb = (size_t)make_ztiles(m, tc.R, tc.zc).nblocks;
-    size_t nb4 = (size_t)make_ztiles(m, 4, tc.zc).nblocks;
-    if (nb4 > nb) nb = nb4;
-    size_t sb = (size_t)stream_blocks_for((long long)L.n);
-    if (sb > nb) nb = sb;
-    L.nparts = nb * kMaxDots;
+    L.ncoef = o.jacobi ? 6 : 7;
+    L.cell_blocks = cell_blocks_for((long long)L.n);
+    L.stream_blocks = stream_blocks_for((long long)L.n, o.stream_blocks);
+    const int nb = L.cell_blocks > L.stream_blocks ? L.cell_blocks : L.stream_blocks;
+    L.groups = red_groups(nb);  // workgroups of the finishing kernel of a split sum
     size_t off = 0;
     L.off_state = off;
     off = align256(off + sizeof(State));
-    L.off_partials = off;
-    off = align256(off + L.nparts * sizeof(double));
+    L.off_part = off;
+    off = align256(off + (size_t)nb * kMaxDots * sizeof(double));
+    L.off_gpart = off;
+    off = align256(off + (size_t)L.groups * kMaxDots * sizeof(double));
+    L.off_cnt = off;
+    off = align256(off + sizeof(uint32_t));
     L.off_coef = off;
     off = align256(off + (size_t)L.ncoef * align256(L.n * L.elt));
     L.off_vec = off;
-    off = align256(off + (size_t)7 * align256(L.n * L.elt));
+    off = align256(off + (size_t)5 * align256(L.n * L.elt));
     L.off_d = off;
     off = align256(off + L.n * sizeof(float));
     L.bytes = off;
@@ -91,10 +75,9 @@ Layout make_layout(s7_dims d, int prec, int jacobi, TileChoice tc) {
 }
 
 template <class T>
-static SysView<T> make_view(s7_dims d, const Layout& L, TileChoice tc, int jacobi, char* ws) {
+static SysView<T> make_view(s7_dims d, const Layout& L, int jacobi, char* ws) {
     SysView<T> S;
     S.m = Mesh{d.nx, d.ny, d.nz};
-    S.zt = make_ztiles(S.m, tc.R, tc.zc);
     S.n = (int)L.n;
     S.unit = jacobi ? 1 : 0;
     const size_t span = align256(L.n * L.elt);
@@ -104,15 +87,15 @@ static SysView<T> make_view(s7_dims d, const Layout& L, TileChoice tc, int jacob
     auto vec = [&](int i) { return reinterpret_cast<T*>(ws + L.off_vec + i * span); };
     S.r = vec(0);
     S.rhat = vec(1);
-    S.p[0] = vec(2);
-    S.p[1] = vec(3);
-    S.s[0] = vec(4);
-    S.s[1] = vec(5);
-    S.y = vec(6);
+    S.p = vec(2);
+    S.s = vec(3);
+    S.y = vec(4);
     S.d = reinterpret_cast<float*>(ws + L.off_d);
     S.st = reinterpret_cast<State*>(ws + L.off_state);
-    S.partials = reinterpret_cast<double*>(ws + L.off_partials);
-    S.stream_blocks = stream_blocks_for((long long)L.n);
+    S.red = Red{reinterpret_cast<double*>(ws + L.off_part), reinterpret_cast<double*>(ws + L.off_gpart),
+                reinterpret_cast<uint32_t*>(ws + L.off_cnt)};
+    S.cell_blocks = L.cell_blocks;
+    S.stream_blocks = L.stream_blocks;
     return S;
 }
 
@@ -120,6 +103,14 @@ static SysView<T> make_view(s7_dims d, const Layout& L, TileChoice tc, int jacob
 struct Coef7 {
     const float* c[7];
 };
+
+// Clears the solver state and the reduction counters (a kernel rather than a
+// memset, so that the same clear is valid inside captured graphs).
+__global__ __launch_bounds__(kThreads) void k_zero_state(State* st, uint32_t* cnt, int ncnt) {
+    uint32_t* w = reinterpret_cast<uint32_t*>(st);
+    for (int i = threadIdx.x; i < (int)(sizeof(State) / 4); i += kThreads) w[i] = 0u;
+    for (int i = threadIdx.x; i < ncnt; i += kThreads) cnt[i] = 0u;
+}
 
 // Working-precision coefficient copies.  jacobi: c[a] / diag for a = 1..6 (unit
 // diagonal).  Otherwise all seven.  Outward links on the boundary faces are
@@ -130,11 +121,8 @@ __global__ __launch_bounds__(kThreads) void k_prep_coef(Coef7 src, T* dst0, size
     const int first = jacobi ? 1 : 0;
     const int n = m.nx * m.ny * m.nz;
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
-        const int x = i % m.nx;
-        const int rest = i / m.nx;
-        const int y = rest % m.ny;
-        const int k = rest / m.ny;
-        const bool in[7] = {true, x > 0, x < m.nx - 1, y > 0, y < m.ny - 1, k > 0, k < m.nz - 1};
+        const Cell c = cell_at(i, m, n);
+        const bool in[7] = {true, c.dw != 0, c.de != 0, c.ds != 0, c.dn != 0, c.db != 0, c.dt != 0};
         const float dg = src.c[0][i];
 #pragma unroll
         for (int a = 0; a < 7; ++a) {
@@ -147,54 +135,33 @@ __global__ __launch_bounds__(kThreads) void k_prep_coef(Coef7 src, T* dst0, size
 }
 
 // r0 = b - A x0 in FP64 with the caller's FP32 coefficients.  Optionally
-// Jacobi-scaled.  Rounded to FP32 into r and r_hat, and d = 0.  Partials:
+// Jacobi-scaled.  Rounded to FP32 into r, r_hat and p, and d = 0.  Partials:
 // ||b_s||^2, (r,r) of the rounded r, ||b||^2 unscaled.
-struct OutInitF32 {
-    struct Raw {
-        double b;
-        float dg;
-    };
-    const double* b;
-    const float* diag;
-    float *r, *rhat, *d;
-    int jacobi;
-    double acc[3];
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{b[idx], diag[idx]}; }
-    __device__ __forceinline__ void emit(const Raw& in, int idx, bool own, double, double ax) {
-        const double bi = own ? in.b : 0.0;
-        double r0 = bi - ax, bs = bi;
-        if (jacobi) {
-            const double dg = own ? (double)in.dg : 1.0;
-            r0 = r0 / dg;
-            bs = bs / dg;
-        }
-        const float rf = own ? (float)r0 : 0.0f;
-        if (own) {
-            r[idx] = rf;
-            rhat[idx] = rf;
-            d[idx] = 0.0f;
-        }
-        acc[0] = fma(bs, bs, acc[0]);
-        acc[1] = fma((double)rf, (double)rf, acc[1]);
-        acc[2] = fma(bi, bi, acc[2]);
-    }
-};
-
-template <int R>
 __global__ __launch_bounds__(kThreads) void k_init_f32(Coef7 cf, const double* b, const double* x0,
                                                        SysView<float> S, int jacobi, double tol,
                                                        int max_iter) {
-    const int L = xcd_remap(blockIdx.x, S.zt.nblocks);
-    int tx, ty, k0, k1;
-    OutInitF32 out{b, cf.c[0], S.r, S.rhat, S.d, jacobi, {0.0, 0.0, 0.0}};
-    if (wave_tile(S.zt, S.m, L, tx, ty, k0, k1)) {
-        SrcLoadF64 src{x0};
-        StencilOp<float, double, false, true> op{{cf.c[0], cf.c[1], cf.c[2], cf.c[3], cf.c[4], cf.c[5], cf.c[6]}, S.m};
-        zmarch<R>(S.m, tx, ty, k0, k1, src, op, out);
+    const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, S.m, S.n);
+    const Nbr<double> xv = load_nbr(x0, c);
+    const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
+    const double bi = b[c.idx];
+    const double ax = apply7<double, float, false, true>(k, xv, c);
+    double r0 = bi - ax, bs = bi;
+    if (jacobi) {
+        const double dg = (double)k.a[0];
+        r0 = r0 / dg;
+        bs = bs / dg;
     }
+    const float rf = (float)r0;
+    if (c.own) {
+        S.r[c.idx] = rf;
+        S.rhat[c.idx] = rf;
+        S.p[c.idx] = rf;
+        S.d[c.idx] = 0.0f;
+    }
+    double acc[3] = {c.own ? bs * bs : 0.0, c.own ? (double)rf * (double)rf : 0.0,
+                     c.own ? bi * bi : 0.0};
     double tot[3];
-    if (reduce_partials<3>(out.acc, S.partials, &S.st->ticket, S.zt.nblocks, blockIdx.x, tot) &&
-        threadIdx.x == 0) {
+    if (grid_reduce<3>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0) {
         tail_init(S.st, tot[0], tot[1], tol, max_iter);
         S.st->bb_true = tot[2];
         S.st->scale = 1.0;
@@ -202,56 +169,30 @@ __global__ __launch_bounds__(kThreads) void k_init_f32(Coef7 cf, const double* b
 }
 
 // True residual r = b - A x in FP64 (caller's coefficients, unscaled).
-// Partials: ||b||^2, ||r||^2, max |r_s| (r_s = r / diag with Jacobi).  With
-// store != 0, r_s goes to dst as FP32: the right-hand side of the next
-// refinement step.
-struct OutResid {
-    struct Raw {
-        double b;
-        float dg;
-    };
-    const double* b;
-    const float* diag;
-    float* dst;
-    int jacobi;
-    int store;
-    double acc[3];
-    __device__ __forceinline__ Raw load(int idx) const { return Raw{b[idx], diag[idx]}; }
-    __device__ __forceinline__ void emit(const Raw& in, int idx, bool own, double, double ax) {
-        if (!own) return;
-        const double bi = in.b;
-        const double r0 = bi - ax;
-        acc[0] = fma(bi, bi, acc[0]);
-        acc[1] = fma(r0, r0, acc[1]);
-        const double rs = jacobi ? r0 / (double)in.dg : r0;
-        const float rf = (float)rs;
-        if (store) dst[idx] = rf;
-        acc[2] = fmax(acc[2], (double)fabsf(rf));
-    }
-};
-
-template <int R>
+// Partials: ||b||^2, ||r||^2, max |r_s| (r_s = r / diag with Jacobi).  If dst is
+// not null, r_s goes there as FP32: the right-hand side of the next refinement
+// step.
 __global__ __launch_bounds__(kThreads) void k_resid(Coef7 cf, const double* b, const double* x,
-                                                    float* dst, Mesh m, ZTiles zt, State* st,
-                                                    double* partials, int jacobi, int store) {
-    const int L = xcd_remap(blockIdx.x, zt.nblocks);
-    int tx, ty, k0, k1;
-    OutResid out{b, cf.c[0], dst, jacobi, store, {0.0, 0.0, 0.0}};
-    if (wave_tile(zt, m, L, tx, ty, k0, k1)) {
-        SrcLoadF64 src{x};
-        StencilOp<float, double, false, true> op{{cf.c[0], cf.c[1], cf.c[2], cf.c[3], cf.c[4], cf.c[5], cf.c[6]}, m};
-        zmarch<R>(m, tx, ty, k0, k1, src, op, out);
-    }
+                                                    float* dst, Mesh m, int n, int nblocks,
+                                                    State* st, Red red, int jacobi) {
+    const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, m, n);
+    const Nbr<double> xv = load_nbr(x, c);
+    const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
+    const double bi = b[c.idx];
+    const double r0 = bi - apply7<double, float, false, true>(k, xv, c);
+    const double rs = jacobi ? r0 / (double)k.a[0] : r0;
+    const float rf = (float)rs;
+    if (dst && c.own) dst[c.idx] = rf;
+    double acc[3] = {c.own ? bi * bi : 0.0, c.own ? r0 * r0 : 0.0, c.own ? (double)fabsf(rf) : 0.0};
     double tot[3];
-    if (reduce_partials<3, 4u>(out.acc, partials, &st->ticket, zt.nblocks, blockIdx.x, tot) &&
-        threadIdx.x == 0) {
+    if (grid_reduce<3, 4u>(acc, red, nblocks, blockIdx.x, tot) && threadIdx.x == 0) {
         st->bb_true = tot[0];
         st->rr_true = tot[1];
         st->rmax = tot[2];
     }
 }
 
-// Start of an inner solve of the refinement: r = r_hat = fl_T(rs / scale)
+// Start of an inner solve of the refinement: r = r_hat = p = fl_T(rs / scale)
 // from the FP32 residual in d, then d = 0.
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_ir_init(SysView<T> S, float inv_scale, double tol,
@@ -263,15 +204,14 @@ __global__ __launch_bounds__(kThreads) void k_ir_init(SysView<T> S, float inv_sc
         const T rt = from_f32<T>(S.d[i] * inv_scale);
         S.r[i] = rt;
         S.rhat[i] = rt;
+        S.p[i] = rt;
         S.d[i] = 0.0f;
         const double v = (double)to_f32(rt);
         acc[0] = fma(v, v, acc[0]);
     }
     double tot[1];
-    if (reduce_partials<1>(acc, S.partials, &S.st->ticket, S.stream_blocks, blockIdx.x, tot) &&
-        threadIdx.x == 0) {
+    if (grid_reduce<1>(acc, S.red, S.stream_blocks, blockIdx.x, tot) && threadIdx.x == 0)
         tail_init(S.st, tot[0], tot[0], tol, max_iter);
-    }
 }
 
 // x += scale * d (FP64), or x = 0 when b = 0.
@@ -282,62 +222,81 @@ __global__ __launch_bounds__(kThreads) void k_update_x(double* x, const float* d
         x[i] = zero ? 0.0 : fma(scale, (double)d[i], x[i]);
 }
 
-// Clears the solver state, including the reduction ticket (a kernel rather
-// than a memset, so that the same clear is valid inside captured graphs).
-__global__ __launch_bounds__(64) void k_zero_state(State* st) {
-    uint32_t* w = reinterpret_cast<uint32_t*>(st);
-    for (int i = threadIdx.x; i < (int)(sizeof(State) / 4); i += 64) w[i] = 0u;
-}
-
 __global__ __launch_bounds__(kThreads) void k_fill0(double* x, int n) {
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) x[i] = 0.0;
 }
 
-template <class T, int R>
-__global__ __launch_bounds__(kThreads) void k_p1(SysView<T> S, int par) {
+// Second half of a split grid sum (see Red), followed by the scalar step of the
+// pass whose partials it sums.
+enum FinishKind { FIN_P1 = 1, FIN_P2 = 2, FIN_INIT = 3, FIN_RESID = 4 };
+
+template <int ND, unsigned MAXMASK, int KIND>
+__global__ __launch_bounds__(kThreads) void k_finish(Red red, int nblocks, State* st, double tol,
+                                                     int max_iter) {
+    if ((KIND == FIN_P1 || KIND == FIN_P2) && st->done) return;
+    double tot[ND];
+    if (!finish_split<ND, MAXMASK>(red, nblocks, tot) || threadIdx.x != 0) return;
+    if constexpr (KIND == FIN_P1) {
+        tail_p1(st, reinterpret_cast<double(&)[1]>(tot));
+    } else if constexpr (KIND == FIN_P2) {
+        tail_p2(st, reinterpret_cast<double(&)[5]>(tot));
+    } else if constexpr (KIND == FIN_INIT) {
+        tail_init(st, tot[0], tot[1], tol, max_iter);
+        st->bb_true = tot[2];
+        st->scale = 1.0;
+    } else {
+        st->bb_true = tot[0];
+        st->rr_true = tot[1];
+        st->rmax = tot[2];
+    }
+}
+
+template <class T, bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_p1(SysView<T> S) {
     if (S.st->done) return;
-    const int L = xcd_remap(blockIdx.x, S.zt.nblocks);
     double acc[1];
-    wg_p1<T, R>(S, L, par, acc);
+    cell_p1<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, acc);
     double tot[1];
-    if (reduce_partials<1>(acc, S.partials, &S.st->ticket, S.zt.nblocks, blockIdx.x, tot) &&
-        threadIdx.x == 0)
+    if (grid_reduce<1>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
         tail_p1(S.st, tot);
 }
 
-template <class T, int R>
-__global__ __launch_bounds__(kThreads) void k_p2(SysView<T> S, int par) {
+template <class T, bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_p2(SysView<T> S) {
     if (S.st->done) return;
-    const int L = xcd_remap(blockIdx.x, S.zt.nblocks);
-    double acc[3];
-    wg_p2<T, R>(S, L, par, acc);
-    double tot[3];
-    if (reduce_partials<3>(acc, S.partials, &S.st->ticket, S.zt.nblocks, blockIdx.x, tot) &&
-        threadIdx.x == 0)
+    double acc[5];
+    cell_p2<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, (float)S.st->alpha, acc);
+    double tot[5];
+    if (grid_reduce<5>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
         tail_p2(S.st, tot);
 }
 
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_p3(SysView<T> S, int par) {
+__global__ __launch_bounds__(kThreads) void k_p3(SysView<T> S) {
     if (S.st->done) return;
     double acc[2];
-    chunk_p3<T>(S, blockIdx.x, par, acc);
+    chunk_p3<T>(S, blockIdx.x, acc);
     double tot[2];
-    if (reduce_partials<2>(acc, S.partials, &S.st->ticket, S.stream_blocks, blockIdx.x, tot) &&
-        threadIdx.x == 0)
+    if (grid_reduce<2>(acc, S.red, S.stream_blocks, blockIdx.x, tot) && threadIdx.x == 0)
         tail_p3(S.st, tot);
 }
 
-template <int R>
 __global__ __launch_bounds__(kThreads) void k_stencil_apply(Coef7 cf, const float* v, float* u,
-                                                            Mesh m, ZTiles zt) {
-    const int L = xcd_remap(blockIdx.x, zt.nblocks);
-    int tx, ty, k0, k1;
-    if (!wave_tile(zt, m, L, tx, ty, k0, k1)) return;
-    SrcLoad<float> src{v};
-    StencilOp<float, float, false, true> op{{cf.c[0], cf.c[1], cf.c[2], cf.c[3], cf.c[4], cf.c[5], cf.c[6]}, m};
-    OutStore<float> out{u};
-    zmarch<R>(m, tx, ty, k0, k1, src, op, out);
+                                                            Mesh m, int n) {
+    const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, m, n);
+    const Nbr<float> vv = load_nbr(v, c);
+    const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
+    const float av = apply7<float, float, false, true>(k, vv, c);
+    if (c.own) u[c.idx] = av;
+}
+
+__global__ __launch_bounds__(kThreads) void k_apply_f64(Coef7 cf, const double* v, double* u,
+                                                        Mesh m, int n) {
+    const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, m, n);
+    const Nbr<double> vv = load_nbr(v, c);
+    const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
+    const double av = apply7<double, float, false, true>(k, vv, c);
+    if (c.own) u[c.idx] = av;
 }
 
 // ---- generator (recipe of the synthetic inputs; see s7.h)
@@ -390,27 +349,6 @@ __global__ __launch_bounds__(kThreads) void k_gen_coef(Coef7 out, double* xstar,
     }
 }
 
-struct OutF64 {
-    using Raw = NoRaw;
-    double* u;
-    __device__ __forceinline__ NoRaw load(int) const { return NoRaw{}; }
-    __device__ __forceinline__ void emit(NoRaw, int idx, bool own, double, double av) {
-        if (own) u[idx] = av;
-    }
-};
-
-template <int R>
-__global__ __launch_bounds__(kThreads) void k_apply_f64(Coef7 cf, const double* v, double* u,
-                                                        Mesh m, ZTiles zt) {
-    const int L = xcd_remap(blockIdx.x, zt.nblocks);
-    int tx, ty, k0, k1;
-    if (!wave_tile(zt, m, L, tx, ty, k0, k1)) return;
-    SrcLoadF64 src{v};
-    StencilOp<float, double, false, true> op{{cf.c[0], cf.c[1], cf.c[2], cf.c[3], cf.c[4], cf.c[5], cf.c[6]}, m};
-    OutF64 out{u};
-    zmarch<R>(m, tx, ty, k0, k1, src, op, out);
-}
-
 // ============================================================== graph cache
 namespace {
 
@@ -440,7 +378,7 @@ int capture_stream(hipStream_t* out) {
 
 // Returns a cached executable graph for `key`, capturing `body` on first use.
 template <class F>
-static int cached_graph(const std::vector<uintptr_t>& key, F body, hipGraphExec_t* out) {
+int cached_graph(const std::vector<uintptr_t>& key, F body, hipGraphExec_t* out) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
         if (it->key == key) {
@@ -479,37 +417,54 @@ static int cached_graph(const std::vector<uintptr_t>& key, F body, hipGraphExec_
 
 // ============================================================== drivers
 static int auto_graph_iters(size_t n, int elt) {
-    const double us = (double)n * (elt == 4 ? 116.0 : 60.0) / 5.0e6 + 15.0;
+    const double us = (double)n * (elt == 4 ? 112.0 : 60.0) / 5.0e6 + 15.0;
     int k = (int)(2000.0 / us);
     if (k < 2) k = 2;
     if (k > 64) k = 64;
-    return k & ~1;
+    return k;
 }
 
-template <class T, int R>
-static void launch_iteration(const SysView<T>& S, int par, hipStream_t s) {
-    hipLaunchKernelGGL((k_p1<T, R>), dim3(S.zt.nblocks), dim3(kThreads), 0, s, S, par);
-    hipLaunchKernelGGL((k_p2<T, R>), dim3(S.zt.nblocks), dim3(kThreads), 0, s, S, par);
-    hipLaunchKernelGGL((k_p3<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S, par);
+template <int ND, unsigned MAXMASK, int KIND>
+static void launch_finish(const Red& red, int nblocks, State* st, hipStream_t s, double tol = 0.0,
+                          int max_iter = 0) {
+    if (red_split(nblocks))
+        hipLaunchKernelGGL((k_finish<ND, MAXMASK, KIND>), dim3(red_groups(nblocks)), dim3(kThreads),
+                           0, s, red, nblocks, st, tol, max_iter);
 }
 
-static const size_t kStateHead = offsetof(State, pad);
+template <class T>
+static void launch_pass(const SysView<T>& S, int pass, hipStream_t s) {
+    if (pass == 0) {
+        if (S.unit)
+            hipLaunchKernelGGL((k_p1<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+        else
+            hipLaunchKernelGGL((k_p1<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+        launch_finish<1, 0u, FIN_P1>(S.red, S.cell_blocks, S.st, s);
+    } else if (pass == 1) {
+        if (S.unit)
+            hipLaunchKernelGGL((k_p2<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+        else
+            hipLaunchKernelGGL((k_p2<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+        launch_finish<5, 0u, FIN_P2>(S.red, S.cell_blocks, S.st, s);
+    } else {
+        hipLaunchKernelGGL((k_p3<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S);
+    }
+}
 
 static int read_state(const State* dst, State* host, hipStream_t s) {
-    S7_HIP(hipMemcpyAsync(host, dst, kStateHead, hipMemcpyDeviceToHost, s));
+    S7_HIP(hipMemcpyAsync(host, dst, sizeof(State), hipMemcpyDeviceToHost, s));
     S7_HIP(hipStreamSynchronize(s));
     return S7_OK;
 }
 
 // Runs BiCGStab iterations from an initialised state until the device says done.
-template <class T, int R>
+template <class T>
 static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t stream,
                           State* host, s7_info* info) {
     int rc = read_state(S.st, host, stream);
     if (rc) return rc;
     if (host->done) return S7_OK;
-    int K = o.graph_iters > 0 ? o.graph_iters : auto_graph_iters((size_t)S.n, (int)sizeof(T));
-    K = (K + 1) & ~1;
+    const int K = o.graph_iters > 0 ? o.graph_iters : auto_graph_iters((size_t)S.n, (int)sizeof(T));
     const long long max_launches = (long long)host->max_iter / K + 3;
     if (o.profile) {
         std::vector<hipEvent_t> ev((size_t)4 * K);
@@ -517,13 +472,10 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
         for (long long l = 0; l < max_launches; ++l) {
             const int it0 = host->iter;
             for (int j = 0; j < K; ++j) {
-                const int par = j & 1;
-                S7_HIP(hipEventRecord(ev[4 * j + 0], stream));
-                hipLaunchKernelGGL((k_p1<T, R>), dim3(S.zt.nblocks), dim3(kThreads), 0, stream, S, par);
-                S7_HIP(hipEventRecord(ev[4 * j + 1], stream));
-                hipLaunchKernelGGL((k_p2<T, R>), dim3(S.zt.nblocks), dim3(kThreads), 0, stream, S, par);
-                S7_HIP(hipEventRecord(ev[4 * j + 2], stream));
-                hipLaunchKernelGGL((k_p3<T>), dim3(S.stream_blocks), dim3(kThreads), 0, stream, S, par);
+                for (int p = 0; p < 3; ++p) {
+                    S7_HIP(hipEventRecord(ev[4 * j + p], stream));
+                    launch_pass<T>(S, p, stream);
+                }
                 S7_HIP(hipEventRecord(ev[4 * j + 3], stream));
             }
             S7_CHECK_LAUNCH();
@@ -544,14 +496,15 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
         }
         for (auto& e : ev) (void)hipEventDestroy(e);
     } else {
-        std::vector<uintptr_t> key = {0x51u, (uintptr_t)TypeTag<T>::value, (uintptr_t)R, (uintptr_t)K,
+        std::vector<uintptr_t> key = {0x52u, (uintptr_t)TypeTag<T>::value, (uintptr_t)K,
                                       (uintptr_t)S.m.nx, (uintptr_t)S.m.ny, (uintptr_t)S.m.nz,
-                                      (uintptr_t)S.zt.zc, (uintptr_t)S.unit, (uintptr_t)S.st,
-                                      (uintptr_t)S.partials, (uintptr_t)S.r, (uintptr_t)S.c[0],
-                                      (uintptr_t)S.d, (uintptr_t)S.stream_blocks};
+                                      (uintptr_t)S.unit, (uintptr_t)S.st, (uintptr_t)S.red.part,
+                                      (uintptr_t)S.r, (uintptr_t)S.c[1], (uintptr_t)S.d,
+                                      (uintptr_t)S.stream_blocks};
         hipGraphExec_t g;
         rc = cached_graph(key, [&](hipStream_t cs) {
-            for (int j = 0; j < K; ++j) launch_iteration<T, R>(S, j & 1, cs);
+            for (int j = 0; j < K; ++j)
+                for (int p = 0; p < 3; ++p) launch_pass<T>(S, p, cs);
         }, &g);
         if (rc) return rc;
         for (long long l = 0; l < max_launches; ++l) {
@@ -575,47 +528,41 @@ static int grid_for(size_t n) {
     return (int)g;
 }
 
-template <int R>
-static int resid_launch(const Coef7& cf, const double* b, const double* x, float* dst, Mesh m,
-                        int zc, State* st, double* partials, int jacobi, int store, hipStream_t s) {
-    ZTiles zt = make_ztiles(m, R, zc);
-    hipLaunchKernelGGL((k_resid<R>), dim3(zt.nblocks), dim3(kThreads), 0, s, cf, b, x, dst, m, zt,
-                       st, partials, jacobi, store);
+template <class T>
+static int resid_launch(const Coef7& cf, const double* b, const double* x, float* dst,
+                        const SysView<T>& S, int jacobi, hipStream_t s) {
+    hipLaunchKernelGGL(k_resid, dim3(S.cell_blocks), dim3(kThreads), 0, s, cf, b, x, dst, S.m, S.n,
+                       S.cell_blocks, S.st, S.red, jacobi);
+    launch_finish<3, 4u, FIN_RESID>(S.red, S.cell_blocks, S.st, s);
     S7_CHECK_LAUNCH();
     return S7_OK;
 }
 
 template <class T>
-static int prep_coef(const Coef7& cf, const SysView<T>& S, size_t span_elems, int jacobi,
-                     hipStream_t s) {
+static int start_solve(const Coef7& cf, const SysView<T>& S, const Layout& Lo, int jacobi,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(kThreads), 0, s, S.st, S.red.cnt, 1);
+    const size_t span_elems = align256(Lo.n * Lo.elt) / Lo.elt;
     hipLaunchKernelGGL((k_prep_coef<T>), dim3(grid_for(S.n)), dim3(kThreads), 0, s, cf,
                        const_cast<T*>(S.c[jacobi ? 1 : 0]), span_elems, S.m, jacobi);
     S7_CHECK_LAUNCH();
     return S7_OK;
 }
 
-static void fill_info_from_state(const State& h, s7_info* info) {
-    if (!info) return;
-    info->status = h.status;
-    info->reason = h.reason;
-    info->rel_res_rec = h.res_rec;
-}
-
-template <int R>
 static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol,
-                      int max_iter, char* ws, const Layout& Lo, TileChoice tc,
-                      const s7_options& o, s7_info* info, hipStream_t s) {
-    SysView<float> S = make_view<float>(d, Lo, tc, o.jacobi, ws);
-    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, S.st);
-    int rc = prep_coef<float>(cf, S, align256(Lo.n * Lo.elt) / Lo.elt, o.jacobi, s);
+                      int max_iter, char* ws, const Layout& Lo, const s7_options& o,
+                      s7_info* info, hipStream_t s) {
+    SysView<float> S = make_view<float>(d, Lo, o.jacobi, ws);
+    int rc = start_solve<float>(cf, S, Lo, o.jacobi, s);
     if (rc) return rc;
     auto t0 = std::chrono::steady_clock::now();
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipLaunchKernelGGL((k_init_f32<R>), dim3(S.zt.nblocks), dim3(kThreads), 0, s, cf, b, x, S,
-                       o.jacobi, rtol, max_iter);
+    hipLaunchKernelGGL(k_init_f32, dim3(S.cell_blocks), dim3(kThreads), 0, s, cf, b, x, S, o.jacobi,
+                       rtol, max_iter);
+    launch_finish<3, 0u, FIN_INIT>(S.red, S.cell_blocks, S.st, s, rtol, max_iter);
     S7_CHECK_LAUNCH();
     State h;
-    rc = run_iterations<float, R>(S, o, s, &h, info);
+    rc = run_iterations<float>(S, o, s, &h, info);
     if (rc) return rc;
     if (o.profile) {
         S7_HIP(hipEventCreate(&e0));
@@ -624,14 +571,16 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
     }
     hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, x, S.d, S.n, 1.0, S.st);
     S7_CHECK_LAUNCH();
-    rc = resid_launch<R>(cf, b, x, nullptr, S.m, tc.zc, S.st, S.partials, o.jacobi, 0, s);
+    rc = resid_launch<float>(cf, b, x, nullptr, S, o.jacobi, s);
     if (rc) return rc;
     if (o.profile) S7_HIP(hipEventRecord(e1, s));
     rc = read_state(S.st, &h, s);
     if (rc) return rc;
     auto t1 = std::chrono::steady_clock::now();
     if (info) {
-        fill_info_from_state(h, info);
+        info->status = h.status;
+        info->reason = h.reason;
+        info->rel_res_rec = h.res_rec;
         info->iters = h.iter;
         info->outer_iters = 1;
         info->rel_res_true = h.bb_true > 0 ? sqrt(h.rr_true / h.bb_true) : 0.0;
@@ -648,13 +597,12 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
     return h.status;
 }
 
-template <class T, int R>
+template <class T>
 static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol,
-                    int max_iter, char* ws, const Layout& Lo, TileChoice tc, const s7_options& o,
+                    int max_iter, char* ws, const Layout& Lo, const s7_options& o,
                     s7_info* info, hipStream_t s, int prec) {
-    SysView<T> S = make_view<T>(d, Lo, tc, o.jacobi, ws);
-    hipLaunchKernelGGL(k_zero_state, dim3(1), dim3(64), 0, s, S.st);
-    int rc = prep_coef<T>(cf, S, align256(Lo.n * Lo.elt) / Lo.elt, o.jacobi, s);
+    SysView<T> S = make_view<T>(d, Lo, o.jacobi, ws);
+    int rc = start_solve<T>(cf, S, Lo, o.jacobi, s);
     if (rc) return rc;
     auto t0 = std::chrono::steady_clock::now();
     const double inner_tol = o.inner_rtol > 0 ? o.inner_rtol : (prec == S7_FP16_IR ? 5e-3 : 1e-2);
@@ -665,7 +613,7 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
     int stall = 0;
     State h;
     for (;;) {
-        rc = resid_launch<R>(cf, b, x, S.d, S.m, tc.zc, S.st, S.partials, o.jacobi, 1, s);
+        rc = resid_launch<T>(cf, b, x, S.d, S, o.jacobi, s);
         if (rc) return rc;
         rc = read_state(S.st, &h, s);
         if (rc) return rc;
@@ -694,12 +642,12 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
             break;
         }
         // power-of-two scale: the inner right-hand side has max |.| in (0.5, 1]
-        double scale = h.rmax > 0 ? exp2(ceil(log2(h.rmax))) : 1.0;
+        const double scale = h.rmax > 0 ? exp2(ceil(log2(h.rmax))) : 1.0;
         hipLaunchKernelGGL((k_ir_init<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S,
                            (float)(1.0 / scale), inner_tol,
                            inner_cap < max_iter - total ? inner_cap : max_iter - total);
         S7_CHECK_LAUNCH();
-        rc = run_iterations<T, R>(S, o, s, &h, info);
+        rc = run_iterations<T>(S, o, s, &h, info);
         if (rc) return rc;
         total += h.iter;
         outer += 1;
@@ -758,19 +706,11 @@ int s7_stencil_apply(s7_dims d, const float* const coef[7], const float* v, floa
         return S7_EINVAL;
     }
     Mesh m{d.nx, d.ny, d.nz};
+    const int n = d.nx * d.ny * d.nz;
     Coef7 cf;
     for (int a = 0; a < 7; ++a) cf.c[a] = coef[a];
-    s7_options o;
-    s7_default_options(&o);
-    TileChoice tc = choose_tiles(d, o, S7_FP32);
-    hipStream_t s = (hipStream_t)stream;
-    if (tc.R == 8) {
-        ZTiles zt = make_ztiles(m, 8, tc.zc);
-        hipLaunchKernelGGL((k_stencil_apply<8>), dim3(zt.nblocks), dim3(kThreads), 0, s, cf, v, u, m, zt);
-    } else {
-        ZTiles zt = make_ztiles(m, 4, tc.zc);
-        hipLaunchKernelGGL((k_stencil_apply<4>), dim3(zt.nblocks), dim3(kThreads), 0, s, cf, v, u, m, zt);
-    }
+    hipLaunchKernelGGL(k_stencil_apply, dim3(cell_blocks_for(n)), dim3(kThreads), 0,
+                       (hipStream_t)stream, cf, v, u, m, n);
     S7_CHECK_LAUNCH();
     return S7_OK;
 }
@@ -779,7 +719,7 @@ size_t s7_workspace_bytes(s7_dims d, int32_t prec, const s7_options* opt) {
     if (!dims_ok(d) || prec < S7_FP32 || prec > S7_FP16_IR) return 0;
     s7_options o;
     options_or_default(opt, o);
-    return make_layout(d, prec, o.jacobi, choose_tiles(d, o, prec)).bytes;
+    return make_layout(d, prec, o).bytes;
 }
 
 int s7_bicgstab_solve(s7_dims d, const float* const coef[7], const double* b, double* x,
@@ -794,8 +734,7 @@ int s7_bicgstab_solve(s7_dims d, const float* const coef[7], const double* b, do
         set_error("s7_bicgstab_solve: invalid argument");
         return S7_EINVAL;
     }
-    TileChoice tc = choose_tiles(d, o, prec);
-    Layout Lo = make_layout(d, prec, o.jacobi, tc);
+    Layout Lo = make_layout(d, prec, o);
     if (ws_bytes < Lo.bytes) {
         set_error("s7_bicgstab_solve: workspace too small (%zu < %zu)", ws_bytes, Lo.bytes);
         return S7_EINVAL;
@@ -804,18 +743,9 @@ int s7_bicgstab_solve(s7_dims d, const float* const coef[7], const double* b, do
     for (int a = 0; a < 7; ++a) cf.c[a] = coef[a];
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
-    int rc;
-    if (prec == S7_FP32) {
-        rc = tc.R == 8 ? solve_fp32<8>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s)
-                       : solve_fp32<4>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s);
-    } else if (prec == S7_BF16_IR) {
-        rc = tc.R == 8 ? solve_ir<bf16, 8>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s, prec)
-                       : solve_ir<bf16, 4>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s, prec);
-    } else {
-        rc = tc.R == 8 ? solve_ir<f16, 8>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s, prec)
-                       : solve_ir<f16, 4>(d, cf, b, x, rtol, max_iter, w, Lo, tc, o, info, s, prec);
-    }
-    return rc;
+    if (prec == S7_FP32) return solve_fp32(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s);
+    if (prec == S7_BF16_IR) return solve_ir<bf16>(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s, prec);
+    return solve_ir<f16>(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s, prec);
 }
 
 int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float* const coef[7],
@@ -837,16 +767,12 @@ int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float* const c
         return S7_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
-    const size_t n = (size_t)d.nx * d.ny * d.nz;
+    const int n = d.nx * d.ny * d.nz;
     hipLaunchKernelGGL(k_gen_coef, dim3(grid_for(n)), dim3(kThreads), 0, s, cf, xstar, m, seed, recipe);
     S7_CHECK_LAUNCH();
     if (b) {
-        s7_options o;
-        s7_default_options(&o);
-        TileChoice tc = choose_tiles(d, o, S7_FP32);
-        ZTiles zt = make_ztiles(m, 4, tc.zc);
-        hipLaunchKernelGGL((k_apply_f64<4>), dim3(zt.nblocks), dim3(kThreads), 0, s, cf,
-                           (const double*)xstar, b, m, zt);
+        hipLaunchKernelGGL(k_apply_f64, dim3(cell_blocks_for(n)), dim3(kThreads), 0, s, cf,
+                           (const double*)xstar, b, m, n);
         S7_CHECK_LAUNCH();
     }
     return S7_OK;

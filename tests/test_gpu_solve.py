@@ -173,13 +173,51 @@ def test_deterministic_and_graph_equals_direct(s7):
     assert i3.pass_count[0] >= i3.iters and i3.pass_ms[0] > 0
 
 
-@pytest.mark.parametrize("rows,zc", [(4, 8), (8, 3), (4, 1), (8, 64)])
-def test_tile_shapes_agree_with_oracle(s7, rows, zc):
+@pytest.mark.parametrize("sb", [1, 3, 64, 1024])
+def test_stream_split_agrees_with_oracle(s7, sb):
+    """The work split of the streaming pass (and so its reduction order) is a tunable."""
     dims = (75, 37, 19)
     prob, A, b = problem(dims, seed=12)
     ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=1000)
-    x, info = gpu_solve(s7, dims, coef_dev(prob), b, rtol=1e-8, rows_per_wave=rows, zchunk=zc)
+    x, info = gpu_solve(s7, dims, coef_dev(prob), b, rtol=1e-8, stream_blocks=sb)
     assert info.status == s7.OK and rel_err(x, ref.x) <= 1e-6
+
+
+def test_split_reduction_matches_oracle(s7):
+    """Above 4096 workgroups a pass stores workgroup partials and a finishing kernel sums
+    them in groups of 1024: 128x96x96 (4608 workgroups) runs that path."""
+    dims = (128, 96, 96)
+    prob, A, b = problem(dims, seed=14)
+    coef = coef_dev(prob)
+    bd = dev(b)
+    for k in (1, 2, 3, 6):
+        rk = oracle.bicgstab(A, b, tol=1e-300, max_iter=k)
+        xk, ik = gpu_solve(s7, dims, coef, bd, rtol=1e-300, max_iter=k)
+        assert ik.iters == k
+        assert abs(ik.rel_res_rec - rk.res_rec) <= 1e-4 * rk.res_rec, (k, ik.rel_res_rec, rk.res_rec)
+        assert rel_err(xk, rk.x) <= 1e-4
+    ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=1000)
+    x, info = gpu_solve(s7, dims, coef, bd, rtol=1e-8)
+    r8 = oracle.bicgstab(A, b, tol=1e-8, max_iter=1000)
+    assert info.status == s7.OK and rel_err(x, ref.x) <= 1e-6
+    assert abs(info.iters - r8.iters) <= max(3, 0.2 * r8.iters)
+    assert abs(info.rel_res_true - oracle.true_rel_residual(A, b, x)) <= 1e-3 * info.rel_res_true
+    for prec in (s7.BF16_IR, s7.FP16_IR):
+        x, info = gpu_solve(s7, dims, coef, bd, rtol=1e-10, max_iter=2000, prec=prec)
+        assert info.status == s7.OK and rel_err(x, ref.x) <= 1e-7
+
+
+def test_multi_group_reduction_matches_oracle(s7):
+    """More than 1024 workgroups per stencil pass: the reduction runs in two levels."""
+    dims = (130, 70, 40)  # 364,000 cells -> 1422 workgroups
+    prob, A, b = problem(dims, seed=13)
+    ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=1000)
+    x, info = gpu_solve(s7, dims, coef_dev(prob), b, rtol=1e-8)
+    assert info.status == s7.OK and rel_err(x, ref.x) <= 1e-6
+    for k in (1, 2, 3):
+        rk = oracle.bicgstab(A, b, tol=1e-300, max_iter=k)
+        xk, ik = gpu_solve(s7, dims, coef_dev(prob), b, rtol=1e-300, max_iter=k)
+        assert abs(ik.rel_res_rec - rk.res_rec) <= 1e-4 * rk.res_rec
 
 
 @pytest.mark.parametrize("prec", ["bf16_ir", "fp16_ir"])
