@@ -25,10 +25,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # Algorithmic bytes per cell of each pass (FP32 storage, Jacobi-scaled: 6 coefficient arrays).
 # P1 reads p, r0 and 6 coefficients and writes s.
-# P2 reads r, s, r0 and 6 coefficients and writes y.
-# P3 reads d, p, r, s, y, r0 and writes d, r, p.
-BYTES_FP32 = {"p1": 36, "p2": 40, "p3": 36}
-BYTES_16 = {"p1": 18, "p2": 20, "p3": 22}  # BF16/FP16 vectors and coefficients, FP32 d
+# P2a reads r, s and writes q.
+# P2b reads q, r0 and 6 coefficients and writes y.
+# P3 reads d, p, q, s, y, r0 and writes d, r, p.
+BYTES_FP32 = {"p1": 36, "p2a": 12, "p2b": 36, "p3": 36}
+BYTES_16 = {"p1": 18, "p2a": 6, "p2b": 18, "p3": 22}  # BF16/FP16 vectors and coefficients, FP32 d
 SRC_FILES = ["paper_2010_03660_amd/csrc/s7_device.hpp", "paper_2010_03660_amd/csrc/s7_single.hip"]
 
 
@@ -139,9 +140,10 @@ def main():
     info, dt = run(s7.FP32, args.steps, profile=1)
     assert info.iters == args.steps, info.as_dict()
     ips = args.steps / dt
-    names = ("p1", "p2", "p3")
+    names = ("p1", "p2a", "p2b", "p3")
     kname = {"p1": "k_p1 (P1: s = A p, (r0,s))",
-             "p2": "k_p2 (P2: q on the fly, y = A q, five dot products)",
+             "p2a": "k_p2a (P2a: q = r - alpha s)",
+             "p2b": "k_p2 (P2b: y = A q and five dot products)",
              "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"}
     pass_ms = {k: info.pass_ms[i] / max(info.pass_count[i], 1) for i, k in enumerate(names)}
     dom = max(names, key=lambda k: pass_ms[k])  # the kernel with the largest share of an iteration
@@ -178,7 +180,7 @@ def main():
         info16, dt16 = run(s7.BF16_IR, args.steps, profile=1)
         it16 = info16.iters
         p16 = {k: info16.pass_ms[i] / max(info16.pass_count[i], 1)
-               for i, k in enumerate(("p1", "p2", "p3"))}
+               for i, k in enumerate(("p1", "p2a", "p2b", "p3"))}
         out["mixed_bf16_ir"] = {
             "iter_per_s": round(it16 / dt16, 3), "inner_iters": it16,
             "outer_steps": info16.outer_iters,

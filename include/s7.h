@@ -110,7 +110,8 @@ typedef struct {
     double rel_res_true; /* ||b - A x|| / ||b|| of the unscaled system, FP64, at exit */
     double t_ms;         /* solver wall time (queue: submit to completion) */
     double t_wait_ms;    /* queue: submit to admission; 0 otherwise */
-    double pass_ms[4];   /* profile: summed time of P1, P2, P3, all other kernels */
+    double pass_ms[4];   /* profile: summed time of the iteration's kernels P1, P2a, P2b, P3
+                            (P1 and P2b include the finishing kernel of a split sum) */
     int32_t pass_count[4];
 } s7_info;
 

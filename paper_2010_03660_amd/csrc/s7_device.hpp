@@ -8,9 +8,9 @@
 //   Infinity Cache; HBM sees each array about once.  Loads are branch-free:
 //   an off-mesh neighbour reads the cell itself, and a zero coefficient
 //   cancels it.
-// * The fused BiCGStab passes: P1 (s = A p and (r0,s)), P2 (q on the fly at
-//   all seven positions, y = A q and five dots) and the streaming P3 (x, r
-//   and p updates and two dots).
+// * The BiCGStab passes: P1 (s = A p and (r0,s)), the streaming P2a
+//   (q = r - alpha s), P2b (y = A q and five dots) and the streaming P3
+//   (x, r and p updates and two dots).
 // * Deterministic hierarchical reductions: FP64 per lane, a fixed wavefront
 //   butterfly, a fixed wave order in LDS, and per-workgroup partials.  The
 //   last workgroup of each group of 1024 sums the group's partials, and the
@@ -279,16 +279,41 @@ constexpr int kSingleMax = 4096;
 __host__ __device__ inline int red_groups(int nblocks) { return (nblocks + kGroup - 1) / kGroup; }
 __host__ __device__ inline bool red_split(int nblocks) { return nblocks > kSingleMax; }
 
-// Values j with bit j of MAXMASK set reduce with max, the others with +.
+// DPP move of an FP64 value (both 32-bit halves with the same control).
+// Lanes whose row is masked off, or that have no source lane, read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Wavefront reduction on the VALU (DPP), in a fixed order: pairs (quad_perm
+// [1,0,3,2]), quads ([2,3,0,1]), half-rows (row_half_mirror), rows
+// (row_mirror), then rows 0+1 and 2+3 (row_bcast:15 into rows 1 and 3) and
+// all four (row_bcast:31 into rows 2 and 3).  The total is in lane 63.  All
+// 64 lanes must be active.  Values j with bit j of MAXMASK set reduce with
+// max (of non-negative values), the others with +.
 template <int ND, unsigned MAXMASK>
 __device__ __forceinline__ void wave_reduce(double (&a)[ND]) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int j = 0; j < ND; ++j) {
-            double o = __shfl_xor(a[j], off, kWave);
-            a[j] = ((MAXMASK >> j) & 1u) ? fmax(a[j], o) : a[j] + o;
-        }
+    for (int j = 0; j < ND; ++j) {
+        const bool mx = (MAXMASK >> j) & 1u;
+        double v = a[j];
+        double t;
+        t = dpp_f64<0xB1, 0xf>(v);
+        v = mx ? fmax(v, t) : v + t;
+        t = dpp_f64<0x4E, 0xf>(v);
+        v = mx ? fmax(v, t) : v + t;
+        t = dpp_f64<0x141, 0xf>(v);
+        v = mx ? fmax(v, t) : v + t;
+        t = dpp_f64<0x140, 0xf>(v);
+        v = mx ? fmax(v, t) : v + t;
+        t = dpp_f64<0x142, 0xa>(v);
+        v = mx ? fmax(v, t) : v + t;
+        t = dpp_f64<0x143, 0xc>(v);
+        v = mx ? fmax(v, t) : v + t;
+        a[j] = v;
     }
 }
 
@@ -306,7 +331,7 @@ __device__ __forceinline__ void block_reduce(double (&acc)[ND], double (&out)[ND
     const int wave = threadIdx.x / kWave;
     wave_reduce<ND, MAXMASK>(acc);
     __syncthreads();
-    if (lane == 0) {
+    if (lane == kWave - 1) {
 #pragma unroll
         for (int j = 0; j < ND; ++j) sm[wave][j] = acc[j];
     }
@@ -405,7 +430,7 @@ struct SysView {
     int n;
     int unit;          // 1: Jacobi-scaled (unit diagonal)
     const T* c[7];
-    T *r, *rhat, *p, *s, *y;
+    T *r, *rhat, *p, *s, *y, *q;
     float* d;          // FP32 correction accumulated by the iteration
     State* st;
     Red red;
@@ -434,27 +459,41 @@ __device__ __forceinline__ void cell_p1(const SysView<T>& S, int g, double (&acc
     acc[0] = c.own ? (double)to_f32(rh) * (double)to_f32(sv) : 0.0;
 }
 
-// P2 at one cell: q = r - alpha s at all seven positions (FP32, never stored),
-// y = A q stored; partials (q,y), (y,y), (q,q), (r0,q), (r0,y).
+// P2a over one contiguous chunk: q = r - alpha s, rounded to the storage type.
+template <class T>
+__device__ __forceinline__ void chunk_p2a(const SysView<T>& S, int b) {
+    int i0, i1;
+    stream_range(S.n, S.stream_blocks, b, i0, i1);
+    const float alpha = (float)S.st->alpha;
+    const T* __restrict__ r = S.r;
+    const T* __restrict__ s = S.s;
+    T* __restrict__ q = S.q;
+    const int nv = (i1 - i0) / 4;
+    for (int v = (int)threadIdx.x; v < nv; v += kThreads) {
+        const int i = i0 + 4 * v;
+        float rv[4], sv[4];
+        ld4_nt(r + i, rv);
+        ld4_nt(s + i, sv);
+        T qv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) qv[j] = from_f32<T>(fmaT(-alpha, sv[j], rv[j]));
+        st4_nt(q + i, qv);
+    }
+    for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads)
+        q[i] = from_f32<T>(fmaT(-alpha, to_f32(s[i]), to_f32(r[i])));
+}
+
+// P2b at one cell: y = A q stored; partials (q,y), (y,y), (q,q), (r0,q), (r0,y).
 template <class T, bool UNIT>
-__device__ __forceinline__ void cell_p2(const SysView<T>& S, int g, float alpha, double (&acc)[5]) {
+__device__ __forceinline__ void cell_p2b(const SysView<T>& S, int g, double (&acc)[5]) {
     const Cell c = cell_at(g, S.m, S.n);
-    const Nbr<float> rv = nbr_f32(load_nbr(S.r, c));
-    const Nbr<float> sv = nbr_f32(load_nbr(S.s, c));
+    const Nbr<float> qv = nbr_f32(load_nbr(S.q, c));
     const Coefs<T, UNIT> k = load_coefs<T, UNIT>(S.c, c.idx);
     const double rh = (double)to_f32(S.rhat[c.idx]);
-    Nbr<float> q;
-    q.c = fmaT(-alpha, sv.c, rv.c);
-    q.w = fmaT(-alpha, sv.w, rv.w);
-    q.e = fmaT(-alpha, sv.e, rv.e);
-    q.s = fmaT(-alpha, sv.s, rv.s);
-    q.n = fmaT(-alpha, sv.n, rv.n);
-    q.b = fmaT(-alpha, sv.b, rv.b);
-    q.t = fmaT(-alpha, sv.t, rv.t);
-    const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k, q, c));
+    const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k, qv, c));
     if (c.own) S.y[c.idx] = yt;
     const double yd = c.own ? (double)to_f32(yt) : 0.0;
-    const double qd = c.own ? (double)q.c : 0.0;
+    const double qd = c.own ? (double)qv.c : 0.0;
     acc[0] = qd * yd;
     acc[1] = yd * yd;
     acc[2] = qd * qd;
@@ -462,18 +501,17 @@ __device__ __forceinline__ void cell_p2(const SysView<T>& S, int g, float alpha,
     acc[4] = rh * yd;
 }
 
-// P3 over one contiguous chunk: q = r - alpha s; d += alpha p + omega q;
-// r = q - omega y; p = r + beta (p - omega s).  Accumulates (r0, r_{i+1}) and
-// (r_{i+1}, r_{i+1}).  In place is safe: every cell reads and writes only
-// itself.  Four consecutive cells per thread and step, with 16-byte (FP32) or
-// 8-byte (16-bit) non-temporal accesses.  Chunk bounds are multiples of 8
-// cells except at the end of the array; the last chunk's tail is scalar.
+// P3 over one contiguous chunk: d += alpha p + omega q; r = q - omega y;
+// p = r + beta (p - omega s).  Accumulates (r0, r_{i+1}) and (r_{i+1}, r_{i+1}).
+// In place is safe: every cell reads and writes only itself.  Four consecutive
+// cells per thread and step, with 16-byte (FP32) or 8-byte (16-bit)
+// non-temporal accesses.  Chunk bounds are multiples of 8 cells except at the
+// end of the array; the last chunk's tail is scalar.
 template <class T>
 __device__ __forceinline__ void p3_math(float alpha, float omega, float beta, float pv, float sv,
-                                        float yv, float rv, float& dv, T& rn, T& pn) {
-    const float q = fmaT(-alpha, sv, rv);
-    dv = fmaT(omega, q, fmaT(alpha, pv, dv));
-    rn = from_f32<T>(fmaT(-omega, yv, q));
+                                        float yv, float qv, float& dv, T& rn, T& pn) {
+    dv = fmaT(omega, qv, fmaT(alpha, pv, dv));
+    rn = from_f32<T>(fmaT(-omega, yv, qv));
     pn = from_f32<T>(fmaT(beta, fmaT(-omega, sv, pv), to_f32(rn)));
 }
 
@@ -485,6 +523,7 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
     T* __restrict__ p = S.p;
     const T* __restrict__ s = S.s;
     const T* __restrict__ y = S.y;
+    const T* __restrict__ q = S.q;
     const T* __restrict__ rh = S.rhat;
     T* __restrict__ r = S.r;
     float* __restrict__ d = S.d;
@@ -492,17 +531,17 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
     const int nv = (i1 - i0) / 4;
     for (int v = (int)threadIdx.x; v < nv; v += kThreads) {
         const int i = i0 + 4 * v;
-        float pv[4], sv[4], yv[4], rv[4], hv[4], dv[4];
+        float pv[4], sv[4], yv[4], qv[4], hv[4], dv[4];
         ld4_nt(p + i, pv);
         ld4_nt(s + i, sv);
         ld4_nt(y + i, yv);
-        ld4_nt(r + i, rv);
+        ld4_nt(q + i, qv);
         ld4_nt(rh + i, hv);
         ld4_nt(d + i, dv);
         T rn[4], pn[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            p3_math<T>(alpha, omega, beta, pv[j], sv[j], yv[j], rv[j], dv[j], rn[j], pn[j]);
+            p3_math<T>(alpha, omega, beta, pv[j], sv[j], yv[j], qv[j], dv[j], rn[j], pn[j]);
             const double rd = (double)to_f32(rn[j]);
             a0 = fma((double)hv[j], rd, a0);
             a1 = fma(rd, rd, a1);
@@ -514,7 +553,7 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
     for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads) {
         float dv = d[i];
         T rn, pn;
-        p3_math<T>(alpha, omega, beta, to_f32(p[i]), to_f32(s[i]), to_f32(y[i]), to_f32(r[i]), dv,
+        p3_math<T>(alpha, omega, beta, to_f32(p[i]), to_f32(s[i]), to_f32(y[i]), to_f32(q[i]), dv,
                    rn, pn);
         d[i] = dv;
         r[i] = rn;

@@ -4,11 +4,11 @@
 // Per iteration, Algorithm 1 runs as three passes.  Each ends in a device-side
 // scalar step:
 //   P1  s_i = A p_i; partial (r0, s_i)                               -> alpha_i
-//   P2  q_i = r_i - alpha s_i on the fly; y_i = A q_i;
-//       partials (q,y), (y,y), (q,q), (r0,q), (r0,y)    -> omega_i, beta_i, half-step test
+//   P2a q_i = r_i - alpha s_i (streaming)
+//   P2b y_i = A q_i; partials (q,y), (y,y), (q,q), (r0,q), (r0,y) -> omega_i, beta_i, half-step test
 //   P3  x += alpha p + omega q; r_{i+1} = q - omega y;
 //       p_{i+1} = r_{i+1} + beta (p_i - omega s_i); partials (r0,r), (r,r) -> stopping tests
-// P1 and P2 are cell-parallel stencils; P3 streams.  The scalars stay on the
+// P1 and P2b are cell-parallel stencils; P2a and P3 stream.  The scalars stay on the
 // device.  The host reads only the `done` word, once per captured graph of K
 // iterations.
 #include <hip/hip_runtime.h>
@@ -67,7 +67,7 @@ Layout make_layout(s7_dims d, int prec, const s7_options& o) {
     L.off_coef = off;
     off = align256(off + (size_t)L.ncoef * align256(L.n * L.elt));
     L.off_vec = off;
-    off = align256(off + (size_t)5 * align256(L.n * L.elt));
+    off = align256(off + (size_t)6 * align256(L.n * L.elt));
     L.off_d = off;
     off = align256(off + L.n * sizeof(float));
     L.bytes = off;
@@ -90,6 +90,7 @@ static SysView<T> make_view(s7_dims d, const Layout& L, int jacobi, char* ws) {
     S.p = vec(2);
     S.s = vec(3);
     S.y = vec(4);
+    S.q = vec(5);
     S.d = reinterpret_cast<float*>(ws + L.off_d);
     S.st = reinterpret_cast<State*>(ws + L.off_state);
     S.red = Red{reinterpret_cast<double*>(ws + L.off_part), reinterpret_cast<double*>(ws + L.off_gpart),
@@ -261,11 +262,17 @@ __global__ __launch_bounds__(kThreads) void k_p1(SysView<T> S) {
         tail_p1(S.st, tot);
 }
 
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_p2a(SysView<T> S) {
+    if (S.st->done) return;
+    chunk_p2a<T>(S, blockIdx.x);
+}
+
 template <class T, bool UNIT>
 __global__ __launch_bounds__(kThreads) void k_p2(SysView<T> S) {
     if (S.st->done) return;
     double acc[5];
-    cell_p2<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, (float)S.st->alpha, acc);
+    cell_p2b<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, acc);
     double tot[5];
     if (grid_reduce<5>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
         tail_p2(S.st, tot);
@@ -432,6 +439,10 @@ static void launch_finish(const Red& red, int nblocks, State* st, hipStream_t s,
                            0, s, red, nblocks, st, tol, max_iter);
 }
 
+// The launches of one iteration: 0 P1, 1 P2a, 2 P2b, 3 P3 (each with the
+// finishing kernel of a split sum where one is needed).
+constexpr int kPasses = 4;
+
 template <class T>
 static void launch_pass(const SysView<T>& S, int pass, hipStream_t s) {
     if (pass == 0) {
@@ -441,6 +452,8 @@ static void launch_pass(const SysView<T>& S, int pass, hipStream_t s) {
             hipLaunchKernelGGL((k_p1<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
         launch_finish<1, 0u, FIN_P1>(S.red, S.cell_blocks, S.st, s);
     } else if (pass == 1) {
+        hipLaunchKernelGGL((k_p2a<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S);
+    } else if (pass == 2) {
         if (S.unit)
             hipLaunchKernelGGL((k_p2<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
         else
@@ -467,16 +480,17 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
     const int K = o.graph_iters > 0 ? o.graph_iters : auto_graph_iters((size_t)S.n, (int)sizeof(T));
     const long long max_launches = (long long)host->max_iter / K + 3;
     if (o.profile) {
-        std::vector<hipEvent_t> ev((size_t)4 * K);
+        constexpr int NP = kPasses;
+        std::vector<hipEvent_t> ev((size_t)(NP + 1) * K);
         for (auto& e : ev) S7_HIP(hipEventCreate(&e));
         for (long long l = 0; l < max_launches; ++l) {
             const int it0 = host->iter;
             for (int j = 0; j < K; ++j) {
-                for (int p = 0; p < 3; ++p) {
-                    S7_HIP(hipEventRecord(ev[4 * j + p], stream));
+                for (int p = 0; p < NP; ++p) {
+                    S7_HIP(hipEventRecord(ev[(NP + 1) * j + p], stream));
                     launch_pass<T>(S, p, stream);
                 }
-                S7_HIP(hipEventRecord(ev[4 * j + 3], stream));
+                S7_HIP(hipEventRecord(ev[(NP + 1) * j + NP], stream));
             }
             S7_CHECK_LAUNCH();
             rc = read_state(S.st, host, stream);
@@ -484,9 +498,9 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
             const int ran = host->iter - it0;
             if (info) {
                 for (int j = 0; j < K && j < ran; ++j) {
-                    for (int p = 0; p < 3; ++p) {
+                    for (int p = 0; p < NP; ++p) {
                         float ms = 0.f;
-                        S7_HIP(hipEventElapsedTime(&ms, ev[4 * j + p], ev[4 * j + p + 1]));
+                        S7_HIP(hipEventElapsedTime(&ms, ev[(NP + 1) * j + p], ev[(NP + 1) * j + p + 1]));
                         info->pass_ms[p] += ms;
                         info->pass_count[p] += 1;
                     }
@@ -504,7 +518,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
         hipGraphExec_t g;
         rc = cached_graph(key, [&](hipStream_t cs) {
             for (int j = 0; j < K; ++j)
-                for (int p = 0; p < 3; ++p) launch_pass<T>(S, p, cs);
+                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, cs);
         }, &g);
         if (rc) return rc;
         for (long long l = 0; l < max_launches; ++l) {
@@ -556,7 +570,6 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
     int rc = start_solve<float>(cf, S, Lo, o.jacobi, s);
     if (rc) return rc;
     auto t0 = std::chrono::steady_clock::now();
-    hipEvent_t e0 = nullptr, e1 = nullptr;
     hipLaunchKernelGGL(k_init_f32, dim3(S.cell_blocks), dim3(kThreads), 0, s, cf, b, x, S, o.jacobi,
                        rtol, max_iter);
     launch_finish<3, 0u, FIN_INIT>(S.red, S.cell_blocks, S.st, s, rtol, max_iter);
@@ -564,16 +577,10 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
     State h;
     rc = run_iterations<float>(S, o, s, &h, info);
     if (rc) return rc;
-    if (o.profile) {
-        S7_HIP(hipEventCreate(&e0));
-        S7_HIP(hipEventCreate(&e1));
-        S7_HIP(hipEventRecord(e0, s));
-    }
     hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, x, S.d, S.n, 1.0, S.st);
     S7_CHECK_LAUNCH();
     rc = resid_launch<float>(cf, b, x, nullptr, S, o.jacobi, s);
     if (rc) return rc;
-    if (o.profile) S7_HIP(hipEventRecord(e1, s));
     rc = read_state(S.st, &h, s);
     if (rc) return rc;
     auto t1 = std::chrono::steady_clock::now();
@@ -585,15 +592,7 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
         info->outer_iters = 1;
         info->rel_res_true = h.bb_true > 0 ? sqrt(h.rr_true / h.bb_true) : 0.0;
         info->t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        if (o.profile) {
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            info->pass_ms[3] += ms;
-            info->pass_count[3] += 1;
-        }
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
     return h.status;
 }
 
