@@ -91,7 +91,8 @@ typedef struct {
     int32_t graph_iters;    /* iterations per captured hipGraph launch; 0 = auto */
     int32_t stream_blocks;  /* workgroups of the streaming pass; 0 = auto (at most 1024);
                                capped at 4096 */
-    int32_t reserved1;
+    int32_t chunk_cells;    /* batched/queue: cells per work item of the persistent
+                               kernel (multiple of 256); 0 = 4096 */
     int32_t profile;        /* 1: launch without graphs, time every pass with HIP
                                events into s7_info.pass_ms */
     int32_t inner_max_iter; /* IR: inner iteration cap per outer step; 0 = 100 */

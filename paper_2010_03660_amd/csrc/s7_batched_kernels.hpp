@@ -1,0 +1,391 @@
+// Batched form: many independent BiCGStab systems of uneven size in one
+// persistent launch.  The paper motivates this (section VIII-B) with many
+// compact problems solved together, and with the four solves per timestep of
+// its application (Algorithm 2).
+//
+// Execution model (no grid barrier, no fence):
+// * A work item is (system, phase, chunk), where a chunk is `chunk_cells`
+//   consecutive cells of one system.  The phases of an iteration are P1,
+//   P2a, P2b and P3, the same as the single-system path.
+// * Each system owns a 64-bit claim word, (phase sequence << 32) | next chunk.
+//   A workgroup claims a chunk with one atomic add, which tells it both the
+//   chunk and the phase it belongs to.  Claims past the last chunk are
+//   ignored.
+// * A workgroup publishes its chunk's partial sums, then counts itself done.
+//   The workgroup completing a phase sums that system's partials in chunk
+//   order, runs the scalar step of Algorithm 1 on a private copy of the
+//   state, stores it, and opens the next phase by storing the next sequence
+//   into the claim word.  The sum order is fixed per system, so a system's
+//   iterates do not depend on the rest of the batch or on scheduling.
+// * Everything one workgroup hands to another inside the launch goes through
+//   device-scope (coherent) loads and stores: the Krylov vectors, partials,
+//   state and control words.  Each XCD's L2 is private and not coherent with
+//   the others.  Release fences would restore coherence only by writing back
+//   a whole L2 per hand-off, at tens of nanoseconds each, serialized.
+// * Every wait is bounded.  A workgroup that finds no work spins with
+//   s_sleep.  After `spin_limit` fruitless tries it records an error and
+//   leaves, and the launch always drains.
+// Included by the solver translation unit (s7_single.hip) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "s7_device.hpp"
+
+namespace s7 {
+
+// ---------------------------------------------------------------- coherent access
+template <class T>
+struct Bits;
+template <>
+struct Bits<float> {
+    using U = uint32_t;
+};
+template <>
+struct Bits<bf16> {
+    using U = uint16_t;
+};
+template <>
+struct Bits<f16> {
+    using U = uint16_t;
+};
+
+template <class T>
+__device__ __forceinline__ T cload(const T* p) {
+    using U = typename Bits<T>::U;
+    const U u = __hip_atomic_load(reinterpret_cast<U*>(const_cast<T*>(p)), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_bit_cast(T, u);
+}
+template <class T>
+__device__ __forceinline__ void cstore(T* p, T v) {
+    using U = typename Bits<T>::U;
+    __hip_atomic_store(reinterpret_cast<U*>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double cload_d(const double* p) { return fetch_published(p); }
+__device__ __forceinline__ void cstore_d(double* p, double v) { publish(p, v); }
+__device__ __forceinline__ int32_t cload_i(const int32_t* p) {
+    return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cstore_i(int32_t* p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ Nbr<T> cload_nbr(const T* v, const Cell& c) {
+    const T* p = v + c.idx;
+    return Nbr<T>{cload(p), cload(p + c.dw), cload(p + c.de), cload(p + c.ds),
+                  cload(p + c.dn), cload(p + c.db), cload(p + c.dt)};
+}
+
+// State copied word by word with coherent accesses.
+__device__ __forceinline__ void state_load(const State* src, State& dst) {
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d = reinterpret_cast<uint32_t*>(&dst);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(State) / 4); ++i)
+        d[i] = __hip_atomic_load(const_cast<uint32_t*>(s + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void state_store(State* dst, const State& src) {
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(&src);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(State) / 4); ++i)
+        __hip_atomic_store(d + i, s[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- tables
+// One system of a batch.  The view is stored with FP32 element pointers and
+// re-typed by `tag` (TypeTag of the storage type); the pointer members are
+// identical in every instantiation.  Red.part holds nchunk * kMaxDots partials.
+struct BCtl;
+
+struct BSys {
+    SysView<float> S;
+    BCtl* ctl;  // the system's control words (in its own workspace slice)
+    int nchunk;
+    int tag;
+};
+
+template <class T>
+__device__ __forceinline__ SysView<T> as_view(const SysView<float>& v) {
+    SysView<T> o;
+    o.m = v.m;
+    o.n = v.n;
+    o.unit = v.unit;
+    for (int a = 0; a < 7; ++a) o.c[a] = reinterpret_cast<const T*>(v.c[a]);
+    o.r = reinterpret_cast<T*>(v.r);
+    o.rhat = reinterpret_cast<T*>(v.rhat);
+    o.p = reinterpret_cast<T*>(v.p);
+    o.s = reinterpret_cast<T*>(v.s);
+    o.y = reinterpret_cast<T*>(v.y);
+    o.q = reinterpret_cast<T*>(v.q);
+    o.d = v.d;
+    o.st = v.st;
+    o.red = v.red;
+    o.cell_blocks = v.cell_blocks;
+    o.stream_blocks = v.stream_blocks;
+    return o;
+}
+
+struct BCtl {
+    unsigned long long claim;  // (phase sequence << 32) | next chunk
+    uint32_t done_cnt;         // chunks finished in the current phase
+    int32_t budget;            // iterations this launch may still run
+    int32_t active;            // 1 while the system takes part in this launch
+    int32_t pad;
+};
+
+// Restarts a system's phase sequence (a new inner solve begins at P1).
+__global__ void k_ctl_reset(BCtl* ctl) {
+    if (threadIdx.x == 0) {
+        ctl->claim = 0ull;
+        ctl->done_cnt = 0u;
+        ctl->budget = 0;
+        ctl->active = 0;
+    }
+}
+
+struct BGlobal {
+    int32_t active;  // systems still active in this launch
+    int32_t error;   // 1: a workgroup gave up waiting
+};
+
+// ---------------------------------------------------------------- chunk work
+// The cells of chunk c, visited four per thread per step: thread t takes cells
+// base + 256*u + t for u = 0..3.  All loads of a step are issued before any
+// store.
+template <class T, bool UNIT>
+__device__ void chunk_p1_b(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
+    for (int base = c0; base < c1; base += 4 * kThreads) {
+        Cell cl[4];
+        Nbr<T> pv[4];
+        Coefs<T, UNIT> k[4];
+        T rh[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int g = base + u * kThreads + (int)threadIdx.x;
+            cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
+            cl[u].own = g < c1;
+            pv[u] = cload_nbr(S.p, cl[u]);
+            k[u] = load_coefs<T, UNIT>(S.c, cl[u].idx);
+            rh[u] = S.rhat[cl[u].idx];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T sv = from_f32<T>(apply7<float, T, UNIT, false>(k[u], nbr_f32(pv[u]), cl[u]));
+            if (cl[u].own) {
+                cstore(S.s + cl[u].idx, sv);
+                acc[0] = fma((double)to_f32(rh[u]), (double)to_f32(sv), acc[0]);
+            }
+        }
+    }
+}
+
+template <class T>
+__device__ void chunk_p2a_b(const SysView<T>& S, int c0, int c1, float alpha) {
+    for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads) {
+        const float r = to_f32(cload(S.r + i)), s = to_f32(cload(S.s + i));
+        cstore(S.q + i, from_f32<T>(fmaT(-alpha, s, r)));
+    }
+}
+
+template <class T, bool UNIT>
+__device__ void chunk_p2b_b(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
+    for (int base = c0; base < c1; base += 4 * kThreads) {
+        Cell cl[4];
+        Nbr<T> qv[4];
+        Coefs<T, UNIT> k[4];
+        T rh[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int g = base + u * kThreads + (int)threadIdx.x;
+            cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
+            cl[u].own = g < c1;
+            qv[u] = cload_nbr(S.q, cl[u]);
+            k[u] = load_coefs<T, UNIT>(S.c, cl[u].idx);
+            rh[u] = S.rhat[cl[u].idx];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const Nbr<float> q = nbr_f32(qv[u]);
+            const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k[u], q, cl[u]));
+            if (cl[u].own) {
+                cstore(S.y + cl[u].idx, yt);
+                const double yd = (double)to_f32(yt), qd = (double)q.c, rd = (double)to_f32(rh[u]);
+                acc[0] = fma(qd, yd, acc[0]);
+                acc[1] = fma(yd, yd, acc[1]);
+                acc[2] = fma(qd, qd, acc[2]);
+                acc[3] = fma(rd, qd, acc[3]);
+                acc[4] = fma(rd, yd, acc[4]);
+            }
+        }
+    }
+}
+
+template <class T>
+__device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, float omega,
+                           float beta, double (&acc)[kMaxDots]) {
+    for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads) {
+        float dv = cload(S.d + i);
+        T rn, pn;
+        p3_math<T>(alpha, omega, beta, to_f32(cload(S.p + i)), to_f32(cload(S.s + i)),
+                   to_f32(cload(S.y + i)), to_f32(cload(S.q + i)), dv, rn, pn);
+        cstore(S.d + i, dv);
+        cstore(S.r + i, rn);
+        cstore(S.p + i, pn);
+        const double rd = (double)to_f32(rn);
+        acc[0] = fma((double)to_f32(S.rhat[i]), rd, acc[0]);
+        acc[1] = fma(rd, rd, acc[1]);
+    }
+}
+
+constexpr int kND[4] = {1, 0, 5, 2};  // dot products of P1, P2a, P2b, P3
+
+template <class T>
+__device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, int c0, int c1,
+                                          float alpha, float omega, float beta,
+                                          double (&acc)[kMaxDots]) {
+    const SysView<T> S = as_view<T>(raw);
+    if (phase == 0) {
+        if (S.unit) chunk_p1_b<T, true>(S, c0, c1, acc);
+        else chunk_p1_b<T, false>(S, c0, c1, acc);
+    } else if (phase == 1) {
+        chunk_p2a_b<T>(S, c0, c1, alpha);
+    } else if (phase == 2) {
+        if (S.unit) chunk_p2b_b<T, true>(S, c0, c1, acc);
+        else chunk_p2b_b<T, false>(S, c0, c1, acc);
+    } else {
+        chunk_p3_b<T>(S, c0, c1, alpha, omega, beta, acc);
+    }
+}
+
+// ---------------------------------------------------------------- persistent kernel
+__global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* glob,
+                                                      int nsys, int chunk_cells,
+                                                      long long spin_limit) {
+    __shared__ int sh_sys, sh_chunk, sh_seq, sh_last;
+    int s = (int)(blockIdx.x % (unsigned)nsys);
+    long long idle = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            sh_sys = -1;
+            if (cload_i(&glob->active) > 0 && cload_i(&glob->error) == 0) {
+                for (int tries = 0; tries < nsys; ++tries, s = (s + 1 == nsys) ? 0 : s + 1) {
+                    if (!cload_i(&sys[s].ctl->active)) continue;
+                    const unsigned long long w0 = __hip_atomic_load(
+                        &sys[s].ctl->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((int)(w0 & 0xffffffffull) >= sys[s].nchunk) continue;
+                    const unsigned long long w = __hip_atomic_fetch_add(
+                        &sys[s].ctl->claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int c = (int)(w & 0xffffffffull);
+                    if (c < sys[s].nchunk) {
+                        sh_sys = s;
+                        sh_chunk = c;
+                        sh_seq = (int)(w >> 32);
+                        break;
+                    }
+                }
+            } else {
+                sh_sys = -2;  // nothing left in this launch
+            }
+        }
+        __syncthreads();
+        const int me = sh_sys;
+        if (me == -2) return;
+        if (me < 0) {
+            if (++idle > spin_limit) {
+                if (threadIdx.x == 0) cstore_i(&glob->error, 1);
+                return;
+            }
+            __builtin_amdgcn_s_sleep(8);
+            __syncthreads();
+            continue;
+        }
+        idle = 0;
+        const SysView<float> S = sys[me].S;
+        const int tag = sys[me].tag;
+        const int chunk = sh_chunk, seq = sh_seq, phase = seq & 3;
+        const int c0 = chunk * chunk_cells;
+        const int c1 = min(S.n, c0 + chunk_cells);
+        const float alpha = (float)cload_d(&S.st->alpha);
+        const float omega = (float)cload_d(&S.st->omega);
+        const float beta = (float)cload_d(&S.st->beta);
+        double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (tag == 0) run_chunk<float>(S, phase, c0, c1, alpha, omega, beta, acc);
+        else if (tag == 1) run_chunk<bf16>(S, phase, c0, c1, alpha, omega, beta, acc);
+        else run_chunk<f16>(S, phase, c0, c1, alpha, omega, beta, acc);
+        // publish this chunk's partials, then count the chunk done
+        double bsum[kMaxDots];
+        block_reduce<kMaxDots, 0u>(acc, bsum);
+        if (threadIdx.x == 0) {
+            for (int j = 0; j < kND[phase]; ++j) publish(&S.red.part[(size_t)chunk * kMaxDots + j], bsum[j]);
+            wait_stores();
+            const uint32_t t = __hip_atomic_fetch_add(&sys[me].ctl->done_cnt, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+            sh_last = (t == (uint32_t)(sys[me].nchunk - 1));
+        }
+        __syncthreads();
+        if (!sh_last) continue;
+        // this workgroup completes the phase: sum the partials in chunk order
+        double tot[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (kND[phase] > 0) sum_range<kMaxDots, 0u, true>(S.red.part, 0, sys[me].nchunk, tot);
+        if (threadIdx.x == 0) {
+            State st;
+            state_load(S.st, st);
+            if (phase == 0) tail_p1(&st, reinterpret_cast<double(&)[1]>(tot));
+            if (phase == 2) tail_p2(&st, reinterpret_cast<double(&)[5]>(tot));
+            if (phase == 3) tail_p3(&st, reinterpret_cast<double(&)[2]>(tot));
+            int32_t budget = cload_i(&sys[me].ctl->budget);
+            bool stop = st.done != 0;
+            if (phase == 3 && !stop) {
+                budget -= 1;
+                stop = budget <= 0;
+            }
+            state_store(S.st, st);
+            __hip_atomic_store(&sys[me].ctl->done_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cstore_i(&sys[me].ctl->budget, budget);
+            if (stop) {
+                cstore_i(&sys[me].ctl->active, 0);
+                // Park the claim word on the phase to resume, with its chunk counter
+                // already exhausted: a workgroup racing this store claims nothing.  The
+                // next launch's arm step rewinds the counter.
+                const unsigned long long resume = (unsigned long long)(st.done ? seq : seq + 1);
+                __hip_atomic_store(&sys[me].ctl->claim, (resume << 32) | (unsigned)sys[me].nchunk,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                wait_stores();
+                __hip_atomic_fetch_add(&glob->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                wait_stores();
+                __hip_atomic_store(&sys[me].ctl->claim, (unsigned long long)(seq + 1) << 32,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Arms a launch: every system that is not done takes part with `budget`
+// iterations; the global count of active systems is set accordingly.
+__global__ __launch_bounds__(kThreads) void k_batched_arm(const BSys* sys, BGlobal* glob, int nsys,
+                                                          int budget) {
+    __shared__ int count;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < nsys; s += kThreads) {
+        const int done = sys[s].S.st->done;
+        sys[s].ctl->claim &= 0xffffffff00000000ull;  // rewind the chunk counter of the parked phase
+        sys[s].ctl->active = done ? 0 : 1;
+        sys[s].ctl->budget = budget;
+        sys[s].ctl->done_cnt = 0u;
+        if (!done) atomicAdd(&count, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        glob->active = count;
+        glob->error = 0;
+    }
+}
+
+}  // namespace s7

@@ -30,7 +30,7 @@ constexpr int kWave = 64;
 constexpr int kWaves = 4;  // wavefronts per workgroup
 constexpr int kThreads = kWave * kWaves;
 constexpr int kMaxDots = 6;
-constexpr int kGroup = 1024;  // workgroups per first-level reduction group
+constexpr int kGroup = 8192;  // workgroup partials summed by one workgroup of a finishing kernel
 
 // ---------------------------------------------------------------- types
 struct bf16 {
@@ -260,24 +260,47 @@ __device__ __forceinline__ void set_breakdown(State* st, int32_t reason) {
 // Reduction scratch of one system: per-workgroup partials, second-level
 // partials and one arrival counter (zero between uses).
 //
-// A grid-wide sum ends in a "last workgroup" step, decided by an atomic ticket
-// after a release fence.  On this multi-XCD device an agent-scope release
-// fence writes back the XCD's L2, which is cheap a few thousand times per
-// pass but ruinous millions of times.  So passes with at most kSingleMax
-// workgroups finish their sums in-kernel.  Larger passes only store their
-// workgroup partials, and a second kernel (k_finish) sums them in blocks of
-// kGroup, then finishes with the ticket among its own workgroups.  Every sum
-// runs in a fixed index order, so the result never depends on arrival order.
+// A grid-wide sum ends in a "last workgroup" step decided by an atomic ticket.
+// The partials are published coherently instead of behind a release fence.
+// The workgroup writes its partial with agent-scope atomic stores, which go to
+// the device coherence point, not the XCD-private L2.  It waits until they
+// have completed (s_waitcnt), then takes the ticket.  The last workgroup reads
+// the partials with agent-scope atomic loads.  On this multi-XCD device an
+// agent-scope release fence would also write back the XCD's whole L2.  At
+// tens of nanoseconds per workgroup, serialized, that fence costs more than
+// the pass it ends.
+// Passes with at most kSingleMax workgroups finish their sums in-kernel.
+// Larger passes only store their workgroup partials; a second kernel
+// (k_finish) sums them in runs of kGroup and finishes with the ticket among
+// its own few workgroups.  Every sum runs in a fixed index order, so the
+// result never depends on arrival order.
 struct Red {
     double* part;
     double* gpart;
     uint32_t* cnt;
 };
 
-constexpr int kSingleMax = 4096;
+constexpr int kSingleMax = 1024;
 
 __host__ __device__ inline int red_groups(int nblocks) { return (nblocks + kGroup - 1) / kGroup; }
 __host__ __device__ inline bool red_split(int nblocks) { return nblocks > kSingleMax; }
+
+__device__ __forceinline__ void publish(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double fetch_published(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until this thread's stores have completed; the signal fences keep the
+// compiler from moving memory operations across the wait.
+__device__ __forceinline__ void wait_stores() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+__device__ __forceinline__ uint32_t take_ticket(uint32_t* cnt) {
+    return __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // DPP move of an FP64 value (both 32-bit halves with the same control).
 // Lanes whose row is masked off, or that have no source lane, read 0.
@@ -348,15 +371,18 @@ __device__ __forceinline__ void block_reduce(double (&acc)[ND], double (&out)[ND
 }
 
 // Sums src[i*ND + j] for i in [i0, i1) into out (thread 0), in a fixed order.
-template <int ND, unsigned MAXMASK>
+// COHERENT: the partials were published by other workgroups of this kernel.
+template <int ND, unsigned MAXMASK, bool COHERENT>
 __device__ __forceinline__ void sum_range(const double* src, int i0, int i1, double (&out)[ND]) {
     double s[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) s[j] = 0.0;
     for (int b = i0 + (int)threadIdx.x; b < i1; b += kThreads) {
 #pragma unroll
-        for (int j = 0; j < ND; ++j)
-            s[j] = comb<ND, MAXMASK>(j, s[j], __builtin_nontemporal_load(&src[(size_t)b * ND + j]));
+        for (int j = 0; j < ND; ++j) {
+            const double* p = &src[(size_t)b * ND + j];
+            s[j] = comb<ND, MAXMASK>(j, s[j], COHERENT ? fetch_published(p) : *p);
+        }
     }
     block_reduce<ND, MAXMASK>(s, out);
 }
@@ -372,15 +398,14 @@ __device__ bool reduce_ticket(double (&acc)[ND], double* part, uint32_t* cnt, in
     block_reduce<ND, MAXMASK>(acc, bsum);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int j = 0; j < ND; ++j) part[(size_t)bid * ND + j] = bsum[j];
-        __threadfence();
-        flag = (atomicAdd(cnt, 1u) == (uint32_t)(nblocks - 1));
+        for (int j = 0; j < ND; ++j) publish(&part[(size_t)bid * ND + j], bsum[j]);
+        wait_stores();
+        flag = (take_ticket(cnt) == (uint32_t)(nblocks - 1));
     }
     __syncthreads();
     if (!flag) return false;
-    __threadfence();
-    sum_range<ND, MAXMASK>(part, 0, nblocks, tot);
-    if (threadIdx.x == 0) *cnt = 0u;
+    sum_range<ND, MAXMASK, true>(part, 0, nblocks, tot);
+    if (threadIdx.x == 0) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
 
@@ -417,7 +442,7 @@ __device__ __forceinline__ bool finish_split(const Red& red, int nblocks, double
 #pragma unroll
     for (int j = 0; j < ND; ++j) gs[j] = 0.0;
     const int g = blockIdx.x;
-    sum_range<ND, MAXMASK>(red.part, g * kGroup, min(nblocks, (g + 1) * kGroup), gs);
+    sum_range<ND, MAXMASK, false>(red.part, g * kGroup, min(nblocks, (g + 1) * kGroup), gs);
     return reduce_ticket<ND, MAXMASK>(gs, red.gpart, red.cnt, (int)gridDim.x, g, tot);
 }
 

@@ -52,10 +52,10 @@ inline int stream_blocks_for(long long n, int cap) {
     return (int)b;
 }
 
-// Workspace of one system:
-// [State][partials][group partials][counters][coef copies][5 vectors of T][d: FP32].
+// Workspace of one system: [State][partials][group partials][counter]
+// [batch control][coef copies][6 vectors of T: r, r0, p, s, y, q][d: FP32].
 struct Layout {
-    size_t off_state, off_part, off_gpart, off_cnt, off_coef, off_vec, off_d, bytes;
+    size_t off_state, off_part, off_gpart, off_cnt, off_ctl, off_coef, off_vec, off_d, bytes;
     int ncoef;
     int cell_blocks, stream_blocks, groups;
     size_t elt;
@@ -65,5 +65,52 @@ struct Layout {
 Layout make_layout(s7_dims d, int prec, const s7_options& o);
 
 void options_or_default(const s7_options* in, s7_options& out);
+
+// ---------------------------------------------------------------- batch engine
+// Runs many systems together: the batched entry point and the request queue
+// both drive it.  Each system brings its own workspace slice (s7_workspace_bytes
+// of its dims and precision).  The engine's tables (one BSys per resident
+// system and the launch-global words) live in a separate device region of
+// engine_table_bytes(capacity).
+struct EngineJob {
+    s7_dims d;
+    const float* coef[7];
+    const double* b;
+    double* x;
+    double rtol;
+    int32_t max_iter;
+    int32_t prec;
+    char* ws;         // the job's workspace slice
+    size_t ws_bytes;
+    s7_info info;     // filled when the job is finished
+    int finished;     // 1 once info is final
+    void* user;       // owner's handle
+    // engine-private progress
+    int stage, tag, nchunk, total, outer, stall, status, reason;
+    double rel, inner_res, scale;
+    Layout lo;
+    double t_start_ms;
+};
+
+size_t engine_table_bytes(int capacity);
+
+class BatchEngine {
+  public:
+    BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream);
+    // Takes part from the next step on; the job's arrays must stay valid until finished.
+    int add(EngineJob* job);
+    // Advances every resident job: starts new ones, runs one persistent launch of at
+    // most `epoch_iters` BiCGStab iterations per job, and handles refinement steps
+    // and epilogues.  Finished jobs leave the resident set.  Returns S7_OK or an error.
+    int step(int epoch_iters);
+    int resident() const { return (int)jobs_.size(); }
+
+  private:
+    char* tables_;
+    int cap_;
+    s7_options o_;
+    hipStream_t st_;
+    std::vector<EngineJob*> jobs_;
+};
 
 }  // namespace s7

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "s7_host.hpp"
+#include "s7_batched_kernels.hpp"
 
 namespace s7 {
 
@@ -64,6 +65,8 @@ Layout make_layout(s7_dims d, int prec, const s7_options& o) {
     off = align256(off + (size_t)L.groups * kMaxDots * sizeof(double));
     L.off_cnt = off;
     off = align256(off + sizeof(uint32_t));
+    L.off_ctl = off;
+    off = align256(off + sizeof(BCtl));
     L.off_coef = off;
     off = align256(off + (size_t)L.ncoef * align256(L.n * L.elt));
     L.off_vec = off;
@@ -674,6 +677,281 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
     return status;
 }
 
+// ============================================================== batch engine
+enum JobStage { J_NEW = 0, J_RESID = 1, J_ITER = 2, J_FINAL = 3, J_DONE = 4 };
+
+size_t engine_table_bytes(int capacity) {
+    return align256(sizeof(BGlobal)) + align256((size_t)capacity * sizeof(BSys));
+}
+
+BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream)
+    : tables_(tables), cap_(capacity), o_(o), st_(stream) {}
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+int BatchEngine::add(EngineJob* j) {
+    if ((int)jobs_.size() >= cap_) {
+        set_error("batch engine: more than %d resident systems", cap_);
+        return S7_EAGAIN;
+    }
+    j->lo = make_layout(j->d, j->prec, o_);
+    j->stage = J_NEW;
+    j->tag = j->prec == S7_FP32 ? 0 : (j->prec == S7_BF16_IR ? 1 : 2);
+    j->total = j->outer = j->stall = 0;
+    j->status = S7_NOT_CONVERGED;
+    j->reason = 0;
+    j->rel = INFINITY;
+    j->inner_res = 0.0;
+    j->scale = 1.0;
+    j->finished = 0;
+    std::memset(&j->info, 0, sizeof(j->info));
+    if (j->t_start_ms <= 0.0) j->t_start_ms = now_ms();
+    jobs_.push_back(j);
+    return S7_OK;
+}
+
+static int chunk_cells_of(const s7_options& o) {
+    int c = o.chunk_cells > 0 ? o.chunk_cells : 4096;
+    c = (c + kThreads - 1) / kThreads * kThreads;
+    return c;
+}
+
+template <class T>
+static int job_view(const EngineJob& j, SysView<T>& S) {
+    S = make_view<T>(j.d, j.lo, 1, j.ws);
+    return S7_OK;
+}
+
+// Launches the first kernels of a job: state clear, coefficient copies, and
+// either the FP32 r0 (iteration starts next) or the first FP64 residual of the
+// refinement.
+template <class T>
+static int job_start(EngineJob& j, const s7_options& o, hipStream_t s) {
+    SysView<T> S = make_view<T>(j.d, j.lo, o.jacobi, j.ws);
+    Coef7 cf;
+    for (int a = 0; a < 7; ++a) cf.c[a] = j.coef[a];
+    int rc = start_solve<T>(cf, S, j.lo, o.jacobi, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl));
+    if constexpr (std::is_same<T, float>::value) {
+        hipLaunchKernelGGL(k_init_f32, dim3(S.cell_blocks), dim3(kThreads), 0, s, cf, j.b, j.x, S,
+                           o.jacobi, j.rtol, j.max_iter);
+        launch_finish<3, 0u, FIN_INIT>(S.red, S.cell_blocks, S.st, s, j.rtol, j.max_iter);
+        j.stage = J_ITER;
+    } else {
+        rc = resid_launch<T>(cf, j.b, j.x, S.d, S, o.jacobi, s);
+        if (rc) return rc;
+        j.stage = J_RESID;
+    }
+    S7_CHECK_LAUNCH();
+    return S7_OK;
+}
+
+// Refinement decision after an FP64 residual pass (same rules as the single
+// solve): stop, or start the next inner solve on r / scale.
+template <class T>
+static int job_outer(EngineJob& j, const State& h, const s7_options& o, hipStream_t s) {
+    SysView<T> S = make_view<T>(j.d, j.lo, o.jacobi, j.ws);
+    if (h.bb_true == 0.0) {
+        hipLaunchKernelGGL(k_fill0, dim3(grid_for(S.n)), dim3(kThreads), 0, s, j.x, S.n);
+        j.rel = 0.0;
+        j.status = S7_OK;
+        j.stage = J_DONE;
+        S7_CHECK_LAUNCH();
+        return S7_OK;
+    }
+    const double nrel = sqrt(h.rr_true / h.bb_true);
+    if (!std::isfinite(nrel)) {
+        j.status = S7_BREAKDOWN;
+        j.reason = S7_REASON_NONFINITE;
+        j.rel = nrel;
+        j.stage = J_DONE;
+        return S7_OK;
+    }
+    j.stall = (nrel > 0.5 * j.rel) ? j.stall + 1 : 0;
+    j.rel = nrel;
+    const int outer_cap = o.outer_max_iter > 0 ? o.outer_max_iter : 30;
+    if (j.rel <= j.rtol) {
+        j.status = S7_OK;
+        j.stage = J_DONE;
+        return S7_OK;
+    }
+    if (j.outer >= outer_cap || j.total >= j.max_iter || j.stall >= 3) {
+        j.status = S7_NOT_CONVERGED;
+        j.stage = J_DONE;
+        return S7_OK;
+    }
+    const double inner_tol = o.inner_rtol > 0 ? o.inner_rtol : (j.prec == S7_FP16_IR ? 5e-3 : 1e-2);
+    const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : 100;
+    j.scale = h.rmax > 0 ? exp2(ceil(log2(h.rmax))) : 1.0;
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl));
+    hipLaunchKernelGGL((k_ir_init<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S,
+                       (float)(1.0 / j.scale), inner_tol,
+                       inner_cap < j.max_iter - j.total ? inner_cap : j.max_iter - j.total);
+    S7_CHECK_LAUNCH();
+    j.stage = J_ITER;
+    return S7_OK;
+}
+
+// After an inner solve finished: FP32 -> x update and true residual (final);
+// refinement -> x += scale d and the next residual pass.
+template <class T>
+static int job_inner_done(EngineJob& j, const State& h, const s7_options& o, hipStream_t s) {
+    SysView<T> S = make_view<T>(j.d, j.lo, o.jacobi, j.ws);
+    Coef7 cf;
+    for (int a = 0; a < 7; ++a) cf.c[a] = j.coef[a];
+    if (j.prec == S7_FP32) {
+        j.total = h.iter;
+        j.status = h.status;
+        j.reason = h.reason;
+        j.inner_res = h.res_rec;
+        hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, j.x, S.d, S.n, 1.0, S.st);
+        int rc = resid_launch<T>(cf, j.b, j.x, nullptr, S, o.jacobi, s);
+        if (rc) return rc;
+        j.stage = J_FINAL;
+        return S7_OK;
+    }
+    j.total += h.iter;
+    j.outer += 1;
+    j.inner_res = h.res_rec;
+    if (h.status == S7_BREAKDOWN && h.iter == 0) {
+        j.status = S7_BREAKDOWN;
+        j.reason = h.reason;
+        j.stage = J_DONE;
+        return S7_OK;
+    }
+    hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, j.x, S.d, S.n, j.scale, S.st);
+    int rc = resid_launch<T>(cf, j.b, j.x, S.d, S, o.jacobi, s);
+    if (rc) return rc;
+    j.stage = J_RESID;
+    return S7_OK;
+}
+
+#define S7_BY_PREC(j, call)                                           \
+    ((j).prec == S7_FP32 ? call<float> : ((j).prec == S7_BF16_IR ? call<bf16> : call<f16>))
+
+static int read_states(std::vector<EngineJob*>& js, std::vector<State>& h, hipStream_t s) {
+    h.resize(js.size());
+    for (size_t i = 0; i < js.size(); ++i)
+        S7_HIP(hipMemcpyAsync(&h[i], js[i]->ws + js[i]->lo.off_state, sizeof(State),
+                              hipMemcpyDeviceToHost, s));
+    S7_HIP(hipStreamSynchronize(s));
+    return S7_OK;
+}
+
+static void finish_job(EngineJob& j, const State* h) {
+    s7_info& inf = j.info;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.iters = j.total;
+    inf.outer_iters = j.prec == S7_FP32 ? 1 : j.outer;
+    inf.status = j.status;
+    inf.reason = j.reason;
+    inf.rel_res_rec = j.inner_res;
+    if (j.prec == S7_FP32 && h) {
+        inf.rel_res_true = h->bb_true > 0 ? sqrt(h->rr_true / h->bb_true) : 0.0;
+    } else {
+        inf.rel_res_true = j.rel;
+    }
+    inf.t_ms = now_ms() - j.t_start_ms;
+    j.stage = J_DONE;
+    j.finished = 1;
+}
+
+int BatchEngine::step(int epoch_iters) {
+    int rc;
+    // 1) start new jobs
+    for (EngineJob* j : jobs_) {
+        if (j->stage != J_NEW) continue;
+        rc = S7_BY_PREC(*j, job_start)(*j, o_, st_);
+        if (rc) return rc;
+    }
+    std::vector<State> h;
+    rc = read_states(jobs_, h, st_);
+    if (rc) return rc;
+    // 2) refinement decisions and inner solves that are already over (trivial starts)
+    for (size_t i = 0; i < jobs_.size(); ++i) {
+        EngineJob* j = jobs_[i];
+        if (j->stage == J_RESID) {
+            rc = S7_BY_PREC(*j, job_outer)(*j, h[i], o_, st_);
+            if (rc) return rc;
+        }
+    }
+    rc = read_states(jobs_, h, st_);
+    if (rc) return rc;
+    // 3) one persistent launch over every job in an inner solve
+    std::vector<BSys> table;
+    std::vector<EngineJob*> in_launch;
+    int max_chunks = 0;
+    const int chunk = chunk_cells_of(o_);
+    for (size_t i = 0; i < jobs_.size(); ++i) {
+        EngineJob* j = jobs_[i];
+        if (j->stage != J_ITER || h[i].done) continue;
+        BSys b;
+        SysView<float> v = make_view<float>(j->d, j->lo, o_.jacobi, j->ws);
+        b.S = v;
+        b.ctl = reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl);
+        b.nchunk = (int)((j->lo.n + chunk - 1) / chunk);
+        b.tag = j->tag;
+        max_chunks = max_chunks > b.nchunk ? max_chunks : b.nchunk;
+        table.push_back(b);
+        in_launch.push_back(j);
+    }
+    if (!table.empty()) {
+        BGlobal* glob = reinterpret_cast<BGlobal*>(tables_);
+        BSys* dsys = reinterpret_cast<BSys*>(tables_ + align256(sizeof(BGlobal)));
+        S7_HIP(hipMemcpyAsync(dsys, table.data(), table.size() * sizeof(BSys), hipMemcpyHostToDevice, st_));
+        const int nsys = (int)table.size();
+        long long total_chunks = 0;
+        for (const BSys& b : table) total_chunks += b.nchunk;
+        int grid = (int)(total_chunks < 1024 ? total_chunks : 1024);
+        if (grid < 1) grid = 1;
+        const long long spin_limit = 5000000;
+        std::vector<uintptr_t> key = {0x53u, (uintptr_t)tables_, (uintptr_t)nsys, (uintptr_t)epoch_iters,
+                                      (uintptr_t)grid, (uintptr_t)chunk};
+        hipGraphExec_t g;
+        rc = cached_graph(key, [&](hipStream_t cs) {
+            hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
+                               nsys, epoch_iters);
+            hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
+                               chunk, spin_limit);
+        }, &g);
+        if (rc) return rc;
+        S7_HIP(hipGraphLaunch(g, st_));
+        BGlobal hg;
+        S7_HIP(hipMemcpyAsync(&hg, glob, sizeof(hg), hipMemcpyDeviceToHost, st_));
+        S7_HIP(hipStreamSynchronize(st_));
+        if (hg.error) {
+            set_error("batched launch: a workgroup exceeded its wait bound");
+            return S7_EHIP;
+        }
+    }
+    rc = read_states(jobs_, h, st_);
+    if (rc) return rc;
+    // 4) inner solves that ended
+    for (size_t i = 0; i < jobs_.size(); ++i) {
+        EngineJob* j = jobs_[i];
+        if (j->stage == J_ITER && h[i].done) {
+            rc = S7_BY_PREC(*j, job_inner_done)(*j, h[i], o_, st_);
+            if (rc) return rc;
+        }
+    }
+    rc = read_states(jobs_, h, st_);
+    if (rc) return rc;
+    // 5) finished jobs leave
+    std::vector<EngineJob*> keep;
+    for (size_t i = 0; i < jobs_.size(); ++i) {
+        EngineJob* j = jobs_[i];
+        if (j->stage == J_FINAL) finish_job(*j, &h[i]);
+        else if (j->stage == J_DONE) finish_job(*j, nullptr);
+        if (!j->finished) keep.push_back(j);
+    }
+    jobs_.swap(keep);
+    return S7_OK;
+}
+
 }  // namespace s7
 
 // ============================================================== C ABI
@@ -775,6 +1053,83 @@ int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float* const c
         S7_CHECK_LAUNCH();
     }
     return S7_OK;
+}
+
+size_t s7_batched_workspace_bytes(int32_t nsys, const s7_dims* d, int32_t prec, const s7_options* opt) {
+    if (nsys < 1 || !d || prec < S7_FP32 || prec > S7_FP16_IR) return 0;
+    s7_options o;
+    options_or_default(opt, o);
+    size_t total = align256(engine_table_bytes(nsys));
+    for (int i = 0; i < nsys; ++i) {
+        if (!dims_ok(d[i])) return 0;
+        total += align256(make_layout(d[i], prec, o).bytes);
+    }
+    return total;
+}
+
+int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const* coef,
+                              const double* const* b, double* const* x, const double* rtol,
+                              const int32_t* max_iter, int32_t prec, void* ws, size_t ws_bytes,
+                              const s7_options* opt, s7_info* info, void* stream) {
+    clear_error();
+    s7_options o;
+    options_or_default(opt, o);
+    if (nsys < 1 || !d || !coef || !b || !x || !rtol || !max_iter || !ws ||
+        ((uintptr_t)ws & 255u) != 0 || prec < S7_FP32 || prec > S7_FP16_IR) {
+        set_error("s7_bicgstab_solve_batched: invalid argument");
+        return S7_EINVAL;
+    }
+    for (int i = 0; i < nsys; ++i) {
+        bool ok = dims_ok(d[i]) && b[i] && x[i] && rtol[i] > 0.0 && max_iter[i] >= 0;
+        for (int a = 0; a < 7 && ok; ++a) ok = coef[7 * i + a] != nullptr;
+        if (!ok) {
+            set_error("s7_bicgstab_solve_batched: invalid argument for system %d", i);
+            return S7_EINVAL;
+        }
+    }
+    const size_t need = s7_batched_workspace_bytes(nsys, d, prec, &o);
+    if (ws_bytes < need) {
+        set_error("s7_bicgstab_solve_batched: workspace too small (%zu < %zu)", ws_bytes, need);
+        return S7_EINVAL;
+    }
+    char* w = (char*)ws;
+    hipStream_t s = (hipStream_t)stream;
+    BatchEngine eng(w, nsys, o, s);
+    std::vector<EngineJob> jobs((size_t)nsys);
+    size_t off = align256(engine_table_bytes(nsys));
+    const double t0 = now_ms();
+    for (int i = 0; i < nsys; ++i) {
+        EngineJob& j = jobs[i];
+        std::memset(&j, 0, sizeof(j));
+        j.d = d[i];
+        for (int a = 0; a < 7; ++a) j.coef[a] = coef[7 * i + a];
+        j.b = b[i];
+        j.x = x[i];
+        j.rtol = rtol[i];
+        j.max_iter = max_iter[i];
+        j.prec = prec;
+        j.ws = w + off;
+        j.ws_bytes = make_layout(d[i], prec, o).bytes;
+        j.t_start_ms = t0;
+        off += align256(j.ws_bytes);
+        int rc = eng.add(&j);
+        if (rc) return rc;
+    }
+    int guard = 0;
+    while (eng.resident() > 0) {
+        int rc = eng.step(1 << 30);
+        if (rc) return rc;
+        if (++guard > 100000) {
+            set_error("s7_bicgstab_solve_batched: no progress");
+            return S7_EHIP;
+        }
+    }
+    int worst = S7_OK;
+    for (int i = 0; i < nsys; ++i) {
+        if (info) info[i] = jobs[i].info;
+        if (jobs[i].info.status > worst) worst = jobs[i].info.status;
+    }
+    return worst;
 }
 
 }  // extern "C"

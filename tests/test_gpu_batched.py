@@ -1,0 +1,153 @@
+"""GPU parity of the batched persistent solver (s7_bicgstab_solve_batched).
+
+Each system of a batch is checked against the FP64 oracle.  Each system's result
+must not depend on the rest of the batch: solved alone through the same path, it
+comes out bit for bit the same, because its sums run in a fixed per-system order."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.conftest import gpu_available
+from tests.gpu_helpers import coef_dev, dev, host, problem, rel_err
+
+pytestmark = pytest.mark.gpu
+
+UNEVEN = [(24, 32, 48), (64, 24, 32), (17, 5, 9), (33, 17, 9), (40, 24, 20), (2, 1, 1),
+          (96, 48, 24), (31, 29, 27)]
+
+
+@pytest.fixture(scope="module")
+def s7():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import paper_2010_03660_amd as s7
+    s7.lib()
+    return s7
+
+
+def make_batch(shapes, seeds):
+    probs = [problem(d, seed=s) for d, s in zip(shapes, seeds)]
+    return probs
+
+
+def run_batch(s7, shapes, probs, rtol, max_iter=1000, prec=0, **opt):
+    import torch
+    coefs = [coef_dev(p) for p, A, b in probs]
+    bs = [dev(b) for p, A, b in probs]
+    xs = [torch.zeros(A.n, dtype=torch.float64, device="cuda") for p, A, b in probs]
+    o = s7.default_options(**opt)
+    rc, infos = s7.bicgstab_solve_batched(shapes, coefs, bs, xs, [rtol] * len(shapes),
+                                          [max_iter] * len(shapes), prec=prec, opt=o)
+    torch.cuda.synchronize()
+    return rc, infos, [host(x) for x in xs]
+
+
+def test_uneven_batch_matches_oracle(s7):
+    seeds = [100 + i for i in range(len(UNEVEN))]
+    probs = make_batch(UNEVEN, seeds)
+    rc, infos, xs = run_batch(s7, UNEVEN, probs, rtol=1e-8)
+    assert rc == s7.OK, [i.as_dict() for i in infos]
+    for (p, A, b), info, x in zip(probs, infos, xs):
+        ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+        assert info.status == s7.OK
+        assert rel_err(x, ref.x) <= 1e-6
+        assert abs(info.rel_res_true - oracle.true_rel_residual(A, b, x)) <= 1e-3 * info.rel_res_true + 1e-15
+        r8 = oracle.bicgstab(A, b, tol=1e-8, max_iter=2000)
+        assert abs(info.iters - r8.iters) <= max(3, 0.2 * r8.iters)
+
+
+@pytest.mark.parametrize("chunk", [256, 1024, 4096])
+def test_alone_equals_in_mix_bitwise(s7, chunk):
+    seeds = [200 + i for i in range(len(UNEVEN))]
+    probs = make_batch(UNEVEN, seeds)
+    rc, infos, xs = run_batch(s7, UNEVEN, probs, rtol=1e-8, chunk_cells=chunk)
+    for k in (0, 3, 6):
+        rc1, inf1, x1 = run_batch(s7, [UNEVEN[k]], [probs[k]], rtol=1e-8, chunk_cells=chunk)
+        assert np.array_equal(x1[0], xs[k]), k
+        assert inf1[0].iters == infos[k].iters
+
+
+def test_batched_iterates_track_oracle(s7):
+    shapes = [(40, 24, 20), (33, 17, 9)]
+    probs = make_batch(shapes, [7, 8])
+    for k in (1, 2, 5):
+        rc, infos, xs = run_batch(s7, shapes, probs, rtol=1e-300, max_iter=k)
+        for (p, A, b), info, x in zip(probs, infos, xs):
+            ref = oracle.bicgstab(A, b, tol=1e-300, max_iter=k)
+            assert info.status == s7.NOT_CONVERGED and info.iters == k
+            assert rel_err(x, ref.x) <= 1e-4
+            assert abs(info.rel_res_rec - ref.res_rec) <= 1e-3 * ref.res_rec
+
+
+def test_batched_edge_systems(s7):
+    import torch
+    # a zero right-hand side, an exact breakdown and a regular system in one batch
+    shapes = [(9, 7, 5), (2, 1, 1), (33, 17, 9)]
+    p0, A0, b0 = problem(shapes[0], seed=2)
+    coef_bd = [np.zeros(2, np.float32) for _ in range(7)]
+    coef_bd[0][:] = 0.0
+    coef_bd[2][0] = 1.0
+    coef_bd[1][1] = -1.0
+    p2, A2, b2 = problem(shapes[2], seed=3)
+    coefs = [coef_dev(p0), [dev(c) for c in coef_bd], coef_dev(p2)]
+    bs = [dev(np.zeros(A0.n)), dev(np.array([1.0, 0.0])), dev(b2)]
+    xs = [torch.ones(A0.n, dtype=torch.float64, device="cuda"),
+          torch.zeros(2, dtype=torch.float64, device="cuda"),
+          torch.zeros(A2.n, dtype=torch.float64, device="cuda")]
+    rc, infos = s7.bicgstab_solve_batched(shapes, coefs, bs, xs, [1e-8] * 3, [100] * 3,
+                                          opt=s7.default_options(jacobi=0))
+    torch.cuda.synchronize()
+    assert infos[0].status == s7.OK and np.all(host(xs[0]) == 0)
+    assert infos[1].status == s7.BREAKDOWN and infos[1].reason == s7.REASON_RS_ZERO
+    assert infos[2].status == s7.OK
+    ref = oracle.bicgstab(A2, b2, tol=1e-12, max_iter=1000, jacobi_scaling=False)
+    assert rel_err(host(xs[2]), ref.x) <= 1e-6
+    assert rc == s7.BREAKDOWN
+
+
+@pytest.mark.parametrize("prec", ["bf16_ir", "fp16_ir"])
+def test_batched_mixed_precision(s7, prec):
+    shapes = [(32, 32, 32), (24, 48, 17), (40, 24, 20)]
+    probs = make_batch(shapes, [5, 6, 7])
+    rc, infos, xs = run_batch(s7, shapes, probs, rtol=1e-10, max_iter=2000,
+                              prec=s7.PREC_NAMES[prec])
+    assert rc == s7.OK, [i.as_dict() for i in infos]
+    for (p, A, b), info, x in zip(probs, infos, xs):
+        ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
+        assert info.rel_res_true <= 1e-10
+        assert rel_err(x, ref.x) <= 1e-7
+        assert info.outer_iters > 1
+
+
+def test_batch_workload_64_systems(s7):
+    """64 systems, each side uniform over {24,...,128}, per-system seeds, tolerance 1e-7:
+    every system checked against the oracle on a sample, all checked for status and
+    true residual."""
+    import torch
+    shapes, seeds = synth.batch_shapes(64, seed=0)
+    n_total = sum(int(np.prod(s)) for s in shapes)
+    coefs, bs, xs, xstars = [], [], [], []
+    for d, sd in zip(shapes, seeds):
+        n = int(np.prod(d))
+        c = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(7)]
+        xsd = torch.empty(n, dtype=torch.float64, device="cuda")
+        bd = torch.empty(n, dtype=torch.float64, device="cuda")
+        s7.generate_problem(d, sd, 0, c, xsd, bd)
+        coefs.append(c)
+        bs.append(bd)
+        xstars.append(xsd)
+        xs.append(torch.zeros(n, dtype=torch.float64, device="cuda"))
+    rc, infos = s7.bicgstab_solve_batched(shapes, coefs, bs, xs, [1e-7] * 64, [2000] * 64)
+    torch.cuda.synchronize()
+    assert rc == s7.OK
+    assert n_total > 5_000_000
+    for k, (d, sd, info) in enumerate(zip(shapes, seeds, infos)):
+        assert info.status == s7.OK
+        assert info.rel_res_true <= 1e-6
+        err = float(torch.linalg.vector_norm(xs[k] - xstars[k]) / torch.linalg.vector_norm(xstars[k]))
+        assert err <= 1e-5
+    for k in (0, 17, 63):
+        p, A, b = problem(shapes[k], seed=seeds[k])
+        ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+        assert rel_err(host(xs[k]), ref.x) <= 1e-5
