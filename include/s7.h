@@ -206,15 +206,42 @@ typedef struct {
     int32_t prec;         /* s7_prec */
 } s7_request;
 
-/* Creates a queue over the caller's device arena (256-byte aligned). */
+/* Bytes at the head of a queue arena that hold the engine tables. */
+size_t s7_queue_table_bytes(void);
+
+/*
+ * Creates a queue over the caller's device arena (256-byte aligned), on the
+ * current device.  The arena stays owned by the caller and must outlive the
+ * queue.  Its head (s7_queue_table_bytes) holds the engine tables for up to
+ * 1024 resident requests; the rest holds the admitted requests' workspaces (s7_workspace_bytes of
+ * their dims and precision).  opt->graph_iters sets the epoch: the most
+ * iterations a resident request runs between two admission points (0 = 16).
+ * One serving thread and one non-blocking stream belong to the queue.
+ * S7_EINVAL for a bad argument or an arena too small for the tables.
+ */
 int s7_queue_create(s7_queue **q, void *arena, size_t arena_bytes, const s7_options *opt);
-/* Copies the descriptor and returns a ticket.  S7_ENOMEM if it can never fit. */
+/*
+ * Copies the descriptor and returns a ticket.  The request's arrays must be
+ * ready on the device (work that writes them has completed) and stay valid
+ * until its result is collected.  Requests are admitted in submission order.
+ * S7_ENOMEM if its workspace exceeds the arena (it could never be admitted);
+ * S7_EINVAL for a bad argument; after a device error, that error.
+ */
 int s7_queue_submit(s7_queue *q, const s7_request *req, uint64_t *ticket);
-/* Non-blocking.  S7_EAGAIN while running; else the request's status, with *info filled. */
+/*
+ * Non-blocking.  S7_EAGAIN while the request is queued or running; else the
+ * request's s7_status, *info filled (t_ms: submit to completion, t_wait_ms:
+ * submit to admission), and the ticket released: a second collection of the
+ * same ticket returns S7_ENOTFOUND.
+ */
 int s7_queue_poll(s7_queue *q, uint64_t ticket, s7_info *info);
-/* Blocks until the request is done. */
+/* Blocks until the request is done, then collects it as s7_queue_poll does. */
 int s7_queue_wait(s7_queue *q, uint64_t ticket, s7_info *info);
-/* Finishes the outstanding work, then releases the queue. */
+/*
+ * Runs every submitted request to completion, stops the serving thread and
+ * releases the queue (uncollected results are dropped).  Returns S7_OK, or
+ * the device error that stopped the queue.  No other call on q may overlap it.
+ */
 int s7_queue_destroy(s7_queue *q);
 
 /*

@@ -24,7 +24,7 @@ PREC_NAMES = {"fp32": FP32, "bf16_ir": BF16_IR, "fp16_ir": FP16_IR}
 __all__ = [
     "Dims", "Options", "Info", "Request", "lib", "default_options", "last_error", "version",
     "stencil_apply", "workspace_bytes", "bicgstab_solve", "batched_workspace_bytes",
-    "bicgstab_solve_batched", "queue_create", "queue_submit", "queue_poll", "queue_wait",
+    "bicgstab_solve_batched", "queue_table_bytes", "queue_create", "queue_submit", "queue_poll", "queue_wait",
     "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
@@ -83,6 +83,7 @@ EXPORTS = {
                                             C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32,
                                             _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info),
                                             _vp]),
+    "s7_queue_table_bytes": (C.c_size_t, []),
     "s7_queue_create": (C.c_int, [C.POINTER(_vp), _vp, C.c_size_t, C.POINTER(Options)]),
     "s7_queue_submit": (C.c_int, [_vp, C.POINTER(Request), C.POINTER(C.c_uint64)]),
     "s7_queue_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(Info)]),
@@ -217,6 +218,10 @@ def bicgstab_solve_batched(dims_list, coefs, bs, xs, rtols, max_iters, prec=FP32
                                          C.byref(opt) if opt else None, infos, _stream(stream))
     _check(rc)
     return rc, list(infos)
+
+
+def queue_table_bytes() -> int:
+    return int(lib().s7_queue_table_bytes())
 
 
 def queue_create(arena, arena_bytes: int | None = None, opt: Options | None = None) -> int:

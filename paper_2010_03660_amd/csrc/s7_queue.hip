@@ -1,10 +1,304 @@
-// Request queue (placeholder until the serving core lands).
+// Request queue with continuous batching: the serving form.  The paper points
+// to real-time and in-the-loop simulation (section VIII-A), where solves arrive
+// continuously.
+//
+// * The caller hands over a device arena, which is the HBM budget.  Its head
+//   holds the batch engine's tables; the rest is carved first-fit, on the host,
+//   into the workspaces of admitted requests.
+// * submit() copies the request descriptor into a FIFO and returns a ticket.
+//   A request whose workspace could never fit in the arena is refused with
+//   S7_ENOMEM.
+// * One serving thread admits requests from the FIFO head while their
+//   workspace fits, then advances every resident request by one engine step:
+//   a persistent launch of at most `epoch_iters` iterations each, plus the
+//   refinement and epilogue work in between.  Requests that arrive during a
+//   step join at the next one, while the others keep their Krylov state on
+//   the device.  A finished request frees its slice for the next admission.
+// * poll() never blocks; wait() blocks until the request is done.  A finished
+//   request's result is handed out once, then its ticket is released.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "s7_host.hpp"
 
-extern "C" {
-int s7_queue_create(s7_queue**, void*, size_t, const s7_options*) { return S7_EINVAL; }
-int s7_queue_submit(s7_queue*, const s7_request*, uint64_t*) { return S7_EINVAL; }
-int s7_queue_poll(s7_queue*, uint64_t, s7_info*) { return S7_EINVAL; }
-int s7_queue_wait(s7_queue*, uint64_t, s7_info*) { return S7_EINVAL; }
-int s7_queue_destroy(s7_queue*) { return S7_EINVAL; }
+using namespace s7;
+
+namespace {
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
 }
+
+// First-fit allocator of 256-byte aligned ranges inside [0, size).
+class Arena {
+  public:
+    explicit Arena(size_t size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
+struct Req {
+    uint64_t ticket;
+    EngineJob job;
+    size_t off = 0, bytes = 0;
+    double t_submit = 0, t_admit = 0;
+    bool done = false;
+};
+
+}  // namespace
+
+struct s7_queue {
+    char* arena;
+    size_t arena_bytes;
+    size_t table_bytes;
+    int device;
+    s7_options opt;
+    int epoch_iters;
+    int capacity;
+    Arena heap;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<BatchEngine> engine;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req*> pending;
+    std::map<uint64_t, std::unique_ptr<Req>> reqs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int error = S7_OK;
+    std::string error_msg;
+    std::thread worker;
+
+    s7_queue(char* a, size_t ab, size_t tb, int dev, const s7_options& o, int cap)
+        : arena(a), arena_bytes(ab), table_bytes(tb), device(dev), opt(o), capacity(cap),
+          heap(ab - tb) {
+        epoch_iters = o.graph_iters > 0 ? o.graph_iters : 16;
+    }
+
+    void run() {
+        (void)hipSetDevice(device);
+        std::vector<Req*> resident;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stop || !pending.empty() || !resident.empty(); });
+                if (stop && pending.empty() && resident.empty()) return;
+                // admit from the head of the FIFO while the workspace fits
+                while (!pending.empty() && (int)resident.size() < capacity) {
+                    Req* r = pending.front();
+                    size_t off;
+                    if (!heap.alloc(r->bytes, &off)) break;
+                    pending.pop_front();
+                    r->off = off;
+                    r->job.ws = arena + table_bytes + off;
+                    r->t_admit = now_ms();
+                    resident.push_back(r);
+                    engine->add(&r->job);
+                }
+            }
+            int rc = resident.empty() ? S7_OK : engine->step(epoch_iters);
+            std::lock_guard<std::mutex> lk(mu);
+            if (rc != S7_OK) {
+                error = rc;
+                error_msg = s7_last_error();
+                for (Req* r : resident) {
+                    r->job.info.status = rc;
+                    r->done = true;
+                }
+                for (Req* r : pending) {
+                    r->job.info.status = rc;
+                    r->done = true;
+                }
+                pending.clear();
+                resident.clear();
+                cv_done.notify_all();
+                stop = true;
+                return;
+            }
+            std::vector<Req*> keep;
+            bool any = false;
+            for (Req* r : resident) {
+                if (r->job.finished) {
+                    r->job.info.t_wait_ms = r->t_admit - r->t_submit;
+                    r->done = true;
+                    heap.release(r->off, r->bytes);
+                    any = true;
+                } else {
+                    keep.push_back(r);
+                }
+            }
+            resident.swap(keep);
+            if (any) cv_done.notify_all();
+        }
+    }
+};
+
+namespace {
+constexpr int kQueueCapacity = 1024;  // resident requests at most
+}
+
+extern "C" {
+
+size_t s7_queue_table_bytes(void) { return align256(engine_table_bytes(kQueueCapacity)); }
+
+int s7_queue_create(s7_queue** q, void* arena, size_t arena_bytes, const s7_options* opt) {
+    clear_error();
+    if (!q || !arena || ((uintptr_t)arena & 255u) != 0) {
+        set_error("s7_queue_create: invalid argument");
+        return S7_EINVAL;
+    }
+    s7_options o;
+    options_or_default(opt, o);
+    const int cap = kQueueCapacity;
+    const size_t tb = s7_queue_table_bytes();
+    if (arena_bytes <= tb + 256) {
+        set_error("s7_queue_create: arena smaller than the engine tables (%zu bytes)", tb);
+        return S7_EINVAL;
+    }
+    int dev = 0;
+    S7_HIP(hipGetDevice(&dev));
+    s7_queue* Q = new (std::nothrow) s7_queue((char*)arena, arena_bytes, tb, dev, o, cap);
+    if (!Q) return S7_EINVAL;
+    hipError_t e = hipStreamCreateWithFlags(&Q->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete Q;
+        set_error("s7_queue_create: %s", hipGetErrorString(e));
+        return S7_EHIP;
+    }
+    Q->engine.reset(new BatchEngine((char*)arena, cap, o, Q->stream));
+    Q->worker = std::thread([Q] { Q->run(); });
+    *q = Q;
+    return S7_OK;
+}
+
+int s7_queue_submit(s7_queue* q, const s7_request* req, uint64_t* ticket) {
+    clear_error();
+    if (!q || !req || !ticket || !dims_ok(req->d) || !req->b || !req->x || !(req->rtol > 0.0) ||
+        req->max_iter < 0 || req->prec < S7_FP32 || req->prec > S7_FP16_IR) {
+        set_error("s7_queue_submit: invalid argument");
+        return S7_EINVAL;
+    }
+    for (int a = 0; a < 7; ++a)
+        if (!req->coef[a]) {
+            set_error("s7_queue_submit: invalid argument");
+            return S7_EINVAL;
+        }
+    const size_t bytes = make_layout(req->d, req->prec, q->opt).bytes;
+    if (align256(bytes) > q->arena_bytes - q->table_bytes) {
+        set_error("s7_queue_submit: request needs %zu bytes, the arena has %zu", bytes,
+                  q->arena_bytes - q->table_bytes);
+        return S7_ENOMEM;
+    }
+    std::unique_ptr<Req> r(new Req());
+    EngineJob& j = r->job;
+    std::memset(&j, 0, sizeof(j));
+    j.d = req->d;
+    for (int a = 0; a < 7; ++a) j.coef[a] = req->coef[a];
+    j.b = req->b;
+    j.x = req->x;
+    j.rtol = req->rtol;
+    j.max_iter = req->max_iter;
+    j.prec = req->prec;
+    j.ws_bytes = bytes;
+    r->bytes = bytes;
+    r->t_submit = now_ms();
+    j.t_start_ms = r->t_submit;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        if (q->stop) {
+            set_error("s7_queue_submit: queue stopped (%s)", q->error_msg.c_str());
+            return q->error ? q->error : S7_EINVAL;
+        }
+        r->ticket = q->next_ticket++;
+        *ticket = r->ticket;
+        q->pending.push_back(r.get());
+        q->reqs[r->ticket] = std::move(r);
+    }
+    q->cv_work.notify_one();
+    return S7_OK;
+}
+
+int s7_queue_poll(s7_queue* q, uint64_t ticket, s7_info* info) {
+    clear_error();
+    if (!q) return S7_EINVAL;
+    std::lock_guard<std::mutex> lk(q->mu);
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return S7_ENOTFOUND;
+    if (!it->second->done) return S7_EAGAIN;
+    if (info) *info = it->second->job.info;
+    const int st = it->second->job.info.status;
+    q->reqs.erase(it);
+    return st;
+}
+
+int s7_queue_wait(s7_queue* q, uint64_t ticket, s7_info* info) {
+    clear_error();
+    if (!q) return S7_EINVAL;
+    std::unique_lock<std::mutex> lk(q->mu);
+    auto it = q->reqs.find(ticket);
+    if (it == q->reqs.end()) return S7_ENOTFOUND;
+    Req* r = it->second.get();
+    q->cv_done.wait(lk, [&] { return r->done; });
+    if (info) *info = r->job.info;
+    const int st = r->job.info.status;
+    q->reqs.erase(ticket);
+    return st;
+}
+
+int s7_queue_destroy(s7_queue* q) {
+    clear_error();
+    if (!q) return S7_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        q->stop = true;
+    }
+    q->cv_work.notify_all();
+    if (q->worker.joinable()) q->worker.join();
+    const int err = q->error;
+    if (q->stream) (void)hipStreamDestroy(q->stream);
+    delete q;
+    return err == S7_OK ? S7_OK : err;
+}
+
+}  // extern "C"

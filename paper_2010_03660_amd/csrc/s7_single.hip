@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <list>
+#include <memory>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -362,9 +363,19 @@ __global__ __launch_bounds__(kThreads) void k_gen_coef(Coef7 out, double* xstar,
 // ============================================================== graph cache
 namespace {
 
+// An instantiated graph.  Holders keep it alive: a graph evicted from the
+// cache while another thread still launches it is destroyed with its last user.
+struct GraphExec {
+    hipGraphExec_t exec = nullptr;
+    ~GraphExec() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+using GraphRef = std::shared_ptr<GraphExec>;
+
 struct GraphEntry {
     std::vector<uintptr_t> key;
-    hipGraphExec_t exec;
+    GraphRef g;
 };
 
 std::mutex g_graph_mu;
@@ -386,14 +397,19 @@ int capture_stream(hipStream_t* out) {
 
 }  // namespace
 
-// Returns a cached executable graph for `key`, capturing `body` on first use.
+// Returns a cached executable graph for `key` on the current device,
+// capturing `body` on first use.  The caller keeps *out until its launches
+// have completed.
 template <class F>
-int cached_graph(const std::vector<uintptr_t>& key, F body, hipGraphExec_t* out) {
+int cached_graph(std::vector<uintptr_t> key, F body, GraphRef* out) {
+    int dev = 0;
+    S7_HIP(hipGetDevice(&dev));
+    key.push_back((uintptr_t)dev);
     std::lock_guard<std::mutex> lk(g_graph_mu);
     for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it) {
         if (it->key == key) {
             g_graphs.splice(g_graphs.begin(), g_graphs, it);
-            *out = g_graphs.front().exec;
+            *out = g_graphs.front().g;
             return S7_OK;
         }
     }
@@ -416,12 +432,11 @@ int cached_graph(const std::vector<uintptr_t>& key, F body, hipGraphExec_t* out)
         set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
         return S7_EHIP;
     }
-    if (g_graphs.size() >= kMaxGraphs) {
-        (void)hipGraphExecDestroy(g_graphs.back().exec);
-        g_graphs.pop_back();
-    }
-    g_graphs.push_front(GraphEntry{key, exec});
-    *out = exec;
+    GraphRef ref = std::make_shared<GraphExec>();
+    ref->exec = exec;
+    if (g_graphs.size() >= kMaxGraphs) g_graphs.pop_back();
+    g_graphs.push_front(GraphEntry{key, ref});
+    *out = ref;
     return S7_OK;
 }
 
@@ -518,14 +533,14 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
                                       (uintptr_t)S.unit, (uintptr_t)S.st, (uintptr_t)S.red.part,
                                       (uintptr_t)S.r, (uintptr_t)S.c[1], (uintptr_t)S.d,
                                       (uintptr_t)S.stream_blocks};
-        hipGraphExec_t g;
+        GraphRef g;
         rc = cached_graph(key, [&](hipStream_t cs) {
             for (int j = 0; j < K; ++j)
                 for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, cs);
         }, &g);
         if (rc) return rc;
         for (long long l = 0; l < max_launches; ++l) {
-            S7_HIP(hipGraphLaunch(g, stream));
+            S7_HIP(hipGraphLaunch(g->exec, stream));
             rc = read_state(S.st, host, stream);
             if (rc) return rc;
             if (host->done) break;
@@ -909,17 +924,13 @@ int BatchEngine::step(int epoch_iters) {
         int grid = (int)(total_chunks < 1024 ? total_chunks : 1024);
         if (grid < 1) grid = 1;
         const long long spin_limit = 5000000;
-        std::vector<uintptr_t> key = {0x53u, (uintptr_t)tables_, (uintptr_t)nsys, (uintptr_t)epoch_iters,
-                                      (uintptr_t)grid, (uintptr_t)chunk};
-        hipGraphExec_t g;
-        rc = cached_graph(key, [&](hipStream_t cs) {
-            hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
-                               nsys, epoch_iters);
-            hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
-                               chunk, spin_limit);
-        }, &g);
-        if (rc) return rc;
-        S7_HIP(hipGraphLaunch(g, st_));
+        // Two launches: the resident set changes from step to step, so a
+        // captured graph would rarely be replayed.
+        hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, st_, (const BSys*)dsys, glob, nsys,
+                           epoch_iters);
+        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, st_, (const BSys*)dsys, glob, nsys,
+                           chunk, spin_limit);
+        S7_CHECK_LAUNCH();
         BGlobal hg;
         S7_HIP(hipMemcpyAsync(&hg, glob, sizeof(hg), hipMemcpyDeviceToHost, st_));
         S7_HIP(hipStreamSynchronize(st_));

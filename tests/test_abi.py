@@ -80,3 +80,23 @@ def test_host_side_argument_checks():
     # u aliasing v
     rc = lib.s7_stencil_apply(B.Dims(8, 8, 8), coef, 4096, 4096, 0)
     assert rc == B.EINVAL
+
+
+def test_queue_host_side_checks():
+    """Queue calls that fail validation return before touching the GPU."""
+    from paper_2010_03660_amd import binding as B
+    lib = B.lib()
+    tb = lib.s7_queue_table_bytes()
+    assert tb > 0 and tb % 256 == 0
+    q = C.c_void_p()
+    assert lib.s7_queue_create(C.byref(q), 0, 1 << 30, None) == B.EINVAL        # no arena
+    assert lib.s7_queue_create(C.byref(q), 4096 + 8, 1 << 30, None) == B.EINVAL  # misaligned
+    assert lib.s7_queue_create(C.byref(q), 4096, tb, None) == B.EINVAL          # tables only
+    assert "arena" in B.last_error()
+    assert lib.s7_queue_create(None, 4096, 1 << 30, None) == B.EINVAL
+    t = C.c_uint64()
+    req = B.Request(B.Dims(8, 8, 8), (C.c_void_p * 7)(*([256] * 7)), 512, 768, 1e-6, 10, 0)
+    assert lib.s7_queue_submit(None, C.byref(req), C.byref(t)) == B.EINVAL
+    assert lib.s7_queue_poll(None, 1, None) == B.EINVAL
+    assert lib.s7_queue_wait(None, 1, None) == B.EINVAL
+    assert lib.s7_queue_destroy(None) == B.EINVAL
