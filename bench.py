@@ -6,9 +6,11 @@ before the timed region starts.  The timed region is one call of the solver with
 fixed iteration count.  That call includes its prologue and epilogue: coefficient
 scaling, r0 = b - A x0, x update and the FP64 true residual.
 
-Printed: one JSON line with the metric, roofline of the dominant kernel (P1), the
+Printed: one JSON line with the metric, the roofline of the dominant kernel, the
 mixed BF16+refinement form, accuracy of converged runs against the manufactured
-solution, and the FP64 CPU oracle timed on a bounded slab of the same workload.
+solution, the batched form (64 uneven systems), the served form (a Poisson request
+stream through the queue against a serial loop of single solves, p50/p99 latency),
+and the FP64 CPU oracle timed on a bounded slab of the same workload.
 """
 from __future__ import annotations
 
@@ -74,6 +76,189 @@ def cpu_baseline(nx: int, ny: int, nz_full: int, slab: int, iters: int):
             "sample": f"{iters} iterations on a {nx}x{ny}x{slab} slab of the same recipe "
                       f"({t:.1f} s), scaled by cell count to {nx}x{ny}x{nz_full}"}
 
+def batched_leg(s7, torch, dev):
+    """64 systems of uneven size (each side uniform over {24,...,128}), seeds 1000+s,
+    tolerance 1e-7: one call of the batched solver against a loop of single solves."""
+    import synth
+    shapes, seeds = synth.batch_shapes(64, seed=0)
+    coefs, bs, xs, xst = [], [], [], []
+    for d, sd in zip(shapes, seeds):
+        n = d[0] * d[1] * d[2]
+        c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(7)]
+        xx = torch.empty(n, dtype=torch.float64, device=dev)
+        bb = torch.empty(n, dtype=torch.float64, device=dev)
+        s7.generate_problem(d, sd, 0, c, xx, bb)
+        coefs.append(c), bs.append(bb), xst.append(xx)
+        xs.append(torch.zeros(n, dtype=torch.float64, device=dev))
+    cells = [d[0] * d[1] * d[2] for d in shapes]
+    ws = torch.empty(s7.batched_workspace_bytes(shapes), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def batched():
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, infos = s7.bicgstab_solve_batched(shapes, coefs, bs, xs, [1e-7] * 64, [2000] * 64, ws=ws)
+        torch.cuda.synchronize()
+        return rc, infos, time.perf_counter() - t0
+
+    batched()  # warm-up (captures the launch graph)
+    rc, infos, dt = batched()
+    iters = [i.iters for i in infos]
+    err = max(float(torch.linalg.vector_norm(x - xx) / torch.linalg.vector_norm(xx))
+              for x, xx in zip(xs, xst))
+    cell_iters = sum(c * k for c, k in zip(cells, iters))
+    # the same systems, one single-system solve after another
+    sws = torch.empty(max(s7.workspace_bytes(d) for d in shapes), dtype=torch.uint8, device=dev)
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d, c, bb, x in zip(shapes, coefs, bs, xs):
+        s7.bicgstab_solve(d, c, bb, x, 1e-7, 2000, ws=sws)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t0
+    return {
+        "workload": "64 systems, sides uniform over {24,32,48,64,96,128}, FP32, rtol 1e-7",
+        "cells": sum(cells), "status": rc, "iters_min_max": [min(iters), max(iters)],
+        "systems_per_s": round(64 / dt, 2), "seconds": round(dt, 4),
+        "cell_iters_per_s": round(cell_iters / dt, 1),
+        "alg_GB/s": round(cell_iters * sum(BYTES_FP32.values()) / dt / 1e9, 1),
+        "max_rel_err_vs_xstar": err,
+        "serial_single_solves_s": round(dts, 4), "speedup_vs_serial": round(dts / dt, 2),
+    }
+
+
+def served_leg(s7, torch, dev, nreq: int, rate: float, burst: int, arena_gb: float, sample: int):
+    """The request stream: Poisson arrivals at `rate` per second, sides log-uniform in
+    [16,256] per axis, half FP32 at rtol 1e-6 and half BF16 + FP64 refinement at 1e-10.
+    The queue (continuous batching) and a serial loop of single-system solves serve the
+    same stream.  Latency runs from the scheduled arrival to the result; it includes the
+    client's generation of the request's inputs on the device."""
+    import queue as pyqueue
+    import threading
+
+    import numpy as np
+
+    import synth
+    prec_of = {"fp32": s7.FP32, "bf16_ir": s7.BF16_IR}
+    gen_stream = torch.cuda.Stream(device=dev)
+
+    def make(r):
+        n = r.dims[0] * r.dims[1] * r.dims[2]
+        with torch.cuda.stream(gen_stream):
+            c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(7)]
+            xx = torch.empty(n, dtype=torch.float64, device=dev)
+            bb = torch.empty(n, dtype=torch.float64, device=dev)
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+        s7.generate_problem(r.dims, r.seed, 0, c, xx, bb, stream=gen_stream)
+        gen_stream.synchronize()
+        return c, bb, x, xx
+
+    def err_of(x, xx):
+        return float(torch.linalg.vector_norm(x - xx) / torch.linalg.vector_norm(xx))
+
+    def summarize(rs, lat, t_first, t_last, errs, status):
+        lat = np.array(lat) * 1e3
+        out = {"solves_per_s": round(len(lat) / (t_last - t_first), 2),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "mean_ms": round(float(lat.mean()), 3), "max_ms": round(float(lat.max()), 3),
+               "not_ok": int(sum(1 for st in status if st != s7.OK))}
+        for m in ("fp32", "bf16_ir"):
+            e = [v for r, v in zip(rs, errs) if r.mode == m]
+            if e:
+                out[f"max_rel_err_vs_xstar_{m}"] = float(f"{max(e):.3e}")
+        return out
+
+    def run_queue(rs, arena, keep=()):
+        q = s7.queue_create(arena)
+        handoff = pyqueue.Queue()
+        t0 = time.perf_counter()
+
+        def producer():
+            try:
+                for r in rs:
+                    wait = t0 + r.arrival_s - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    c, bb, x, xx = make(r)
+                    t_sub = time.perf_counter()
+                    tk = s7.queue_submit(q, r.dims, c, bb, x, r.rtol, 4000, prec_of[r.mode])
+                    handoff.put((r, tk, t_sub, c, bb, x, xx))
+            finally:
+                handoff.put(None)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        lat, errs, status, kept, done = [], [], [], {}, []
+        while True:
+            item = handoff.get()
+            if item is None:
+                break
+            r, tk, t_sub, c, bb, x, xx = item
+            rc, info = s7.queue_wait(q, tk)
+            t_done = t_sub + info.t_ms * 1e-3
+            done.append(t_done)
+            lat.append(t_done - (t0 + r.arrival_s))
+            status.append(rc)
+            errs.append(err_of(x, xx))
+            if r.rid in keep:
+                kept[r.rid] = x.clone()
+        th.join()
+        s7.queue_destroy(q)
+        if len(status) != len(rs):
+            raise RuntimeError("the request producer stopped early")
+        return summarize(rs, lat, t0 + rs[0].arrival_s, max(done), errs, status), kept
+
+    def run_serial(rs):
+        ws = torch.empty(max(s7.workspace_bytes(r.dims, prec_of[r.mode]) for r in rs),
+                         dtype=torch.uint8, device=dev)
+        t0 = time.perf_counter()
+        lat, errs, status = [], [], []
+        for r in rs:
+            wait = t0 + r.arrival_s - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            c, bb, x, xx = make(r)
+            info = s7.bicgstab_solve(r.dims, c, bb, x, r.rtol, 4000, prec=prec_of[r.mode], ws=ws)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - (t0 + r.arrival_s))
+            status.append(info.status)
+            errs.append(err_of(x, xx))
+        return summarize(rs, lat, t0 + rs[0].arrival_s, time.perf_counter(), errs, status)
+
+    arena = torch.empty(int(arena_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    res = {"workload": f"{nreq} requests, Poisson arrivals at {rate:g}/s, sides log-uniform in "
+                       f"[16,256] per axis, 50/50 FP32 rtol 1e-6 / BF16+FP64 IR rtol 1e-10",
+           "arena_GiB": arena_gb, "latency": "scheduled arrival to result"}
+    warm = synth.serve_stream(8, rate=1e9, seed=1)
+    run_queue(warm, arena)
+    run_serial(warm)
+
+    reqs = synth.serve_stream(nreq, rate=rate, seed=0)
+    print(f"[bench] served stream: {nreq} requests at {rate:g}/s through the queue",
+          file=sys.stderr, flush=True)
+    keep = set(r.rid for r in reqs[:: max(1, nreq // sample)]) if sample else set()
+    res["queue"], kept = run_queue(reqs, arena, keep)
+    print("[bench] served stream: serial single-system loop", file=sys.stderr, flush=True)
+    res["serial"] = run_serial(reqs)
+    if burst:
+        # capacity: the first `burst` requests all arrive at once
+        br = [synth.Request(r.rid, 0.0, r.dims, r.mode, r.rtol, r.seed) for r in reqs[:burst]]
+        print(f"[bench] burst of {burst} requests", file=sys.stderr, flush=True)
+        res["burst"] = {"requests": burst, "queue": run_queue(br, arena)[0], "serial": run_serial(br)}
+    # each sampled request solved alone through the batched path must match its served result
+    same = 0
+    for rid in sorted(kept):
+        r = reqs[rid]
+        c, bb, x, xx = make(r)
+        s7.bicgstab_solve_batched([r.dims], [c], [bb], [x], [r.rtol], [4000], prec=prec_of[r.mode])
+        torch.cuda.synchronize()
+        same += bool(torch.equal(x, kept[rid]))
+    res["alone_vs_mix_identical"] = f"{same}/{len(kept)}"
+    return res
 
 def main():
     ap = argparse.ArgumentParser()
@@ -86,6 +271,16 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-slab", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served stream (the full workload is 10000)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-burst", type=int, default=400,
+                    help="requests of the all-at-once capacity run (0: skip)")
+    ap.add_argument("--serve-sample", type=int, default=100,
+                    help="served requests re-solved alone for the identity check")
+    ap.add_argument("--arena-gb", type=float, default=64.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 2 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -205,6 +400,14 @@ def main():
 
     del ws, coef, xs, b, x
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("[bench] batched: 64 uneven systems", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(s7, torch, dev)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["served"] = served_leg(s7, torch, dev, args.serve_requests, args.serve_rate,
+                                   args.serve_burst, args.arena_gb, args.serve_sample)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nx, ny, nz, min(args.cpu_slab, nz), args.cpu_iters)

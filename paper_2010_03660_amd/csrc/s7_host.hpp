@@ -96,7 +96,10 @@ size_t engine_table_bytes(int capacity);
 
 class BatchEngine {
   public:
-    BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream);
+    // use_graph: replay the persistent launch from a captured hipGraph, for
+    // callers whose resident set repeats (the batched entry point).
+    BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
+                bool use_graph = false);
     // Takes part from the next step on; the job's arrays must stay valid until finished.
     int add(EngineJob* job);
     // Advances every resident job: starts new ones, runs one persistent launch of at
@@ -110,6 +113,7 @@ class BatchEngine {
     int cap_;
     s7_options o_;
     hipStream_t st_;
+    bool graph_;
     std::vector<EngineJob*> jobs_;
 };
 

@@ -699,8 +699,9 @@ size_t engine_table_bytes(int capacity) {
     return align256(sizeof(BGlobal)) + align256((size_t)capacity * sizeof(BSys));
 }
 
-BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream)
-    : tables_(tables), cap_(capacity), o_(o), st_(stream) {}
+BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
+                         bool use_graph)
+    : tables_(tables), cap_(capacity), o_(o), st_(stream), graph_(use_graph) {}
 
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
@@ -924,13 +925,25 @@ int BatchEngine::step(int epoch_iters) {
         int grid = (int)(total_chunks < 1024 ? total_chunks : 1024);
         if (grid < 1) grid = 1;
         const long long spin_limit = 5000000;
-        // Two launches: the resident set changes from step to step, so a
-        // captured graph would rarely be replayed.
-        hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, st_, (const BSys*)dsys, glob, nsys,
-                           epoch_iters);
-        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, st_, (const BSys*)dsys, glob, nsys,
-                           chunk, spin_limit);
-        S7_CHECK_LAUNCH();
+        auto body = [&](hipStream_t cs) {
+            hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
+                               nsys, epoch_iters);
+            hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
+                               chunk, spin_limit);
+        };
+        GraphRef g;  // held until the launch has completed
+        if (graph_) {
+            // the table is re-uploaded before every replay, so the key needs only its shape
+            std::vector<uintptr_t> key = {0x53u, (uintptr_t)tables_, (uintptr_t)nsys,
+                                          (uintptr_t)epoch_iters, (uintptr_t)grid, (uintptr_t)chunk};
+            rc = cached_graph(key, body, &g);
+            if (rc) return rc;
+            S7_HIP(hipGraphLaunch(g->exec, st_));
+        } else {
+            // the serving loop: the resident set changes from step to step
+            body(st_);
+            S7_CHECK_LAUNCH();
+        }
         BGlobal hg;
         S7_HIP(hipMemcpyAsync(&hg, glob, sizeof(hg), hipMemcpyDeviceToHost, st_));
         S7_HIP(hipStreamSynchronize(st_));
@@ -1105,7 +1118,7 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
     }
     char* w = (char*)ws;
     hipStream_t s = (hipStream_t)stream;
-    BatchEngine eng(w, nsys, o, s);
+    BatchEngine eng(w, nsys, o, s, /*use_graph=*/true);
     std::vector<EngineJob> jobs((size_t)nsys);
     size_t off = align256(engine_table_bytes(nsys));
     const double t0 = now_ms();
