@@ -25,13 +25,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-# Algorithmic bytes per cell of each pass (FP32 storage, Jacobi-scaled: 6 coefficient arrays).
-# P1 reads p, r0 and 6 coefficients and writes s.
-# P2a reads r, s and writes q.
-# P2b reads q, r0 and 6 coefficients and writes y.
-# P3 reads d, p, q, s, y, r0 and writes d, r, p.
-BYTES_FP32 = {"p1": 36, "p2a": 12, "p2b": 36, "p3": 36}
-BYTES_16 = {"p1": 18, "p2a": 6, "p2b": 18, "p3": 22}  # BF16/FP16 vectors and coefficients, FP32 d
+# Algorithmic bytes per cell of each pass (Jacobi-scaled: 6 coefficient arrays), by
+# schedule.  Three passes (the solver's default):
+#   P1 reads p, r0 and 6 coefficients and writes s;
+#   P2 reads r, s, r0 and 6 coefficients (q = r - alpha s formed on the fly) and writes y;
+#   P3 reads d, p, r, s, y, r0 and writes d, r, p.
+# Four passes (q stored): P2a reads r, s and writes q; P2b reads q, r0 and the
+# coefficients and writes y; P3 reads q instead of r.
+# Slots of s7_info.pass_ms: 0 P1, 1 P2a, 2 P2 or P2b, 3 P3.
+BYTES = {
+    ("f32", 3): {"p1": 36, "p2": 40, "p3": 36},
+    ("f32", 4): {"p1": 36, "p2a": 12, "p2b": 36, "p3": 36},
+    ("16", 3): {"p1": 18, "p2": 20, "p3": 22},  # BF16/FP16 vectors and coefficients, FP32 d
+    ("16", 4): {"p1": 18, "p2a": 6, "p2b": 18, "p3": 22},
+}
+SLOT = {"p1": 0, "p2a": 1, "p2": 2, "p2b": 2, "p3": 3}
+KERNEL = {"p1": "k_p1 (P1: s = A p, (r0,s))",
+          "p2": "k_p2f (P2: y = A q with q = r - alpha s formed on the fly, five dot products)",
+          "p2a": "k_p2a (P2a: q = r - alpha s, (q,q))",
+          "p2b": "k_p2 (P2b: y = A q, four dot products)",
+          "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"}
+BATCH_BYTES = sum(BYTES[("f32", 4)].values())  # the batched engine runs the four-pass schedule
 SRC_FILES = ["paper_2010_03660_amd/csrc/s7_device.hpp", "paper_2010_03660_amd/csrc/s7_single.hip"]
 
 
@@ -124,7 +138,7 @@ def batched_leg(s7, torch, dev):
         "cells": sum(cells), "status": rc, "iters_min_max": [min(iters), max(iters)],
         "systems_per_s": round(64 / dt, 2), "seconds": round(dt, 4),
         "cell_iters_per_s": round(cell_iters / dt, 1),
-        "alg_GB/s": round(cell_iters * sum(BYTES_FP32.values()) / dt / 1e9, 1),
+        "alg_GB/s": round(cell_iters * BATCH_BYTES / dt / 1e9, 1),
         "max_rel_err_vs_xstar": err,
         "serial_single_solves_s": round(dts, 4), "speedup_vs_serial": round(dts / dt, 2),
     }
@@ -271,6 +285,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-slab", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--schedule", type=int, default=3, choices=(3, 4),
+                    help="passes per iteration of the single-system solver")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -321,7 +337,7 @@ def main():
 
     def run(prec, iters, rtol=1e-300, profile=0):
         x.zero_()
-        o = s7.default_options(profile=profile)
+        o = s7.default_options(profile=profile, schedule={3: 1, 4: 2}[args.schedule])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = s7.bicgstab_solve(dims, coef, b, x, rtol, iters, prec=prec, ws=ws, opt=o)
@@ -335,23 +351,20 @@ def main():
     info, dt = run(s7.FP32, args.steps, profile=1)
     assert info.iters == args.steps, info.as_dict()
     ips = args.steps / dt
-    names = ("p1", "p2a", "p2b", "p3")
-    kname = {"p1": "k_p1 (P1: s = A p, (r0,s))",
-             "p2a": "k_p2a (P2a: q = r - alpha s)",
-             "p2b": "k_p2 (P2b: y = A q and five dot products)",
-             "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"}
-    pass_ms = {k: info.pass_ms[i] / max(info.pass_count[i], 1) for i, k in enumerate(names)}
-    dom = max(names, key=lambda k: pass_ms[k])  # the kernel with the largest share of an iteration
-    dom_gbs = BYTES_FP32[dom] * n / (pass_ms[dom] * 1e-3) / 1e9
-    iter_bytes = sum(BYTES_FP32.values()) * n
+    sched = args.schedule
+    bytes32 = BYTES[("f32", sched)]
+    pass_ms = {k: info.pass_ms[SLOT[k]] / max(info.pass_count[SLOT[k]], 1) for k in bytes32}
+    dom = max(bytes32, key=lambda k: pass_ms[k])  # the kernel with the largest share of an iteration
+    dom_gbs = bytes32[dom] * n / (pass_ms[dom] * 1e-3) / 1e9
+    iter_bytes = sum(bytes32.values()) * n
     kernel_ms_iter = sum(pass_ms.values())
     traffic = traffic_from_profile(n, dom)
-    roofline = {"bound": "hbm", "kernel": kname[dom],
+    roofline = {"bound": "hbm", "kernel": KERNEL[dom],
                 "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": BYTES_FP32[dom] * n,
+                "algorithmic_bytes_per_launch": bytes32[dom] * n,
                 "avg_launch_ms": round(pass_ms[dom], 4)}
-    passes = {k: {"avg_ms": round(ms, 4), "GB/s": round(BYTES_FP32[k] * n / (ms * 1e-3) / 1e9, 1)}
+    passes = {k: {"avg_ms": round(ms, 4), "GB/s": round(bytes32[k] * n / (ms * 1e-3) / 1e9, 1)}
               for k, ms in pass_ms.items()}
     out = {
         "metric": "BiCGStab iter/s + %HBM peak at 600x595x1536; served solves/s, p99 latency",
@@ -360,7 +373,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded 7-point variable-coefficient recipe, b = A x*)",
         "config": {"workload": f"BiCGStab FP32, one system on the {nx}x{ny}x{nz} mesh",
-                   "cells": n, "jacobi": True, "timed": "one solve call of `steps` iterations"},
+                   "cells": n, "jacobi": True, "passes_per_iteration": sched,
+                   "bytes_per_cell_iteration": sum(bytes32.values()),
+                   "timed": "one solve call of `steps` iterations"},
         "gflops": round(44 * n * ips / 1e9, 1),
         "hbm_frac_per_iteration": round(iter_bytes * ips / 1e9 / HBM_PEAK_GBS, 4),
         "hbm_frac_kernels_only": round(iter_bytes / (kernel_ms_iter * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -374,13 +389,13 @@ def main():
         run(s7.BF16_IR, args.warmup)
         info16, dt16 = run(s7.BF16_IR, args.steps, profile=1)
         it16 = info16.iters
-        p16 = {k: info16.pass_ms[i] / max(info16.pass_count[i], 1)
-               for i, k in enumerate(("p1", "p2a", "p2b", "p3"))}
+        bytes16 = BYTES[("16", sched)]
+        p16 = {k: info16.pass_ms[SLOT[k]] / max(info16.pass_count[SLOT[k]], 1) for k in bytes16}
         out["mixed_bf16_ir"] = {
             "iter_per_s": round(it16 / dt16, 3), "inner_iters": it16,
             "outer_steps": info16.outer_iters,
-            "passes_GB/s": {k: round(BYTES_16[k] * n / (p16[k] * 1e-3) / 1e9, 1) for k in p16},
-            "kernel_bytes_per_iter": sum(BYTES_16.values()) * n,
+            "passes_GB/s": {k: round(bytes16[k] * n / (p16[k] * 1e-3) / 1e9, 1) for k in p16},
+            "kernel_bytes_per_iter": sum(bytes16.values()) * n,
         }
 
     # ---- accuracy: converged runs against the manufactured solution x*

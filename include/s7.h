@@ -97,7 +97,9 @@ typedef struct {
                                events into s7_info.pass_ms */
     int32_t inner_max_iter; /* IR: inner iteration cap per outer step; 0 = 100 */
     int32_t outer_max_iter; /* IR: outer step cap; 0 = 30 */
-    int32_t reserved0;
+    int32_t schedule;       /* single-system solve: 1 three passes per iteration (q = r - alpha s
+                               formed on the fly where it is used, never stored), 2 four
+                               passes (q stored by a streaming pass); 0 = 1 */
     double inner_rtol;      /* IR: inner relative tolerance; 0 = 1e-2 (BF16), 5e-3 (FP16) */
 } s7_options;
 
@@ -215,7 +217,9 @@ size_t s7_queue_table_bytes(void);
  * queue.  Its head (s7_queue_table_bytes) holds the engine tables for up to
  * 1024 resident requests; the rest holds the admitted requests' workspaces (s7_workspace_bytes of
  * their dims and precision).  opt->graph_iters sets the epoch: the most
- * iterations a resident request runs between two admission points (0 = 16).
+ * iterations a resident request runs between two admission points; 0 (the
+ * default) gives each request the iterations that fit a time slice of about
+ * 2 ms at its size.
  * One serving thread and one non-blocking stream belong to the queue.
  * S7_EINVAL for a bad argument or an arena too small for the tables.
  */

@@ -103,9 +103,11 @@ struct BCtl;
 
 struct BSys {
     SysView<float> S;
-    BCtl* ctl;  // the system's control words (in its own workspace slice)
+    BCtl* ctl;   // the system's control words (in its own workspace slice)
     int nchunk;
     int tag;
+    int budget;  // iterations this system may run in the launch
+    int pad;
 };
 
 template <class T>
@@ -184,10 +186,13 @@ __device__ void chunk_p1_b(const SysView<T>& S, int c0, int c1, double (&acc)[kM
 }
 
 template <class T>
-__device__ void chunk_p2a_b(const SysView<T>& S, int c0, int c1, float alpha) {
+__device__ void chunk_p2a_b(const SysView<T>& S, int c0, int c1, float alpha, double (&acc)[kMaxDots]) {
     for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads) {
         const float r = to_f32(cload(S.r + i)), s = to_f32(cload(S.s + i));
-        cstore(S.q + i, from_f32<T>(fmaT(-alpha, s, r)));
+        const T q = from_f32<T>(fmaT(-alpha, s, r));
+        cstore(S.q + i, q);
+        const double qd = (double)to_f32(q);
+        acc[0] = fma(qd, qd, acc[0]);
     }
 }
 
@@ -216,9 +221,8 @@ __device__ void chunk_p2b_b(const SysView<T>& S, int c0, int c1, double (&acc)[k
                 const double yd = (double)to_f32(yt), qd = (double)q.c, rd = (double)to_f32(rh[u]);
                 acc[0] = fma(qd, yd, acc[0]);
                 acc[1] = fma(yd, yd, acc[1]);
-                acc[2] = fma(qd, qd, acc[2]);
-                acc[3] = fma(rd, qd, acc[3]);
-                acc[4] = fma(rd, yd, acc[4]);
+                acc[2] = fma(rd, qd, acc[2]);
+                acc[3] = fma(rd, yd, acc[3]);
             }
         }
     }
@@ -241,7 +245,7 @@ __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, flo
     }
 }
 
-constexpr int kND[4] = {1, 0, 5, 2};  // dot products of P1, P2a, P2b, P3
+constexpr int kND[4] = {1, 1, 4, 2};  // dot products of P1, P2a, P2b, P3
 
 template <class T>
 __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, int c0, int c1,
@@ -252,7 +256,7 @@ __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, 
         if (S.unit) chunk_p1_b<T, true>(S, c0, c1, acc);
         else chunk_p1_b<T, false>(S, c0, c1, acc);
     } else if (phase == 1) {
-        chunk_p2a_b<T>(S, c0, c1, alpha);
+        chunk_p2a_b<T>(S, c0, c1, alpha, acc);
     } else if (phase == 2) {
         if (S.unit) chunk_p2b_b<T, true>(S, c0, c1, acc);
         else chunk_p2b_b<T, false>(S, c0, c1, acc);
@@ -335,7 +339,8 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
             State st;
             state_load(S.st, st);
             if (phase == 0) tail_p1(&st, reinterpret_cast<double(&)[1]>(tot));
-            if (phase == 2) tail_p2(&st, reinterpret_cast<double(&)[5]>(tot));
+            if (phase == 1) tail_p2a(&st, reinterpret_cast<double(&)[1]>(tot));
+            if (phase == 2) tail_p2(&st, reinterpret_cast<double(&)[4]>(tot));
             if (phase == 3) tail_p3(&st, reinterpret_cast<double(&)[2]>(tot));
             int32_t budget = cload_i(&sys[me].ctl->budget);
             bool stop = st.done != 0;
@@ -366,10 +371,9 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
     }
 }
 
-// Arms a launch: every system that is not done takes part with `budget`
-// iterations; the global count of active systems is set accordingly.
-__global__ __launch_bounds__(kThreads) void k_batched_arm(const BSys* sys, BGlobal* glob, int nsys,
-                                                          int budget) {
+// Arms a launch: every system that is not done takes part with its own
+// iteration budget; the global count of active systems is set accordingly.
+__global__ __launch_bounds__(kThreads) void k_batched_arm(const BSys* sys, BGlobal* glob, int nsys) {
     __shared__ int count;
     if (threadIdx.x == 0) count = 0;
     __syncthreads();
@@ -377,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void k_batched_arm(const BSys* sys, BGlob
         const int done = sys[s].S.st->done;
         sys[s].ctl->claim &= 0xffffffff00000000ull;  // rewind the chunk counter of the parked phase
         sys[s].ctl->active = done ? 0 : 1;
-        sys[s].ctl->budget = budget;
+        sys[s].ctl->budget = sys[s].budget;
         sys[s].ctl->done_cnt = 0u;
         if (!done) atomicAdd(&count, 1);
     }
@@ -385,6 +389,19 @@ __global__ __launch_bounds__(kThreads) void k_batched_arm(const BSys* sys, BGlob
     if (threadIdx.x == 0) {
         glob->active = count;
         glob->error = 0;
+    }
+}
+
+static_assert(sizeof(State) % 8 == 0, "State is copied in 8-byte words");
+
+// Copies the states of nsys systems into one contiguous array, so that the
+// host reads them with a single transfer.
+__global__ __launch_bounds__(kThreads) void k_gather_states(State* const* src, State* dst, int nsys) {
+    constexpr int W = (int)(sizeof(State) / 8);
+    const int total = nsys * W;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < total; i += gridDim.x * kThreads) {
+        const int s = i / W, w = i - s * W;
+        reinterpret_cast<uint64_t*>(dst + s)[w] = reinterpret_cast<const uint64_t*>(src[s])[w];
     }
 }
 

@@ -9,13 +9,12 @@
 //   an off-mesh neighbour reads the cell itself, and a zero coefficient
 //   cancels it.
 // * The BiCGStab passes: P1 (s = A p and (r0,s)), the streaming P2a
-//   (q = r - alpha s), P2b (y = A q and five dots) and the streaming P3
-//   (x, r and p updates and two dots).
+//   (q = r - alpha s and (q,q)), P2b (y = A q and four dots) and the
+//   streaming P3 (x, r and p updates and two dots).
 // * Deterministic hierarchical reductions: FP64 per lane, a fixed wavefront
-//   butterfly, a fixed wave order in LDS, and per-workgroup partials.  The
-//   last workgroup of each group of 1024 sums the group's partials, and the
-//   last group sums the group partials.  "Last" is decided by atomic tickets,
-//   and every sum runs in a fixed index order.
+//   DPP sequence, a fixed wave order in LDS, and per-workgroup partials,
+//   summed in a fixed index order by the last workgroup to arrive (an atomic
+//   ticket) or, for grids above 1024 workgroups, by a finishing kernel.
 // * The scalar steps of Algorithm 1 (alpha, omega, beta, stopping and
 //   breakdown tests), run by one thread of the last workgroup.
 #pragma once
@@ -147,9 +146,28 @@ __device__ __forceinline__ float fmaT(float a, float b, float c) { return __buil
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // ---------------------------------------------------------------- geometry
+// rnx and rplane are 1/nx and 1/(nx ny) rounded to FP64, for the index
+// divisions of cell_at (make_mesh fills them).
 struct Mesh {
     int nx, ny, nz;
+    double rnx, rplane;
 };
+
+inline Mesh make_mesh(int nx, int ny, int nz) {
+    return Mesh{nx, ny, nz, 1.0 / (double)nx, 1.0 / ((double)nx * (double)ny)};
+}
+
+// floor(a / d) for 0 <= a < 2^31 and d >= 1, with rd = fl64(1/d).  The FP64
+// product is within 2^31 * 2^-52 < 1 of a/d, so the truncated estimate is off
+// by at most one; the remainder test corrects it.  About a fifth of the
+// instructions of a generic 32-bit division.
+__device__ __forceinline__ int div_rcp(int a, int d, double rd) {
+    int q = (int)((double)a * rd);
+    const int r = a - q * d;
+    q += r >= d ? 1 : 0;
+    q -= r < 0 ? 1 : 0;
+    return q;
+}
 
 // One cell of the mesh and the offsets of its six neighbours.  An off-mesh
 // neighbour gets offset 0: it reads the cell itself, and its coefficient is
@@ -165,9 +183,9 @@ __device__ __forceinline__ Cell cell_at(int g, const Mesh& m, int n) {
     c.own = g < n;
     c.idx = c.own ? g : n - 1;
     const int plane = m.nx * m.ny;
-    const int k = c.idx / plane;
+    const int k = div_rcp(c.idx, plane, m.rplane);
     const int rem = c.idx - k * plane;
-    const int j = rem / m.nx;
+    const int j = div_rcp(rem, m.nx, m.rnx);
     const int i = rem - j * m.nx;
     c.dw = i > 0 ? -1 : 0;
     c.de = i < m.nx - 1 ? 1 : 0;
@@ -303,18 +321,21 @@ __device__ __forceinline__ uint32_t take_ticket(uint32_t* cnt) {
 }
 
 // DPP move of an FP64 value (both 32-bit halves with the same control).
-// Lanes whose row is masked off, or that have no source lane, read 0.
+// Lanes of a masked-off row get an unspecified value: no zero fill of the
+// destination first, which would add two moves to every step.  The reduction
+// below only reads lanes whose every input is defined.
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROWMASK, 0xf, false);
     return __hiloint2double(hi, lo);
 }
 
 // Wavefront reduction on the VALU (DPP), in a fixed order: pairs (quad_perm
 // [1,0,3,2]), quads ([2,3,0,1]), half-rows (row_half_mirror), rows
 // (row_mirror), then rows 0+1 and 2+3 (row_bcast:15 into rows 1 and 3) and
-// all four (row_bcast:31 into rows 2 and 3).  The total is in lane 63.  All
+// all four (row_bcast:31 into rows 2 and 3).  The total is in lane 63, whose
+// inputs are all defined; the other lanes end with unspecified values.  All
 // 64 lanes must be active.  Values j with bit j of MAXMASK set reduce with
 // max (of non-negative values), the others with +.
 template <int ND, unsigned MAXMASK>
@@ -484,9 +505,10 @@ __device__ __forceinline__ void cell_p1(const SysView<T>& S, int g, double (&acc
     acc[0] = c.own ? (double)to_f32(rh) * (double)to_f32(sv) : 0.0;
 }
 
-// P2a over one contiguous chunk: q = r - alpha s, rounded to the storage type.
+// P2a over one contiguous chunk: q = r - alpha s, rounded to the storage type;
+// partial (q, q) of the rounded q, for the half-step test.
 template <class T>
-__device__ __forceinline__ void chunk_p2a(const SysView<T>& S, int b) {
+__device__ __forceinline__ void chunk_p2a(const SysView<T>& S, int b, double (&acc)[1]) {
     int i0, i1;
     stream_range(S.n, S.stream_blocks, b, i0, i1);
     const float alpha = (float)S.st->alpha;
@@ -501,20 +523,52 @@ __device__ __forceinline__ void chunk_p2a(const SysView<T>& S, int b) {
         ld4_nt(s + i, sv);
         T qv[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) qv[j] = from_f32<T>(fmaT(-alpha, sv[j], rv[j]));
+        for (int j = 0; j < 4; ++j) {
+            qv[j] = from_f32<T>(fmaT(-alpha, sv[j], rv[j]));
+            const double qd = (double)to_f32(qv[j]);
+            acc[0] = fma(qd, qd, acc[0]);
+        }
         st4_nt(q + i, qv);
     }
-    for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads)
-        q[i] = from_f32<T>(fmaT(-alpha, to_f32(s[i]), to_f32(r[i])));
+    for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads) {
+        const T qv = from_f32<T>(fmaT(-alpha, to_f32(s[i]), to_f32(r[i])));
+        q[i] = qv;
+        const double qd = (double)to_f32(qv);
+        acc[0] = fma(qd, qd, acc[0]);
+    }
 }
 
-// P2b at one cell: y = A q stored; partials (q,y), (y,y), (q,q), (r0,q), (r0,y).
+// P2b at one cell: y = A q stored; partials (q,y), (y,y), (r0,q), (r0,y).
 template <class T, bool UNIT>
-__device__ __forceinline__ void cell_p2b(const SysView<T>& S, int g, double (&acc)[5]) {
+__device__ __forceinline__ void cell_p2b(const SysView<T>& S, int g, double (&acc)[4]) {
     const Cell c = cell_at(g, S.m, S.n);
     const Nbr<float> qv = nbr_f32(load_nbr(S.q, c));
     const Coefs<T, UNIT> k = load_coefs<T, UNIT>(S.c, c.idx);
     const double rh = (double)to_f32(S.rhat[c.idx]);
+    const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k, qv, c));
+    if (c.own) S.y[c.idx] = yt;
+    const double yd = c.own ? (double)to_f32(yt) : 0.0;
+    const double qd = c.own ? (double)qv.c : 0.0;
+    acc[0] = qd * yd;
+    acc[1] = yd * yd;
+    acc[2] = rh * qd;
+    acc[3] = rh * yd;
+}
+
+// The three-pass schedule's P2 at one cell: q = r - alpha s is formed on the
+// fly at the cell and its six neighbours (FP32, not stored), y = A q stored;
+// partials (q,y), (y,y), (q,q), (r0,q), (r0,y).  P3 then forms the same q
+// from r and s again, with the same rounding.
+template <class T, bool UNIT>
+__device__ __forceinline__ void cell_p2f(const SysView<T>& S, int g, float alpha, double (&acc)[5]) {
+    const Cell c = cell_at(g, S.m, S.n);
+    const Nbr<float> rv = nbr_f32(load_nbr(S.r, c));
+    const Nbr<float> sv = nbr_f32(load_nbr(S.s, c));
+    const Coefs<T, UNIT> k = load_coefs<T, UNIT>(S.c, c.idx);
+    const double rh = (double)to_f32(S.rhat[c.idx]);
+    const Nbr<float> qv{fmaT(-alpha, sv.c, rv.c), fmaT(-alpha, sv.w, rv.w), fmaT(-alpha, sv.e, rv.e),
+                        fmaT(-alpha, sv.s, rv.s), fmaT(-alpha, sv.n, rv.n), fmaT(-alpha, sv.b, rv.b),
+                        fmaT(-alpha, sv.t, rv.t)};
     const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k, qv, c));
     if (c.own) S.y[c.idx] = yt;
     const double yd = c.own ? (double)to_f32(yt) : 0.0;
@@ -540,7 +594,9 @@ __device__ __forceinline__ void p3_math(float alpha, float omega, float beta, fl
     pn = from_f32<T>(fmaT(beta, fmaT(-omega, sv, pv), to_f32(rn)));
 }
 
-template <class T>
+// QR (three-pass schedule): q is formed from the old r and s, r - alpha s,
+// instead of being read.
+template <class T, bool QR>
 __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&acc)[2]) {
     int i0, i1;
     stream_range(S.n, S.stream_blocks, b, i0, i1);
@@ -548,7 +604,7 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
     T* __restrict__ p = S.p;
     const T* __restrict__ s = S.s;
     const T* __restrict__ y = S.y;
-    const T* __restrict__ q = S.q;
+    const T* __restrict__ q = QR ? S.r : S.q;
     const T* __restrict__ rh = S.rhat;
     T* __restrict__ r = S.r;
     float* __restrict__ d = S.d;
@@ -563,6 +619,10 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
         ld4_nt(q + i, qv);
         ld4_nt(rh + i, hv);
         ld4_nt(d + i, dv);
+        if (QR) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) qv[j] = fmaT(-alpha, sv[j], qv[j]);
+        }
         T rn[4], pn[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -578,8 +638,9 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
     for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads) {
         float dv = d[i];
         T rn, pn;
-        p3_math<T>(alpha, omega, beta, to_f32(p[i]), to_f32(s[i]), to_f32(y[i]), to_f32(q[i]), dv,
-                   rn, pn);
+        const float sv = to_f32(s[i]);
+        const float qv = QR ? fmaT(-alpha, sv, to_f32(q[i])) : to_f32(q[i]);
+        p3_math<T>(alpha, omega, beta, to_f32(p[i]), sv, to_f32(y[i]), qv, dv, rn, pn);
         d[i] = dv;
         r[i] = rn;
         p[i] = pn;
@@ -608,20 +669,22 @@ __device__ __forceinline__ void tail_p1(State* st, const double (&tot)[1]) {
     st->alpha = a;
 }
 
-// After P2: half-step test on ||q||, else omega_i = (q, y) / (y, y), and
+// After P2a: (q, q) for the half-step test.
+__device__ __forceinline__ void tail_p2a(State* st, const double (&tot)[1]) { st->qq = tot[0]; }
+
+// After P2b: half-step test on ||q||, else omega_i = (q, y) / (y, y), and
 // beta_i = (alpha_i / omega_i) rho_{i+1} / rho_i with rho_{i+1} = (r0, r_{i+1})
 // expanded as (r0, q_i) - omega_i (r0, y_i), so that P3 can form p_{i+1} in the
 // same pass as r_{i+1}.  P3 also computes (r0, r_{i+1}) directly.  That exact
 // value becomes rho for the next iteration and drives the breakdown test.
-__device__ __forceinline__ void tail_p2(State* st, const double (&tot)[5]) {
+__device__ __forceinline__ void tail_p2(State* st, const double (&tot)[4]) {
     st->qy = tot[0];
     st->yy = tot[1];
-    st->qq = tot[2];
-    st->rq = tot[3];
-    st->ry = tot[4];
+    st->rq = tot[2];
+    st->ry = tot[3];
     st->beta = 0.0;
     st->beta_bad = RS_NONE;
-    const double qn = sqrt(tot[2]) / st->nb;
+    const double qn = sqrt(st->qq) / st->nb;
     if (qn <= st->tol) {
         st->omega = 0.0;  // P3 then adds alpha p only and sets r = q
         st->half = 1;
@@ -637,7 +700,7 @@ __device__ __forceinline__ void tail_p2(State* st, const double (&tot)[5]) {
         return;
     }
     st->omega = w;
-    const double rho_next = tot[3] - w * tot[4];
+    const double rho_next = tot[2] - w * tot[3];
     const double beta = (st->alpha / w) * (rho_next / st->rho);
     if (rho_next == 0.0) {
         st->beta_bad = RS_RHO_ZERO;

@@ -100,20 +100,28 @@ class BatchEngine {
     // callers whose resident set repeats (the batched entry point).
     BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
                 bool use_graph = false);
+    ~BatchEngine();
+    BatchEngine(const BatchEngine&) = delete;
+    BatchEngine& operator=(const BatchEngine&) = delete;
     // Takes part from the next step on; the job's arrays must stay valid until finished.
     int add(EngineJob* job);
-    // Advances every resident job: starts new ones, runs one persistent launch of at
-    // most `epoch_iters` BiCGStab iterations per job, and handles refinement steps
-    // and epilogues.  Finished jobs leave the resident set.  Returns S7_OK or an error.
-    int step(int epoch_iters);
+    // Advances every resident job: starts new ones, runs one persistent launch, and
+    // handles refinement steps and epilogues.  In the launch each job runs at most
+    // `epoch_iters` BiCGStab iterations; with epoch_iters <= 0 its budget is what
+    // fits in about `slice_ms` at its size (small systems run many iterations, large
+    // ones few), so one launch takes about slice_ms.  Finished jobs leave the
+    // resident set.  Returns S7_OK or an error.
+    int step(int epoch_iters, double slice_ms = 2.0);
     int resident() const { return (int)jobs_.size(); }
 
   private:
+    int read_states(std::vector<State>& h);
     char* tables_;
     int cap_;
     s7_options o_;
     hipStream_t st_;
     bool graph_;
+    State* host_states_ = nullptr;  // pinned, cap_ entries
     std::vector<EngineJob*> jobs_;
 };
 

@@ -10,10 +10,13 @@
 //   S7_ENOMEM.
 // * One serving thread admits requests from the FIFO head while their
 //   workspace fits, then advances every resident request by one engine step:
-//   a persistent launch of at most `epoch_iters` iterations each, plus the
-//   refinement and epilogue work in between.  Requests that arrive during a
-//   step join at the next one, while the others keep their Krylov state on
-//   the device.  A finished request frees its slice for the next admission.
+//   a persistent launch plus the refinement and epilogue work around it.  In
+//   the launch each request runs the iterations that fit a time slice of
+//   about 2 ms at its size (or a fixed count, if the options set one), so a
+//   small request finishes within a few slices even beside a large one.
+//   Requests that arrive during a step join at the next one, while the others
+//   keep their Krylov state on the device.  A finished request frees its
+//   workspace for the next admission.
 // * poll() never blocks; wait() blocks until the request is done.  A finished
 //   request's result is handed out once, then its ticket is released.
 #include <hip/hip_runtime.h>
@@ -33,6 +36,8 @@
 using namespace s7;
 
 namespace {
+
+constexpr double kSliceMs = 2.0;  // target length of one persistent launch
 
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
@@ -113,7 +118,7 @@ struct s7_queue {
     s7_queue(char* a, size_t ab, size_t tb, int dev, const s7_options& o, int cap)
         : arena(a), arena_bytes(ab), table_bytes(tb), device(dev), opt(o), capacity(cap),
           heap(ab - tb) {
-        epoch_iters = o.graph_iters > 0 ? o.graph_iters : 16;
+        epoch_iters = o.graph_iters > 0 ? o.graph_iters : 0;  // 0: time slices
     }
 
     void run() {
@@ -137,7 +142,7 @@ struct s7_queue {
                     engine->add(&r->job);
                 }
             }
-            int rc = resident.empty() ? S7_OK : engine->step(epoch_iters);
+            int rc = resident.empty() ? S7_OK : engine->step(epoch_iters, kSliceMs);
             std::lock_guard<std::mutex> lk(mu);
             if (rc != S7_OK) {
                 error = rc;

@@ -81,7 +81,7 @@ Layout make_layout(s7_dims d, int prec, const s7_options& o) {
 template <class T>
 static SysView<T> make_view(s7_dims d, const Layout& L, int jacobi, char* ws) {
     SysView<T> S;
-    S.m = Mesh{d.nx, d.ny, d.nz};
+    S.m = make_mesh(d.nx, d.ny, d.nz);
     S.n = (int)L.n;
     S.unit = jacobi ? 1 : 0;
     const size_t span = align256(L.n * L.elt);
@@ -233,18 +233,28 @@ __global__ __launch_bounds__(kThreads) void k_fill0(double* x, int n) {
 
 // Second half of a split grid sum (see Red), followed by the scalar step of the
 // pass whose partials it sums.
-enum FinishKind { FIN_P1 = 1, FIN_P2 = 2, FIN_INIT = 3, FIN_RESID = 4 };
+enum FinishKind { FIN_P1 = 1, FIN_P2 = 2, FIN_INIT = 3, FIN_RESID = 4, FIN_P2F = 5 };
+
+// Scalar step after the three-pass schedule's P2 (five sums: (q,y), (y,y),
+// (q,q), (r0,q), (r0,y)).
+__device__ __forceinline__ void tail_p2f(State* st, const double (&tot)[5]) {
+    st->qq = tot[2];
+    const double t4[4] = {tot[0], tot[1], tot[3], tot[4]};
+    tail_p2(st, t4);
+}
 
 template <int ND, unsigned MAXMASK, int KIND>
 __global__ __launch_bounds__(kThreads) void k_finish(Red red, int nblocks, State* st, double tol,
                                                      int max_iter) {
-    if ((KIND == FIN_P1 || KIND == FIN_P2) && st->done) return;
+    if ((KIND == FIN_P1 || KIND == FIN_P2 || KIND == FIN_P2F) && st->done) return;
     double tot[ND];
     if (!finish_split<ND, MAXMASK>(red, nblocks, tot) || threadIdx.x != 0) return;
     if constexpr (KIND == FIN_P1) {
         tail_p1(st, reinterpret_cast<double(&)[1]>(tot));
     } else if constexpr (KIND == FIN_P2) {
-        tail_p2(st, reinterpret_cast<double(&)[5]>(tot));
+        tail_p2(st, reinterpret_cast<double(&)[4]>(tot));
+    } else if constexpr (KIND == FIN_P2F) {
+        tail_p2f(st, reinterpret_cast<double(&)[5]>(tot));
     } else if constexpr (KIND == FIN_INIT) {
         tail_init(st, tot[0], tot[1], tol, max_iter);
         st->bb_true = tot[2];
@@ -269,24 +279,38 @@ __global__ __launch_bounds__(kThreads) void k_p1(SysView<T> S) {
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_p2a(SysView<T> S) {
     if (S.st->done) return;
-    chunk_p2a<T>(S, blockIdx.x);
+    double acc[1] = {0.0};
+    chunk_p2a<T>(S, blockIdx.x, acc);
+    double tot[1];
+    if (grid_reduce<1>(acc, S.red, S.stream_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+        tail_p2a(S.st, tot);
 }
 
 template <class T, bool UNIT>
 __global__ __launch_bounds__(kThreads) void k_p2(SysView<T> S) {
     if (S.st->done) return;
-    double acc[5];
+    double acc[4];
     cell_p2b<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, acc);
-    double tot[5];
-    if (grid_reduce<5>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+    double tot[4];
+    if (grid_reduce<4>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
         tail_p2(S.st, tot);
 }
 
-template <class T>
+template <class T, bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_p2f(SysView<T> S) {
+    if (S.st->done) return;
+    double acc[5];
+    cell_p2f<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, (float)S.st->alpha, acc);
+    double tot[5];
+    if (grid_reduce<5>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+        tail_p2f(S.st, tot);
+}
+
+template <class T, bool QR>
 __global__ __launch_bounds__(kThreads) void k_p3(SysView<T> S) {
     if (S.st->done) return;
     double acc[2];
-    chunk_p3<T>(S, blockIdx.x, acc);
+    chunk_p3<T, QR>(S, blockIdx.x, acc);
     double tot[2];
     if (grid_reduce<2>(acc, S.red, S.stream_blocks, blockIdx.x, tot) && threadIdx.x == 0)
         tail_p3(S.st, tot);
@@ -458,11 +482,28 @@ static void launch_finish(const Red& red, int nblocks, State* st, hipStream_t s,
 }
 
 // The launches of one iteration: 0 P1, 1 P2a, 2 P2b, 3 P3 (each with the
-// finishing kernel of a split sum where one is needed).
+// finishing kernel of a split sum where one is needed).  The three-pass
+// schedule has no P2a: its pass 2 forms q on the fly, and its P3 forms q again.
 constexpr int kPasses = 4;
+enum Schedule { SCHED_AUTO = 0, SCHED_THREE = 1, SCHED_FOUR = 2 };
 
 template <class T>
-static void launch_pass(const SysView<T>& S, int pass, hipStream_t s) {
+static void launch_pass(const SysView<T>& S, int pass, int sched, hipStream_t s) {
+    if (sched == SCHED_THREE) {
+        if (pass == 1) return;
+        if (pass == 2) {
+            if (S.unit)
+                hipLaunchKernelGGL((k_p2f<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+            else
+                hipLaunchKernelGGL((k_p2f<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+            launch_finish<5, 0u, FIN_P2F>(S.red, S.cell_blocks, S.st, s);
+            return;
+        }
+        if (pass == 3) {
+            hipLaunchKernelGGL((k_p3<T, true>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S);
+            return;
+        }
+    }
     if (pass == 0) {
         if (S.unit)
             hipLaunchKernelGGL((k_p1<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
@@ -476,10 +517,15 @@ static void launch_pass(const SysView<T>& S, int pass, hipStream_t s) {
             hipLaunchKernelGGL((k_p2<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
         else
             hipLaunchKernelGGL((k_p2<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
-        launch_finish<5, 0u, FIN_P2>(S.red, S.cell_blocks, S.st, s);
+        launch_finish<4, 0u, FIN_P2>(S.red, S.cell_blocks, S.st, s);
     } else {
-        hipLaunchKernelGGL((k_p3<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S);
+        hipLaunchKernelGGL((k_p3<T, false>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S);
     }
+}
+
+// The schedule of an iteration: the option if set, else the three-pass one.
+static int schedule_of(const s7_options& o) {
+    return o.schedule == SCHED_FOUR ? SCHED_FOUR : SCHED_THREE;
 }
 
 static int read_state(const State* dst, State* host, hipStream_t s) {
@@ -497,6 +543,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
     if (host->done) return S7_OK;
     const int K = o.graph_iters > 0 ? o.graph_iters : auto_graph_iters((size_t)S.n, (int)sizeof(T));
     const long long max_launches = (long long)host->max_iter / K + 3;
+    const int sched = schedule_of(o);
     if (o.profile) {
         constexpr int NP = kPasses;
         std::vector<hipEvent_t> ev((size_t)(NP + 1) * K);
@@ -506,7 +553,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
             for (int j = 0; j < K; ++j) {
                 for (int p = 0; p < NP; ++p) {
                     S7_HIP(hipEventRecord(ev[(NP + 1) * j + p], stream));
-                    launch_pass<T>(S, p, stream);
+                    launch_pass<T>(S, p, sched, stream);
                 }
                 S7_HIP(hipEventRecord(ev[(NP + 1) * j + NP], stream));
             }
@@ -532,11 +579,11 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
                                       (uintptr_t)S.m.nx, (uintptr_t)S.m.ny, (uintptr_t)S.m.nz,
                                       (uintptr_t)S.unit, (uintptr_t)S.st, (uintptr_t)S.red.part,
                                       (uintptr_t)S.r, (uintptr_t)S.c[1], (uintptr_t)S.d,
-                                      (uintptr_t)S.stream_blocks};
+                                      (uintptr_t)S.stream_blocks, (uintptr_t)sched};
         GraphRef g;
         rc = cached_graph(key, [&](hipStream_t cs) {
             for (int j = 0; j < K; ++j)
-                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, cs);
+                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, cs);
         }, &g);
         if (rc) return rc;
         for (long long l = 0; l < max_launches; ++l) {
@@ -695,13 +742,26 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
 // ============================================================== batch engine
 enum JobStage { J_NEW = 0, J_RESID = 1, J_ITER = 2, J_FINAL = 3, J_DONE = 4 };
 
+// Engine tables: [BGlobal][BSys x cap][State* x cap][State x cap].
+static size_t off_sys() { return align256(sizeof(BGlobal)); }
+static size_t off_sptr(int cap) { return off_sys() + align256((size_t)cap * sizeof(BSys)); }
+static size_t off_sgather(int cap) { return off_sptr(cap) + align256((size_t)cap * sizeof(State*)); }
+
 size_t engine_table_bytes(int capacity) {
-    return align256(sizeof(BGlobal)) + align256((size_t)capacity * sizeof(BSys));
+    return off_sgather(capacity) + align256((size_t)capacity * sizeof(State));
 }
 
 BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
                          bool use_graph)
-    : tables_(tables), cap_(capacity), o_(o), st_(stream), graph_(use_graph) {}
+    : tables_(tables), cap_(capacity), o_(o), st_(stream), graph_(use_graph) {
+    if (hipHostMalloc((void**)&host_states_, (size_t)capacity * sizeof(State), hipHostMallocDefault) !=
+        hipSuccess)
+        host_states_ = nullptr;  // read_states reports it
+}
+
+BatchEngine::~BatchEngine() {
+    if (host_states_) (void)hipHostFree(host_states_);
+}
 
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
@@ -849,13 +909,36 @@ static int job_inner_done(EngineJob& j, const State& h, const s7_options& o, hip
 #define S7_BY_PREC(j, call)                                           \
     ((j).prec == S7_FP32 ? call<float> : ((j).prec == S7_BF16_IR ? call<bf16> : call<f16>))
 
-static int read_states(std::vector<EngineJob*>& js, std::vector<State>& h, hipStream_t s) {
-    h.resize(js.size());
-    for (size_t i = 0; i < js.size(); ++i)
-        S7_HIP(hipMemcpyAsync(&h[i], js[i]->ws + js[i]->lo.off_state, sizeof(State),
-                              hipMemcpyDeviceToHost, s));
-    S7_HIP(hipStreamSynchronize(s));
+// Every resident job's State, in job order: one gather kernel and one transfer.
+int BatchEngine::read_states(std::vector<State>& h) {
+    const int n = (int)jobs_.size();
+    h.resize((size_t)n);
+    if (n == 0) return S7_OK;
+    if (!host_states_) {
+        set_error("batch engine: pinned host buffer unavailable");
+        return S7_EHIP;
+    }
+    State** dptr = reinterpret_cast<State**>(tables_ + off_sptr(cap_));
+    State* dst = reinterpret_cast<State*>(tables_ + off_sgather(cap_));
+    hipLaunchKernelGGL(k_gather_states, dim3((n * (int)(sizeof(State) / 8) + kThreads - 1) / kThreads),
+                       dim3(kThreads), 0, st_, (State* const*)dptr, dst, n);
+    S7_CHECK_LAUNCH();
+    S7_HIP(hipMemcpyAsync(host_states_, dst, (size_t)n * sizeof(State), hipMemcpyDeviceToHost, st_));
+    S7_HIP(hipStreamSynchronize(st_));
+    std::memcpy(h.data(), host_states_, (size_t)n * sizeof(State));
     return S7_OK;
+}
+
+// Per-job iteration budget of one launch in time-slice mode: the estimated
+// iteration time is a latency floor (four hand-offs between workgroups) plus
+// the traffic of the iteration at a conservative HBM rate.
+static int slice_budget(const EngineJob& j, double slice_ms) {
+    const double bytes = j.prec == S7_FP32 ? 120.0 : 64.0;
+    const double t_ms = 0.03 + (double)j.lo.n * bytes / 4.0e9;
+    double b = slice_ms / t_ms;
+    if (b < 1.0) b = 1.0;
+    if (b > 4096.0) b = 4096.0;
+    return (int)b;
 }
 
 static void finish_job(EngineJob& j, const State* h) {
@@ -876,16 +959,21 @@ static void finish_job(EngineJob& j, const State* h) {
     j.finished = 1;
 }
 
-int BatchEngine::step(int epoch_iters) {
+int BatchEngine::step(int epoch_iters, double slice_ms) {
     int rc;
-    // 1) start new jobs
+    // 1) start new jobs; the state pointer table follows the resident set
+    std::vector<State*> sptr;
     for (EngineJob* j : jobs_) {
+        sptr.push_back(reinterpret_cast<State*>(j->ws + j->lo.off_state));
         if (j->stage != J_NEW) continue;
         rc = S7_BY_PREC(*j, job_start)(*j, o_, st_);
         if (rc) return rc;
     }
+    if (!sptr.empty())
+        S7_HIP(hipMemcpyAsync(tables_ + off_sptr(cap_), sptr.data(), sptr.size() * sizeof(State*),
+                              hipMemcpyHostToDevice, st_));
     std::vector<State> h;
-    rc = read_states(jobs_, h, st_);
+    rc = read_states(h);
     if (rc) return rc;
     // 2) refinement decisions and inner solves that are already over (trivial starts)
     for (size_t i = 0; i < jobs_.size(); ++i) {
@@ -895,7 +983,7 @@ int BatchEngine::step(int epoch_iters) {
             if (rc) return rc;
         }
     }
-    rc = read_states(jobs_, h, st_);
+    rc = read_states(h);
     if (rc) return rc;
     // 3) one persistent launch over every job in an inner solve
     std::vector<BSys> table;
@@ -911,13 +999,15 @@ int BatchEngine::step(int epoch_iters) {
         b.ctl = reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl);
         b.nchunk = (int)((j->lo.n + chunk - 1) / chunk);
         b.tag = j->tag;
+        b.budget = epoch_iters > 0 ? epoch_iters : slice_budget(*j, slice_ms);
+        b.pad = 0;
         max_chunks = max_chunks > b.nchunk ? max_chunks : b.nchunk;
         table.push_back(b);
         in_launch.push_back(j);
     }
     if (!table.empty()) {
         BGlobal* glob = reinterpret_cast<BGlobal*>(tables_);
-        BSys* dsys = reinterpret_cast<BSys*>(tables_ + align256(sizeof(BGlobal)));
+        BSys* dsys = reinterpret_cast<BSys*>(tables_ + off_sys());
         S7_HIP(hipMemcpyAsync(dsys, table.data(), table.size() * sizeof(BSys), hipMemcpyHostToDevice, st_));
         const int nsys = (int)table.size();
         long long total_chunks = 0;
@@ -927,7 +1017,7 @@ int BatchEngine::step(int epoch_iters) {
         const long long spin_limit = 5000000;
         auto body = [&](hipStream_t cs) {
             hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
-                               nsys, epoch_iters);
+                               nsys);
             hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
                                chunk, spin_limit);
         };
@@ -952,7 +1042,7 @@ int BatchEngine::step(int epoch_iters) {
             return S7_EHIP;
         }
     }
-    rc = read_states(jobs_, h, st_);
+    rc = read_states(h);
     if (rc) return rc;
     // 4) inner solves that ended
     for (size_t i = 0; i < jobs_.size(); ++i) {
@@ -962,7 +1052,7 @@ int BatchEngine::step(int epoch_iters) {
             if (rc) return rc;
         }
     }
-    rc = read_states(jobs_, h, st_);
+    rc = read_states(h);
     if (rc) return rc;
     // 5) finished jobs leave
     std::vector<EngineJob*> keep;
@@ -1006,7 +1096,7 @@ int s7_stencil_apply(s7_dims d, const float* const coef[7], const float* v, floa
         set_error("s7_stencil_apply: invalid argument");
         return S7_EINVAL;
     }
-    Mesh m{d.nx, d.ny, d.nz};
+    const Mesh m = make_mesh(d.nx, d.ny, d.nz);
     const int n = d.nx * d.ny * d.nz;
     Coef7 cf;
     for (int a = 0; a < 7; ++a) cf.c[a] = coef[a];
@@ -1056,7 +1146,7 @@ int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float* const c
         set_error("s7_generate_problem: invalid argument");
         return S7_EINVAL;
     }
-    Mesh m{d.nx, d.ny, d.nz};
+    const Mesh m = make_mesh(d.nx, d.ny, d.nz);
     Coef7 cf;
     bool all = coef != nullptr;
     for (int a = 0; a < 7; ++a) {

@@ -184,8 +184,8 @@ def test_stream_split_agrees_with_oracle(s7, sb):
 
 
 def test_split_reduction_matches_oracle(s7):
-    """Above 4096 workgroups a pass stores workgroup partials and a finishing kernel sums
-    them in groups of 1024: 128x96x96 (4608 workgroups) runs that path."""
+    """Above 1024 workgroups a stencil pass stores workgroup partials and a finishing
+    kernel sums them (in groups of 8192): 128x96x96 (4608 workgroups) runs that path."""
     dims = (128, 96, 96)
     prob, A, b = problem(dims, seed=14)
     coef = coef_dev(prob)
@@ -208,8 +208,9 @@ def test_split_reduction_matches_oracle(s7):
 
 
 def test_multi_group_reduction_matches_oracle(s7):
-    """More than 1024 workgroups per stencil pass: the reduction runs in two levels."""
-    dims = (130, 70, 40)  # 364,000 cells -> 1422 workgroups
+    """More than 8192 workgroups per stencil pass: the finishing kernel runs several
+    groups and the last one sums the group sums."""
+    dims = (160, 128, 128)  # 2,621,440 cells -> 10,240 workgroups, two groups
     prob, A, b = problem(dims, seed=13)
     ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=1000)
     x, info = gpu_solve(s7, dims, coef_dev(prob), b, rtol=1e-8)
@@ -279,3 +280,27 @@ def test_precisions_share_workspace_without_interference(s7):
         if prec in out:
             assert np.array_equal(out[prec], host(x))
         out[prec] = host(x)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_schedules_agree(s7, prec):
+    """Three passes (q formed where it is used) and four passes (q stored) compute the
+    same q in FP32: for FP32 storage the iterates agree to the rounding of the (q,q)
+    sum; both match the oracle."""
+    dims = (70, 40, 20)
+    prob, A, b = problem(dims, seed=21)
+    coef = coef_dev(prob)
+    bd = dev(b)
+    rtol = 1e-8 if prec == 0 else 1e-10
+    ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=1000)
+    out = [gpu_solve(s7, dims, coef, bd, rtol=rtol, max_iter=2000, prec=prec, schedule=sc) for sc in (1, 2)]
+    for x, info in out:
+        assert info.status == s7.OK and rel_err(x, ref.x) <= (1e-6 if prec == 0 else 1e-7)
+    if prec == 0:
+        assert out[0][1].iters == out[1][1].iters
+        assert rel_err(out[0][0], out[1][0]) <= 1e-12
+    for k in (1, 2, 5):
+        rk = oracle.bicgstab(A, b, tol=1e-300, max_iter=k)
+        for sc in (1, 2):
+            xk, ik = gpu_solve(s7, dims, coef, bd, rtol=1e-300, max_iter=k, schedule=sc)
+            assert rel_err(xk, rk.x) <= 1e-4 and abs(ik.rel_res_rec - rk.res_rec) <= 1e-4 * rk.res_rec
