@@ -100,6 +100,16 @@ typedef struct {
     int32_t schedule;       /* single-system solve: 1 three passes per iteration (q = r - alpha s
                                formed on the fly where it is used, never stored), 2 four
                                passes (q stored by a streaming pass); 0 = 1 */
+    int32_t tune;           /* 1: the fields left at 0 among schedule and stream_blocks
+                               (single solve) and chunk_cells (batched) take autotuned values
+                               for the problem's size class.  An untuned class is timed first
+                               on synthetic data in the caller's workspace (the caller's arrays
+                               are not touched); the choice is kept for the process and, if
+                               the environment variable S7_TUNE_CACHE names a file, appended
+                               there and read back by later processes.  The request queue
+                               does not tune: its resident set changes every step, and each
+                               request's sums must not depend on it.  0: fixed defaults. */
+    int32_t reserved1;      /* must be 0 */
     double inner_rtol;      /* IR: inner relative tolerance; 0 = 1e-2 (BF16), 5e-3 (FP16) */
 } s7_options;
 

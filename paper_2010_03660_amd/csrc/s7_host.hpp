@@ -4,9 +4,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/s7.h"
 #include "s7_device.hpp"
@@ -66,6 +68,19 @@ Layout make_layout(s7_dims d, int prec, const s7_options& o);
 
 void options_or_default(const s7_options* in, s7_options& out);
 
+// ---------------------------------------------------------------- autotuning cache
+// Tuned launch parameters per size class.  kind: TUNE_SINGLE (val: schedule,
+// stream_blocks) or TUNE_BATCH (val: chunk_cells, persistent grid).  Classes
+// are half-octaves of the cell count (and, for batches, of the system count).
+enum TuneKind { TUNE_SINGLE = 1, TUNE_BATCH = 2 };
+struct TuneKey {
+    int kind, tag, unit, nbucket, sbucket;
+    bool operator<(const TuneKey& o) const;
+};
+inline int size_bucket(double v) { return v < 1.0 ? 0 : (int)floor(2.0 * log2(v)); }
+bool tune_lookup(const TuneKey& k, int (&val)[2]);
+void tune_store(const TuneKey& k, const int (&val)[2]);
+
 // ---------------------------------------------------------------- batch engine
 // Runs many systems together: the batched entry point and the request queue
 // both drive it.  Each system brings its own workspace slice (s7_workspace_bytes
@@ -94,6 +109,8 @@ struct EngineJob {
 
 size_t engine_table_bytes(int capacity);
 
+struct BSys;  // one system of a persistent launch (device table entry)
+
 class BatchEngine {
   public:
     // use_graph: replay the persistent launch from a captured hipGraph, for
@@ -113,14 +130,22 @@ class BatchEngine {
     // resident set.  Returns S7_OK or an error.
     int step(int epoch_iters, double slice_ms = 2.0);
     int resident() const { return (int)jobs_.size(); }
+    // Picks chunk_cells and the persistent grid for the size class of the resident
+    // jobs (all not yet started), by timing short trials on synthetic contents of
+    // their workspaces, unless the class is cached.  Call before the first step.
+    int tune();
 
   private:
     int read_states(std::vector<State>& h);
+    // Uploads `table` and runs one persistent launch (arm + kernel), then waits for it.
+    int launch(const std::vector<BSys>& table, int epoch_key, int chunk, int grid);
     char* tables_;
     int cap_;
     s7_options o_;
     hipStream_t st_;
     bool graph_;
+    int chunk_;     // cells per work item of the persistent kernel
+    int grid_cap_;  // most workgroups of a persistent launch
     State* host_states_ = nullptr;  // pinned, cap_ entries
     std::vector<EngineJob*> jobs_;
 };

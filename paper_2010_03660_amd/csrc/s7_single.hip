@@ -13,6 +13,7 @@
 // iterations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -55,7 +56,9 @@ Layout make_layout(s7_dims d, int prec, const s7_options& o) {
     L.ncoef = o.jacobi ? 6 : 7;
     L.cell_blocks = cell_blocks_for((long long)L.n);
     L.stream_blocks = stream_blocks_for((long long)L.n, o.stream_blocks);
-    const int nb = L.cell_blocks > L.stream_blocks ? L.cell_blocks : L.stream_blocks;
+    // partials for any streaming split up to kSingleMax, so the workspace size
+    // does not depend on the (tunable) split
+    const int nb = L.cell_blocks > kSingleMax ? L.cell_blocks : kSingleMax;
     L.groups = red_groups(nb);  // workgroups of the finishing kernel of a split sum
     size_t off = 0;
     L.off_state = off;
@@ -628,6 +631,100 @@ static int start_solve(const Coef7& cf, const SysView<T>& S, const Layout& Lo, i
     return S7_OK;
 }
 
+// ============================================================== autotuning trials
+// A trial runs iterations on synthetic contents written into the workspace:
+// unit diagonal, off-diagonals -0.15 (row sums 0.1 inside the mesh, so the
+// system is well conditioned), r = r0 = p = 1.  The iteration kernels touch
+// only the workspace, so the caller's arrays are never read or written.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_tune_fill(SysView<T> S) {
+    const T one = from_f32<T>(1.0f), zero = from_f32<T>(0.0f), off = from_f32<T>(-0.15f);
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < S.n; i += gridDim.x * kThreads) {
+        for (int a = S.unit ? 1 : 0; a < 7; ++a) const_cast<T*>(S.c[a])[i] = a == 0 ? one : off;
+        S.r[i] = one;
+        S.rhat[i] = one;
+        S.p[i] = one;
+        S.s[i] = zero;
+        S.y[i] = zero;
+        S.q[i] = zero;
+        S.d[i] = 0.0f;
+    }
+}
+
+__global__ void k_tune_state(State* st, uint32_t* cnt, int n) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    *st = State{};
+    st->rho = (double)n;
+    st->nb = sqrt((double)n);
+    st->tol = 0.0;
+    st->max_iter = 1 << 30;
+    *cnt = 0u;
+}
+
+// Fills the workspace with a trial system and arms its State.
+template <class T>
+static int tune_prepare(const SysView<T>& S, hipStream_t s) {
+    hipLaunchKernelGGL((k_tune_fill<T>), dim3(grid_for(S.n)), dim3(kThreads), 0, s, S);
+    hipLaunchKernelGGL(k_tune_state, dim3(1), dim3(64), 0, s, S.st, S.red.cnt, S.n);
+    S7_CHECK_LAUNCH();
+    return S7_OK;
+}
+
+// Picks the schedule and the streaming split of the single-system solve for the
+// size class of d: each candidate runs one warm-up and K timed iterations.
+template <class T>
+static int tune_single(s7_dims d, const Layout& Lo, int jacobi, char* ws, hipStream_t s, int (&best)[2]) {
+    const TuneKey key{TUNE_SINGLE, TypeTag<T>::value, jacobi, size_bucket((double)Lo.n), 0};
+    if (tune_lookup(key, best)) return S7_OK;
+    SysView<T> S = make_view<T>(d, Lo, jacobi, ws);
+    const int K = std::max(2, std::min(12, auto_graph_iters(Lo.n, (int)sizeof(T)) / 2));
+    hipEvent_t e0, e1;
+    S7_HIP(hipEventCreate(&e0));
+    S7_HIP(hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    best[0] = SCHED_THREE;
+    best[1] = stream_blocks_for((long long)Lo.n, 0);
+    int rc = S7_OK;
+    std::vector<int> tried;
+    for (int sched : {SCHED_THREE, SCHED_FOUR}) {
+        for (int cap : {256, 512, 1024}) {
+            const int sb = stream_blocks_for((long long)Lo.n, cap);
+            const int id = sched * 4096 + sb;
+            if (std::find(tried.begin(), tried.end(), id) != tried.end()) continue;
+            tried.push_back(id);
+            S.stream_blocks = sb;
+            if ((rc = tune_prepare<T>(S, s))) break;
+            for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, s);
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = S7_EHIP; break; }
+            for (int j = 0; j < K; ++j)
+                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, s);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = S7_EHIP;
+                break;
+            }
+            State h;
+            if ((rc = read_state(S.st, &h, s))) break;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (h.done || h.iter != K + 1) continue;  // the trial system stopped: no timing
+            if (ms < best_ms) {
+                best_ms = ms;
+                best[0] = sched;
+                best[1] = sb;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        set_error("autotuning trial failed");
+        return rc;
+    }
+    tune_store(key, best);
+    return S7_OK;
+}
+
 static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol,
                       int max_iter, char* ws, const Layout& Lo, const s7_options& o,
                       s7_info* info, hipStream_t s) {
@@ -751,9 +848,12 @@ size_t engine_table_bytes(int capacity) {
     return off_sgather(capacity) + align256((size_t)capacity * sizeof(State));
 }
 
+static int chunk_cells_of(const s7_options& o);
+
 BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
                          bool use_graph)
-    : tables_(tables), cap_(capacity), o_(o), st_(stream), graph_(use_graph) {
+    : tables_(tables), cap_(capacity), o_(o), st_(stream), graph_(use_graph),
+      chunk_(chunk_cells_of(o)), grid_cap_(1024) {
     if (hipHostMalloc((void**)&host_states_, (size_t)capacity * sizeof(State), hipHostMallocDefault) !=
         hipSuccess)
         host_states_ = nullptr;  // read_states reports it
@@ -959,6 +1059,122 @@ static void finish_job(EngineJob& j, const State* h) {
     j.finished = 1;
 }
 
+int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk, int grid_cap) {
+    BGlobal* glob = reinterpret_cast<BGlobal*>(tables_);
+    BSys* dsys = reinterpret_cast<BSys*>(tables_ + off_sys());
+    S7_HIP(hipMemcpyAsync(dsys, table.data(), table.size() * sizeof(BSys), hipMemcpyHostToDevice, st_));
+    const int nsys = (int)table.size();
+    long long total_chunks = 0;
+    for (const BSys& b : table) total_chunks += b.nchunk;
+    int grid = (int)(total_chunks < grid_cap ? total_chunks : grid_cap);
+    if (grid < 1) grid = 1;
+    const long long spin_limit = 5000000;
+    auto body = [&](hipStream_t cs) {
+        hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys);
+        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
+                           chunk, spin_limit);
+    };
+    GraphRef g;  // held until the launch has completed
+    if (graph_) {
+        // the table is re-uploaded before every replay, so the key needs only its shape
+        std::vector<uintptr_t> key = {0x53u, (uintptr_t)tables_, (uintptr_t)nsys, (uintptr_t)epoch_key,
+                                      (uintptr_t)grid, (uintptr_t)chunk};
+        int rc = cached_graph(key, body, &g);
+        if (rc) return rc;
+        S7_HIP(hipGraphLaunch(g->exec, st_));
+    } else {
+        // the serving loop: the resident set changes from step to step
+        body(st_);
+        S7_CHECK_LAUNCH();
+    }
+    BGlobal hg;
+    S7_HIP(hipMemcpyAsync(&hg, glob, sizeof(hg), hipMemcpyDeviceToHost, st_));
+    S7_HIP(hipStreamSynchronize(st_));
+    if (hg.error) {
+        set_error("batched launch: a workgroup exceeded its wait bound");
+        return S7_EHIP;
+    }
+    return S7_OK;
+}
+
+template <class T>
+static int tune_prepare_job(const EngineJob& j, const s7_options& o, hipStream_t s) {
+    return tune_prepare<T>(make_view<T>(j.d, j.lo, o.jacobi, j.ws), s);
+}
+
+int BatchEngine::tune() {
+    if (jobs_.empty()) return S7_OK;
+    double total = 0.0;
+    for (const EngineJob* j : jobs_) {
+        if (j->stage != J_NEW) {
+            set_error("batch engine: tune() after the first step");
+            return S7_EINVAL;
+        }
+        total += (double)j->lo.n;
+    }
+    const TuneKey key{TUNE_BATCH, jobs_[0]->tag, o_.jacobi, size_bucket(total), size_bucket((double)jobs_.size())};
+    int best[2];
+    if (tune_lookup(key, best)) {
+        chunk_ = best[0];
+        grid_cap_ = best[1];
+        return S7_OK;
+    }
+    const bool graph = graph_;
+    graph_ = false;  // trials launch directly
+    hipEvent_t e0, e1;
+    S7_HIP(hipEventCreate(&e0));
+    S7_HIP(hipEventCreate(&e1));
+    const int K = 4;
+    float best_ms = INFINITY;
+    best[0] = chunk_;
+    best[1] = grid_cap_;
+    int rc = S7_OK;
+    for (int chunk : {1024, 2048, 4096, 8192, 16384}) {
+        for (int gcap : {1024, 2048}) {
+            std::vector<BSys> table;
+            long long chunks = 0;
+            for (EngineJob* j : jobs_) {
+                if ((rc = S7_BY_PREC(*j, tune_prepare_job)(*j, o_, st_))) break;
+                hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st_,
+                                   reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl));
+                BSys b;
+                b.S = make_view<float>(j->d, j->lo, o_.jacobi, j->ws);
+                b.ctl = reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl);
+                b.nchunk = (int)((j->lo.n + chunk - 1) / chunk);
+                b.tag = j->tag;
+                b.budget = K;
+                b.pad = 0;
+                chunks += b.nchunk;
+                table.push_back(b);
+            }
+            if (rc) break;
+            if (gcap > 1024 && chunks <= 1024) continue;  // same grid as the smaller cap
+            if (hipEventRecord(e0, st_) != hipSuccess) { rc = S7_EHIP; break; }
+            if ((rc = launch(table, K, chunk, gcap))) break;
+            if (hipEventRecord(e1, st_) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = S7_EHIP;
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best[0] = chunk;
+                best[1] = gcap;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    graph_ = graph;
+    if (rc) return rc;
+    tune_store(key, best);
+    chunk_ = best[0];
+    grid_cap_ = best[1];
+    return S7_OK;
+}
+
 int BatchEngine::step(int epoch_iters, double slice_ms) {
     int rc;
     // 1) start new jobs; the state pointer table follows the resident set
@@ -988,8 +1204,7 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
     // 3) one persistent launch over every job in an inner solve
     std::vector<BSys> table;
     std::vector<EngineJob*> in_launch;
-    int max_chunks = 0;
-    const int chunk = chunk_cells_of(o_);
+    const int chunk = chunk_;
     for (size_t i = 0; i < jobs_.size(); ++i) {
         EngineJob* j = jobs_[i];
         if (j->stage != J_ITER || h[i].done) continue;
@@ -1001,46 +1216,12 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
         b.tag = j->tag;
         b.budget = epoch_iters > 0 ? epoch_iters : slice_budget(*j, slice_ms);
         b.pad = 0;
-        max_chunks = max_chunks > b.nchunk ? max_chunks : b.nchunk;
         table.push_back(b);
         in_launch.push_back(j);
     }
     if (!table.empty()) {
-        BGlobal* glob = reinterpret_cast<BGlobal*>(tables_);
-        BSys* dsys = reinterpret_cast<BSys*>(tables_ + off_sys());
-        S7_HIP(hipMemcpyAsync(dsys, table.data(), table.size() * sizeof(BSys), hipMemcpyHostToDevice, st_));
-        const int nsys = (int)table.size();
-        long long total_chunks = 0;
-        for (const BSys& b : table) total_chunks += b.nchunk;
-        int grid = (int)(total_chunks < 1024 ? total_chunks : 1024);
-        if (grid < 1) grid = 1;
-        const long long spin_limit = 5000000;
-        auto body = [&](hipStream_t cs) {
-            hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
-                               nsys);
-            hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
-                               chunk, spin_limit);
-        };
-        GraphRef g;  // held until the launch has completed
-        if (graph_) {
-            // the table is re-uploaded before every replay, so the key needs only its shape
-            std::vector<uintptr_t> key = {0x53u, (uintptr_t)tables_, (uintptr_t)nsys,
-                                          (uintptr_t)epoch_iters, (uintptr_t)grid, (uintptr_t)chunk};
-            rc = cached_graph(key, body, &g);
-            if (rc) return rc;
-            S7_HIP(hipGraphLaunch(g->exec, st_));
-        } else {
-            // the serving loop: the resident set changes from step to step
-            body(st_);
-            S7_CHECK_LAUNCH();
-        }
-        BGlobal hg;
-        S7_HIP(hipMemcpyAsync(&hg, glob, sizeof(hg), hipMemcpyDeviceToHost, st_));
-        S7_HIP(hipStreamSynchronize(st_));
-        if (hg.error) {
-            set_error("batched launch: a workgroup exceeded its wait bound");
-            return S7_EHIP;
-        }
+        rc = launch(table, epoch_iters, chunk, grid_cap_);
+        if (rc) return rc;
     }
     rc = read_states(h);
     if (rc) return rc;
@@ -1134,6 +1315,16 @@ int s7_bicgstab_solve(s7_dims d, const float* const coef[7], const double* b, do
     for (int a = 0; a < 7; ++a) cf.c[a] = coef[a];
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
+    if (o.tune && (o.schedule == 0 || o.stream_blocks == 0)) {
+        int best[2];
+        const int rc = prec == S7_FP32      ? tune_single<float>(d, Lo, o.jacobi, w, s, best)
+                       : prec == S7_BF16_IR ? tune_single<bf16>(d, Lo, o.jacobi, w, s, best)
+                                            : tune_single<f16>(d, Lo, o.jacobi, w, s, best);
+        if (rc) return rc;
+        if (o.schedule == 0) o.schedule = best[0];
+        if (o.stream_blocks == 0) o.stream_blocks = best[1];
+        Lo = make_layout(d, prec, o);
+    }
     if (prec == S7_FP32) return solve_fp32(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s);
     if (prec == S7_BF16_IR) return solve_ir<bf16>(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s, prec);
     return solve_ir<f16>(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s, prec);
@@ -1227,6 +1418,10 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
         j.t_start_ms = t0;
         off += align256(j.ws_bytes);
         int rc = eng.add(&j);
+        if (rc) return rc;
+    }
+    if (o.tune && o.chunk_cells == 0) {
+        int rc = eng.tune();
         if (rc) return rc;
     }
     int guard = 0;

@@ -1,0 +1,89 @@
+"""GPU tests of the autotuner (options.tune = 1).
+
+Tuning times short trials on synthetic contents of the caller's workspace, so the
+caller's arrays must come out exactly as an untuned solve with the chosen parameters
+would leave them, and the result must match the FP64 oracle.  Choices are cached per
+size class and appended to the file named by S7_TUNE_CACHE."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import gpu_available
+from tests.gpu_helpers import coef_dev, dev, host, problem, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def s7(tmp_path_factory):
+    if not gpu_available():
+        pytest.skip("no GPU")
+    path = tmp_path_factory.mktemp("tune") / "s7tune.txt"
+    os.environ["S7_TUNE_CACHE"] = str(path)  # read at the first tuned call of the process
+    import paper_2010_03660_amd as s7
+    s7.lib()
+    yield s7, path
+    os.environ.pop("S7_TUNE_CACHE", None)
+
+
+def solve(s7, dims, coef, b, x0, **opt):
+    import torch
+    x = dev(x0.copy())
+    info = s7.bicgstab_solve(dims, coef, dev(b), x, opt.pop("rtol", 1e-8), 2000,
+                             prec=opt.pop("prec", 0), opt=s7.default_options(**opt))
+    torch.cuda.synchronize()
+    return host(x), info
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tuned_single_solve(s7, prec):
+    s7, path = s7
+    dims = (70, 40, 20)
+    prob, A, b = problem(dims, seed=31)
+    coef = coef_dev(prob)
+    x0 = np.linspace(-0.5, 0.5, A.n)
+    rtol = 1e-8 if prec == 0 else 1e-10
+    x1, i1 = solve(s7, dims, coef, b, x0, tune=1, prec=prec, rtol=rtol)  # trials, then the solve
+    x2, i2 = solve(s7, dims, coef, b, x0, tune=1, prec=prec, rtol=rtol)  # cached choice
+    assert np.array_equal(x1, x2) and i1.iters == i2.iters
+    ref = oracle.bicgstab(A, b, x0=x0, tol=1e-13, max_iter=2000)
+    assert i1.status == s7.OK and rel_err(x1, ref.x) <= (1e-6 if prec == 0 else 1e-7)
+    # the choice is one of the explicit settings: some explicit run reproduces it bit for bit
+    same = False
+    for sched in (1, 2):
+        for sb in (256, 512, 1024):
+            xe, ie = solve(s7, dims, coef, b, x0, schedule=sched, stream_blocks=sb, prec=prec, rtol=rtol)
+            same = same or (np.array_equal(xe, x1) and ie.iters == i1.iters)
+    assert same
+    lines = path.read_text().split("\n")
+    assert any(l.startswith("s7tune1 1 ") for l in lines)
+
+
+def test_tuned_batched_solve(s7):
+    import torch
+    s7, path = s7
+    shapes = [(24, 32, 48), (17, 5, 9), (40, 24, 20), (64, 24, 32), (2, 1, 1)]
+    probs = [problem(d, seed=40 + i) for i, d in enumerate(shapes)]
+    coefs = [coef_dev(p) for p, A, b in probs]
+    bs = [dev(b) for p, A, b in probs]
+
+    def run(**opt):
+        xs = [torch.zeros(A.n, dtype=torch.float64, device="cuda") for p, A, b in probs]
+        rc, infos = s7.bicgstab_solve_batched(shapes, coefs, bs, xs, [1e-8] * len(shapes),
+                                              [2000] * len(shapes), opt=s7.default_options(**opt))
+        torch.cuda.synchronize()
+        return rc, infos, [host(x) for x in xs]
+
+    rc, infos, xs = run(tune=1)
+    assert rc == s7.OK
+    for (p, A, b), x in zip(probs, xs):
+        ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+        assert rel_err(x, ref.x) <= 1e-6
+    rc2, infos2, xs2 = run(tune=1)
+    assert all(np.array_equal(a, c) for a, c in zip(xs, xs2))
+    # the tuned chunk is one of the candidates: an explicit run reproduces the result
+    chunk = int([l for l in path.read_text().split("\n") if l.startswith("s7tune1 2 ")][-1].split()[6])
+    rc3, infos3, xs3 = run(chunk_cells=chunk)
+    assert all(np.array_equal(a, c) for a, c in zip(xs, xs3))
