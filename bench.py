@@ -46,6 +46,7 @@ KERNEL = {"p1": "k_p1 (P1: s = A p, (r0,s))",
           "p2b": "k_p2 (P2b: y = A q, four dot products)",
           "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"}
 BATCH_BYTES = sum(BYTES[("f32", 4)].values())  # the batched engine runs the four-pass schedule
+SPLIT_CELLS = 1 << 21  # the queue's default: larger requests take the single-system path
 SRC_FILES = ["paper_2010_03660_amd/csrc/s7_device.hpp", "paper_2010_03660_amd/csrc/s7_single.hip"]
 
 
@@ -113,11 +114,12 @@ def batched_leg(s7, torch, dev):
             x.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, infos = s7.bicgstab_solve_batched(shapes, coefs, bs, xs, [1e-7] * 64, [2000] * 64, ws=ws)
+        rc, infos = s7.bicgstab_solve_batched(shapes, coefs, bs, xs, [1e-7] * 64, [2000] * 64, ws=ws,
+                                              opt=s7.default_options(tune=1))
         torch.cuda.synchronize()
         return rc, infos, time.perf_counter() - t0
 
-    batched()  # warm-up (captures the launch graph)
+    batched()  # warm-up: autotunes the size class and captures the launch graph
     rc, infos, dt = batched()
     iters = [i.iters for i in infos]
     err = max(float(torch.linalg.vector_norm(x - xx) / torch.linalg.vector_norm(xx))
@@ -125,12 +127,15 @@ def batched_leg(s7, torch, dev):
     cell_iters = sum(c * k for c, k in zip(cells, iters))
     # the same systems, one single-system solve after another
     sws = torch.empty(max(s7.workspace_bytes(d) for d in shapes), dtype=torch.uint8, device=dev)
+    o1 = s7.default_options(tune=1)
+    for d, c, bb, x in zip(shapes, coefs, bs, xs):  # warm-up: tunes each size class
+        s7.bicgstab_solve(d, c, bb, x, 1e-7, 3, ws=sws, opt=o1)
     for x in xs:
         x.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for d, c, bb, x in zip(shapes, coefs, bs, xs):
-        s7.bicgstab_solve(d, c, bb, x, 1e-7, 2000, ws=sws)
+        s7.bicgstab_solve(d, c, bb, x, 1e-7, 2000, ws=sws, opt=o1)
     torch.cuda.synchronize()
     dts = time.perf_counter() - t0
     return {
@@ -263,12 +268,16 @@ def served_leg(s7, torch, dev, nreq: int, rate: float, burst: int, arena_gb: flo
         br = [synth.Request(r.rid, 0.0, r.dims, r.mode, r.rtol, r.seed) for r in reqs[:burst]]
         print(f"[bench] burst of {burst} requests", file=sys.stderr, flush=True)
         res["burst"] = {"requests": burst, "queue": run_queue(br, arena)[0], "serial": run_serial(br)}
-    # each sampled request solved alone through the batched path must match its served result
+    # each sampled request solved alone, through the path the queue gave it (the batch
+    # engine, or the single-system path from 2^21 cells), must match its served result
     same = 0
     for rid in sorted(kept):
         r = reqs[rid]
         c, bb, x, xx = make(r)
-        s7.bicgstab_solve_batched([r.dims], [c], [bb], [x], [r.rtol], [4000], prec=prec_of[r.mode])
+        if r.dims[0] * r.dims[1] * r.dims[2] >= SPLIT_CELLS:
+            s7.bicgstab_solve(r.dims, c, bb, x, r.rtol, 4000, prec=prec_of[r.mode])
+        else:
+            s7.bicgstab_solve_batched([r.dims], [c], [bb], [x], [r.rtol], [4000], prec=prec_of[r.mode])
         torch.cuda.synchronize()
         same += bool(torch.equal(x, kept[rid]))
     res["alone_vs_mix_identical"] = f"{same}/{len(kept)}"
@@ -285,8 +294,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-slab", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=8)
-    ap.add_argument("--schedule", type=int, default=3, choices=(3, 4),
-                    help="passes per iteration of the single-system solver")
+    ap.add_argument("--schedule", type=int, default=0, choices=(0, 3, 4),
+                    help="passes per iteration of the single-system solver (0: autotuned)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -337,7 +346,7 @@ def main():
 
     def run(prec, iters, rtol=1e-300, profile=0):
         x.zero_()
-        o = s7.default_options(profile=profile, schedule={3: 1, 4: 2}[args.schedule])
+        o = s7.default_options(profile=profile, schedule={0: 0, 3: 1, 4: 2}[args.schedule], tune=1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = s7.bicgstab_solve(dims, coef, b, x, rtol, iters, prec=prec, ws=ws, opt=o)
@@ -351,7 +360,8 @@ def main():
     info, dt = run(s7.FP32, args.steps, profile=1)
     assert info.iters == args.steps, info.as_dict()
     ips = args.steps / dt
-    sched = args.schedule
+    sched = 4 if info.pass_count[SLOT["p2a"]] > 0 else 3  # the schedule the (tuned) solve ran;
+    # the library counts only the passes it launched
     bytes32 = BYTES[("f32", sched)]
     pass_ms = {k: info.pass_ms[SLOT[k]] / max(info.pass_count[SLOT[k]], 1) for k in bytes32}
     dom = max(bytes32, key=lambda k: pass_ms[k])  # the kernel with the largest share of an iteration
@@ -389,7 +399,8 @@ def main():
         run(s7.BF16_IR, args.warmup)
         info16, dt16 = run(s7.BF16_IR, args.steps, profile=1)
         it16 = info16.iters
-        bytes16 = BYTES[("16", sched)]
+        sched16 = 4 if info16.pass_count[SLOT["p2a"]] > 0 else 3
+        bytes16 = BYTES[("16", sched16)]
         p16 = {k: info16.pass_ms[SLOT[k]] / max(info16.pass_count[SLOT[k]], 1) for k in bytes16}
         out["mixed_bf16_ir"] = {
             "iter_per_s": round(it16 / dt16, 3), "inner_iters": it16,

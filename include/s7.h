@@ -109,7 +109,9 @@ typedef struct {
                                there and read back by later processes.  The request queue
                                does not tune: its resident set changes every step, and each
                                request's sums must not depend on it.  0: fixed defaults. */
-    int32_t reserved1;      /* must be 0 */
+    int32_t split_cells;    /* request queue: requests of at least this many cells run on the
+                               single-system path (on a second stream, one at a time) instead of
+                               the batch engine; 0 = 2^21, -1 = never */
     double inner_rtol;      /* IR: inner relative tolerance; 0 = 1e-2 (BF16), 5e-3 (FP16) */
 } s7_options;
 

@@ -6,8 +6,12 @@
 // Execution model (no grid barrier, no fence):
 // * A work item is (system, phase, chunk), where a chunk is `chunk_cells`
 //   consecutive cells of one system.  The phases of an iteration are P1,
-//   P2a, P2b and P3, the same as the single-system path.
-// * Each system owns a 64-bit claim word, (phase sequence << 32) | next chunk.
+//   P2a, P2b and P3, the four-pass schedule of the single-system path.
+//   Around the iteration a job also runs, on the device, its epilogue and
+//   its refinement steps: X (x += scale d), R (the FP64 residual) and I (the
+//   next inner right-hand side), so a job needs the host only to start.
+// * Each system owns a 64-bit claim word, (phase sequence << 32) | next chunk;
+//   the low three bits of the sequence name the phase.
 //   A workgroup claims a chunk with one atomic add, which tells it both the
 //   chunk and the phase it belongs to.  Claims past the last chunk are
 //   ignored.
@@ -48,6 +52,10 @@ struct Bits<bf16> {
 template <>
 struct Bits<f16> {
     using U = uint16_t;
+};
+template <>
+struct Bits<double> {
+    using U = uint64_t;
 };
 
 template <class T>
@@ -108,7 +116,20 @@ struct BSys {
     int tag;
     int budget;  // iterations this system may run in the launch
     int pad;
+    Coef7 cf;    // the caller's FP32 coefficients (residual passes)
+    const double* b;
+    double* x;
 };
+
+// Phases of a job.  An iteration is P1, P2a, P2b, P3.  Around the inner
+// iteration: X (x += scale d), R (FP64 residual b - A x) and, for refinement,
+// I (next inner right-hand side r = r0 = p = d / scale).  A phase sequence
+// number is (count << 3) | kind.
+enum PhaseKind : int { K_P1 = 0, K_P2A = 1, K_P2B = 2, K_P3 = 3, K_X = 4, K_R = 5, K_I = 6, K_FINAL = 7 };
+constexpr int kND[7] = {1, 1, 4, 2, 0, 3, 1};  // sums of each phase
+__host__ __device__ inline uint32_t seq_next(uint32_t seq, int kind) {
+    return (((seq >> 3) + 1u) << 3) | (uint32_t)kind;
+}
 
 template <class T>
 __device__ __forceinline__ SysView<T> as_view(const SysView<float>& v) {
@@ -139,10 +160,10 @@ struct BCtl {
     int32_t pad;
 };
 
-// Restarts a system's phase sequence (a new inner solve begins at P1).
-__global__ void k_ctl_reset(BCtl* ctl) {
+// Restarts a system's phase sequence at phase `kind`.
+__global__ void k_ctl_reset(BCtl* ctl, int kind) {
     if (threadIdx.x == 0) {
-        ctl->claim = 0ull;
+        ctl->claim = (unsigned long long)kind << 32;
         ctl->done_cnt = 0u;
         ctl->budget = 0;
         ctl->active = 0;
@@ -150,8 +171,10 @@ __global__ void k_ctl_reset(BCtl* ctl) {
 }
 
 struct BGlobal {
-    int32_t active;  // systems still active in this launch
-    int32_t error;   // 1: a workgroup gave up waiting
+    int32_t active;       // systems still active in this launch
+    int32_t error;        // 1: a workgroup gave up waiting
+    long long t0;         // wall clock at the arm step
+    long long slice;      // wall-clock ticks after which systems park (0: no limit)
 };
 
 // ---------------------------------------------------------------- chunk work
@@ -172,7 +195,7 @@ __device__ void chunk_p1_b(const SysView<T>& S, int c0, int c1, double (&acc)[kM
             cl[u].own = g < c1;
             pv[u] = cload_nbr(S.p, cl[u]);
             k[u] = load_coefs<T, UNIT>(S.c, cl[u].idx);
-            rh[u] = S.rhat[cl[u].idx];
+            rh[u] = cload(S.rhat + cl[u].idx);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -210,7 +233,7 @@ __device__ void chunk_p2b_b(const SysView<T>& S, int c0, int c1, double (&acc)[k
             cl[u].own = g < c1;
             qv[u] = cload_nbr(S.q, cl[u]);
             k[u] = load_coefs<T, UNIT>(S.c, cl[u].idx);
-            rh[u] = S.rhat[cl[u].idx];
+            rh[u] = cload(S.rhat + cl[u].idx);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -240,19 +263,61 @@ __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, flo
         cstore(S.r + i, rn);
         cstore(S.p + i, pn);
         const double rd = (double)to_f32(rn);
-        acc[0] = fma((double)to_f32(S.rhat[i]), rd, acc[0]);
+        acc[0] = fma((double)to_f32(cload(S.rhat + i)), rd, acc[0]);
         acc[1] = fma(rd, rd, acc[1]);
     }
 }
 
-constexpr int kND[4] = {1, 1, 4, 2};  // dot products of P1, P2a, P2b, P3
+// X: x += scale d in FP64 (x = 0 when zero is set).
+__device__ void chunk_x_b(const SysView<float>& S, double* x, int c0, int c1, double scale, bool zero) {
+    for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads)
+        cstore(x + i, zero ? 0.0 : fma(scale, (double)cload(S.d + i), cload(x + i)));
+}
+
+// R: r = b - A x in FP64 with the caller's coefficients; r_s = r / diag with
+// Jacobi scaling.  write_d: d = fl32(r_s), the next inner right-hand side.
+// Sums: ||b||^2, ||r||^2, max |fl32(r_s)|.
+__device__ void chunk_r_b(const SysView<float>& S, const Coef7& cf, const double* b, const double* x,
+                          int c0, int c1, bool write_d, double (&acc)[kMaxDots]) {
+    for (int g = c0 + (int)threadIdx.x; g < c1; g += kThreads) {
+        const Cell c = cell_at(g, S.m, S.n);
+        const double* px = x + c.idx;
+        const Nbr<double> xv{cload(px), cload(px + c.dw), cload(px + c.de), cload(px + c.ds),
+                             cload(px + c.dn), cload(px + c.db), cload(px + c.dt)};
+        const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
+        const double bi = b[c.idx];
+        const double r0 = bi - apply7<double, float, false, true>(k, xv, c);
+        const double rs = S.unit ? r0 / (double)k.a[0] : r0;
+        const float rf = (float)rs;
+        if (write_d) cstore(S.d + c.idx, rf);
+        acc[0] = fma(bi, bi, acc[0]);
+        acc[1] = fma(r0, r0, acc[1]);
+        acc[2] = fmax(acc[2], (double)fabsf(rf));
+    }
+}
+
+// I: r = r0 = p = fl_T(d * inv_scale), d = 0; sum (r, r).
+template <class T>
+__device__ void chunk_i_b(const SysView<T>& S, int c0, int c1, float inv_scale, double (&acc)[kMaxDots]) {
+    for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads) {
+        const T rt = from_f32<T>(cload(S.d + i) * inv_scale);
+        cstore(S.r + i, rt);
+        cstore(S.rhat + i, rt);
+        cstore(S.p + i, rt);
+        cstore(S.d + i, 0.0f);
+        const double v = (double)to_f32(rt);
+        acc[0] = fma(v, v, acc[0]);
+    }
+}
 
 template <class T>
 __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, int c0, int c1,
-                                          float alpha, float omega, float beta,
+                                          float alpha, float omega, float beta, float inv_scale,
                                           double (&acc)[kMaxDots]) {
     const SysView<T> S = as_view<T>(raw);
-    if (phase == 0) {
+    if (phase == K_I) {
+        chunk_i_b<T>(S, c0, c1, inv_scale, acc);
+    } else if (phase == 0) {
         if (S.unit) chunk_p1_b<T, true>(S, c0, c1, acc);
         else chunk_p1_b<T, false>(S, c0, c1, acc);
     } else if (phase == 1) {
@@ -265,11 +330,72 @@ __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, 
     }
 }
 
+// ---------------------------------------------------------------- job control
+// After the inner iteration stopped (st.done): the FP32 epilogue, or the
+// bookkeeping of one refinement step.  Returns the next phase.
+__device__ int after_inner(State& st) {
+    if (st.trial) return K_FINAL;  // a tuning trial never touches the caller's arrays
+    if (!st.ir) {
+        st.total = st.iter;
+        st.ostatus = st.status;
+        st.oreason = st.reason;
+        st.inner_res = st.res_rec;
+        st.scale = 1.0;
+        st.xzero = st.nbzero;  // b = 0: x = 0
+        return K_X;
+    }
+    st.total += st.iter;
+    st.outer += 1;
+    st.inner_res = st.res_rec;
+    if (st.status == ST_BREAKDOWN && st.iter == 0) {
+        st.ostatus = ST_BREAKDOWN;
+        st.oreason = st.reason;
+        return K_FINAL;
+    }
+    return K_X;
+}
+
+// After the residual pass: the final true residual (FP32 jobs), or the
+// refinement decision (the same rules as the single-system solve).
+__device__ int after_resid(State& st, const double (&tot)[kMaxDots]) {
+    st.bb_true = tot[0];
+    st.rr_true = tot[1];
+    st.rmax = tot[2];
+    if (!st.ir) return K_FINAL;
+    if (tot[0] == 0.0) {
+        st.xzero = 1;
+        st.rel = 0.0;
+        st.ostatus = ST_OK;
+        return K_X;
+    }
+    const double nrel = sqrt(tot[1] / tot[0]);
+    if (!isfinite(nrel)) {
+        st.ostatus = ST_BREAKDOWN;
+        st.oreason = RS_NONFINITE;
+        st.rel = nrel;
+        return K_FINAL;
+    }
+    st.stall = (nrel > 0.5 * st.rel) ? st.stall + 1 : 0;
+    st.rel = nrel;
+    if (nrel <= st.rtol_o) {
+        st.ostatus = ST_OK;
+        return K_FINAL;
+    }
+    if (st.outer >= st.outer_cap || st.total >= st.max_total || st.stall >= 3) {
+        st.ostatus = ST_NOT_CONVERGED;
+        return K_FINAL;
+    }
+    // power-of-two scale: the inner right-hand side has max |.| in (0.5, 1]
+    st.scale = st.rmax > 0.0 ? exp2(ceil(log2(st.rmax))) : 1.0;
+    return K_I;
+}
+
 // ---------------------------------------------------------------- persistent kernel
 __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* glob,
                                                       int nsys, int chunk_cells,
                                                       long long spin_limit) {
-    __shared__ int sh_sys, sh_chunk, sh_seq, sh_last;
+    __shared__ int sh_sys, sh_chunk, sh_last;
+    __shared__ uint32_t sh_seq;
     int s = (int)(blockIdx.x % (unsigned)nsys);
     long long idle = 0;
     for (;;) {
@@ -287,7 +413,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
                     if (c < sys[s].nchunk) {
                         sh_sys = s;
                         sh_chunk = c;
-                        sh_seq = (int)(w >> 32);
+                        sh_seq = (uint32_t)(w >> 32);
                         break;
                     }
                 }
@@ -308,87 +434,138 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
             continue;
         }
         idle = 0;
-        const SysView<float> S = sys[me].S;
-        const int tag = sys[me].tag;
-        const int chunk = sh_chunk, seq = sh_seq, phase = seq & 3;
+        const BSys& B = sys[me];
+        const SysView<float> S = B.S;
+        const int tag = B.tag;
+        const int chunk = sh_chunk;
+        const uint32_t seq = sh_seq;
+        const int kind = (int)(seq & 7u);
         const int c0 = chunk * chunk_cells;
         const int c1 = min(S.n, c0 + chunk_cells);
-        const float alpha = (float)cload_d(&S.st->alpha);
-        const float omega = (float)cload_d(&S.st->omega);
-        const float beta = (float)cload_d(&S.st->beta);
         double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (tag == 0) run_chunk<float>(S, phase, c0, c1, alpha, omega, beta, acc);
-        else if (tag == 1) run_chunk<bf16>(S, phase, c0, c1, alpha, omega, beta, acc);
-        else run_chunk<f16>(S, phase, c0, c1, alpha, omega, beta, acc);
+        if (kind == K_X) {
+            chunk_x_b(S, B.x, c0, c1, cload_d(&S.st->scale), cload_i(&S.st->xzero) != 0);
+        } else if (kind == K_R) {
+            chunk_r_b(S, B.cf, B.b, B.x, c0, c1, cload_i(&S.st->ir) != 0, acc);
+        } else {
+            const float alpha = (float)cload_d(&S.st->alpha);
+            const float omega = (float)cload_d(&S.st->omega);
+            const float beta = (float)cload_d(&S.st->beta);
+            const float inv_scale = kind == K_I ? (float)(1.0 / cload_d(&S.st->scale)) : 1.0f;
+            if (tag == 0) run_chunk<float>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+            else if (tag == 1) run_chunk<bf16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+            else run_chunk<f16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+        }
         // publish this chunk's partials, then count the chunk done
         double bsum[kMaxDots];
-        block_reduce<kMaxDots, 0u>(acc, bsum);
+        if (kind == K_R) block_reduce<kMaxDots, 4u>(acc, bsum);
+        else block_reduce<kMaxDots, 0u>(acc, bsum);
         if (threadIdx.x == 0) {
-            for (int j = 0; j < kND[phase]; ++j) publish(&S.red.part[(size_t)chunk * kMaxDots + j], bsum[j]);
+            for (int j = 0; j < kND[kind]; ++j) publish(&S.red.part[(size_t)chunk * kMaxDots + j], bsum[j]);
             wait_stores();
-            const uint32_t t = __hip_atomic_fetch_add(&sys[me].ctl->done_cnt, 1u, __ATOMIC_RELAXED,
+            const uint32_t t = __hip_atomic_fetch_add(&B.ctl->done_cnt, 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
-            sh_last = (t == (uint32_t)(sys[me].nchunk - 1));
+            sh_last = (t == (uint32_t)(B.nchunk - 1));
         }
         __syncthreads();
         if (!sh_last) continue;
         // this workgroup completes the phase: sum the partials in chunk order
         double tot[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (kND[phase] > 0) sum_range<kMaxDots, 0u, true>(S.red.part, 0, sys[me].nchunk, tot);
+        if (kind == K_R) sum_range<kMaxDots, 4u, true>(S.red.part, 0, B.nchunk, tot);
+        else if (kND[kind] > 0) sum_range<kMaxDots, 0u, true>(S.red.part, 0, B.nchunk, tot);
         if (threadIdx.x == 0) {
             State st;
             state_load(S.st, st);
-            if (phase == 0) tail_p1(&st, reinterpret_cast<double(&)[1]>(tot));
-            if (phase == 1) tail_p2a(&st, reinterpret_cast<double(&)[1]>(tot));
-            if (phase == 2) tail_p2(&st, reinterpret_cast<double(&)[4]>(tot));
-            if (phase == 3) tail_p3(&st, reinterpret_cast<double(&)[2]>(tot));
-            int32_t budget = cload_i(&sys[me].ctl->budget);
-            bool stop = st.done != 0;
-            if (phase == 3 && !stop) {
+            int next = K_FINAL;
+            bool iter_done = false;
+            switch (kind) {
+                case K_P1: tail_p1(&st, reinterpret_cast<double(&)[1]>(tot)); next = K_P2A; break;
+                case K_P2A: tail_p2a(&st, reinterpret_cast<double(&)[1]>(tot)); next = K_P2B; break;
+                case K_P2B: tail_p2(&st, reinterpret_cast<double(&)[4]>(tot)); next = K_P3; break;
+                case K_P3:
+                    tail_p3(&st, reinterpret_cast<double(&)[2]>(tot));
+                    next = K_P1;
+                    iter_done = true;
+                    break;
+                case K_X: next = st.xzero ? K_FINAL : K_R; break;
+                case K_R: next = after_resid(st, tot); break;
+                default: {  // K_I: the next inner solve starts
+                    const int left = st.max_total - st.total;
+                    tail_init(&st, tot[0], tot[0], st.inner_tol, st.inner_cap < left ? st.inner_cap : left);
+                    next = K_P1;
+                }
+            }
+            if ((kind <= K_P3 || kind == K_I) && st.done) next = after_inner(st);
+            int32_t budget = cload_i(&B.ctl->budget);
+            bool stop = next == K_FINAL;
+            if (iter_done && next == K_P1) {
                 budget -= 1;
                 stop = budget <= 0;
             }
+            // time slice: any phase boundary is a resumable point
+            const long long slice = __hip_atomic_load(&glob->slice, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (slice > 0 &&
+                wall_clock64() - __hip_atomic_load(&glob->t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > slice)
+                stop = true;
+            if (next == K_FINAL) st.final = 1;
             state_store(S.st, st);
-            __hip_atomic_store(&sys[me].ctl->done_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            cstore_i(&sys[me].ctl->budget, budget);
+            __hip_atomic_store(&B.ctl->done_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cstore_i(&B.ctl->budget, budget);
+            const uint32_t nseq = seq_next(seq, next == K_FINAL ? K_P1 : next);
             if (stop) {
-                cstore_i(&sys[me].ctl->active, 0);
+                cstore_i(&B.ctl->active, 0);
                 // Park the claim word on the phase to resume, with its chunk counter
                 // already exhausted: a workgroup racing this store claims nothing.  The
                 // next launch's arm step rewinds the counter.
-                const unsigned long long resume = (unsigned long long)(st.done ? seq : seq + 1);
-                __hip_atomic_store(&sys[me].ctl->claim, (resume << 32) | (unsigned)sys[me].nchunk,
+                __hip_atomic_store(&B.ctl->claim, ((unsigned long long)nseq << 32) | (unsigned)B.nchunk,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 wait_stores();
                 __hip_atomic_fetch_add(&glob->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 wait_stores();
-                __hip_atomic_store(&sys[me].ctl->claim, (unsigned long long)(seq + 1) << 32,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&B.ctl->claim, (unsigned long long)nseq << 32, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         __syncthreads();
     }
 }
 
-// Arms a launch: every system that is not done takes part with its own
-// iteration budget; the global count of active systems is set accordingly.
-__global__ __launch_bounds__(kThreads) void k_batched_arm(const BSys* sys, BGlobal* glob, int nsys) {
+// Arms a launch: every job that is not finished takes part with its own
+// iteration budget; the global count of active jobs is set accordingly.  With
+// a time slice, every job parks at its first phase boundary after `slice`
+// wall-clock ticks.  A job
+// whose first inner solve stopped at once (set up by the host, e.g. b = 0)
+// moves on to its epilogue.
+__global__ __launch_bounds__(kThreads) void k_batched_arm(const BSys* sys, BGlobal* glob, int nsys,
+                                                          long long slice) {
     __shared__ int count;
     if (threadIdx.x == 0) count = 0;
     __syncthreads();
     for (int s = threadIdx.x; s < nsys; s += kThreads) {
-        const int done = sys[s].S.st->done;
-        sys[s].ctl->claim &= 0xffffffff00000000ull;  // rewind the chunk counter of the parked phase
-        sys[s].ctl->active = done ? 0 : 1;
+        State* st = sys[s].S.st;
+        bool fin = st->final != 0;
+        uint32_t seq = (uint32_t)(sys[s].ctl->claim >> 32);  // rewinds the chunk counter
+        if (!fin && st->done && (seq & 7u) == (uint32_t)K_P1) {
+            State cp = *st;
+            const int next = after_inner(cp);
+            if (next == K_FINAL) cp.final = 1;
+            *st = cp;
+            fin = cp.final != 0;
+            seq = seq_next(seq, next == K_FINAL ? K_P1 : next);
+        }
+        sys[s].ctl->claim = (unsigned long long)seq << 32;
+        sys[s].ctl->active = fin ? 0 : 1;
         sys[s].ctl->budget = sys[s].budget;
         sys[s].ctl->done_cnt = 0u;
-        if (!done) atomicAdd(&count, 1);
+        if (!fin) atomicAdd(&count, 1);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         glob->active = count;
         glob->error = 0;
+        glob->t0 = wall_clock64();
+        glob->slice = slice;
     }
 }
 

@@ -145,6 +145,11 @@ __device__ __forceinline__ void st4_nt(T* p, const T (&v)[4]) {
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// The caller's seven FP32 coefficient arrays: diag, xm, xp, ym, yp, zm, zp.
+struct Coef7 {
+    const float* c[7];
+};
+
 // ---------------------------------------------------------------- geometry
 // rnx and rplane are 1/nx and 1/(nx ny) rounded to FP64, for the index
 // divisions of cell_at (make_mesh fills them).
@@ -263,6 +268,14 @@ struct State {
     double rmax, scale, pad_d[2];     // max |r_s| of the last residual pass, IR scale
     int32_t iter, max_iter, done, status;
     int32_t reason, half, beta_bad, nbzero;
+    // Jobs of the batch engine run their whole solve on the device: the
+    // refinement loop (or the FP32 epilogue) around the inner iteration.
+    double rtol_o, inner_tol, rel, inner_res;  // requested tolerance, inner tolerance,
+                                               // last true relative residual, last inner residual
+    int32_t total, outer, stall, inner_cap;    // iterations so far, outer steps, stalled steps
+    int32_t outer_cap, max_total, final, ir;   // caps; final: the job is finished; ir: refinement
+    int32_t xzero, ostatus, oreason, trial;    // x = 0 then finish; the job's status and reason;
+                                               // trial: a tuning run, which ends with its iteration
 };
 
 enum : int32_t { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2 };

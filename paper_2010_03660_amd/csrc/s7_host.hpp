@@ -100,9 +100,8 @@ struct EngineJob {
     s7_info info;     // filled when the job is finished
     int finished;     // 1 once info is final
     void* user;       // owner's handle
-    // engine-private progress
-    int stage, tag, nchunk, total, outer, stall, status, reason;
-    double rel, inner_res, scale;
+    // engine-private
+    int stage, tag;
     Layout lo;
     double t_start_ms;
 };
@@ -122,12 +121,13 @@ class BatchEngine {
     BatchEngine& operator=(const BatchEngine&) = delete;
     // Takes part from the next step on; the job's arrays must stay valid until finished.
     int add(EngineJob* job);
-    // Advances every resident job: starts new ones, runs one persistent launch, and
-    // handles refinement steps and epilogues.  In the launch each job runs at most
-    // `epoch_iters` BiCGStab iterations; with epoch_iters <= 0 its budget is what
-    // fits in about `slice_ms` at its size (small systems run many iterations, large
-    // ones few), so one launch takes about slice_ms.  Finished jobs leave the
-    // resident set.  Returns S7_OK or an error.
+    // Advances every resident job: starts new ones, then runs one persistent launch
+    // in which each job continues its solve (iterations, refinement steps and
+    // epilogue all run on the device).  In the launch each job runs at most
+    // `epoch_iters` BiCGStab iterations; with epoch_iters <= 0 every job runs until
+    // `slice_ms` of device wall-clock time have passed, then parks at its next phase
+    // boundary, so one launch takes about slice_ms whatever the sizes.  Finished jobs
+    // leave the resident set with their info filled.  Returns S7_OK or an error.
     int step(int epoch_iters, double slice_ms = 2.0);
     int resident() const { return (int)jobs_.size(); }
     // Picks chunk_cells and the persistent grid for the size class of the resident
@@ -138,7 +138,7 @@ class BatchEngine {
   private:
     int read_states(std::vector<State>& h);
     // Uploads `table` and runs one persistent launch (arm + kernel), then waits for it.
-    int launch(const std::vector<BSys>& table, int epoch_key, int chunk, int grid);
+    int launch(const std::vector<BSys>& table, int epoch_key, int chunk, int grid, long long slice = 0);
     char* tables_;
     int cap_;
     s7_options o_;
@@ -146,6 +146,7 @@ class BatchEngine {
     bool graph_;
     int chunk_;     // cells per work item of the persistent kernel
     int grid_cap_;  // most workgroups of a persistent launch
+    double ticks_per_ms_ = 100000.0;  // device wall clock
     State* host_states_ = nullptr;  // pinned, cap_ entries
     std::vector<EngineJob*> jobs_;
 };

@@ -8,15 +8,18 @@
 // * submit() copies the request descriptor into a FIFO and returns a ticket.
 //   A request whose workspace could never fit in the arena is refused with
 //   S7_ENOMEM.
-// * One serving thread admits requests from the FIFO head while their
-//   workspace fits, then advances every resident request by one engine step:
-//   a persistent launch plus the refinement and epilogue work around it.  In
-//   the launch each request runs the iterations that fit a time slice of
-//   about 2 ms at its size (or a fixed count, if the options set one), so a
-//   small request finishes within a few slices even beside a large one.
-//   Requests that arrive during a step join at the next one, while the others
-//   keep their Krylov state on the device.  A finished request frees its
-//   workspace for the next admission.
+// * The serving thread admits requests from the FIFO head while their
+//   workspace fits.
+//   - Small requests join the batch engine.  Each engine step is one
+//     persistent launch in which every resident request runs its solve
+//     (iterations, refinement steps, epilogue) for a time slice of about 2 ms,
+//     or a fixed number of iterations if the options set one.  Requests that
+//     arrive during a step join at the next one; the others keep their Krylov
+//     state on the device.
+//   - Large requests (split_cells and up) gain nothing from batching and run
+//     best on the single-system path.  A second thread solves them one at a
+//     time on its own stream, concurrently with the engine's launches.
+//   A finished request frees its workspace for the next admission.
 // * poll() never blocks; wait() blocks until the request is done.  A finished
 //   request's result is handed out once, then its ticket is released.
 #include <hip/hip_runtime.h>
@@ -37,7 +40,9 @@ using namespace s7;
 
 namespace {
 
-constexpr double kSliceMs = 2.0;  // target length of one persistent launch
+constexpr double kSliceMs = 2.0;      // target length of one persistent launch
+constexpr int kQueueCapacity = 1024;  // resident engine requests at most
+constexpr long long kSplitCells = 1ll << 21;
 
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
@@ -86,6 +91,7 @@ class Arena {
 struct Req {
     uint64_t ticket;
     EngineJob job;
+    bool big = false;
     size_t off = 0, bytes = 0;
     double t_submit = 0, t_admit = 0;
     bool done = false;
@@ -100,37 +106,65 @@ struct s7_queue {
     int device;
     s7_options opt;
     int epoch_iters;
-    int capacity;
+    long long split_cells;
     Arena heap;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr, big_stream = nullptr;
     std::unique_ptr<BatchEngine> engine;
 
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<Req*> pending;
+    std::condition_variable cv_work, cv_done, cv_big;
+    std::deque<Req*> pending;    // submitted, not admitted
+    std::deque<Req*> big_ready;  // admitted large requests
     std::map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_ticket = 1;
-    bool stop = false;
+    uint64_t gen = 0;  // bumped by every submission and every release
+    bool stop = false, stop_big = false;
     int error = S7_OK;
     std::string error_msg;
-    std::thread worker;
+    std::thread worker, big_worker;
 
-    s7_queue(char* a, size_t ab, size_t tb, int dev, const s7_options& o, int cap)
-        : arena(a), arena_bytes(ab), table_bytes(tb), device(dev), opt(o), capacity(cap),
-          heap(ab - tb) {
+    s7_queue(char* a, size_t ab, size_t tb, int dev, const s7_options& o)
+        : arena(a), arena_bytes(ab), table_bytes(tb), device(dev), opt(o), heap(ab - tb) {
         epoch_iters = o.graph_iters > 0 ? o.graph_iters : 0;  // 0: time slices
+        split_cells = o.split_cells < 0 ? (1ll << 62) : (o.split_cells > 0 ? o.split_cells : kSplitCells);
     }
 
+    // Marks every unfinished request failed with rc and stops both threads (lock held).
+    void fail_all(int rc, std::vector<Req*>& resident) {
+        error = rc;
+        for (Req* r : resident) r->job.info.status = rc, r->done = true;
+        for (Req* r : pending) r->job.info.status = rc, r->done = true;
+        for (Req* r : big_ready) r->job.info.status = rc, r->done = true;
+        pending.clear();
+        big_ready.clear();
+        resident.clear();
+        stop = stop_big = true;
+        cv_done.notify_all();
+        cv_big.notify_all();
+    }
+
+    void finish(Req* r) {  // lock held
+        r->job.info.t_wait_ms = r->t_admit - r->t_submit;
+        r->done = true;
+        heap.release(r->off, r->bytes);
+        ++gen;
+    }
+
+    // The serving thread: admission and the batch engine.
     void run() {
         (void)hipSetDevice(device);
         std::vector<Req*> resident;
+        uint64_t seen = ~0ull;
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return stop || !pending.empty() || !resident.empty(); });
-                if (stop && pending.empty() && resident.empty()) return;
-                // admit from the head of the FIFO while the workspace fits
-                while (!pending.empty() && (int)resident.size() < capacity) {
+                // sleep while there is nothing to run and nothing new could be admitted
+                cv_work.wait(lk, [&] {
+                    return !resident.empty() || (!pending.empty() && gen != seen) ||
+                           (stop && pending.empty());
+                });
+                if (stop && pending.empty() && resident.empty()) break;
+                while (!pending.empty() && (int)resident.size() < kQueueCapacity) {
                     Req* r = pending.front();
                     size_t off;
                     if (!heap.alloc(r->bytes, &off)) break;
@@ -138,36 +172,29 @@ struct s7_queue {
                     r->off = off;
                     r->job.ws = arena + table_bytes + off;
                     r->t_admit = now_ms();
-                    resident.push_back(r);
-                    engine->add(&r->job);
+                    if (r->big) {
+                        big_ready.push_back(r);
+                        cv_big.notify_one();
+                    } else {
+                        resident.push_back(r);
+                        engine->add(&r->job);
+                    }
                 }
+                seen = gen;
             }
-            int rc = resident.empty() ? S7_OK : engine->step(epoch_iters, kSliceMs);
+            if (resident.empty()) continue;
+            const int rc = engine->step(epoch_iters, kSliceMs);
             std::lock_guard<std::mutex> lk(mu);
             if (rc != S7_OK) {
-                error = rc;
                 error_msg = s7_last_error();
-                for (Req* r : resident) {
-                    r->job.info.status = rc;
-                    r->done = true;
-                }
-                for (Req* r : pending) {
-                    r->job.info.status = rc;
-                    r->done = true;
-                }
-                pending.clear();
-                resident.clear();
-                cv_done.notify_all();
-                stop = true;
+                fail_all(rc, resident);
                 return;
             }
             std::vector<Req*> keep;
             bool any = false;
             for (Req* r : resident) {
                 if (r->job.finished) {
-                    r->job.info.t_wait_ms = r->t_admit - r->t_submit;
-                    r->done = true;
-                    heap.release(r->off, r->bytes);
+                    finish(r);
                     any = true;
                 } else {
                     keep.push_back(r);
@@ -176,12 +203,43 @@ struct s7_queue {
             resident.swap(keep);
             if (any) cv_done.notify_all();
         }
+        std::lock_guard<std::mutex> lk(mu);
+        stop_big = true;  // everything admitted: the large-request thread drains and leaves
+        cv_big.notify_all();
+    }
+
+    // The second thread: large requests, one at a time, on the single-system path.
+    void run_big() {
+        (void)hipSetDevice(device);
+        for (;;) {
+            Req* r;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_big.wait(lk, [&] { return !big_ready.empty() || stop_big; });
+                if (big_ready.empty()) return;
+                r = big_ready.front();
+                big_ready.pop_front();
+            }
+            const EngineJob& j = r->job;
+            s7_info info;
+            const int rc = s7_bicgstab_solve(j.d, j.coef, j.b, j.x, j.rtol, j.max_iter, j.prec, j.ws,
+                                             j.ws_bytes, &opt, &info, big_stream);
+            std::lock_guard<std::mutex> lk(mu);
+            if (rc < 0) {
+                if (error == S7_OK) {
+                    error = rc;
+                    error_msg = s7_last_error();
+                }
+                info.status = rc;
+            }
+            info.t_ms = now_ms() - r->t_submit;
+            r->job.info = info;
+            finish(r);
+            cv_done.notify_all();
+            cv_work.notify_one();  // memory came free
+        }
     }
 };
-
-namespace {
-constexpr int kQueueCapacity = 1024;  // resident requests at most
-}
 
 extern "C" {
 
@@ -195,7 +253,6 @@ int s7_queue_create(s7_queue** q, void* arena, size_t arena_bytes, const s7_opti
     }
     s7_options o;
     options_or_default(opt, o);
-    const int cap = kQueueCapacity;
     const size_t tb = s7_queue_table_bytes();
     if (arena_bytes <= tb + 256) {
         set_error("s7_queue_create: arena smaller than the engine tables (%zu bytes)", tb);
@@ -203,16 +260,19 @@ int s7_queue_create(s7_queue** q, void* arena, size_t arena_bytes, const s7_opti
     }
     int dev = 0;
     S7_HIP(hipGetDevice(&dev));
-    s7_queue* Q = new (std::nothrow) s7_queue((char*)arena, arena_bytes, tb, dev, o, cap);
+    s7_queue* Q = new (std::nothrow) s7_queue((char*)arena, arena_bytes, tb, dev, o);
     if (!Q) return S7_EINVAL;
     hipError_t e = hipStreamCreateWithFlags(&Q->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&Q->big_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
+        if (Q->stream) (void)hipStreamDestroy(Q->stream);
         delete Q;
         set_error("s7_queue_create: %s", hipGetErrorString(e));
         return S7_EHIP;
     }
-    Q->engine.reset(new BatchEngine((char*)arena, cap, o, Q->stream));
+    Q->engine.reset(new BatchEngine((char*)arena, kQueueCapacity, o, Q->stream));
     Q->worker = std::thread([Q] { Q->run(); });
+    Q->big_worker = std::thread([Q] { Q->run_big(); });
     *q = Q;
     return S7_OK;
 }
@@ -247,6 +307,7 @@ int s7_queue_submit(s7_queue* q, const s7_request* req, uint64_t* ticket) {
     j.prec = req->prec;
     j.ws_bytes = bytes;
     r->bytes = bytes;
+    r->big = (long long)req->d.nx * req->d.ny * req->d.nz >= q->split_cells;
     r->t_submit = now_ms();
     j.t_start_ms = r->t_submit;
     {
@@ -259,6 +320,7 @@ int s7_queue_submit(s7_queue* q, const s7_request* req, uint64_t* ticket) {
         *ticket = r->ticket;
         q->pending.push_back(r.get());
         q->reqs[r->ticket] = std::move(r);
+        ++q->gen;
     }
     q->cv_work.notify_one();
     return S7_OK;
@@ -299,9 +361,11 @@ int s7_queue_destroy(s7_queue* q) {
         q->stop = true;
     }
     q->cv_work.notify_all();
-    if (q->worker.joinable()) q->worker.join();
+    if (q->worker.joinable()) q->worker.join();  // drains, then releases the large-request thread
+    if (q->big_worker.joinable()) q->big_worker.join();
     const int err = q->error;
     if (q->stream) (void)hipStreamDestroy(q->stream);
+    if (q->big_stream) (void)hipStreamDestroy(q->big_stream);
     delete q;
     return err == S7_OK ? S7_OK : err;
 }

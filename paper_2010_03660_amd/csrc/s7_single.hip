@@ -108,9 +108,6 @@ static SysView<T> make_view(s7_dims d, const Layout& L, int jacobi, char* ws) {
 }
 
 // ============================================================== kernels
-struct Coef7 {
-    const float* c[7];
-};
 
 // Clears the solver state and the reduction counters (a kernel rather than a
 // memset, so that the same clear is valid inside captured graphs).
@@ -567,6 +564,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
             if (info) {
                 for (int j = 0; j < K && j < ran; ++j) {
                     for (int p = 0; p < NP; ++p) {
+                        if (sched == SCHED_THREE && p == 1) continue;  // no P2a in this schedule
                         float ms = 0.f;
                         S7_HIP(hipEventElapsedTime(&ms, ev[(NP + 1) * j + p], ev[(NP + 1) * j + p + 1]));
                         info->pass_ms[p] += ms;
@@ -633,14 +631,19 @@ static int start_solve(const Coef7& cf, const SysView<T>& S, const Layout& Lo, i
 
 // ============================================================== autotuning trials
 // A trial runs iterations on synthetic contents written into the workspace:
-// unit diagonal, off-diagonals -0.15 (row sums 0.1 inside the mesh, so the
-// system is well conditioned), r = r0 = p = 1.  The iteration kernels touch
-// only the workspace, so the caller's arrays are never read or written.
+// unit diagonal, off-diagonals -0.15 with the outward links of boundary cells
+// zeroed (as for real coefficients; row sums 0.1 inside the mesh, so the
+// system is well conditioned), r = r0 = p = 1.  Its State marks it as a trial
+// with tolerance -1: it never converges, and if it stopped anyway (a breakdown)
+// it would end there.  So the caller's arrays are never read or written.
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_tune_fill(SysView<T> S) {
     const T one = from_f32<T>(1.0f), zero = from_f32<T>(0.0f), off = from_f32<T>(-0.15f);
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < S.n; i += gridDim.x * kThreads) {
-        for (int a = S.unit ? 1 : 0; a < 7; ++a) const_cast<T*>(S.c[a])[i] = a == 0 ? one : off;
+        const Cell c = cell_at(i, S.m, S.n);
+        const bool in[7] = {true, c.dw != 0, c.de != 0, c.ds != 0, c.dn != 0, c.db != 0, c.dt != 0};
+        for (int a = S.unit ? 1 : 0; a < 7; ++a)
+            const_cast<T*>(S.c[a])[i] = a == 0 ? one : (in[a] ? off : zero);
         S.r[i] = one;
         S.rhat[i] = one;
         S.p[i] = one;
@@ -656,8 +659,9 @@ __global__ void k_tune_state(State* st, uint32_t* cnt, int n) {
     *st = State{};
     st->rho = (double)n;
     st->nb = sqrt((double)n);
-    st->tol = 0.0;
+    st->tol = -1.0;
     st->max_iter = 1 << 30;
+    st->trial = 1;
     *cnt = 0u;
 }
 
@@ -837,7 +841,9 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
 }
 
 // ============================================================== batch engine
-enum JobStage { J_NEW = 0, J_RESID = 1, J_ITER = 2, J_FINAL = 3, J_DONE = 4 };
+// A job is J_NEW until its first kernels are launched, then J_RUN: the device
+// runs the rest of its solve (iterations, refinement steps, epilogue).
+enum JobStage { J_NEW = 0, J_RUN = 1 };
 
 // Engine tables: [BGlobal][BSys x cap][State* x cap][State x cap].
 static size_t off_sys() { return align256(sizeof(BGlobal)); }
@@ -857,6 +863,10 @@ BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStr
     if (hipHostMalloc((void**)&host_states_, (size_t)capacity * sizeof(State), hipHostMallocDefault) !=
         hipSuccess)
         host_states_ = nullptr;  // read_states reports it
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+        ticks_per_ms_ = (double)khz;
 }
 
 BatchEngine::~BatchEngine() {
@@ -876,12 +886,6 @@ int BatchEngine::add(EngineJob* j) {
     j->lo = make_layout(j->d, j->prec, o_);
     j->stage = J_NEW;
     j->tag = j->prec == S7_FP32 ? 0 : (j->prec == S7_BF16_IR ? 1 : 2);
-    j->total = j->outer = j->stall = 0;
-    j->status = S7_NOT_CONVERGED;
-    j->reason = 0;
-    j->rel = INFINITY;
-    j->inner_res = 0.0;
-    j->scale = 1.0;
     j->finished = 0;
     std::memset(&j->info, 0, sizeof(j->info));
     if (j->t_start_ms <= 0.0) j->t_start_ms = now_ms();
@@ -895,15 +899,27 @@ static int chunk_cells_of(const s7_options& o) {
     return c;
 }
 
-template <class T>
-static int job_view(const EngineJob& j, SysView<T>& S) {
-    S = make_view<T>(j.d, j.lo, 1, j.ws);
-    return S7_OK;
+// The device-side job parameters: refinement (ir), tolerances and caps.
+__global__ void k_job_init(State* st, int ir, double rtol, double inner_tol, int inner_cap,
+                           int outer_cap, int max_total) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    st->ir = ir;
+    st->rtol_o = rtol;
+    st->inner_tol = inner_tol;
+    st->inner_cap = inner_cap;
+    st->outer_cap = outer_cap;
+    st->max_total = max_total;
+    st->rel = INFINITY;
+    st->inner_res = 0.0;
+    st->total = st->outer = st->stall = 0;
+    st->final = st->xzero = 0;
+    st->ostatus = ST_NOT_CONVERGED;
+    st->oreason = RS_NONE;
 }
 
-// Launches the first kernels of a job: state clear, coefficient copies, and
-// either the FP32 r0 (iteration starts next) or the first FP64 residual of the
-// refinement.
+// Launches the first kernels of a job: state clear, coefficient copies, job
+// parameters, and either the FP32 r0 (the iteration starts at P1) or nothing
+// more for refinement (it starts with the FP64 residual phase).
 template <class T>
 static int job_start(EngineJob& j, const s7_options& o, hipStream_t s) {
     SysView<T> S = make_view<T>(j.d, j.lo, o.jacobi, j.ws);
@@ -911,103 +927,40 @@ static int job_start(EngineJob& j, const s7_options& o, hipStream_t s) {
     for (int a = 0; a < 7; ++a) cf.c[a] = j.coef[a];
     int rc = start_solve<T>(cf, S, j.lo, o.jacobi, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl));
+    const bool ir = !std::is_same<T, float>::value;
+    const double inner_tol = o.inner_rtol > 0 ? o.inner_rtol : (j.prec == S7_FP16_IR ? 5e-3 : 1e-2);
+    const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : 100;
+    const int outer_cap = o.outer_max_iter > 0 ? o.outer_max_iter : 30;
+    hipLaunchKernelGGL(k_job_init, dim3(1), dim3(64), 0, s, S.st, ir ? 1 : 0, j.rtol, inner_tol,
+                       inner_cap, outer_cap, j.max_iter);
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl),
+                       ir ? (int)K_R : (int)K_P1);
     if constexpr (std::is_same<T, float>::value) {
         hipLaunchKernelGGL(k_init_f32, dim3(S.cell_blocks), dim3(kThreads), 0, s, cf, j.b, j.x, S,
                            o.jacobi, j.rtol, j.max_iter);
         launch_finish<3, 0u, FIN_INIT>(S.red, S.cell_blocks, S.st, s, j.rtol, j.max_iter);
-        j.stage = J_ITER;
-    } else {
-        rc = resid_launch<T>(cf, j.b, j.x, S.d, S, o.jacobi, s);
-        if (rc) return rc;
-        j.stage = J_RESID;
     }
     S7_CHECK_LAUNCH();
-    return S7_OK;
-}
-
-// Refinement decision after an FP64 residual pass (same rules as the single
-// solve): stop, or start the next inner solve on r / scale.
-template <class T>
-static int job_outer(EngineJob& j, const State& h, const s7_options& o, hipStream_t s) {
-    SysView<T> S = make_view<T>(j.d, j.lo, o.jacobi, j.ws);
-    if (h.bb_true == 0.0) {
-        hipLaunchKernelGGL(k_fill0, dim3(grid_for(S.n)), dim3(kThreads), 0, s, j.x, S.n);
-        j.rel = 0.0;
-        j.status = S7_OK;
-        j.stage = J_DONE;
-        S7_CHECK_LAUNCH();
-        return S7_OK;
-    }
-    const double nrel = sqrt(h.rr_true / h.bb_true);
-    if (!std::isfinite(nrel)) {
-        j.status = S7_BREAKDOWN;
-        j.reason = S7_REASON_NONFINITE;
-        j.rel = nrel;
-        j.stage = J_DONE;
-        return S7_OK;
-    }
-    j.stall = (nrel > 0.5 * j.rel) ? j.stall + 1 : 0;
-    j.rel = nrel;
-    const int outer_cap = o.outer_max_iter > 0 ? o.outer_max_iter : 30;
-    if (j.rel <= j.rtol) {
-        j.status = S7_OK;
-        j.stage = J_DONE;
-        return S7_OK;
-    }
-    if (j.outer >= outer_cap || j.total >= j.max_iter || j.stall >= 3) {
-        j.status = S7_NOT_CONVERGED;
-        j.stage = J_DONE;
-        return S7_OK;
-    }
-    const double inner_tol = o.inner_rtol > 0 ? o.inner_rtol : (j.prec == S7_FP16_IR ? 5e-3 : 1e-2);
-    const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : 100;
-    j.scale = h.rmax > 0 ? exp2(ceil(log2(h.rmax))) : 1.0;
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl));
-    hipLaunchKernelGGL((k_ir_init<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S,
-                       (float)(1.0 / j.scale), inner_tol,
-                       inner_cap < j.max_iter - j.total ? inner_cap : j.max_iter - j.total);
-    S7_CHECK_LAUNCH();
-    j.stage = J_ITER;
-    return S7_OK;
-}
-
-// After an inner solve finished: FP32 -> x update and true residual (final);
-// refinement -> x += scale d and the next residual pass.
-template <class T>
-static int job_inner_done(EngineJob& j, const State& h, const s7_options& o, hipStream_t s) {
-    SysView<T> S = make_view<T>(j.d, j.lo, o.jacobi, j.ws);
-    Coef7 cf;
-    for (int a = 0; a < 7; ++a) cf.c[a] = j.coef[a];
-    if (j.prec == S7_FP32) {
-        j.total = h.iter;
-        j.status = h.status;
-        j.reason = h.reason;
-        j.inner_res = h.res_rec;
-        hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, j.x, S.d, S.n, 1.0, S.st);
-        int rc = resid_launch<T>(cf, j.b, j.x, nullptr, S, o.jacobi, s);
-        if (rc) return rc;
-        j.stage = J_FINAL;
-        return S7_OK;
-    }
-    j.total += h.iter;
-    j.outer += 1;
-    j.inner_res = h.res_rec;
-    if (h.status == S7_BREAKDOWN && h.iter == 0) {
-        j.status = S7_BREAKDOWN;
-        j.reason = h.reason;
-        j.stage = J_DONE;
-        return S7_OK;
-    }
-    hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, j.x, S.d, S.n, j.scale, S.st);
-    int rc = resid_launch<T>(cf, j.b, j.x, S.d, S, o.jacobi, s);
-    if (rc) return rc;
-    j.stage = J_RESID;
+    j.stage = J_RUN;
     return S7_OK;
 }
 
 #define S7_BY_PREC(j, call)                                           \
     ((j).prec == S7_FP32 ? call<float> : ((j).prec == S7_BF16_IR ? call<bf16> : call<f16>))
+
+static void finish_job(EngineJob& j, const State& h) {
+    s7_info& inf = j.info;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.iters = h.total;
+    inf.outer_iters = h.ir ? h.outer : 1;
+    inf.status = h.ostatus;
+    inf.reason = h.oreason;
+    inf.rel_res_rec = h.inner_res;
+    if (h.ir) inf.rel_res_true = h.rel;
+    else inf.rel_res_true = h.bb_true > 0 ? sqrt(h.rr_true / h.bb_true) : 0.0;
+    inf.t_ms = now_ms() - j.t_start_ms;
+    j.finished = 1;
+}
 
 // Every resident job's State, in job order: one gather kernel and one transfer.
 int BatchEngine::read_states(std::vector<State>& h) {
@@ -1029,37 +982,8 @@ int BatchEngine::read_states(std::vector<State>& h) {
     return S7_OK;
 }
 
-// Per-job iteration budget of one launch in time-slice mode: the estimated
-// iteration time is a latency floor (four hand-offs between workgroups) plus
-// the traffic of the iteration at a conservative HBM rate.
-static int slice_budget(const EngineJob& j, double slice_ms) {
-    const double bytes = j.prec == S7_FP32 ? 120.0 : 64.0;
-    const double t_ms = 0.03 + (double)j.lo.n * bytes / 4.0e9;
-    double b = slice_ms / t_ms;
-    if (b < 1.0) b = 1.0;
-    if (b > 4096.0) b = 4096.0;
-    return (int)b;
-}
-
-static void finish_job(EngineJob& j, const State* h) {
-    s7_info& inf = j.info;
-    std::memset(&inf, 0, sizeof(inf));
-    inf.iters = j.total;
-    inf.outer_iters = j.prec == S7_FP32 ? 1 : j.outer;
-    inf.status = j.status;
-    inf.reason = j.reason;
-    inf.rel_res_rec = j.inner_res;
-    if (j.prec == S7_FP32 && h) {
-        inf.rel_res_true = h->bb_true > 0 ? sqrt(h->rr_true / h->bb_true) : 0.0;
-    } else {
-        inf.rel_res_true = j.rel;
-    }
-    inf.t_ms = now_ms() - j.t_start_ms;
-    j.stage = J_DONE;
-    j.finished = 1;
-}
-
-int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk, int grid_cap) {
+int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk, int grid_cap,
+                        long long slice) {
     BGlobal* glob = reinterpret_cast<BGlobal*>(tables_);
     BSys* dsys = reinterpret_cast<BSys*>(tables_ + off_sys());
     S7_HIP(hipMemcpyAsync(dsys, table.data(), table.size() * sizeof(BSys), hipMemcpyHostToDevice, st_));
@@ -1070,7 +994,8 @@ int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk
     if (grid < 1) grid = 1;
     const long long spin_limit = 5000000;
     auto body = [&](hipStream_t cs) {
-        hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys);
+        hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
+                           slice);
         hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
                            chunk, spin_limit);
     };
@@ -1078,7 +1003,7 @@ int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk
     if (graph_) {
         // the table is re-uploaded before every replay, so the key needs only its shape
         std::vector<uintptr_t> key = {0x53u, (uintptr_t)tables_, (uintptr_t)nsys, (uintptr_t)epoch_key,
-                                      (uintptr_t)grid, (uintptr_t)chunk};
+                                      (uintptr_t)grid, (uintptr_t)chunk, (uintptr_t)slice};
         int rc = cached_graph(key, body, &g);
         if (rc) return rc;
         S7_HIP(hipGraphLaunch(g->exec, st_));
@@ -1136,7 +1061,7 @@ int BatchEngine::tune() {
             for (EngineJob* j : jobs_) {
                 if ((rc = S7_BY_PREC(*j, tune_prepare_job)(*j, o_, st_))) break;
                 hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st_,
-                                   reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl));
+                                   reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl), (int)K_P1);
                 BSys b;
                 b.S = make_view<float>(j->d, j->lo, o_.jacobi, j->ws);
                 b.ctl = reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl);
@@ -1144,6 +1069,9 @@ int BatchEngine::tune() {
                 b.tag = j->tag;
                 b.budget = K;
                 b.pad = 0;
+                for (int a = 0; a < 7; ++a) b.cf.c[a] = j->coef[a];
+                b.b = j->b;
+                b.x = j->x;
                 chunks += b.nchunk;
                 table.push_back(b);
             }
@@ -1176,6 +1104,7 @@ int BatchEngine::tune() {
 }
 
 int BatchEngine::step(int epoch_iters, double slice_ms) {
+    if (jobs_.empty()) return S7_OK;
     int rc;
     // 1) start new jobs; the state pointer table follows the resident set
     std::vector<State*> sptr;
@@ -1185,63 +1114,35 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
         rc = S7_BY_PREC(*j, job_start)(*j, o_, st_);
         if (rc) return rc;
     }
-    if (!sptr.empty())
-        S7_HIP(hipMemcpyAsync(tables_ + off_sptr(cap_), sptr.data(), sptr.size() * sizeof(State*),
-                              hipMemcpyHostToDevice, st_));
-    std::vector<State> h;
-    rc = read_states(h);
-    if (rc) return rc;
-    // 2) refinement decisions and inner solves that are already over (trivial starts)
-    for (size_t i = 0; i < jobs_.size(); ++i) {
-        EngineJob* j = jobs_[i];
-        if (j->stage == J_RESID) {
-            rc = S7_BY_PREC(*j, job_outer)(*j, h[i], o_, st_);
-            if (rc) return rc;
-        }
-    }
-    rc = read_states(h);
-    if (rc) return rc;
-    // 3) one persistent launch over every job in an inner solve
+    S7_HIP(hipMemcpyAsync(tables_ + off_sptr(cap_), sptr.data(), sptr.size() * sizeof(State*),
+                          hipMemcpyHostToDevice, st_));
+    // 2) one persistent launch over every resident job
     std::vector<BSys> table;
-    std::vector<EngineJob*> in_launch;
     const int chunk = chunk_;
-    for (size_t i = 0; i < jobs_.size(); ++i) {
-        EngineJob* j = jobs_[i];
-        if (j->stage != J_ITER || h[i].done) continue;
+    for (EngineJob* j : jobs_) {
         BSys b;
-        SysView<float> v = make_view<float>(j->d, j->lo, o_.jacobi, j->ws);
-        b.S = v;
+        b.S = make_view<float>(j->d, j->lo, o_.jacobi, j->ws);
         b.ctl = reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl);
         b.nchunk = (int)((j->lo.n + chunk - 1) / chunk);
         b.tag = j->tag;
-        b.budget = epoch_iters > 0 ? epoch_iters : slice_budget(*j, slice_ms);
+        b.budget = epoch_iters > 0 ? epoch_iters : (1 << 30);
         b.pad = 0;
+        for (int a = 0; a < 7; ++a) b.cf.c[a] = j->coef[a];
+        b.b = j->b;
+        b.x = j->x;
         table.push_back(b);
-        in_launch.push_back(j);
     }
-    if (!table.empty()) {
-        rc = launch(table, epoch_iters, chunk, grid_cap_);
-        if (rc) return rc;
-    }
+    const long long slice = epoch_iters > 0 ? 0 : (long long)(slice_ms * ticks_per_ms_);
+    rc = launch(table, epoch_iters, chunk, grid_cap_, slice);
+    if (rc) return rc;
+    // 3) finished jobs leave
+    std::vector<State> h;
     rc = read_states(h);
     if (rc) return rc;
-    // 4) inner solves that ended
-    for (size_t i = 0; i < jobs_.size(); ++i) {
-        EngineJob* j = jobs_[i];
-        if (j->stage == J_ITER && h[i].done) {
-            rc = S7_BY_PREC(*j, job_inner_done)(*j, h[i], o_, st_);
-            if (rc) return rc;
-        }
-    }
-    rc = read_states(h);
-    if (rc) return rc;
-    // 5) finished jobs leave
     std::vector<EngineJob*> keep;
     for (size_t i = 0; i < jobs_.size(); ++i) {
-        EngineJob* j = jobs_[i];
-        if (j->stage == J_FINAL) finish_job(*j, &h[i]);
-        else if (j->stage == J_DONE) finish_job(*j, nullptr);
-        if (!j->finished) keep.push_back(j);
+        if (h[i].final) finish_job(*jobs_[i], h[i]);
+        else keep.push_back(jobs_[i]);
     }
     jobs_.swap(keep);
     return S7_OK;

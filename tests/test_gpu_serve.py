@@ -211,3 +211,38 @@ def test_served_degenerate_requests(s7):
     assert out[3][0] == s7.OK
     ref = oracle.bicgstab(A2, b2, tol=1e-12, max_iter=1000, jacobi_scaling=False)
     assert rel_err(host(xs[3]), ref.x) <= 1e-6
+
+
+def test_large_requests_take_the_single_system_path(s7):
+    """With split_cells = 20000, requests of at least that many cells run on the
+    single-system path beside the batch engine: each result equals that path's result
+    alone (bit for bit), the small ones equal the batched path alone, and all match the
+    oracle."""
+    import torch
+    probs = [problem(d, seed=700 + i) for i, (d, p) in enumerate(MIX)]
+    coefs, bs, xs = inputs(probs)
+    reqs = [(d, coefs[i], bs[i], xs[i], RTOL[p], 2000, p) for i, (d, p) in enumerate(MIX)]
+    ar = arena(s7, 64 << 20)
+    q = s7.queue_create(ar, opt=s7.default_options(split_cells=20000))
+    try:
+        out = [s7.queue_wait(q, s7.queue_submit(q, *r)) for r in reqs[:1]]  # one alone first
+        out += [s7.queue_wait(q, t) for t in [s7.queue_submit(q, *r) for r in reqs[1:]]]
+    finally:
+        s7.queue_destroy(q)
+    big = 0
+    for i, ((d, prec), (p, A, b), (rc, info)) in enumerate(zip(MIX, probs, out)):
+        assert rc == s7.OK, (i, info.as_dict())
+        ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
+        assert rel_err(host(xs[i]), ref.x) <= (1e-6 if prec == 0 else 1e-7), i
+        x1 = torch.zeros_like(xs[i])
+        if int(np.prod(d)) >= 20000:
+            big += 1
+            i1 = s7.bicgstab_solve(d, coefs[i], bs[i], x1, RTOL[prec], 2000, prec=prec)
+        else:
+            rc1, inf1 = s7.bicgstab_solve_batched([d], [coefs[i]], [bs[i]], [x1], [RTOL[prec]], [2000],
+                                                  prec=prec)
+            i1 = inf1[0]
+        torch.cuda.synchronize()
+        assert np.array_equal(host(x1), host(xs[i])), i
+        assert i1.iters == info.iters, i
+    assert big >= 3

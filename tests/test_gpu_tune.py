@@ -37,6 +37,31 @@ def solve(s7, dims, coef, b, x0, **opt):
     return host(x), info
 
 
+def test_trials_leave_caller_arrays_untouched(s7):
+    """Trials of untuned classes run on synthetic workspace contents: with max_iter = 0
+    the caller's x must come back exactly as x0 (single and batched forms)."""
+    import torch
+    s7, path = s7
+    dims = (128, 128, 64)  # a size class no other test tunes
+    prob, A, b = problem(dims, seed=51)
+    x = torch.full((A.n,), 0.25, dtype=torch.float64, device="cuda")
+    info = s7.bicgstab_solve(dims, coef_dev(prob), dev(b), x, 1e-8, 0, opt=s7.default_options(tune=1))
+    torch.cuda.synchronize()
+    assert info.status == s7.NOT_CONVERGED and info.iters == 0
+    assert bool((x == 0.25).all())
+    shapes = [(50, 50, 50), (20, 20, 20), (10, 10, 10)]
+    probs = [problem(d, seed=52 + i) for i, d in enumerate(shapes)]
+    xs = [torch.full((A.n,), 0.25, dtype=torch.float64, device="cuda") for p, A, b in probs]
+    rc, infos = s7.bicgstab_solve_batched(shapes, [coef_dev(p) for p, A, b in probs],
+                                          [dev(b) for p, A, b in probs], xs, [1e-8] * 3, [0] * 3,
+                                          opt=s7.default_options(tune=1))
+    torch.cuda.synchronize()
+    assert rc == s7.NOT_CONVERGED and all(i.iters == 0 for i in infos)
+    assert all(bool((x == 0.25).all()) for x in xs)
+    text = path.read_text()
+    assert "s7tune1 1 " in text and "s7tune1 2 " in text
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_tuned_single_solve(s7, prec):
     s7, path = s7
