@@ -379,27 +379,33 @@ __device__ __forceinline__ double comb(int j, double a, double b) {
     return ((MAXMASK >> j) & 1u) ? fmax(a, b) : a + b;
 }
 
-// Workgroup sum of acc (fixed butterfly, then waves in order).  out is written
-// in thread 0 only; the other threads' out is left as it was.
+// Workgroup sum of acc, in a fixed order: every thread stores its values in
+// LDS; the first wavefront adds the four values of lane l (threads l, l+64,
+// l+128, l+192, in that order) and reduces the wavefront with DPP.  Only one
+// wavefront of the four runs the DPP sequence.  out is written in thread 0
+// only; the other threads' out is left as it was.
 template <int ND, unsigned MAXMASK>
 __device__ __forceinline__ void block_reduce(double (&acc)[ND], double (&out)[ND]) {
-    __shared__ double sm[kWaves][kMaxDots];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    wave_reduce<ND, MAXMASK>(acc);
-    __syncthreads();
-    if (lane == kWave - 1) {
+    __shared__ double sm[kMaxDots][kThreads];
+    __syncthreads();  // the previous use of sm is over
 #pragma unroll
-        for (int j = 0; j < ND; ++j) sm[wave][j] = acc[j];
-    }
+    for (int j = 0; j < ND; ++j) sm[j][threadIdx.x] = acc[j];
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {
+        double v[ND];
 #pragma unroll
         for (int j = 0; j < ND; ++j) {
-            double v = sm[0][j];
+            double t = sm[j][threadIdx.x];
 #pragma unroll
-            for (int w = 1; w < kWaves; ++w) v = comb<ND, MAXMASK>(j, v, sm[w][j]);
-            out[j] = v;
+            for (int w = 1; w < kWaves; ++w) t = comb<ND, MAXMASK>(j, t, sm[j][threadIdx.x + w * kWave]);
+            v[j] = t;
+        }
+        wave_reduce<ND, MAXMASK>(v);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+            const int lo = __builtin_amdgcn_readlane(__double2loint(v[j]), kWave - 1);
+            const int hi = __builtin_amdgcn_readlane(__double2hiint(v[j]), kWave - 1);
+            if (threadIdx.x == 0) out[j] = __hiloint2double(hi, lo);
         }
     }
 }
