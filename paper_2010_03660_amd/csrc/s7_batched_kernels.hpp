@@ -178,18 +178,19 @@ struct BGlobal {
 };
 
 // ---------------------------------------------------------------- chunk work
-// The cells of chunk c, visited four per thread per step: thread t takes cells
-// base + 256*u + t for u = 0..3.  All loads of a step are issued before any
+// The cells of chunk c, visited kU per thread per step: thread t takes cells
+// base + 256*u + t for u < kU.  All loads of a step are issued before any
 // store.
+constexpr int kU = 4;
 template <class T, bool UNIT>
 __device__ void chunk_p1_b(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += 4 * kThreads) {
-        Cell cl[4];
-        Nbr<T> pv[4];
-        Coefs<T, UNIT> k[4];
-        T rh[4];
+    for (int base = c0; base < c1; base += kU * kThreads) {
+        Cell cl[kU];
+        Nbr<T> pv[kU];
+        Coefs<T, UNIT> k[kU];
+        T rh[kU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kU; ++u) {
             const int g = base + u * kThreads + (int)threadIdx.x;
             cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
             cl[u].own = g < c1;
@@ -198,7 +199,7 @@ __device__ void chunk_p1_b(const SysView<T>& S, int c0, int c1, double (&acc)[kM
             rh[u] = cload(S.rhat + cl[u].idx);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kU; ++u) {
             const T sv = from_f32<T>(apply7<float, T, UNIT, false>(k[u], nbr_f32(pv[u]), cl[u]));
             if (cl[u].own) {
                 cstore(S.s + cl[u].idx, sv);
@@ -221,13 +222,13 @@ __device__ void chunk_p2a_b(const SysView<T>& S, int c0, int c1, float alpha, do
 
 template <class T, bool UNIT>
 __device__ void chunk_p2b_b(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += 4 * kThreads) {
-        Cell cl[4];
-        Nbr<T> qv[4];
-        Coefs<T, UNIT> k[4];
-        T rh[4];
+    for (int base = c0; base < c1; base += kU * kThreads) {
+        Cell cl[kU];
+        Nbr<T> qv[kU];
+        Coefs<T, UNIT> k[kU];
+        T rh[kU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kU; ++u) {
             const int g = base + u * kThreads + (int)threadIdx.x;
             cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
             cl[u].own = g < c1;
@@ -236,7 +237,7 @@ __device__ void chunk_p2b_b(const SysView<T>& S, int c0, int c1, double (&acc)[k
             rh[u] = cload(S.rhat + cl[u].idx);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kU; ++u) {
             const Nbr<float> q = nbr_f32(qv[u]);
             const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k[u], q, cl[u]));
             if (cl[u].own) {
@@ -385,8 +386,15 @@ __device__ int after_resid(State& st, const double (&tot)[kMaxDots]) {
         st.ostatus = ST_NOT_CONVERGED;
         return K_FINAL;
     }
-    // power-of-two scale: the inner right-hand side has max |.| in (0.5, 1]
-    st.scale = st.rmax > 0.0 ? exp2(ceil(log2(st.rmax))) : 1.0;
+    // power-of-two scale 2^ceil(log2 rmax), exactly: the inner right-hand side
+    // has max |.| in (0.5, 1]
+    if (st.rmax > 0.0) {
+        int e;
+        const double m = frexp(st.rmax, &e);  // rmax = m 2^e, m in [0.5, 1)
+        st.scale = ldexp(1.0, m == 0.5 ? e - 1 : e);
+    } else {
+        st.scale = 1.0;
+    }
     return K_I;
 }
 
@@ -396,6 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
                                                       long long spin_limit) {
     __shared__ int sh_sys, sh_chunk, sh_last;
     __shared__ uint32_t sh_seq;
+    __shared__ State sh_state;
     int s = (int)(blockIdx.x % (unsigned)nsys);
     long long idle = 0;
     for (;;) {
@@ -474,7 +483,9 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
         if (kind == K_R) sum_range<kMaxDots, 4u, true>(S.red.part, 0, B.nchunk, tot);
         else if (kND[kind] > 0) sum_range<kMaxDots, 0u, true>(S.red.part, 0, B.nchunk, tot);
         if (threadIdx.x == 0) {
-            State st;
+            // the private state copy lives in LDS: a register copy would raise the
+            // register count of the whole kernel
+            State& st = sh_state;
             state_load(S.st, st);
             int next = K_FINAL;
             bool iter_done = false;

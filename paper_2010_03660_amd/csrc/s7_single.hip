@@ -806,8 +806,14 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
             status = S7_NOT_CONVERGED;
             break;
         }
-        // power-of-two scale: the inner right-hand side has max |.| in (0.5, 1]
-        const double scale = h.rmax > 0 ? exp2(ceil(log2(h.rmax))) : 1.0;
+        // power-of-two scale 2^ceil(log2 rmax), exactly: the inner right-hand side
+        // has max |.| in (0.5, 1]
+        double scale = 1.0;
+        if (h.rmax > 0) {
+            int e;
+            const double m = std::frexp(h.rmax, &e);  // rmax = m 2^e, m in [0.5, 1)
+            scale = std::ldexp(1.0, m == 0.5 ? e - 1 : e);
+        }
         hipLaunchKernelGGL((k_ir_init<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S,
                            (float)(1.0 / scale), inner_tol,
                            inner_cap < max_iter - total ? inner_cap : max_iter - total);
