@@ -296,6 +296,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=8)
     ap.add_argument("--schedule", type=int, default=0, choices=(0, 3, 4),
                     help="passes per iteration of the single-system solver (0: autotuned)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="fixed default launch parameters instead of autotuned ones")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -346,7 +348,8 @@ def main():
 
     def run(prec, iters, rtol=1e-300, profile=0):
         x.zero_()
-        o = s7.default_options(profile=profile, schedule={0: 0, 3: 1, 4: 2}[args.schedule], tune=1)
+        o = s7.default_options(profile=profile, schedule={0: 0, 3: 1, 4: 2}[args.schedule],
+                               tune=0 if args.no_tune else 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = s7.bicgstab_solve(dims, coef, b, x, rtol, iters, prec=prec, ws=ws, opt=o)
