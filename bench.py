@@ -293,7 +293,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-slab", type=int, default=64)
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=48)
     ap.add_argument("--schedule", type=int, default=0, choices=(0, 3, 4),
                     help="passes per iteration of the single-system solver (0: autotuned)")
     ap.add_argument("--no-tune", action="store_true",
