@@ -5,9 +5,10 @@
 //   x-fastest order, so a workgroup covers 256 consecutive cells.  All seven
 //   operand values and the coefficients are loaded straight from memory.  The
 //   neighbour re-reads (x+-1, y+-1, z+-1) are served by L1, L2 and the
-//   Infinity Cache; HBM sees each array about once.  Loads are branch-free:
-//   an off-mesh neighbour reads the cell itself, and a zero coefficient
-//   cancels it.
+//   Infinity Cache.  Arrays read once per pass (coefficients, r0, b) use
+//   non-temporal loads, which leaves the L2 to the stencil operands.  Loads
+//   are branch-free: an off-mesh neighbour reads the cell itself, and a zero
+//   coefficient cancels it.
 // * The BiCGStab passes: P1 (s = A p and (r0,s)), the streaming P2a
 //   (q = r - alpha s and (q,q)), P2b (y = A q and four dots) and the
 //   streaming P3 (x, r and p updates and two dots).
@@ -83,6 +84,7 @@ __device__ __forceinline__ f16 from_f32<f16>(float f) { return (f16)f; }  // RNE
 // r0, and the vectors a pass writes).  The cached path is kept for operands
 // whose halo neighbours re-read them.
 __device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ f16 ld_nt(const f16* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ bf16 ld_nt(const bf16* p) {
     bf16 r;
@@ -233,6 +235,16 @@ __device__ __forceinline__ Coefs<CT, UNIT> load_coefs(const CT* const* c, int id
     Coefs<CT, UNIT> r;
 #pragma unroll
     for (int a = UNIT ? 1 : 0; a < 7; ++a) r.a[a] = c[a][idx];
+    return r;
+}
+
+// The same with non-temporal loads: each coefficient is read once per pass, so
+// it need not take L2 capacity from the stencil operands' neighbour reuse.
+template <class CT, bool UNIT>
+__device__ __forceinline__ Coefs<CT, UNIT> load_coefs_nt(const CT* const* c, int idx) {
+    Coefs<CT, UNIT> r;
+#pragma unroll
+    for (int a = UNIT ? 1 : 0; a < 7; ++a) r.a[a] = ld_nt(c[a] + idx);
     return r;
 }
 
@@ -517,8 +529,8 @@ template <class T, bool UNIT>
 __device__ __forceinline__ void cell_p1(const SysView<T>& S, int g, double (&acc)[1]) {
     const Cell c = cell_at(g, S.m, S.n);
     const Nbr<float> pv = nbr_f32(load_nbr(S.p, c));
-    const Coefs<T, UNIT> k = load_coefs<T, UNIT>(S.c, c.idx);
-    const T rh = S.rhat[c.idx];
+    const Coefs<T, UNIT> k = load_coefs_nt<T, UNIT>(S.c, c.idx);
+    const T rh = ld_nt(S.rhat + c.idx);
     const T sv = from_f32<T>(apply7<float, T, UNIT, false>(k, pv, c));
     if (c.own) S.s[c.idx] = sv;
     acc[0] = c.own ? (double)to_f32(rh) * (double)to_f32(sv) : 0.0;
@@ -562,8 +574,8 @@ template <class T, bool UNIT>
 __device__ __forceinline__ void cell_p2b(const SysView<T>& S, int g, double (&acc)[4]) {
     const Cell c = cell_at(g, S.m, S.n);
     const Nbr<float> qv = nbr_f32(load_nbr(S.q, c));
-    const Coefs<T, UNIT> k = load_coefs<T, UNIT>(S.c, c.idx);
-    const double rh = (double)to_f32(S.rhat[c.idx]);
+    const Coefs<T, UNIT> k = load_coefs_nt<T, UNIT>(S.c, c.idx);
+    const double rh = (double)to_f32(ld_nt(S.rhat + c.idx));
     const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k, qv, c));
     if (c.own) S.y[c.idx] = yt;
     const double yd = c.own ? (double)to_f32(yt) : 0.0;
@@ -583,8 +595,8 @@ __device__ __forceinline__ void cell_p2f(const SysView<T>& S, int g, float alpha
     const Cell c = cell_at(g, S.m, S.n);
     const Nbr<float> rv = nbr_f32(load_nbr(S.r, c));
     const Nbr<float> sv = nbr_f32(load_nbr(S.s, c));
-    const Coefs<T, UNIT> k = load_coefs<T, UNIT>(S.c, c.idx);
-    const double rh = (double)to_f32(S.rhat[c.idx]);
+    const Coefs<T, UNIT> k = load_coefs_nt<T, UNIT>(S.c, c.idx);
+    const double rh = (double)to_f32(ld_nt(S.rhat + c.idx));
     const Nbr<float> qv{fmaT(-alpha, sv.c, rv.c), fmaT(-alpha, sv.w, rv.w), fmaT(-alpha, sv.e, rv.e),
                         fmaT(-alpha, sv.s, rv.s), fmaT(-alpha, sv.n, rv.n), fmaT(-alpha, sv.b, rv.b),
                         fmaT(-alpha, sv.t, rv.t)};

@@ -147,8 +147,8 @@ __global__ __launch_bounds__(kThreads) void k_init_f32(Coef7 cf, const double* b
                                                        int max_iter) {
     const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, S.m, S.n);
     const Nbr<double> xv = load_nbr(x0, c);
-    const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
-    const double bi = b[c.idx];
+    const Coefs<float, false> k = load_coefs_nt<float, false>(cf.c, c.idx);
+    const double bi = ld_nt(b + c.idx);
     const double ax = apply7<double, float, false, true>(k, xv, c);
     double r0 = bi - ax, bs = bi;
     if (jacobi) {
@@ -182,8 +182,8 @@ __global__ __launch_bounds__(kThreads) void k_resid(Coef7 cf, const double* b, c
                                                     State* st, Red red, int jacobi) {
     const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, m, n);
     const Nbr<double> xv = load_nbr(x, c);
-    const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
-    const double bi = b[c.idx];
+    const Coefs<float, false> k = load_coefs_nt<float, false>(cf.c, c.idx);
+    const double bi = ld_nt(b + c.idx);
     const double r0 = bi - apply7<double, float, false, true>(k, xv, c);
     const double rs = jacobi ? r0 / (double)k.a[0] : r0;
     const float rf = (float)rs;
