@@ -23,7 +23,8 @@
  *
  * Memory.  Every array argument is a DEVICE pointer owned by the caller, for
  * example a PyTorch tensor.  The library allocates no device memory of its
- * own.  Scratch comes from a caller-provided workspace of the size that
+ * own (the batch engine keeps a small pinned host buffer for reading its
+ * states).  Scratch comes from a caller-provided workspace of the size that
  * s7_workspace_bytes() reports, 256-byte aligned.
  *
  * Streams.  `stream` is a hipStream_t passed as void*; 0 means the null
@@ -56,7 +57,7 @@ enum s7_status {
                              max_iter < 0, workspace too small or misaligned */
     S7_ENOMEM = -2,       /* request larger than the whole queue arena */
     S7_EHIP = -3,         /* HIP runtime error (message in s7_last_error) */
-    S7_EAGAIN = -4,       /* poll: not finished yet; submit: queue full */
+    S7_EAGAIN = -4,       /* poll: not finished yet */
     S7_ENOTFOUND = -5     /* unknown ticket */
 };
 
@@ -175,7 +176,9 @@ size_t s7_workspace_bytes(s7_dims d, int32_t prec, const s7_options *opt);
  *         aligned.  Its contents are scratch.
  *   opt   NULL for defaults.  info: optional, filled on return.
  * b == 0 gives x = 0, 0 iterations, S7_OK.  max_iter == 0 leaves x = x0 and
- * returns S7_NOT_CONVERGED, unless x0 already meets rtol.
+ * returns S7_NOT_CONVERGED, unless x0 already meets rtol.  The schedule and
+ * the streaming split (options, or autotuned with opt->tune) change only the
+ * order of rounding, not the method.
  */
 int s7_bicgstab_solve(s7_dims d, const float *const coef[7], const double *b, double *x,
                       double rtol, int32_t max_iter, int32_t prec, void *ws, size_t ws_bytes,
@@ -192,9 +195,14 @@ size_t s7_batched_workspace_bytes(int32_t nsys, const s7_dims *d, int32_t prec,
  *   d[s]; coef[7*s + c], device float arrays in the order above; b[s] and x[s],
  *   device doubles; rtol[s]; max_iter[s].
  * info, if not NULL, is an array of nsys and receives each system's result.
- * Each system's iterates depend only on that system and its tile shape, never
- * on the rest of the batch.  Returns the worst status: a negative error, or
- * else the largest of S7_OK, S7_NOT_CONVERGED and S7_BREAKDOWN.
+ * All systems use precision prec.  The whole of each solve runs on the
+ * device: the iterations (four passes each), and the refinement steps or the
+ * FP32 epilogue.  Each system's iterates depend only on that system and on
+ * chunk_cells (the work-item size, which fixes its summation order), never
+ * on the rest of the batch.  With opt->tune = 1 and chunk_cells = 0 the
+ * work-item size and the persistent grid are autotuned per size class.
+ * Returns the worst status: a negative error, or else the largest of S7_OK,
+ * S7_NOT_CONVERGED and S7_BREAKDOWN.
  */
 int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims *d, const float *const *coef,
                               const double *const *b, double *const *x, const double *rtol,
