@@ -40,11 +40,20 @@ BYTES = {
     ("16", 4): {"p1": 18, "p2a": 6, "p2b": 18, "p3": 22},
 }
 SLOT = {"p1": 0, "p2a": 1, "p2": 2, "p2b": 2, "p3": 3}
-KERNEL = {"p1": "k_p1 (P1: s = A p, (r0,s))",
-          "p2": "k_p2f (P2: y = A q with q = r - alpha s formed on the fly, five dot products)",
-          "p2a": "k_p2a (P2a: q = r - alpha s, (q,q))",
-          "p2b": "k_p2 (P2b: y = A q, four dot products)",
-          "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"}
+# s7_info.schedule: 1 three passes, 2 four passes, 3 three passes on cell pairs
+PASSES = {1: 3, 2: 4, 3: 3}
+KERNEL = {
+    1: {"p1": "k_p1 (P1: s = A p, (r0,s))",
+        "p2": "k_p2f (P2: y = A q with q = r - alpha s formed on the fly, five dot products)",
+        "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"},
+    2: {"p1": "k_p1 (P1: s = A p, (r0,s))",
+        "p2a": "k_p2a (P2a: q = r - alpha s, (q,q))",
+        "p2b": "k_p2 (P2b: y = A q, four dot products)",
+        "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"},
+    3: {"p1": "k_p1_pair (P1 on x-adjacent cell pairs: s = A p, (r0,s))",
+        "p2": "k_p2f_pair (P2 on cell pairs: y = A q with q = r - alpha s on the fly, five dot products)",
+        "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"},
+}
 BATCH_BYTES = sum(BYTES[("f32", 4)].values())  # the batched engine runs the four-pass schedule
 SPLIT_CELLS = 1 << 21  # the queue's default: larger requests take the single-system path
 SRC_FILES = ["paper_2010_03660_amd/csrc/s7_device.hpp", "paper_2010_03660_amd/csrc/s7_single.hip"]
@@ -58,15 +67,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(n_cells: int, kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if still current."""
+def traffic_from_profile(n_cells: int, kernel: str, schedule: int):
+    """HBM bytes per launch of pass `kernel` from the committed counter summary, if it was
+    taken on the same schedule and the kernel sources have not changed since."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_paper600x595x1536_traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash() or t.get("cells") != n_cells:
+    if (t.get("source_hash") != kernel_source_hash() or t.get("cells") != n_cells
+            or t.get("schedule") != schedule):
         return None
     return t.get("bytes_per_launch")
 
@@ -363,16 +374,15 @@ def main():
     info, dt = run(s7.FP32, args.steps, profile=1)
     assert info.iters == args.steps, info.as_dict()
     ips = args.steps / dt
-    sched = 4 if info.pass_count[SLOT["p2a"]] > 0 else 3  # the schedule the (tuned) solve ran;
-    # the library counts only the passes it launched
-    bytes32 = BYTES[("f32", sched)]
+    sched = info.schedule  # the schedule the (tuned) solve ran
+    bytes32 = BYTES[("f32", PASSES[sched])]
     pass_ms = {k: info.pass_ms[SLOT[k]] / max(info.pass_count[SLOT[k]], 1) for k in bytes32}
     dom = max(bytes32, key=lambda k: pass_ms[k])  # the kernel with the largest share of an iteration
     dom_gbs = bytes32[dom] * n / (pass_ms[dom] * 1e-3) / 1e9
     iter_bytes = sum(bytes32.values()) * n
     kernel_ms_iter = sum(pass_ms.values())
-    traffic = traffic_from_profile(n, dom)
-    roofline = {"bound": "hbm", "kernel": KERNEL[dom],
+    traffic = traffic_from_profile(n, dom, sched)
+    roofline = {"bound": "hbm", "kernel": KERNEL[sched][dom],
                 "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": bytes32[dom] * n,
@@ -386,7 +396,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded 7-point variable-coefficient recipe, b = A x*)",
         "config": {"workload": f"BiCGStab FP32, one system on the {nx}x{ny}x{nz} mesh",
-                   "cells": n, "jacobi": True, "passes_per_iteration": sched,
+                   "cells": n, "jacobi": True, "schedule": sched, "passes_per_iteration": PASSES[sched],
                    "bytes_per_cell_iteration": sum(bytes32.values()),
                    "timed": "one solve call of `steps` iterations"},
         "gflops": round(44 * n * ips / 1e9, 1),
@@ -402,11 +412,10 @@ def main():
         run(s7.BF16_IR, args.warmup)
         info16, dt16 = run(s7.BF16_IR, args.steps, profile=1)
         it16 = info16.iters
-        sched16 = 4 if info16.pass_count[SLOT["p2a"]] > 0 else 3
-        bytes16 = BYTES[("16", sched16)]
+        bytes16 = BYTES[("16", PASSES[info16.schedule])]
         p16 = {k: info16.pass_ms[SLOT[k]] / max(info16.pass_count[SLOT[k]], 1) for k in bytes16}
         out["mixed_bf16_ir"] = {
-            "iter_per_s": round(it16 / dt16, 3), "inner_iters": it16,
+            "iter_per_s": round(it16 / dt16, 3), "inner_iters": it16, "schedule": info16.schedule,
             "outer_steps": info16.outer_iters,
             "passes_GB/s": {k: round(bytes16[k] * n / (p16[k] * 1e-3) / 1e9, 1) for k in p16},
             "kernel_bytes_per_iter": sum(bytes16.values()) * n,

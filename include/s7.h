@@ -100,7 +100,9 @@ typedef struct {
     int32_t outer_max_iter; /* IR: outer step cap; 0 = 30 */
     int32_t schedule;       /* single-system solve: 1 three passes per iteration (q = r - alpha s
                                formed on the fly where it is used, never stored), 2 four
-                               passes (q stored by a streaming pass); 0 = 1 */
+                               passes (q stored by a streaming pass), 3 three passes whose
+                               stencil passes give each thread two x-adjacent cells (meshes with
+                               an even nx; 1 otherwise); 0 = 3 */
     int32_t tune;           /* 1: the fields left at 0 among schedule and stream_blocks
                                (single solve) and chunk_cells (batched) take autotuned values
                                for the problem's size class.  An untuned class is timed first
@@ -129,6 +131,10 @@ typedef struct {
     double pass_ms[4];   /* profile: summed time of the iteration's kernels P1, P2a, P2b, P3
                             (P1 and P2b include the finishing kernel of a split sum) */
     int32_t pass_count[4];
+    int32_t schedule;    /* single-system solve: the schedule it ran (1 three passes, 2 four
+                            passes, 3 three passes on cell pairs); batched and queue engine
+                            solves: 2 */
+    int32_t reserved;
 } s7_info;
 
 /* Fills *opt with the defaults described above. */

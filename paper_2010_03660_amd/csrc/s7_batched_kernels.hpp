@@ -149,6 +149,7 @@ __device__ __forceinline__ SysView<T> as_view(const SysView<float>& v) {
     o.red = v.red;
     o.cell_blocks = v.cell_blocks;
     o.stream_blocks = v.stream_blocks;
+    o.pair_blocks = v.pair_blocks;
     return o;
 }
 

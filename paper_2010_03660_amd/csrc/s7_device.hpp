@@ -513,6 +513,7 @@ struct SysView {
     Red red;
     int cell_blocks;   // workgroups of the cell-parallel passes: ceil(n / 256)
     int stream_blocks; // workgroups of the streaming pass
+    int pair_blocks;   // workgroups of the paired passes, ceil(n / 512); 0 if nx is odd
 };
 
 // Work split of the streaming pass: chunk b of nb covers a contiguous range
@@ -609,6 +610,136 @@ __device__ __forceinline__ void cell_p2f(const SysView<T>& S, int g, float alpha
     acc[2] = qd * qd;
     acc[3] = rh * qd;
     acc[4] = rh * yd;
+}
+
+// ---------------------------------------------------------------- paired cells
+// For meshes with an even nx, a stencil pass can give each thread two
+// x-adjacent cells (2t, 2t+1) of the flat order.  A pair never crosses a row,
+// and its own values, its y and z neighbours and its coefficients are single
+// 8-byte (FP32) or 4-byte (16-bit) accesses: about half the load instructions
+// of one cell per thread.  Each cell's stencil sum is formed exactly as in the
+// one-cell kernels.
+struct F2 {
+    float a, b;
+};
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ F2 ld2(const float* p) {
+    const f32x2 v = *reinterpret_cast<const f32x2*>(p);
+    return F2{v.x, v.y};
+}
+__device__ __forceinline__ F2 ld2_nt(const float* p) {
+    const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+    return F2{v.x, v.y};
+}
+__device__ __forceinline__ F2 split16(uint32_t u, const bf16*) {
+    return F2{__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u)};
+}
+__device__ __forceinline__ F2 split16(uint32_t u, const f16*) {
+    return F2{(float)__builtin_bit_cast(f16, (uint16_t)(u & 0xffffu)),
+              (float)__builtin_bit_cast(f16, (uint16_t)(u >> 16))};
+}
+template <class T>
+__device__ __forceinline__ F2 ld2(const T* p) {
+    return split16(*reinterpret_cast<const uint32_t*>(p), p);
+}
+template <class T>
+__device__ __forceinline__ F2 ld2_nt(const T* p) {
+    return split16(__builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p)), p);
+}
+__device__ __forceinline__ void st2(float* p, float a, float b) {
+    *reinterpret_cast<f32x2*>(p) = f32x2{a, b};
+}
+__device__ __forceinline__ void st2(bf16* p, bf16 a, bf16 b) {
+    *reinterpret_cast<uint32_t*>(p) = (uint32_t)a.u | ((uint32_t)b.u << 16);
+}
+__device__ __forceinline__ void st2(f16* p, f16 a, f16 b) {
+    *reinterpret_cast<uint32_t*>(p) =
+        (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+
+// Pair gp of the mesh: cells 2gp and 2gp+1.  dw and de are the offsets of the
+// west neighbour of the first cell and the east neighbour of the second (0
+// and 1 at the mesh faces: the cell itself, whose coefficient is zero).
+// Threads past the end take the last pair and own nothing.
+__device__ __forceinline__ Cell cell2_at(int gp, const Mesh& m, int n) {
+    Cell c;
+    const int g0 = 2 * gp;
+    c.own = g0 < n;
+    c.idx = c.own ? g0 : n - 2;
+    const int plane = m.nx * m.ny;
+    const int k = div_rcp(c.idx, plane, m.rplane);
+    const int rem = c.idx - k * plane;
+    const int j = div_rcp(rem, m.nx, m.rnx);
+    const int i = rem - j * m.nx;
+    c.dw = i > 0 ? -1 : 0;
+    c.de = i + 1 < m.nx - 1 ? 2 : 1;
+    c.ds = j > 0 ? -m.nx : 0;
+    c.dn = j < m.ny - 1 ? m.nx : 0;
+    c.db = k > 0 ? -plane : 0;
+    c.dt = k < m.nz - 1 ? plane : 0;
+    return c;
+}
+
+template <class T>
+__device__ __forceinline__ void load_nbr2(const T* v, const Cell& c, Nbr<float>& v0, Nbr<float>& v1) {
+    const T* p = v + c.idx;
+    const F2 ce = ld2(p), s = ld2(p + c.ds), nn = ld2(p + c.dn), b = ld2(p + c.db), t = ld2(p + c.dt);
+    const float w = to_f32(p[c.dw]), e = to_f32(p[c.de]);
+    v0 = Nbr<float>{ce.a, w, ce.b, s.a, nn.a, b.a, t.a};
+    v1 = Nbr<float>{ce.b, ce.a, e, s.b, nn.b, b.b, t.b};
+}
+
+template <class T, bool UNIT>
+__device__ __forceinline__ void load_coefs2_nt(const T* const* c, int idx, Coefs<float, UNIT>& k0,
+                                               Coefs<float, UNIT>& k1) {
+#pragma unroll
+    for (int a = UNIT ? 1 : 0; a < 7; ++a) {
+        const F2 v = ld2_nt(c[a] + idx);
+        k0.a[a] = v.a;
+        k1.a[a] = v.b;
+    }
+}
+
+// P1 on a pair: s = A p and the pair's part of (r0, s).
+template <class T, bool UNIT>
+__device__ __forceinline__ void pair_p1(const SysView<T>& S, const Cell& c, double (&acc)[1]) {
+    Nbr<float> p0, p1;
+    load_nbr2(S.p, c, p0, p1);
+    Coefs<float, UNIT> k0, k1;
+    load_coefs2_nt<T, UNIT>(S.c, c.idx, k0, k1);
+    const F2 rh = ld2_nt(S.rhat + c.idx);
+    const T s0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, p0, c));
+    const T s1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, p1, c));
+    if (c.own) st2(S.s + c.idx, s0, s1);
+    acc[0] = c.own ? fma((double)rh.b, (double)to_f32(s1), (double)rh.a * (double)to_f32(s0)) : 0.0;
+}
+
+// The three-pass P2 on a pair: q = r - alpha s on the fly, y = A q stored;
+// the pair's parts of (q,y), (y,y), (q,q), (r0,q), (r0,y).
+template <class T, bool UNIT>
+__device__ __forceinline__ void pair_p2f(const SysView<T>& S, const Cell& c, float alpha, double (&acc)[5]) {
+    Nbr<float> r0, r1, s0, s1;
+    load_nbr2(S.r, c, r0, r1);
+    load_nbr2(S.s, c, s0, s1);
+    Coefs<float, UNIT> k0, k1;
+    load_coefs2_nt<T, UNIT>(S.c, c.idx, k0, k1);
+    const F2 rh = ld2_nt(S.rhat + c.idx);
+    auto qof = [&](const Nbr<float>& r, const Nbr<float>& s) {
+        return Nbr<float>{fmaT(-alpha, s.c, r.c), fmaT(-alpha, s.w, r.w), fmaT(-alpha, s.e, r.e),
+                          fmaT(-alpha, s.s, r.s), fmaT(-alpha, s.n, r.n), fmaT(-alpha, s.b, r.b),
+                          fmaT(-alpha, s.t, r.t)};
+    };
+    const Nbr<float> q0 = qof(r0, s0), q1 = qof(r1, s1);
+    const T y0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, q0, c));
+    const T y1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, q1, c));
+    if (c.own) st2(S.y + c.idx, y0, y1);
+    const double ya = c.own ? (double)to_f32(y0) : 0.0, yb = c.own ? (double)to_f32(y1) : 0.0;
+    const double qa = c.own ? (double)q0.c : 0.0, qb = c.own ? (double)q1.c : 0.0;
+    acc[0] = fma(qb, yb, qa * ya);
+    acc[1] = fma(yb, yb, ya * ya);
+    acc[2] = fma(qb, qb, qa * qa);
+    acc[3] = fma((double)rh.b, qb, (double)rh.a * qa);
+    acc[4] = fma((double)rh.b, yb, (double)rh.a * ya);
 }
 
 // P3 over one contiguous chunk: d += alpha p + omega q; r = q - omega y;

@@ -104,6 +104,7 @@ static SysView<T> make_view(s7_dims d, const Layout& L, int jacobi, char* ws) {
                 reinterpret_cast<uint32_t*>(ws + L.off_cnt)};
     S.cell_blocks = L.cell_blocks;
     S.stream_blocks = L.stream_blocks;
+    S.pair_blocks = d.nx % 2 == 0 ? (int)((L.n + 2 * kThreads - 1) / (2 * kThreads)) : 0;
     return S;
 }
 
@@ -297,6 +298,26 @@ __global__ __launch_bounds__(kThreads) void k_p2(SysView<T> S) {
 }
 
 template <class T, bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_p1_pair(SysView<T> S) {
+    if (S.st->done) return;
+    double acc[1];
+    pair_p1<T, UNIT>(S, cell2_at(blockIdx.x * kThreads + threadIdx.x, S.m, S.n), acc);
+    double tot[1];
+    if (grid_reduce<1>(acc, S.red, S.pair_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+        tail_p1(S.st, tot);
+}
+
+template <class T, bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_p2f_pair(SysView<T> S) {
+    if (S.st->done) return;
+    double acc[5];
+    pair_p2f<T, UNIT>(S, cell2_at(blockIdx.x * kThreads + threadIdx.x, S.m, S.n), (float)S.st->alpha, acc);
+    double tot[5];
+    if (grid_reduce<5>(acc, S.red, S.pair_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+        tail_p2f(S.st, tot);
+}
+
+template <class T, bool UNIT>
 __global__ __launch_bounds__(kThreads) void k_p2f(SysView<T> S) {
     if (S.st->done) return;
     double acc[5];
@@ -485,11 +506,25 @@ static void launch_finish(const Red& red, int nblocks, State* st, hipStream_t s,
 // finishing kernel of a split sum where one is needed).  The three-pass
 // schedule has no P2a: its pass 2 forms q on the fly, and its P3 forms q again.
 constexpr int kPasses = 4;
-enum Schedule { SCHED_AUTO = 0, SCHED_THREE = 1, SCHED_FOUR = 2 };
+enum Schedule { SCHED_AUTO = 0, SCHED_THREE = 1, SCHED_FOUR = 2, SCHED_PAIRS = 3 };
 
 template <class T>
 static void launch_pass(const SysView<T>& S, int pass, int sched, hipStream_t s) {
-    if (sched == SCHED_THREE) {
+    if (sched == SCHED_PAIRS && S.pair_blocks > 0 && pass != 3) {
+        if (pass == 1) return;
+        const int nb = S.pair_blocks;
+        if (pass == 0) {
+            if (S.unit) hipLaunchKernelGGL((k_p1_pair<T, true>), dim3(nb), dim3(kThreads), 0, s, S);
+            else hipLaunchKernelGGL((k_p1_pair<T, false>), dim3(nb), dim3(kThreads), 0, s, S);
+            launch_finish<1, 0u, FIN_P1>(S.red, nb, S.st, s);
+        } else {
+            if (S.unit) hipLaunchKernelGGL((k_p2f_pair<T, true>), dim3(nb), dim3(kThreads), 0, s, S);
+            else hipLaunchKernelGGL((k_p2f_pair<T, false>), dim3(nb), dim3(kThreads), 0, s, S);
+            launch_finish<5, 0u, FIN_P2F>(S.red, nb, S.st, s);
+        }
+        return;
+    }
+    if (sched == SCHED_THREE || sched == SCHED_PAIRS) {
         if (pass == 1) return;
         if (pass == 2) {
             if (S.unit)
@@ -523,9 +558,17 @@ static void launch_pass(const SysView<T>& S, int pass, int sched, hipStream_t s)
     }
 }
 
-// The schedule of an iteration: the option if set, else the three-pass one.
+// The schedule of an iteration: the option if set, else three passes on cell
+// pairs (which fall back to single cells when nx is odd).
 static int schedule_of(const s7_options& o) {
-    return o.schedule == SCHED_FOUR ? SCHED_FOUR : SCHED_THREE;
+    if (o.schedule == SCHED_THREE || o.schedule == SCHED_FOUR) return o.schedule;
+    return SCHED_PAIRS;
+}
+
+template <class T>
+static int effective_schedule(const s7_options& o, const SysView<T>& S) {
+    const int sc = schedule_of(o);
+    return sc == SCHED_PAIRS && S.pair_blocks == 0 ? SCHED_THREE : sc;
 }
 
 static int read_state(const State* dst, State* host, hipStream_t s) {
@@ -564,7 +607,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
             if (info) {
                 for (int j = 0; j < K && j < ran; ++j) {
                     for (int p = 0; p < NP; ++p) {
-                        if (sched == SCHED_THREE && p == 1) continue;  // no P2a in this schedule
+                        if (sched != SCHED_FOUR && p == 1) continue;  // no P2a in this schedule
                         float ms = 0.f;
                         S7_HIP(hipEventElapsedTime(&ms, ev[(NP + 1) * j + p], ev[(NP + 1) * j + p + 1]));
                         info->pass_ms[p] += ms;
@@ -686,11 +729,12 @@ static int tune_single(s7_dims d, const Layout& Lo, int jacobi, char* ws, hipStr
     S7_HIP(hipEventCreate(&e0));
     S7_HIP(hipEventCreate(&e1));
     float best_ms = INFINITY;
-    best[0] = SCHED_THREE;
+    best[0] = S.pair_blocks > 0 ? SCHED_PAIRS : SCHED_THREE;
     best[1] = stream_blocks_for((long long)Lo.n, 0);
     int rc = S7_OK;
     std::vector<int> tried;
-    for (int sched : {SCHED_THREE, SCHED_FOUR}) {
+    for (int sched : {SCHED_PAIRS, SCHED_THREE, SCHED_FOUR}) {
+        if (sched == SCHED_PAIRS && S.pair_blocks == 0) continue;  // odd nx: same as SCHED_THREE
         for (int cap : {256, 512, 1024}) {
             const int sb = stream_blocks_for((long long)Lo.n, cap);
             const int id = sched * 4096 + sb;
@@ -756,6 +800,7 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
         info->rel_res_rec = h.res_rec;
         info->iters = h.iter;
         info->outer_iters = 1;
+        info->schedule = effective_schedule(o, S);
         info->rel_res_true = h.bb_true > 0 ? sqrt(h.rr_true / h.bb_true) : 0.0;
         info->t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
@@ -839,6 +884,7 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
         info->reason = reason;
         info->iters = total;
         info->outer_iters = outer;
+        info->schedule = effective_schedule(o, S);
         info->rel_res_true = rel;
         info->rel_res_rec = inner_res;
         info->t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -959,6 +1005,7 @@ static void finish_job(EngineJob& j, const State& h) {
     std::memset(&inf, 0, sizeof(inf));
     inf.iters = h.total;
     inf.outer_iters = h.ir ? h.outer : 1;
+    inf.schedule = SCHED_FOUR;
     inf.status = h.ostatus;
     inf.reason = h.oreason;
     inf.rel_res_rec = h.inner_res;

@@ -284,24 +284,27 @@ def test_precisions_share_workspace_without_interference(s7):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_schedules_agree(s7, prec):
-    """Three passes (q formed where it is used) and four passes (q stored) compute the
-    same q in FP32: for FP32 storage the iterates agree to the rounding of the (q,q)
-    sum; both match the oracle."""
+    """Three passes (q formed where it is used), four passes (q stored) and three passes
+    on cell pairs compute the same q in FP32: for FP32 storage the first two agree to
+    the rounding of the (q,q) sum; all match the oracle."""
     dims = (70, 40, 20)
     prob, A, b = problem(dims, seed=21)
     coef = coef_dev(prob)
     bd = dev(b)
     rtol = 1e-8 if prec == 0 else 1e-10
     ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=1000)
-    out = [gpu_solve(s7, dims, coef, bd, rtol=rtol, max_iter=2000, prec=prec, schedule=sc) for sc in (1, 2)]
+    out = [gpu_solve(s7, dims, coef, bd, rtol=rtol, max_iter=2000, prec=prec, schedule=sc) for sc in (1, 2, 3)]
     for x, info in out:
         assert info.status == s7.OK and rel_err(x, ref.x) <= (1e-6 if prec == 0 else 1e-7)
     if prec == 0:
         assert out[0][1].iters == out[1][1].iters
         assert rel_err(out[0][0], out[1][0]) <= 1e-12
+        # pairs: the same stencil sums, dot products rounded in another order
+        assert abs(out[2][1].iters - out[0][1].iters) <= 2
+        assert rel_err(out[2][0], out[0][0]) <= 1e-6
     for k in (1, 2, 5):
         rk = oracle.bicgstab(A, b, tol=1e-300, max_iter=k)
-        for sc in (1, 2):
+        for sc in (1, 2, 3):
             xk, ik = gpu_solve(s7, dims, coef, bd, rtol=1e-300, max_iter=k, schedule=sc)
             assert rel_err(xk, rk.x) <= 1e-4 and abs(ik.rel_res_rec - rk.res_rec) <= 1e-4 * rk.res_rec
 
@@ -343,3 +346,19 @@ def test_paper_mesh_solve_sampled_planes(s7, prec):
         rel = float(np.linalg.norm(rk) / np.linalg.norm(bk))
         assert rel <= res_bound, (k, rel)
         assert rel_err(xk[r0:r1], prob.xstar[r0:r1]) <= 10 * err_bound, k
+
+
+@pytest.mark.parametrize("dims", [(2, 1, 1), (2, 3, 5), (34, 17, 9), (70, 40, 20), (128, 96, 96)])
+@pytest.mark.parametrize("prec", [0, 2])
+def test_paired_schedule_matches_oracle(s7, dims, prec):
+    """Schedule 3 (two x-adjacent cells per thread, for even nx) on small, ragged and
+    split-reduction shapes, FP32 and FP16 with refinement."""
+    prob, A, b = problem(dims, seed=61)
+    ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
+    rtol = 1e-8 if prec == 0 else 1e-10
+    x, info = gpu_solve(s7, dims, coef_dev(prob), b, rtol=rtol, max_iter=2000, prec=prec, schedule=3)
+    assert info.status == s7.OK, info.as_dict()
+    assert rel_err(x, ref.x) <= (1e-6 if prec == 0 else 1e-7)
+    if prec == 0:
+        r8 = oracle.bicgstab(A, b, tol=1e-8, max_iter=2000)
+        assert abs(info.iters - r8.iters) <= max(3, 0.2 * r8.iters)
