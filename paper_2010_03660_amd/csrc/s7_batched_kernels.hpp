@@ -210,6 +210,106 @@ __device__ void chunk_p1_b(const SysView<T>& S, int c0, int c1, double (&acc)[kM
     }
 }
 
+// Coherent loads and stores of two adjacent elements (8 bytes FP32, 4 bytes
+// 16-bit; the first element's index is even).
+__device__ __forceinline__ F2 cload2(const float* p) {
+    const uint64_t u = __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<float*>(p)),
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return F2{__uint_as_float((uint32_t)u), __uint_as_float((uint32_t)(u >> 32))};
+}
+template <class T>
+__device__ __forceinline__ F2 cload2(const T* p) {
+    const uint32_t u = __hip_atomic_load(reinterpret_cast<uint32_t*>(const_cast<T*>(p)), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return split16(u, p);
+}
+__device__ __forceinline__ void cstore2(float* p, float a, float b) {
+    const uint64_t u = (uint64_t)__float_as_uint(a) | ((uint64_t)__float_as_uint(b) << 32);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void cstore2(T* p, T a, T b) {
+    using U = typename Bits<T>::U;
+    const uint32_t u = (uint32_t)__builtin_bit_cast(U, a) | ((uint32_t)__builtin_bit_cast(U, b) << 16);
+    __hip_atomic_store(reinterpret_cast<uint32_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void cload_nbr2(const T* v, const Cell& c, Nbr<float>& v0, Nbr<float>& v1) {
+    const T* p = v + c.idx;
+    const F2 ce = cload2(p), s = cload2(p + c.ds), nn = cload2(p + c.dn), b = cload2(p + c.db),
+             t = cload2(p + c.dt);
+    const float w = to_f32(cload(p + c.dw)), e = to_f32(cload(p + c.de));
+    v0 = Nbr<float>{ce.a, w, ce.b, s.a, nn.a, b.a, t.a};
+    v1 = Nbr<float>{ce.b, ce.a, e, s.b, nn.b, b.b, t.b};
+}
+
+// P1 and P2b of a chunk on x-adjacent cell pairs (systems with an even nx):
+// thread t takes pairs base/2 + 256*u + t for u < kUP.
+constexpr int kUP = 2;
+template <class T, bool UNIT>
+__device__ void chunk_p1_pairs(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
+    for (int base = c0; base < c1; base += 2 * kUP * kThreads) {
+        Cell cl[kUP];
+        Nbr<float> p0[kUP], p1[kUP];
+        Coefs<float, UNIT> k0[kUP], k1[kUP];
+        F2 rh[kUP];
+#pragma unroll
+        for (int u = 0; u < kUP; ++u) {
+            const int gp = base / 2 + u * kThreads + (int)threadIdx.x;
+            const bool in = 2 * gp < c1;
+            cl[u] = cell2_at(in ? gp : S.n / 2 - 1, S.m, S.n);
+            cl[u].own = in;
+            cload_nbr2(S.p, cl[u], p0[u], p1[u]);
+            load_coefs2_nt<T, UNIT>(S.c, cl[u].idx, k0[u], k1[u]);
+            rh[u] = cload2(S.rhat + cl[u].idx);
+        }
+#pragma unroll
+        for (int u = 0; u < kUP; ++u) {
+            const T s0 = from_f32<T>(apply7<float, float, UNIT, false>(k0[u], p0[u], cl[u]));
+            const T s1 = from_f32<T>(apply7<float, float, UNIT, false>(k1[u], p1[u], cl[u]));
+            if (cl[u].own) {
+                cstore2(S.s + cl[u].idx, s0, s1);
+                acc[0] = fma((double)rh[u].b, (double)to_f32(s1), fma((double)rh[u].a, (double)to_f32(s0), acc[0]));
+            }
+        }
+    }
+}
+
+template <class T, bool UNIT>
+__device__ void chunk_p2b_pairs(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
+    for (int base = c0; base < c1; base += 2 * kUP * kThreads) {
+        Cell cl[kUP];
+        Nbr<float> q0[kUP], q1[kUP];
+        Coefs<float, UNIT> k0[kUP], k1[kUP];
+        F2 rh[kUP];
+#pragma unroll
+        for (int u = 0; u < kUP; ++u) {
+            const int gp = base / 2 + u * kThreads + (int)threadIdx.x;
+            const bool in = 2 * gp < c1;
+            cl[u] = cell2_at(in ? gp : S.n / 2 - 1, S.m, S.n);
+            cl[u].own = in;
+            cload_nbr2(S.q, cl[u], q0[u], q1[u]);
+            load_coefs2_nt<T, UNIT>(S.c, cl[u].idx, k0[u], k1[u]);
+            rh[u] = cload2(S.rhat + cl[u].idx);
+        }
+#pragma unroll
+        for (int u = 0; u < kUP; ++u) {
+            const T y0 = from_f32<T>(apply7<float, float, UNIT, false>(k0[u], q0[u], cl[u]));
+            const T y1 = from_f32<T>(apply7<float, float, UNIT, false>(k1[u], q1[u], cl[u]));
+            if (cl[u].own) {
+                cstore2(S.y + cl[u].idx, y0, y1);
+                const double ya = (double)to_f32(y0), yb = (double)to_f32(y1);
+                const double qa = (double)q0[u].c, qb = (double)q1[u].c;
+                const double ra = (double)rh[u].a, rb = (double)rh[u].b;
+                acc[0] = fma(qb, yb, fma(qa, ya, acc[0]));
+                acc[1] = fma(yb, yb, fma(ya, ya, acc[1]));
+                acc[2] = fma(rb, qb, fma(ra, qa, acc[2]));
+                acc[3] = fma(rb, yb, fma(ra, ya, acc[3]));
+            }
+        }
+    }
+}
+
 template <class T>
 __device__ void chunk_p2a_b(const SysView<T>& S, int c0, int c1, float alpha, double (&acc)[kMaxDots]) {
     for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads) {
@@ -320,13 +420,25 @@ __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, 
     if (phase == K_I) {
         chunk_i_b<T>(S, c0, c1, inv_scale, acc);
     } else if (phase == 0) {
-        if (S.unit) chunk_p1_b<T, true>(S, c0, c1, acc);
-        else chunk_p1_b<T, false>(S, c0, c1, acc);
+        if (S.pair_blocks > 0) {
+            if (S.unit) chunk_p1_pairs<T, true>(S, c0, c1, acc);
+            else chunk_p1_pairs<T, false>(S, c0, c1, acc);
+        } else if (S.unit) {
+            chunk_p1_b<T, true>(S, c0, c1, acc);
+        } else {
+            chunk_p1_b<T, false>(S, c0, c1, acc);
+        }
     } else if (phase == 1) {
         chunk_p2a_b<T>(S, c0, c1, alpha, acc);
     } else if (phase == 2) {
-        if (S.unit) chunk_p2b_b<T, true>(S, c0, c1, acc);
-        else chunk_p2b_b<T, false>(S, c0, c1, acc);
+        if (S.pair_blocks > 0) {
+            if (S.unit) chunk_p2b_pairs<T, true>(S, c0, c1, acc);
+            else chunk_p2b_pairs<T, false>(S, c0, c1, acc);
+        } else if (S.unit) {
+            chunk_p2b_b<T, true>(S, c0, c1, acc);
+        } else {
+            chunk_p2b_b<T, false>(S, c0, c1, acc);
+        }
     } else {
         chunk_p3_b<T>(S, c0, c1, alpha, omega, beta, acc);
     }
