@@ -312,7 +312,15 @@ __device__ void chunk_p2b_pairs(const SysView<T>& S, int c0, int c1, double (&ac
 
 template <class T>
 __device__ void chunk_p2a_b(const SysView<T>& S, int c0, int c1, float alpha, double (&acc)[kMaxDots]) {
-    for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads) {
+    const int c1e = c0 + ((c1 - c0) & ~1);  // pairs, then a last odd cell
+    for (int i = c0 + 2 * (int)threadIdx.x; i < c1e; i += 2 * kThreads) {
+        const F2 r = cload2(S.r + i), sv = cload2(S.s + i);
+        const T qa = from_f32<T>(fmaT(-alpha, sv.a, r.a)), qb = from_f32<T>(fmaT(-alpha, sv.b, r.b));
+        cstore2(S.q + i, qa, qb);
+        const double da = (double)to_f32(qa), db = (double)to_f32(qb);
+        acc[0] = fma(db, db, fma(da, da, acc[0]));
+    }
+    for (int i = c1e + (int)threadIdx.x; i < c1; i += kThreads) {
         const float r = to_f32(cload(S.r + i)), s = to_f32(cload(S.s + i));
         const T q = from_f32<T>(fmaT(-alpha, s, r));
         cstore(S.q + i, q);
@@ -356,7 +364,23 @@ __device__ void chunk_p2b_b(const SysView<T>& S, int c0, int c1, double (&acc)[k
 template <class T>
 __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, float omega,
                            float beta, double (&acc)[kMaxDots]) {
-    for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads) {
+    // pairs of cells (c0 is even), then a last odd cell if c1 is odd
+    const int c1e = c0 + ((c1 - c0) & ~1);
+    for (int i = c0 + 2 * (int)threadIdx.x; i < c1e; i += 2 * kThreads) {
+        const F2 d2 = cload2(S.d + i), p2 = cload2(S.p + i), s2 = cload2(S.s + i), y2 = cload2(S.y + i),
+                 q2 = cload2(S.q + i), h2 = cload2(S.rhat + i);
+        float da = d2.a, db = d2.b;
+        T ra, pa, rb, pb;
+        p3_math<T>(alpha, omega, beta, p2.a, s2.a, y2.a, q2.a, da, ra, pa);
+        p3_math<T>(alpha, omega, beta, p2.b, s2.b, y2.b, q2.b, db, rb, pb);
+        cstore2(S.d + i, da, db);
+        cstore2(S.r + i, ra, rb);
+        cstore2(S.p + i, pa, pb);
+        const double xa = (double)to_f32(ra), xb = (double)to_f32(rb);
+        acc[0] = fma((double)h2.b, xb, fma((double)h2.a, xa, acc[0]));
+        acc[1] = fma(xb, xb, fma(xa, xa, acc[1]));
+    }
+    for (int i = c1e + (int)threadIdx.x; i < c1; i += kThreads) {
         float dv = cload(S.d + i);
         T rn, pn;
         p3_math<T>(alpha, omega, beta, to_f32(cload(S.p + i)), to_f32(cload(S.s + i)),
