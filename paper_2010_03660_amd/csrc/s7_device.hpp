@@ -144,6 +144,49 @@ __device__ __forceinline__ void st4_nt(T* p, const T (&v)[4]) {
     __builtin_nontemporal_store(a, reinterpret_cast<u16x4*>(p));
 }
 
+// W consecutive elements as FP32, and back: W = 4 (8- or 16-byte accesses) or
+// W = 8 (16-byte accesses of 16-bit data, two 16-byte accesses of FP32).
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+template <int W, class T>
+__device__ __forceinline__ void ldw_nt(const T* p, float (&v)[W]) {
+    if constexpr (W == 4) {
+        ld4_nt(p, v);
+    } else if constexpr (sizeof(T) == 4) {
+        float a[4], b[4];
+        ld4_nt(p, a);
+        ld4_nt(p + 4, b);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = a[j], v[4 + j] = b[j];
+    } else {
+        const u16x8 a = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(p));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            T t;
+            const uint16_t u = a[j];
+            __builtin_memcpy(&t, &u, 2);
+            v[j] = to_f32(t);
+        }
+    }
+}
+template <int W, class T>
+__device__ __forceinline__ void stw_nt(T* p, const T (&v)[W]) {
+    if constexpr (W == 4) {
+        st4_nt(p, v);
+    } else if constexpr (sizeof(T) == 4) {
+        const T a[4] = {v[0], v[1], v[2], v[3]}, b[4] = {v[4], v[5], v[6], v[7]};
+        st4_nt(p, a);
+        st4_nt(p + 4, b);
+    } else {
+        u16x8 a;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = bits16(v[j]);
+        __builtin_nontemporal_store(a, reinterpret_cast<u16x8*>(p));
+    }
+}
+// Elements per thread and step of the streaming passes: 16-byte accesses.
+template <class T>
+constexpr int kVec = sizeof(T) == 2 ? 8 : 4;
+
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -547,22 +590,23 @@ __device__ __forceinline__ void chunk_p2a(const SysView<T>& S, int b, double (&a
     const T* __restrict__ r = S.r;
     const T* __restrict__ s = S.s;
     T* __restrict__ q = S.q;
-    const int nv = (i1 - i0) / 4;
+    constexpr int W = kVec<T>;
+    const int nv = (i1 - i0) / W;
     for (int v = (int)threadIdx.x; v < nv; v += kThreads) {
-        const int i = i0 + 4 * v;
-        float rv[4], sv[4];
-        ld4_nt(r + i, rv);
-        ld4_nt(s + i, sv);
-        T qv[4];
+        const int i = i0 + W * v;
+        float rv[W], sv[W];
+        ldw_nt<W>(r + i, rv);
+        ldw_nt<W>(s + i, sv);
+        T qv[W];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < W; ++j) {
             qv[j] = from_f32<T>(fmaT(-alpha, sv[j], rv[j]));
             const double qd = (double)to_f32(qv[j]);
             acc[0] = fma(qd, qd, acc[0]);
         }
-        st4_nt(q + i, qv);
+        stw_nt<W>(q + i, qv);
     }
-    for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads) {
+    for (int i = i0 + W * nv + (int)threadIdx.x; i < i1; i += kThreads) {
         const T qv = from_f32<T>(fmaT(-alpha, to_f32(s[i]), to_f32(r[i])));
         q[i] = qv;
         const double qd = (double)to_f32(qv);
@@ -771,33 +815,34 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
     T* __restrict__ r = S.r;
     float* __restrict__ d = S.d;
     double a0 = 0.0, a1 = 0.0;
-    const int nv = (i1 - i0) / 4;
+    constexpr int W = kVec<T>;
+    const int nv = (i1 - i0) / W;
     for (int v = (int)threadIdx.x; v < nv; v += kThreads) {
-        const int i = i0 + 4 * v;
-        float pv[4], sv[4], yv[4], qv[4], hv[4], dv[4];
-        ld4_nt(p + i, pv);
-        ld4_nt(s + i, sv);
-        ld4_nt(y + i, yv);
-        ld4_nt(q + i, qv);
-        ld4_nt(rh + i, hv);
-        ld4_nt(d + i, dv);
+        const int i = i0 + W * v;
+        float pv[W], sv[W], yv[W], qv[W], hv[W], dv[W];
+        ldw_nt<W>(p + i, pv);
+        ldw_nt<W>(s + i, sv);
+        ldw_nt<W>(y + i, yv);
+        ldw_nt<W>(q + i, qv);
+        ldw_nt<W>(rh + i, hv);
+        ldw_nt<W>(d + i, dv);
         if (QR) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) qv[j] = fmaT(-alpha, sv[j], qv[j]);
+            for (int j = 0; j < W; ++j) qv[j] = fmaT(-alpha, sv[j], qv[j]);
         }
-        T rn[4], pn[4];
+        T rn[W], pn[W];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < W; ++j) {
             p3_math<T>(alpha, omega, beta, pv[j], sv[j], yv[j], qv[j], dv[j], rn[j], pn[j]);
             const double rd = (double)to_f32(rn[j]);
             a0 = fma((double)hv[j], rd, a0);
             a1 = fma(rd, rd, a1);
         }
-        st4_nt(d + i, dv);
-        st4_nt(r + i, rn);
-        st4_nt(p + i, pn);
+        stw_nt<W>(d + i, dv);
+        stw_nt<W>(r + i, rn);
+        stw_nt<W>(p + i, pn);
     }
-    for (int i = i0 + 4 * nv + (int)threadIdx.x; i < i1; i += kThreads) {
+    for (int i = i0 + W * nv + (int)threadIdx.x; i < i1; i += kThreads) {
         float dv = d[i];
         T rn, pn;
         const float sv = to_f32(s[i]);
