@@ -9,8 +9,9 @@ scaling, r0 = b - A x0, x update and the FP64 true residual.
 Printed: one JSON line with the metric, the roofline of the dominant kernel, the
 mixed BF16+refinement form, accuracy of converged runs against the manufactured
 solution, the batched form (64 uneven systems), the served form (a Poisson request
-stream through the queue against a serial loop of single solves, p50/p99 latency),
-and the FP64 CPU oracle timed on a bounded slab of the same workload.
+stream through the queue against a serial loop of single solves, p50/p99 latency), the
+solver pattern of the paper's SIMPLE loop (Algorithm 2), and the FP64 CPU oracle timed on
+a bounded slab of the same workload.
 """
 from __future__ import annotations
 
@@ -158,6 +159,51 @@ def batched_leg(s7, torch, dev):
         "max_rel_err_vs_xstar": err,
         "serial_single_solves_s": round(dts, 4), "speedup_vs_serial": round(dts / dt, 2),
     }
+
+
+def simple_leg(s7, torch, dev, dims, outer: int):
+    """The solver pattern of Algorithm 2 (SIMPLE): per outer iteration the momentum
+    systems u, v, w, capped at 5 BiCGStab iterations, then the continuity system, capped
+    at 20; every solve warm-starts from its previous solution.  The three momentum solves
+    go into one batched call, against three single-system calls.  On the paper's
+    100x400x100 momentum mesh (4M cells) the batched call runs each system alone (at
+    least split_cells cells); on a compact mesh they share one persistent launch."""
+    dims = tuple(dims)
+    n = dims[0] * dims[1] * dims[2]
+    coefs, bs, xs = [], [], []
+    for f in range(4):
+        c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(7)]
+        xx = torch.empty(n, dtype=torch.float64, device=dev)
+        bb = torch.empty(n, dtype=torch.float64, device=dev)
+        s7.generate_problem(dims, 2000 + f, 0, c, xx, bb)
+        coefs.append(c), bs.append(bb)
+        xs.append(torch.zeros(n, dtype=torch.float64, device=dev))
+    ws = torch.empty(max(s7.batched_workspace_bytes([dims] * 3), s7.workspace_bytes(dims)),
+                     dtype=torch.uint8, device=dev)
+
+    def run(batched: bool):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(outer):
+            if batched:
+                s7.bicgstab_solve_batched([dims] * 3, coefs[:3], bs[:3], xs[:3], [1e-12] * 3, [5] * 3, ws=ws)
+            else:
+                for f in range(3):
+                    s7.bicgstab_solve(dims, coefs[f], bs[f], xs[f], 1e-12, 5, ws=ws)
+            s7.bicgstab_solve(dims, coefs[3], bs[3], xs[3], 1e-12, 20, ws=ws)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    run(True)
+    run(False)
+    tb, ts = run(True), run(False)
+    return {"workload": f"SIMPLE pattern on {dims[0]}x{dims[1]}x{dims[2]}: u, v, w capped at 5 "
+                        f"iterations, p at 20, "
+                        f"warm-started, {outer} outer iterations",
+            "outer_per_s_batched": round(outer / tb, 2), "outer_per_s_single": round(outer / ts, 2),
+            "us_per_cell_outer_batched": round(tb / outer / n * 1e6, 5)}
 
 
 def served_leg(s7, torch, dev, nreq: int, rate: float, burst: int, arena_gb: float, sample: int):
@@ -311,6 +357,9 @@ def main():
                     help="fixed default launch parameters instead of autotuned ones")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-simple", action="store_true")
+    ap.add_argument("--simple-dims", type=int, nargs=3, default=[100, 400, 100])
+    ap.add_argument("--simple-outer", type=int, default=15)
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the served stream (the full workload is 10000)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -441,6 +490,11 @@ def main():
     if not args.no_batched:
         print("[bench] batched: 64 uneven systems", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(s7, torch, dev)
+        torch.cuda.empty_cache()
+    if not args.no_simple:
+        print("[bench] SIMPLE pattern", file=sys.stderr, flush=True)
+        out["simple_pattern"] = [simple_leg(s7, torch, dev, args.simple_dims, args.simple_outer),
+                                 simple_leg(s7, torch, dev, (40, 40, 40), 4 * args.simple_outer)]
         torch.cuda.empty_cache()
     if not args.no_serve:
         out["served"] = served_leg(s7, torch, dev, args.serve_requests, args.serve_rate,

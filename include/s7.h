@@ -112,9 +112,10 @@ typedef struct {
                                there and read back by later processes.  The request queue
                                does not tune: its resident set changes every step, and each
                                request's sums must not depend on it.  0: fixed defaults. */
-    int32_t split_cells;    /* request queue: requests of at least this many cells run on the
-                               single-system path (on a second stream, one at a time) instead of
-                               the batch engine; 0 = 2^21, -1 = never */
+    int32_t split_cells;    /* systems of at least this many cells run on the single-system
+                               path instead of the batch engine: in the request queue on a
+                               second stream, one at a time; in the batched solve after the
+                               shared launch.  0 = 2^21, -1 = never */
     double inner_rtol;      /* IR: inner relative tolerance; 0 = 1e-2 (BF16), 5e-3 (FP16) */
 } s7_options;
 
@@ -207,6 +208,10 @@ size_t s7_batched_workspace_bytes(int32_t nsys, const s7_dims *d, int32_t prec,
  * chunk_cells (the work-item size, which fixes its summation order), never
  * on the rest of the batch.  With opt->tune = 1 and chunk_cells = 0 the
  * work-item size and the persistent grid are autotuned per size class.
+ * A system of split_cells cells or more (default 2^21) is solved on its own
+ * by the multi-kernel path of s7_bicgstab_solve, in its slice of the
+ * workspace, after the shared launch; its iterates are those of
+ * s7_bicgstab_solve with the same options.
  * Returns the worst status: a negative error, or else the largest of S7_OK,
  * S7_NOT_CONVERGED and S7_BREAKDOWN.
  */

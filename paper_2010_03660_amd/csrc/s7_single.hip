@@ -1355,6 +1355,15 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
     hipStream_t s = (hipStream_t)stream;
     BatchEngine eng(w, nsys, o, s, /*use_graph=*/true);
     std::vector<EngineJob> jobs((size_t)nsys);
+    // A system of split_cells cells or more gains nothing from the shared
+    // launch: its phases already fill the chip, and at thousands of chunks per
+    // phase the claim and completion atomics on its control words, which
+    // serialize, cost more than the pass itself.  It runs alone on the
+    // multi-kernel path, in its own slice of the workspace, after the shared
+    // launch.  The choice depends only on the system's own size, so a system's
+    // result still does not depend on the rest of the batch.
+    const long long split = o.split_cells < 0 ? (1ll << 62) : (o.split_cells > 0 ? o.split_cells : 1ll << 21);
+    std::vector<char> alone((size_t)nsys, 0);
     size_t off = align256(engine_table_bytes(nsys));
     const double t0 = now_ms();
     for (int i = 0; i < nsys; ++i) {
@@ -1371,10 +1380,14 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
         j.ws_bytes = make_layout(d[i], prec, o).bytes;
         j.t_start_ms = t0;
         off += align256(j.ws_bytes);
+        if ((long long)d[i].nx * d[i].ny * d[i].nz >= split) {
+            alone[i] = 1;
+            continue;
+        }
         int rc = eng.add(&j);
         if (rc) return rc;
     }
-    if (o.tune && o.chunk_cells == 0) {
+    if (o.tune && o.chunk_cells == 0 && eng.resident() > 0) {
         int rc = eng.tune();
         if (rc) return rc;
     }
@@ -1386,6 +1399,13 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
             set_error("s7_bicgstab_solve_batched: no progress");
             return S7_EHIP;
         }
+    }
+    for (int i = 0; i < nsys; ++i) {
+        if (!alone[i]) continue;
+        EngineJob& j = jobs[i];
+        const int rc = s7_bicgstab_solve(j.d, j.coef, j.b, j.x, j.rtol, j.max_iter, prec, j.ws, j.ws_bytes,
+                                         &o, &j.info, stream);
+        if (rc < 0) return rc;
     }
     int worst = S7_OK;
     for (int i = 0; i < nsys; ++i) {

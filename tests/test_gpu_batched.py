@@ -151,3 +151,51 @@ def test_batch_workload_64_systems(s7):
         p, A, b = problem(shapes[k], seed=seeds[k])
         ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
         assert rel_err(host(xs[k]), ref.x) <= 1e-5
+
+
+def test_simple_pattern_warm_started(s7):
+    """The application pattern of Algorithm 2 (SIMPLE): per outer iteration, the three
+    momentum systems u, v, w in one batched call capped at 5 iterations, then the
+    continuity system capped at 20, each warm-started from its previous solution.  Three
+    outer iterations, each result checked against the oracle running the same capped,
+    warm-started solves in FP64."""
+    import torch
+    dims = (32, 24, 20)
+    probs = [problem(dims, seed=900 + f) for f in range(4)]  # u, v, w, p
+    coefs = [coef_dev(p) for p, A, b in probs]
+    bs = [dev(b) for p, A, b in probs]
+    xs = [torch.zeros(A.n, dtype=torch.float64, device="cuda") for p, A, b in probs]
+    xo = [np.zeros(A.n) for p, A, b in probs]
+    for it in range(3):
+        rc, infos = s7.bicgstab_solve_batched([dims] * 3, coefs[:3], bs[:3], xs[:3], [1e-12] * 3, [5] * 3)
+        info_p = s7.bicgstab_solve(dims, coefs[3], bs[3], xs[3], 1e-12, 20)
+        torch.cuda.synchronize()
+        assert all(i.iters == 5 for i in infos) and info_p.iters == 20
+        for f, (p, A, b) in enumerate(probs):
+            ref = oracle.bicgstab(A, b, x0=xo[f], tol=1e-12, max_iter=5 if f < 3 else 20)
+            xo[f] = ref.x
+            assert rel_err(host(xs[f]), ref.x) <= 1e-4, (it, f)
+
+
+def test_large_systems_run_alone(s7):
+    """Systems of split_cells cells or more leave the shared launch for the multi-kernel
+    path: each comes out bit for bit as from bicgstab_solve, and the systems left in the
+    shared launch come out as in a batch that routes nothing."""
+    import torch
+    shapes = [(24, 32, 48), (40, 24, 20), (17, 5, 9), (48, 40, 24)]  # 36864, 19200, 765, 46080 cells
+    probs = make_batch(shapes, [300 + i for i in range(4)])
+    rc, infos, xs = run_batch(s7, shapes, probs, rtol=1e-8, split_cells=20000)
+    rc0, infos0, xs0 = run_batch(s7, shapes, probs, rtol=1e-8, split_cells=-1)
+    assert rc == s7.OK and rc0 == s7.OK
+    for k in (1, 2):
+        assert np.array_equal(xs[k], xs0[k]) and infos[k].iters == infos0[k].iters
+    for k in (0, 3):
+        p, A, b = probs[k]
+        x1 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        info1 = s7.bicgstab_solve(shapes[k], coef_dev(p), dev(b), x1, 1e-8, 1000,
+                                  opt=s7.default_options(split_cells=20000))
+        torch.cuda.synchronize()
+        assert np.array_equal(host(x1), xs[k]) and info1.iters == infos[k].iters
+        assert infos[k].schedule == info1.schedule
+        ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+        assert rel_err(xs[k], ref.x) <= 1e-6
