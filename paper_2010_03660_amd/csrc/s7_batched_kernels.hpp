@@ -546,25 +546,28 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
     long long idle = 0;
     for (;;) {
         if (threadIdx.x == 0) {
+            // Each probe is a round trip to memory: the system's flag and claim
+            // word are loaded together, and the launch-wide words are read only
+            // when no system has work.
             sh_sys = -1;
-            if (cload_i(&glob->active) > 0 && cload_i(&glob->error) == 0) {
-                for (int tries = 0; tries < nsys; ++tries, s = (s + 1 == nsys) ? 0 : s + 1) {
-                    if (!cload_i(&sys[s].ctl->active)) continue;
-                    const unsigned long long w0 = __hip_atomic_load(
-                        &sys[s].ctl->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if ((int)(w0 & 0xffffffffull) >= sys[s].nchunk) continue;
-                    const unsigned long long w = __hip_atomic_fetch_add(
-                        &sys[s].ctl->claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const int c = (int)(w & 0xffffffffull);
-                    if (c < sys[s].nchunk) {
-                        sh_sys = s;
-                        sh_chunk = c;
-                        sh_seq = (uint32_t)(w >> 32);
-                        break;
-                    }
+            for (int tries = 0; tries < nsys; ++tries, s = (s + 1 == nsys) ? 0 : s + 1) {
+                const int act = cload_i(&sys[s].ctl->active);
+                const unsigned long long w0 =
+                    __hip_atomic_load(&sys[s].ctl->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!act || (int)(w0 & 0xffffffffull) >= sys[s].nchunk) continue;
+                const unsigned long long w = __hip_atomic_fetch_add(
+                    &sys[s].ctl->claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int c = (int)(w & 0xffffffffull);
+                if (c < sys[s].nchunk) {
+                    sh_sys = s;
+                    sh_chunk = c;
+                    sh_seq = (uint32_t)(w >> 32);
+                    break;
                 }
-            } else {
-                sh_sys = -2;  // nothing left in this launch
+            }
+            if (sh_sys == -1) {
+                const int live = cload_i(&glob->active), err = cload_i(&glob->error);
+                if (live <= 0 || err != 0) sh_sys = -2;  // nothing left in this launch
             }
         }
         __syncthreads();
