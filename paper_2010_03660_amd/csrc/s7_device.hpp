@@ -701,6 +701,18 @@ __device__ __forceinline__ void st2(f16* p, f16 a, f16 b) {
         (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
 
+// Non-temporal pair stores, for stencil-pass outputs: nothing reads them back
+// from the L2 within the pass, so they should not displace the neighbour planes.
+__device__ __forceinline__ void st2_nt(float* p, float a, float b) {
+    __builtin_nontemporal_store(f32x2{a, b}, reinterpret_cast<f32x2*>(p));
+}
+template <class T>
+__device__ __forceinline__ void st2_nt(T* p, T a, T b) {
+    using U = uint16_t;
+    __builtin_nontemporal_store((uint32_t)__builtin_bit_cast(U, a) | ((uint32_t)__builtin_bit_cast(U, b) << 16),
+                                reinterpret_cast<uint32_t*>(p));
+}
+
 // Pair gp of the mesh: cells 2gp and 2gp+1.  dw and de are the offsets of the
 // west neighbour of the first cell and the east neighbour of the second (0
 // and 1 at the mesh faces: the cell itself, whose coefficient is zero).
@@ -754,7 +766,7 @@ __device__ __forceinline__ void pair_p1(const SysView<T>& S, const Cell& c, doub
     const F2 rh = ld2_nt(S.rhat + c.idx);
     const T s0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, p0, c));
     const T s1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, p1, c));
-    if (c.own) st2(S.s + c.idx, s0, s1);
+    if (c.own) st2_nt(S.s + c.idx, s0, s1);
     acc[0] = c.own ? fma((double)rh.b, (double)to_f32(s1), (double)rh.a * (double)to_f32(s0)) : 0.0;
 }
 
@@ -776,7 +788,7 @@ __device__ __forceinline__ void pair_p2f(const SysView<T>& S, const Cell& c, flo
     const Nbr<float> q0 = qof(r0, s0), q1 = qof(r1, s1);
     const T y0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, q0, c));
     const T y1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, q1, c));
-    if (c.own) st2(S.y + c.idx, y0, y1);
+    if (c.own) st2_nt(S.y + c.idx, y0, y1);
     const double ya = c.own ? (double)to_f32(y0) : 0.0, yb = c.own ? (double)to_f32(y1) : 0.0;
     const double qa = c.own ? (double)q0.c : 0.0, qb = c.own ? (double)q1.c : 0.0;
     acc[0] = fma(qb, yb, qa * ya);
