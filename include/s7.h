@@ -90,8 +90,8 @@ typedef struct {
                                iterated matrix has a unit diagonal (section IV,
                                first paragraph); 0: iterate on A as given */
     int32_t graph_iters;    /* iterations per captured hipGraph launch; 0 = auto */
-    int32_t stream_blocks;  /* workgroups of the streaming pass; 0 = auto (at most 1024);
-                               capped at 4096 */
+    int32_t stream_blocks;  /* workgroups of the streaming passes; 0 = auto (at most 256);
+                               capped at 1024 */
     int32_t chunk_cells;    /* batched/queue: cells per work item of the persistent
                                kernel (multiple of 256); 0 = 4096 */
     int32_t profile;        /* 1: launch without graphs, time every pass with HIP

@@ -561,12 +561,6 @@ struct SysView {
 
 // Work split of the streaming pass: chunk b of nb covers a contiguous range
 // aligned to 8 elements, so vector loads stay aligned.
-__host__ __device__ inline void stream_range(int n, int nb, int b, int& i0, int& i1) {
-    const int n8 = (n + 7) / 8;
-    const int per = (n8 + nb - 1) / nb;
-    i0 = min(n, b * per * 8);
-    i1 = min(n, (b + 1) * per * 8);
-}
 
 // P1 at one cell: s = A p; partial (r0, s).
 template <class T, bool UNIT>
@@ -580,20 +574,18 @@ __device__ __forceinline__ void cell_p1(const SysView<T>& S, int g, double (&acc
     acc[0] = c.own ? (double)to_f32(rh) * (double)to_f32(sv) : 0.0;
 }
 
-// P2a over one contiguous chunk: q = r - alpha s, rounded to the storage type;
-// partial (q, q) of the rounded q, for the half-step test.
+// P2a, workgroup b of the streaming grid: q = r - alpha s, rounded to the
+// storage type; partial (q, q) of the rounded q, for the half-step test.
 template <class T>
 __device__ __forceinline__ void chunk_p2a(const SysView<T>& S, int b, double (&acc)[1]) {
-    int i0, i1;
-    stream_range(S.n, S.stream_blocks, b, i0, i1);
     const float alpha = (float)S.st->alpha;
     const T* __restrict__ r = S.r;
     const T* __restrict__ s = S.s;
     T* __restrict__ q = S.q;
     constexpr int W = kVec<T>;
-    const int nv = (i1 - i0) / W;
-    for (int v = (int)threadIdx.x; v < nv; v += kThreads) {
-        const int i = i0 + W * v;
+    const int nv = S.n / W, step = S.stream_blocks * kThreads;
+    for (int v = b * kThreads + (int)threadIdx.x; v < nv; v += step) {
+        const int i = W * v;
         float rv[W], sv[W];
         ldw_nt<W>(r + i, rv);
         ldw_nt<W>(s + i, sv);
@@ -606,7 +598,7 @@ __device__ __forceinline__ void chunk_p2a(const SysView<T>& S, int b, double (&a
         }
         stw_nt<W>(q + i, qv);
     }
-    for (int i = i0 + W * nv + (int)threadIdx.x; i < i1; i += kThreads) {
+    for (int i = W * nv + b * kThreads + (int)threadIdx.x; i < S.n; i += step) {
         const T qv = from_f32<T>(fmaT(-alpha, to_f32(s[i]), to_f32(r[i])));
         q[i] = qv;
         const double qd = (double)to_f32(qv);
@@ -798,12 +790,12 @@ __device__ __forceinline__ void pair_p2f(const SysView<T>& S, const Cell& c, flo
     acc[4] = fma((double)rh.b, yb, (double)rh.a * ya);
 }
 
-// P3 over one contiguous chunk: d += alpha p + omega q; r = q - omega y;
-// p = r + beta (p - omega s).  Accumulates (r0, r_{i+1}) and (r_{i+1}, r_{i+1}).
-// In place is safe: every cell reads and writes only itself.  Four consecutive
-// cells per thread and step, with 16-byte (FP32) or 8-byte (16-bit)
-// non-temporal accesses.  Chunk bounds are multiples of 8 cells except at the
-// end of the array; the last chunk's tail is scalar.
+// P3, workgroup b of the streaming grid: d += alpha p + omega q;
+// r = q - omega y; p = r + beta (p - omega s).  Accumulates (r0, r_{i+1}) and
+// (r_{i+1}, r_{i+1}).  In place is safe: every cell reads and writes only
+// itself.  Each thread takes kVec<T> consecutive cells per step (16-byte
+// non-temporal accesses), and the grid strides over the arrays; the last
+// n mod kVec<T> cells are scalar.
 template <class T>
 __device__ __forceinline__ void p3_math(float alpha, float omega, float beta, float pv, float sv,
                                         float yv, float qv, float& dv, T& rn, T& pn) {
@@ -816,8 +808,6 @@ __device__ __forceinline__ void p3_math(float alpha, float omega, float beta, fl
 // instead of being read.
 template <class T, bool QR>
 __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&acc)[2]) {
-    int i0, i1;
-    stream_range(S.n, S.stream_blocks, b, i0, i1);
     const float alpha = (float)S.st->alpha, omega = (float)S.st->omega, beta = (float)S.st->beta;
     T* __restrict__ p = S.p;
     const T* __restrict__ s = S.s;
@@ -828,9 +818,9 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
     float* __restrict__ d = S.d;
     double a0 = 0.0, a1 = 0.0;
     constexpr int W = kVec<T>;
-    const int nv = (i1 - i0) / W;
-    for (int v = (int)threadIdx.x; v < nv; v += kThreads) {
-        const int i = i0 + W * v;
+    const int nv = S.n / W, step = S.stream_blocks * kThreads;
+    for (int v = b * kThreads + (int)threadIdx.x; v < nv; v += step) {
+        const int i = W * v;
         float pv[W], sv[W], yv[W], qv[W], hv[W], dv[W];
         ldw_nt<W>(p + i, pv);
         ldw_nt<W>(s + i, sv);
@@ -854,7 +844,7 @@ __device__ __forceinline__ void chunk_p3(const SysView<T>& S, int b, double (&ac
         stw_nt<W>(r + i, rn);
         stw_nt<W>(p + i, pn);
     }
-    for (int i = i0 + W * nv + (int)threadIdx.x; i < i1; i += kThreads) {
+    for (int i = W * nv + b * kThreads + (int)threadIdx.x; i < S.n; i += step) {
         float dv = d[i];
         T rn, pn;
         const float sv = to_f32(s[i]);

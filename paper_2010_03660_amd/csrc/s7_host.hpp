@@ -42,13 +42,15 @@ inline size_t elt_size(int prec) { return prec == S7_FP32 ? 4 : 2; }
 
 inline int cell_blocks_for(long long n) { return (int)((n + kThreads - 1) / kThreads); }
 
-// Workgroups of the streaming pass: at most 1024 by default (mixed read/write
-// streams reach a higher HBM rate with fewer concurrent streams), at least
-// one per 2048 cells.
+// Workgroups of the streaming passes: at most 256 by default, at least one per
+// 2048 cells.  The grid strides over the arrays in tiles of kThreads vector
+// accesses, so all workgroups sweep the same region of each array together;
+// with 256 workgroups (one per CU) these mixed read/write streams reached the
+// highest HBM rate.
 inline int stream_blocks_for(long long n, int cap) {
     long long b = (n + kThreads * 8 - 1) / (kThreads * 8);
     if (b < 1) b = 1;
-    if (cap <= 0) cap = 1024;
+    if (cap <= 0) cap = 256;
     if (cap > kSingleMax) cap = kSingleMax;  // the streaming passes always finish in-kernel
     if (b > cap) b = cap;
     return (int)b;

@@ -203,10 +203,9 @@ __global__ __launch_bounds__(kThreads) void k_resid(Coef7 cf, const double* b, c
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_ir_init(SysView<T> S, float inv_scale, double tol,
                                                       int max_iter) {
-    int i0, i1;
-    stream_range(S.n, S.stream_blocks, blockIdx.x, i0, i1);
     double acc[1] = {0.0};
-    for (int i = i0 + (int)threadIdx.x; i < i1; i += kThreads) {
+    const int step = S.stream_blocks * kThreads;
+    for (int i = (int)(blockIdx.x * kThreads + threadIdx.x); i < S.n; i += step) {
         const T rt = from_f32<T>(S.d[i] * inv_scale);
         S.r[i] = rt;
         S.rhat[i] = rt;
