@@ -93,7 +93,7 @@ typedef struct {
     int32_t stream_blocks;  /* workgroups of the streaming passes; 0 = auto (at most 256);
                                capped at 1024 */
     int32_t chunk_cells;    /* batched/queue: cells per work item of the persistent
-                               kernel (multiple of 256); 0 = 4096 */
+                               kernel, rounded up to a multiple of 256; 0 = 16384 */
     int32_t profile;        /* 1: launch without graphs, time every pass with HIP
                                events into s7_info.pass_ms */
     int32_t inner_max_iter; /* IR: inner iteration cap per outer step; 0 = 100 */

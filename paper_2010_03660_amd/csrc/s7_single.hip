@@ -944,8 +944,13 @@ int BatchEngine::add(EngineJob* j) {
     return S7_OK;
 }
 
+// Cells per work item.  Every chunk costs a claim and a completion, each a
+// round trip to memory on the system's own control words, so chunks are
+// large by default: a small system is one or two chunks, done by one
+// workgroup with no hand-off, and the batch itself supplies the parallelism.
 static int chunk_cells_of(const s7_options& o) {
-    int c = o.chunk_cells > 0 ? o.chunk_cells : 4096;
+    int c = o.chunk_cells > 0 ? o.chunk_cells : 16384;
+    if (c > (1 << 30)) c = 1 << 30;
     c = (c + kThreads - 1) / kThreads * kThreads;
     return c;
 }
@@ -1106,7 +1111,7 @@ int BatchEngine::tune() {
     best[0] = chunk_;
     best[1] = grid_cap_;
     int rc = S7_OK;
-    for (int chunk : {1024, 2048, 4096, 8192, 16384}) {
+    for (int chunk : {1024, 2048, 4096, 8192, 16384, 32768, 65536}) {
         for (int gcap : {1024, 2048}) {
             std::vector<BSys> table;
             long long chunks = 0;
