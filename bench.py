@@ -55,7 +55,7 @@ KERNEL = {
         "p2": "k_p2f_pair (P2 on cell pairs: y = A q with q = r - alpha s on the fly, five dot products)",
         "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"},
 }
-BATCH_BYTES = sum(BYTES[("f32", 4)].values())  # the batched engine runs the four-pass schedule
+BATCH_BYTES = sum(BYTES[("f32", 3)].values())  # the batched engine runs the three-pass schedule
 SPLIT_CELLS = 1 << 21  # the queue's default: larger requests take the single-system path
 SRC_FILES = ["paper_2010_03660_amd/csrc/s7_device.hpp", "paper_2010_03660_amd/csrc/s7_single.hip"]
 

@@ -132,9 +132,9 @@ typedef struct {
     double pass_ms[4];   /* profile: summed time of the iteration's kernels P1, P2a, P2b, P3
                             (P1 and P2b include the finishing kernel of a split sum) */
     int32_t pass_count[4];
-    int32_t schedule;    /* single-system solve: the schedule it ran (1 three passes, 2 four
-                            passes, 3 three passes on cell pairs); batched and queue engine
-                            solves: 2 */
+    int32_t schedule;    /* the schedule it ran: 1 three passes, 2 four passes, 3 three
+                            passes on cell pairs.  Batched and queue engine solves run
+                            three phases per iteration: 3 if nx is even, else 1 */
     int32_t reserved;
 } s7_info;
 
@@ -203,7 +203,7 @@ size_t s7_batched_workspace_bytes(int32_t nsys, const s7_dims *d, int32_t prec,
  *   device doubles; rtol[s]; max_iter[s].
  * info, if not NULL, is an array of nsys and receives each system's result.
  * All systems use precision prec.  The whole of each solve runs on the
- * device: the iterations (four passes each), and the refinement steps or the
+ * device: the iterations (three phases each), and the refinement steps or the
  * FP32 epilogue.  Each system's iterates depend only on that system and on
  * chunk_cells (the work-item size, which fixes its summation order), never
  * on the rest of the batch.  With opt->tune = 1 and chunk_cells = 0 the

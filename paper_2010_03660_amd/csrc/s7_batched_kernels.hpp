@@ -5,8 +5,9 @@
 //
 // Execution model (no grid barrier, no fence):
 // * A work item is (system, phase, chunk), where a chunk is `chunk_cells`
-//   consecutive cells of one system.  The phases of an iteration are P1,
-//   P2a, P2b and P3, the four-pass schedule of the single-system path.
+//   consecutive cells of one system.  The phases of an iteration are P1, P2
+//   and P3, the three-pass schedule of the single-system path: P2 forms
+//   q = r - alpha s on the fly, and P3 forms it again.
 //   Around the iteration a job also runs, on the device, its epilogue and
 //   its refinement steps: X (x += scale d), R (the FP64 residual) and I (the
 //   next inner right-hand side), so a job needs the host only to start.
@@ -121,12 +122,12 @@ struct BSys {
     double* x;
 };
 
-// Phases of a job.  An iteration is P1, P2a, P2b, P3.  Around the inner
+// Phases of a job.  An iteration is P1, P2, P3.  Around the inner
 // iteration: X (x += scale d), R (FP64 residual b - A x) and, for refinement,
 // I (next inner right-hand side r = r0 = p = d / scale).  A phase sequence
 // number is (count << 3) | kind.
-enum PhaseKind : int { K_P1 = 0, K_P2A = 1, K_P2B = 2, K_P3 = 3, K_X = 4, K_R = 5, K_I = 6, K_FINAL = 7 };
-constexpr int kND[7] = {1, 1, 4, 2, 0, 3, 1};  // sums of each phase
+enum PhaseKind : int { K_P1 = 0, K_P2 = 1, K_P3 = 2, K_X = 3, K_R = 4, K_I = 5, K_FINAL = 6 };
+constexpr int kND[6] = {1, 5, 2, 0, 3, 1};  // sums of each phase
 __host__ __device__ inline uint32_t seq_next(uint32_t seq, int kind) {
     return (((seq >> 3) + 1u) << 3) | (uint32_t)kind;
 }
@@ -243,8 +244,8 @@ __device__ __forceinline__ void cload_nbr2(const T* v, const Cell& c, Nbr<float>
     v1 = Nbr<float>{ce.b, ce.a, e, s.b, nn.b, b.b, t.b};
 }
 
-// P1 and P2b of a chunk on x-adjacent cell pairs (systems with an even nx):
-// thread t takes pairs base/2 + 256*u + t for u < kUP.
+// P1 of a chunk on x-adjacent cell pairs (systems with an even nx): thread t
+// takes pairs base/2 + 256*u + t for u < kUP.
 constexpr int kUP = 2;
 template <class T, bool UNIT>
 __device__ void chunk_p1_pairs(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
@@ -275,100 +276,91 @@ __device__ void chunk_p1_pairs(const SysView<T>& S, int c0, int c1, double (&acc
     }
 }
 
-template <class T, bool UNIT>
-__device__ void chunk_p2b_pairs(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += 2 * kUP * kThreads) {
-        Cell cl[kUP];
-        Nbr<float> q0[kUP], q1[kUP];
-        Coefs<float, UNIT> k0[kUP], k1[kUP];
-        F2 rh[kUP];
-#pragma unroll
-        for (int u = 0; u < kUP; ++u) {
-            const int gp = base / 2 + u * kThreads + (int)threadIdx.x;
-            const bool in = 2 * gp < c1;
-            cl[u] = cell2_at(in ? gp : S.n / 2 - 1, S.m, S.n);
-            cl[u].own = in;
-            cload_nbr2(S.q, cl[u], q0[u], q1[u]);
-            load_coefs2_nt<T, UNIT>(S.c, cl[u].idx, k0[u], k1[u]);
-            rh[u] = cload2(S.rhat + cl[u].idx);
-        }
-#pragma unroll
-        for (int u = 0; u < kUP; ++u) {
-            const T y0 = from_f32<T>(apply7<float, float, UNIT, false>(k0[u], q0[u], cl[u]));
-            const T y1 = from_f32<T>(apply7<float, float, UNIT, false>(k1[u], q1[u], cl[u]));
-            if (cl[u].own) {
-                cstore2(S.y + cl[u].idx, y0, y1);
-                const double ya = (double)to_f32(y0), yb = (double)to_f32(y1);
-                const double qa = (double)q0[u].c, qb = (double)q1[u].c;
-                const double ra = (double)rh[u].a, rb = (double)rh[u].b;
-                acc[0] = fma(qb, yb, fma(qa, ya, acc[0]));
-                acc[1] = fma(yb, yb, fma(ya, ya, acc[1]));
-                acc[2] = fma(rb, qb, fma(ra, qa, acc[2]));
-                acc[3] = fma(rb, yb, fma(ra, ya, acc[3]));
-            }
-        }
-    }
+// P2 of the three-phase iteration: q = r - alpha s formed in FP32 at the cell
+// and its six neighbours, y = A q stored; sums (q,y), (y,y), (q,q), (r0,q),
+// (r0,y).  Two cells per thread and step.
+__device__ __forceinline__ Nbr<float> q_of(const Nbr<float>& r, const Nbr<float>& s, float alpha) {
+    return Nbr<float>{fmaT(-alpha, s.c, r.c), fmaT(-alpha, s.w, r.w), fmaT(-alpha, s.e, r.e),
+                      fmaT(-alpha, s.s, r.s), fmaT(-alpha, s.n, r.n), fmaT(-alpha, s.b, r.b),
+                      fmaT(-alpha, s.t, r.t)};
 }
-
-template <class T>
-__device__ void chunk_p2a_b(const SysView<T>& S, int c0, int c1, float alpha, double (&acc)[kMaxDots]) {
-    const int c1e = c0 + ((c1 - c0) & ~1);  // pairs, then a last odd cell
-    for (int i = c0 + 2 * (int)threadIdx.x; i < c1e; i += 2 * kThreads) {
-        const F2 r = cload2(S.r + i), sv = cload2(S.s + i);
-        const T qa = from_f32<T>(fmaT(-alpha, sv.a, r.a)), qb = from_f32<T>(fmaT(-alpha, sv.b, r.b));
-        cstore2(S.q + i, qa, qb);
-        const double da = (double)to_f32(qa), db = (double)to_f32(qb);
-        acc[0] = fma(db, db, fma(da, da, acc[0]));
-    }
-    for (int i = c1e + (int)threadIdx.x; i < c1; i += kThreads) {
-        const float r = to_f32(cload(S.r + i)), s = to_f32(cload(S.s + i));
-        const T q = from_f32<T>(fmaT(-alpha, s, r));
-        cstore(S.q + i, q);
-        const double qd = (double)to_f32(q);
-        acc[0] = fma(qd, qd, acc[0]);
-    }
+__device__ __forceinline__ void acc_p2f(double (&acc)[kMaxDots], double q, double y, double h) {
+    acc[0] = fma(q, y, acc[0]);
+    acc[1] = fma(y, y, acc[1]);
+    acc[2] = fma(q, q, acc[2]);
+    acc[3] = fma(h, q, acc[3]);
+    acc[4] = fma(h, y, acc[4]);
 }
-
+constexpr int kUF = 2;
 template <class T, bool UNIT>
-__device__ void chunk_p2b_b(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += kU * kThreads) {
-        Cell cl[kU];
-        Nbr<T> qv[kU];
-        Coefs<T, UNIT> k[kU];
-        T rh[kU];
+__device__ void chunk_p2f_b(const SysView<T>& S, int c0, int c1, float alpha, double (&acc)[kMaxDots]) {
+    for (int base = c0; base < c1; base += kUF * kThreads) {
+        Cell cl[kUF];
+        Nbr<T> rv[kUF], sv[kUF];
+        Coefs<T, UNIT> k[kUF];
+        T rh[kUF];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < kUF; ++u) {
             const int g = base + u * kThreads + (int)threadIdx.x;
             cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
             cl[u].own = g < c1;
-            qv[u] = cload_nbr(S.q, cl[u]);
+            rv[u] = cload_nbr(S.r, cl[u]);
+            sv[u] = cload_nbr(S.s, cl[u]);
             k[u] = load_coefs<T, UNIT>(S.c, cl[u].idx);
             rh[u] = cload(S.rhat + cl[u].idx);
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const Nbr<float> q = nbr_f32(qv[u]);
+        for (int u = 0; u < kUF; ++u) {
+            const Nbr<float> q = q_of(nbr_f32(rv[u]), nbr_f32(sv[u]), alpha);
             const T yt = from_f32<T>(apply7<float, T, UNIT, false>(k[u], q, cl[u]));
             if (cl[u].own) {
                 cstore(S.y + cl[u].idx, yt);
-                const double yd = (double)to_f32(yt), qd = (double)q.c, rd = (double)to_f32(rh[u]);
-                acc[0] = fma(qd, yd, acc[0]);
-                acc[1] = fma(yd, yd, acc[1]);
-                acc[2] = fma(rd, qd, acc[2]);
-                acc[3] = fma(rd, yd, acc[3]);
+                acc_p2f(acc, (double)q.c, (double)to_f32(yt), (double)to_f32(rh[u]));
             }
         }
     }
 }
 
-template <class T>
+// The same on x-adjacent cell pairs (systems with an even nx).
+template <class T, bool UNIT>
+__device__ void chunk_p2f_pairs(const SysView<T>& S, int c0, int c1, float alpha, double (&acc)[kMaxDots]) {
+    for (int base = c0; base < c1; base += 2 * kThreads) {
+        const int gp = base / 2 + (int)threadIdx.x;
+        const bool in = 2 * gp < c1;
+        Cell cl = cell2_at(in ? gp : S.n / 2 - 1, S.m, S.n);
+        cl.own = in;
+        Nbr<float> r0, r1, s0, s1;
+        cload_nbr2(S.r, cl, r0, r1);
+        cload_nbr2(S.s, cl, s0, s1);
+        Coefs<float, UNIT> k0, k1;
+        load_coefs2_nt<T, UNIT>(S.c, cl.idx, k0, k1);
+        const F2 rh = cload2(S.rhat + cl.idx);
+        const Nbr<float> q0 = q_of(r0, s0, alpha), q1 = q_of(r1, s1, alpha);
+        const T y0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, q0, cl));
+        const T y1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, q1, cl));
+        if (in) {
+            cstore2(S.y + cl.idx, y0, y1);
+            acc_p2f(acc, (double)q0.c, (double)to_f32(y0), (double)rh.a);
+            acc_p2f(acc, (double)q1.c, (double)to_f32(y1), (double)rh.b);
+        }
+    }
+}
+
+// P3.  QR (three-phase iteration): q = r - alpha s is formed from the old r
+// and s instead of being read.
+template <class T, bool QR>
 __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, float omega,
                            float beta, double (&acc)[kMaxDots]) {
     // pairs of cells (c0 is even), then a last odd cell if c1 is odd
     const int c1e = c0 + ((c1 - c0) & ~1);
     for (int i = c0 + 2 * (int)threadIdx.x; i < c1e; i += 2 * kThreads) {
         const F2 d2 = cload2(S.d + i), p2 = cload2(S.p + i), s2 = cload2(S.s + i), y2 = cload2(S.y + i),
-                 q2 = cload2(S.q + i), h2 = cload2(S.rhat + i);
+                 h2 = cload2(S.rhat + i);
+        F2 q2 = cload2((QR ? S.r : S.q) + i);
+        if (QR) {
+            q2.a = fmaT(-alpha, s2.a, q2.a);
+            q2.b = fmaT(-alpha, s2.b, q2.b);
+        }
         float da = d2.a, db = d2.b;
         T ra, pa, rb, pb;
         p3_math<T>(alpha, omega, beta, p2.a, s2.a, y2.a, q2.a, da, ra, pa);
@@ -383,8 +375,9 @@ __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, flo
     for (int i = c1e + (int)threadIdx.x; i < c1; i += kThreads) {
         float dv = cload(S.d + i);
         T rn, pn;
-        p3_math<T>(alpha, omega, beta, to_f32(cload(S.p + i)), to_f32(cload(S.s + i)),
-                   to_f32(cload(S.y + i)), to_f32(cload(S.q + i)), dv, rn, pn);
+        const float sv = to_f32(cload(S.s + i));
+        const float qv = QR ? fmaT(-alpha, sv, to_f32(cload(S.r + i))) : to_f32(cload(S.q + i));
+        p3_math<T>(alpha, omega, beta, to_f32(cload(S.p + i)), sv, to_f32(cload(S.y + i)), qv, dv, rn, pn);
         cstore(S.d + i, dv);
         cstore(S.r + i, rn);
         cstore(S.p + i, pn);
@@ -443,7 +436,7 @@ __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, 
     const SysView<T> S = as_view<T>(raw);
     if (phase == K_I) {
         chunk_i_b<T>(S, c0, c1, inv_scale, acc);
-    } else if (phase == 0) {
+    } else if (phase == K_P1) {
         if (S.pair_blocks > 0) {
             if (S.unit) chunk_p1_pairs<T, true>(S, c0, c1, acc);
             else chunk_p1_pairs<T, false>(S, c0, c1, acc);
@@ -452,19 +445,17 @@ __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, 
         } else {
             chunk_p1_b<T, false>(S, c0, c1, acc);
         }
-    } else if (phase == 1) {
-        chunk_p2a_b<T>(S, c0, c1, alpha, acc);
-    } else if (phase == 2) {
+    } else if (phase == K_P2) {
         if (S.pair_blocks > 0) {
-            if (S.unit) chunk_p2b_pairs<T, true>(S, c0, c1, acc);
-            else chunk_p2b_pairs<T, false>(S, c0, c1, acc);
+            if (S.unit) chunk_p2f_pairs<T, true>(S, c0, c1, alpha, acc);
+            else chunk_p2f_pairs<T, false>(S, c0, c1, alpha, acc);
         } else if (S.unit) {
-            chunk_p2b_b<T, true>(S, c0, c1, acc);
+            chunk_p2f_b<T, true>(S, c0, c1, alpha, acc);
         } else {
-            chunk_p2b_b<T, false>(S, c0, c1, acc);
+            chunk_p2f_b<T, false>(S, c0, c1, alpha, acc);
         }
     } else {
-        chunk_p3_b<T>(S, c0, c1, alpha, omega, beta, acc);
+        chunk_p3_b<T, true>(S, c0, c1, alpha, omega, beta, acc);
     }
 }
 
@@ -630,9 +621,8 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
             int next = K_FINAL;
             bool iter_done = false;
             switch (kind) {
-                case K_P1: tail_p1(&st, reinterpret_cast<double(&)[1]>(tot)); next = K_P2A; break;
-                case K_P2A: tail_p2a(&st, reinterpret_cast<double(&)[1]>(tot)); next = K_P2B; break;
-                case K_P2B: tail_p2(&st, reinterpret_cast<double(&)[4]>(tot)); next = K_P3; break;
+                case K_P1: tail_p1(&st, reinterpret_cast<double(&)[1]>(tot)); next = K_P2; break;
+                case K_P2: tail_p2f(&st, reinterpret_cast<double(&)[5]>(tot)); next = K_P3; break;
                 case K_P3:
                     tail_p3(&st, reinterpret_cast<double(&)[2]>(tot));
                     next = K_P1;

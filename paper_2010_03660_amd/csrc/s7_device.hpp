@@ -920,6 +920,14 @@ __device__ __forceinline__ void tail_p2(State* st, const double (&tot)[4]) {
     }
 }
 
+// Scalar step after the three-pass schedule's P2 (five sums: (q,y), (y,y),
+// (q,q), (r0,q), (r0,y)).
+__device__ __forceinline__ void tail_p2f(State* st, const double (&tot)[5]) {
+    st->qq = tot[2];
+    const double t4[4] = {tot[0], tot[1], tot[3], tot[4]};
+    tail_p2(st, t4);
+}
+
 // After P3: stopping tests, then the breakdown tests on rho_{i+1}.
 __device__ __forceinline__ void tail_p3(State* st, const double (&tot)[2]) {
     st->iter += 1;

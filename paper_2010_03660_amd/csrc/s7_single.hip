@@ -235,14 +235,6 @@ __global__ __launch_bounds__(kThreads) void k_fill0(double* x, int n) {
 // pass whose partials it sums.
 enum FinishKind { FIN_P1 = 1, FIN_P2 = 2, FIN_INIT = 3, FIN_RESID = 4, FIN_P2F = 5 };
 
-// Scalar step after the three-pass schedule's P2 (five sums: (q,y), (y,y),
-// (q,q), (r0,q), (r0,y)).
-__device__ __forceinline__ void tail_p2f(State* st, const double (&tot)[5]) {
-    st->qq = tot[2];
-    const double t4[4] = {tot[0], tot[1], tot[3], tot[4]};
-    tail_p2(st, t4);
-}
-
 template <int ND, unsigned MAXMASK, int KIND>
 __global__ __launch_bounds__(kThreads) void k_finish(Red red, int nblocks, State* st, double tol,
                                                      int max_iter) {
@@ -1009,7 +1001,7 @@ static void finish_job(EngineJob& j, const State& h) {
     std::memset(&inf, 0, sizeof(inf));
     inf.iters = h.total;
     inf.outer_iters = h.ir ? h.outer : 1;
-    inf.schedule = SCHED_FOUR;
+    inf.schedule = j.d.nx % 2 == 0 ? SCHED_PAIRS : SCHED_THREE;  // the persistent kernel's phases
     inf.status = h.ostatus;
     inf.reason = h.oreason;
     inf.rel_res_rec = h.inner_res;
