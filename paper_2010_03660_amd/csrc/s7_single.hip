@@ -205,7 +205,27 @@ __global__ __launch_bounds__(kThreads) void k_ir_init(SysView<T> S, float inv_sc
                                                       int max_iter) {
     double acc[1] = {0.0};
     const int step = S.stream_blocks * kThreads;
-    for (int i = (int)(blockIdx.x * kThreads + threadIdx.x); i < S.n; i += step) {
+    // kVec<T> cells per thread and step with 16-byte accesses, then the tail
+    constexpr int W = kVec<T>;
+    const int nv = S.n / W;
+    const float zero[W] = {};
+    for (int v = (int)(blockIdx.x * kThreads + threadIdx.x); v < nv; v += step) {
+        const int i = W * v;
+        float dv[W];
+        ldw_nt<W>(S.d + i, dv);
+        T rt[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            rt[j] = from_f32<T>(dv[j] * inv_scale);
+            const double x = (double)to_f32(rt[j]);
+            acc[0] = fma(x, x, acc[0]);
+        }
+        stw_nt<W>(S.r + i, rt);
+        stw_nt<W>(S.rhat + i, rt);
+        stw_nt<W>(S.p + i, rt);
+        stw_nt<W>(S.d + i, zero);
+    }
+    for (int i = W * nv + (int)(blockIdx.x * kThreads + threadIdx.x); i < S.n; i += step) {
         const T rt = from_f32<T>(S.d[i] * inv_scale);
         S.r[i] = rt;
         S.rhat[i] = rt;
@@ -220,10 +240,34 @@ __global__ __launch_bounds__(kThreads) void k_ir_init(SysView<T> S, float inv_sc
 }
 
 // x += scale * d (FP64), or x = 0 when b = 0.
+// x += scale d in FP64 (x = 0 when b was zero).  Four cells per thread and
+// step with 16-byte accesses when x is 16-byte aligned (d, in the workspace,
+// always is); the caller's x may be only 8-byte aligned, which takes the
+// scalar loop.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 __global__ __launch_bounds__(kThreads) void k_update_x(double* x, const float* d, int n,
                                                        double scale, const State* st) {
     const bool zero = st->nbzero != 0;
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+    const int step = (int)gridDim.x * kThreads;
+    int head = 0;
+    if ((reinterpret_cast<uintptr_t>(x) & 15u) == 0) {
+        const int nv = n / 4;
+        for (int v = (int)(blockIdx.x * kThreads + threadIdx.x); v < nv; v += step) {
+            const int i = 4 * v;
+            float dv[4];
+            ld4_nt(d + i, dv);
+            f64x2* px = reinterpret_cast<f64x2*>(x + i);
+            f64x2 a = __builtin_nontemporal_load(px), b = __builtin_nontemporal_load(px + 1);
+            a.x = zero ? 0.0 : fma(scale, (double)dv[0], a.x);
+            a.y = zero ? 0.0 : fma(scale, (double)dv[1], a.y);
+            b.x = zero ? 0.0 : fma(scale, (double)dv[2], b.x);
+            b.y = zero ? 0.0 : fma(scale, (double)dv[3], b.y);
+            __builtin_nontemporal_store(a, px);
+            __builtin_nontemporal_store(b, px + 1);
+        }
+        head = 4 * nv;
+    }
+    for (int i = head + (int)(blockIdx.x * kThreads + threadIdx.x); i < n; i += step)
         x[i] = zero ? 0.0 : fma(scale, (double)d[i], x[i]);
 }
 
@@ -778,7 +822,7 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
     State h;
     rc = run_iterations<float>(S, o, s, &h, info);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, x, S.d, S.n, 1.0, S.st);
+    hipLaunchKernelGGL(k_update_x, dim3(S.stream_blocks), dim3(kThreads), 0, s, x, S.d, S.n, 1.0, S.st);
     S7_CHECK_LAUNCH();
     rc = resid_launch<float>(cf, b, x, nullptr, S, o.jacobi, s);
     if (rc) return rc;
@@ -864,7 +908,7 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
             reason = h.reason;
             break;
         }
-        hipLaunchKernelGGL(k_update_x, dim3(grid_for(S.n)), dim3(kThreads), 0, s, x, S.d, S.n,
+        hipLaunchKernelGGL(k_update_x, dim3(S.stream_blocks), dim3(kThreads), 0, s, x, S.d, S.n,
                            scale, S.st);
         S7_CHECK_LAUNCH();
     }

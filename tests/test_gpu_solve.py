@@ -362,3 +362,27 @@ def test_paired_schedule_matches_oracle(s7, dims, prec):
     if prec == 0:
         r8 = oracle.bicgstab(A, b, tol=1e-8, max_iter=2000)
         assert abs(info.iters - r8.iters) <= max(3, 0.2 * r8.iters)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16_ir"])
+def test_x_only_8_byte_aligned(s7, prec):
+    """The caller's x need only be 8-byte aligned.  The x update takes 16-byte accesses
+    when it can and a scalar loop otherwise; both give the same bits.  A ragged length
+    (n mod 4 = 3) also exercises the tail."""
+    import torch
+    dims = (33, 17, 9)  # 5049 cells
+    prob, A, b = problem(dims, seed=21)
+    coef, bd = coef_dev(prob), dev(b)
+    p = s7.PREC_NAMES[prec]
+    rtol = 1e-8 if prec == "fp32" else 1e-10
+    xa = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    buf = torch.zeros(A.n + 1, dtype=torch.float64, device="cuda")
+    xm = buf[1:]  # 8 bytes past a 256-byte boundary
+    assert xa.data_ptr() % 16 == 0 and xm.data_ptr() % 16 == 8
+    ia = s7.bicgstab_solve(dims, coef, bd, xa, rtol, 2000, prec=p)
+    im = s7.bicgstab_solve(dims, coef, bd, xm, rtol, 2000, prec=p)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(xa), host(xm)) and ia.iters == im.iters
+    assert float(buf[0]) == 0.0  # nothing written before x
+    ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
+    assert rel_err(host(xm), ref.x) <= (1e-6 if prec == "fp32" else 1e-7)
