@@ -88,20 +88,27 @@ __device__ __forceinline__ Nbr<T> cload_nbr(const T* v, const Cell& c) {
                   cload(p + c.dn), cload(p + c.db), cload(p + c.dt)};
 }
 
-// State copied word by word with coherent accesses.
+// The State copied between memory and an LDS copy with coherent accesses, one
+// 4-byte word per thread of the workgroup, so that a copy costs one round trip
+// to memory rather than one per word.  Called by every thread.
+constexpr int kStateWords = (int)(sizeof(State) / 4);
+static_assert(sizeof(State) % 4 == 0 && kStateWords <= kThreads, "State is copied one word per thread");
 __device__ __forceinline__ void state_load(const State* src, State& dst) {
-    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
-    uint32_t* d = reinterpret_cast<uint32_t*>(&dst);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(State) / 4); ++i)
-        d[i] = __hip_atomic_load(const_cast<uint32_t*>(s + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int w = (int)threadIdx.x;
+    if (w < kStateWords)
+        reinterpret_cast<uint32_t*>(&dst)[w] = __hip_atomic_load(
+            const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(src) + w), __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
 }
+// Each thread waits until its word has reached memory.
 __device__ __forceinline__ void state_store(State* dst, const State& src) {
-    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-    const uint32_t* s = reinterpret_cast<const uint32_t*>(&src);
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(State) / 4); ++i)
-        __hip_atomic_store(d + i, s[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int w = (int)threadIdx.x;
+    if (w < kStateWords) {
+        __hip_atomic_store(reinterpret_cast<uint32_t*>(dst) + w, reinterpret_cast<const uint32_t*>(&src)[w],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_stores();
+    }
 }
 
 // ---------------------------------------------------------------- tables
@@ -530,8 +537,8 @@ __device__ int after_resid(State& st, const double (&tot)[kMaxDots]) {
 __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* glob,
                                                       int nsys, int chunk_cells,
                                                       long long spin_limit) {
-    __shared__ int sh_sys, sh_chunk, sh_last;
-    __shared__ uint32_t sh_seq;
+    __shared__ int sh_sys, sh_chunk, sh_last, sh_stop, sh_budget;
+    __shared__ uint32_t sh_seq, sh_nseq;
     __shared__ State sh_state;
     int s = (int)(blockIdx.x % (unsigned)nsys);
     long long idle = 0;
@@ -613,11 +620,11 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
         double tot[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (kind == K_R) sum_range<kMaxDots, 4u, true>(S.red.part, 0, B.nchunk, tot);
         else if (kND[kind] > 0) sum_range<kMaxDots, 0u, true>(S.red.part, 0, B.nchunk, tot);
+        // the private state copy lives in LDS: a register copy would raise the
+        // register count of the whole kernel
+        state_load(S.st, sh_state);
         if (threadIdx.x == 0) {
-            // the private state copy lives in LDS: a register copy would raise the
-            // register count of the whole kernel
             State& st = sh_state;
-            state_load(S.st, st);
             int next = K_FINAL;
             bool iter_done = false;
             switch (kind) {
@@ -649,11 +656,18 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
                 wall_clock64() - __hip_atomic_load(&glob->t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > slice)
                 stop = true;
             if (next == K_FINAL) st.final = 1;
-            state_store(S.st, st);
+            sh_stop = stop ? 1 : 0;
+            sh_budget = budget;
+            sh_nseq = seq_next(seq, next == K_FINAL ? K_P1 : next);
+        }
+        __syncthreads();
+        state_store(S.st, sh_state);
+        __syncthreads();  // every word of the State has reached memory
+        if (threadIdx.x == 0) {
             __hip_atomic_store(&B.ctl->done_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            cstore_i(&B.ctl->budget, budget);
-            const uint32_t nseq = seq_next(seq, next == K_FINAL ? K_P1 : next);
-            if (stop) {
+            cstore_i(&B.ctl->budget, sh_budget);
+            const uint32_t nseq = sh_nseq;
+            if (sh_stop) {
                 cstore_i(&B.ctl->active, 0);
                 // Park the claim word on the phase to resume, with its chunk counter
                 // already exhausted: a workgroup racing this store claims nothing.  The
