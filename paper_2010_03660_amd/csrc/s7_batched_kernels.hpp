@@ -603,6 +603,10 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
             else if (tag == 1) run_chunk<bf16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
             else run_chunk<f16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
         }
+        // Every thread waits until its own vector stores have reached memory: a
+        // workgroup barrier does not wait for them, and the next phase may read
+        // them from another workgroup.
+        wait_stores();
         // publish this chunk's partials, then count the chunk done
         double bsum[kMaxDots];
         if (kind == K_R) block_reduce<kMaxDots, 4u>(acc, bsum);
