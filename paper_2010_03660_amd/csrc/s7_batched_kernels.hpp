@@ -130,11 +130,12 @@ struct BSys {
 };
 
 // Phases of a job.  An iteration is P1, P2, P3.  Around the inner
-// iteration: X (x += scale d), R (FP64 residual b - A x) and, for refinement,
-// I (next inner right-hand side r = r0 = p = d / scale).  A phase sequence
+// iteration: S (an FP32 job's start: r0 = b - A x0), X (x += scale d), R (FP64
+// residual b - A x) and, for refinement, I (next inner right-hand side
+// r = r0 = p = d / scale).  A refinement job starts at R.  A phase sequence
 // number is (count << 3) | kind.
-enum PhaseKind : int { K_P1 = 0, K_P2 = 1, K_P3 = 2, K_X = 3, K_R = 4, K_I = 5, K_FINAL = 6 };
-constexpr int kND[6] = {1, 5, 2, 0, 3, 1};  // sums of each phase
+enum PhaseKind : int { K_P1 = 0, K_P2 = 1, K_P3 = 2, K_X = 3, K_R = 4, K_I = 5, K_S = 6, K_FINAL = 7 };
+constexpr int kND[7] = {1, 5, 2, 0, 3, 1, 3};  // sums of each phase
 __host__ __device__ inline uint32_t seq_next(uint32_t seq, int kind) {
     return (((seq >> 3) + 1u) << 3) | (uint32_t)kind;
 }
@@ -177,6 +178,72 @@ __global__ void k_ctl_reset(BCtl* ctl, int kind) {
         ctl->budget = 0;
         ctl->active = 0;
     }
+}
+
+// One new job of a batch (a table of these is filled by the host).  The
+// start kernel writes its working-precision coefficient copies and sets its
+// State and control words; its first phase then runs in the persistent
+// launch.  Coefficient copies are read there with plain loads, so they must be
+// written by an earlier kernel, not by a phase of the same launch.
+struct JobStart {
+    Coef7 cf;        // the caller's FP32 coefficients
+    void* coef_dst;  // first working-precision copy; copies are `span` elements apart
+    size_t span;
+    Mesh m;
+    int n, jacobi, tag, first;  // first: the first phase (K_S, or K_R for refinement)
+    State* st;
+    uint32_t* cnt;
+    BCtl* ctl;
+    double rtol, inner_tol;
+    int inner_cap, outer_cap, max_total, ir;
+};
+
+template <class T>
+__device__ void start_coef_copies(const JobStart& J, int i0, int step) {
+    const int first = J.jacobi ? 1 : 0;
+    T* dst0 = reinterpret_cast<T*>(J.coef_dst);
+    for (int i = i0; i < J.n; i += step) {
+        const Cell c = cell_at(i, J.m, J.n);
+        const bool in[7] = {true, c.dw != 0, c.de != 0, c.ds != 0, c.dn != 0, c.db != 0, c.dt != 0};
+        const float dg = J.cf.c[0][i];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) {
+            if (a < first) continue;
+            float v = in[a] ? J.cf.c[a][i] : 0.0f;
+            if (J.jacobi) v = v / dg;
+            dst0[(size_t)(a - first) * J.span + i] = from_f32<T>(v);
+        }
+    }
+}
+
+// Starts every new job of a step in one launch: blockIdx.y is the job.
+// Working-precision coefficient copies: c[a] / diag for a = 1..6 with Jacobi
+// scaling (unit diagonal), else all seven; outward links on the boundary faces
+// are zeroed, so the iteration never needs face tests.
+__global__ __launch_bounds__(kThreads) void k_jobs_start(const JobStart* jobs) {
+    const JobStart& J = jobs[blockIdx.y];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        State st{};
+        st.ir = J.ir;
+        st.rtol_o = J.rtol;
+        st.inner_tol = J.inner_tol;
+        st.inner_cap = J.inner_cap;
+        st.outer_cap = J.outer_cap;
+        st.max_total = J.max_total;
+        st.rel = INFINITY;
+        st.ostatus = ST_NOT_CONVERGED;
+        st.oreason = RS_NONE;
+        *J.st = st;
+        *J.cnt = 0u;
+        J.ctl->claim = (unsigned long long)J.first << 32;
+        J.ctl->done_cnt = 0u;
+        J.ctl->budget = 0;
+        J.ctl->active = 0;
+    }
+    const int i0 = (int)(blockIdx.x * kThreads + threadIdx.x), step = (int)gridDim.x * kThreads;
+    if (J.tag == 0) start_coef_copies<float>(J, i0, step);
+    else if (J.tag == 1) start_coef_copies<bf16>(J, i0, step);
+    else start_coef_copies<f16>(J, i0, step);
 }
 
 struct BGlobal {
@@ -422,6 +489,35 @@ __device__ void chunk_r_b(const SysView<float>& S, const Coef7& cf, const double
     }
 }
 
+// S (FP32 jobs): r0 = b - A x0 in FP64 with the caller's coefficients,
+// Jacobi-scaled, rounded to FP32 into r, r0 and p; d = 0.  Sums: ||b_s||^2,
+// (r,r) of the rounded r, ||b||^2 unscaled.
+__device__ void chunk_s_b(const SysView<float>& S, const Coef7& cf, const double* b, const double* x,
+                          int c0, int c1, double (&acc)[kMaxDots]) {
+    for (int g = c0 + (int)threadIdx.x; g < c1; g += kThreads) {
+        const Cell c = cell_at(g, S.m, S.n);
+        const double* px = x + c.idx;
+        const Nbr<double> xv{cload(px), cload(px + c.dw), cload(px + c.de), cload(px + c.ds),
+                             cload(px + c.dn), cload(px + c.db), cload(px + c.dt)};
+        const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
+        const double bi = b[c.idx];
+        double r0 = bi - apply7<double, float, false, true>(k, xv, c), bs = bi;
+        if (S.unit) {
+            const double dg = (double)k.a[0];
+            r0 = r0 / dg;
+            bs = bs / dg;
+        }
+        const float rf = (float)r0;
+        cstore(S.r + c.idx, rf);
+        cstore(S.rhat + c.idx, rf);
+        cstore(S.p + c.idx, rf);
+        cstore(S.d + c.idx, 0.0f);
+        acc[0] = fma(bs, bs, acc[0]);
+        acc[1] = fma((double)rf, (double)rf, acc[1]);
+        acc[2] = fma(bi, bi, acc[2]);
+    }
+}
+
 // I: r = r0 = p = fl_T(d * inv_scale), d = 0; sum (r, r).
 template <class T>
 __device__ void chunk_i_b(const SysView<T>& S, int c0, int c1, float inv_scale, double (&acc)[kMaxDots]) {
@@ -594,6 +690,8 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
             chunk_x_b(S, B.x, c0, c1, cload_d(&S.st->scale), cload_i(&S.st->xzero) != 0);
         } else if (kind == K_R) {
             chunk_r_b(S, B.cf, B.b, B.x, c0, c1, cload_i(&S.st->ir) != 0, acc);
+        } else if (kind == K_S) {
+            chunk_s_b(S, B.cf, B.b, B.x, c0, c1, acc);
         } else {
             const float alpha = (float)cload_d(&S.st->alpha);
             const float omega = (float)cload_d(&S.st->omega);
@@ -641,13 +739,19 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
                     break;
                 case K_X: next = st.xzero ? K_FINAL : K_R; break;
                 case K_R: next = after_resid(st, tot); break;
+                case K_S:  // an FP32 job's start
+                    tail_init(&st, tot[0], tot[1], st.rtol_o, st.max_total);
+                    st.bb_true = tot[2];
+                    st.scale = 1.0;
+                    next = K_P1;
+                    break;
                 default: {  // K_I: the next inner solve starts
                     const int left = st.max_total - st.total;
                     tail_init(&st, tot[0], tot[0], st.inner_tol, st.inner_cap < left ? st.inner_cap : left);
                     next = K_P1;
                 }
             }
-            if ((kind <= K_P3 || kind == K_I) && st.done) next = after_inner(st);
+            if ((kind <= K_P3 || kind == K_I || kind == K_S) && st.done) next = after_inner(st);
             int32_t budget = cload_i(&B.ctl->budget);
             bool stop = next == K_FINAL;
             if (iter_done && next == K_P1) {

@@ -928,17 +928,19 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
 }
 
 // ============================================================== batch engine
-// A job is J_NEW until its first kernels are launched, then J_RUN: the device
+// A job is J_NEW until it is in a start launch, then J_RUN: the device
 // runs the rest of its solve (iterations, refinement steps, epilogue).
 enum JobStage { J_NEW = 0, J_RUN = 1 };
 
-// Engine tables: [BGlobal][BSys x cap][State* x cap][State x cap].
+// Engine tables: [BGlobal][BSys x cap][State* x cap][State x cap][JobStart x cap].
 static size_t off_sys() { return align256(sizeof(BGlobal)); }
 static size_t off_sptr(int cap) { return off_sys() + align256((size_t)cap * sizeof(BSys)); }
 static size_t off_sgather(int cap) { return off_sptr(cap) + align256((size_t)cap * sizeof(State*)); }
 
+static size_t off_jobs(int cap) { return off_sgather(cap) + align256((size_t)cap * sizeof(State)); }
+
 size_t engine_table_bytes(int capacity) {
-    return off_sgather(capacity) + align256((size_t)capacity * sizeof(State));
+    return off_jobs(capacity) + align256((size_t)capacity * sizeof(JobStart));
 }
 
 static int chunk_cells_of(const s7_options& o);
@@ -991,50 +993,30 @@ static int chunk_cells_of(const s7_options& o) {
     return c;
 }
 
-// The device-side job parameters: refinement (ir), tolerances and caps.
-__global__ void k_job_init(State* st, int ir, double rtol, double inner_tol, int inner_cap,
-                           int outer_cap, int max_total) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    st->ir = ir;
-    st->rtol_o = rtol;
-    st->inner_tol = inner_tol;
-    st->inner_cap = inner_cap;
-    st->outer_cap = outer_cap;
-    st->max_total = max_total;
-    st->rel = INFINITY;
-    st->inner_res = 0.0;
-    st->total = st->outer = st->stall = 0;
-    st->final = st->xzero = 0;
-    st->ostatus = ST_NOT_CONVERGED;
-    st->oreason = RS_NONE;
-}
-
-// Launches the first kernels of a job: state clear, coefficient copies, job
-// parameters, and either the FP32 r0 (the iteration starts at P1) or nothing
-// more for refinement (it starts with the FP64 residual phase).
-template <class T>
-static int job_start(EngineJob& j, const s7_options& o, hipStream_t s) {
-    SysView<T> S = make_view<T>(j.d, j.lo, o.jacobi, j.ws);
-    Coef7 cf;
-    for (int a = 0; a < 7; ++a) cf.c[a] = j.coef[a];
-    int rc = start_solve<T>(cf, S, j.lo, o.jacobi, s);
-    if (rc) return rc;
-    const bool ir = !std::is_same<T, float>::value;
-    const double inner_tol = o.inner_rtol > 0 ? o.inner_rtol : (j.prec == S7_FP16_IR ? 5e-3 : 1e-2);
-    const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : 100;
-    const int outer_cap = o.outer_max_iter > 0 ? o.outer_max_iter : 30;
-    hipLaunchKernelGGL(k_job_init, dim3(1), dim3(64), 0, s, S.st, ir ? 1 : 0, j.rtol, inner_tol,
-                       inner_cap, outer_cap, j.max_iter);
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl),
-                       ir ? (int)K_R : (int)K_P1);
-    if constexpr (std::is_same<T, float>::value) {
-        hipLaunchKernelGGL(k_init_f32, dim3(S.cell_blocks), dim3(kThreads), 0, s, cf, j.b, j.x, S,
-                           o.jacobi, j.rtol, j.max_iter);
-        launch_finish<3, 0u, FIN_INIT>(S.red, S.cell_blocks, S.st, s, j.rtol, j.max_iter);
-    }
-    S7_CHECK_LAUNCH();
-    j.stage = J_RUN;
-    return S7_OK;
+// The start-table entry of a new job: coefficient copies, State and control
+// words, and the first phase (the FP32 start S, or the FP64 residual R that
+// begins refinement).
+static JobStart job_entry(const EngineJob& j, const s7_options& o) {
+    JobStart J{};
+    SysView<float> S = make_view<float>(j.d, j.lo, o.jacobi, j.ws);  // pointer members only
+    for (int a = 0; a < 7; ++a) J.cf.c[a] = j.coef[a];
+    J.coef_dst = const_cast<float*>(S.c[o.jacobi ? 1 : 0]);
+    J.span = align256(j.lo.n * j.lo.elt) / j.lo.elt;
+    J.m = S.m;
+    J.n = S.n;
+    J.jacobi = o.jacobi ? 1 : 0;
+    J.tag = j.tag;
+    J.ir = j.prec == S7_FP32 ? 0 : 1;
+    J.first = J.ir ? (int)K_R : (int)K_S;
+    J.st = S.st;
+    J.cnt = S.red.cnt;
+    J.ctl = reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl);
+    J.rtol = j.rtol;
+    J.inner_tol = o.inner_rtol > 0 ? o.inner_rtol : (j.prec == S7_FP16_IR ? 5e-3 : 1e-2);
+    J.inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : 100;
+    J.outer_cap = o.outer_max_iter > 0 ? o.outer_max_iter : 30;
+    J.max_total = j.max_iter;
+    return J;
 }
 
 #define S7_BY_PREC(j, call)                                           \
@@ -1199,16 +1181,30 @@ int BatchEngine::tune() {
 int BatchEngine::step(int epoch_iters, double slice_ms) {
     if (jobs_.empty()) return S7_OK;
     int rc;
-    // 1) start new jobs; the state pointer table follows the resident set
+    // 1) start new jobs, all in one launch; the state pointer table follows the
+    // resident set
     std::vector<State*> sptr;
+    std::vector<JobStart> starts;
+    size_t max_n = 1;
     for (EngineJob* j : jobs_) {
         sptr.push_back(reinterpret_cast<State*>(j->ws + j->lo.off_state));
         if (j->stage != J_NEW) continue;
-        rc = S7_BY_PREC(*j, job_start)(*j, o_, st_);
-        if (rc) return rc;
+        starts.push_back(job_entry(*j, o_));
+        max_n = std::max(max_n, j->lo.n);
+        j->stage = J_RUN;
     }
     S7_HIP(hipMemcpyAsync(tables_ + off_sptr(cap_), sptr.data(), sptr.size() * sizeof(State*),
                           hipMemcpyHostToDevice, st_));
+    if (!starts.empty()) {
+        JobStart* dj = reinterpret_cast<JobStart*>(tables_ + off_jobs(cap_));
+        S7_HIP(hipMemcpyAsync(dj, starts.data(), starts.size() * sizeof(JobStart), hipMemcpyHostToDevice, st_));
+        const int gx = (int)std::min<size_t>(128, (max_n + kThreads - 1) / kThreads);
+        for (size_t k = 0; k < starts.size(); k += 65535) {  // the grid's y extent is at most 65535
+            const unsigned ny = (unsigned)std::min<size_t>(65535, starts.size() - k);
+            hipLaunchKernelGGL(k_jobs_start, dim3(gx, ny), dim3(kThreads), 0, st_, (const JobStart*)(dj + k));
+        }
+        S7_CHECK_LAUNCH();
+    }
     // 2) one persistent launch over every resident job
     std::vector<BSys> table;
     const int chunk = chunk_;
