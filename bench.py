@@ -10,8 +10,8 @@ Printed: one JSON line with the metric, the roofline of the dominant kernel, the
 mixed BF16+refinement form, accuracy of converged runs against the manufactured
 solution, the batched form (64 uneven systems), the served form (a Poisson request
 stream through the queue against a serial loop of single solves, p50/p99 latency), the
-solver pattern of the paper's SIMPLE loop (Algorithm 2), and the FP64 CPU oracle timed on
-a bounded slab of the same workload.
+solver pattern of the paper's SIMPLE loop (Algorithm 2), one GPU's z-slab share of the mesh
+for an 8-GPU split, and the FP64 CPU oracle timed on a bounded slab of the same workload.
 """
 from __future__ import annotations
 
@@ -361,6 +361,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-simple", action="store_true")
+    ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--simple-dims", type=int, nargs=3, default=[100, 400, 100])
     ap.add_argument("--simple-outer", type=int, default=15)
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -457,6 +458,31 @@ def main():
         "passes": passes,
         "roofline": roofline,
     }
+
+    # ---- one GPU's share of an 8-GPU z-slab decomposition of the same mesh:
+    # the first nz/8 planes, a contiguous prefix of every array
+    if not args.no_shard and nz >= 8:
+        dims8 = (nx, ny, nz // 8)
+        n8 = nx * ny * (nz // 8)
+        print(f"[bench] z-slab share {dims8}: FP32 timed {args.steps} iterations", file=sys.stderr, flush=True)
+        c8, b8, x8 = [c[:n8] for c in coef], b[:n8], x[:n8]
+        o8 = s7.default_options(profile=1, schedule={0: 0, 3: 1, 4: 2}[args.schedule],
+                                tune=0 if args.no_tune else 1)
+        s7.bicgstab_solve(dims8, c8, b8, x8, 1e-300, args.warmup, ws=ws, opt=o8)
+        x8.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        i8 = s7.bicgstab_solve(dims8, c8, b8, x8, 1e-300, args.steps, ws=ws, opt=o8)
+        torch.cuda.synchronize()
+        dt8 = time.perf_counter() - t0
+        by8 = BYTES[("f32", PASSES[i8.schedule])]
+        pm8 = {k: i8.pass_ms[SLOT[k]] / max(i8.pass_count[SLOT[k]], 1) for k in by8}
+        out["z_slab_share_of_8"] = {
+            "workload": f"FP32 on {dims8[0]}x{dims8[1]}x{dims8[2]}, one GPU's z-slab of the "
+                        f"{nx}x{ny}x{nz} mesh split over 8 GPUs (halo exchange and all-reduce not included)",
+            "iter_per_s": round(i8.iters / dt8, 2), "schedule": i8.schedule,
+            "hbm_frac_per_iteration": round(sum(by8.values()) * n8 * i8.iters / dt8 / 1e9 / HBM_PEAK_GBS, 4),
+            "passes_GB/s": {k: round(by8[k] * n8 / (ms * 1e-3) / 1e9, 1) for k, ms in pm8.items()}}
 
     # ---- mixed: BF16 storage, FP32 arithmetic, inside FP64 refinement
     if not args.no_mixed:
