@@ -1,4 +1,4 @@
-"""FP64 CPU oracle for BiCGStab on 7-point stencil systems.
+"""FP64 CPU oracle for BiCGStab on 7-point stencil systems and 2D 9-point systems.
 
 TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package.  The GPU library never
@@ -66,6 +66,10 @@ def _load():
         lib.oracle_csr_nnz.argtypes = [C.c_int32] * 3
         lib.oracle_build_csr.restype = C.c_int64
         lib.oracle_build_csr.argtypes = [C.c_int32] * 3 + [_fp] * 7 + [_ip, _ip, _dp]
+        lib.oracle_csr_nnz_2d9.restype = C.c_int64
+        lib.oracle_csr_nnz_2d9.argtypes = [C.c_int32] * 2
+        lib.oracle_build_csr_2d9.restype = C.c_int64
+        lib.oracle_build_csr_2d9.argtypes = [C.c_int32] * 2 + [_fp] * 9 + [_ip, _ip, _dp]
         lib.oracle_spmv.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, _dp]
         lib.oracle_spmv_rows.argtypes = [C.c_int64, C.c_int64, _ip, _ip, _dp, _dp, _dp]
         lib.oracle_dot.restype = C.c_double
@@ -121,6 +125,22 @@ def build_csr(nx: int, ny: int, nz: int, coef) -> CSR:
                                _i(rowptr), _i(col), _d(val))
     assert got == nnz
     return CSR(n, rowptr, col, val, (nx, ny, nz))
+
+
+def build_csr_2d9(nx: int, ny: int, coef) -> CSR:
+    """CSR of the 2D 9-point operator from coef = (diag, w, e, s, n, sw, se, nw, ne), float32."""
+    lib = _load()
+    n = nx * ny
+    cs = [np.ascontiguousarray(c, dtype=np.float32) for c in coef]
+    assert len(cs) == 9 and all(c.size == n for c in cs)
+    nnz = lib.oracle_csr_nnz_2d9(nx, ny)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(nnz, dtype=np.int64)
+    val = np.zeros(nnz, dtype=np.float64)
+    got = lib.oracle_build_csr_2d9(nx, ny, *[c.ctypes.data_as(_fp) for c in cs], _i(rowptr), _i(col),
+                                   _d(val))
+    assert got == nnz
+    return CSR(n, rowptr, col, val, (nx, ny, 1))
 
 
 def spmv(A: CSR, x: np.ndarray) -> np.ndarray:

@@ -1,6 +1,6 @@
 /*
  * FP64 CPU oracle for BiCGStab on the 7-point variable-coefficient stencil
- * system.  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU
+ * system (and on the 2D 9-point operator of section IV, "SpMV (2D)").  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU
  * baseline of the benchmark call it; the GPU library never does, and the two
  * share no code.
  *
@@ -102,6 +102,48 @@ int64_t oracle_build_csr(int32_t nx, int32_t ny, int32_t nz,
                 rowptr[c + 1] = e;
             }
     return e;
+}
+
+/*
+ * The 2D 9-point operator (section IV, "SpMV (2D)"): on an nx x ny mesh, row
+ * (i,j) holds the main diagonal and eight off-diagonals w, e, s, n (the four
+ * axis neighbours: w multiplies the value at (i-1,j), e at (i+1,j), s at
+ * (i,j-1), n at (i,j+1)) and sw, se, nw, ne (the corners: sw multiplies the
+ * value at (i-1,j-1), se at (i+1,j-1), nw at (i-1,j+1), ne at (i+1,j+1)).
+ * Neighbours outside the mesh are zero and their coefficients are not
+ * entered.  Arrays are nx*ny floats, x fastest.
+ */
+int64_t oracle_csr_nnz_2d9(int32_t nx, int32_t ny) {
+    int64_t e = 0;
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i)
+            for (int64_t dj = -1; dj <= 1; ++dj)
+                for (int64_t di = -1; di <= 1; ++di)
+                    if (i + di >= 0 && i + di < nx && j + dj >= 0 && j + dj < ny) ++e;
+    return e;
+}
+
+int64_t oracle_build_csr_2d9(int32_t nx, int32_t ny, const float *diag, const float *w,
+                             const float *e, const float *s, const float *n,
+                             const float *sw, const float *se, const float *nw,
+                             const float *ne, int64_t *rowptr, int64_t *col, double *val) {
+    /* the coefficient of neighbour (di, dj), by (dj+1)*3 + (di+1): ascending columns */
+    const float *by[9] = {sw, s, se, w, diag, e, nw, n, ne};
+    int64_t k = 0;
+    rowptr[0] = 0;
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+            const int64_t c = i + nx * j;
+            for (int64_t dj = -1; dj <= 1; ++dj)
+                for (int64_t di = -1; di <= 1; ++di) {
+                    if (i + di < 0 || i + di >= nx || j + dj < 0 || j + dj >= ny) continue;
+                    col[k] = c + di + nx * dj;
+                    val[k] = (double)by[(dj + 1) * 3 + (di + 1)][c];
+                    ++k;
+                }
+            rowptr[c + 1] = k;
+        }
+    return k;
 }
 
 /* y = A x, each row summed left to right over its entries. */

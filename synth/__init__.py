@@ -153,6 +153,29 @@ def make_problem(nx: int, ny: int, nz: int, seed: int = 0, recipe: int = RECIPE_
 
 
 # ---------------------------------------------------------------------------
+# The 2D 9-point operator (section IV, "SpMV (2D)")
+# ---------------------------------------------------------------------------
+# Off-diagonal ids 20..27 = w, e, s, n, sw, se, nw, ne; each drawn as the 3D
+# off-diagonals are, -(0.5 + m 2^-24) per cell.  Diagonal: fl32(sum |off| +
+# 0.1), the eight magnitudes summed in FP64 in that order (exact), outward
+# links included.  x* as in 3D (aid 7), over the cells i + nx*j.
+AID_2D9 = tuple(range(20, 28))
+COEF_NAMES_2D9 = ("diag", "w", "e", "s", "n", "sw", "se", "nw", "ne")
+PAPER_MESHES_2D9 = ((4800, 4800), (22800, 22800))  # the sizes section IV names
+
+
+def make_problem_2d9(nx: int, ny: int, seed: int = 0) -> Problem:
+    """Coefficients (diag, w, e, s, n, sw, se, nw, ne) and x* of the 2D 9-point recipe."""
+    cells = np.arange(nx * ny, dtype=np.int64)
+    offs = [offdiag_base(seed, aid, cells) for aid in AID_2D9]
+    acc = np.zeros(cells.shape, dtype=np.float64)
+    for c in offs:
+        acc = acc + np.abs(c.astype(np.float64))
+    diag = (acc + 0.1).astype(np.float32)
+    return Problem(nx, ny, 1, [diag] + offs, xstar_values(seed, cells), cells)
+
+
+# ---------------------------------------------------------------------------
 # Workload shapes (the paper's mesh and the stand-ins around it)
 # ---------------------------------------------------------------------------
 PAPER_MESH = (600, 595, 1536)  # the CS-1 run's mesh
