@@ -308,6 +308,49 @@ int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float *const c
 int s7_bandwidth_probe(int32_t kind, int32_t width, float *a, float *b, float *c, size_t n,
                        int32_t blocks, void *stream);
 
+/*
+ * The 2D 9-point operator (section IV, "SpMV (2D)"; the paper sizes it at
+ * 4800 x 4800 and 22800 x 22800 meshes).  On an nx x ny mesh, cell (i,j) is
+ * element i + nx*j (x fastest) and
+ *
+ *   (A v)(i,j) = diag v(i,j) + w v(i-1,j) + e v(i+1,j) + s v(i,j-1) + n v(i,j+1)
+ *              + sw v(i-1,j-1) + se v(i+1,j-1) + nw v(i-1,j+1) + ne v(i+1,j+1).
+ *
+ * Coefficients come as nine device float arrays in the order
+ * {diag, w, e, s, n, sw, se, nw, ne}.  Values outside the mesh are zero and
+ * the coefficients of those outward links are ignored.  nx*ny must be below
+ * 2^31.  Everything else (ownership, streams, errors) is as for the 3D calls.
+ */
+
+/* u = A v in FP32 (terms in the order above, fused multiply-adds).
+ * Asynchronous on `stream`.  v and u must not alias. */
+int s7_stencil9_apply(int32_t nx, int32_t ny, const float *const coef[9], const float *v, float *u,
+                      void *stream);
+
+/* Workspace for s7_bicgstab_solve_2d9 (0 for invalid dims). */
+size_t s7_workspace_bytes_2d9(int32_t nx, int32_t ny, const s7_options *opt);
+
+/*
+ * BiCGStab (Algorithm 1, the readings of s7_bicgstab_solve) on the 2D 9-point
+ * system, in FP32 storage and arithmetic with FP64 inner products, b and x
+ * FP64 at the boundary; x holds x0 on entry and the solution on return.  The
+ * iteration is the three-pass schedule.  Of the options it reads jacobi,
+ * profile, graph_iters and stream_blocks.  Returns as s7_bicgstab_solve.
+ */
+int s7_bicgstab_solve_2d9(int32_t nx, int32_t ny, const float *const coef[9], const double *b, double *x,
+                          double rtol, int32_t max_iter, void *ws, size_t ws_bytes, const s7_options *opt,
+                          s7_info *info, void *stream);
+
+/*
+ * Synthetic 2D 9-point problem: off-diagonal a (a = 1..8, array id 19 + a)
+ * is -(0.5 + m 2^-24) with m the top 23 bits of the SplitMix64 hash of
+ * (seed, array id, cell); diag = fl32(sum |off| + 0.1), summed in FP64 in
+ * the order above; x* as in s7_generate_problem; b = A x* in FP64.  Any of
+ * coef[c], xstar and b may be NULL to skip it; b needs all nine and xstar.
+ */
+int s7_generate_problem_2d9(int32_t nx, int32_t ny, uint64_t seed, float *const coef[9], double *xstar,
+                            double *b, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

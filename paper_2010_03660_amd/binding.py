@@ -25,7 +25,8 @@ __all__ = [
     "Dims", "Options", "Info", "Request", "lib", "default_options", "last_error", "version",
     "stencil_apply", "workspace_bytes", "bicgstab_solve", "batched_workspace_bytes",
     "bicgstab_solve_batched", "queue_table_bytes", "queue_create", "queue_submit", "queue_poll", "queue_wait",
-    "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error",
+    "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error", "stencil9_apply",
+    "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
     "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
@@ -92,6 +93,12 @@ EXPORTS = {
     "s7_queue_destroy": (C.c_int, [_vp]),
     "s7_generate_problem": (C.c_int, [Dims, C.c_uint64, C.c_int32, C.POINTER(_vp), _vp, _vp, _vp]),
     "s7_bandwidth_probe": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_size_t, C.c_int32, _vp]),
+    "s7_stencil9_apply": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_vp), _vp, _vp, _vp]),
+    "s7_workspace_bytes_2d9": (C.c_size_t, [C.c_int32, C.c_int32, C.POINTER(Options)]),
+    "s7_bicgstab_solve_2d9": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_vp), _vp, _vp, C.c_double,
+                                        C.c_int32, _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info),
+                                        _vp]),
+    "s7_generate_problem_2d9": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_vp), _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -269,3 +276,39 @@ def generate_problem(dims, seed: int, recipe: int, coef=None, xstar=None, b=None
 def bandwidth_probe(kind: int, width: int, a, b, c, n: int, blocks: int, stream=None) -> None:
     _check(lib().s7_bandwidth_probe(int(kind), int(width), _ptr(a), _ptr(b), _ptr(c), int(n),
                                     int(blocks), _stream(stream)), allow=(OK,))
+
+
+# ---- the 2D 9-point operator: coefficients (diag, w, e, s, n, sw, se, nw, ne)
+def _coef9(coef: Sequence) -> C.Array:
+    if len(coef) != 9:
+        raise ValueError("need 9 coefficient arrays: diag, w, e, s, n, sw, se, nw, ne")
+    return (_vp * 9)(*[_ptr(c) for c in coef])
+
+
+def stencil9_apply(nx: int, ny: int, coef, v, u, stream=None) -> None:
+    _check(lib().s7_stencil9_apply(int(nx), int(ny), _coef9(coef), _ptr(v), _ptr(u), _stream(stream)),
+           allow=(OK,))
+
+
+def workspace_bytes_2d9(nx: int, ny: int, opt: Options | None = None) -> int:
+    return int(lib().s7_workspace_bytes_2d9(int(nx), int(ny), C.byref(opt) if opt else None))
+
+
+def bicgstab_solve_2d9(nx: int, ny: int, coef, b, x, rtol, max_iter, ws=None,
+                       opt: Options | None = None, stream=None) -> Info:
+    """FP32 BiCGStab on the 2D 9-point system, in place in x (x0 on entry)."""
+    info = Info()
+    nbytes = workspace_bytes_2d9(nx, ny, opt)
+    ws = _workspace(nbytes, ws)
+    wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
+    rc = lib().s7_bicgstab_solve_2d9(int(nx), int(ny), _coef9(coef), _ptr(b), _ptr(x), float(rtol),
+                                     int(max_iter), _ptr(ws), wsb, C.byref(opt) if opt else None,
+                                     C.byref(info), _stream(stream))
+    _check(rc)
+    return info
+
+
+def generate_problem_2d9(nx: int, ny: int, seed: int, coef=None, xstar=None, b=None, stream=None):
+    cp = _coef9(coef) if coef is not None else None
+    _check(lib().s7_generate_problem_2d9(int(nx), int(ny), int(seed), cp, _ptr(xstar), _ptr(b),
+                                         _stream(stream)), allow=(OK,))

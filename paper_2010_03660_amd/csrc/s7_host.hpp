@@ -66,7 +66,9 @@ struct Layout {
     size_t n;
 };
 
-Layout make_layout(s7_dims d, int prec, const s7_options& o);
+// ncoef: working coefficient copies (0: 6 with Jacobi scaling, else 7, the
+// 7-point operator).
+Layout make_layout(s7_dims d, int prec, const s7_options& o, int ncoef = 0);
 
 void options_or_default(const s7_options* in, s7_options& out);
 

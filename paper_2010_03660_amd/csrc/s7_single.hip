@@ -49,11 +49,11 @@ void options_or_default(const s7_options* in, s7_options& out) {
     }
 }
 
-Layout make_layout(s7_dims d, int prec, const s7_options& o) {
+Layout make_layout(s7_dims d, int prec, const s7_options& o, int ncoef) {
     Layout L;
     L.n = (size_t)d.nx * d.ny * d.nz;
     L.elt = elt_size(prec);
-    L.ncoef = o.jacobi ? 6 : 7;
+    L.ncoef = ncoef > 0 ? ncoef : (o.jacobi ? 6 : 7);
     L.cell_blocks = cell_blocks_for((long long)L.n);
     L.stream_blocks = stream_blocks_for((long long)L.n, o.stream_blocks);
     // partials for any streaming split up to kSingleMax, so the workspace size
@@ -1452,3 +1452,6 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
 }
 
 }  // extern "C"
+
+// The 2D 9-point operator (section IV, "SpMV (2D)"), on the same machinery.
+#include "s7_stencil9.hpp"
