@@ -11,7 +11,8 @@ mixed BF16+refinement form, accuracy of converged runs against the manufactured
 solution, the batched form (64 uneven systems), the served form (a Poisson request
 stream through the queue against a serial loop of single solves, p50/p99 latency), the
 solver pattern of the paper's SIMPLE loop (Algorithm 2), one GPU's z-slab share of the mesh
-for an 8-GPU split, and the FP64 CPU oracle timed on a bounded slab of the same workload.
+for an 8-GPU split, the 2D 9-point workload of section IV at 4800^2 and 22800^2, and the
+FP64 CPU oracle timed on a bounded slab of the same workload.
 """
 from __future__ import annotations
 
@@ -209,6 +210,51 @@ def simple_leg(s7, torch, dev, dims, outer: int):
             "us_per_cell_outer_batched": round(tb / outer / n * 1e6, 5)}
 
 
+# 2D 9-point, Jacobi (8 coefficient arrays), FP32: algorithmic bytes per cell
+BYTES_2D9 = {"p1": (1 + 1 + 8) * 4 + 4,   # p, r0, 8 coef; s
+             "p2": (2 + 1 + 8) * 4 + 4,   # r, s, r0, 8 coef; y
+             "p3": 6 * 4 + 3 * 4}         # d, p, r, s, y, r0; d, r, p
+
+
+def stencil9_leg(s7, torch, dev, steps: int, warmup: int):
+    """The 2D 9-point workload of section IV at the two sizes the paper names: FP32
+    BiCGStab, `steps` timed iterations, with the passes timed by HIP events."""
+    out = []
+    for nx, ny in ((4800, 4800), (22800, 22800)):
+        n = nx * ny
+        c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(9)]
+        xs = torch.empty(n, dtype=torch.float64, device=dev)
+        b = torch.empty(n, dtype=torch.float64, device=dev)
+        s7.generate_problem_2d9(nx, ny, 0, c, xs, b)
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        ws = torch.empty(s7.workspace_bytes_2d9(nx, ny), dtype=torch.uint8, device=dev)
+        o = s7.default_options(profile=1)
+        s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-300, warmup, ws=ws, opt=o)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-300, steps, ws=ws, opt=o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pm = {k: info.pass_ms[SLOT[k]] / max(info.pass_count[SLOT[k]], 1) for k in BYTES_2D9}
+        per_iter = sum(BYTES_2D9.values()) * n
+        # a converged run to rtol 1e-8: error against the manufactured solution
+        x.zero_()
+        conv = s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-8, 2000, ws=ws)
+        err = float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))
+        out.append({"workload": f"2D 9-point, FP32, Jacobi, {nx}x{ny} ({n} cells)",
+                    "iter_per_s": round(info.iters / dt, 2),
+                    "bytes_per_cell_iteration": sum(BYTES_2D9.values()),
+                    "hbm_frac_per_iteration": round(per_iter * info.iters / dt / 1e9 / HBM_PEAK_GBS, 4),
+                    "passes": {k: {"avg_ms": round(ms, 4), "GB/s": round(BYTES_2D9[k] * n / (ms * 1e-3) / 1e9, 1)}
+                               for k, ms in pm.items()},
+                    "converged_rtol1e-8": {"status": conv.status, "iters": conv.iters,
+                                           "rel_res_true": conv.rel_res_true, "rel_err_vs_xstar": err}})
+        del c, xs, b, x, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def served_leg(s7, torch, dev, nreq: int, rate: float, burst: int, arena_gb: float, sample: int):
     """The request stream: Poisson arrivals at `rate` per second, sides log-uniform in
     [16,256] per axis, half FP32 at rtol 1e-6 and half BF16 + FP64 refinement at 1e-10.
@@ -362,6 +408,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-simple", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
+    ap.add_argument("--no-2d9", action="store_true")
     ap.add_argument("--simple-dims", type=int, nargs=3, default=[100, 400, 100])
     ap.add_argument("--simple-outer", type=int, default=15)
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -525,6 +572,9 @@ def main():
         out["simple_pattern"] = [simple_leg(s7, torch, dev, args.simple_dims, args.simple_outer),
                                  simple_leg(s7, torch, dev, (40, 40, 40), 4 * args.simple_outer)]
         torch.cuda.empty_cache()
+    if not args.no_2d9:
+        print("[bench] 2D 9-point", file=sys.stderr, flush=True)
+        out["stencil9_2d"] = stencil9_leg(s7, torch, dev, args.steps, args.warmup)
     if not args.no_serve:
         out["served"] = served_leg(s7, torch, dev, args.serve_requests, args.serve_rate,
                                    args.serve_burst, args.arena_gb, args.serve_sample)
