@@ -216,9 +216,15 @@ BYTES_2D9 = {"p1": (1 + 1 + 8) * 4 + 4,   # p, r0, 8 coef; s
              "p3": 6 * 4 + 3 * 4}         # d, p, r, s, y, r0; d, r, p
 
 
+BYTES_2D9_16 = {"p1": (1 + 1 + 8) * 2 + 2,
+                "p2": (2 + 1 + 8) * 2 + 2,
+                "p3": 4 + 5 * 2 + 4 + 2 * 2}  # d FP32; p, r, s, y, r0 16-bit; d, r, p written
+
+
 def stencil9_leg(s7, torch, dev, steps: int, warmup: int):
     """The 2D 9-point workload of section IV at the two sizes the paper names: FP32
-    BiCGStab, `steps` timed iterations, with the passes timed by HIP events."""
+    BiCGStab, `steps` timed iterations with the passes timed by HIP events, and the
+    BF16 inner iteration inside FP64 refinement."""
     out = []
     for nx, ny in ((4800, 4800), (22800, 22800)):
         n = nx * ny
@@ -227,7 +233,8 @@ def stencil9_leg(s7, torch, dev, steps: int, warmup: int):
         b = torch.empty(n, dtype=torch.float64, device=dev)
         s7.generate_problem_2d9(nx, ny, 0, c, xs, b)
         x = torch.zeros(n, dtype=torch.float64, device=dev)
-        ws = torch.empty(s7.workspace_bytes_2d9(nx, ny), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(s7.workspace_bytes_2d9(nx, ny, pr) for pr in (s7.FP32, s7.BF16_IR)),
+                         dtype=torch.uint8, device=dev)
         o = s7.default_options(profile=1)
         s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-300, warmup, ws=ws, opt=o)
         x.zero_()
@@ -242,7 +249,24 @@ def stencil9_leg(s7, torch, dev, steps: int, warmup: int):
         x.zero_()
         conv = s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-8, 2000, ws=ws)
         err = float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))
+        # BF16 storage inside FP64 refinement: inner iterations timed, then converged to 1e-10
+        x.zero_()
+        s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-300, warmup, prec=s7.BF16_IR, ws=ws, opt=o)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        i16 = s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-300, steps, prec=s7.BF16_IR, ws=ws, opt=o)
+        torch.cuda.synchronize()
+        dt16 = time.perf_counter() - t0
+        x.zero_()
+        c16 = s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-10, 2000, prec=s7.BF16_IR, ws=ws)
+        err16 = float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))
         out.append({"workload": f"2D 9-point, FP32, Jacobi, {nx}x{ny} ({n} cells)",
+                    "bf16_ir": {"inner_iter_per_s": round(i16.iters / dt16, 2),
+                                "bytes_per_cell_inner_iteration": sum(BYTES_2D9_16.values()),
+                                "converged_rtol1e-10": {"status": c16.status, "inner_iters": c16.iters,
+                                                        "outer": c16.outer_iters, "rel_res_true": c16.rel_res_true,
+                                                        "rel_err_vs_xstar": err16}},
                     "iter_per_s": round(info.iters / dt, 2),
                     "bytes_per_cell_iteration": sum(BYTES_2D9.values()),
                     "hbm_frac_per_iteration": round(per_iter * info.iters / dt / 1e9 / HBM_PEAK_GBS, 4),

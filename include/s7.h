@@ -327,19 +327,22 @@ int s7_bandwidth_probe(int32_t kind, int32_t width, float *a, float *b, float *c
 int s7_stencil9_apply(int32_t nx, int32_t ny, const float *const coef[9], const float *v, float *u,
                       void *stream);
 
-/* Workspace for s7_bicgstab_solve_2d9 (0 for invalid dims). */
-size_t s7_workspace_bytes_2d9(int32_t nx, int32_t ny, const s7_options *opt);
+/* Workspace for s7_bicgstab_solve_2d9 (0 for invalid dims or precision). */
+size_t s7_workspace_bytes_2d9(int32_t nx, int32_t ny, int32_t prec, const s7_options *opt);
 
 /*
  * BiCGStab (Algorithm 1, the readings of s7_bicgstab_solve) on the 2D 9-point
- * system, in FP32 storage and arithmetic with FP64 inner products, b and x
- * FP64 at the boundary; x holds x0 on entry and the solution on return.  The
+ * system; x holds x0 on entry and the solution on return, b and x FP64.
+ * prec as for s7_bicgstab_solve: S7_FP32 stores and computes in FP32 with
+ * FP64 inner products; S7_BF16_IR and S7_FP16_IR store in 16 bits inside FP64
+ * iterative refinement (the same outer loop, tolerances and caps).  The
  * iteration is the three-pass schedule.  Of the options it reads jacobi,
- * profile, graph_iters and stream_blocks.  Returns as s7_bicgstab_solve.
+ * profile, graph_iters, stream_blocks and the refinement fields.  Returns as
+ * s7_bicgstab_solve.
  */
 int s7_bicgstab_solve_2d9(int32_t nx, int32_t ny, const float *const coef[9], const double *b, double *x,
-                          double rtol, int32_t max_iter, void *ws, size_t ws_bytes, const s7_options *opt,
-                          s7_info *info, void *stream);
+                          double rtol, int32_t max_iter, int32_t prec, void *ws, size_t ws_bytes,
+                          const s7_options *opt, s7_info *info, void *stream);
 
 /*
  * Synthetic 2D 9-point problem: off-diagonal a (a = 1..8, array id 19 + a)

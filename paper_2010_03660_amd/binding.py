@@ -94,10 +94,10 @@ EXPORTS = {
     "s7_generate_problem": (C.c_int, [Dims, C.c_uint64, C.c_int32, C.POINTER(_vp), _vp, _vp, _vp]),
     "s7_bandwidth_probe": (C.c_int, [C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_size_t, C.c_int32, _vp]),
     "s7_stencil9_apply": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_vp), _vp, _vp, _vp]),
-    "s7_workspace_bytes_2d9": (C.c_size_t, [C.c_int32, C.c_int32, C.POINTER(Options)]),
+    "s7_workspace_bytes_2d9": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(Options)]),
     "s7_bicgstab_solve_2d9": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(_vp), _vp, _vp, C.c_double,
-                                        C.c_int32, _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info),
-                                        _vp]),
+                                        C.c_int32, C.c_int32, _vp, C.c_size_t, C.POINTER(Options),
+                                        C.POINTER(Info), _vp]),
     "s7_generate_problem_2d9": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_vp), _vp, _vp, _vp]),
 }
 
@@ -290,19 +290,19 @@ def stencil9_apply(nx: int, ny: int, coef, v, u, stream=None) -> None:
            allow=(OK,))
 
 
-def workspace_bytes_2d9(nx: int, ny: int, opt: Options | None = None) -> int:
-    return int(lib().s7_workspace_bytes_2d9(int(nx), int(ny), C.byref(opt) if opt else None))
+def workspace_bytes_2d9(nx: int, ny: int, prec=FP32, opt: Options | None = None) -> int:
+    return int(lib().s7_workspace_bytes_2d9(int(nx), int(ny), int(prec), C.byref(opt) if opt else None))
 
 
-def bicgstab_solve_2d9(nx: int, ny: int, coef, b, x, rtol, max_iter, ws=None,
+def bicgstab_solve_2d9(nx: int, ny: int, coef, b, x, rtol, max_iter, prec=FP32, ws=None,
                        opt: Options | None = None, stream=None) -> Info:
-    """FP32 BiCGStab on the 2D 9-point system, in place in x (x0 on entry)."""
+    """BiCGStab on the 2D 9-point system, in place in x (x0 on entry)."""
     info = Info()
-    nbytes = workspace_bytes_2d9(nx, ny, opt)
+    nbytes = workspace_bytes_2d9(nx, ny, prec, opt)
     ws = _workspace(nbytes, ws)
     wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
     rc = lib().s7_bicgstab_solve_2d9(int(nx), int(ny), _coef9(coef), _ptr(b), _ptr(x), float(rtol),
-                                     int(max_iter), _ptr(ws), wsb, C.byref(opt) if opt else None,
+                                     int(max_iter), int(prec), _ptr(ws), wsb, C.byref(opt) if opt else None,
                                      C.byref(info), _stream(stream))
     _check(rc)
     return info

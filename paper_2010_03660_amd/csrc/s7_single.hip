@@ -842,13 +842,13 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
     return h.status;
 }
 
-template <class T>
-static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol,
-                    int max_iter, char* ws, const Layout& Lo, const s7_options& o,
-                    s7_info* info, hipStream_t s, int prec) {
-    SysView<T> S = make_view<T>(d, Lo, o.jacobi, ws);
-    int rc = start_solve<T>(cf, S, Lo, o.jacobi, s);
-    if (rc) return rc;
+// The outer loop of iterative refinement (reading 13), for any operator:
+// resid() forms the FP64 residual b - A x into State (||b||^2, ||r||^2,
+// max |r_s|) and r_s into d as FP32; iterate(h) runs an inner solve from the
+// State that k_ir_init set, leaving it in *h.
+template <class T, class Resid, class Iterate>
+static int refine(const SysView<T>& S, double* x, double rtol, int max_iter, const s7_options& o, int prec,
+                  int schedule, s7_info* info, hipStream_t s, Resid resid, Iterate iterate) {
     auto t0 = std::chrono::steady_clock::now();
     const double inner_tol = o.inner_rtol > 0 ? o.inner_rtol : (prec == S7_FP16_IR ? 5e-3 : 1e-2);
     const int inner_cap = o.inner_max_iter > 0 ? o.inner_max_iter : 100;
@@ -857,11 +857,10 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
     double rel = INFINITY, inner_res = 0.0;
     int stall = 0;
     State h;
+    int rc;
     for (;;) {
-        rc = resid_launch<T>(cf, b, x, S.d, S, o.jacobi, s);
-        if (rc) return rc;
-        rc = read_state(S.st, &h, s);
-        if (rc) return rc;
+        if ((rc = resid())) return rc;
+        if ((rc = read_state(S.st, &h, s))) return rc;
         if (h.bb_true == 0.0) {
             hipLaunchKernelGGL(k_fill0, dim3(grid_for(S.n)), dim3(kThreads), 0, s, x, S.n);
             S7_CHECK_LAUNCH();
@@ -898,8 +897,7 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
                            (float)(1.0 / scale), inner_tol,
                            inner_cap < max_iter - total ? inner_cap : max_iter - total);
         S7_CHECK_LAUNCH();
-        rc = run_iterations<T>(S, o, s, &h, info);
-        if (rc) return rc;
+        if ((rc = iterate(&h))) return rc;
         total += h.iter;
         outer += 1;
         inner_res = h.res_rec;
@@ -919,12 +917,24 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
         info->reason = reason;
         info->iters = total;
         info->outer_iters = outer;
-        info->schedule = effective_schedule(o, S);
+        info->schedule = schedule;
         info->rel_res_true = rel;
         info->rel_res_rec = inner_res;
         info->t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     return status;
+}
+
+template <class T>
+static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol,
+                    int max_iter, char* ws, const Layout& Lo, const s7_options& o,
+                    s7_info* info, hipStream_t s, int prec) {
+    SysView<T> S = make_view<T>(d, Lo, o.jacobi, ws);
+    int rc = start_solve<T>(cf, S, Lo, o.jacobi, s);
+    if (rc) return rc;
+    return refine<T>(S, x, rtol, max_iter, o, prec, effective_schedule(o, S), info, s,
+                     [&]() { return resid_launch<T>(cf, b, x, S.d, S, o.jacobi, s); },
+                     [&](State* h) { return run_iterations<T>(S, o, s, h, info); });
 }
 
 // ============================================================== batch engine

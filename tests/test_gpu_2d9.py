@@ -151,6 +151,29 @@ def test_degenerate_inputs(s7):
         s7.bicgstab_solve_2d9(0, 5, coef, dev(b), dev(x), 1e-8, 10)
 
 
+@pytest.mark.parametrize("prec", ["bf16_ir", "fp16_ir"])
+@pytest.mark.parametrize("dims", [(64, 48), (129, 33)])
+def test_mixed_precision_refinement(s7, prec, dims):
+    """16-bit storage inside FP64 refinement reaches the FP64 oracle's solution."""
+    import torch
+    p, A, b = problem9(dims, seed=6)
+    ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
+    x = dev(np.zeros(A.n))
+    info = s7.bicgstab_solve_2d9(*dims, [dev(c) for c in p.coef], dev(b), x, 1e-10, 2000,
+                                 prec=s7.PREC_NAMES[prec])
+    torch.cuda.synchronize()
+    assert info.status == s7.OK and info.rel_res_true <= 1e-10
+    assert abs(info.rel_res_true - oracle.true_rel_residual(A, b, host(x))) <= 1e-3 * info.rel_res_true + 1e-16
+    assert rel_err(host(x), ref.x) <= 1e-7
+    assert info.outer_iters > 1
+    # b = 0: x = 0 exactly
+    x0 = dev(np.ones(A.n))
+    info = s7.bicgstab_solve_2d9(*dims, [dev(c) for c in p.coef], dev(np.zeros(A.n)), x0, 1e-10, 100,
+                                 prec=s7.PREC_NAMES[prec])
+    torch.cuda.synchronize()
+    assert info.status == s7.OK and np.all(host(x0) == 0)
+
+
 def test_paper_size_4800_manufactured_solution(s7):
     import torch
     nx = ny = 4800
