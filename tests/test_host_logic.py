@@ -88,3 +88,14 @@ def test_bench_byte_accounting_matches_the_design():
     # P1: p, r0 and 6 coefficients read, s written, 4 bytes each
     assert bench.BYTES[("f32", 3)]["p1"] == (1 + 1 + 6) * 4 + 4
     assert set(bench.KERNEL) == set(bench.PASSES) == {1, 2, 3}
+
+
+def test_bench_byte_accounting_2d9():
+    """2D 9-point, Jacobi (8 coefficient arrays): 128 B per cell and iteration in FP32,
+    68 B with 16-bit storage (the FP32 correction d stays 4 bytes)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.BYTES_2D9 == {"p1": 44, "p2": 48, "p3": 36}
+    assert sum(bench.BYTES_2D9.values()) == 128
+    assert bench.BYTES_2D9_16 == {"p1": 22, "p2": 24, "p3": 22}
+    assert sum(bench.BYTES_2D9_16.values()) == 68
