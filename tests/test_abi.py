@@ -100,3 +100,35 @@ def test_queue_host_side_checks():
     assert lib.s7_queue_poll(None, 1, None) == B.EINVAL
     assert lib.s7_queue_wait(None, 1, None) == B.EINVAL
     assert lib.s7_queue_destroy(None) == B.EINVAL
+
+
+def test_host_side_argument_checks_2d9():
+    """The 2D 9-point calls validate on the host: dims, precision, tolerance, caps,
+    workspace size and alignment, aliasing.  The workspace holds 8 (Jacobi) or 9
+    coefficient copies, six vectors and the FP32 correction."""
+    from paper_2010_03660_amd import binding as B
+    lib = B.lib()
+    assert lib.s7_workspace_bytes_2d9(0, 4, 0, None) == 0
+    assert lib.s7_workspace_bytes_2d9(65536, 32768, 0, None) == 0  # N >= 2^31
+    assert lib.s7_workspace_bytes_2d9(8, 8, 7, None) == 0          # no such precision
+    n = 1000 * 1000
+    f32 = lib.s7_workspace_bytes_2d9(1000, 1000, B.FP32, None)
+    b16 = lib.s7_workspace_bytes_2d9(1000, 1000, B.BF16_IR, None)
+    assert f32 >= (8 + 6 + 1) * n * 4 and b16 >= (8 + 6) * n * 2 + n * 4 and b16 < f32
+    o = B.default_options(jacobi=0)
+    assert lib.s7_workspace_bytes_2d9(1000, 1000, B.FP32, C.byref(o)) >= f32 + n * 4
+    coef = (C.c_void_p * 9)(*([256] * 9))
+    info = B.Info()
+    for nx, rtol, mi, prec in ((8, -1.0, 10, 0), (8, float("nan"), 10, 0), (8, 1e-6, -1, 0), (0, 1e-6, 10, 0),
+                               (8, 1e-6, 10, 5)):
+        rc = lib.s7_bicgstab_solve_2d9(nx, 8, coef, 256, 512, rtol, mi, prec, 1024, 1 << 20, None,
+                                       C.byref(info), 0)
+        assert rc == B.EINVAL and "invalid" in B.last_error(), (nx, rtol, mi, prec)
+    rc = lib.s7_bicgstab_solve_2d9(8, 8, coef, 256, 512, 1e-6, 10, 0, 1024, 16, None, C.byref(info), 0)
+    assert rc == B.EINVAL and "workspace" in B.last_error()
+    rc = lib.s7_bicgstab_solve_2d9(8, 8, coef, 256, 512, 1e-6, 10, 0, 1032, 1 << 30, None, C.byref(info), 0)
+    assert rc == B.EINVAL
+    assert lib.s7_stencil9_apply(8, 8, coef, 4096, 4096, 0) == B.EINVAL
+    missing = (C.c_void_p * 9)(*([256] * 8 + [None]))
+    assert lib.s7_stencil9_apply(8, 8, missing, 4096, 8192, 0) == B.EINVAL
+    assert lib.s7_generate_problem_2d9(8, 8, 0, None, None, 4096, 0) == B.EINVAL  # b needs coef and x*
