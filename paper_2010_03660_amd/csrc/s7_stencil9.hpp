@@ -5,16 +5,15 @@
 //
 // FP32 storage, or BF16/FP16 storage inside FP64 iterative refinement (the
 // outer loop shared with the 3D solver).  The iteration is the three-pass
-// schedule of the 3D solver, one cell per
-// thread in the two stencil passes: P1 s = A p with (r0, s); P2 forms
-// q = r - alpha s at the cell and its eight neighbours, y = A q, and the five
-// sums; P3 is the 3D streaming pass unchanged (it touches no coefficient).
-// Working coefficient copies are Jacobi-scaled with every outward link
-// (axis or corner) zeroed, so all nine loads of a cell stay in the mesh and
-// need no test: an off-mesh neighbour reads the cell itself, times zero.
-// Included by the solver translation unit (s7_single.hip) only, after the
-// pieces it shares with the 3D path (State, reductions, P3, x update, graph
-// cache).
+// schedule of the 3D solver, one cell per thread in the two stencil passes:
+// P1 s = A p with (r0, s); P2 forms q = r - alpha s at the cell and its eight
+// neighbours, y = A q, and the five sums; P3 is the 3D streaming pass
+// unchanged (it touches no coefficient).  Working coefficient copies are
+// Jacobi-scaled with every outward link (axis or corner) zeroed, so all nine
+// loads of a cell stay in the mesh and need no test: an off-mesh neighbour
+// reads the cell itself, times zero.  Included by the solver translation
+// unit (s7_single.hip) only, after the pieces it shares with the 3D path
+// (State, reductions, P3, refinement loop, x update, graph cache).
 #pragma once
 
 namespace s7 {
