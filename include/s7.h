@@ -19,7 +19,8 @@
  *
  * Layout.  Every per-cell array is [nz][ny][nx], x fastest: cell (i,j,k) is
  * element i + nx*(j + ny*k).  Coefficients come as seven arrays in the order
- * {diag, xm, xp, ym, yp, zm, zp}.  N = nx*ny*nz must be below 2^31.
+ * {diag, xm, xp, ym, yp, zm, zp}.  N = nx*ny*nz must be at most 2^31 - 2^21
+ * (cell indices are 32-bit, with headroom for the grids that stride over them).
  *
  * Memory.  Every array argument is a DEVICE pointer owned by the caller, for
  * example a PyTorch tensor.  The library allocates no device memory of its
@@ -53,7 +54,7 @@ enum s7_status {
     S7_OK = 0,
     S7_NOT_CONVERGED = 1, /* iteration cap reached; x holds the last iterate */
     S7_BREAKDOWN = 2,     /* see s7_info.reason; x holds the last iterate */
-    S7_EINVAL = -1,       /* null pointer, dim < 1, N >= 2^31, rtol <= 0 or NaN,
+    S7_EINVAL = -1,       /* null pointer, dim < 1, N > 2^31 - 2^21, rtol <= 0 or NaN,
                              max_iter < 0, workspace too small or misaligned */
     S7_ENOMEM = -2,       /* request larger than the whole queue arena */
     S7_EHIP = -3,         /* HIP runtime error (message in s7_last_error) */
@@ -93,7 +94,8 @@ typedef struct {
     int32_t stream_blocks;  /* workgroups of the streaming passes; 0 = auto (at most 256);
                                capped at 1024 */
     int32_t chunk_cells;    /* batched/queue: cells per work item of the persistent
-                               kernel, rounded up to a multiple of 256; 0 = 16384 */
+                               kernel, rounded up to a multiple of 256, at most 2^24;
+                               0 = 16384 */
     int32_t profile;        /* 1: launch without graphs, time every pass with HIP
                                events into s7_info.pass_ms */
     int32_t inner_max_iter; /* IR: inner iteration cap per outer step; 0 = 100 */
@@ -318,8 +320,8 @@ int s7_bandwidth_probe(int32_t kind, int32_t width, float *a, float *b, float *c
  *
  * Coefficients come as nine device float arrays in the order
  * {diag, w, e, s, n, sw, se, nw, ne}.  Values outside the mesh are zero and
- * the coefficients of those outward links are ignored.  nx*ny must be below
- * 2^31.  Everything else (ownership, streams, errors) is as for the 3D calls.
+ * the coefficients of those outward links are ignored.  nx*ny must be at
+ * most 2^31 - 2^21.  Everything else (ownership, streams, errors) is as for the 3D calls.
  */
 
 /* u = A v in FP32 (terms in the order above, fused multiply-adds).

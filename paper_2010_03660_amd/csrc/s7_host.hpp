@@ -30,10 +30,13 @@ void clear_error();
 
 #define S7_CHECK_LAUNCH() S7_HIP(hipGetLastError())
 
+// Largest mesh: cell indices are 32-bit, and a thread index or a grid-stride
+// loop may run up to 2^20 past the last cell, so N stays 2^21 below 2^31.
+constexpr long long kMaxCells = (1ll << 31) - (1ll << 21);
 inline bool dims_ok(s7_dims d) {
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) return false;
     long long n = (long long)d.nx * d.ny * d.nz;
-    return n < (1ll << 31);
+    return n <= kMaxCells;
 }
 
 inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }

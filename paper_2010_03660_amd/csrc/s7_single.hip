@@ -998,7 +998,7 @@ int BatchEngine::add(EngineJob* j) {
 // workgroup with no hand-off, and the batch itself supplies the parallelism.
 static int chunk_cells_of(const s7_options& o) {
     int c = o.chunk_cells > 0 ? o.chunk_cells : 16384;
-    if (c > (1 << 30)) c = 1 << 30;
+    if (c > (1 << 24)) c = 1 << 24;  // chunk start + chunk_cells stays within 32 bits
     c = (c + kThreads - 1) / kThreads * kThreads;
     return c;
 }

@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void k9_gen(Coef9 out, double* xstar, int
 
 // ---------------------------------------------------------------- driver
 static bool dims2_ok(int32_t nx, int32_t ny) {
-    return nx >= 1 && ny >= 1 && (long long)nx * ny < (1ll << 31);
+    return nx >= 1 && ny >= 1 && (long long)nx * ny <= kMaxCells;
 }
 
 static Layout make_layout9(int32_t nx, int32_t ny, int prec, const s7_options& o) {

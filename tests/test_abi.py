@@ -56,6 +56,9 @@ def test_host_side_argument_checks():
     assert o.jacobi == 1
     assert lib.s7_workspace_bytes(B.Dims(0, 4, 4), 0, None) == 0
     assert lib.s7_workspace_bytes(B.Dims(2048, 2048, 1024), 0, None) == 0  # N >= 2^31
+    # the largest mesh: N = 2^31 - 2^21 = 2048 * 1024 * 1023, and one column more
+    assert lib.s7_workspace_bytes(B.Dims(2048, 1024, 1023), 0, None) > 0
+    assert lib.s7_workspace_bytes(B.Dims(2049, 1024, 1023), 0, None) == 0
     assert lib.s7_workspace_bytes(B.Dims(8, 8, 8), 0, None) > 0
     coef = (C.c_void_p * 7)(*([256] * 7))
     info = B.Info()
