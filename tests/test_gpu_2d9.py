@@ -4,8 +4,8 @@ The device generator must reproduce the host recipe bit for bit; the stencil
 apply and the solve are checked against the oracle's CSR operator and its
 Algorithm 1 on ragged meshes (tails of a workgroup, one-cell and one-row
 meshes), with and without Jacobi scaling; the first iterates track the
-oracle's; degenerate inputs behave as in 3D; and at the paper's 4800 x 4800
-size the solve reaches the manufactured solution."""
+oracle's; degenerate inputs behave as in 3D; and at the paper's 4800 x 4800 and
+22800 x 22800 sizes the solve reaches the manufactured solution."""
 import numpy as np
 import pytest
 
@@ -174,9 +174,11 @@ def test_mixed_precision_refinement(s7, prec, dims):
     assert info.status == s7.OK and np.all(host(x0) == 0)
 
 
-def test_paper_size_4800_manufactured_solution(s7):
+@pytest.mark.parametrize("side", [4800, 22800])
+def test_paper_sizes_manufactured_solution(s7, side):
+    """The two sizes section IV names, in the launch configuration the bench times."""
     import torch
-    nx = ny = 4800
+    nx = ny = side
     n = nx * ny
     c = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(9)]
     xs = torch.empty(n, dtype=torch.float64, device="cuda")
