@@ -246,3 +246,25 @@ def test_large_requests_take_the_single_system_path(s7):
         assert np.array_equal(host(x1), host(xs[i])), i
         assert i1.iters == info.iters, i
     assert big >= 3
+
+
+def test_three_precisions_resident_together(s7):
+    """FP32, BF16+IR and FP16+IR requests share the persistent launches: each result
+    reaches the oracle's solution and equals the same request solved alone."""
+    import torch
+    mix = [((24, 32, 20), 0), ((17, 13, 9), 2), ((40, 24, 20), 1), ((33, 17, 9), 2), ((9, 7, 5), 0),
+           ((31, 29, 27), 2)]
+    rtol = {0: 1e-8, 1: 1e-10, 2: 1e-10}
+    probs = [problem(d, seed=700 + i) for i, (d, p) in enumerate(mix)]
+    coefs, bs, xs = inputs(probs)
+    reqs = [(d, coefs[i], bs[i], xs[i], rtol[p], 2000, p) for i, (d, p) in enumerate(mix)]
+    out = serve(s7, reqs, 64 << 20, chunk=1024)
+    for i, ((d, prec), (p, A, b), (rc, info)) in enumerate(zip(mix, probs, out)):
+        assert rc == s7.OK and info.status == s7.OK, (i, info.as_dict())
+        ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
+        assert rel_err(host(xs[i]), ref.x) <= (1e-6 if prec == 0 else 1e-7), i
+        x1 = torch.zeros_like(xs[i])
+        rc1, inf1 = s7.bicgstab_solve_batched([d], [coefs[i]], [bs[i]], [x1], [rtol[prec]], [2000], prec=prec,
+                                              opt=s7.default_options(chunk_cells=1024))
+        torch.cuda.synchronize()
+        assert np.array_equal(host(x1), host(xs[i])) and inf1[0].iters == info.iters, i
