@@ -356,6 +356,31 @@ int s7_bicgstab_solve_2d9(int32_t nx, int32_t ny, const float *const coef[9], co
 int s7_generate_problem_2d9(int32_t nx, int32_t ny, uint64_t seed, float *const coef[9], double *xstar,
                             double *b, void *stream);
 
+/* Workspace for s7_bicgstab_solve_batched_2d9 over these nsys meshes
+ * (0 for an invalid mesh or precision). */
+size_t s7_batched_workspace_bytes_2d9(int32_t nsys, const int32_t *nx, const int32_t *ny, int32_t prec,
+                                      const s7_options *opt);
+
+/*
+ * The batched form of s7_bicgstab_solve_2d9: nsys independent 2D 9-point
+ * systems of uneven mesh sizes solved together in one persistent launch, as
+ * s7_bicgstab_solve_batched does for the 7-point operator (section VIII-B's
+ * many compact problems).  Per-system arguments are host arrays of length
+ * nsys: nx[s], ny[s]; coef[9*s + c], device float arrays in the order
+ * {diag, w, e, s, n, sw, se, nw, ne}; b[s] and x[s], device doubles; rtol[s];
+ * max_iter[s].  info, if not NULL, is an array of nsys.  Each iteration is
+ * three phases (P1, P2 with the five sums, P3), one cell per thread; the
+ * refinement steps or the FP32 epilogue also run on the device.  A system's
+ * iterates depend only on that system and chunk_cells.  A mesh of
+ * split_cells cells or more (default 2^21) is solved alone by
+ * s7_bicgstab_solve_2d9 after the shared launch.  Returns as
+ * s7_bicgstab_solve_batched.
+ */
+int s7_bicgstab_solve_batched_2d9(int32_t nsys, const int32_t *nx, const int32_t *ny, const float *const *coef,
+                                  const double *const *b, double *const *x, const double *rtol,
+                                  const int32_t *max_iter, int32_t prec, void *ws, size_t ws_bytes,
+                                  const s7_options *opt, s7_info *info, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,8 @@ __all__ = [
     "stencil_apply", "workspace_bytes", "bicgstab_solve", "batched_workspace_bytes",
     "bicgstab_solve_batched", "queue_table_bytes", "queue_create", "queue_submit", "queue_poll", "queue_wait",
     "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error", "stencil9_apply",
-    "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9",
+    "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9", "batched_workspace_bytes_2d9",
+    "bicgstab_solve_batched_2d9",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
     "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
@@ -99,6 +100,12 @@ EXPORTS = {
                                         C.c_int32, C.c_int32, _vp, C.c_size_t, C.POINTER(Options),
                                         C.POINTER(Info), _vp]),
     "s7_generate_problem_2d9": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_vp), _vp, _vp, _vp]),
+    "s7_batched_workspace_bytes_2d9": (C.c_size_t, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                                    C.c_int32, C.POINTER(Options)]),
+    "s7_bicgstab_solve_batched_2d9": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                                C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
+                                                C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32,
+                                                _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info), _vp]),
 }
 
 _lib = None
@@ -312,3 +319,36 @@ def generate_problem_2d9(nx: int, ny: int, seed: int, coef=None, xstar=None, b=N
     cp = _coef9(coef) if coef is not None else None
     _check(lib().s7_generate_problem_2d9(int(nx), int(ny), int(seed), cp, _ptr(xstar), _ptr(b),
                                          _stream(stream)), allow=(OK,))
+
+
+def _sides(meshes):
+    n = len(meshes)
+    return n, (C.c_int32 * n)(*[int(m[0]) for m in meshes]), (C.c_int32 * n)(*[int(m[1]) for m in meshes])
+
+
+def batched_workspace_bytes_2d9(meshes, prec=FP32, opt: Options | None = None) -> int:
+    """meshes: a list of (nx, ny)."""
+    n, nx, ny = _sides(meshes)
+    return int(lib().s7_batched_workspace_bytes_2d9(n, nx, ny, int(prec), C.byref(opt) if opt else None))
+
+
+def bicgstab_solve_batched_2d9(meshes, coefs, bs, xs, rtols, max_iters, prec=FP32, ws=None,
+                               opt: Options | None = None, stream=None):
+    """Solves len(meshes) 2D 9-point systems in one persistent launch; meshes is a
+    list of (nx, ny), coefs a list of nine arrays each.  Returns (status, [Info])."""
+    n, nx, ny = _sides(meshes)
+    if any(len(cs) != 9 for cs in coefs):
+        raise ValueError("need 9 coefficient arrays per system: diag, w, e, s, n, sw, se, nw, ne")
+    cp = (_vp * (9 * n))(*[_ptr(c) for cs in coefs for c in cs])
+    bp = (_vp * n)(*[_ptr(b) for b in bs])
+    xp = (_vp * n)(*[_ptr(x) for x in xs])
+    rt = (C.c_double * n)(*[float(r) for r in rtols])
+    mi = (C.c_int32 * n)(*[int(m) for m in max_iters])
+    infos = (Info * n)()
+    nbytes = batched_workspace_bytes_2d9(meshes, prec, opt)
+    ws = _workspace(nbytes, ws)
+    wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
+    rc = lib().s7_bicgstab_solve_batched_2d9(n, nx, ny, cp, bp, xp, rt, mi, int(prec), _ptr(ws), wsb,
+                                             C.byref(opt) if opt else None, infos, _stream(stream))
+    _check(rc)
+    return rc, list(infos)

@@ -30,12 +30,16 @@
 // * Every wait is bounded.  A workgroup that finds no work spins with
 //   s_sleep.  After `spin_limit` fruitless tries it records an error and
 //   leaves, and the launch always drains.
+// * The kernel is a template on the operator: OP_7PT, the 3D 7-point
+//   stencil, or OP_9PT, the 2D 9-point stencil of section IV.  One launch
+//   holds systems of one operator.
 // Included by the solver translation unit (s7_single.hip) only.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include "s7_device.hpp"
+#include "s7_stencil9_device.hpp"
 
 namespace s7 {
 
@@ -117,6 +121,8 @@ __device__ __forceinline__ void state_store(State* dst, const State& src) {
 // identical in every instantiation.  Red.part holds nchunk * kMaxDots partials.
 struct BCtl;
 
+enum OpKind : int { OP_7PT = 0, OP_9PT = 1 };
+
 struct BSys {
     SysView<float> S;
     BCtl* ctl;   // the system's control words (in its own workspace slice)
@@ -127,6 +133,10 @@ struct BSys {
     Coef7 cf;    // the caller's FP32 coefficients (residual passes)
     const double* b;
     double* x;
+    // OP_9PT: the caller's coefficients 7 and 8 (nw, ne), and the working
+    // copies of coefficients 7 and 8 (the first seven are in S)
+    const float* cf9[2];
+    const float* wk9[2];
 };
 
 // Phases of a job.  An iteration is P1, P2, P3.  Around the inner
@@ -187,6 +197,7 @@ __global__ void k_ctl_reset(BCtl* ctl, int kind) {
 // written by an earlier kernel, not by a phase of the same launch.
 struct JobStart {
     Coef7 cf;        // the caller's FP32 coefficients
+    const float* cf9[2];  // OP_9PT: the caller's coefficients 7 and 8
     void* coef_dst;  // first working-precision copy; copies are `span` elements apart
     size_t span;
     Mesh m;
@@ -195,7 +206,7 @@ struct JobStart {
     uint32_t* cnt;
     BCtl* ctl;
     double rtol, inner_tol;
-    int inner_cap, outer_cap, max_total, ir;
+    int inner_cap, outer_cap, max_total, ir, op;
 };
 
 template <class T>
@@ -210,6 +221,28 @@ __device__ void start_coef_copies(const JobStart& J, int i0, int step) {
         for (int a = 0; a < 7; ++a) {
             if (a < first) continue;
             float v = in[a] ? J.cf.c[a][i] : 0.0f;
+            if (J.jacobi) v = v / dg;
+            dst0[(size_t)(a - first) * J.span + i] = from_f32<T>(v);
+        }
+    }
+}
+
+// The same for the 2D 9-point operator: c[a] / diag for a = 1..8 with Jacobi
+// scaling, else all nine; outward links (axis or corner) zeroed.
+template <class T>
+__device__ void start_coef_copies9(const JobStart& J, int i0, int step) {
+    const int first = J.jacobi ? 1 : 0;
+    T* dst0 = reinterpret_cast<T*>(J.coef_dst);
+    const Coef9 src = coef9_of(J.cf, J.cf9);
+    for (int i = i0; i < J.n; i += step) {
+        const Cell c = cell_at(i, J.m, J.n);
+        bool in[9];
+        inside9(c, in);
+        const float dg = src.c[0][i];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            if (a < first) continue;
+            float v = in[a] ? src.c[a][i] : 0.0f;
             if (J.jacobi) v = v / dg;
             dst0[(size_t)(a - first) * J.span + i] = from_f32<T>(v);
         }
@@ -241,9 +274,17 @@ __global__ __launch_bounds__(kThreads) void k_jobs_start(const JobStart* jobs) {
         J.ctl->active = 0;
     }
     const int i0 = (int)(blockIdx.x * kThreads + threadIdx.x), step = (int)gridDim.x * kThreads;
-    if (J.tag == 0) start_coef_copies<float>(J, i0, step);
-    else if (J.tag == 1) start_coef_copies<bf16>(J, i0, step);
-    else start_coef_copies<f16>(J, i0, step);
+    if (J.op == OP_9PT) {
+        if (J.tag == 0) start_coef_copies9<float>(J, i0, step);
+        else if (J.tag == 1) start_coef_copies9<bf16>(J, i0, step);
+        else start_coef_copies9<f16>(J, i0, step);
+    } else if (J.tag == 0) {
+        start_coef_copies<float>(J, i0, step);
+    } else if (J.tag == 1) {
+        start_coef_copies<bf16>(J, i0, step);
+    } else {
+        start_coef_copies<f16>(J, i0, step);
+    }
 }
 
 struct BGlobal {
@@ -562,6 +603,160 @@ __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, 
     }
 }
 
+// ---------------------------------------------------------------- 2D 9-point chunk work
+// The nine values of a vector at a cell (order diag, w, e, s, n, sw, se, nw,
+// ne), coherent loads; working vectors widened to FP32.
+template <class T>
+__device__ __forceinline__ void cload9f(const T* v, const Cell& c, float (&x)[9]) {
+    int o[9];
+    offsets9(c, o);
+    const T* p = v + c.idx;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) x[a] = to_f32(cload(p + o[a]));
+}
+__device__ __forceinline__ void cload9d(const double* v, const Cell& c, double (&x)[9]) {
+    int o[9];
+    offsets9(c, o);
+    const double* p = v + c.idx;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) x[a] = cload(p + o[a]);
+}
+
+// The working copies of a 9-point system: the first seven in the view, the
+// last two beside it.
+template <class T>
+__device__ __forceinline__ Coef9T<T> work9(const SysView<T>& S, const float* const (&extra)[2]) {
+    Coef9T<T> k;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) k.c[a] = S.c[a];
+    k.c[7] = reinterpret_cast<const T*>(extra[0]);
+    k.c[8] = reinterpret_cast<const T*>(extra[1]);
+    return k;
+}
+
+// P1: s = A p, rounded to T; (r0, s).  Two cells per thread and step, thread t
+// taking cells base + 256*u + t; all loads of a step before any store.
+constexpr int kU9 = 2;
+template <class T, bool UNIT>
+__device__ void chunk_p1_b9(const SysView<T>& S, const Coef9T<T>& k, int c0, int c1, double (&acc)[kMaxDots]) {
+    for (int base = c0; base < c1; base += kU9 * kThreads) {
+        Cell cl[kU9];
+        float pv[kU9][9];
+        T rh[kU9];
+#pragma unroll
+        for (int u = 0; u < kU9; ++u) {
+            const int g = base + u * kThreads + (int)threadIdx.x;
+            cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
+            cl[u].own = g < c1;
+            cload9f(S.p, cl[u], pv[u]);
+            rh[u] = cload(S.rhat + cl[u].idx);
+        }
+#pragma unroll
+        for (int u = 0; u < kU9; ++u) {
+            const T sv = from_f32<T>(apply9_work<T, UNIT>(k, cl[u].idx, pv[u]));
+            if (cl[u].own) {
+                cstore(S.s + cl[u].idx, sv);
+                acc[0] = fma((double)to_f32(rh[u]), (double)to_f32(sv), acc[0]);
+            }
+        }
+    }
+}
+
+// P2: q = r - alpha s formed in FP32 at the cell and its eight neighbours,
+// y = A q stored; sums (q,y), (y,y), (q,q), (r0,q), (r0,y).
+template <class T, bool UNIT>
+__device__ void chunk_p2f_b9(const SysView<T>& S, const Coef9T<T>& k, int c0, int c1, float alpha,
+                             double (&acc)[kMaxDots]) {
+    for (int base = c0; base < c1; base += kU9 * kThreads) {
+        Cell cl[kU9];
+        float q[kU9][9];
+        T rh[kU9];
+#pragma unroll
+        for (int u = 0; u < kU9; ++u) {
+            const int g = base + u * kThreads + (int)threadIdx.x;
+            cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
+            cl[u].own = g < c1;
+            float rv[9], sv[9];
+            cload9f(S.r, cl[u], rv);
+            cload9f(S.s, cl[u], sv);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) q[u][a] = fmaT(-alpha, sv[a], rv[a]);
+            rh[u] = cload(S.rhat + cl[u].idx);
+        }
+#pragma unroll
+        for (int u = 0; u < kU9; ++u) {
+            const T yt = from_f32<T>(apply9_work<T, UNIT>(k, cl[u].idx, q[u]));
+            if (cl[u].own) {
+                cstore(S.y + cl[u].idx, yt);
+                acc_p2f(acc, (double)q[u][0], (double)to_f32(yt), (double)to_f32(rh[u]));
+            }
+        }
+    }
+}
+
+// R: r = b - A x in FP64 with the caller's coefficients (outward links
+// masked); the rest as for the 7-point operator.
+__device__ void chunk_r_b9(const SysView<float>& S, const Coef9& cf, const double* b, const double* x,
+                           int c0, int c1, bool write_d, double (&acc)[kMaxDots]) {
+    for (int g = c0 + (int)threadIdx.x; g < c1; g += kThreads) {
+        const Cell c = cell_at(g, S.m, S.n);
+        double xv[9];
+        cload9d(x, c, xv);
+        const double bi = b[c.idx];
+        const double r0 = bi - apply9_masked<double>(cf, c, xv);
+        const double rs = S.unit ? r0 / (double)cf.c[0][c.idx] : r0;
+        const float rf = (float)rs;
+        if (write_d) cstore(S.d + c.idx, rf);
+        acc[0] = fma(bi, bi, acc[0]);
+        acc[1] = fma(r0, r0, acc[1]);
+        acc[2] = fmax(acc[2], (double)fabsf(rf));
+    }
+}
+
+// S (FP32 jobs): r0 = b - A x0, as for the 7-point operator.
+__device__ void chunk_s_b9(const SysView<float>& S, const Coef9& cf, const double* b, const double* x,
+                           int c0, int c1, double (&acc)[kMaxDots]) {
+    for (int g = c0 + (int)threadIdx.x; g < c1; g += kThreads) {
+        const Cell c = cell_at(g, S.m, S.n);
+        double xv[9];
+        cload9d(x, c, xv);
+        const double bi = b[c.idx];
+        double r0 = bi - apply9_masked<double>(cf, c, xv), bs = bi;
+        if (S.unit) {
+            const double dg = (double)cf.c[0][c.idx];
+            r0 = r0 / dg;
+            bs = bs / dg;
+        }
+        const float rf = (float)r0;
+        cstore(S.r + c.idx, rf);
+        cstore(S.rhat + c.idx, rf);
+        cstore(S.p + c.idx, rf);
+        cstore(S.d + c.idx, 0.0f);
+        acc[0] = fma(bs, bs, acc[0]);
+        acc[1] = fma((double)rf, (double)rf, acc[1]);
+        acc[2] = fma(bi, bi, acc[2]);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void run_chunk9(const SysView<float>& raw, const float* const (&wk)[2], int phase,
+                                           int c0, int c1, float alpha, float omega, float beta,
+                                           float inv_scale, double (&acc)[kMaxDots]) {
+    const SysView<T> S = as_view<T>(raw);
+    const Coef9T<T> k = work9<T>(S, wk);
+    if (phase == K_I) {
+        chunk_i_b<T>(S, c0, c1, inv_scale, acc);
+    } else if (phase == K_P1) {
+        if (S.unit) chunk_p1_b9<T, true>(S, k, c0, c1, acc);
+        else chunk_p1_b9<T, false>(S, k, c0, c1, acc);
+    } else if (phase == K_P2) {
+        if (S.unit) chunk_p2f_b9<T, true>(S, k, c0, c1, alpha, acc);
+        else chunk_p2f_b9<T, false>(S, k, c0, c1, alpha, acc);
+    } else {
+        chunk_p3_b<T, true>(S, c0, c1, alpha, omega, beta, acc);
+    }
+}
+
 // ---------------------------------------------------------------- job control
 // After the inner iteration stopped (st.done): the FP32 epilogue, or the
 // bookkeeping of one refinement step.  Returns the next phase.
@@ -630,6 +825,7 @@ __device__ int after_resid(State& st, const double (&tot)[kMaxDots]) {
 }
 
 // ---------------------------------------------------------------- persistent kernel
+template <int OP>
 __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* glob,
                                                       int nsys, int chunk_cells,
                                                       long long spin_limit) {
@@ -689,17 +885,27 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
         if (kind == K_X) {
             chunk_x_b(S, B.x, c0, c1, cload_d(&S.st->scale), cload_i(&S.st->xzero) != 0);
         } else if (kind == K_R) {
-            chunk_r_b(S, B.cf, B.b, B.x, c0, c1, cload_i(&S.st->ir) != 0, acc);
+            if constexpr (OP == OP_9PT)
+                chunk_r_b9(S, coef9_of(B.cf, B.cf9), B.b, B.x, c0, c1, cload_i(&S.st->ir) != 0, acc);
+            else
+                chunk_r_b(S, B.cf, B.b, B.x, c0, c1, cload_i(&S.st->ir) != 0, acc);
         } else if (kind == K_S) {
-            chunk_s_b(S, B.cf, B.b, B.x, c0, c1, acc);
+            if constexpr (OP == OP_9PT) chunk_s_b9(S, coef9_of(B.cf, B.cf9), B.b, B.x, c0, c1, acc);
+            else chunk_s_b(S, B.cf, B.b, B.x, c0, c1, acc);
         } else {
             const float alpha = (float)cload_d(&S.st->alpha);
             const float omega = (float)cload_d(&S.st->omega);
             const float beta = (float)cload_d(&S.st->beta);
             const float inv_scale = kind == K_I ? (float)(1.0 / cload_d(&S.st->scale)) : 1.0f;
-            if (tag == 0) run_chunk<float>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
-            else if (tag == 1) run_chunk<bf16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
-            else run_chunk<f16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+            if constexpr (OP == OP_9PT) {
+                if (tag == 0) run_chunk9<float>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+                else if (tag == 1) run_chunk9<bf16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+                else run_chunk9<f16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+            } else {
+                if (tag == 0) run_chunk<float>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+                else if (tag == 1) run_chunk<bf16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+                else run_chunk<f16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+            }
         }
         // Every thread waits until its own vector stores have reached memory: a
         // workgroup barrier does not wait for them, and the next phase may read

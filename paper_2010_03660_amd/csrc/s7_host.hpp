@@ -79,7 +79,7 @@ void options_or_default(const s7_options* in, s7_options& out);
 // Tuned launch parameters per size class.  kind: TUNE_SINGLE (val: schedule,
 // stream_blocks) or TUNE_BATCH (val: chunk_cells, persistent grid).  Classes
 // are half-octaves of the cell count (and, for batches, of the system count).
-enum TuneKind { TUNE_SINGLE = 1, TUNE_BATCH = 2 };
+enum TuneKind { TUNE_SINGLE = 1, TUNE_BATCH = 2, TUNE_BATCH9 = 3 };
 struct TuneKey {
     int kind, tag, unit, nbucket, sbucket;
     bool operator<(const TuneKey& o) const;
@@ -95,8 +95,9 @@ void tune_store(const TuneKey& k, const int (&val)[2]);
 // system and the launch-global words) live in a separate device region of
 // engine_table_bytes(capacity).
 struct EngineJob {
-    s7_dims d;
+    s7_dims d;            // nz = 1 for the 2D 9-point operator
     const float* coef[7];
+    const float* coef9[2];  // the 2D 9-point operator's coefficients 7 and 8 (nw, ne)
     const double* b;
     double* x;
     double rtol;
@@ -120,9 +121,10 @@ struct BSys;  // one system of a persistent launch (device table entry)
 class BatchEngine {
   public:
     // use_graph: replay the persistent launch from a captured hipGraph, for
-    // callers whose resident set repeats (the batched entry point).
+    // callers whose resident set repeats (the batched entry point).  op: the
+    // operator of every job (0: 3D 7-point, 1: 2D 9-point).
     BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
-                bool use_graph = false);
+                bool use_graph = false, int op = 0);
     ~BatchEngine();
     BatchEngine(const BatchEngine&) = delete;
     BatchEngine& operator=(const BatchEngine&) = delete;
@@ -153,6 +155,7 @@ class BatchEngine {
     bool graph_;
     int chunk_;     // cells per work item of the persistent kernel
     int grid_cap_;  // most workgroups of a persistent launch
+    int op_;        // the operator of every job
     double ticks_per_ms_ = 100000.0;  // device wall clock
     State* host_states_ = nullptr;  // pinned, cap_ entries
     std::vector<EngineJob*> jobs_;

@@ -956,9 +956,9 @@ size_t engine_table_bytes(int capacity) {
 static int chunk_cells_of(const s7_options& o);
 
 BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
-                         bool use_graph)
+                         bool use_graph, int op)
     : tables_(tables), cap_(capacity), o_(o), st_(stream), graph_(use_graph),
-      chunk_(chunk_cells_of(o)), grid_cap_(1024) {
+      chunk_(chunk_cells_of(o)), grid_cap_(1024), op_(op) {
     if (hipHostMalloc((void**)&host_states_, (size_t)capacity * sizeof(State), hipHostMallocDefault) !=
         hipSuccess)
         host_states_ = nullptr;  // read_states reports it
@@ -982,7 +982,7 @@ int BatchEngine::add(EngineJob* j) {
         set_error("batch engine: more than %d resident systems", cap_);
         return S7_EAGAIN;
     }
-    j->lo = make_layout(j->d, j->prec, o_);
+    j->lo = make_layout(j->d, j->prec, o_, op_ == OP_9PT ? (o_.jacobi ? 8 : 9) : 0);
     j->stage = J_NEW;
     j->tag = j->prec == S7_FP32 ? 0 : (j->prec == S7_BF16_IR ? 1 : 2);
     j->finished = 0;
@@ -1006,10 +1006,13 @@ static int chunk_cells_of(const s7_options& o) {
 // The start-table entry of a new job: coefficient copies, State and control
 // words, and the first phase (the FP32 start S, or the FP64 residual R that
 // begins refinement).
-static JobStart job_entry(const EngineJob& j, const s7_options& o) {
+static JobStart job_entry(const EngineJob& j, const s7_options& o, int op) {
     JobStart J{};
     SysView<float> S = make_view<float>(j.d, j.lo, o.jacobi, j.ws);  // pointer members only
     for (int a = 0; a < 7; ++a) J.cf.c[a] = j.coef[a];
+    J.cf9[0] = j.coef9[0];
+    J.cf9[1] = j.coef9[1];
+    J.op = op;
     J.coef_dst = const_cast<float*>(S.c[o.jacobi ? 1 : 0]);
     J.span = align256(j.lo.n * j.lo.elt) / j.lo.elt;
     J.m = S.m;
@@ -1032,12 +1035,37 @@ static JobStart job_entry(const EngineJob& j, const s7_options& o) {
 #define S7_BY_PREC(j, call)                                           \
     ((j).prec == S7_FP32 ? call<float> : ((j).prec == S7_BF16_IR ? call<bf16> : call<f16>))
 
-static void finish_job(EngineJob& j, const State& h) {
+// The table entry of a resident job in a persistent launch.
+static BSys sys_entry(const EngineJob& j, const s7_options& o, int op, int chunk, int budget) {
+    BSys b;
+    std::memset(&b, 0, sizeof(b));
+    b.S = make_view<float>(j.d, j.lo, o.jacobi, j.ws);
+    b.ctl = reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl);
+    b.nchunk = (int)((j.lo.n + chunk - 1) / chunk);
+    b.tag = j.tag;
+    b.budget = budget;
+    for (int a = 0; a < 7; ++a) b.cf.c[a] = j.coef[a];
+    b.b = j.b;
+    b.x = j.x;
+    if (op == OP_9PT) {
+        // the working copies of coefficients 7 and 8 follow the first seven
+        const size_t span = align256(j.lo.n * j.lo.elt);
+        const int first = o.jacobi ? 1 : 0;
+        for (int i = 0; i < 2; ++i) {
+            b.cf9[i] = j.coef9[i];
+            b.wk9[i] = reinterpret_cast<const float*>(j.ws + j.lo.off_coef + (size_t)(7 + i - first) * span);
+        }
+    }
+    return b;
+}
+
+static void finish_job(EngineJob& j, const State& h, int op) {
     s7_info& inf = j.info;
     std::memset(&inf, 0, sizeof(inf));
     inf.iters = h.total;
     inf.outer_iters = h.ir ? h.outer : 1;
-    inf.schedule = j.d.nx % 2 == 0 ? SCHED_PAIRS : SCHED_THREE;  // the persistent kernel's phases
+    // the persistent kernel's phases: cell pairs for the 7-point operator with an even nx
+    inf.schedule = op == OP_7PT && j.d.nx % 2 == 0 ? SCHED_PAIRS : SCHED_THREE;
     inf.status = h.ostatus;
     inf.reason = h.oreason;
     inf.rel_res_rec = h.inner_res;
@@ -1081,14 +1109,18 @@ int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk
     auto body = [&](hipStream_t cs) {
         hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
                            slice);
-        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
-                           chunk, spin_limit);
+        if (op_ == OP_9PT)
+            hipLaunchKernelGGL(k_batched<OP_9PT>, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
+                               nsys, chunk, spin_limit);
+        else
+            hipLaunchKernelGGL(k_batched<OP_7PT>, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
+                               nsys, chunk, spin_limit);
     };
     GraphRef g;  // held until the launch has completed
     if (graph_) {
         // the table is re-uploaded before every replay, so the key needs only its shape
         std::vector<uintptr_t> key = {0x53u, (uintptr_t)tables_, (uintptr_t)nsys, (uintptr_t)epoch_key,
-                                      (uintptr_t)grid, (uintptr_t)chunk, (uintptr_t)slice};
+                                      (uintptr_t)grid, (uintptr_t)chunk, (uintptr_t)slice, (uintptr_t)op_};
         int rc = cached_graph(key, body, &g);
         if (rc) return rc;
         S7_HIP(hipGraphLaunch(g->exec, st_));
@@ -1107,9 +1139,16 @@ int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk
     return S7_OK;
 }
 
+// A trial system in the job's workspace; the 9-point operator's two extra
+// working copies are zero (the trial is the 5-point part).
 template <class T>
-static int tune_prepare_job(const EngineJob& j, const s7_options& o, hipStream_t s) {
-    return tune_prepare<T>(make_view<T>(j.d, j.lo, o.jacobi, j.ws), s);
+static int tune_prepare_job(const EngineJob& j, const s7_options& o, int op, hipStream_t s) {
+    const int rc = tune_prepare<T>(make_view<T>(j.d, j.lo, o.jacobi, j.ws), s);
+    if (rc || op != OP_9PT) return rc;
+    const size_t span = align256(j.lo.n * j.lo.elt);
+    const int first = o.jacobi ? 1 : 0;
+    S7_HIP(hipMemsetAsync(j.ws + j.lo.off_coef + (size_t)(7 - first) * span, 0, 2 * span, s));
+    return S7_OK;
 }
 
 int BatchEngine::tune() {
@@ -1122,7 +1161,8 @@ int BatchEngine::tune() {
         }
         total += (double)j->lo.n;
     }
-    const TuneKey key{TUNE_BATCH, jobs_[0]->tag, o_.jacobi, size_bucket(total), size_bucket((double)jobs_.size())};
+    const TuneKey key{op_ == OP_9PT ? TUNE_BATCH9 : TUNE_BATCH, jobs_[0]->tag, o_.jacobi, size_bucket(total),
+                      size_bucket((double)jobs_.size())};
     int best[2];
     if (tune_lookup(key, best)) {
         chunk_ = best[0];
@@ -1144,19 +1184,10 @@ int BatchEngine::tune() {
             std::vector<BSys> table;
             long long chunks = 0;
             for (EngineJob* j : jobs_) {
-                if ((rc = S7_BY_PREC(*j, tune_prepare_job)(*j, o_, st_))) break;
+                if ((rc = S7_BY_PREC(*j, tune_prepare_job)(*j, o_, op_, st_))) break;
                 hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st_,
                                    reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl), (int)K_P1);
-                BSys b;
-                b.S = make_view<float>(j->d, j->lo, o_.jacobi, j->ws);
-                b.ctl = reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl);
-                b.nchunk = (int)((j->lo.n + chunk - 1) / chunk);
-                b.tag = j->tag;
-                b.budget = K;
-                b.pad = 0;
-                for (int a = 0; a < 7; ++a) b.cf.c[a] = j->coef[a];
-                b.b = j->b;
-                b.x = j->x;
+                const BSys b = sys_entry(*j, o_, op_, chunk, K);
                 chunks += b.nchunk;
                 table.push_back(b);
             }
@@ -1199,7 +1230,7 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
     for (EngineJob* j : jobs_) {
         sptr.push_back(reinterpret_cast<State*>(j->ws + j->lo.off_state));
         if (j->stage != J_NEW) continue;
-        starts.push_back(job_entry(*j, o_));
+        starts.push_back(job_entry(*j, o_, op_));
         max_n = std::max(max_n, j->lo.n);
         j->stage = J_RUN;
     }
@@ -1218,19 +1249,7 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
     // 2) one persistent launch over every resident job
     std::vector<BSys> table;
     const int chunk = chunk_;
-    for (EngineJob* j : jobs_) {
-        BSys b;
-        b.S = make_view<float>(j->d, j->lo, o_.jacobi, j->ws);
-        b.ctl = reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl);
-        b.nchunk = (int)((j->lo.n + chunk - 1) / chunk);
-        b.tag = j->tag;
-        b.budget = epoch_iters > 0 ? epoch_iters : (1 << 30);
-        b.pad = 0;
-        for (int a = 0; a < 7; ++a) b.cf.c[a] = j->coef[a];
-        b.b = j->b;
-        b.x = j->x;
-        table.push_back(b);
-    }
+    for (EngineJob* j : jobs_) table.push_back(sys_entry(*j, o_, op_, chunk, epoch_iters > 0 ? epoch_iters : (1 << 30)));
     const long long slice = epoch_iters > 0 ? 0 : (long long)(slice_ms * ticks_per_ms_);
     rc = launch(table, epoch_iters, chunk, grid_cap_, slice);
     if (rc) return rc;
@@ -1240,11 +1259,62 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
     if (rc) return rc;
     std::vector<EngineJob*> keep;
     for (size_t i = 0; i < jobs_.size(); ++i) {
-        if (h[i].final) finish_job(*jobs_[i], h[i]);
+        if (h[i].final) finish_job(*jobs_[i], h[i], op_);
         else keep.push_back(jobs_[i]);
     }
     jobs_.swap(keep);
     return S7_OK;
+}
+
+// A system of split_cells cells or more gains nothing from the shared launch:
+// its phases already fill the chip, and at thousands of chunks per phase the
+// claim and completion atomics on its control words, which serialize, cost
+// more than the pass itself.  It runs alone on the multi-kernel path, in its
+// own slice of the workspace, after the shared launch.  The choice depends
+// only on the system's own size, so a system's result still does not depend
+// on the rest of the batch.
+static long long split_cells_of(const s7_options& o) {
+    return o.split_cells < 0 ? (1ll << 62) : (o.split_cells > 0 ? o.split_cells : 1ll << 21);
+}
+
+// Runs a batch whose jobs are filled in (workspace slices included): the jobs
+// marked in `big` run one by one through `alone`, after the others have run
+// together on one engine.  Fills info[i] and returns the worst status.
+template <class Alone>
+static int run_batch(std::vector<EngineJob>& jobs, const std::vector<char>& big, int op, char* w,
+                     const s7_options& o, hipStream_t s, s7_info* info, const char* who, Alone alone) {
+    const int nsys = (int)jobs.size();
+    BatchEngine eng(w, nsys, o, s, /*use_graph=*/true, op);
+    for (int i = 0; i < nsys; ++i) {
+        if (big[i]) continue;
+        EngineJob& j = jobs[i];
+        const int rc = eng.add(&j);
+        if (rc) return rc;
+    }
+    if (o.tune && o.chunk_cells == 0 && eng.resident() > 0) {
+        const int rc = eng.tune();
+        if (rc) return rc;
+    }
+    int guard = 0;
+    while (eng.resident() > 0) {
+        const int rc = eng.step(1 << 30);
+        if (rc) return rc;
+        if (++guard > 100000) {
+            set_error("%s: no progress", who);
+            return S7_EHIP;
+        }
+    }
+    for (int i = 0; i < nsys; ++i) {
+        if (!big[i]) continue;
+        const int rc = alone(jobs[i]);
+        if (rc < 0) return rc;
+    }
+    int worst = S7_OK;
+    for (int i = 0; i < nsys; ++i) {
+        if (info) info[i] = jobs[i].info;
+        if (jobs[i].info.status > worst) worst = jobs[i].info.status;
+    }
+    return worst;
 }
 
 }  // namespace s7
@@ -1398,18 +1468,9 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
         return S7_EINVAL;
     }
     char* w = (char*)ws;
-    hipStream_t s = (hipStream_t)stream;
-    BatchEngine eng(w, nsys, o, s, /*use_graph=*/true);
+    const long long split = split_cells_of(o);
     std::vector<EngineJob> jobs((size_t)nsys);
-    // A system of split_cells cells or more gains nothing from the shared
-    // launch: its phases already fill the chip, and at thousands of chunks per
-    // phase the claim and completion atomics on its control words, which
-    // serialize, cost more than the pass itself.  It runs alone on the
-    // multi-kernel path, in its own slice of the workspace, after the shared
-    // launch.  The choice depends only on the system's own size, so a system's
-    // result still does not depend on the rest of the batch.
-    const long long split = o.split_cells < 0 ? (1ll << 62) : (o.split_cells > 0 ? o.split_cells : 1ll << 21);
-    std::vector<char> alone((size_t)nsys, 0);
+    std::vector<char> big((size_t)nsys, 0);
     size_t off = align256(engine_table_bytes(nsys));
     const double t0 = now_ms();
     for (int i = 0; i < nsys; ++i) {
@@ -1425,40 +1486,14 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
         j.ws = w + off;
         j.ws_bytes = make_layout(d[i], prec, o).bytes;
         j.t_start_ms = t0;
+        big[i] = (long long)d[i].nx * d[i].ny * d[i].nz >= split;
         off += align256(j.ws_bytes);
-        if ((long long)d[i].nx * d[i].ny * d[i].nz >= split) {
-            alone[i] = 1;
-            continue;
-        }
-        int rc = eng.add(&j);
-        if (rc) return rc;
     }
-    if (o.tune && o.chunk_cells == 0 && eng.resident() > 0) {
-        int rc = eng.tune();
-        if (rc) return rc;
-    }
-    int guard = 0;
-    while (eng.resident() > 0) {
-        int rc = eng.step(1 << 30);
-        if (rc) return rc;
-        if (++guard > 100000) {
-            set_error("s7_bicgstab_solve_batched: no progress");
-            return S7_EHIP;
-        }
-    }
-    for (int i = 0; i < nsys; ++i) {
-        if (!alone[i]) continue;
-        EngineJob& j = jobs[i];
-        const int rc = s7_bicgstab_solve(j.d, j.coef, j.b, j.x, j.rtol, j.max_iter, prec, j.ws, j.ws_bytes,
-                                         &o, &j.info, stream);
-        if (rc < 0) return rc;
-    }
-    int worst = S7_OK;
-    for (int i = 0; i < nsys; ++i) {
-        if (info) info[i] = jobs[i].info;
-        if (jobs[i].info.status > worst) worst = jobs[i].info.status;
-    }
-    return worst;
+    return run_batch(jobs, big, OP_7PT, w, o, (hipStream_t)stream, info, "s7_bicgstab_solve_batched",
+                     [&](EngineJob& j) {
+                         return s7_bicgstab_solve(j.d, j.coef, j.b, j.x, j.rtol, j.max_iter, prec, j.ws,
+                                                  j.ws_bytes, &o, &j.info, stream);
+                     });
 }
 
 }  // extern "C"

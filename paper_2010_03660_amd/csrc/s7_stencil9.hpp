@@ -16,86 +16,9 @@
 // (State, reductions, P3, refinement loop, x update, graph cache).
 #pragma once
 
+#include "s7_stencil9_device.hpp"
+
 namespace s7 {
-
-// Nine coefficient arrays in the order {diag, w, e, s, n, sw, se, nw, ne}:
-// the caller's (FP32), or the working copies in the storage type T.
-template <class T>
-struct Coef9T {
-    const T* c[9];
-};
-using Coef9 = Coef9T<float>;
-
-// Offsets of the nine points from the cell; an off-mesh neighbour maps to the
-// cell itself (its coefficient is zero or masked).
-__device__ __forceinline__ void offsets9(const Cell& c, int (&o)[9]) {
-    o[0] = 0;
-    o[1] = c.dw;
-    o[2] = c.de;
-    o[3] = c.ds;
-    o[4] = c.dn;
-    o[5] = (c.dw && c.ds) ? c.dw + c.ds : 0;
-    o[6] = (c.de && c.ds) ? c.de + c.ds : 0;
-    o[7] = (c.dw && c.dn) ? c.dw + c.dn : 0;
-    o[8] = (c.de && c.dn) ? c.de + c.dn : 0;
-}
-
-// Whether each of the nine links stays in the mesh.
-__device__ __forceinline__ void inside9(const Cell& c, bool (&in)[9]) {
-    in[0] = true;
-    in[1] = c.dw != 0;
-    in[2] = c.de != 0;
-    in[3] = c.ds != 0;
-    in[4] = c.dn != 0;
-    in[5] = in[1] && in[3];
-    in[6] = in[2] && in[3];
-    in[7] = in[1] && in[4];
-    in[8] = in[2] && in[4];
-}
-
-template <class V>
-__device__ __forceinline__ void load9(const V* v, const Cell& c, V (&x)[9]) {
-    int o[9];
-    offsets9(c, o);
-    const V* p = v + c.idx;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) x[a] = p[o[a]];
-}
-
-// The nine values of a working vector in storage type T, widened to FP32.
-template <class T>
-__device__ __forceinline__ void load9f(const T* v, const Cell& c, float (&x)[9]) {
-    int o[9];
-    offsets9(c, o);
-    const T* p = v + c.idx;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) x[a] = to_f32(p[o[a]]);
-}
-
-__device__ __forceinline__ float fma9(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma9(double a, double b, double c) { return fma(a, b, c); }
-
-// (A v) at one cell with the caller's coefficients; outward links masked.
-// Terms in the order diag, w, e, s, n, sw, se, nw, ne.
-template <class V>
-__device__ __forceinline__ V apply9_masked(const Coef9& cf, const Cell& c, const V (&x)[9]) {
-    bool in[9];
-    inside9(c, in);
-    V acc = (V)cf.c[0][c.idx] * x[0];
-#pragma unroll
-    for (int a = 1; a < 9; ++a) acc = fma9(in[a] ? (V)cf.c[a][c.idx] : (V)0, x[a], acc);
-    return acc;
-}
-
-// (A v) at one cell with the working copies (outward links already zero).
-// UNIT: Jacobi-scaled, the diagonal is one and c[0] is not stored.
-template <class T, bool UNIT>
-__device__ __forceinline__ float apply9_work(const Coef9T<T>& k, int idx, const float (&x)[9]) {
-    float acc = UNIT ? x[0] : to_f32(ld_nt(k.c[0] + idx)) * x[0];
-#pragma unroll
-    for (int a = 1; a < 9; ++a) acc = fma9(to_f32(ld_nt(k.c[a] + idx)), x[a], acc);
-    return acc;
-}
 
 // ---------------------------------------------------------------- kernels
 __global__ __launch_bounds__(kThreads) void k9_apply_f32(Coef9 cf, const float* v, float* u, Mesh m, int n) {
@@ -468,6 +391,78 @@ int s7_bicgstab_solve_2d9(int32_t nx, int32_t ny, const float* const coef[9], co
     if (prec == S7_FP32) return solve9(nx, ny, cf, b, x, rtol, max_iter, (char*)ws, Lo, o, info, st);
     if (prec == S7_BF16_IR) return solve9_ir<bf16>(nx, ny, cf, b, x, rtol, max_iter, (char*)ws, Lo, o, info, st, prec);
     return solve9_ir<f16>(nx, ny, cf, b, x, rtol, max_iter, (char*)ws, Lo, o, info, st, prec);
+}
+
+size_t s7_batched_workspace_bytes_2d9(int32_t nsys, const int32_t* nx, const int32_t* ny, int32_t prec,
+                                      const s7_options* opt) {
+    if (nsys < 1 || !nx || !ny || prec < S7_FP32 || prec > S7_FP16_IR) return 0;
+    s7_options o;
+    options_or_default(opt, o);
+    size_t total = align256(engine_table_bytes(nsys));
+    for (int i = 0; i < nsys; ++i) {
+        if (!dims2_ok(nx[i], ny[i])) return 0;
+        total += align256(make_layout9(nx[i], ny[i], prec, o).bytes);
+    }
+    return total;
+}
+
+int s7_bicgstab_solve_batched_2d9(int32_t nsys, const int32_t* nx, const int32_t* ny, const float* const* coef,
+                                  const double* const* b, double* const* x, const double* rtol,
+                                  const int32_t* max_iter, int32_t prec, void* ws, size_t ws_bytes,
+                                  const s7_options* opt, s7_info* info, void* stream) {
+    clear_error();
+    s7_options o;
+    options_or_default(opt, o);
+    if (nsys < 1 || !nx || !ny || !coef || !b || !x || !rtol || !max_iter || !ws ||
+        ((uintptr_t)ws & 255u) != 0 || prec < S7_FP32 || prec > S7_FP16_IR) {
+        set_error("s7_bicgstab_solve_batched_2d9: invalid argument");
+        return S7_EINVAL;
+    }
+    for (int i = 0; i < nsys; ++i) {
+        if (!dims2_ok(nx[i], ny[i]) || !coef9_ok(coef + 9 * (size_t)i) || !b[i] || !x[i] || !(rtol[i] > 0.0) ||
+            max_iter[i] < 0) {
+            set_error("s7_bicgstab_solve_batched_2d9: invalid argument for system %d", i);
+            return S7_EINVAL;
+        }
+    }
+    const size_t need = s7_batched_workspace_bytes_2d9(nsys, nx, ny, prec, &o);
+    if (ws_bytes < need) {
+        set_error("s7_bicgstab_solve_batched_2d9: workspace too small (%zu < %zu)", ws_bytes, need);
+        return S7_EINVAL;
+    }
+    char* w = (char*)ws;
+    const long long split = split_cells_of(o);
+    std::vector<EngineJob> jobs((size_t)nsys);
+    std::vector<char> big((size_t)nsys, 0);
+    size_t off = align256(engine_table_bytes(nsys));
+    const double t0 = now_ms();
+    for (int i = 0; i < nsys; ++i) {
+        EngineJob& j = jobs[i];
+        std::memset(&j, 0, sizeof(j));
+        j.d = s7_dims{nx[i], ny[i], 1};
+        for (int a = 0; a < 7; ++a) j.coef[a] = coef[9 * (size_t)i + a];
+        j.coef9[0] = coef[9 * (size_t)i + 7];
+        j.coef9[1] = coef[9 * (size_t)i + 8];
+        j.b = b[i];
+        j.x = x[i];
+        j.rtol = rtol[i];
+        j.max_iter = max_iter[i];
+        j.prec = prec;
+        j.ws = w + off;
+        j.ws_bytes = make_layout9(nx[i], ny[i], prec, o).bytes;
+        j.t_start_ms = t0;
+        big[i] = (long long)nx[i] * ny[i] >= split;
+        off += align256(j.ws_bytes);
+    }
+    return run_batch(jobs, big, OP_9PT, w, o, (hipStream_t)stream, info, "s7_bicgstab_solve_batched_2d9",
+                     [&](EngineJob& j) {
+                         const float* c9[9];
+                         for (int a = 0; a < 7; ++a) c9[a] = j.coef[a];
+                         c9[7] = j.coef9[0];
+                         c9[8] = j.coef9[1];
+                         return s7_bicgstab_solve_2d9(j.d.nx, j.d.ny, c9, j.b, j.x, j.rtol, j.max_iter, prec, j.ws,
+                                                      j.ws_bytes, &o, &j.info, stream);
+                     });
 }
 
 int s7_generate_problem_2d9(int32_t nx, int32_t ny, uint64_t seed, float* const coef[9], double* xstar,

@@ -135,3 +135,37 @@ def test_host_side_argument_checks_2d9():
     missing = (C.c_void_p * 9)(*([256] * 8 + [None]))
     assert lib.s7_stencil9_apply(8, 8, missing, 4096, 8192, 0) == B.EINVAL
     assert lib.s7_generate_problem_2d9(8, 8, 0, None, None, 4096, 0) == B.EINVAL  # b needs coef and x*
+
+
+def test_host_side_argument_checks_batched_2d9():
+    """The batched 2D call validates every system on the host before any device work,
+    and its workspace is the engine tables plus one 2D workspace per mesh."""
+    from paper_2010_03660_amd import binding as B
+    lib = B.lib()
+    nx = (C.c_int32 * 2)(100, 3)
+    ny = (C.c_int32 * 2)(37, 1)
+    total = lib.s7_batched_workspace_bytes_2d9(2, nx, ny, B.FP32, None)
+    one = lib.s7_workspace_bytes_2d9(100, 37, B.FP32, None) + lib.s7_workspace_bytes_2d9(3, 1, B.FP32, None)
+    assert total > one
+    assert lib.s7_batched_workspace_bytes_2d9(0, nx, ny, B.FP32, None) == 0
+    assert lib.s7_batched_workspace_bytes_2d9(2, nx, ny, 9, None) == 0
+    bad = (C.c_int32 * 2)(100, 0)
+    assert lib.s7_batched_workspace_bytes_2d9(2, bad, ny, B.FP32, None) == 0
+    coef = (C.c_void_p * 18)(*([256] * 18))
+    bp = (C.c_void_p * 2)(512, 768)
+    xp = (C.c_void_p * 2)(1024, 1280)
+    rt = (C.c_double * 2)(1e-8, 1e-8)
+    mi = (C.c_int32 * 2)(10, 10)
+    infos = (B.Info * 2)()
+
+    def call(nx_, coef_=coef, rt_=rt, mi_=mi, ws=4096, wsb=1 << 30, prec=0):
+        return lib.s7_bicgstab_solve_batched_2d9(2, nx_, ny, coef_, bp, xp, rt_, mi_, prec, ws, wsb, None,
+                                                 infos, 0)
+    assert call(bad) == B.EINVAL and "system 1" in B.last_error()
+    missing = (C.c_void_p * 18)(*([256] * 17 + [None]))
+    assert call(nx, coef_=missing) == B.EINVAL and "system 1" in B.last_error()
+    assert call(nx, rt_=(C.c_double * 2)(1e-8, float("nan"))) == B.EINVAL
+    assert call(nx, mi_=(C.c_int32 * 2)(-1, 10)) == B.EINVAL and "system 0" in B.last_error()
+    assert call(nx, wsb=16) == B.EINVAL and "workspace" in B.last_error()
+    assert call(nx, ws=4100) == B.EINVAL  # not 256-byte aligned
+    assert call(nx, prec=3) == B.EINVAL
