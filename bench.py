@@ -162,6 +162,62 @@ def batched_leg(s7, torch, dev):
     }
 
 
+def batched_2d9_leg(s7, torch, dev):
+    """64 2D 9-point systems, each side uniform over {96,...,512}, seeds 2000+s,
+    tolerance 1e-7: one call of the batched solver against a loop of single solves."""
+    import synth
+    shapes, seeds = synth.batch_shapes_2d9(64, seed=0)
+    coefs, bs, xs, xst = [], [], [], []
+    for (nx, ny), sd in zip(shapes, seeds):
+        n = nx * ny
+        c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(9)]
+        xx = torch.empty(n, dtype=torch.float64, device=dev)
+        bb = torch.empty(n, dtype=torch.float64, device=dev)
+        s7.generate_problem_2d9(nx, ny, sd, c, xx, bb)
+        coefs.append(c), bs.append(bb), xst.append(xx)
+        xs.append(torch.zeros(n, dtype=torch.float64, device=dev))
+    cells = [nx * ny for nx, ny in shapes]
+    ws = torch.empty(s7.batched_workspace_bytes_2d9(shapes), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def batched():
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, infos = s7.bicgstab_solve_batched_2d9(shapes, coefs, bs, xs, [1e-7] * 64, [2000] * 64, ws=ws,
+                                                  opt=s7.default_options(tune=1))
+        torch.cuda.synchronize()
+        return rc, infos, time.perf_counter() - t0
+
+    batched()  # warm-up: autotunes the size class and captures the launch graph
+    rc, infos, dt = batched()
+    iters = [i.iters for i in infos]
+    err = max(float(torch.linalg.vector_norm(x - xx) / torch.linalg.vector_norm(xx))
+              for x, xx in zip(xs, xst))
+    cell_iters = sum(c * k for c, k in zip(cells, iters))
+    sws = torch.empty(max(s7.workspace_bytes_2d9(nx, ny) for nx, ny in shapes), dtype=torch.uint8, device=dev)
+    for (nx, ny), c, bb, x in zip(shapes, coefs, bs, xs):  # warm-up: graphs per size
+        s7.bicgstab_solve_2d9(nx, ny, c, bb, x, 1e-7, 3, ws=sws)
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (nx, ny), c, bb, x in zip(shapes, coefs, bs, xs):
+        s7.bicgstab_solve_2d9(nx, ny, c, bb, x, 1e-7, 2000, ws=sws)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t0
+    return {
+        "workload": "64 2D 9-point systems, sides uniform over {96,128,192,256,384,512}, FP32, rtol 1e-7",
+        "cells": sum(cells), "status": rc, "iters_min_max": [min(iters), max(iters)],
+        "systems_per_s": round(64 / dt, 2), "seconds": round(dt, 4),
+        "cell_iters_per_s": round(cell_iters / dt, 1),
+        "alg_GB/s": round(cell_iters * sum(BYTES_2D9.values()) / dt / 1e9, 1),
+        "max_rel_err_vs_xstar": err,
+        "serial_single_solves_s": round(dts, 4), "speedup_vs_serial": round(dts / dt, 2),
+    }
+
+
 def simple_leg(s7, torch, dev, dims, outer: int):
     """The solver pattern of Algorithm 2 (SIMPLE): per outer iteration the momentum
     systems u, v, w, capped at 5 BiCGStab iterations, then the continuity system, capped
@@ -599,6 +655,10 @@ def main():
     if not args.no_2d9:
         print("[bench] 2D 9-point", file=sys.stderr, flush=True)
         out["stencil9_2d"] = stencil9_leg(s7, torch, dev, args.steps, args.warmup)
+        if not args.no_batched:
+            print("[bench] batched 2D 9-point: 64 uneven meshes", file=sys.stderr, flush=True)
+            out["batched_2d9"] = batched_2d9_leg(s7, torch, dev)
+            torch.cuda.empty_cache()
     if not args.no_serve:
         out["served"] = served_leg(s7, torch, dev, args.serve_requests, args.serve_rate,
                                    args.serve_burst, args.arena_gb, args.serve_sample)

@@ -241,15 +241,29 @@ typedef struct {
     int32_t prec;         /* s7_prec */
 } s7_request;
 
-/* Bytes at the head of a queue arena that hold the engine tables. */
+/* A 2D 9-point request (s7_queue_submit_2d9): an nx x ny mesh with the nine
+ * coefficient arrays in the order {diag, w, e, s, n, sw, se, nw, ne}. */
+typedef struct {
+    int32_t nx, ny;
+    const float *coef[9]; /* device arrays, kept alive by the caller until done */
+    const double *b;      /* device */
+    double *x;            /* device; x0 on submit, solution when done */
+    double rtol;
+    int32_t max_iter;
+    int32_t prec;         /* s7_prec */
+} s7_request_2d9;
+
+/* Bytes at the head of a queue arena that hold the engine tables (one for
+ * 3D 7-point requests, one for 2D 9-point requests). */
 size_t s7_queue_table_bytes(void);
 
 /*
  * Creates a queue over the caller's device arena (256-byte aligned), on the
  * current device.  The arena stays owned by the caller and must outlive the
  * queue.  Its head (s7_queue_table_bytes) holds the engine tables for up to
- * 1024 resident requests; the rest holds the admitted requests' workspaces (s7_workspace_bytes of
- * their dims and precision).  opt->graph_iters sets the epoch: the most
+ * 1024 resident requests of each operator; the rest holds the admitted
+ * requests' workspaces (s7_workspace_bytes of their dims and precision, or
+ * s7_workspace_bytes_2d9 of their mesh).  opt->graph_iters sets the epoch: the most
  * iterations a resident request runs between two admission points; 0 (the
  * default) gives each request the iterations that fit a time slice of about
  * 2 ms at its size.
@@ -265,6 +279,14 @@ int s7_queue_create(s7_queue **q, void *arena, size_t arena_bytes, const s7_opti
  * S7_EINVAL for a bad argument; after a device error, that error.
  */
 int s7_queue_submit(s7_queue *q, const s7_request *req, uint64_t *ticket);
+/*
+ * The same for a 2D 9-point request (section IV's operator, solved as by
+ * s7_bicgstab_solve_2d9).  It shares the arena, the admission order and the
+ * tickets with 3D requests; small ones run on the queue's second batch
+ * engine, meshes of split_cells cells or more on the large-request thread.
+ * Its workspace is s7_workspace_bytes_2d9 of its mesh and precision.
+ */
+int s7_queue_submit_2d9(s7_queue *q, const s7_request_2d9 *req, uint64_t *ticket);
 /*
  * Non-blocking.  S7_EAGAIN while the request is queued or running; else the
  * request's s7_status, *info filled (t_ms: submit to completion, t_wait_ms:

@@ -27,7 +27,7 @@ __all__ = [
     "bicgstab_solve_batched", "queue_table_bytes", "queue_create", "queue_submit", "queue_poll", "queue_wait",
     "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error", "stencil9_apply",
     "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9", "batched_workspace_bytes_2d9",
-    "bicgstab_solve_batched_2d9",
+    "bicgstab_solve_batched_2d9", "Request2D9", "queue_submit_2d9",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
     "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
@@ -62,6 +62,11 @@ class Info(C.Structure):
 class Request(C.Structure):
     _fields_ = [("d", Dims), ("coef", C.c_void_p * 7), ("b", C.c_void_p), ("x", C.c_void_p),
                 ("rtol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32)]
+
+
+class Request2D9(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("coef", C.c_void_p * 9), ("b", C.c_void_p),
+                ("x", C.c_void_p), ("rtol", C.c_double), ("max_iter", C.c_int32), ("prec", C.c_int32)]
 
 
 class S7Error(RuntimeError):
@@ -100,6 +105,7 @@ EXPORTS = {
                                         C.c_int32, C.c_int32, _vp, C.c_size_t, C.POINTER(Options),
                                         C.POINTER(Info), _vp]),
     "s7_generate_problem_2d9": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_vp), _vp, _vp, _vp]),
+    "s7_queue_submit_2d9": (C.c_int, [_vp, C.POINTER(Request2D9), C.POINTER(C.c_uint64)]),
     "s7_batched_workspace_bytes_2d9": (C.c_size_t, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                                     C.c_int32, C.POINTER(Options)]),
     "s7_bicgstab_solve_batched_2d9": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -352,3 +358,11 @@ def bicgstab_solve_batched_2d9(meshes, coefs, bs, xs, rtols, max_iters, prec=FP3
                                              C.byref(opt) if opt else None, infos, _stream(stream))
     _check(rc)
     return rc, list(infos)
+
+
+def queue_submit_2d9(q: int, nx: int, ny: int, coef, b, x, rtol, max_iter, prec=FP32) -> int:
+    """Queues a 2D 9-point request; coef holds nine arrays.  Returns its ticket."""
+    req = Request2D9(int(nx), int(ny), _coef9(coef), _ptr(b), _ptr(x), float(rtol), int(max_iter), int(prec))
+    t = C.c_uint64()
+    _check(lib().s7_queue_submit_2d9(q, C.byref(req), C.byref(t)), allow=(OK,))
+    return t.value

@@ -20,6 +20,10 @@
 //     best on the single-system path.  A second thread solves them one at a
 //     time on its own stream, concurrently with the engine's launches.
 //   A finished request frees its workspace for the next admission.
+// * 2D 9-point requests (s7_queue_submit_2d9) share the arena, the FIFO and
+//   the large-request thread.  Small ones join a second batch engine, whose
+//   persistent kernel is the 9-point instantiation; each round of the serving
+//   thread steps the engines that have residents, one time slice each.
 // * poll() never blocks; wait() blocks until the request is done.  A finished
 //   request's result is handed out once, then its ticket is released.
 #include <hip/hip_runtime.h>
@@ -91,6 +95,7 @@ class Arena {
 struct Req {
     uint64_t ticket;
     EngineJob job;
+    int op = 0;  // 0: 3D 7-point, 1: 2D 9-point
     bool big = false;
     size_t off = 0, bytes = 0;
     double t_submit = 0, t_admit = 0;
@@ -109,7 +114,8 @@ struct s7_queue {
     long long split_cells;
     Arena heap;
     hipStream_t stream = nullptr, big_stream = nullptr;
-    std::unique_ptr<BatchEngine> engine;
+    std::unique_ptr<BatchEngine> engine;   // 3D 7-point requests
+    std::unique_ptr<BatchEngine> engine9;  // 2D 9-point requests
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done, cv_big;
@@ -177,13 +183,15 @@ struct s7_queue {
                         cv_big.notify_one();
                     } else {
                         resident.push_back(r);
-                        engine->add(&r->job);
+                        (r->op ? engine9 : engine)->add(&r->job);
                     }
                 }
                 seen = gen;
             }
             if (resident.empty()) continue;
-            const int rc = engine->step(epoch_iters, kSliceMs);
+            int rc = S7_OK;
+            if (engine->resident() > 0) rc = engine->step(epoch_iters, kSliceMs);
+            if (rc == S7_OK && engine9->resident() > 0) rc = engine9->step(epoch_iters, kSliceMs);
             std::lock_guard<std::mutex> lk(mu);
             if (rc != S7_OK) {
                 error_msg = s7_last_error();
@@ -222,8 +230,18 @@ struct s7_queue {
             }
             const EngineJob& j = r->job;
             s7_info info;
-            const int rc = s7_bicgstab_solve(j.d, j.coef, j.b, j.x, j.rtol, j.max_iter, j.prec, j.ws,
-                                             j.ws_bytes, &opt, &info, big_stream);
+            int rc;
+            if (r->op) {
+                const float* c9[9];
+                for (int a = 0; a < 7; ++a) c9[a] = j.coef[a];
+                c9[7] = j.coef9[0];
+                c9[8] = j.coef9[1];
+                rc = s7_bicgstab_solve_2d9(j.d.nx, j.d.ny, c9, j.b, j.x, j.rtol, j.max_iter, j.prec, j.ws,
+                                           j.ws_bytes, &opt, &info, big_stream);
+            } else {
+                rc = s7_bicgstab_solve(j.d, j.coef, j.b, j.x, j.rtol, j.max_iter, j.prec, j.ws, j.ws_bytes,
+                                       &opt, &info, big_stream);
+            }
             std::lock_guard<std::mutex> lk(mu);
             if (rc < 0) {
                 if (error == S7_OK) {
@@ -243,7 +261,10 @@ struct s7_queue {
 
 extern "C" {
 
-size_t s7_queue_table_bytes(void) { return align256(engine_table_bytes(kQueueCapacity)); }
+// Two engine tables: the 7-point engine's, then the 9-point engine's.
+static size_t one_table_bytes() { return align256(engine_table_bytes(kQueueCapacity)); }
+
+size_t s7_queue_table_bytes(void) { return 2 * one_table_bytes(); }
 
 int s7_queue_create(s7_queue** q, void* arena, size_t arena_bytes, const s7_options* opt) {
     clear_error();
@@ -271,11 +292,47 @@ int s7_queue_create(s7_queue** q, void* arena, size_t arena_bytes, const s7_opti
         return S7_EHIP;
     }
     Q->engine.reset(new BatchEngine((char*)arena, kQueueCapacity, o, Q->stream));
+    Q->engine9.reset(new BatchEngine((char*)arena + one_table_bytes(), kQueueCapacity, o, Q->stream,
+                                     /*use_graph=*/false, /*op=*/1));
     Q->worker = std::thread([Q] { Q->run(); });
     Q->big_worker = std::thread([Q] { Q->run_big(); });
     *q = Q;
     return S7_OK;
 }
+
+}  // extern "C"
+
+// Queues a request whose job descriptor is filled in; bytes is its workspace.
+static int enqueue(s7_queue* q, const EngineJob& job, int op, size_t bytes, uint64_t* ticket, const char* who) {
+    if (align256(bytes) > q->arena_bytes - q->table_bytes) {
+        set_error("%s: request needs %zu bytes, the arena has %zu", who, bytes, q->arena_bytes - q->table_bytes);
+        return S7_ENOMEM;
+    }
+    std::unique_ptr<Req> r(new Req());
+    r->job = job;
+    r->job.ws_bytes = bytes;
+    r->op = op;
+    r->bytes = bytes;
+    r->big = (long long)job.d.nx * job.d.ny * job.d.nz >= q->split_cells;
+    r->t_submit = now_ms();
+    r->job.t_start_ms = r->t_submit;
+    {
+        std::lock_guard<std::mutex> lk(q->mu);
+        if (q->stop) {
+            set_error("%s: queue stopped (%s)", who, q->error_msg.c_str());
+            return q->error ? q->error : S7_EINVAL;
+        }
+        r->ticket = q->next_ticket++;
+        *ticket = r->ticket;
+        q->pending.push_back(r.get());
+        q->reqs[r->ticket] = std::move(r);
+        ++q->gen;
+    }
+    q->cv_work.notify_one();
+    return S7_OK;
+}
+
+extern "C" {
 
 int s7_queue_submit(s7_queue* q, const s7_request* req, uint64_t* ticket) {
     clear_error();
@@ -289,14 +346,7 @@ int s7_queue_submit(s7_queue* q, const s7_request* req, uint64_t* ticket) {
             set_error("s7_queue_submit: invalid argument");
             return S7_EINVAL;
         }
-    const size_t bytes = make_layout(req->d, req->prec, q->opt).bytes;
-    if (align256(bytes) > q->arena_bytes - q->table_bytes) {
-        set_error("s7_queue_submit: request needs %zu bytes, the arena has %zu", bytes,
-                  q->arena_bytes - q->table_bytes);
-        return S7_ENOMEM;
-    }
-    std::unique_ptr<Req> r(new Req());
-    EngineJob& j = r->job;
+    EngineJob j;
     std::memset(&j, 0, sizeof(j));
     j.d = req->d;
     for (int a = 0; a < 7; ++a) j.coef[a] = req->coef[a];
@@ -305,25 +355,32 @@ int s7_queue_submit(s7_queue* q, const s7_request* req, uint64_t* ticket) {
     j.rtol = req->rtol;
     j.max_iter = req->max_iter;
     j.prec = req->prec;
-    j.ws_bytes = bytes;
-    r->bytes = bytes;
-    r->big = (long long)req->d.nx * req->d.ny * req->d.nz >= q->split_cells;
-    r->t_submit = now_ms();
-    j.t_start_ms = r->t_submit;
-    {
-        std::lock_guard<std::mutex> lk(q->mu);
-        if (q->stop) {
-            set_error("s7_queue_submit: queue stopped (%s)", q->error_msg.c_str());
-            return q->error ? q->error : S7_EINVAL;
-        }
-        r->ticket = q->next_ticket++;
-        *ticket = r->ticket;
-        q->pending.push_back(r.get());
-        q->reqs[r->ticket] = std::move(r);
-        ++q->gen;
+    return enqueue(q, j, 0, make_layout(req->d, req->prec, q->opt).bytes, ticket, "s7_queue_submit");
+}
+
+int s7_queue_submit_2d9(s7_queue* q, const s7_request_2d9* req, uint64_t* ticket) {
+    clear_error();
+    bool ok = q && req && ticket && req->nx >= 1 && req->ny >= 1 &&
+              (long long)req->nx * req->ny <= kMaxCells && req->b && req->x && req->rtol > 0.0 &&
+              req->max_iter >= 0 && req->prec >= S7_FP32 && req->prec <= S7_FP16_IR;
+    for (int a = 0; a < 9 && ok; ++a) ok = req->coef[a] != nullptr;
+    if (!ok) {
+        set_error("s7_queue_submit_2d9: invalid argument");
+        return S7_EINVAL;
     }
-    q->cv_work.notify_one();
-    return S7_OK;
+    EngineJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.d = s7_dims{req->nx, req->ny, 1};
+    for (int a = 0; a < 7; ++a) j.coef[a] = req->coef[a];
+    j.coef9[0] = req->coef[7];
+    j.coef9[1] = req->coef[8];
+    j.b = req->b;
+    j.x = req->x;
+    j.rtol = req->rtol;
+    j.max_iter = req->max_iter;
+    j.prec = req->prec;
+    const size_t bytes = make_layout(j.d, req->prec, q->opt, q->opt.jacobi ? 8 : 9).bytes;
+    return enqueue(q, j, 1, bytes, ticket, "s7_queue_submit_2d9");
 }
 
 int s7_queue_poll(s7_queue* q, uint64_t ticket, s7_info* info) {

@@ -199,6 +199,20 @@ def batch_shapes(nsys: int = 64, seed: int = 0):
     return [tuple(int(v) for v in row) for row in sides], [1000 + s for s in range(nsys)]
 
 
+# the batched 2D 9-point workload: 64 meshes, each side uniform over these
+BATCH_SIDES_2D9 = (96, 128, 192, 256, 384, 512)
+AID_BATCH_SIDES_2D9 = 28
+
+
+def batch_shapes_2d9(nsys: int = 64, seed: int = 0):
+    """Per-system 2D mesh sides (nx, ny), each uniform over BATCH_SIDES_2D9, plus
+    per-system seeds 2000 + s."""
+    u = uniform01(seed, AID_BATCH_SIDES_2D9, np.arange(2 * nsys))
+    idx = np.minimum((u * len(BATCH_SIDES_2D9)).astype(np.int64), len(BATCH_SIDES_2D9) - 1)
+    sides = np.array(BATCH_SIDES_2D9)[idx].reshape(nsys, 2)
+    return [tuple(int(v) for v in row) for row in sides], [2000 + s for s in range(nsys)]
+
+
 @dataclass
 class Request:
     rid: int

@@ -38,12 +38,14 @@ def test_struct_layouts_match_header(tmp_path):
     src.write_text('#include "s7.h"\n#include <stdio.h>\n#include <stddef.h>\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(s7_options),'
                    ' sizeof(s7_info), sizeof(s7_request), offsetof(s7_info, pass_ms),'
-                   ' offsetof(s7_request, rtol), sizeof(s7_dims)); return 0;}\n')
+                   ' offsetof(s7_request, rtol), sizeof(s7_dims)); printf("%zu %zu\\n",'
+                   ' sizeof(s7_request_2d9), offsetof(s7_request_2d9, rtol)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(binding.Options), C.sizeof(binding.Info), C.sizeof(binding.Request),
-            binding.Info.pass_ms.offset, binding.Request.rtol.offset, C.sizeof(binding.Dims)]
+            binding.Info.pass_ms.offset, binding.Request.rtol.offset, C.sizeof(binding.Dims),
+            C.sizeof(binding.Request2D9), binding.Request2D9.rtol.offset]
     assert got == want
 
 
@@ -103,6 +105,8 @@ def test_queue_host_side_checks():
     assert lib.s7_queue_poll(None, 1, None) == B.EINVAL
     assert lib.s7_queue_wait(None, 1, None) == B.EINVAL
     assert lib.s7_queue_destroy(None) == B.EINVAL
+    req9 = B.Request2D9(8, 8, (C.c_void_p * 9)(*([256] * 9)), 512, 768, 1e-6, 10, 0)
+    assert lib.s7_queue_submit_2d9(None, C.byref(req9), C.byref(t)) == B.EINVAL
 
 
 def test_host_side_argument_checks_2d9():

@@ -99,3 +99,13 @@ def test_bench_byte_accounting_2d9():
     assert sum(bench.BYTES_2D9.values()) == 128
     assert bench.BYTES_2D9_16 == {"p1": 22, "p2": 24, "p3": 22}
     assert sum(bench.BYTES_2D9_16.values()) == 68
+
+
+def test_batch_shapes_2d9():
+    shapes, seeds = synth.batch_shapes_2d9(64, seed=0)
+    assert len(shapes) == 64 and seeds == [2000 + s for s in range(64)]
+    flat = [v for d in shapes for v in d]
+    assert set(flat) == set(synth.BATCH_SIDES_2D9)  # every side value occurs
+    assert all(len(d) == 2 for d in shapes)
+    assert max(nx * ny for nx, ny in shapes) < 2 ** 21  # every mesh stays in the shared launch
+    assert synth.batch_shapes_2d9(64, seed=0) == (shapes, seeds)
