@@ -469,6 +469,101 @@ def served_leg(s7, torch, dev, nreq: int, rate: float, burst: int, arena_gb: flo
     res["alone_vs_mix_identical"] = f"{same}/{len(kept)}"
     return res
 
+def served_2d9_leg(s7, torch, dev, nreq: int, arena_gb: float, sample: int = 10):
+    """A burst of `nreq` 2D 9-point requests arriving at once: sides log-uniform in
+    [64, 1024] per axis, 50/50 FP32 rtol 1e-6 / BF16+FP64 IR rtol 1e-10.  The queue and a
+    serial loop of single-system calls serve the same burst; the inputs are generated
+    beforehand, and latency runs from the burst's start to each result."""
+    import numpy as np
+
+    import synth
+    prec_of = {"fp32": s7.FP32, "bf16_ir": s7.BF16_IR}
+    reqs = synth.serve_stream_2d9(nreq, seed=0)
+
+    def make(r):
+        nx, ny = r.dims
+        n = nx * ny
+        c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(9)]
+        xx = torch.empty(n, dtype=torch.float64, device=dev)
+        bb = torch.empty(n, dtype=torch.float64, device=dev)
+        s7.generate_problem_2d9(nx, ny, r.seed, c, xx, bb)
+        return c, bb, torch.zeros(n, dtype=torch.float64, device=dev), xx
+
+    data = [make(r) for r in reqs]
+    torch.cuda.synchronize()
+    arena = torch.empty(int(arena_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+
+    def summarize(rs, lat, t_total, status):
+        lat = np.array(lat) * 1e3
+        out = {"solves_per_s": round(len(lat) / t_total, 2),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "not_ok": int(sum(1 for st in status if st != s7.OK))}
+        for m in ("fp32", "bf16_ir"):
+            e = [float(torch.linalg.vector_norm(d[2] - d[3]) / torch.linalg.vector_norm(d[3]))
+                 for r, d in zip(rs, data) if r.mode == m]
+            if e:
+                out[f"max_rel_err_vs_xstar_{m}"] = float(f"{max(e):.3e}")
+        return out
+
+    def run_queue(rs):
+        for d in data[:len(rs)]:
+            d[2].zero_()
+        torch.cuda.synchronize()
+        q = s7.queue_create(arena)
+        t0 = time.perf_counter()
+        subs = []
+        for r, (c, bb, x, xx) in zip(rs, data):
+            subs.append((time.perf_counter(), s7.queue_submit_2d9(q, *r.dims, c, bb, x, r.rtol, 4000,
+                                                                 prec_of[r.mode])))
+        lat, status = [], []
+        for t_sub, tk in subs:
+            rc, info = s7.queue_wait(q, tk)
+            lat.append(t_sub - t0 + info.t_ms * 1e-3)
+            status.append(rc)
+        s7.queue_destroy(q)
+        return summarize(rs, lat, max(lat), status)
+
+    def run_serial(rs):
+        ws = torch.empty(max(s7.workspace_bytes_2d9(*r.dims, prec_of[r.mode]) for r in rs),
+                         dtype=torch.uint8, device=dev)
+        for d in data[:len(rs)]:
+            d[2].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat, status = [], []
+        for r, (c, bb, x, xx) in zip(rs, data):
+            info = s7.bicgstab_solve_2d9(*r.dims, c, bb, x, r.rtol, 4000, prec=prec_of[r.mode], ws=ws)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+            status.append(info.status)
+        return summarize(rs, lat, lat[-1], status)
+
+    run_queue(reqs[:8])  # warm-up
+    run_serial(reqs[:8])
+    res = {"workload": f"burst of {nreq} 2D 9-point requests, sides log-uniform in [64,1024] per axis, "
+                       f"50/50 FP32 rtol 1e-6 / BF16+FP64 IR rtol 1e-10",
+           "cells": sum(r.dims[0] * r.dims[1] for r in reqs), "latency": "burst start to result"}
+    print(f"[bench] served 2D burst: {nreq} requests through the queue", file=sys.stderr, flush=True)
+    res["queue"] = run_queue(reqs)
+    keep = list(range(0, nreq, max(1, nreq // sample)))
+    kept = {i: data[i][2].clone() for i in keep}
+    print("[bench] served 2D burst: serial single-system loop", file=sys.stderr, flush=True)
+    res["serial"] = run_serial(reqs)
+    # each sampled request solved alone by the batched 2D call must match its served result
+    same = 0
+    for i in keep:
+        r, (c, bb, x, xx) = reqs[i], data[i]
+        x.zero_()
+        s7.bicgstab_solve_batched_2d9([r.dims], [c], [bb], [x], [r.rtol], [4000], prec=prec_of[r.mode])
+        torch.cuda.synchronize()
+        same += bool(torch.equal(x, kept[i]))
+    res["alone_vs_mix_identical"] = f"{same}/{len(keep)}"
+    del data, arena
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -499,6 +594,8 @@ def main():
     ap.add_argument("--serve-sample", type=int, default=100,
                     help="served requests re-solved alone for the identity check")
     ap.add_argument("--arena-gb", type=float, default=64.0)
+    ap.add_argument("--serve-2d9-burst", type=int, default=200,
+                    help="2D 9-point requests in the served burst leg (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 2 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -663,6 +760,8 @@ def main():
         out["served"] = served_leg(s7, torch, dev, args.serve_requests, args.serve_rate,
                                    args.serve_burst, args.arena_gb, args.serve_sample)
         torch.cuda.empty_cache()
+        if not args.no_2d9 and args.serve_2d9_burst > 0:
+            out["served_2d9"] = served_2d9_leg(s7, torch, dev, args.serve_2d9_burst, 16.0)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nx, ny, nz, min(args.cpu_slab, nz), args.cpu_iters)

@@ -237,3 +237,23 @@ def serve_stream(n: int = 10000, rate: float = 200.0, seed: int = 0, lo: int = 1
         out.append(Request(i, float(t[i]), tuple(int(v) for v in sides[i]), mode,
                            1e-6 if mode == "fp32" else 1e-10, 1_000_000 + i))
     return out
+
+
+AID_SERVE2_GAP, AID_SERVE2_SIDE, AID_SERVE2_MODE = 29, 30, 31
+
+
+def serve_stream_2d9(n: int = 200, rate: float = 200.0, seed: int = 0, lo: int = 64, hi: int = 1024):
+    """2D 9-point requests: Poisson arrivals, sides (nx, ny) log-uniform in [lo, hi],
+    50/50 modes (FP32 1e-6, BF16+IR 1e-10), seeds 3 * 10^6 + id."""
+    ids = np.arange(n)
+    gaps = -np.log1p(-uniform01(seed, AID_SERVE2_GAP, ids)) / rate
+    t = np.cumsum(gaps)
+    u = uniform01(seed, AID_SERVE2_SIDE, np.arange(2 * n)).reshape(n, 2)
+    sides = np.rint(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))).astype(np.int64)
+    modes = uniform01(seed, AID_SERVE2_MODE, ids) < 0.5
+    out = []
+    for i in range(n):
+        mode = "fp32" if modes[i] else "bf16_ir"
+        out.append(Request(i, float(t[i]), tuple(int(v) for v in sides[i]), mode,
+                           1e-6 if mode == "fp32" else 1e-10, 3_000_000 + i))
+    return out

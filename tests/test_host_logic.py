@@ -109,3 +109,18 @@ def test_batch_shapes_2d9():
     assert all(len(d) == 2 for d in shapes)
     assert max(nx * ny for nx, ny in shapes) < 2 ** 21  # every mesh stays in the shared launch
     assert synth.batch_shapes_2d9(64, seed=0) == (shapes, seeds)
+
+
+def test_serve_stream_2d9_statistics():
+    """2D requests: sides log-uniform in [64, 1024] per axis, half FP32 at 1e-6 and half
+    BF16+refinement at 1e-10, seeds 3 * 10^6 + id, a stream of its own."""
+    reqs = synth.serve_stream_2d9(4000, seed=0)
+    sides = np.array([r.dims for r in reqs])
+    assert sides.shape == (4000, 2) and sides.min() >= 64 and sides.max() <= 1024
+    logs = np.log(sides.astype(float))
+    assert abs(logs.mean() - 0.5 * (math.log(64) + math.log(1024))) < 0.03
+    modes = [r.mode for r in reqs]
+    assert abs(modes.count("fp32") / len(modes) - 0.5) < 0.03
+    assert all(r.rtol == (1e-6 if r.mode == "fp32" else 1e-10) for r in reqs)
+    assert [r.seed for r in reqs[:2]] == [3_000_000, 3_000_001]
+    assert synth.serve_stream_2d9(10, seed=0)[3].dims == reqs[3].dims
