@@ -136,7 +136,8 @@ typedef struct {
     int32_t pass_count[4];
     int32_t schedule;    /* the schedule it ran: 1 three passes, 2 four passes, 3 three
                             passes on cell pairs.  Batched and queue engine solves run
-                            three phases per iteration: 3 if nx is even, else 1 */
+                            three phases per iteration: 3 if nx is even, else 1; the
+                            2D 9-point solves (single, batched, queued) report 1 */
     int32_t reserved;
 } s7_info;
 
