@@ -173,3 +173,35 @@ def test_many_small_meshes(s7):
         p, A, b = probs[k]
         ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
         assert rel_err(xs[k], ref.x) <= 1e-5
+
+
+def test_batch_workload_64_meshes(s7):
+    """The batched 2D workload the benchmark times: 64 meshes, each side uniform over
+    {96,...,512}, seeds 2000 + s, tolerance 1e-7, autotuned.  Every system is checked
+    for status, true residual and error against x*; a sample against the oracle."""
+    import torch
+    shapes, seeds = synth.batch_shapes_2d9(64, seed=0)
+    coefs, bs, xs, xstars = [], [], [], []
+    for (nx, ny), sd in zip(shapes, seeds):
+        n = nx * ny
+        c = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(9)]
+        xsd = torch.empty(n, dtype=torch.float64, device="cuda")
+        bd = torch.empty(n, dtype=torch.float64, device="cuda")
+        s7.generate_problem_2d9(nx, ny, sd, c, xsd, bd)
+        coefs.append(c)
+        bs.append(bd)
+        xstars.append(xsd)
+        xs.append(torch.zeros(n, dtype=torch.float64, device="cuda"))
+    rc, infos = s7.bicgstab_solve_batched_2d9(shapes, coefs, bs, xs, [1e-7] * 64, [2000] * 64,
+                                              opt=s7.default_options(tune=1))
+    torch.cuda.synchronize()
+    assert rc == s7.OK
+    for k, info in enumerate(infos):
+        assert info.status == s7.OK and info.rel_res_true <= 1e-6, k
+        err = float(torch.linalg.vector_norm(xs[k] - xstars[k]) / torch.linalg.vector_norm(xstars[k]))
+        assert err <= 1e-5, (k, err)
+    big = max(range(64), key=lambda k: shapes[k][0] * shapes[k][1])
+    for k in (0, 31, big):
+        (p, A, b), = problems9([shapes[k]], [seeds[k]])
+        ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+        assert rel_err(host(xs[k]), ref.x) <= 1e-5, k

@@ -144,3 +144,34 @@ def test_submit_2d9_refuses_what_cannot_fit(s7):
         assert e.value.code == s7.EINVAL
     finally:
         s7.queue_destroy(q)
+
+
+def test_served_burst_workload(s7):
+    """The first 40 requests of the benchmark's 2D request stream (sides log-uniform in
+    [64, 1024], 50/50 FP32 at 1e-6 and BF16+IR at 1e-10), submitted at once: all reach
+    their manufactured solutions, a sample matches the oracle."""
+    import torch
+    reqs = synth.serve_stream_2d9(40, seed=0)
+    data = []
+    for r in reqs:
+        nx, ny = r.dims
+        n = nx * ny
+        c = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(9)]
+        xs = torch.empty(n, dtype=torch.float64, device="cuda")
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        s7.generate_problem_2d9(nx, ny, r.seed, c, xs, b)
+        data.append((c, b, zeros(n), xs))
+    torch.cuda.synchronize()
+    prec = {"fp32": s7.FP32, "bf16_ir": s7.BF16_IR}
+    out = run_queue(s7, lambda q: [s7.queue_submit_2d9(q, *r.dims, c, b, x, r.rtol, 4000, prec[r.mode])
+                                   for r, (c, b, x, xs) in zip(reqs, data)], 4 << 30)
+    for r, (c, b, x, xs), (rc, info) in zip(reqs, data, out):
+        assert rc == s7.OK, (r, info.as_dict())
+        err = float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))
+        assert err <= (1e-3 if r.mode == "fp32" else 1e-8), (r, err)
+    for k in (0, 7, 21):
+        r = reqs[k]
+        p, A, b = problem9(r.dims, r.seed)
+        ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=4000)
+        # FP32 at rtol 1e-6 stops near its own tolerance; BF16+IR reaches 1e-10
+        assert rel_err(host(data[k][2]), ref.x) <= (5e-4 if r.mode == "fp32" else 1e-8), (k, r.mode)
