@@ -66,23 +66,23 @@ struct Bits<double> {
 template <class T>
 __device__ __forceinline__ T cload(const T* p) {
     using U = typename Bits<T>::U;
-    const U u = __hip_atomic_load(reinterpret_cast<U*>(const_cast<T*>(p)), __ATOMIC_RELAXED,
+    const U u = __hip_atomic_load(gbl(reinterpret_cast<U*>(const_cast<T*>(p))), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
     return __builtin_bit_cast(T, u);
 }
 template <class T>
 __device__ __forceinline__ void cstore(T* p, T v) {
     using U = typename Bits<T>::U;
-    __hip_atomic_store(reinterpret_cast<U*>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
+    __hip_atomic_store(gbl(reinterpret_cast<U*>(p)), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double cload_d(const double* p) { return fetch_published(p); }
 __device__ __forceinline__ void cstore_d(double* p, double v) { publish(p, v); }
 __device__ __forceinline__ int32_t cload_i(const int32_t* p) {
-    return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gbl(const_cast<int32_t*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void cstore_i(int32_t* p, int32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <class T>
@@ -101,7 +101,7 @@ __device__ __forceinline__ void state_load(const State* src, State& dst) {
     const int w = (int)threadIdx.x;
     if (w < kStateWords)
         reinterpret_cast<uint32_t*>(&dst)[w] = __hip_atomic_load(
-            const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(src) + w), __ATOMIC_RELAXED,
+            gbl(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(src) + w)), __ATOMIC_RELAXED,
             __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
 }
@@ -109,7 +109,7 @@ __device__ __forceinline__ void state_load(const State* src, State& dst) {
 __device__ __forceinline__ void state_store(State* dst, const State& src) {
     const int w = (int)threadIdx.x;
     if (w < kStateWords) {
-        __hip_atomic_store(reinterpret_cast<uint32_t*>(dst) + w, reinterpret_cast<const uint32_t*>(&src)[w],
+        __hip_atomic_store(gbl(reinterpret_cast<uint32_t*>(dst) + w), reinterpret_cast<const uint32_t*>(&src)[w],
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wait_stores();
     }
@@ -329,25 +329,25 @@ __device__ void chunk_p1_b(const SysView<T>& S, int c0, int c1, double (&acc)[kM
 // Coherent loads and stores of two adjacent elements (8 bytes FP32, 4 bytes
 // 16-bit; the first element's index is even).
 __device__ __forceinline__ F2 cload2(const float* p) {
-    const uint64_t u = __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<float*>(p)),
+    const uint64_t u = __hip_atomic_load(gbl(reinterpret_cast<uint64_t*>(const_cast<float*>(p))),
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return F2{__uint_as_float((uint32_t)u), __uint_as_float((uint32_t)(u >> 32))};
 }
 template <class T>
 __device__ __forceinline__ F2 cload2(const T* p) {
-    const uint32_t u = __hip_atomic_load(reinterpret_cast<uint32_t*>(const_cast<T*>(p)), __ATOMIC_RELAXED,
+    const uint32_t u = __hip_atomic_load(gbl(reinterpret_cast<uint32_t*>(const_cast<T*>(p))), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
     return split16(u, p);
 }
 __device__ __forceinline__ void cstore2(float* p, float a, float b) {
     const uint64_t u = (uint64_t)__float_as_uint(a) | ((uint64_t)__float_as_uint(b) << 32);
-    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gbl(reinterpret_cast<uint64_t*>(p)), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <class T>
 __device__ __forceinline__ void cstore2(T* p, T a, T b) {
     using U = typename Bits<T>::U;
     const uint32_t u = (uint32_t)__builtin_bit_cast(U, a) | ((uint32_t)__builtin_bit_cast(U, b) << 16);
-    __hip_atomic_store(reinterpret_cast<uint32_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gbl(reinterpret_cast<uint32_t*>(p)), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <class T>
 __device__ __forceinline__ void cload_nbr2(const T* v, const Cell& c, Nbr<float>& v0, Nbr<float>& v1) {
@@ -519,7 +519,7 @@ __device__ void chunk_r_b(const SysView<float>& S, const Coef7& cf, const double
         const Nbr<double> xv{cload(px), cload(px + c.dw), cload(px + c.de), cload(px + c.ds),
                              cload(px + c.dn), cload(px + c.db), cload(px + c.dt)};
         const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
-        const double bi = b[c.idx];
+        const double bi = *gbl(b + c.idx);
         const double r0 = bi - apply7<double, float, false, true>(k, xv, c);
         const double rs = S.unit ? r0 / (double)k.a[0] : r0;
         const float rf = (float)rs;
@@ -541,7 +541,7 @@ __device__ void chunk_s_b(const SysView<float>& S, const Coef7& cf, const double
         const Nbr<double> xv{cload(px), cload(px + c.dw), cload(px + c.de), cload(px + c.ds),
                              cload(px + c.dn), cload(px + c.db), cload(px + c.dt)};
         const Coefs<float, false> k = load_coefs<float, false>(cf.c, c.idx);
-        const double bi = b[c.idx];
+        const double bi = *gbl(b + c.idx);
         double r0 = bi - apply7<double, float, false, true>(k, xv, c), bs = bi;
         if (S.unit) {
             const double dg = (double)k.a[0];
@@ -702,9 +702,9 @@ __device__ void chunk_r_b9(const SysView<float>& S, const Coef9& cf, const doubl
         const Cell c = cell_at(g, S.m, S.n);
         double xv[9];
         cload9d(x, c, xv);
-        const double bi = b[c.idx];
+        const double bi = *gbl(b + c.idx);
         const double r0 = bi - apply9_masked<double>(cf, c, xv);
-        const double rs = S.unit ? r0 / (double)cf.c[0][c.idx] : r0;
+        const double rs = S.unit ? r0 / (double)*gbl(cf.c[0] + c.idx) : r0;
         const float rf = (float)rs;
         if (write_d) cstore(S.d + c.idx, rf);
         acc[0] = fma(bi, bi, acc[0]);
@@ -720,10 +720,10 @@ __device__ void chunk_s_b9(const SysView<float>& S, const Coef9& cf, const doubl
         const Cell c = cell_at(g, S.m, S.n);
         double xv[9];
         cload9d(x, c, xv);
-        const double bi = b[c.idx];
+        const double bi = *gbl(b + c.idx);
         double r0 = bi - apply9_masked<double>(cf, c, xv), bs = bi;
         if (S.unit) {
-            const double dg = (double)cf.c[0][c.idx];
+            const double dg = (double)*gbl(cf.c[0] + c.idx);
             r0 = r0 / dg;
             bs = bs / dg;
         }
@@ -826,7 +826,7 @@ __device__ int after_resid(State& st, const double (&tot)[kMaxDots]) {
 
 // ---------------------------------------------------------------- persistent kernel
 template <int OP>
-__global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* glob,
+__global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ sys, BGlobal* glob,
                                                       int nsys, int chunk_cells,
                                                       long long spin_limit) {
     __shared__ int sh_sys, sh_chunk, sh_last, sh_stop, sh_budget;
@@ -843,10 +843,10 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
             for (int tries = 0; tries < nsys; ++tries, s = (s + 1 == nsys) ? 0 : s + 1) {
                 const int act = cload_i(&sys[s].ctl->active);
                 const unsigned long long w0 =
-                    __hip_atomic_load(&sys[s].ctl->claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_load(gbl(&sys[s].ctl->claim), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (!act || (int)(w0 & 0xffffffffull) >= sys[s].nchunk) continue;
                 const unsigned long long w = __hip_atomic_fetch_add(
-                    &sys[s].ctl->claim, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    gbl(&sys[s].ctl->claim), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const int c = (int)(w & 0xffffffffull);
                 if (c < sys[s].nchunk) {
                     sh_sys = s;
@@ -861,7 +861,11 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
             }
         }
         __syncthreads();
-        const int me = sh_sys;
+        // The claim is the same for the whole workgroup: taking it as a scalar
+        // lets the table entry and the system's base pointers live in scalar
+        // registers, and the vector accesses take a scalar base with a 32-bit
+        // lane offset.
+        const int me = __builtin_amdgcn_readfirstlane(sh_sys);
         if (me == -2) return;
         if (me < 0) {
             if (++idle > spin_limit) {
@@ -876,8 +880,8 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
         const BSys& B = sys[me];
         const SysView<float> S = B.S;
         const int tag = B.tag;
-        const int chunk = sh_chunk;
-        const uint32_t seq = sh_seq;
+        const int chunk = __builtin_amdgcn_readfirstlane(sh_chunk);
+        const uint32_t seq = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh_seq);
         const int kind = (int)(seq & 7u);
         const int c0 = chunk * chunk_cells;
         const int c1 = min(S.n, c0 + chunk_cells);
@@ -918,7 +922,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
         if (threadIdx.x == 0) {
             for (int j = 0; j < kND[kind]; ++j) publish(&S.red.part[(size_t)chunk * kMaxDots + j], bsum[j]);
             wait_stores();
-            const uint32_t t = __hip_atomic_fetch_add(&B.ctl->done_cnt, 1u, __ATOMIC_RELAXED,
+            const uint32_t t = __hip_atomic_fetch_add(gbl(&B.ctl->done_cnt), 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             sh_last = (t == (uint32_t)(B.nchunk - 1));
         }
@@ -978,7 +982,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
         state_store(S.st, sh_state);
         __syncthreads();  // every word of the State has reached memory
         if (threadIdx.x == 0) {
-            __hip_atomic_store(&B.ctl->done_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(gbl(&B.ctl->done_cnt), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             cstore_i(&B.ctl->budget, sh_budget);
             const uint32_t nseq = sh_nseq;
             if (sh_stop) {
@@ -986,13 +990,13 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* sys, BGlobal* 
                 // Park the claim word on the phase to resume, with its chunk counter
                 // already exhausted: a workgroup racing this store claims nothing.  The
                 // next launch's arm step rewinds the counter.
-                __hip_atomic_store(&B.ctl->claim, ((unsigned long long)nseq << 32) | (unsigned)B.nchunk,
+                __hip_atomic_store(gbl(&B.ctl->claim), ((unsigned long long)nseq << 32) | (unsigned)B.nchunk,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 wait_stores();
                 __hip_atomic_fetch_add(&glob->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 wait_stores();
-                __hip_atomic_store(&B.ctl->claim, (unsigned long long)nseq << 32, __ATOMIC_RELAXED,
+                __hip_atomic_store(gbl(&B.ctl->claim), (unsigned long long)nseq << 32, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
         }

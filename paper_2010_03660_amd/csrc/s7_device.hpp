@@ -80,17 +80,32 @@ template <>
 __device__ __forceinline__ f16 from_f32<f16>(float f) { return (f16)f; }  // RNE
 
 // ---------------------------------------------------------------- streaming access
+// Every array here is device (global) memory.  A pointer the compiler cannot
+// trace to a kernel argument (one read from a table in memory) is generic to
+// it, and generic accesses become flat instructions with 64-bit per-lane
+// addresses; seen through the global address space they become global
+// instructions, which also take a scalar base with a 32-bit lane offset.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gbl(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // Non-temporal loads and stores for data touched once per pass (coefficients,
 // r0, and the vectors a pass writes).  The cached path is kept for operands
 // whose halo neighbours re-read them.
-__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ double ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ f16 ld_nt(const f16* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(gbl(p)); }
+__device__ __forceinline__ double ld_nt(const double* p) { return __builtin_nontemporal_load(gbl(p)); }
+__device__ __forceinline__ f16 ld_nt(const f16* p) { return __builtin_nontemporal_load(gbl(p)); }
 __device__ __forceinline__ bf16 ld_nt(const bf16* p) {
     bf16 r;
-    r.u = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
+    r.u = __builtin_nontemporal_load(gbl(reinterpret_cast<const uint16_t*>(p)));
     return r;
 }
+// A plain (cached) load through the global address space.
+__device__ __forceinline__ float ld(const float* p) { return *gbl(p); }
+__device__ __forceinline__ double ld(const double* p) { return *gbl(p); }
+__device__ __forceinline__ f16 ld(const f16* p) { return *gbl(p); }
+__device__ __forceinline__ bf16 ld(const bf16* p) { return bf16{*gbl(reinterpret_cast<const uint16_t*>(p))}; }
 __device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void st_nt(f16* p, f16 v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void st_nt(bf16* p, bf16 v) {
@@ -277,7 +292,7 @@ template <class CT, bool UNIT>
 __device__ __forceinline__ Coefs<CT, UNIT> load_coefs(const CT* const* c, int idx) {
     Coefs<CT, UNIT> r;
 #pragma unroll
-    for (int a = UNIT ? 1 : 0; a < 7; ++a) r.a[a] = c[a][idx];
+    for (int a = UNIT ? 1 : 0; a < 7; ++a) r.a[a] = ld(c[a] + idx);
     return r;
 }
 
@@ -372,10 +387,10 @@ __host__ __device__ inline int red_groups(int nblocks) { return (nblocks + kGrou
 __host__ __device__ inline bool red_split(int nblocks) { return nblocks > kSingleMax; }
 
 __device__ __forceinline__ void publish(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double fetch_published(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gbl(const_cast<double*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Waits until this thread's stores have completed; the signal fences keep the
 // compiler from moving memory operations across the wait.
@@ -664,7 +679,7 @@ __device__ __forceinline__ F2 ld2(const float* p) {
     return F2{v.x, v.y};
 }
 __device__ __forceinline__ F2 ld2_nt(const float* p) {
-    const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+    const f32x2 v = __builtin_nontemporal_load(gbl(reinterpret_cast<const f32x2*>(p)));
     return F2{v.x, v.y};
 }
 __device__ __forceinline__ F2 split16(uint32_t u, const bf16*) {
@@ -680,7 +695,7 @@ __device__ __forceinline__ F2 ld2(const T* p) {
 }
 template <class T>
 __device__ __forceinline__ F2 ld2_nt(const T* p) {
-    return split16(__builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p)), p);
+    return split16(__builtin_nontemporal_load(gbl(reinterpret_cast<const uint32_t*>(p))), p);
 }
 __device__ __forceinline__ void st2(float* p, float a, float b) {
     *reinterpret_cast<f32x2*>(p) = f32x2{a, b};

@@ -71,9 +71,9 @@ template <class V>
 __device__ __forceinline__ V apply9_masked(const Coef9& cf, const Cell& c, const V (&x)[9]) {
     bool in[9];
     inside9(c, in);
-    V acc = (V)cf.c[0][c.idx] * x[0];
+    V acc = (V)*gbl(cf.c[0] + c.idx) * x[0];
 #pragma unroll
-    for (int a = 1; a < 9; ++a) acc = fma9(in[a] ? (V)cf.c[a][c.idx] : (V)0, x[a], acc);
+    for (int a = 1; a < 9; ++a) acc = fma9(in[a] ? (V)*gbl(cf.c[a] + c.idx) : (V)0, x[a], acc);
     return acc;
 }
 
