@@ -564,6 +564,122 @@ def served_2d9_leg(s7, torch, dev, nreq: int, arena_gb: float, sample: int = 10)
     return res
 
 
+def served_mixed_leg(s7, torch, dev, nreq: int, rate: float):
+    """3D and 2D requests in one Poisson stream at `rate` per second (each operator half
+    of it: the 3D stream's sides log-uniform in [16,256] per axis, the 2D stream's in
+    [64,1024]; 50/50 FP32 rtol 1e-6 / BF16+FP64 IR rtol 1e-10), through the queue and
+    through a serial loop of single-system calls.  Inputs are generated beforehand;
+    latency runs from the scheduled arrival to the result."""
+    import queue as pyqueue
+    import threading
+
+    import numpy as np
+
+    import synth
+    prec_of = {"fp32": s7.FP32, "bf16_ir": s7.BF16_IR}
+    half = nreq // 2
+    reqs = [("3d", r) for r in synth.serve_stream(half, rate=rate / 2, seed=5)]
+    reqs += [("2d", r) for r in synth.serve_stream_2d9(nreq - half, rate=rate / 2, seed=5)]
+    reqs.sort(key=lambda kr: kr[1].arrival_s)
+
+    def make(kind, r):
+        n = int(np.prod(r.dims))
+        c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(7 if kind == "3d" else 9)]
+        xx = torch.empty(n, dtype=torch.float64, device=dev)
+        bb = torch.empty(n, dtype=torch.float64, device=dev)
+        if kind == "3d":
+            s7.generate_problem(r.dims, r.seed, 0, c, xx, bb)
+        else:
+            s7.generate_problem_2d9(*r.dims, r.seed, c, xx, bb)
+        return c, bb, torch.zeros(n, dtype=torch.float64, device=dev), xx
+
+    data = [make(k, r) for k, r in reqs]
+    torch.cuda.synchronize()
+    arena = torch.empty(32 << 30, dtype=torch.uint8, device=dev)
+
+    def summarize(lat, status):
+        out = {}
+        for kind in ("3d", "2d"):
+            v = np.array([t for (k, r), t in zip(reqs, lat) if k == kind]) * 1e3
+            out[kind] = {"p50_ms": round(float(np.percentile(v, 50)), 3),
+                         "p99_ms": round(float(np.percentile(v, 99)), 3)}
+        out["not_ok"] = int(sum(1 for st in status if st != s7.OK))
+        out["max_rel_err_vs_xstar"] = float(f"{max(float(torch.linalg.vector_norm(d[2] - d[3]) / torch.linalg.vector_norm(d[3])) for d in data):.3e}")
+        return out
+
+    def run_queue():
+        for d in data:
+            d[2].zero_()
+        torch.cuda.synchronize()
+        q = s7.queue_create(arena)
+        handoff = pyqueue.Queue()
+        t0 = time.perf_counter()
+
+        def producer():
+            try:
+                for (kind, r), (c, bb, x, xx) in zip(reqs, data):
+                    wait = t0 + r.arrival_s - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    t_sub = time.perf_counter()
+                    if kind == "3d":
+                        tk = s7.queue_submit(q, r.dims, c, bb, x, r.rtol, 4000, prec_of[r.mode])
+                    else:
+                        tk = s7.queue_submit_2d9(q, *r.dims, c, bb, x, r.rtol, 4000, prec_of[r.mode])
+                    handoff.put((r, tk, t_sub))
+            finally:
+                handoff.put(None)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        lat, status = [], []
+        while True:
+            item = handoff.get()
+            if item is None:
+                break
+            r, tk, t_sub = item
+            rc, info = s7.queue_wait(q, tk)
+            lat.append(t_sub + info.t_ms * 1e-3 - (t0 + r.arrival_s))
+            status.append(rc)
+        th.join()
+        s7.queue_destroy(q)
+        if len(status) != len(reqs):
+            raise RuntimeError("the request producer stopped early")
+        return summarize(lat, status)
+
+    def run_serial():
+        ws = torch.empty(max(s7.workspace_bytes(r.dims, prec_of[r.mode]) if k == "3d" else
+                             s7.workspace_bytes_2d9(*r.dims, prec_of[r.mode]) for k, r in reqs),
+                         dtype=torch.uint8, device=dev)
+        for d in data:
+            d[2].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat, status = [], []
+        for (kind, r), (c, bb, x, xx) in zip(reqs, data):
+            wait = t0 + r.arrival_s - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            if kind == "3d":
+                info = s7.bicgstab_solve(r.dims, c, bb, x, r.rtol, 4000, prec=prec_of[r.mode], ws=ws)
+            else:
+                info = s7.bicgstab_solve_2d9(*r.dims, c, bb, x, r.rtol, 4000, prec=prec_of[r.mode], ws=ws)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - (t0 + r.arrival_s))
+            status.append(info.status)
+        return summarize(lat, status)
+
+    print(f"[bench] mixed 3D/2D stream: {nreq} requests at {rate:g}/s", file=sys.stderr, flush=True)
+    res = {"workload": f"{nreq} requests, Poisson at {rate:g}/s, half 3D 7-point (sides log-uniform in [16,256]) "
+                       f"and half 2D 9-point (sides in [64,1024]), 50/50 FP32 rtol 1e-6 / BF16+FP64 IR rtol 1e-10",
+           "latency": "scheduled arrival to result", "queue": run_queue()}
+    print("[bench] mixed 3D/2D stream: serial single-system loop", file=sys.stderr, flush=True)
+    res["serial"] = run_serial()
+    del data, arena
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -594,6 +710,8 @@ def main():
     ap.add_argument("--serve-sample", type=int, default=100,
                     help="served requests re-solved alone for the identity check")
     ap.add_argument("--arena-gb", type=float, default=64.0)
+    ap.add_argument("--serve-mixed", type=int, default=400,
+                    help="requests in the mixed 3D/2D Poisson stream leg (0: skip)")
     ap.add_argument("--serve-2d9-burst", type=int, default=200,
                     help="2D 9-point requests in the served burst leg (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -762,6 +880,8 @@ def main():
         torch.cuda.empty_cache()
         if not args.no_2d9 and args.serve_2d9_burst > 0:
             out["served_2d9"] = served_2d9_leg(s7, torch, dev, args.serve_2d9_burst, 16.0)
+        if not args.no_2d9 and args.serve_mixed > 0:
+            out["served_mixed"] = served_mixed_leg(s7, torch, dev, args.serve_mixed, args.serve_rate)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nx, ny, nz, min(args.cpu_slab, nz), args.cpu_iters)
