@@ -85,6 +85,8 @@ def _load():
         lib.oracle_bicgstab.restype = C.c_int
         lib.oracle_bicgstab.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, _dp, C.c_double, C.c_int64,
                                         C.POINTER(_State), C.c_int64, _dp, _dp, _dp, _dp]
+        lib.oracle_bicgstab_pipelined.restype = C.c_int
+        lib.oracle_bicgstab_pipelined.argtypes = lib.oracle_bicgstab.argtypes
         _lib = lib
     return _lib
 
@@ -207,6 +209,26 @@ def bicgstab(A: CSR, b, x0=None, tol: float = 1e-8, max_iter: int = 500,
     tr = [np.zeros(max(nt, 1)) for _ in range(4)]
     lib.oracle_bicgstab(A.n, _i(As.rowptr), _i(As.col), _d(As.val), _d(bs), _d(x), tol,
                         max_iter, C.byref(st), nt, *[_d(t) for t in tr])
+    k = min(nt, int(st.iter))
+    return Result(x, int(st.status), int(st.reason), int(st.iter), float(st.res_rec),
+                  true_rel_residual(A, b, x), bool(st.half_exit),
+                  tr[0][:k], tr[1][:k], tr[2][:k], tr[3][:k])
+
+
+def bicgstab_pipelined(A: CSR, b, x0=None, tol: float = 1e-8, max_iter: int = 500,
+                       jacobi_scaling: bool = True, ntrace: int = 0) -> Result:
+    """Pipelined BiCGStab (Cools and Vanroose 2017) with one reduction per iteration, in
+    FP64: the iterates of Algorithm 1 in exact arithmetic, with the matrix products
+    carried by recurrences.  Same conventions as bicgstab()."""
+    lib = _load()
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    As, bs = jacobi(A, b) if jacobi_scaling else (A, b)
+    st = _State()
+    nt = max(int(ntrace), 0)
+    tr = [np.zeros(max(nt, 1)) for _ in range(4)]
+    lib.oracle_bicgstab_pipelined(A.n, _i(As.rowptr), _i(As.col), _d(As.val), _d(bs), _d(x), tol,
+                                  max_iter, C.byref(st), nt, *[_d(t) for t in tr])
     k = min(nt, int(st.iter))
     return Result(x, int(st.status), int(st.reason), int(st.iter), float(st.res_rec),
                   true_rel_residual(A, b, x), bool(st.half_exit),

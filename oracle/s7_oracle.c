@@ -309,3 +309,160 @@ int oracle_bicgstab(int64_t n, const int64_t *rowptr, const int64_t *col,
     free(buf);
     return st->status;
 }
+
+/*
+ * Pipelined BiCGStab (Cools and Vanroose, "The communication-hiding pipelined
+ * BiCGStab method for the parallel solution of large unsymmetric linear
+ * systems", Parallel Computing 65, 2017), in a form with a single reduction
+ * per iteration.  In exact arithmetic its iterates are those of Algorithm 1;
+ * the matrix products are carried forward by recurrences instead:
+ *   s_i = A p_i, z_i = A s_i, w_i = A r_i, t_i = A w_i, v_i = A z_i, y_i = A q_i.
+ * Iteration i:
+ *   p = r + beta (p - omega s),  s = w + beta (s - omega z),  z = t + beta (z - omega v)
+ *   q = r - alpha s,  y = w - alpha z,  v = A z
+ *   one reduction: (r,r), (q,y), (y,y), (q,q), (r0,q), (r0,y), (r0,t), (r0,v), (r0,s), (r0,z)
+ *   omega = (q,y)/(y,y);  x += alpha p + omega q;  r = q - omega y;  w = y - omega (t - alpha v)
+ *   rho' = (r0,q) - omega (r0,y)                       [= (r0, r_{i+1})]
+ *   beta = (alpha/omega) rho'/rho
+ *   sigma' = (r0,y) - omega ((r0,t) - alpha (r0,v)) + beta ((r0,s) - omega (r0,z))   [= (r0, A p_{i+1})]
+ *   alpha' = rho'/sigma';  t = A w
+ * with beta = 0 and p = s = z = v = 0 before iteration 0, w_0 = A r_0, t_0 = A w_0,
+ * rho_0 = (r0, r_0), alpha_0 = rho_0 / (r0, w_0).
+ * Readings (the method is not in the paper; these mirror Algorithm 1's):
+ *   - ||r_i|| is taken in iteration i's reduction, so the stopping test on
+ *     r_i, and the iteration cap, are decided there: x_i is returned and the
+ *     work of that iteration before the reduction is discarded;
+ *   - the half-step test on ||q|| and x += alpha p, as in Algorithm 1;
+ *   - breakdown: (r0, w_0) or sigma' == 0, (y,y) == 0, or a non-finite scalar;
+ *     rho' == 0 is a breakdown unless the recurrence value of ||r_{i+1}||^2,
+ *     (q,q) - 2 omega (q,y) + omega^2 (y,y), already meets the tolerance.
+ * x holds x0 on entry and the last iterate on exit; traces as oracle_bicgstab
+ * (rho, alpha, omega of iteration i, and ||r_{i+1}||/||b|| once known).
+ */
+int oracle_bicgstab_pipelined(int64_t n, const int64_t *rowptr, const int64_t *col,
+                              const double *val, const double *b, double *x, double tol,
+                              int64_t max_iter, oracle_bicg *st, int64_t ntrace,
+                              double *tr_rho, double *tr_alpha, double *tr_omega, double *tr_res) {
+    memset(st, 0, sizeof(*st));
+    st->tol = tol;
+    st->max_iter = max_iter;
+    st->nb = sqrt(oracle_dot(n, b, b));
+    if (st->nb == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        st->status = OR_OK;
+        st->done = 1;
+        return st->status;
+    }
+    double *buf = (double *)calloc((size_t)n * 11, sizeof(double));
+    if (!buf) return OR_ENOMEM;
+    double *r = buf, *rh = buf + n, *p = buf + 2 * n, *s = buf + 3 * n, *z = buf + 4 * n,
+           *q = buf + 5 * n, *y = buf + 6 * n, *w = buf + 7 * n, *t = buf + 8 * n, *v = buf + 9 * n,
+           *tmp = buf + 10 * n;
+    oracle_spmv(n, rowptr, col, val, x, tmp);
+    for (int64_t i = 0; i < n; ++i) {
+        r[i] = b[i] - tmp[i];
+        rh[i] = r[i];
+    }
+    oracle_spmv(n, rowptr, col, val, r, w);
+    oracle_spmv(n, rowptr, col, val, w, t);
+    st->rho = oracle_dot(n, rh, r);
+    st->res_rec = sqrt(oracle_dot(n, r, r)) / st->nb;
+    if (!isfinite(st->res_rec)) {
+        set_breakdown(st, OR_REASON_NONFINITE);
+    } else if (st->res_rec <= tol) {
+        st->status = OR_OK;
+        st->done = 1;
+    } else if (max_iter <= 0) {
+        st->status = OR_NOT_CONVERGED;
+        st->done = 1;
+    } else {
+        st->sigma = oracle_dot(n, rh, w);
+        if (st->sigma == 0.0) set_breakdown(st, OR_REASON_RS_ZERO);
+        else {
+            st->alpha = st->rho / st->sigma;
+            if (!isfinite(st->alpha)) set_breakdown(st, OR_REASON_NONFINITE);
+        }
+    }
+    st->beta = 0.0;
+    st->omega = 0.0;
+    while (!st->done) {
+        const int64_t it = st->iter;
+        const double a = st->alpha, bt = st->beta, om = st->omega;
+        for (int64_t i = 0; i < n; ++i) {
+            p[i] = r[i] + bt * (p[i] - om * s[i]);
+            s[i] = w[i] + bt * (s[i] - om * z[i]);
+            z[i] = t[i] + bt * (z[i] - om * v[i]);
+            q[i] = r[i] - a * s[i];
+            y[i] = w[i] - a * z[i];
+        }
+        oracle_spmv(n, rowptr, col, val, z, v);
+        const double rr = oracle_dot(n, r, r), qy = oracle_dot(n, q, y), yy = oracle_dot(n, y, y),
+                     qq = oracle_dot(n, q, q), rq = oracle_dot(n, rh, q), ry = oracle_dot(n, rh, y),
+                     rt = oracle_dot(n, rh, t), rv = oracle_dot(n, rh, v), rs = oracle_dot(n, rh, s),
+                     rz = oracle_dot(n, rh, z);
+        /* stopping tests on r_i, taken in this reduction */
+        const double res = sqrt(rr) / st->nb;
+        st->res_rec = res;
+        if (it > 0 && tr_res && it - 1 < ntrace) tr_res[it - 1] = res;
+        if (!isfinite(res)) { set_breakdown(st, OR_REASON_NONFINITE); break; }
+        if (res <= tol) { st->status = OR_OK; st->done = 1; break; }
+        if (it >= max_iter) { st->status = OR_NOT_CONVERGED; st->done = 1; break; }
+        if (it < ntrace) {
+            if (tr_rho) tr_rho[it] = st->rho;
+            if (tr_alpha) tr_alpha[it] = a;
+        }
+        const double qn = sqrt(qq) / st->nb;
+        if (qn <= tol) {
+            for (int64_t i = 0; i < n; ++i) x[i] = x[i] + a * p[i];
+            st->omega = 0.0;
+            st->iter = it + 1;
+            st->res_rec = qn;
+            st->half_exit = 1;
+            st->status = OR_OK;
+            st->done = 1;
+            if (it < ntrace) {
+                if (tr_omega) tr_omega[it] = 0.0;
+                if (tr_res) tr_res[it] = qn;
+            }
+            break;
+        }
+        if (yy == 0.0) { set_breakdown(st, OR_REASON_YY_ZERO); break; }
+        const double omn = qy / yy;
+        if (!isfinite(omn)) { set_breakdown(st, OR_REASON_NONFINITE); break; }
+        if (it < ntrace && tr_omega) tr_omega[it] = omn;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + a * p[i] + omn * q[i];
+            r[i] = q[i] - omn * y[i];
+            w[i] = y[i] - omn * (t[i] - a * v[i]);
+        }
+        st->iter = it + 1;
+        st->omega = omn;
+        const double rho_new = rq - omn * ry;
+        if (rho_new == 0.0) {
+            const double est = qq - 2.0 * omn * qy + omn * omn * yy;
+            const double rn = sqrt(est > 0.0 ? est : 0.0) / st->nb;
+            if (rn <= tol) {
+                st->res_rec = rn;
+                st->status = OR_OK;
+                st->done = 1;
+                if (it < ntrace && tr_res) tr_res[it] = rn;
+            } else {
+                set_breakdown(st, OR_REASON_RHO_ZERO);
+            }
+            break;
+        }
+        const double bnew = (a / omn) * (rho_new / st->rho);
+        const double sig = ry - omn * (rt - a * rv) + bnew * (rs - omn * rz);
+        if (!isfinite(bnew) || !isfinite(sig)) { set_breakdown(st, OR_REASON_NONFINITE); break; }
+        if (sig == 0.0) { set_breakdown(st, OR_REASON_RS_ZERO); break; }
+        st->beta = bnew;
+        st->sigma = sig;
+        st->rho = rho_new;
+        st->alpha = rho_new / sig;
+        if (!isfinite(st->alpha)) { set_breakdown(st, OR_REASON_NONFINITE); break; }
+        oracle_spmv(n, rowptr, col, val, w, t);
+    }
+    free(buf);
+    return st->status;
+}
+
