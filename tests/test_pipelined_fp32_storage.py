@@ -1,0 +1,98 @@
+"""Why the GPU path keeps the classical iteration: with FP32 storage, the pipelined
+BiCGStab's recurrences for the matrix products drift from the matrix they stand for.
+
+Both iterations are emulated here on the CPU with every vector rounded to FP32 after
+each operation and the inner products taken in FP64, as the GPU kernels do.  At the
+same recurrence tolerance the classical iteration's true residual stays near its
+recurrence residual, while the pipelined one's (y = w - alpha z in place of A q,
+w = y - omega (t - alpha v) in place of A r) ends orders of magnitude above it.  The
+FP64 oracle of each iteration reaches the solution (tests/test_oracle_pins_pipelined.py),
+so the difference is the storage precision, not the recurrences themselves."""
+import numpy as np
+import scipy.sparse as sp
+
+import oracle
+import synth
+
+F = np.float32
+
+
+def system(dims, seed):
+    prob = synth.make_problem(*dims, seed=seed)
+    A = oracle.build_csr(*dims, prob.coef)
+    b = oracle.spmv(A, prob.xstar)
+    As, bs = oracle.jacobi(A, b)
+    S = sp.csr_matrix((As.val.astype(F).astype(np.float64), As.col, As.rowptr), shape=(A.n, A.n))
+    return A, b, S, bs
+
+
+def mv(S, v):
+    return (S @ v.astype(np.float64)).astype(F)
+
+
+def dot(a, b):
+    return float(a.astype(np.float64) @ b.astype(np.float64))
+
+
+def classical_fp32(S, bs, tol, max_iter=2000):
+    r = bs.astype(F)
+    rh, p, x = r.copy(), r.copy(), np.zeros_like(r)
+    nb, rho = np.linalg.norm(bs), dot(r, r)
+    for _ in range(max_iter):
+        s = mv(S, p)
+        a = F(rho / dot(rh, s))
+        q = r - a * s
+        if np.sqrt(dot(q, q)) / nb <= tol:
+            return x + a * p
+        y = mv(S, q)
+        om = F(dot(q, y) / dot(y, y))
+        x = x + a * p + om * q
+        r = q - om * y
+        if np.sqrt(dot(r, r)) / nb <= tol:
+            return x
+        rho_new = dot(rh, r)
+        p = r + F((a / om) * (rho_new / rho)) * (p - om * s)
+        rho = rho_new
+    return x
+
+
+def pipelined_fp32(S, bs, tol, max_iter=2000):
+    r = bs.astype(F)
+    rh, x = r.copy(), np.zeros_like(r)
+    w = mv(S, r)
+    t = mv(S, w)
+    p = s = z = v = np.zeros_like(r)
+    nb, rho = np.linalg.norm(bs), dot(r, r)
+    alpha, beta, om = rho / dot(rh, w), 0.0, 0.0
+    for _ in range(max_iter):
+        a, bt, o = F(alpha), F(beta), F(om)
+        p = r + bt * (p - o * s)
+        s = w + bt * (s - o * z)
+        z = t + bt * (z - o * v)
+        q = r - a * s
+        y = w - a * z
+        v = mv(S, z)
+        if np.sqrt(dot(r, r)) / nb <= tol:
+            return x
+        if np.sqrt(dot(q, q)) / nb <= tol:
+            return x + a * p
+        om = dot(q, y) / dot(y, y)
+        x = x + a * p + F(om) * q
+        r = q - F(om) * y
+        w = y - F(om) * (t - a * v)
+        rho_new = dot(rh, q) - om * dot(rh, y)
+        beta = (alpha / om) * (rho_new / rho)
+        sigma = dot(rh, y) - om * (dot(rh, t) - alpha * dot(rh, v)) + beta * (dot(rh, s) - om * dot(rh, z))
+        rho, alpha = rho_new, rho_new / sigma
+        t = mv(S, w)
+    return x
+
+
+def test_pipelined_recurrences_drift_in_fp32_storage():
+    A, b, S, bs = system((9, 7, 5), 11)
+    xc = classical_fp32(S, bs, 1e-6).astype(np.float64)
+    xp = pipelined_fp32(S, bs, 1e-6).astype(np.float64)
+    rc = oracle.true_rel_residual(A, b, xc)
+    rp = oracle.true_rel_residual(A, b, xp)
+    assert rc <= 1e-5, rc
+    assert rp >= 1e-3, rp
