@@ -162,6 +162,55 @@ def batched_leg(s7, torch, dev):
     }
 
 
+def pipelined_leg(s7, torch, dev, steps: int):
+    """The pipelined BiCGStab against the classical solve, FP32, Jacobi: iterations per
+    second on the paper's mesh (`steps` iterations, residual replacements included), and
+    converged solves to 1e-6 on 256^3 and 32^3 (the latter where kernel boundaries and
+    reductions, not bandwidth, set the time)."""
+    out = {}
+    for dims in ((600, 595, 1536), (256, 256, 256), (32, 32, 32)):
+        n = dims[0] * dims[1] * dims[2]
+        c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(7)]
+        xs = torch.empty(n, dtype=torch.float64, device=dev)
+        b = torch.empty(n, dtype=torch.float64, device=dev)
+        s7.generate_problem(dims, 0, 0, c, xs, b)
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        wsp = torch.empty(s7.workspace_bytes_pipelined(dims), dtype=torch.uint8, device=dev)
+        wsc = torch.empty(s7.workspace_bytes(dims), dtype=torch.uint8, device=dev)
+
+        def timed(fn, rtol, iters):
+            x.zero_()
+            fn(rtol, 3)  # warm-up: graphs
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = fn(rtol, iters)
+            torch.cuda.synchronize()
+            return info, time.perf_counter() - t0
+
+        pipe = lambda rtol, it: s7.bicgstab_solve_pipelined(dims, c, b, x, rtol, it, ws=wsp)
+        clas = lambda rtol, it: s7.bicgstab_solve(dims, c, b, x, rtol, it, ws=wsc)
+        key = "x".join(str(v) for v in dims)
+        if n > 100_000_000:
+            ip, tp = timed(pipe, 1e-300, steps)
+            ic, tc = timed(clas, 1e-300, steps)
+            out[key] = {"iterations": steps, "pipelined_iter_per_s": round(ip.iters / tp, 2),
+                        "classical_iter_per_s": round(ic.iters / tc, 2)}
+        else:
+            ip, tp = timed(pipe, 1e-6, 2000)
+            ep = float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))
+            ic, tc = timed(clas, 1e-6, 2000)
+            ec = float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))
+            out[key] = {"rtol": 1e-6,
+                        "pipelined": {"ms": round(tp * 1e3, 3), "iters": ip.iters, "status": ip.status,
+                                      "rel_res_true": ip.rel_res_true, "rel_err_vs_xstar": ep},
+                        "classical": {"ms": round(tc * 1e3, 3), "iters": ic.iters, "status": ic.status,
+                                      "rel_res_true": ic.rel_res_true, "rel_err_vs_xstar": ec}}
+        del c, xs, b, x, wsp, wsc
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_2d9_leg(s7, torch, dev):
     """64 2D 9-point systems, each side uniform over {96,...,512}, seeds 2000+s,
     tolerance 1e-7: one call of the batched solver against a loop of single solves."""
@@ -700,6 +749,7 @@ def main():
     ap.add_argument("--no-simple", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--no-2d9", action="store_true")
+    ap.add_argument("--no-pipelined", action="store_true")
     ap.add_argument("--simple-dims", type=int, nargs=3, default=[100, 400, 100])
     ap.add_argument("--simple-outer", type=int, default=15)
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -862,6 +912,9 @@ def main():
         print("[bench] batched: 64 uneven systems", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(s7, torch, dev)
         torch.cuda.empty_cache()
+    if not args.no_pipelined:
+        print("[bench] pipelined BiCGStab", file=sys.stderr, flush=True)
+        out["pipelined"] = pipelined_leg(s7, torch, dev, args.steps)
     if not args.no_simple:
         print("[bench] SIMPLE pattern", file=sys.stderr, flush=True)
         out["simple_pattern"] = [simple_leg(s7, torch, dev, args.simple_dims, args.simple_outer),

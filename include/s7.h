@@ -135,7 +135,7 @@ typedef struct {
                             (P1 and P2b include the finishing kernel of a split sum) */
     int32_t pass_count[4];
     int32_t schedule;    /* the schedule it ran: 1 three passes, 2 four passes, 3 three
-                            passes on cell pairs.  Batched and queue engine solves run
+                            passes on cell pairs, 4 the pipelined solve.  Batched and queue engine solves run
                             three phases per iteration: 3 if nx is even, else 1; the
                             2D 9-point solves (single, batched, queued) report 1 */
     int32_t reserved;
@@ -222,6 +222,31 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims *d, const float *const
                               const double *const *b, double *const *x, const double *rtol,
                               const int32_t *max_iter, int32_t prec, void *ws, size_t ws_bytes,
                               const s7_options *opt, s7_info *info, void *stream);
+
+/* Workspace for s7_bicgstab_solve_pipelined (0 for invalid dims). */
+size_t s7_workspace_bytes_pipelined(s7_dims d, const s7_options *opt);
+
+/*
+ * Pipelined BiCGStab (Cools and Vanroose, Parallel Computing 65, 2017), in the
+ * form with one reduction per iteration: the iterates of Algorithm 1 in exact
+ * arithmetic, with the matrix products carried by recurrences (s = A p,
+ * z = A s, w = A r, t = A w, v = A z).  The paper uses the classical form;
+ * this variant trades more vector traffic for fewer points where the
+ * iteration waits on a global sum.  FP32 storage, FP64 inner products.  In
+ * FP32 the recurrences drift from A, so every 10 iterations x absorbs the
+ * correction and r = b - A x (FP64), w, t, s, z, v and the scalars are
+ * recomputed from their definitions (residual replacement); the true
+ * residual then floors near 1e-7, and rtol should be 1e-6 or above.  Readings
+ * as s7_bicgstab_solve, except that the stopping test on r_i is taken in
+ * iteration i's reduction (x_i is returned; the half iteration computed before
+ * it is not applied).  Four passes per iteration (two streaming, two
+ * stencil); info->schedule = 4.  Of the options it reads jacobi and
+ * graph_iters.  Arguments, ownership and returns as s7_bicgstab_solve with
+ * prec = S7_FP32.
+ */
+int s7_bicgstab_solve_pipelined(s7_dims d, const float *const coef[7], const double *b, double *x,
+                                double rtol, int32_t max_iter, void *ws, size_t ws_bytes,
+                                const s7_options *opt, s7_info *info, void *stream);
 
 /*
  * Request queue with continuous batching (serving form; section VIII-A names

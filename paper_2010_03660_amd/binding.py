@@ -27,7 +27,8 @@ __all__ = [
     "bicgstab_solve_batched", "queue_table_bytes", "queue_create", "queue_submit", "queue_poll", "queue_wait",
     "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error", "stencil9_apply",
     "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9", "batched_workspace_bytes_2d9",
-    "bicgstab_solve_batched_2d9", "Request2D9", "queue_submit_2d9",
+    "bicgstab_solve_batched_2d9", "Request2D9", "queue_submit_2d9", "workspace_bytes_pipelined",
+    "bicgstab_solve_pipelined",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
     "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
@@ -105,6 +106,9 @@ EXPORTS = {
                                         C.c_int32, C.c_int32, _vp, C.c_size_t, C.POINTER(Options),
                                         C.POINTER(Info), _vp]),
     "s7_generate_problem_2d9": (C.c_int, [C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_vp), _vp, _vp, _vp]),
+    "s7_workspace_bytes_pipelined": (C.c_size_t, [Dims, C.POINTER(Options)]),
+    "s7_bicgstab_solve_pipelined": (C.c_int, [Dims, C.POINTER(_vp), _vp, _vp, C.c_double, C.c_int32, _vp,
+                                              C.c_size_t, C.POINTER(Options), C.POINTER(Info), _vp]),
     "s7_queue_submit_2d9": (C.c_int, [_vp, C.POINTER(Request2D9), C.POINTER(C.c_uint64)]),
     "s7_batched_workspace_bytes_2d9": (C.c_size_t, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                                     C.c_int32, C.POINTER(Options)]),
@@ -366,3 +370,22 @@ def queue_submit_2d9(q: int, nx: int, ny: int, coef, b, x, rtol, max_iter, prec=
     t = C.c_uint64()
     _check(lib().s7_queue_submit_2d9(q, C.byref(req), C.byref(t)), allow=(OK,))
     return t.value
+
+
+def workspace_bytes_pipelined(dims, opt: Options | None = None) -> int:
+    return int(lib().s7_workspace_bytes_pipelined(_dims(dims), C.byref(opt) if opt else None))
+
+
+def bicgstab_solve_pipelined(dims, coef, b, x, rtol, max_iter, ws=None, opt: Options | None = None,
+                             stream=None) -> Info:
+    """Pipelined BiCGStab (one reduction per iteration, residual replacement), FP32, in
+    place in x (x0 on entry)."""
+    info = Info()
+    nbytes = workspace_bytes_pipelined(dims, opt)
+    ws = _workspace(nbytes, ws)
+    wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
+    rc = lib().s7_bicgstab_solve_pipelined(_dims(dims), _coef(coef), _ptr(b), _ptr(x), float(rtol), int(max_iter),
+                                           _ptr(ws), wsb, C.byref(opt) if opt else None, C.byref(info),
+                                           _stream(stream))
+    _check(rc)
+    return info

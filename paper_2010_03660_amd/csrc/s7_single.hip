@@ -1500,3 +1500,5 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
 
 // The 2D 9-point operator (section IV, "SpMV (2D)"), on the same machinery.
 #include "s7_stencil9.hpp"
+// Pipelined BiCGStab (one reduction per iteration), on the 7-point operator.
+#include "s7_pipelined.hpp"

@@ -173,3 +173,21 @@ def test_host_side_argument_checks_batched_2d9():
     assert call(nx, wsb=16) == B.EINVAL and "workspace" in B.last_error()
     assert call(nx, ws=4100) == B.EINVAL  # not 256-byte aligned
     assert call(nx, prec=3) == B.EINVAL
+
+
+def test_host_side_argument_checks_pipelined():
+    from paper_2010_03660_amd import binding as B
+    lib = B.lib()
+    d = B.Dims(40, 30, 20)
+    n = 40 * 30 * 20
+    assert lib.s7_workspace_bytes_pipelined(B.Dims(0, 3, 3), None) == 0
+    # the classical FP32 workspace plus four vectors (z, w, t, v)
+    assert lib.s7_workspace_bytes_pipelined(d, None) >= lib.s7_workspace_bytes(d, B.FP32, None) + 4 * n * 4
+    coef = (C.c_void_p * 7)(*([256] * 7))
+    info = B.Info()
+    rc = lib.s7_bicgstab_solve_pipelined(d, coef, 512, 768, 1e-8, 10, 1024, 16, None, C.byref(info), 0)
+    assert rc == B.EINVAL and "workspace" in B.last_error()
+    rc = lib.s7_bicgstab_solve_pipelined(d, coef, 512, 768, float("nan"), 10, 1024, 1 << 30, None, C.byref(info), 0)
+    assert rc == B.EINVAL
+    rc = lib.s7_bicgstab_solve_pipelined(d, coef, 512, 768, 1e-8, 10, 1032, 1 << 30, None, C.byref(info), 0)
+    assert rc == B.EINVAL  # workspace not 256-byte aligned

@@ -1,0 +1,117 @@
+"""GPU parity of the pipelined BiCGStab solve (one reduction per iteration, residual
+replacement every 10 iterations) against the oracle's pipelined variant, which is
+itself pinned to SciPy's BiCGStab and the classical oracle.
+
+Ragged meshes (one cell, workgroup tails, more than 1024 workgroups so that the sums
+take the split path), both scalings, the first iterates (before any replacement),
+the degenerate cases of Algorithm 1, and 256^3 against the manufactured solution and
+the classical solve.  With FP32 storage and replacement the true residual floors near
+1e-7, so the solves run to a recurrence tolerance of 1e-6 (the FP32 requests of the
+serving workload use the same)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import gpu_available
+from tests.gpu_helpers import coef_dev, dev, host, problem, rel_err
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1, 1), (3, 1, 2), (9, 7, 5), (33, 17, 9), (64, 48, 20), (80, 64, 64)]
+
+
+@pytest.fixture(scope="module")
+def s7():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    import paper_2010_03660_amd as s7
+    s7.lib()
+    return s7
+
+
+def solve(s7, dims, coef, b, x0=None, rtol=1e-6, max_iter=1000, **opt):
+    import torch
+    n = int(np.prod(dims))
+    x = dev(np.zeros(n) if x0 is None else np.asarray(x0, np.float64))
+    info = s7.bicgstab_solve_pipelined(dims, coef, dev(b), x, rtol, max_iter, opt=s7.default_options(**opt))
+    torch.cuda.synchronize()
+    return host(x), info
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("jacobi", [1, 0])
+def test_solution_matches_oracle(s7, dims, jacobi):
+    prob, A, b = problem(dims, seed=11)
+    ref = oracle.bicgstab_pipelined(A, b, tol=1e-12, max_iter=2000, jacobi_scaling=bool(jacobi))
+    assert ref.status == oracle.OK
+    x, info = solve(s7, dims, coef_dev(prob), b, jacobi=jacobi)
+    assert info.status == s7.OK and info.schedule == 4
+    # FP32 at a recurrence tolerance of 1e-6: the true residual is at most a few times 1e-6
+    assert info.rel_res_true <= 3e-6
+    assert rel_err(x, ref.x) <= 1e-4
+    assert abs(info.rel_res_true - oracle.true_rel_residual(A, b, x)) <= 1e-3 * info.rel_res_true + 1e-15
+    # the replacements move the FP32 trajectory further from the FP64 one than rounding alone
+    r6 = oracle.bicgstab_pipelined(A, b, tol=1e-6, max_iter=2000, jacobi_scaling=bool(jacobi))
+    assert abs(info.iters - r6.iters) <= max(5, 0.3 * r6.iters)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5])
+def test_iterates_track_oracle(s7, k):
+    dims = (33, 17, 9)
+    prob, A, b = problem(dims, seed=4)
+    ref = oracle.bicgstab_pipelined(A, b, tol=1e-300, max_iter=k)
+    x, info = solve(s7, dims, coef_dev(prob), b, rtol=1e-300, max_iter=k)
+    assert info.status == s7.NOT_CONVERGED and info.iters == k
+    assert rel_err(x, ref.x) <= 1e-4
+    assert abs(info.rel_res_rec - ref.res_rec) <= 1e-3 * ref.res_rec
+
+
+def test_degenerate_cases(s7):
+    dims = (9, 7, 5)
+    prob, A, b = problem(dims, seed=2)
+    coef = coef_dev(prob)
+    # b = 0: x = 0 exactly, no iteration
+    x, info = solve(s7, dims, coef, np.zeros(A.n), x0=np.ones(A.n))
+    assert info.status == s7.OK and info.iters == 0 and np.all(x == 0)
+    # max_iter = 0: x0 back
+    x, info = solve(s7, dims, coef, b, x0=np.full(A.n, 0.5), max_iter=0)
+    assert info.status == s7.NOT_CONVERGED and info.iters == 0 and np.all(x == 0.5)
+    # diagonal A (Jacobi): the half-step exit of iteration 0, x = b / diag
+    n = 24
+    d = (1.0 + np.arange(n) % 5).astype(np.float32)
+    cd = [d] + [np.zeros(n, np.float32) for _ in range(6)]
+    bd = np.linspace(-1.0, 1.0, n)
+    x, info = solve(s7, (4, 3, 2), [dev(c) for c in cd], bd, rtol=1e-6)
+    assert info.status == s7.OK and info.iters == 1
+    assert rel_err(x, bd / d.astype(np.float64)) <= 1e-6
+    # exact breakdown: A = [[0, 1], [-1, 0]], b = (1, 0), (r0, A r0) = 0
+    cb = [np.zeros(2, np.float32) for _ in range(7)]
+    cb[2][0] = 1.0
+    cb[1][1] = -1.0
+    x, info = solve(s7, (2, 1, 1), [dev(c) for c in cb], np.array([1.0, 0.0]), jacobi=0)
+    assert info.status == s7.BREAKDOWN and info.reason == s7.REASON_RS_ZERO
+    with pytest.raises(s7.S7Error):
+        s7.bicgstab_solve_pipelined((0, 5, 5), coef, dev(b), dev(np.zeros(A.n)), 1e-8, 10)
+
+
+def test_cube256_against_manufactured_and_classical(s7):
+    """256^3 (16.8 M cells) to a recurrence tolerance of 1e-6: the pipelined and the
+    classical solves both reach x*, in about as many iterations."""
+    import torch
+    dims = (256, 256, 256)
+    n = 256 ** 3
+    c = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(7)]
+    xs = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty(n, dtype=torch.float64, device="cuda")
+    s7.generate_problem(dims, 0, 0, c, xs, b)
+    xp = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ip = s7.bicgstab_solve_pipelined(dims, c, b, xp, 1e-6, 1000)
+    xc = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ic = s7.bicgstab_solve(dims, c, b, xc, 1e-6, 1000)
+    torch.cuda.synchronize()
+    assert ip.status == s7.OK and ic.status == s7.OK
+    ep = float(torch.linalg.vector_norm(xp - xs) / torch.linalg.vector_norm(xs))
+    ec = float(torch.linalg.vector_norm(xc - xs) / torch.linalg.vector_norm(xs))
+    assert ep <= 1e-4 and ec <= 1e-4, (ep, ec)
+    assert abs(ip.iters - ic.iters) <= max(5, 0.3 * ic.iters)
+    assert ip.rel_res_true <= 3e-6
