@@ -115,3 +115,24 @@ def test_cube256_against_manufactured_and_classical(s7):
     assert ep <= 1e-4 and ec <= 1e-4, (ep, ec)
     assert abs(ip.iters - ic.iters) <= max(5, 0.3 * ic.iters)
     assert ip.rel_res_true <= 3e-6
+
+
+def test_workspace_reused_for_other_arrays(s7):
+    """The iteration graph holds the addresses of x, b and the coefficients (the
+    replacement step reads them): reusing one workspace for another system of the same
+    shape, and for the same system with new x and b arrays, gives each its own answer."""
+    import torch
+    dims = (40, 24, 20)
+    ws = torch.empty(s7.workspace_bytes_pipelined(dims), dtype=torch.uint8, device="cuda")
+    results = []
+    for seed in (21, 22, 21):
+        prob, A, b = problem(dims, seed=seed)
+        x = dev(np.zeros(A.n))
+        info = s7.bicgstab_solve_pipelined(dims, coef_dev(prob), dev(b), x, 1e-6, 1000, ws=ws)
+        torch.cuda.synchronize()
+        assert info.status == s7.OK
+        ref = oracle.bicgstab_pipelined(A, b, tol=1e-12, max_iter=2000)
+        assert rel_err(host(x), ref.x) <= 1e-4, seed
+        results.append((host(x), info.iters))
+    # the same system through fresh arrays: the same bits
+    assert np.array_equal(results[0][0], results[2][0]) and results[0][1] == results[2][1]
