@@ -104,7 +104,11 @@ typedef struct {
                                formed on the fly where it is used, never stored), 2 four
                                passes (q stored by a streaming pass), 3 three passes whose
                                stencil passes give each thread two x-adjacent cells (meshes with
-                               an even nx; 1 otherwise); 0 = 3 */
+                               an even nx; 1 otherwise), 5 three passes whose stencil passes
+                               stage the operand of a 4096-cell tile and one mesh row on
+                               either side in LDS (meshes with an even nx of at most 4096;
+                               3 otherwise); 0 = 5 on meshes of at least 2^22 cells where
+                               it applies, else 3 */
     int32_t tune;           /* 1: the fields left at 0 among schedule and stream_blocks
                                (single solve) and chunk_cells (batched) take autotuned values
                                for the problem's size class.  An untuned class is timed first
@@ -119,6 +123,13 @@ typedef struct {
                                second stream, one at a time; in the batched solve after the
                                shared launch.  0 = 2^21, -1 = never */
     double inner_rtol;      /* IR: inner relative tolerance; 0 = 1e-2 (BF16), 5e-3 (FP16) */
+    int32_t xcd_run;        /* single-system paired and single-cell stencil passes: consecutive
+                               workgroup tiles that one XCD sweeps in a row (workgroups are
+                               dealt to the eight XCDs in turn, each with its own L2); k > 1:
+                               runs of k tiles, -1: an eighth of a mesh plane's tiles (each XCD
+                               sweeps one band of every plane), 0 or 1: plain order (default;
+                               the runs measured no faster).  Results do not depend on it. */
+    int32_t reserved_opt;   /* 0 */
 } s7_options;
 
 typedef struct {
@@ -135,7 +146,8 @@ typedef struct {
                             (P1 and P2b include the finishing kernel of a split sum) */
     int32_t pass_count[4];
     int32_t schedule;    /* the schedule it ran: 1 three passes, 2 four passes, 3 three
-                            passes on cell pairs, 4 the pipelined solve.  Batched and queue engine solves run
+                            passes on cell pairs, 4 the pipelined solve, 5 three passes
+                            with LDS-staged stencil operands.  Batched and queue engine solves run
                             three phases per iteration: 3 if nx is even, else 1; the
                             2D 9-point solves (single, batched, queued) report 1 */
     int32_t reserved;

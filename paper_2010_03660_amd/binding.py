@@ -43,7 +43,8 @@ class Options(C.Structure):
     _fields_ = [("jacobi", C.c_int32), ("graph_iters", C.c_int32), ("stream_blocks", C.c_int32),
                 ("chunk_cells", C.c_int32), ("profile", C.c_int32), ("inner_max_iter", C.c_int32),
                 ("outer_max_iter", C.c_int32), ("schedule", C.c_int32), ("tune", C.c_int32),
-                ("split_cells", C.c_int32), ("inner_rtol", C.c_double)]
+                ("split_cells", C.c_int32), ("inner_rtol", C.c_double), ("xcd_run", C.c_int32),
+                ("reserved_opt", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -261,6 +261,27 @@ __device__ __forceinline__ Cell cell_at(int g, const Mesh& m, int n) {
     return c;
 }
 
+// XCD-aware tile order of a cell-parallel stencil pass.  The chip deals the
+// workgroups of a launch to its eight XCDs in turn (workgroup b to XCD b mod
+// 8), and each XCD has its own L2.  In plain order the y and z neighbours of
+// a workgroup's cells belong to tiles that run on other XCDs, so each XCD
+// fetches them into its own L2 again.  Here workgroup b takes tile
+// xcd_tile(b) instead: the tiles form rounds of 8 * run, and in each round XCD
+// x sweeps the run of tiles [x run, (x + 1) run) in order.  With run about an
+// eighth of a plane's tiles, every XCD works through one band of each plane
+// after the other, so the rows above and below a tile and the plane below it
+// were mostly fetched into the same L2 shortly before.  Tiles of an incomplete
+// last round keep their own index.  run <= 1 is plain order.  The partial sums
+// are stored by tile, so every sum has the same order as in plain order.
+__device__ __forceinline__ int xcd_tile(int b, int nb, int run) {
+    if (run <= 1) return b;
+    const int span = 8 * run;
+    const int w = b % span;
+    const int base = b - w;
+    if (base + span > nb) return b;
+    return base + (w & 7) * run + (w >> 3);
+}
+
 // The seven operand values of a cell: centre, west, east, south, north,
 // below, above.
 template <class V>
@@ -803,6 +824,99 @@ __device__ __forceinline__ void pair_p2f(const SysView<T>& S, const Cell& c, flo
     acc[2] = fma(qb, qb, qa * qa);
     acc[3] = fma((double)rh.b, qb, (double)rh.a * qa);
     acc[4] = fma((double)rh.b, yb, (double)rh.a * ya);
+}
+
+// ---------------------------------------------------------------- staged stencil passes
+// The stencil passes in a second form (meshes with an even nx of at most
+// kLdsMaxNx).  A workgroup takes a tile of kLdsTile consecutive cells of the
+// flat order, [c0, c0 + kLdsTile).  It first stages the stencil operand over
+// [c0 - nx, c0 + kLdsTile + nx), widened to multiples of 8 cells, into LDS as
+// FP32, with zeros outside the mesh: the tile and one row on either side, so
+// every x and y neighbour of a tile cell is in LDS.  P2 stages q = r - alpha s,
+// formed once per cell as it is staged, instead of loading both r and s at
+// every neighbour.  The staging loads are 16-byte accesses in flat order.
+// Each thread then takes the pairs (2 consecutive cells) u * kThreads + tid of
+// the tile: centre, west, east, south and north from LDS, below and above from
+// memory.  A neighbour across a mesh face is another cell of the mesh (or a
+// staged zero) whose coefficient is zero in the working copies, so the
+// per-cell sum is exactly that of the flat kernels.  Measured at 600x595x1536,
+// the flat P2 re-read its two operands' neighbours through the caches at about
+// 1.1 ms per pass over a halo-free stream of the same arrays; staging removes
+// most of that.
+constexpr int kLdsTile = 4096;
+constexpr int kLdsMaxNx = 4096;
+
+__host__ __device__ inline int lds_lo(int c0, int nx) { return (c0 - nx) >> 3 << 3; }
+__host__ __device__ inline int lds_count(int nx) { return kLdsTile + 2 * nx + 16; }
+inline int lds_blocks(long long n) { return (int)((n + kLdsTile - 1) / kLdsTile); }
+
+// Stages v (Q: r - alpha s with v = r, w = s) over [lo, lo + cnt) into sm.
+template <class T, bool Q>
+__device__ __forceinline__ void stage_rows(const T* v, const T* w, float alpha, int lo, int cnt, int n,
+                                           float* sm) {
+    constexpr int W = kVec<T>;
+    for (int e = (int)threadIdx.x; e < cnt / W; e += kThreads) {
+        const int g = lo + W * e;
+        float a[W], b[W];
+        if (g >= 0 && g + W <= n) {
+            if constexpr (sizeof(T) == 4) {
+                const f32x4 x = *reinterpret_cast<const f32x4*>(v + g);
+                a[0] = x.x, a[1] = x.y, a[2] = x.z, a[3] = x.w;
+                if (Q) {
+                    const f32x4 y = *reinterpret_cast<const f32x4*>(w + g);
+                    b[0] = y.x, b[1] = y.y, b[2] = y.z, b[3] = y.w;
+                }
+            } else {
+                const u16x8 x = *reinterpret_cast<const u16x8*>(v + g);
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    T t;
+                    const uint16_t u = x[j];
+                    __builtin_memcpy(&t, &u, 2);
+                    a[j] = to_f32(t);
+                }
+                if (Q) {
+                    const u16x8 y = *reinterpret_cast<const u16x8*>(w + g);
+#pragma unroll
+                    for (int j = 0; j < W; ++j) {
+                        T t;
+                        const uint16_t u = y[j];
+                        __builtin_memcpy(&t, &u, 2);
+                        b[j] = to_f32(t);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const bool in = g + j >= 0 && g + j < n;
+                a[j] = in ? to_f32(v[g + j]) : 0.0f;
+                b[j] = (Q && in) ? to_f32(w[g + j]) : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) sm[W * e + j] = Q ? fmaT(-alpha, b[j], a[j]) : a[j];
+    }
+}
+
+// The seven operand values of the pair at LDS position L (first cell), with
+// the pair's vertical neighbours vb, vt (FP32) from memory.
+__device__ __forceinline__ void lds_nbr2(const float* sm, int L, int nx, F2 vb, F2 vt, Nbr<float>& v0,
+                                         Nbr<float>& v1) {
+    const f32x2 c = *reinterpret_cast<const f32x2*>(sm + L);
+    const f32x2 s = *reinterpret_cast<const f32x2*>(sm + L - nx);
+    const f32x2 nn = *reinterpret_cast<const f32x2*>(sm + L + nx);
+    const float w = sm[L - 1], e = sm[L + 2];
+    v0 = Nbr<float>{c.x, w, c.y, s.x, nn.x, vb.a, vt.a};
+    v1 = Nbr<float>{c.y, c.x, e, s.y, nn.y, vb.b, vt.b};
+}
+
+// Offsets of the cells below and above cell idx (0 across the z faces).
+__device__ __forceinline__ void z_offsets(int idx, const Mesh& m, int& db, int& dt) {
+    const int plane = m.nx * m.ny;
+    const int k = div_rcp(idx, plane, m.rplane);
+    db = k > 0 ? -plane : 0;
+    dt = k < m.nz - 1 ? plane : 0;
 }
 
 // P3, workgroup b of the streaming grid: d += alpha p + omega q;

@@ -303,12 +303,13 @@ __global__ __launch_bounds__(kThreads) void k_finish(Red red, int nblocks, State
 }
 
 template <class T, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_p1(SysView<T> S) {
+__global__ __launch_bounds__(kThreads) void k_p1(SysView<T> S, int run) {
     if (S.st->done) return;
+    const int t = xcd_tile(blockIdx.x, S.cell_blocks, run);
     double acc[1];
-    cell_p1<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, acc);
+    cell_p1<T, UNIT>(S, t * kThreads + threadIdx.x, acc);
     double tot[1];
-    if (grid_reduce<1>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+    if (grid_reduce<1>(acc, S.red, S.cell_blocks, t, tot) && threadIdx.x == 0)
         tail_p1(S.st, tot);
 }
 
@@ -323,43 +324,122 @@ __global__ __launch_bounds__(kThreads) void k_p2a(SysView<T> S) {
 }
 
 template <class T, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_p2(SysView<T> S) {
+__global__ __launch_bounds__(kThreads) void k_p2(SysView<T> S, int run) {
     if (S.st->done) return;
+    const int t = xcd_tile(blockIdx.x, S.cell_blocks, run);
     double acc[4];
-    cell_p2b<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, acc);
+    cell_p2b<T, UNIT>(S, t * kThreads + threadIdx.x, acc);
     double tot[4];
-    if (grid_reduce<4>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+    if (grid_reduce<4>(acc, S.red, S.cell_blocks, t, tot) && threadIdx.x == 0)
         tail_p2(S.st, tot);
 }
 
 template <class T, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_p1_pair(SysView<T> S) {
+__global__ __launch_bounds__(kThreads) void k_p1_pair(SysView<T> S, int run) {
     if (S.st->done) return;
+    const int t = xcd_tile(blockIdx.x, S.pair_blocks, run);
     double acc[1];
-    pair_p1<T, UNIT>(S, cell2_at(blockIdx.x * kThreads + threadIdx.x, S.m, S.n), acc);
+    pair_p1<T, UNIT>(S, cell2_at(t * kThreads + threadIdx.x, S.m, S.n), acc);
     double tot[1];
-    if (grid_reduce<1>(acc, S.red, S.pair_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+    if (grid_reduce<1>(acc, S.red, S.pair_blocks, t, tot) && threadIdx.x == 0)
         tail_p1(S.st, tot);
 }
 
 template <class T, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_p2f_pair(SysView<T> S) {
+__global__ __launch_bounds__(kThreads) void k_p2f_pair(SysView<T> S, int run) {
     if (S.st->done) return;
+    const int t = xcd_tile(blockIdx.x, S.pair_blocks, run);
     double acc[5];
-    pair_p2f<T, UNIT>(S, cell2_at(blockIdx.x * kThreads + threadIdx.x, S.m, S.n), (float)S.st->alpha, acc);
+    pair_p2f<T, UNIT>(S, cell2_at(t * kThreads + threadIdx.x, S.m, S.n), (float)S.st->alpha, acc);
     double tot[5];
-    if (grid_reduce<5>(acc, S.red, S.pair_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+    if (grid_reduce<5>(acc, S.red, S.pair_blocks, t, tot) && threadIdx.x == 0)
         tail_p2f(S.st, tot);
 }
 
 template <class T, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_p2f(SysView<T> S) {
+__global__ __launch_bounds__(kThreads) void k_p2f(SysView<T> S, int run) {
     if (S.st->done) return;
+    const int t = xcd_tile(blockIdx.x, S.cell_blocks, run);
     double acc[5];
-    cell_p2f<T, UNIT>(S, blockIdx.x * kThreads + threadIdx.x, (float)S.st->alpha, acc);
+    cell_p2f<T, UNIT>(S, t * kThreads + threadIdx.x, (float)S.st->alpha, acc);
     double tot[5];
-    if (grid_reduce<5>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0)
+    if (grid_reduce<5>(acc, S.red, S.cell_blocks, t, tot) && threadIdx.x == 0)
         tail_p2f(S.st, tot);
+}
+
+// The staged stencil passes (kLdsTile cells per workgroup; the dynamic LDS holds
+// lds_count(nx) floats).  Each thread sums its pairs' products first, in pair
+// order, then the workgroup and the grid sums follow as in the flat passes.
+template <class T, bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_p1_lds(SysView<T> S, int nblocks) {
+    extern __shared__ float stage[];
+    if (S.st->done) return;
+    const int nx = S.m.nx, c0 = blockIdx.x * kLdsTile, lo = lds_lo(c0, nx);
+    const int hi = (c0 + kLdsTile + nx + 7) >> 3 << 3;
+    stage_rows<T, false>(S.p, nullptr, 0.0f, lo, hi - lo, S.n, stage);
+    __syncthreads();
+    double acc[1] = {0.0};
+    const Cell none{};
+#pragma unroll 2
+    for (int u = 0; u < kLdsTile / (2 * kThreads); ++u) {
+        const int idx = c0 + 2 * (u * kThreads + (int)threadIdx.x);
+        if (idx >= S.n) break;
+        int db, dt;
+        z_offsets(idx, S.m, db, dt);
+        const F2 pb = ld2(S.p + idx + db), pt = ld2(S.p + idx + dt);
+        Nbr<float> p0, p1;
+        lds_nbr2(stage, idx - lo, nx, pb, pt, p0, p1);
+        Coefs<float, UNIT> k0, k1;
+        load_coefs2_nt<T, UNIT>(S.c, idx, k0, k1);
+        const F2 rh = ld2_nt(S.rhat + idx);
+        const T s0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, p0, none));
+        const T s1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, p1, none));
+        st2_nt(S.s + idx, s0, s1);
+        acc[0] += fma((double)rh.b, (double)to_f32(s1), (double)rh.a * (double)to_f32(s0));
+    }
+    double tot[1];
+    if (grid_reduce<1>(acc, S.red, nblocks, blockIdx.x, tot) && threadIdx.x == 0) tail_p1(S.st, tot);
+}
+
+template <class T, bool UNIT>
+__global__ __launch_bounds__(kThreads) void k_p2f_lds(SysView<T> S, int nblocks) {
+    extern __shared__ float stage[];
+    if (S.st->done) return;
+    const float alpha = (float)S.st->alpha;
+    const int nx = S.m.nx, c0 = blockIdx.x * kLdsTile, lo = lds_lo(c0, nx);
+    const int hi = (c0 + kLdsTile + nx + 7) >> 3 << 3;
+    stage_rows<T, true>(S.r, S.s, alpha, lo, hi - lo, S.n, stage);
+    __syncthreads();
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const Cell none{};
+#pragma unroll 2
+    for (int u = 0; u < kLdsTile / (2 * kThreads); ++u) {
+        const int idx = c0 + 2 * (u * kThreads + (int)threadIdx.x);
+        if (idx >= S.n) break;
+        int db, dt;
+        z_offsets(idx, S.m, db, dt);
+        const F2 rb = ld2(S.r + idx + db), sb = ld2(S.s + idx + db);
+        const F2 rt = ld2(S.r + idx + dt), st = ld2(S.s + idx + dt);
+        const F2 qb{fmaT(-alpha, sb.a, rb.a), fmaT(-alpha, sb.b, rb.b)};
+        const F2 qt{fmaT(-alpha, st.a, rt.a), fmaT(-alpha, st.b, rt.b)};
+        Nbr<float> q0, q1;
+        lds_nbr2(stage, idx - lo, nx, qb, qt, q0, q1);
+        Coefs<float, UNIT> k0, k1;
+        load_coefs2_nt<T, UNIT>(S.c, idx, k0, k1);
+        const F2 rh = ld2_nt(S.rhat + idx);
+        const T y0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, q0, none));
+        const T y1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, q1, none));
+        st2_nt(S.y + idx, y0, y1);
+        const double ya = (double)to_f32(y0), yb = (double)to_f32(y1);
+        const double qa = (double)q0.c, qb2 = (double)q1.c;
+        acc[0] += fma(qb2, yb, qa * ya);
+        acc[1] += fma(yb, yb, ya * ya);
+        acc[2] += fma(qb2, qb2, qa * qa);
+        acc[3] += fma((double)rh.b, qb2, (double)rh.a * qa);
+        acc[4] += fma((double)rh.b, yb, (double)rh.a * ya);
+    }
+    double tot[5];
+    if (grid_reduce<5>(acc, S.red, nblocks, blockIdx.x, tot) && threadIdx.x == 0) tail_p2f(S.st, tot);
 }
 
 template <class T, bool QR>
@@ -541,31 +621,67 @@ static void launch_finish(const Red& red, int nblocks, State* st, hipStream_t s,
 // finishing kernel of a split sum where one is needed).  The three-pass
 // schedule has no P2a: its pass 2 forms q on the fly, and its P3 forms q again.
 constexpr int kPasses = 4;
-enum Schedule { SCHED_AUTO = 0, SCHED_THREE = 1, SCHED_FOUR = 2, SCHED_PAIRS = 3 };
+enum Schedule { SCHED_AUTO = 0, SCHED_THREE = 1, SCHED_FOUR = 2, SCHED_PAIRS = 3, SCHED_LDS = 5 };
+
+// Tiles per XCD run of a stencil pass (xcd_tile): the option if above 1, an
+// eighth of a plane's tiles for -1, else plain order.  Measured at
+// 600x595x1536 and 256^3, runs of 44, 87 (an eighth of a plane) and 174 tiles
+// left the paired passes' times within 2 % of plain order, so plain order is
+// the default.
+static int tile_run(int xcd_run, const Mesh& m, int tile_cells) {
+    if (xcd_run > 1) return xcd_run;
+    if (xcd_run != -1) return 1;
+    const long long r = (long long)m.nx * m.ny / (8LL * tile_cells);
+    return r < 1 ? 1 : (r > (1 << 20) ? (1 << 20) : (int)r);
+}
+
+// The staged stencil passes apply to meshes with an even nx of at most kLdsMaxNx.
+template <class T>
+static bool lds_ok(const SysView<T>& S) {
+    return S.pair_blocks > 0 && S.m.nx <= kLdsMaxNx;
+}
 
 template <class T>
-static void launch_pass(const SysView<T>& S, int pass, int sched, hipStream_t s) {
-    if (sched == SCHED_PAIRS && S.pair_blocks > 0 && pass != 3) {
-        if (pass == 1) return;
-        const int nb = S.pair_blocks;
+static void launch_pass(const SysView<T>& S, int pass, int sched, int xr, hipStream_t s) {
+    // With 16-bit storage the staged P1 measured slower than the paired one (its
+    // single operand is read in 4-byte pairs either way), so it keeps the pairs.
+    if (sched == SCHED_LDS && lds_ok(S) && (pass == 2 || (pass == 0 && sizeof(T) == 4))) {
+        const int nb = lds_blocks(S.n);
+        const size_t lds = (size_t)lds_count(S.m.nx) * sizeof(float);
         if (pass == 0) {
-            if (S.unit) hipLaunchKernelGGL((k_p1_pair<T, true>), dim3(nb), dim3(kThreads), 0, s, S);
-            else hipLaunchKernelGGL((k_p1_pair<T, false>), dim3(nb), dim3(kThreads), 0, s, S);
+            if (S.unit) hipLaunchKernelGGL((k_p1_lds<T, true>), dim3(nb), dim3(kThreads), lds, s, S, nb);
+            else hipLaunchKernelGGL((k_p1_lds<T, false>), dim3(nb), dim3(kThreads), lds, s, S, nb);
             launch_finish<1, 0u, FIN_P1>(S.red, nb, S.st, s);
         } else {
-            if (S.unit) hipLaunchKernelGGL((k_p2f_pair<T, true>), dim3(nb), dim3(kThreads), 0, s, S);
-            else hipLaunchKernelGGL((k_p2f_pair<T, false>), dim3(nb), dim3(kThreads), 0, s, S);
+            if (S.unit) hipLaunchKernelGGL((k_p2f_lds<T, true>), dim3(nb), dim3(kThreads), lds, s, S, nb);
+            else hipLaunchKernelGGL((k_p2f_lds<T, false>), dim3(nb), dim3(kThreads), lds, s, S, nb);
             launch_finish<5, 0u, FIN_P2F>(S.red, nb, S.st, s);
         }
         return;
     }
-    if (sched == SCHED_THREE || sched == SCHED_PAIRS) {
+    if ((sched == SCHED_PAIRS || sched == SCHED_LDS) && S.pair_blocks > 0 && pass != 3) {
+        if (pass == 1) return;
+        const int nb = S.pair_blocks;
+        const int run = tile_run(xr, S.m, 2 * kThreads);
+        if (pass == 0) {
+            if (S.unit) hipLaunchKernelGGL((k_p1_pair<T, true>), dim3(nb), dim3(kThreads), 0, s, S, run);
+            else hipLaunchKernelGGL((k_p1_pair<T, false>), dim3(nb), dim3(kThreads), 0, s, S, run);
+            launch_finish<1, 0u, FIN_P1>(S.red, nb, S.st, s);
+        } else {
+            if (S.unit) hipLaunchKernelGGL((k_p2f_pair<T, true>), dim3(nb), dim3(kThreads), 0, s, S, run);
+            else hipLaunchKernelGGL((k_p2f_pair<T, false>), dim3(nb), dim3(kThreads), 0, s, S, run);
+            launch_finish<5, 0u, FIN_P2F>(S.red, nb, S.st, s);
+        }
+        return;
+    }
+    const int run = tile_run(xr, S.m, kThreads);
+    if (sched == SCHED_THREE || sched == SCHED_PAIRS || sched == SCHED_LDS) {
         if (pass == 1) return;
         if (pass == 2) {
             if (S.unit)
-                hipLaunchKernelGGL((k_p2f<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+                hipLaunchKernelGGL((k_p2f<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S, run);
             else
-                hipLaunchKernelGGL((k_p2f<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+                hipLaunchKernelGGL((k_p2f<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S, run);
             launch_finish<5, 0u, FIN_P2F>(S.red, S.cell_blocks, S.st, s);
             return;
         }
@@ -576,34 +692,36 @@ static void launch_pass(const SysView<T>& S, int pass, int sched, hipStream_t s)
     }
     if (pass == 0) {
         if (S.unit)
-            hipLaunchKernelGGL((k_p1<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+            hipLaunchKernelGGL((k_p1<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S, run);
         else
-            hipLaunchKernelGGL((k_p1<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+            hipLaunchKernelGGL((k_p1<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S, run);
         launch_finish<1, 0u, FIN_P1>(S.red, S.cell_blocks, S.st, s);
     } else if (pass == 1) {
         hipLaunchKernelGGL((k_p2a<T>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S);
     } else if (pass == 2) {
         if (S.unit)
-            hipLaunchKernelGGL((k_p2<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+            hipLaunchKernelGGL((k_p2<T, true>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S, run);
         else
-            hipLaunchKernelGGL((k_p2<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S);
+            hipLaunchKernelGGL((k_p2<T, false>), dim3(S.cell_blocks), dim3(kThreads), 0, s, S, run);
         launch_finish<4, 0u, FIN_P2>(S.red, S.cell_blocks, S.st, s);
     } else {
         hipLaunchKernelGGL((k_p3<T, false>), dim3(S.stream_blocks), dim3(kThreads), 0, s, S);
     }
 }
 
-// The schedule of an iteration: the option if set, else three passes on cell
-// pairs (which fall back to single cells when nx is odd).
-static int schedule_of(const s7_options& o) {
-    if (o.schedule == SCHED_THREE || o.schedule == SCHED_FOUR) return o.schedule;
-    return SCHED_PAIRS;
-}
+// The schedule of an iteration: the option if set (one that does not apply to
+// the mesh falls back to cell pairs, and cell pairs to single cells when nx is
+// odd); by default the staged passes on meshes of at least kLdsMinCells cells
+// where they apply, else cell pairs.  Below that size the staged passes'
+// kLdsTile-cell workgroups are too few to fill the chip.
+constexpr long long kLdsMinCells = 4LL << 20;
 
 template <class T>
 static int effective_schedule(const s7_options& o, const SysView<T>& S) {
-    const int sc = schedule_of(o);
-    return sc == SCHED_PAIRS && S.pair_blocks == 0 ? SCHED_THREE : sc;
+    if (o.schedule == SCHED_THREE || o.schedule == SCHED_FOUR) return o.schedule;
+    if (o.schedule == SCHED_LDS && lds_ok(S)) return SCHED_LDS;
+    if (o.schedule == SCHED_AUTO && lds_ok(S) && (long long)S.n >= kLdsMinCells) return SCHED_LDS;
+    return S.pair_blocks > 0 ? SCHED_PAIRS : SCHED_THREE;
 }
 
 static int read_state(const State* dst, State* host, hipStream_t s) {
@@ -621,7 +739,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
     if (host->done) return S7_OK;
     const int K = o.graph_iters > 0 ? o.graph_iters : auto_graph_iters((size_t)S.n, (int)sizeof(T));
     const long long max_launches = (long long)host->max_iter / K + 3;
-    const int sched = schedule_of(o);
+    const int sched = effective_schedule(o, S);
     if (o.profile) {
         constexpr int NP = kPasses;
         std::vector<hipEvent_t> ev((size_t)(NP + 1) * K);
@@ -631,7 +749,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
             for (int j = 0; j < K; ++j) {
                 for (int p = 0; p < NP; ++p) {
                     S7_HIP(hipEventRecord(ev[(NP + 1) * j + p], stream));
-                    launch_pass<T>(S, p, sched, stream);
+                    launch_pass<T>(S, p, sched, o.xcd_run, stream);
                 }
                 S7_HIP(hipEventRecord(ev[(NP + 1) * j + NP], stream));
             }
@@ -658,11 +776,12 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
                                       (uintptr_t)S.m.nx, (uintptr_t)S.m.ny, (uintptr_t)S.m.nz,
                                       (uintptr_t)S.unit, (uintptr_t)S.st, (uintptr_t)S.red.part,
                                       (uintptr_t)S.r, (uintptr_t)S.c[1], (uintptr_t)S.d,
-                                      (uintptr_t)S.stream_blocks, (uintptr_t)sched};
+                                      (uintptr_t)S.stream_blocks, (uintptr_t)sched,
+                                      (uintptr_t)o.xcd_run};
         GraphRef g;
         rc = cached_graph(key, [&](hipStream_t cs) {
             for (int j = 0; j < K; ++j)
-                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, cs);
+                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, o.xcd_run, cs);
         }, &g);
         if (rc) return rc;
         for (long long l = 0; l < max_launches; ++l) {
@@ -755,7 +874,8 @@ static int tune_prepare(const SysView<T>& S, hipStream_t s) {
 // Picks the schedule and the streaming split of the single-system solve for the
 // size class of d: each candidate runs one warm-up and K timed iterations.
 template <class T>
-static int tune_single(s7_dims d, const Layout& Lo, int jacobi, char* ws, hipStream_t s, int (&best)[2]) {
+static int tune_single(s7_dims d, const Layout& Lo, int jacobi, int xr, char* ws, hipStream_t s,
+                       int (&best)[2]) {
     const TuneKey key{TUNE_SINGLE, TypeTag<T>::value, jacobi, size_bucket((double)Lo.n), 0};
     if (tune_lookup(key, best)) return S7_OK;
     SysView<T> S = make_view<T>(d, Lo, jacobi, ws);
@@ -765,11 +885,13 @@ static int tune_single(s7_dims d, const Layout& Lo, int jacobi, char* ws, hipStr
     S7_HIP(hipEventCreate(&e1));
     float best_ms = INFINITY;
     best[0] = S.pair_blocks > 0 ? SCHED_PAIRS : SCHED_THREE;
+    if (lds_ok(S) && (long long)S.n >= kLdsMinCells) best[0] = SCHED_LDS;
     best[1] = stream_blocks_for((long long)Lo.n, 0);
     int rc = S7_OK;
     std::vector<int> tried;
-    for (int sched : {SCHED_PAIRS, SCHED_THREE, SCHED_FOUR}) {
+    for (int sched : {SCHED_LDS, SCHED_PAIRS, SCHED_THREE, SCHED_FOUR}) {
         if (sched == SCHED_PAIRS && S.pair_blocks == 0) continue;  // odd nx: same as SCHED_THREE
+        if (sched == SCHED_LDS && !lds_ok(S)) continue;
         for (int cap : {256, 512, 1024}) {
             const int sb = stream_blocks_for((long long)Lo.n, cap);
             const int id = sched * 4096 + sb;
@@ -777,10 +899,10 @@ static int tune_single(s7_dims d, const Layout& Lo, int jacobi, char* ws, hipStr
             tried.push_back(id);
             S.stream_blocks = sb;
             if ((rc = tune_prepare<T>(S, s))) break;
-            for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, s);
+            for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, xr, s);
             if (hipEventRecord(e0, s) != hipSuccess) { rc = S7_EHIP; break; }
             for (int j = 0; j < K; ++j)
-                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, s);
+                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, xr, s);
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 rc = S7_EHIP;
                 break;
@@ -1387,9 +1509,9 @@ int s7_bicgstab_solve(s7_dims d, const float* const coef[7], const double* b, do
     char* w = (char*)ws;
     if (o.tune && (o.schedule == 0 || o.stream_blocks == 0)) {
         int best[2];
-        const int rc = prec == S7_FP32      ? tune_single<float>(d, Lo, o.jacobi, w, s, best)
-                       : prec == S7_BF16_IR ? tune_single<bf16>(d, Lo, o.jacobi, w, s, best)
-                                            : tune_single<f16>(d, Lo, o.jacobi, w, s, best);
+        const int rc = prec == S7_FP32      ? tune_single<float>(d, Lo, o.jacobi, o.xcd_run, w, s, best)
+                       : prec == S7_BF16_IR ? tune_single<bf16>(d, Lo, o.jacobi, o.xcd_run, w, s, best)
+                                            : tune_single<f16>(d, Lo, o.jacobi, o.xcd_run, w, s, best);
         if (rc) return rc;
         if (o.schedule == 0) o.schedule = best[0];
         if (o.stream_blocks == 0) o.stream_blocks = best[1];

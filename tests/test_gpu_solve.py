@@ -293,18 +293,19 @@ def test_schedules_agree(s7, prec):
     bd = dev(b)
     rtol = 1e-8 if prec == 0 else 1e-10
     ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=1000)
-    out = [gpu_solve(s7, dims, coef, bd, rtol=rtol, max_iter=2000, prec=prec, schedule=sc) for sc in (1, 2, 3)]
+    out = [gpu_solve(s7, dims, coef, bd, rtol=rtol, max_iter=2000, prec=prec, schedule=sc) for sc in (1, 2, 3, 5)]
     for x, info in out:
         assert info.status == s7.OK and rel_err(x, ref.x) <= (1e-6 if prec == 0 else 1e-7)
     if prec == 0:
         assert out[0][1].iters == out[1][1].iters
         assert rel_err(out[0][0], out[1][0]) <= 1e-12
         # pairs: the same stencil sums, dot products rounded in another order
-        assert abs(out[2][1].iters - out[0][1].iters) <= 2
-        assert rel_err(out[2][0], out[0][0]) <= 1e-6
+        for j in (2, 3):  # pairs, staged: the same stencil sums, dots in another order
+            assert abs(out[j][1].iters - out[0][1].iters) <= 2
+            assert rel_err(out[j][0], out[0][0]) <= 1e-6
     for k in (1, 2, 5):
         rk = oracle.bicgstab(A, b, tol=1e-300, max_iter=k)
-        for sc in (1, 2, 3):
+        for sc in (1, 2, 3, 5):
             xk, ik = gpu_solve(s7, dims, coef, bd, rtol=1e-300, max_iter=k, schedule=sc)
             assert rel_err(xk, rk.x) <= 1e-4 and abs(ik.rel_res_rec - rk.res_rec) <= 1e-4 * rk.res_rec
 
@@ -386,3 +387,67 @@ def test_x_only_8_byte_aligned(s7, prec):
     assert float(buf[0]) == 0.0  # nothing written before x
     ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
     assert rel_err(host(xm), ref.x) <= (1e-6 if prec == "fp32" else 1e-7)
+
+
+@pytest.mark.parametrize("dims", [(2, 1, 1), (4, 3, 2), (34, 17, 9), (70, 40, 20), (4096, 3, 4),
+                                  (128, 96, 96)])
+@pytest.mark.parametrize("prec,jacobi", [(0, 1), (0, 0), (2, 1)])
+def test_staged_schedule_matches_oracle(s7, dims, prec, jacobi):
+    """Schedule 5 (the stencil operand of a 4096-cell tile and one row on either side
+    staged in LDS; below and above from memory) on meshes smaller than one tile, ragged
+    tiles, the widest allowed rows (nx = 4096: the y neighbours lie a whole tile away)
+    and several hundred tiles; FP32 in both scalings and FP16 with refinement."""
+    prob, A, b = problem(dims, seed=67)
+    ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000, jacobi_scaling=bool(jacobi))
+    rtol = 1e-8 if prec == 0 else 1e-10
+    coef, bd = coef_dev(prob), dev(b)
+    x, info = gpu_solve(s7, dims, coef, bd, rtol=rtol, max_iter=2000, prec=prec, schedule=5,
+                        jacobi=jacobi)
+    assert info.status == s7.OK, info.as_dict()
+    assert info.schedule == 5
+    assert rel_err(x, ref.x) <= (1e-6 if prec == 0 else 1e-7)
+    if prec == 0:
+        r8 = oracle.bicgstab(A, b, tol=1e-8, max_iter=2000, jacobi_scaling=bool(jacobi))
+        assert abs(info.iters - r8.iters) <= max(3, 0.2 * r8.iters)
+        for k in (1, 2, 5):
+            rk = oracle.bicgstab(A, b, tol=1e-300, max_iter=k, jacobi_scaling=bool(jacobi))
+            xk, ik = gpu_solve(s7, dims, coef, bd, rtol=1e-300, max_iter=k, schedule=5, jacobi=jacobi)
+            if rk.status == oracle.NOT_CONVERGED and rk.res_rec > 1e-5:  # above the FP32 floor
+                assert ik.iters == k
+                assert rel_err(xk, rk.x) <= 1e-4, (k, rel_err(xk, rk.x))
+                assert abs(ik.rel_res_rec - rk.res_rec) <= 1e-4 * rk.res_rec
+
+
+def test_staged_schedule_split_sums(s7):
+    """More than 1024 tiles (4,300,800 cells, 1050 tiles): the staged passes store
+    workgroup partials and the finishing kernel sums them.  Iterates 1..3 against the
+    oracle, and the converged solution against x* and the oracle."""
+    dims = (160, 160, 168)
+    prob, A, b = problem(dims, seed=68)
+    coef, bd = coef_dev(prob), dev(b)
+    for k in (1, 2, 3):
+        rk = oracle.bicgstab(A, b, tol=1e-300, max_iter=k)
+        xk, ik = gpu_solve(s7, dims, coef, bd, rtol=1e-300, max_iter=k, schedule=5)
+        assert ik.iters == k and ik.schedule == 5
+        assert abs(ik.rel_res_rec - rk.res_rec) <= 1e-4 * rk.res_rec, (k, ik.rel_res_rec, rk.res_rec)
+        assert rel_err(xk, rk.x) <= 1e-4
+    x, info = gpu_solve(s7, dims, coef, bd, rtol=1e-9, max_iter=2000)  # default: staged at this size
+    assert info.status == s7.OK and info.schedule == 5
+    ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+    assert rel_err(x, ref.x) <= 1e-6
+    assert rel_err(x, prob.xstar) <= 1e-6
+
+
+@pytest.mark.parametrize("sched", [1, 3])
+def test_xcd_tile_runs_do_not_change_results(s7, sched):
+    """The XCD-aware tile order (xcd_run) only changes which workgroup takes which tile;
+    partial sums are kept by tile, so the results are bit for bit those of plain order,
+    with ragged last rounds (128x96x96: 2304 paired or 4608 single-cell tiles)."""
+    dims = (128, 96, 96)
+    prob, A, b = problem(dims, seed=15)
+    coef, bd = coef_dev(prob), dev(b)
+    base, ib = gpu_solve(s7, dims, coef, bd, rtol=1e-8, schedule=sched)
+    assert ib.status == s7.OK
+    for xr in (-1, 5, 100):
+        x, info = gpu_solve(s7, dims, coef, bd, rtol=1e-8, schedule=sched, xcd_run=xr)
+        assert info.iters == ib.iters and np.array_equal(x, base), xr
