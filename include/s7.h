@@ -206,6 +206,32 @@ int s7_bicgstab_solve(s7_dims d, const float *const coef[7], const double *b, do
                       double rtol, int32_t max_iter, int32_t prec, void *ws, size_t ws_bytes,
                       const s7_options *opt, s7_info *info, void *stream);
 
+/* Size of the fixed workspace of s7_bicgstab_solve_noalloc: 64 MiB per GPU. */
+#define S7_NOALLOC_WS_BYTES (64u << 20)
+
+/*
+ * For callers that cannot allocate device memory (tight serving loops, code
+ * that must not call hipMalloc): s7_bicgstab_solve with prec = S7_FP32 and
+ * its workspace taken from a fixed 64 MiB array in device memory that the
+ * library holds on each GPU it runs on until the process ends, instead of a
+ * caller workspace.  The caller still provides coef, b and x, as for
+ * s7_bicgstab_solve.  No device memory is allocated or freed: kernels are
+ * launched directly (no hipGraph, no autotuning trials, no profiling events;
+ * opt->tune and opt->profile are ignored), and the solver state is read back
+ * with hipMemcpyAsync into host stack memory.  The results are bit for bit
+ * those of s7_bicgstab_solve(prec = S7_FP32) with the same options and no
+ * tuning.
+ * Limit: s7_workspace_bytes(d, S7_FP32, opt) <= S7_NOALLOC_WS_BYTES (about a
+ * million cells); a larger system returns S7_EINVAL.  The array keeps the
+ * last call's contents; every call clears what must start at zero.  All calls
+ * on one GPU share the array: calls that overlap in time on one GPU (other
+ * host threads, other streams) race and must be serialised by the caller.
+ * Synchronous, like s7_bicgstab_solve; same status codes.
+ */
+int s7_bicgstab_solve_noalloc(s7_dims d, const float *const coef[7], const double *b, double *x,
+                              double rtol, int32_t max_iter, const s7_options *opt, s7_info *info,
+                              void *stream);
+
 /* Workspace for s7_bicgstab_solve_batched over these nsys systems. */
 size_t s7_batched_workspace_bytes(int32_t nsys, const s7_dims *d, int32_t prec,
                                   const s7_options *opt);

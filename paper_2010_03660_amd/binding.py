@@ -28,7 +28,7 @@ __all__ = [
     "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error", "stencil9_apply",
     "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9", "batched_workspace_bytes_2d9",
     "bicgstab_solve_batched_2d9", "Request2D9", "queue_submit_2d9", "workspace_bytes_pipelined",
-    "bicgstab_solve_pipelined",
+    "bicgstab_solve_pipelined", "bicgstab_solve_noalloc", "NOALLOC_WS_BYTES",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
     "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
@@ -111,6 +111,8 @@ EXPORTS = {
     "s7_bicgstab_solve_pipelined": (C.c_int, [Dims, C.POINTER(_vp), _vp, _vp, C.c_double, C.c_int32, _vp,
                                               C.c_size_t, C.POINTER(Options), C.POINTER(Info), _vp]),
     "s7_queue_submit_2d9": (C.c_int, [_vp, C.POINTER(Request2D9), C.POINTER(C.c_uint64)]),
+    "s7_bicgstab_solve_noalloc": (C.c_int, [Dims, C.POINTER(_vp), _vp, _vp, C.c_double, C.c_int32,
+                                            C.POINTER(Options), C.POINTER(Info), _vp]),
     "s7_batched_workspace_bytes_2d9": (C.c_size_t, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                                     C.c_int32, C.POINTER(Options)]),
     "s7_bicgstab_solve_batched_2d9": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -216,6 +218,21 @@ def bicgstab_solve(dims, coef, b, x, rtol, max_iter, prec=FP32, ws=None,
     rc = lib().s7_bicgstab_solve(_dims(dims), _coef(coef), _ptr(b), _ptr(x), float(rtol),
                                  int(max_iter), int(prec), _ptr(ws), wsb,
                                  C.byref(opt) if opt else None, C.byref(info), _stream(stream))
+    _check(rc)
+    return info
+
+
+NOALLOC_WS_BYTES = 64 << 20  # S7_NOALLOC_WS_BYTES
+
+
+def bicgstab_solve_noalloc(dims, coef, b, x, rtol, max_iter, opt: Options | None = None,
+                           stream=None) -> Info:
+    """FP32 solve in place in x with the library's fixed per-GPU workspace: nothing is
+    allocated.  Returns the Info record; raises on error codes < 0."""
+    info = Info()
+    rc = lib().s7_bicgstab_solve_noalloc(_dims(dims), _coef(coef), _ptr(b), _ptr(x), float(rtol),
+                                         int(max_iter), C.byref(opt) if opt else None,
+                                         C.byref(info), _stream(stream))
     _check(rc)
     return info
 

@@ -733,14 +733,24 @@ static int read_state(const State* dst, State* host, hipStream_t s) {
 // Runs BiCGStab iterations from an initialised state until the device says done.
 template <class T>
 static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t stream,
-                          State* host, s7_info* info) {
+                          State* host, s7_info* info, bool direct = false) {
     int rc = read_state(S.st, host, stream);
     if (rc) return rc;
     if (host->done) return S7_OK;
     const int K = o.graph_iters > 0 ? o.graph_iters : auto_graph_iters((size_t)S.n, (int)sizeof(T));
     const long long max_launches = (long long)host->max_iter / K + 3;
     const int sched = effective_schedule(o, S);
-    if (o.profile) {
+    if (direct) {
+        // plain launches: no graph (its instantiation allocates) and no events
+        for (long long l = 0; l < max_launches; ++l) {
+            for (int j = 0; j < K; ++j)
+                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, o.xcd_run, stream);
+            S7_CHECK_LAUNCH();
+            rc = read_state(S.st, host, stream);
+            if (rc) return rc;
+            if (host->done) break;
+        }
+    } else if (o.profile) {
         constexpr int NP = kPasses;
         std::vector<hipEvent_t> ev((size_t)(NP + 1) * K);
         for (auto& e : ev) S7_HIP(hipEventCreate(&e));
@@ -932,7 +942,7 @@ static int tune_single(s7_dims d, const Layout& Lo, int jacobi, int xr, char* ws
 
 static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol,
                       int max_iter, char* ws, const Layout& Lo, const s7_options& o,
-                      s7_info* info, hipStream_t s) {
+                      s7_info* info, hipStream_t s, bool direct = false) {
     SysView<float> S = make_view<float>(d, Lo, o.jacobi, ws);
     int rc = start_solve<float>(cf, S, Lo, o.jacobi, s);
     if (rc) return rc;
@@ -942,7 +952,7 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
     launch_finish<3, 0u, FIN_INIT>(S.red, S.cell_blocks, S.st, s, rtol, max_iter);
     S7_CHECK_LAUNCH();
     State h;
-    rc = run_iterations<float>(S, o, s, &h, info);
+    rc = run_iterations<float>(S, o, s, &h, info, direct);
     if (rc) return rc;
     hipLaunchKernelGGL(k_update_x, dim3(S.stream_blocks), dim3(kThreads), 0, s, x, S.d, S.n, 1.0, S.st);
     S7_CHECK_LAUNCH();
@@ -1520,6 +1530,64 @@ int s7_bicgstab_solve(s7_dims d, const float* const coef[7], const double* b, do
     if (prec == S7_FP32) return solve_fp32(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s);
     if (prec == S7_BF16_IR) return solve_ir<bf16>(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s, prec);
     return solve_ir<f16>(d, cf, b, x, rtol, max_iter, w, Lo, o, info, s, prec);
+}
+
+// ============================================================== solve without allocation
+// The workspace of s7_bicgstab_solve_noalloc: a fixed array in device memory,
+// one copy per GPU, held until the process ends.  Its name stands for the array
+// in device code only; host code reaches it through the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[S7_NOALLOC_WS_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+static int scratch_for_current_device(void** out) {
+    int dev = 0;
+    S7_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("s7_bicgstab_solve_noalloc: device index %d out of range", dev);
+        return S7_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            return S7_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return S7_OK;
+}
+
+int s7_bicgstab_solve_noalloc(s7_dims d, const float* const coef[7], const double* b, double* x,
+                              double rtol, int32_t max_iter, const s7_options* opt, s7_info* info,
+                              void* stream) {
+    clear_error();
+    if (info) std::memset(info, 0, sizeof(*info));
+    s7_options o;
+    options_or_default(opt, o);
+    o.tune = 0;     // tuning trials time with events
+    o.profile = 0;  // per-pass timing creates events
+    if (!dims_ok(d) || !coef_ok(coef) || !b || !x || !(rtol > 0.0) || max_iter < 0) {
+        set_error("s7_bicgstab_solve_noalloc: invalid argument");
+        return S7_EINVAL;
+    }
+    const Layout Lo = make_layout(d, S7_FP32, o);
+    if (Lo.bytes > (size_t)S7_NOALLOC_WS_BYTES) {
+        set_error("s7_bicgstab_solve_noalloc: the system needs %zu workspace bytes, more than the "
+                  "%zu of the fixed workspace", Lo.bytes, (size_t)S7_NOALLOC_WS_BYTES);
+        return S7_EINVAL;
+    }
+    void* ws = nullptr;
+    const int rc = scratch_for_current_device(&ws);
+    if (rc) return rc;
+    Coef7 cf;
+    for (int a = 0; a < 7; ++a) cf.c[a] = coef[a];
+    return solve_fp32(d, cf, b, x, rtol, max_iter, (char*)ws, Lo, o, info, (hipStream_t)stream, true);
 }
 
 int s7_generate_problem(s7_dims d, uint64_t seed, int32_t recipe, float* const coef[7],
