@@ -204,6 +204,25 @@ BATCH_SIDES_2D9 = (96, 128, 192, 256, 384, 512)
 AID_BATCH_SIDES_2D9 = 28
 
 
+# planes of the paper's mesh at which a converged solution is checked on the host: the
+# two faces, their inner neighbours, the middle plane, and 16 more drawn from the seed
+AID_SAMPLE_PLANES = 32
+
+
+def sample_planes(nz: int, extra: int = 16, seed: int = 0):
+    """The fixed planes {0, 1, nz/2, nz-2, nz-1} and `extra` further distinct planes of
+    [0, nz), drawn by hashing (seed, AID_SAMPLE_PLANES, draw) until enough are found."""
+    planes = sorted({0, 1, nz // 2, nz - 2, nz - 1} & set(range(nz)))
+    fixed = len(planes)
+    draw = 0
+    while len(planes) < min(nz, fixed + extra):
+        k = int(uniform01(seed, AID_SAMPLE_PLANES, np.array([draw]))[0] * nz)
+        draw += 1
+        if k not in planes:
+            planes.append(k)
+    return sorted(planes)
+
+
 def batch_shapes_2d9(nsys: int = 64, seed: int = 0):
     """Per-system 2D mesh sides (nx, ny), each uniform over BATCH_SIDES_2D9, plus
     per-system seeds 2000 + s."""

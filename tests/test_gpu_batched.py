@@ -153,6 +153,41 @@ def test_batch_workload_64_systems(s7):
         assert rel_err(host(xs[k]), ref.x) <= 1e-5
 
 
+def test_batch_workload_64_systems_vs_oracle(s7):
+    """The same 64 systems solved in one batched call at recurrence tolerance 1e-8 (the
+    FP32 error floor is near 3e-7, so 1e-7 leaves errors up to about 5e-6), every one
+    checked against the FP64 oracle's solution at 1e-6.  The oracle runs the 64 systems
+    on host threads (its C calls release the interpreter lock)."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    shapes, seeds = synth.batch_shapes(64, seed=0)
+    coefs, bs, xs = [], [], []
+    for d, sd in zip(shapes, seeds):
+        n = int(np.prod(d))
+        c = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(7)]
+        bd = torch.empty(n, dtype=torch.float64, device="cuda")
+        s7.generate_problem(d, sd, 0, c, torch.empty(n, dtype=torch.float64, device="cuda"), bd)
+        coefs.append(c)
+        bs.append(bd)
+        xs.append(torch.zeros(n, dtype=torch.float64, device="cuda"))
+    rc, infos = s7.bicgstab_solve_batched(shapes, coefs, bs, xs, [1e-8] * 64, [2000] * 64)
+    torch.cuda.synchronize()
+    assert rc == s7.OK
+    xh = [host(x) for x in xs]
+    del coefs, bs, xs
+
+    def check(k):
+        p, A, b = problem(shapes[k], seed=seeds[k])
+        ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+        return ref.status, rel_err(xh[k], ref.x)
+
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        res = list(ex.map(check, range(64)))
+    for k, (status, err) in enumerate(res):
+        assert status == oracle.OK and infos[k].status == s7.OK, k
+        assert err <= 1e-6, (k, shapes[k], err)
+
+
 def test_simple_pattern_warm_started(s7):
     """The application pattern of Algorithm 2 (SIMPLE): per outer iteration, the three
     momentum systems u, v, w in one batched call capped at 5 iterations, then the

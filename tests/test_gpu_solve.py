@@ -6,10 +6,12 @@ error against the oracle's solution):
   residual 1e-8 and the oracle reference is converged to 1e-12;
 * iterates: after k <= 8 iterations from x0 = 0 the FP32 iterate agrees with the oracle's
   to 1e-4 relative (rounding of FP32 vectors grows with k, per iteration about 1e-6);
-* iteration counts at tolerance 1e-6 within max(3, 20%): FP32 rounding of the Krylov
-  vectors moves the trajectory after the first ~10 iterations (an FP32 emulation in numpy
-  differs from the FP64 run by a similar amount), and the stop must be genuine: the FP64
-  true residual at exit is at most 1.5x the tolerance;
+* iteration counts within max(3, 20%) of the oracle's, a sanity bound on these fixed
+  seeds: FP32 rounding of the Krylov vectors moves the trajectory and with it the
+  stopping iteration.  tests/test_fp32_iteration_spread.py emulates FP32 storage on the
+  same systems: its count differs from the FP64 oracle's by more than max(3, 10%) on
+  several of them and by up to 30%.  The stop must be genuine: the FP64 true residual at
+  exit is at most 1.5x the tolerance;
 * BF16/FP16 + FP64 refinement: true residual <= requested 1e-10 and error <= 1e-7.
 """
 import numpy as np
@@ -130,6 +132,30 @@ def test_exact_breakdown(s7):
     assert ref.status == oracle.BREAKDOWN and ref.reason == oracle.REASON_RS_ZERO
     x, info = gpu_solve(s7, (2, 1, 1), [dev(c) for c in coef], np.array([1.0, 0.0]), jacobi=0)
     assert info.status == s7.BREAKDOWN and info.reason == s7.REASON_RS_ZERO
+
+
+@pytest.mark.parametrize("case", ["yy_zero", "rho_zero"])
+@pytest.mark.parametrize("sched", [1, 2, 3, 5])
+def test_golden_breakdowns(s7, case, sched):
+    """The hand-worked (y,y) = 0 and (r0, r_1) = 0 systems of tests/golden (every value
+    exact in FP32): the GPU stops with the same breakdown reason after the same number of
+    iterations as the oracle, in every schedule; x holds the last iterate."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "bicgstab_breakdowns.json")) as f:
+        g = json.load(f)[case]
+    coef = [np.array(g["coef"][nm], np.float32) for nm in synth.COEF_NAMES]
+    b = np.array(g["b"])
+    ref = oracle.bicgstab(oracle.build_csr(*g["dims"], coef), b, tol=1e-8, max_iter=10,
+                          jacobi_scaling=False)
+    assert ref.status == oracle.BREAKDOWN
+    x, info = gpu_solve(s7, tuple(g["dims"]), [dev(c) for c in coef], b, jacobi=0, max_iter=10,
+                        schedule=sched)
+    assert info.status == s7.BREAKDOWN and info.reason == ref.reason, info.as_dict()
+    assert info.iters == ref.iters == g["iters"]
+    if "x" in g:
+        assert np.array_equal(x, g["x"])
 
 
 def test_nonfinite_coefficient_is_breakdown(s7):
@@ -314,9 +340,10 @@ def test_schedules_agree(s7, prec):
 def test_paper_mesh_solve_sampled_planes(s7, prec):
     """600x595x1536 (548M unknowns), the configuration the benchmark times, solved to
     convergence with default (untuned) options.  The oracle cannot hold this system, so:
-    the whole solution is checked against the manufactured x* on the device, and on
-    sampled planes the oracle computes the FP64 residual b - A x of the GPU's x row by
-    row (the CSR of planes k-1..k+1 is exact on the rows of plane k)."""
+    the whole solution is checked against the manufactured x* on the device, and on 21
+    sampled planes (0, 1, nz/2, nz-2, nz-1 and 16 seeded others) the oracle computes the
+    FP64 residual b - A x of the GPU's x row by row (the CSR of planes k-1..k+1 is exact
+    on the rows of plane k)."""
     import torch
     p = s7.PREC_NAMES[prec]
     rtol, err_bound, res_bound = (1e-9, 1e-6, 2e-6) if p == s7.FP32 else (1e-10, 1e-7, 1e-9)
@@ -335,7 +362,9 @@ def test_paper_mesh_solve_sampled_planes(s7, prec):
     assert err <= err_bound, err
     del coef, b
     plane = nx * ny
-    for k in (0, 1, nz // 2, nz - 2, nz - 1):
+    planes_checked = synth.sample_planes(nz, 16, seed=0)
+    assert len(planes_checked) == 21
+    for k in planes_checked:
         planes = [q for q in (k - 1, k, k + 1) if 0 <= q < nz]
         prob = synth.make_problem(nx, ny, nz, seed=0, planes=planes)
         A = oracle.build_csr(nx, ny, len(planes), prob.coef)

@@ -264,6 +264,48 @@ def test_exact_breakdown(oracle_mod):
     assert res.status == oracle_mod.BREAKDOWN and res.reason == oracle_mod.REASON_RS_ZERO
 
 
+@pytest.mark.parametrize("case", ["yy_zero", "rho_zero"])
+def test_golden_breakdowns(oracle_mod, case):
+    """The two exact breakdowns of the scalar steps, on hand-worked 2x1x1 systems
+    (tests/golden/bicgstab_breakdowns.json): (y,y) = 0 after the q-step, and
+    (r0, r_1) = 0 after a full step.  Every intermediate value is exact."""
+    with open(os.path.join(GOLDEN, "bicgstab_breakdowns.json")) as f:
+        g = json.load(f)[case]
+    coef = [np.array(g["coef"][nm], np.float32) for nm in synth.COEF_NAMES]
+    A = oracle_mod.build_csr(*g["dims"], coef)
+    b = np.array(g["b"])
+    st = oracle_mod.Stepper(A, b, tol=1e-8, max_iter=10, jacobi_scaling=False)
+    st.step()
+    assert np.array_equal(st.s, g["s"]) and st.st.sigma == g["sigma"] and st.st.alpha == g["alpha"]
+    assert np.array_equal(st.q, g["q"]) and np.array_equal(st.y, g["y"])
+    if "omega" in g:
+        assert st.st.omega == g["omega"]
+        assert np.array_equal(st.x, g["x"]) and np.array_equal(st.r, g["r"])
+    reason = getattr(oracle_mod, "REASON_" + g["reason"])
+    assert st.done and st.st.status == oracle_mod.BREAKDOWN and st.st.reason == reason
+    assert st.st.iter == g["iters"]
+    res = oracle_mod.bicgstab(A, b, tol=1e-8, max_iter=10, jacobi_scaling=False)
+    assert res.status == oracle_mod.BREAKDOWN and res.reason == reason and res.iters == g["iters"]
+
+
+@pytest.mark.parametrize("dims,rows", [((5, 4, 3), (0, 60)), ((5, 4, 3), (20, 40)),
+                                       ((7, 3, 4), (17, 53)), ((6, 6, 6), (215, 216)),
+                                       ((4, 1, 1), (1, 3)), ((3, 5, 2), (0, 0))])
+def test_spmv_rows_equals_rows_of_spmv_and_dense(oracle_mod, dims, rows):
+    """The row-range product (used on sampled planes of meshes too large for the whole
+    product) equals the same rows of the full product and of the dense matrix from the
+    stencil definition, on ragged row ranges that start and end inside planes."""
+    prob = synth.make_problem(*dims, seed=23)
+    A = oracle_mod.build_csr(*dims, prob.coef)
+    v = synth.xstar_values(24, np.arange(A.n))
+    r0, r1 = rows
+    part = oracle_mod.spmv_rows(A, v, r0, r1)
+    assert part.shape == (r1 - r0,)
+    assert np.array_equal(part, oracle_mod.spmv(A, v)[r0:r1])
+    D = dense_from_definition(*dims, prob.coef)
+    np.testing.assert_allclose(part, (D @ v)[r0:r1], rtol=1e-14, atol=1e-14)
+
+
 def test_nonfinite_input_is_breakdown(oracle_mod):
     dims = (3, 2, 2)
     prob = synth.make_problem(*dims, seed=4)
