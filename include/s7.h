@@ -271,11 +271,16 @@ size_t s7_workspace_bytes_pipelined(s7_dims d, const s7_options *opt);
  * z = A s, w = A r, t = A w, v = A z).  The paper uses the classical form;
  * this variant trades more vector traffic for fewer points where the
  * iteration waits on a global sum.  FP32 storage, FP64 inner products.  In
- * FP32 the recurrences drift from A, so every 10 iterations x absorbs the
- * correction and r = b - A x (FP64), w, t, s, z, v and the scalars are
- * recomputed from their definitions (residual replacement); the true
- * residual then floors near 1e-7, and rtol should be 1e-6 or above.  Readings
- * as s7_bicgstab_solve, except that the stopping test on r_i is taken in
+ * FP32 the recurrences drift from A, so every 10 iterations x (FP64) absorbs
+ * the correction and r = b - A x (FP64), w, t, s, z, v and the scalars are
+ * recomputed from their definitions (residual replacement).  A stop that the
+ * recurrences decide is confirmed on that true residual at the next
+ * replacement: S7_OK means the FP64 true residual of the iterated system
+ * (Jacobi-scaled by default) is at most rtol.  If it is not, the iteration
+ * continues from the replaced residual with the search direction restarted,
+ * which lets the true residual fall below the FP32 storage floor (about 1e-7)
+ * as in iterative refinement, until rtol or max_iter.  Readings as
+ * s7_bicgstab_solve, except that the stopping test on r_i is taken in
  * iteration i's reduction (x_i is returned; the half iteration computed before
  * it is not applied).  Four passes per iteration (two streaming, two
  * stencil); info->schedule = 4.  Of the options it reads jacobi and

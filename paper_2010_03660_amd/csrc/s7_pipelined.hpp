@@ -30,8 +30,18 @@
 // magnitude above the recurrence residual.  Every kReplace iterations the
 // iteration folds d into x and recomputes r = b - A x (FP64), w = A r,
 // t = A w, s = A p, z = A s, v = A z from their definitions, then rho and
-// (r0, A p) from the new vectors.  Included by the solver translation unit
-// (s7_single.hip) only.
+// (r0, A p) from the new vectors.
+//
+// Verified stops.  A stop that the recurrences decide (||r_i|| or ||q_i|| at
+// most the tolerance, or rho_{i+1} = 0 with a small residual) is only a
+// candidate unless r_i was replaced since the last update: the iteration then
+// idles until the next replacement, whose true residual decides.  At most the
+// tolerance, the solve ends with S7_OK; otherwise it goes on from the replaced
+// vectors with the search direction restarted (beta = 0: p = r, s = w, z = t)
+// until the true residual meets the tolerance or the iteration cap ends it.
+// With x kept in FP64 and r recomputed from it, the true residual keeps
+// falling below the FP32 storage floor, as in iterative refinement.  Included
+// by the solver translation unit (s7_single.hip) only.
 #pragma once
 
 namespace s7 {
@@ -41,7 +51,10 @@ namespace s7 {
 struct PipeScalars {
     double ry, rt, rs, rz;
     double alpha_next;
-    int32_t flag, pad;
+    int32_t flag;
+    int32_t verify;  // 1: a candidate stop waits for the next replacement
+    int32_t fresh;   // 1: r was replaced and no update has been applied since
+    int32_t pad;
 };
 
 struct PipeView {
@@ -73,7 +86,32 @@ __device__ __forceinline__ void tail_w0(State* st, PipeScalars* ps, const double
 }
 
 // After a replacement: rho = (r0, r), (r0, A p_{i+1}) = (r0, w) + beta ((r0, s) - omega (r0, z)).
-__device__ __forceinline__ void tail_rr(State* st, PipeScalars* ps, const double (&tot)[4]) {
+// tot[4] = (r, r) of the replaced r decides a candidate stop.
+__device__ __forceinline__ void tail_rr(State* st, PipeScalars* ps, const double (&tot)[5]) {
+    ps->fresh = 1;
+    if (ps->verify) {
+        ps->verify = 0;
+        const double res = sqrt(tot[4]) / st->nb;
+        if (!isfinite(res)) {
+            set_breakdown(st, RS_NONFINITE);
+            return;
+        }
+        if (res <= st->tol) {
+            st->res_rec = res;
+            st->status = ST_OK;
+            st->done = 1;
+            return;
+        }
+        if (st->iter >= st->max_iter) {
+            st->res_rec = res;
+            st->status = ST_NOT_CONVERGED;
+            st->done = 1;
+            return;
+        }
+        st->half = 0;
+        st->beta = 0.0;  // restart the direction from the true residual
+        st->omega = 0.0;
+    }
     const double rho = tot[0];
     const double sig = tot[1] + st->beta * (tot[2] - st->omega * tot[3]);
     double a;
@@ -114,8 +152,12 @@ __device__ __forceinline__ void tail_k2(State* st, PipeScalars* ps, const double
         return;
     }
     if (res <= st->tol) {
-        st->status = ST_OK;
-        st->done = 1;
+        if (ps->fresh) {  // r_i is the replaced true residual
+            st->status = ST_OK;
+            st->done = 1;
+        } else {
+            ps->verify = 1;
+        }
         return;
     }
     if (st->iter >= st->max_iter) {
@@ -124,14 +166,14 @@ __device__ __forceinline__ void tail_k2(State* st, PipeScalars* ps, const double
         return;
     }
     const double qn = sqrt(qq) / st->nb;
-    if (qn <= st->tol) {  // half-step exit: x += alpha p
+    if (qn <= st->tol) {  // half-step exit: x += alpha p, then the true residual decides
         st->iter += 1;
         st->res_rec = qn;
         st->half = 1;
         st->omega = 0.0;
-        st->status = ST_OK;
-        st->done = 1;
         ps->flag = 1;
+        ps->fresh = 0;
+        ps->verify = 1;
         return;
     }
     if (yy == 0.0) {
@@ -149,6 +191,7 @@ __device__ __forceinline__ void tail_k2(State* st, PipeScalars* ps, const double
     st->qq = qq;
     st->iter += 1;
     ps->flag = 2;  // the full update of this iteration is applied whatever follows
+    ps->fresh = 0;
     const double a = st->alpha;
     const double rho_new = rq - om * ps->ry;
     if (rho_new == 0.0) {
@@ -156,8 +199,7 @@ __device__ __forceinline__ void tail_k2(State* st, PipeScalars* ps, const double
         const double rn = sqrt(est > 0.0 ? est : 0.0) / st->nb;
         if (rn <= st->tol) {
             st->res_rec = rn;
-            st->status = ST_OK;
-            st->done = 1;
+            ps->verify = 1;
         } else {
             set_breakdown(st, RS_RHO_ZERO);
         }
@@ -184,14 +226,19 @@ __device__ __forceinline__ void tail_k2(State* st, PipeScalars* ps, const double
     ps->alpha_next = an;
 }
 
+// The iteration's kernels idle once the solve has stopped, and while a
+// candidate stop waits for the next replacement; the replacement's only once
+// it has stopped.
+__device__ __forceinline__ bool pipe_idle(const State* st, const PipeScalars* ps) { return st->done || ps->verify; }
+
 template <int ND, int KIND>
 __global__ __launch_bounds__(kThreads) void kp_finish(Red red, int nblocks, State* st, PipeScalars* ps) {
-    if (st->done) return;
+    if ((KIND == PF_K1 || KIND == PF_K2) ? pipe_idle(st, ps) : st->done != 0) return;
     double tot[ND];
     if (finish_split<ND>(red, nblocks, tot) && threadIdx.x == 0) {
         if constexpr (KIND == PF_W0) tail_w0(st, ps, reinterpret_cast<double(&)[1]>(tot));
         else if constexpr (KIND == PF_K1) tail_k1(ps, reinterpret_cast<double(&)[4]>(tot));
-        else if constexpr (KIND == PF_RR) tail_rr(st, ps, reinterpret_cast<double(&)[4]>(tot));
+        else if constexpr (KIND == PF_RR) tail_rr(st, ps, reinterpret_cast<double(&)[5]>(tot));
         else tail_k2(st, ps, reinterpret_cast<double(&)[6]>(tot));
     }
 }
@@ -235,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void kp_w0(SysView<float> S, PipeView P) 
 }
 
 __global__ __launch_bounds__(kThreads) void kp_k1(SysView<float> S, PipeView P) {
-    if (S.st->done) return;
+    if (pipe_idle(S.st, P.ps)) return;
     const float a = (float)S.st->alpha, bt = (float)S.st->beta, om = (float)S.st->omega;
     const int i = blockIdx.x * kThreads + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -263,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void kp_k1(SysView<float> S, PipeView P) 
 
 template <bool UNIT>
 __global__ __launch_bounds__(kThreads) void kp_k2(SysView<float> S, PipeView P) {
-    if (S.st->done) return;
+    if (pipe_idle(S.st, P.ps)) return;
     const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, S.m, S.n);
     const float v = pipe_apply<UNIT>(S, P.z, c);
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -305,7 +352,7 @@ __global__ __launch_bounds__(kThreads) void kp_k4(SysView<float> S, PipeView P) 
         S.st->alpha = P.ps->alpha_next;
         P.ps->flag = 0;
     }
-    if (S.st->done) return;
+    if (pipe_idle(S.st, P.ps)) return;
     const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, S.m, S.n);
     const float t = pipe_apply<UNIT>(S, P.w, c);
     if (c.own) P.t[c.idx] = t;
@@ -330,20 +377,33 @@ __global__ __launch_bounds__(kThreads) void kp_apply(SysView<float> S, const flo
     if (c.own) out[c.idx] = u;
 }
 
-// (r0, r), (r0, w), (r0, s), (r0, z) of the replaced vectors.
+// r = fl32((b - A x) / diag) in FP64 with the caller's coefficients: the
+// replaced residual of the iterated system.
+__global__ __launch_bounds__(kThreads) void kp_resid(Coef7 cf, const double* b, const double* x, float* r,
+                                                     Mesh m, int n, const State* st, int jacobi) {
+    if (st->done) return;
+    const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, m, n);
+    const Nbr<double> xv = load_nbr(x, c);
+    const Coefs<float, false> k = load_coefs_nt<float, false>(cf.c, c.idx);
+    const double r0 = ld_nt(b + c.idx) - apply7<double, float, false, true>(k, xv, c);
+    if (c.own) r[c.idx] = (float)(jacobi ? r0 / (double)k.a[0] : r0);
+}
+
+// (r0, r), (r0, w), (r0, s), (r0, z) and (r, r) of the replaced vectors.
 __global__ __launch_bounds__(kThreads) void kp_rr(SysView<float> S, PipeView P) {
     if (S.st->done) return;
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (i < S.n) {
-        const double h = (double)S.rhat[i];
-        acc[0] = h * (double)S.r[i];
+        const double h = (double)S.rhat[i], r = (double)S.r[i];
+        acc[0] = h * r;
         acc[1] = h * (double)P.w[i];
         acc[2] = h * (double)S.s[i];
         acc[3] = h * (double)P.z[i];
+        acc[4] = r * r;
     }
-    double tot[4];
-    if (grid_reduce<4>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0) tail_rr(S.st, P.ps, tot);
+    double tot[5];
+    if (grid_reduce<5>(acc, S.red, S.cell_blocks, blockIdx.x, tot) && threadIdx.x == 0) tail_rr(S.st, P.ps, tot);
 }
 
 // ---------------------------------------------------------------- driver
@@ -383,9 +443,8 @@ static void pipe_apply_launch(const SysView<float>& S, const float* in, float* o
 static void pipe_replace(const SysView<float>& S, const PipeView& P, const Coef7& cf, const double* b, double* x,
                          int jacobi, hipStream_t s) {
     hipLaunchKernelGGL(kp_fold, dim3(S.stream_blocks), dim3(kThreads), 0, s, x, S.d, S.n, S.st);
-    hipLaunchKernelGGL(k_resid, dim3(S.cell_blocks), dim3(kThreads), 0, s, cf, b, (const double*)x, S.r, S.m, S.n,
-                       S.cell_blocks, S.st, S.red, jacobi);
-    launch_finish<3, 4u, FIN_RESID>(S.red, S.cell_blocks, S.st, s);
+    hipLaunchKernelGGL(kp_resid, dim3(S.cell_blocks), dim3(kThreads), 0, s, cf, b, (const double*)x, S.r, S.m, S.n,
+                       (const State*)S.st, jacobi);
     auto ap = S.unit ? pipe_apply_launch<true> : pipe_apply_launch<false>;
     ap(S, S.r, P.w, s);
     ap(S, P.w, P.t, s);
@@ -393,7 +452,7 @@ static void pipe_replace(const SysView<float>& S, const PipeView& P, const Coef7
     ap(S, S.s, P.z, s);
     ap(S, P.z, P.v, s);
     hipLaunchKernelGGL(kp_rr, dim3(S.cell_blocks), dim3(kThreads), 0, s, S, P);
-    pipe_finish<4, PF_RR>(S, P, s);
+    pipe_finish<5, PF_RR>(S, P, s);
 }
 
 static int solve_pipelined(s7_dims d, const Coef7& cf, const double* b, double* x, double rtol, int max_iter,

@@ -5,9 +5,12 @@ itself pinned to SciPy's BiCGStab and the classical oracle.
 Ragged meshes (one cell, workgroup tails, more than 1024 workgroups so that the sums
 take the split path), both scalings, the first iterates (before any replacement),
 the degenerate cases of Algorithm 1, and 256^3 against the manufactured solution and
-the classical solve.  With FP32 storage and replacement the true residual floors near
-1e-7, so the solves run to a recurrence tolerance of 1e-6 (the FP32 requests of the
-serving workload use the same)."""
+the classical solve.  A stop that the FP32 recurrences decide is confirmed on the FP64
+true residual at the next replacement (and the iteration goes on, its direction
+restarted, if that is above the tolerance), so S7_OK means a true residual at or below
+rtol, and x keeps improving below the FP32 storage floor (about 1e-7) as in iterative
+refinement.  The solves therefore run to 1e-8 and meet the 1e-6 bar against the oracle's
+solution; 1e-10 is reached too."""
 import numpy as np
 import pytest
 
@@ -44,15 +47,18 @@ def test_solution_matches_oracle(s7, dims, jacobi):
     prob, A, b = problem(dims, seed=11)
     ref = oracle.bicgstab_pipelined(A, b, tol=1e-12, max_iter=2000, jacobi_scaling=bool(jacobi))
     assert ref.status == oracle.OK
-    x, info = solve(s7, dims, coef_dev(prob), b, jacobi=jacobi)
+    x, info = solve(s7, dims, coef_dev(prob), b, rtol=1e-8, max_iter=2000, jacobi=jacobi)
     assert info.status == s7.OK and info.schedule == 4
-    # FP32 at a recurrence tolerance of 1e-6: the true residual is at most a few times 1e-6
-    assert info.rel_res_true <= 3e-6
-    assert rel_err(x, ref.x) <= 1e-4
+    # a verified stop: the true residual of the iterated system is at most 1e-8 (the
+    # unscaled one reported here differs by the spread of the diagonal, below 3x)
+    assert info.rel_res_true <= 3e-8
+    assert rel_err(x, ref.x) <= 1e-6
     assert abs(info.rel_res_true - oracle.true_rel_residual(A, b, x)) <= 1e-3 * info.rel_res_true + 1e-15
-    # the replacements move the FP32 trajectory further from the FP64 one than rounding alone
-    r6 = oracle.bicgstab_pipelined(A, b, tol=1e-6, max_iter=2000, jacobi_scaling=bool(jacobi))
-    assert abs(info.iters - r6.iters) <= max(5, 0.3 * r6.iters)
+    if A.n >= 300:
+        # a sanity bound: replacements and restarts move the FP32 trajectory (on meshes
+        # of a few cells a restart can take many more iterations; the stop stays genuine)
+        r8 = oracle.bicgstab_pipelined(A, b, tol=1e-8, max_iter=2000, jacobi_scaling=bool(jacobi))
+        assert abs(info.iters - r8.iters) <= max(5, 0.3 * r8.iters)
 
 
 @pytest.mark.parametrize("k", [1, 2, 5])
@@ -95,8 +101,9 @@ def test_degenerate_cases(s7):
 
 
 def test_cube256_against_manufactured_and_classical(s7):
-    """256^3 (16.8 M cells) to a recurrence tolerance of 1e-6: the pipelined and the
-    classical solves both reach x*, in about as many iterations."""
+    """256^3 (16.8 M cells) to 1e-6: the pipelined and the classical solves both reach
+    x*, in about as many iterations; to 1e-8 the pipelined one's verified stop gives
+    an error below 1e-6 against x*."""
     import torch
     dims = (256, 256, 256)
     n = 256 ** 3
@@ -115,6 +122,11 @@ def test_cube256_against_manufactured_and_classical(s7):
     assert ep <= 1e-4 and ec <= 1e-4, (ep, ec)
     assert abs(ip.iters - ic.iters) <= max(5, 0.3 * ic.iters)
     assert ip.rel_res_true <= 3e-6
+    xp.zero_()
+    i8 = s7.bicgstab_solve_pipelined(dims, c, b, xp, 1e-8, 1000)
+    torch.cuda.synchronize()
+    assert i8.status == s7.OK and i8.rel_res_true <= 3e-8
+    assert float(torch.linalg.vector_norm(xp - xs) / torch.linalg.vector_norm(xs)) <= 1e-6
 
 
 def test_workspace_reused_for_other_arrays(s7):
@@ -128,11 +140,36 @@ def test_workspace_reused_for_other_arrays(s7):
     for seed in (21, 22, 21):
         prob, A, b = problem(dims, seed=seed)
         x = dev(np.zeros(A.n))
-        info = s7.bicgstab_solve_pipelined(dims, coef_dev(prob), dev(b), x, 1e-6, 1000, ws=ws)
+        info = s7.bicgstab_solve_pipelined(dims, coef_dev(prob), dev(b), x, 1e-8, 1000, ws=ws)
         torch.cuda.synchronize()
         assert info.status == s7.OK
         ref = oracle.bicgstab_pipelined(A, b, tol=1e-12, max_iter=2000)
-        assert rel_err(host(x), ref.x) <= 1e-4, seed
+        assert rel_err(host(x), ref.x) <= 1e-6, seed
         results.append((host(x), info.iters))
     # the same system through fresh arrays: the same bits
     assert np.array_equal(results[0][0], results[2][0]) and results[0][1] == results[2][1]
+
+
+@pytest.mark.parametrize("jacobi", [1, 0])
+def test_verified_stop_goes_below_the_fp32_floor(s7, jacobi):
+    """With FP32 Krylov vectors the classical solve's true residual stalls near 2e-7; the
+    pipelined solve's replacements recompute r from the FP64 x, and its stops are
+    verified on that true residual, so it reaches 1e-10 (and the oracle's solution to
+    1e-8)."""
+    dims = (33, 17, 9)
+    prob, A, b = problem(dims, seed=12)
+    ref = oracle.bicgstab_pipelined(A, b, tol=1e-13, max_iter=2000, jacobi_scaling=bool(jacobi))
+    x, info = solve(s7, dims, coef_dev(prob), b, rtol=1e-10, max_iter=2000, jacobi=jacobi)
+    assert info.status == s7.OK, info.as_dict()
+    assert info.rel_res_true <= 3e-10 and oracle.true_rel_residual(A, b, x) <= 3e-10
+    assert rel_err(x, ref.x) <= 1e-8
+
+
+def test_unverifiable_tolerance_ends_at_the_cap(s7):
+    """A tolerance below what the iteration reaches within the cap ends with
+    S7_NOT_CONVERGED at the cap, never with a recurrence-only S7_OK."""
+    dims = (33, 17, 9)
+    prob, A, b = problem(dims, seed=13)
+    x, info = solve(s7, dims, coef_dev(prob), b, rtol=1e-15, max_iter=60)
+    assert info.status == s7.NOT_CONVERGED and info.iters <= 60
+    assert info.rel_res_true > 1e-15
