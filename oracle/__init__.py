@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-fno-fast-math", "-std=c99", "-o", tmp, _SRC, "-lm"])
+                               "-fno-fast-math", "-std=c99", "-fopenmp", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -71,6 +71,7 @@ def _load():
         lib.oracle_build_csr_2d9.restype = C.c_int64
         lib.oracle_build_csr_2d9.argtypes = [C.c_int32] * 2 + [_fp] * 9 + [_ip, _ip, _dp]
         lib.oracle_spmv.argtypes = [C.c_int64, _ip, _ip, _dp, _dp, _dp]
+        lib.oracle_set_threads.argtypes = [C.c_int32]
         lib.oracle_spmv_rows.argtypes = [C.c_int64, C.c_int64, _ip, _ip, _dp, _dp, _dp]
         lib.oracle_dot.restype = C.c_double
         lib.oracle_dot.argtypes = [C.c_int64, _dp, _dp]
@@ -157,6 +158,11 @@ def spmv_rows(A: CSR, x: np.ndarray, r0: int, r1: int) -> np.ndarray:
     y = np.empty(r1 - r0, dtype=np.float64)
     _load().oracle_spmv_rows(r0, r1, _i(A.rowptr), _i(A.col), _d(A.val), _d(x), _d(y))
     return y
+
+
+def set_threads(t: int) -> None:
+    """Threads of the SpMV row loop (timing only; results do not depend on it)."""
+    _load().oracle_set_threads(int(t))
 
 
 def dot(a, b) -> float:

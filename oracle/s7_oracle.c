@@ -146,9 +146,20 @@ int64_t oracle_build_csr_2d9(int32_t nx, int32_t ny, const float *diag, const fl
     return k;
 }
 
+/*
+ * Threads of the row loop of oracle_spmv (1 by default).  Rows are independent
+ * and each is still summed left to right, so the product is the same for any
+ * count; only the CPU baseline of the benchmark sets more than one, to time
+ * the oracle on all host cores.  Inner products and vector updates stay
+ * single-threaded.
+ */
+static int g_threads = 1;
+void oracle_set_threads(int32_t t) { g_threads = t > 1 ? t : 1; }
+
 /* y = A x, each row summed left to right over its entries. */
 void oracle_spmv(int64_t n, const int64_t *rowptr, const int64_t *col,
                  const double *val, const double *x, double *y) {
+#pragma omp parallel for schedule(static) num_threads(g_threads) if (g_threads > 1)
     for (int64_t r = 0; r < n; ++r) {
         double acc = 0.0;
         for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) acc += val[e] * x[col[e]];

@@ -317,6 +317,25 @@ def test_nonfinite_input_is_breakdown(oracle_mod):
     assert res.status == oracle_mod.BREAKDOWN and res.reason == oracle_mod.REASON_NONFINITE
 
 
+def test_spmv_threads_do_not_change_results(oracle_mod):
+    """The oracle's SpMV row loop may run on several threads to time it on all host
+    cores; every row is still summed left to right, so the product and a whole solve
+    are bit for bit those of one thread."""
+    dims = (20, 16, 12)
+    prob = synth.make_problem(*dims, seed=25)
+    A = oracle_mod.build_csr(*dims, prob.coef)
+    b = oracle_mod.spmv(A, prob.xstar)
+    r1 = oracle_mod.bicgstab(A, b, tol=1e-10, max_iter=500)
+    try:
+        oracle_mod.set_threads(4)
+        y4 = oracle_mod.spmv(A, prob.xstar)
+        r4 = oracle_mod.bicgstab(A, b, tol=1e-10, max_iter=500)
+    finally:
+        oracle_mod.set_threads(1)
+    assert np.array_equal(y4, b)
+    assert r4.iters == r1.iters and np.array_equal(r4.x, r1.x)
+
+
 def test_table1_flop_accounting():
     with open(os.path.join(GOLDEN, "table1_ops.json")) as f:
         g = json.load(f)
