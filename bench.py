@@ -66,7 +66,7 @@ KERNEL = {
 SURVEY_BYTES = {"p1": 48, "p2": 36, "p3": 32}
 BATCH_BYTES = sum(BYTES[("f32", 3)].values())  # the batched engine runs the three-pass schedule
 SPLIT_CELLS = 1 << 21  # the queue's default: larger requests take the single-system path
-SRC_FILES = ["paper_2010_03660_amd/csrc/s7_device.hpp", "paper_2010_03660_amd/csrc/s7_single.hip"]
+SRC_FILES = ["paper_2010_03660_amd/csrc/s7_device.hpp", "paper_2010_03660_amd/csrc/s7_passes.hpp"]
 
 
 def kernel_source_hash() -> str:

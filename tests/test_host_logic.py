@@ -87,7 +87,9 @@ def test_bench_byte_accounting_matches_the_design():
     assert sum(bench.BYTES[("16", 4)].values()) == 64
     # P1: p, r0 and 6 coefficients read, s written, 4 bytes each
     assert bench.BYTES[("f32", 3)]["p1"] == (1 + 1 + 6) * 4 + 4
-    assert set(bench.KERNEL) == set(bench.PASSES) == {1, 2, 3}
+    assert set(bench.KERNEL) == set(bench.PASSES) == {1, 2, 3, 5}
+    # the survey's split of the same Jacobi FP32 iteration (p formed in P1 there): 116 B
+    assert sum(bench.SURVEY_BYTES.values()) == 116
 
 
 def test_bench_byte_accounting_2d9():
