@@ -820,6 +820,50 @@ def served_mixed_leg(s7, torch, dev, nreq: int, rate: float):
     return res
 
 
+# Streaming probes of s7_bandwidth_probe: kind & 3 selects the pattern, +4 non-temporal
+# stores, +8 non-temporal loads.  Bytes moved per element of each of the three arrays.
+PROBE_KINDS = [("read", 0, 4), ("read NT", 8, 4), ("copy", 1, 8), ("copy NT", 13, 8),
+               ("triad", 2, 12), ("triad NT", 14, 12), ("6R/2W", 3, 16), ("6R/2W NT", 15, 16)]
+# bytes read and written per element, for the counter calibration
+PROBE_RW = {0: (4, 0), 1: (4, 4), 2: (8, 4), 3: (12, 4)}
+
+
+def probe_leg(s7, torch, dev, counters_only: bool):
+    """The streaming ceilings of this GPU: each probe over three 2 GiB arrays with 16-byte
+    accesses, timed with HIP events for several grid sizes (best median reported).  With
+    counters_only, one dispatch of each probe at 1024 workgroups: the calibration run for
+    the byte counters (its kernels run in the order of PROBE_KINDS)."""
+    n = 1 << 29
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.ones(n, dtype=torch.float32, device=dev)
+    c = torch.ones(n, dtype=torch.float32, device=dev)
+    out = {"elements_per_array": n, "kinds": {}}
+    for name, kind, bpe in PROBE_KINDS:
+        rd, wr = PROBE_RW[kind & 3]
+        if counters_only:
+            s7.bandwidth_probe(kind, 4, a, b, c, n, 1024)
+            torch.cuda.synchronize()
+            out["kinds"][name] = {"kind": kind, "read_bytes": rd * n, "write_bytes": wr * n}
+            continue
+        best = None
+        for blocks in (256, 1024, 4096, 16384):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ts = []
+            for _ in range(6):
+                e0.record()
+                s7.bandwidth_probe(kind, 4, a, b, c, n, blocks)  # torch's current stream
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            med = sorted(ts[1:])[len(ts[1:]) // 2]
+            gbs = bpe * n / (med * 1e-3) / 1e9
+            if best is None or gbs > best[0]:
+                best = (gbs, blocks, med)
+        out["kinds"][name] = {"kind": kind, "GB/s": round(best[0], 1), "blocks": best[1],
+                              "median_ms": round(best[2], 4), "frac_of_8TBs": round(best[0] / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -859,7 +903,11 @@ def main():
     ap.add_argument("--serve-2d9-burst", type=int, default=200,
                     help="2D 9-point requests in the served burst leg (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only run a 2 GiB device copy (calibrates HBM byte counters)")
+                    help="only run one dispatch of each streaming probe on 2 GiB arrays "
+                         "(calibrates the HBM byte counters)")
+    ap.add_argument("--probe", action="store_true",
+                    help="only measure the streaming ceilings (copy, triad, 6-read/2-write, read-only; "
+                         "cached and non-temporal) and print them as JSON")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -873,13 +921,8 @@ def main():
     s7.lib()
     dev = torch.device("cuda:0")
 
-    if args.copy_probe:
-        src = torch.ones(1 << 29, dtype=torch.float32, device=dev)  # 2 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "launches": 3}))
+    if args.copy_probe or args.probe:
+        print(json.dumps(probe_leg(s7, torch, dev, counters_only=args.copy_probe)), flush=True)
         return
 
     nx, ny, nz = (int(v) for v in args.dims.split(","))

@@ -123,12 +123,12 @@ typedef struct {
                                second stream, one at a time; in the batched solve after the
                                shared launch.  0 = 2^21, -1 = never */
     double inner_rtol;      /* IR: inner relative tolerance; 0 = 1e-2 (BF16), 5e-3 (FP16) */
-    int32_t xcd_run;        /* single-system paired and single-cell stencil passes: consecutive
-                               workgroup tiles that one XCD sweeps in a row (workgroups are
-                               dealt to the eight XCDs in turn, each with its own L2); k > 1:
-                               runs of k tiles, -1: an eighth of a mesh plane's tiles (each XCD
-                               sweeps one band of every plane), 0 or 1: plain order (default;
-                               the runs measured no faster).  Results do not depend on it. */
+    int32_t xcd_run;        /* single-system stencil passes (all forms): consecutive workgroup
+                               tiles that one XCD sweeps in a row (workgroups are dealt to the
+                               eight XCDs in turn, each with its own L2); k > 1: runs of k
+                               tiles, -1: an eighth of a mesh plane's tiles (each XCD sweeps one
+                               band of every plane), 0 or 1: plain order (default; the runs
+                               measured no faster).  Results do not depend on it. */
     int32_t reserved_opt;   /* 0 */
 } s7_options;
 

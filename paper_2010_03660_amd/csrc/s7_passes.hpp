@@ -106,10 +106,11 @@ __global__ __launch_bounds__(kThreads) void k_p2f(SysView<T> S, int run) {
 // lds_count(nx) floats).  Each thread sums its pairs' products first, in pair
 // order, then the workgroup and the grid sums follow as in the flat passes.
 template <class T, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_p1_lds(SysView<T> S, int nblocks) {
+__global__ __launch_bounds__(kThreads) void k_p1_lds(SysView<T> S, int nblocks, int run) {
     extern __shared__ float stage[];
     if (S.st->done) return;
-    const int nx = S.m.nx, c0 = blockIdx.x * kLdsTile, lo = lds_lo(c0, nx);
+    const int tile = xcd_tile(blockIdx.x, nblocks, run);
+    const int nx = S.m.nx, c0 = tile * kLdsTile, lo = lds_lo(c0, nx);
     const int hi = (c0 + kLdsTile + nx + 7) >> 3 << 3;
     stage_rows<T, false>(S.p, nullptr, 0.0f, lo, hi - lo, S.n, stage);
     __syncthreads();
@@ -133,15 +134,16 @@ __global__ __launch_bounds__(kThreads) void k_p1_lds(SysView<T> S, int nblocks) 
         acc[0] += fma((double)rh.b, (double)to_f32(s1), (double)rh.a * (double)to_f32(s0));
     }
     double tot[1];
-    if (grid_reduce<1>(acc, S.red, nblocks, blockIdx.x, tot) && threadIdx.x == 0) tail_p1(S.st, tot);
+    if (grid_reduce<1>(acc, S.red, nblocks, tile, tot) && threadIdx.x == 0) tail_p1(S.st, tot);
 }
 
 template <class T, bool UNIT>
-__global__ __launch_bounds__(kThreads) void k_p2f_lds(SysView<T> S, int nblocks) {
+__global__ __launch_bounds__(kThreads) void k_p2f_lds(SysView<T> S, int nblocks, int run) {
     extern __shared__ float stage[];
     if (S.st->done) return;
     const float alpha = (float)S.st->alpha;
-    const int nx = S.m.nx, c0 = blockIdx.x * kLdsTile, lo = lds_lo(c0, nx);
+    const int tile = xcd_tile(blockIdx.x, nblocks, run);
+    const int nx = S.m.nx, c0 = tile * kLdsTile, lo = lds_lo(c0, nx);
     const int hi = (c0 + kLdsTile + nx + 7) >> 3 << 3;
     stage_rows<T, true>(S.r, S.s, alpha, lo, hi - lo, S.n, stage);
     __syncthreads();
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_p2f_lds(SysView<T> S, int nblocks)
         acc[4] += fma((double)rh.b, yb, (double)rh.a * ya);
     }
     double tot[5];
-    if (grid_reduce<5>(acc, S.red, nblocks, blockIdx.x, tot) && threadIdx.x == 0) tail_p2f(S.st, tot);
+    if (grid_reduce<5>(acc, S.red, nblocks, tile, tot) && threadIdx.x == 0) tail_p2f(S.st, tot);
 }
 
 template <class T, bool QR>

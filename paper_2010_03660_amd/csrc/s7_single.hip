@@ -472,13 +472,14 @@ static void launch_pass(const SysView<T>& S, int pass, int sched, int xr, hipStr
     if (sched == SCHED_LDS && lds_ok(S) && (pass == 2 || (pass == 0 && sizeof(T) == 4))) {
         const int nb = lds_blocks(S.n);
         const size_t lds = (size_t)lds_count(S.m.nx) * sizeof(float);
+        const int run = tile_run(xr, S.m, kLdsTile);
         if (pass == 0) {
-            if (S.unit) hipLaunchKernelGGL((k_p1_lds<T, true>), dim3(nb), dim3(kThreads), lds, s, S, nb);
-            else hipLaunchKernelGGL((k_p1_lds<T, false>), dim3(nb), dim3(kThreads), lds, s, S, nb);
+            if (S.unit) hipLaunchKernelGGL((k_p1_lds<T, true>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
+            else hipLaunchKernelGGL((k_p1_lds<T, false>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
             launch_finish<1, 0u, FIN_P1>(S.red, nb, S.st, s);
         } else {
-            if (S.unit) hipLaunchKernelGGL((k_p2f_lds<T, true>), dim3(nb), dim3(kThreads), lds, s, S, nb);
-            else hipLaunchKernelGGL((k_p2f_lds<T, false>), dim3(nb), dim3(kThreads), lds, s, S, nb);
+            if (S.unit) hipLaunchKernelGGL((k_p2f_lds<T, true>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
+            else hipLaunchKernelGGL((k_p2f_lds<T, false>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
             launch_finish<5, 0u, FIN_P2F>(S.red, nb, S.st, s);
         }
         return;

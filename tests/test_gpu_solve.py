@@ -467,11 +467,12 @@ def test_staged_schedule_split_sums(s7):
     assert rel_err(x, prob.xstar) <= 1e-6
 
 
-@pytest.mark.parametrize("sched", [1, 3])
+@pytest.mark.parametrize("sched", [1, 3, 5])
 def test_xcd_tile_runs_do_not_change_results(s7, sched):
     """The XCD-aware tile order (xcd_run) only changes which workgroup takes which tile;
     partial sums are kept by tile, so the results are bit for bit those of plain order,
-    with ragged last rounds (128x96x96: 2304 paired or 4608 single-cell tiles)."""
+    with ragged last rounds (128x96x96: 2304 paired, 4608 single-cell or 288 staged
+    tiles)."""
     dims = (128, 96, 96)
     prob, A, b = problem(dims, seed=15)
     coef, bd = coef_dev(prob), dev(b)
