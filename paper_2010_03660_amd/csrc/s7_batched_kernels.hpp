@@ -461,6 +461,107 @@ __device__ void chunk_p2f_pairs(const SysView<T>& S, int c0, int c1, float alpha
     }
 }
 
+// ---------------------------------------------------------------- staged chunk work
+// The paired P1 and P2 of a chunk with the stencil operand staged in LDS, for
+// systems with an even nx of at most kStageMaxNx.  The chunk is taken in
+// sub-tiles of kStageTile cells; each is staged with one row either side
+// (P2: q = r - alpha s formed once per cell), then its pairs read the centre
+// and the x and y neighbours from LDS and the z neighbours with coherent
+// loads.  Staging uses 16-byte loads that bypass the XCD's L2 (volatile,
+// system scope): the values were written by other workgroups of the launch.
+// Thread t visits the pairs c0/2 + 256 u + t in the order of the flat chunk
+// functions, so the sums are the same bit for bit.
+constexpr int kStageTile = 4096;
+constexpr int kStageMaxNx = 1024;
+constexpr int kStageLds = kStageTile + 2 * kStageMaxNx + 24;  // one row and cell either side, 8-aligned
+
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+template <class T>
+__device__ __forceinline__ void stage_coherent(const T* v, const T* w, float alpha, bool q, int lo, int cnt,
+                                               int n, float* sm) {
+    constexpr int W = kVec<T>;
+    for (int e = (int)threadIdx.x; e < cnt / W; e += kThreads) {
+        const int g = lo + W * e;
+        float a[W], b[W];
+        if (g >= 0 && g + W <= n) {
+            if constexpr (sizeof(T) == 4) {
+                const f32x4 x = *(volatile __attribute__((address_space(1))) f32x4*)gbl(
+                    reinterpret_cast<f32x4*>(const_cast<T*>(v + g)));
+                a[0] = x.x, a[1] = x.y, a[2] = x.z, a[3] = x.w;
+                if (q) {
+                    const f32x4 y = *(volatile __attribute__((address_space(1))) f32x4*)gbl(
+                        reinterpret_cast<f32x4*>(const_cast<T*>(w + g)));
+                    b[0] = y.x, b[1] = y.y, b[2] = y.z, b[3] = y.w;
+                }
+            } else {
+                const u16x8_t x = *(volatile __attribute__((address_space(1))) u16x8_t*)gbl(
+                    reinterpret_cast<u16x8_t*>(const_cast<T*>(v + g)));
+#pragma unroll
+                for (int j = 0; j < W; ++j) a[j] = to_f32(__builtin_bit_cast(T, (uint16_t)x[j]));
+                if (q) {
+                    const u16x8_t y = *(volatile __attribute__((address_space(1))) u16x8_t*)gbl(
+                        reinterpret_cast<u16x8_t*>(const_cast<T*>(w + g)));
+#pragma unroll
+                    for (int j = 0; j < W; ++j) b[j] = to_f32(__builtin_bit_cast(T, (uint16_t)y[j]));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const bool in = g + j >= 0 && g + j < n;
+                a[j] = in ? to_f32(cload(v + g + j)) : 0.0f;
+                b[j] = (q && in) ? to_f32(cload(w + g + j)) : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) sm[W * e + j] = q ? fmaT(-alpha, b[j], a[j]) : a[j];
+    }
+}
+
+template <class T, bool UNIT, bool P2>
+__device__ void chunk_staged(const SysView<T>& S, int c0, int c1, float alpha, float* sm, double (&acc)[kMaxDots]) {
+    const int nx = S.m.nx;
+    for (int t0 = c0; t0 < c1; t0 += kStageTile) {
+        const int t1 = min(c1, t0 + kStageTile);
+        const int lo = (t0 - nx) >> 3 << 3, hi = (t1 + nx + 7) >> 3 << 3;
+        __syncthreads();  // the previous sub-tile's reads of sm are over
+        stage_coherent<T>(P2 ? S.r : S.p, S.s, alpha, P2, lo, hi - lo, S.n, sm);
+        __syncthreads();
+        for (int u = 0; u < kStageTile / (2 * kThreads); ++u) {
+            const int idx = t0 + 2 * (u * kThreads + (int)threadIdx.x);
+            if (idx >= t1) break;
+            int db, dt;
+            z_offsets(idx, S.m, db, dt);
+            F2 vb, vt;
+            if (P2) {
+                const F2 rb = cload2(S.r + idx + db), sb = cload2(S.s + idx + db);
+                const F2 rt = cload2(S.r + idx + dt), st = cload2(S.s + idx + dt);
+                vb = F2{fmaT(-alpha, sb.a, rb.a), fmaT(-alpha, sb.b, rb.b)};
+                vt = F2{fmaT(-alpha, st.a, rt.a), fmaT(-alpha, st.b, rt.b)};
+            } else {
+                vb = cload2(S.p + idx + db);
+                vt = cload2(S.p + idx + dt);
+            }
+            Nbr<float> v0, v1;
+            lds_nbr2(sm, idx - lo, nx, vb, vt, v0, v1);
+            Coefs<float, UNIT> k0, k1;
+            load_coefs2_nt<T, UNIT>(S.c, idx, k0, k1);
+            const F2 rh = cload2(S.rhat + idx);
+            const Cell none{};
+            const T o0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, v0, none));
+            const T o1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, v1, none));
+            if (P2) {
+                cstore2(S.y + idx, o0, o1);
+                acc_p2f(acc, (double)v0.c, (double)to_f32(o0), (double)rh.a);
+                acc_p2f(acc, (double)v1.c, (double)to_f32(o1), (double)rh.b);
+            } else {
+                cstore2(S.s + idx, o0, o1);
+                acc[0] = fma((double)rh.b, (double)to_f32(o1), fma((double)rh.a, (double)to_f32(o0), acc[0]));
+            }
+        }
+    }
+}
+
 // P3.  QR (three-phase iteration): q = r - alpha s is formed from the old r
 // and s instead of being read.
 template <class T, bool QR>
@@ -576,12 +677,15 @@ __device__ void chunk_i_b(const SysView<T>& S, int c0, int c1, float inv_scale, 
 template <class T>
 __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, int c0, int c1,
                                           float alpha, float omega, float beta, float inv_scale,
-                                          double (&acc)[kMaxDots]) {
+                                          float* sm, double (&acc)[kMaxDots]) {
     const SysView<T> S = as_view<T>(raw);
     if (phase == K_I) {
         chunk_i_b<T>(S, c0, c1, inv_scale, acc);
     } else if (phase == K_P1) {
-        if (S.pair_blocks > 0) {
+        if (S.pair_blocks > 0 && S.m.nx <= kStageMaxNx) {
+            if (S.unit) chunk_staged<T, true, false>(S, c0, c1, 0.0f, sm, acc);
+            else chunk_staged<T, false, false>(S, c0, c1, 0.0f, sm, acc);
+        } else if (S.pair_blocks > 0) {
             if (S.unit) chunk_p1_pairs<T, true>(S, c0, c1, acc);
             else chunk_p1_pairs<T, false>(S, c0, c1, acc);
         } else if (S.unit) {
@@ -590,7 +694,10 @@ __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, 
             chunk_p1_b<T, false>(S, c0, c1, acc);
         }
     } else if (phase == K_P2) {
-        if (S.pair_blocks > 0) {
+        if (S.pair_blocks > 0 && S.m.nx <= kStageMaxNx) {
+            if (S.unit) chunk_staged<T, true, true>(S, c0, c1, alpha, sm, acc);
+            else chunk_staged<T, false, true>(S, c0, c1, alpha, sm, acc);
+        } else if (S.pair_blocks > 0) {
             if (S.unit) chunk_p2f_pairs<T, true>(S, c0, c1, alpha, acc);
             else chunk_p2f_pairs<T, false>(S, c0, c1, alpha, acc);
         } else if (S.unit) {
@@ -738,19 +845,58 @@ __device__ void chunk_s_b9(const SysView<float>& S, const Coef9& cf, const doubl
     }
 }
 
+// The 9-point P1 and P2 of a chunk with the operand staged in LDS (systems with
+// nx of at most kStageMaxNx): each sub-tile of kStageTile cells is staged with
+// one row and one cell either side, and all nine points of a cell are read from
+// LDS.  Thread t visits the cells c0 + 256 j + t in the order of the flat chunk
+// functions, so the sums are the same bit for bit.
+template <class T, bool UNIT, bool P2>
+__device__ void chunk_staged9(const SysView<T>& S, const Coef9T<T>& k, int c0, int c1, float alpha, float* sm,
+                              double (&acc)[kMaxDots]) {
+    const int nx = S.m.nx;
+    for (int t0 = c0; t0 < c1; t0 += kStageTile) {
+        const int t1 = min(c1, t0 + kStageTile);
+        const int lo = (t0 - nx - 1) >> 3 << 3, hi = (t1 + nx + 1 + 7) >> 3 << 3;
+        __syncthreads();
+        stage_coherent<T>(P2 ? S.r : S.p, S.s, alpha, P2, lo, hi - lo, S.n, sm);
+        __syncthreads();
+        for (int u = 0; u < kStageTile / kThreads; ++u) {
+            const int idx = t0 + u * kThreads + (int)threadIdx.x;
+            if (idx >= t1) break;
+            const int L = idx - lo;
+            const float v[9] = {sm[L], sm[L - 1], sm[L + 1], sm[L - nx], sm[L + nx],
+                                sm[L - nx - 1], sm[L - nx + 1], sm[L + nx - 1], sm[L + nx + 1]};
+            const T rh = cload(S.rhat + idx);
+            const T o = from_f32<T>(apply9_work<T, UNIT>(k, idx, v));
+            if (P2) {
+                cstore(S.y + idx, o);
+                acc_p2f(acc, (double)v[0], (double)to_f32(o), (double)to_f32(rh));
+            } else {
+                cstore(S.s + idx, o);
+                acc[0] = fma((double)to_f32(rh), (double)to_f32(o), acc[0]);
+            }
+        }
+    }
+}
+
 template <class T>
 __device__ __forceinline__ void run_chunk9(const SysView<float>& raw, const float* const (&wk)[2], int phase,
                                            int c0, int c1, float alpha, float omega, float beta,
-                                           float inv_scale, double (&acc)[kMaxDots]) {
+                                           float inv_scale, float* sm, double (&acc)[kMaxDots]) {
     const SysView<T> S = as_view<T>(raw);
     const Coef9T<T> k = work9<T>(S, wk);
+    const bool staged = S.m.nx <= kStageMaxNx;
     if (phase == K_I) {
         chunk_i_b<T>(S, c0, c1, inv_scale, acc);
     } else if (phase == K_P1) {
-        if (S.unit) chunk_p1_b9<T, true>(S, k, c0, c1, acc);
+        if (staged && S.unit) chunk_staged9<T, true, false>(S, k, c0, c1, 0.0f, sm, acc);
+        else if (staged) chunk_staged9<T, false, false>(S, k, c0, c1, 0.0f, sm, acc);
+        else if (S.unit) chunk_p1_b9<T, true>(S, k, c0, c1, acc);
         else chunk_p1_b9<T, false>(S, k, c0, c1, acc);
     } else if (phase == K_P2) {
-        if (S.unit) chunk_p2f_b9<T, true>(S, k, c0, c1, alpha, acc);
+        if (staged && S.unit) chunk_staged9<T, true, true>(S, k, c0, c1, alpha, sm, acc);
+        else if (staged) chunk_staged9<T, false, true>(S, k, c0, c1, alpha, sm, acc);
+        else if (S.unit) chunk_p2f_b9<T, true>(S, k, c0, c1, alpha, acc);
         else chunk_p2f_b9<T, false>(S, k, c0, c1, alpha, acc);
     } else {
         chunk_p3_b<T, true>(S, c0, c1, alpha, omega, beta, acc);
@@ -832,6 +978,8 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
     __shared__ int sh_sys, sh_chunk, sh_last, sh_stop, sh_budget;
     __shared__ uint32_t sh_seq, sh_nseq;
     __shared__ State sh_state;
+    // the staged chunk functions' LDS
+    __shared__ float sh_stage[kStageLds];
     int s = (int)(blockIdx.x % (unsigned)nsys);
     long long idle = 0;
     for (;;) {
@@ -902,13 +1050,14 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
             const float beta = (float)cload_d(&S.st->beta);
             const float inv_scale = kind == K_I ? (float)(1.0 / cload_d(&S.st->scale)) : 1.0f;
             if constexpr (OP == OP_9PT) {
-                if (tag == 0) run_chunk9<float>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
-                else if (tag == 1) run_chunk9<bf16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
-                else run_chunk9<f16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+                if (tag == 0) run_chunk9<float>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
+                else if (tag == 1)
+                    run_chunk9<bf16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
+                else run_chunk9<f16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
             } else {
-                if (tag == 0) run_chunk<float>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
-                else if (tag == 1) run_chunk<bf16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
-                else run_chunk<f16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, acc);
+                if (tag == 0) run_chunk<float>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
+                else if (tag == 1) run_chunk<bf16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
+                else run_chunk<f16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
             }
         }
         // Every thread waits until its own vector stores have reached memory: a
