@@ -108,7 +108,8 @@ typedef struct {
                                stage the operand of a 4096-cell tile and one mesh row on
                                either side in LDS (meshes with an even nx of at most 4096;
                                3 otherwise); 0 = 5 on meshes of at least 2^22 cells where
-                               it applies, else 3 */
+                               it applies, else 3.  With tune = 1, lds_tile and xcd_run left at
+                               0 are tuned together with the schedule. */
     int32_t tune;           /* 1: the fields left at 0 among schedule and stream_blocks
                                (single solve) and chunk_cells (batched) take autotuned values
                                for the problem's size class.  An untuned class is timed first
@@ -129,7 +130,10 @@ typedef struct {
                                tiles, -1: an eighth of a mesh plane's tiles (each XCD sweeps one
                                band of every plane), 0 or 1: plain order (default; the runs
                                measured no faster).  Results do not depend on it. */
-    int32_t reserved_opt;   /* 0 */
+    int32_t lds_tile;       /* schedule 5: cells of a workgroup's tile, 2048, 4096 or 8192
+                               (8, 16 or 32 cells per thread); 0 = 4096, or the autotuned
+                               value with tune = 1.  A tile whose LDS (tile + 2 nx floats) does
+                               not fit takes the largest of 4096 and 2048 that does. */
 } s7_options;
 
 typedef struct {
@@ -150,7 +154,7 @@ typedef struct {
                             with LDS-staged stencil operands.  Batched and queue engine solves run
                             three phases per iteration: 3 if nx is even, else 1; the
                             2D 9-point solves (single, batched, queued) report 1 */
-    int32_t reserved;
+    int32_t lds_tile;    /* schedule 5: the tile the staged passes ran with; 0 otherwise */
 } s7_info;
 
 /* Fills *opt with the defaults described above. */

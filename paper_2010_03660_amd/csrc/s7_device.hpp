@@ -843,12 +843,15 @@ __device__ __forceinline__ void pair_p2f(const SysView<T>& S, const Cell& c, flo
 // the flat P2 re-read its two operands' neighbours through the caches at about
 // 1.1 ms per pass over a halo-free stream of the same arrays; staging removes
 // most of that.
-constexpr int kLdsTile = 4096;
+constexpr int kLdsTile = 4096;         // the default tile: 16 cells (8 pairs) per thread
 constexpr int kLdsMaxNx = 4096;
+constexpr int kLdsMaxFloats = 13056;   // staging LDS of a workgroup: 52 KiB beside the 12 KiB of the reduction
 
 __host__ __device__ inline int lds_lo(int c0, int nx) { return (c0 - nx) >> 3 << 3; }
-__host__ __device__ inline int lds_count(int nx) { return kLdsTile + 2 * nx + 16; }
-inline int lds_blocks(long long n) { return (int)((n + kLdsTile - 1) / kLdsTile); }
+__host__ __device__ inline int lds_count(int nx, int tile) { return tile + 2 * nx + 16; }
+inline int lds_blocks(long long n, int tile) { return (int)((n + tile - 1) / tile); }
+// Whether a tile of `tile` cells and its two halo rows fit the staging LDS.
+inline bool lds_fits(int nx, int tile) { return nx <= kLdsMaxNx && lds_count(nx, tile) <= kLdsMaxFloats; }
 
 // Stages v (Q: r - alpha s with v = r, w = s) over [lo, lo + cnt) into sm.
 template <class T, bool Q>

@@ -85,8 +85,11 @@ struct TuneKey {
     bool operator<(const TuneKey& o) const;
 };
 inline int size_bucket(double v) { return v < 1.0 ? 0 : (int)floor(2.0 * log2(v)); }
-bool tune_lookup(const TuneKey& k, int (&val)[2]);
-void tune_store(const TuneKey& k, const int (&val)[2]);
+bool tune_lookup(const TuneKey& k, int (&val)[4]);
+void tune_store(const TuneKey& k, const int (&val)[4]);
+// Appends one line to the file named by S7_TUNE_LOG, if set (the timing of
+// each autotuning trial).
+void tune_log(const char* line);
 
 // ---------------------------------------------------------------- batch engine
 // Runs many systems together: the batched entry point and the request queue

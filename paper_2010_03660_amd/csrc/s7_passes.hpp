@@ -102,22 +102,22 @@ __global__ __launch_bounds__(kThreads) void k_p2f(SysView<T> S, int run) {
         tail_p2f(S.st, tot);
 }
 
-// The staged stencil passes (kLdsTile cells per workgroup; the dynamic LDS holds
-// lds_count(nx) floats).  Each thread sums its pairs' products first, in pair
+// The staged stencil passes (TILE cells per workgroup: 2048, 4096 or 8192; the
+// dynamic LDS holds lds_count(nx, TILE) floats).  Each thread sums its pairs' products first, in pair
 // order, then the workgroup and the grid sums follow as in the flat passes.
-template <class T, bool UNIT>
+template <class T, bool UNIT, int TILE>
 __global__ __launch_bounds__(kThreads) void k_p1_lds(SysView<T> S, int nblocks, int run) {
     extern __shared__ float stage[];
     if (S.st->done) return;
     const int tile = xcd_tile(blockIdx.x, nblocks, run);
-    const int nx = S.m.nx, c0 = tile * kLdsTile, lo = lds_lo(c0, nx);
-    const int hi = (c0 + kLdsTile + nx + 7) >> 3 << 3;
+    const int nx = S.m.nx, c0 = tile * TILE, lo = lds_lo(c0, nx);
+    const int hi = (c0 + TILE + nx + 7) >> 3 << 3;
     stage_rows<T, false>(S.p, nullptr, 0.0f, lo, hi - lo, S.n, stage);
     __syncthreads();
     double acc[1] = {0.0};
     const Cell none{};
 #pragma unroll 2
-    for (int u = 0; u < kLdsTile / (2 * kThreads); ++u) {
+    for (int u = 0; u < TILE / (2 * kThreads); ++u) {
         const int idx = c0 + 2 * (u * kThreads + (int)threadIdx.x);
         if (idx >= S.n) break;
         int db, dt;
@@ -137,20 +137,20 @@ __global__ __launch_bounds__(kThreads) void k_p1_lds(SysView<T> S, int nblocks, 
     if (grid_reduce<1>(acc, S.red, nblocks, tile, tot) && threadIdx.x == 0) tail_p1(S.st, tot);
 }
 
-template <class T, bool UNIT>
+template <class T, bool UNIT, int TILE>
 __global__ __launch_bounds__(kThreads) void k_p2f_lds(SysView<T> S, int nblocks, int run) {
     extern __shared__ float stage[];
     if (S.st->done) return;
     const float alpha = (float)S.st->alpha;
     const int tile = xcd_tile(blockIdx.x, nblocks, run);
-    const int nx = S.m.nx, c0 = tile * kLdsTile, lo = lds_lo(c0, nx);
-    const int hi = (c0 + kLdsTile + nx + 7) >> 3 << 3;
+    const int nx = S.m.nx, c0 = tile * TILE, lo = lds_lo(c0, nx);
+    const int hi = (c0 + TILE + nx + 7) >> 3 << 3;
     stage_rows<T, true>(S.r, S.s, alpha, lo, hi - lo, S.n, stage);
     __syncthreads();
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const Cell none{};
 #pragma unroll 2
-    for (int u = 0; u < kLdsTile / (2 * kThreads); ++u) {
+    for (int u = 0; u < TILE / (2 * kThreads); ++u) {
         const int idx = c0 + 2 * (u * kThreads + (int)threadIdx.x);
         if (idx >= S.n) break;
         int db, dt;

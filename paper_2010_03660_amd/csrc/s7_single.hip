@@ -459,29 +459,71 @@ static int tile_run(int xcd_run, const Mesh& m, int tile_cells) {
     return r < 1 ? 1 : (r > (1 << 20) ? (1 << 20) : (int)r);
 }
 
-// The staged stencil passes apply to meshes with an even nx of at most kLdsMaxNx.
+// The staged passes' tile for this mesh: the requested one (2048, 4096 or 8192
+// cells) if its LDS fits, else the largest of 4096 and 2048 that fits; 0 when
+// the staged passes do not apply (odd nx, or rows too long for the LDS).
+static int lds_tile_for(int requested, int nx, bool even) {
+    if (!even) return 0;
+    if ((requested == 2048 || requested == 4096 || requested == 8192) && lds_fits(nx, requested))
+        return requested;
+    for (int t : {kLdsTile, 2048})
+        if (lds_fits(nx, t)) return t;
+    return 0;
+}
+
+// The schedule of an iteration: the option if set (one that does not apply to
+// the mesh falls back to cell pairs, and cell pairs to single cells when nx is
+// odd); by default the staged passes on meshes of at least kLdsMinCells cells
+// where they apply, else cell pairs.  Below that size the staged passes'
+// workgroups are too few to fill the chip.
+constexpr long long kLdsMinCells = 4LL << 20;
+
 template <class T>
-static bool lds_ok(const SysView<T>& S) {
-    return S.pair_blocks > 0 && S.m.nx <= kLdsMaxNx;
+static int effective_schedule(const s7_options& o, const SysView<T>& S) {
+    if (o.schedule == SCHED_THREE || o.schedule == SCHED_FOUR) return o.schedule;
+    const bool staged = lds_tile_for(o.lds_tile, S.m.nx, S.pair_blocks > 0) > 0;
+    if (o.schedule == SCHED_LDS && staged) return SCHED_LDS;
+    if (o.schedule == SCHED_AUTO && staged && (long long)S.n >= kLdsMinCells) return SCHED_LDS;
+    return S.pair_blocks > 0 ? SCHED_PAIRS : SCHED_THREE;
+}
+
+// Launch parameters of an iteration's passes: the schedule, the XCD tile order
+// and the staged passes' tile.
+struct PassLaunch {
+    int sched, xr, tile;
+};
+
+template <class T>
+static PassLaunch pass_launch(const s7_options& o, const SysView<T>& S) {
+    const int sched = effective_schedule(o, S);
+    return PassLaunch{sched, o.xcd_run, sched == SCHED_LDS ? lds_tile_for(o.lds_tile, S.m.nx, true) : 0};
+}
+
+template <class T, int TILE>
+static void launch_staged(const SysView<T>& S, int pass, int xr, hipStream_t s) {
+    const int nb = lds_blocks(S.n, TILE);
+    const size_t lds = (size_t)lds_count(S.m.nx, TILE) * sizeof(float);
+    const int run = tile_run(xr, S.m, TILE);
+    if (pass == 0) {
+        if (S.unit) hipLaunchKernelGGL((k_p1_lds<T, true, TILE>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
+        else hipLaunchKernelGGL((k_p1_lds<T, false, TILE>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
+        launch_finish<1, 0u, FIN_P1>(S.red, nb, S.st, s);
+    } else {
+        if (S.unit) hipLaunchKernelGGL((k_p2f_lds<T, true, TILE>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
+        else hipLaunchKernelGGL((k_p2f_lds<T, false, TILE>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
+        launch_finish<5, 0u, FIN_P2F>(S.red, nb, S.st, s);
+    }
 }
 
 template <class T>
-static void launch_pass(const SysView<T>& S, int pass, int sched, int xr, hipStream_t s) {
+static void launch_pass(const SysView<T>& S, int pass, const PassLaunch& L, hipStream_t s) {
+    const int sched = L.sched, xr = L.xr;
     // With 16-bit storage the staged P1 measured slower than the paired one (its
     // single operand is read in 4-byte pairs either way), so it keeps the pairs.
-    if (sched == SCHED_LDS && lds_ok(S) && (pass == 2 || (pass == 0 && sizeof(T) == 4))) {
-        const int nb = lds_blocks(S.n);
-        const size_t lds = (size_t)lds_count(S.m.nx) * sizeof(float);
-        const int run = tile_run(xr, S.m, kLdsTile);
-        if (pass == 0) {
-            if (S.unit) hipLaunchKernelGGL((k_p1_lds<T, true>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
-            else hipLaunchKernelGGL((k_p1_lds<T, false>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
-            launch_finish<1, 0u, FIN_P1>(S.red, nb, S.st, s);
-        } else {
-            if (S.unit) hipLaunchKernelGGL((k_p2f_lds<T, true>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
-            else hipLaunchKernelGGL((k_p2f_lds<T, false>), dim3(nb), dim3(kThreads), lds, s, S, nb, run);
-            launch_finish<5, 0u, FIN_P2F>(S.red, nb, S.st, s);
-        }
+    if (sched == SCHED_LDS && L.tile > 0 && (pass == 2 || (pass == 0 && sizeof(T) == 4))) {
+        if (L.tile == 2048) launch_staged<T, 2048>(S, pass, xr, s);
+        else if (L.tile == 8192) launch_staged<T, 8192>(S, pass, xr, s);
+        else launch_staged<T, kLdsTile>(S, pass, xr, s);
         return;
     }
     if ((sched == SCHED_PAIRS || sched == SCHED_LDS) && S.pair_blocks > 0 && pass != 3) {
@@ -534,21 +576,6 @@ static void launch_pass(const SysView<T>& S, int pass, int sched, int xr, hipStr
     }
 }
 
-// The schedule of an iteration: the option if set (one that does not apply to
-// the mesh falls back to cell pairs, and cell pairs to single cells when nx is
-// odd); by default the staged passes on meshes of at least kLdsMinCells cells
-// where they apply, else cell pairs.  Below that size the staged passes'
-// kLdsTile-cell workgroups are too few to fill the chip.
-constexpr long long kLdsMinCells = 4LL << 20;
-
-template <class T>
-static int effective_schedule(const s7_options& o, const SysView<T>& S) {
-    if (o.schedule == SCHED_THREE || o.schedule == SCHED_FOUR) return o.schedule;
-    if (o.schedule == SCHED_LDS && lds_ok(S)) return SCHED_LDS;
-    if (o.schedule == SCHED_AUTO && lds_ok(S) && (long long)S.n >= kLdsMinCells) return SCHED_LDS;
-    return S.pair_blocks > 0 ? SCHED_PAIRS : SCHED_THREE;
-}
-
 static int read_state(const State* dst, State* host, hipStream_t s) {
     S7_HIP(hipMemcpyAsync(host, dst, sizeof(State), hipMemcpyDeviceToHost, s));
     S7_HIP(hipStreamSynchronize(s));
@@ -564,12 +591,13 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
     if (host->done) return S7_OK;
     const int K = o.graph_iters > 0 ? o.graph_iters : auto_graph_iters((size_t)S.n, (int)sizeof(T));
     const long long max_launches = (long long)host->max_iter / K + 3;
-    const int sched = effective_schedule(o, S);
+    const PassLaunch PL = pass_launch(o, S);
+    const int sched = PL.sched;
     if (direct) {
         // plain launches: no graph (its instantiation allocates) and no events
         for (long long l = 0; l < max_launches; ++l) {
             for (int j = 0; j < K; ++j)
-                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, o.xcd_run, stream);
+                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, PL, stream);
             S7_CHECK_LAUNCH();
             rc = read_state(S.st, host, stream);
             if (rc) return rc;
@@ -584,7 +612,7 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
             for (int j = 0; j < K; ++j) {
                 for (int p = 0; p < NP; ++p) {
                     S7_HIP(hipEventRecord(ev[(NP + 1) * j + p], stream));
-                    launch_pass<T>(S, p, sched, o.xcd_run, stream);
+                    launch_pass<T>(S, p, PL, stream);
                 }
                 S7_HIP(hipEventRecord(ev[(NP + 1) * j + NP], stream));
             }
@@ -612,11 +640,11 @@ static int run_iterations(const SysView<T>& S, const s7_options& o, hipStream_t 
                                       (uintptr_t)S.unit, (uintptr_t)S.st, (uintptr_t)S.red.part,
                                       (uintptr_t)S.r, (uintptr_t)S.c[1], (uintptr_t)S.d,
                                       (uintptr_t)S.stream_blocks, (uintptr_t)sched,
-                                      (uintptr_t)o.xcd_run};
+                                      (uintptr_t)(intptr_t)PL.xr, (uintptr_t)PL.tile};
         GraphRef g;
         rc = cached_graph(key, [&](hipStream_t cs) {
             for (int j = 0; j < K; ++j)
-                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, o.xcd_run, cs);
+                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, PL, cs);
         }, &g);
         if (rc) return rc;
         for (long long l = 0; l < max_launches; ++l) {
@@ -706,11 +734,16 @@ static int tune_prepare(const SysView<T>& S, hipStream_t s) {
     return S7_OK;
 }
 
-// Picks the schedule and the streaming split of the single-system solve for the
-// size class of d: each candidate runs one warm-up and K timed iterations.
+// Picks the launch parameters of the single-system solve for the size class of
+// d: first the pass form (the staged passes with tiles of 2048, 4096 and 8192
+// cells, i.e. 8, 16 or 32 cells per thread, each in plain and band-per-XCD tile
+// order; cell pairs; single cells in three and in four passes) at the default
+// streaming split, then the streaming split (256, 512 or 1024 workgroups) for
+// the best form.  Each candidate runs one warm-up and K timed iterations on
+// the trial system.  best = {schedule, stream_blocks, lds_tile, xcd_run}.
 template <class T>
 static int tune_single(s7_dims d, const Layout& Lo, int jacobi, int xr, char* ws, hipStream_t s,
-                       int (&best)[2]) {
+                       int (&best)[4]) {
     const TuneKey key{TUNE_SINGLE, TypeTag<T>::value, jacobi, size_bucket((double)Lo.n), 0};
     if (tune_lookup(key, best)) return S7_OK;
     SysView<T> S = make_view<T>(d, Lo, jacobi, ws);
@@ -718,42 +751,62 @@ static int tune_single(s7_dims d, const Layout& Lo, int jacobi, int xr, char* ws
     hipEvent_t e0, e1;
     S7_HIP(hipEventCreate(&e0));
     S7_HIP(hipEventCreate(&e1));
-    float best_ms = INFINITY;
-    best[0] = S.pair_blocks > 0 ? SCHED_PAIRS : SCHED_THREE;
-    if (lds_ok(S) && (long long)S.n >= kLdsMinCells) best[0] = SCHED_LDS;
-    best[1] = stream_blocks_for((long long)Lo.n, 0);
+    const bool even = S.pair_blocks > 0;
+    std::vector<PassLaunch> forms;
+    for (int tile : {2048, 4096, 8192}) {
+        if (!even || lds_tile_for(tile, S.m.nx, true) != tile) continue;
+        for (int x : {1, -1}) forms.push_back(PassLaunch{SCHED_LDS, x, tile});
+    }
+    if (even) forms.push_back(PassLaunch{SCHED_PAIRS, xr, 0});
+    forms.push_back(PassLaunch{SCHED_THREE, xr, 0});
+    forms.push_back(PassLaunch{SCHED_FOUR, xr, 0});
     int rc = S7_OK;
-    std::vector<int> tried;
-    for (int sched : {SCHED_LDS, SCHED_PAIRS, SCHED_THREE, SCHED_FOUR}) {
-        if (sched == SCHED_PAIRS && S.pair_blocks == 0) continue;  // odd nx: same as SCHED_THREE
-        if (sched == SCHED_LDS && !lds_ok(S)) continue;
-        for (int cap : {256, 512, 1024}) {
+    // one timed trial: iterations per millisecond, or a negative value if the
+    // trial system stopped (then the time says nothing)
+    auto trial = [&](const PassLaunch& L, int sb, float* out_ms) -> int {
+        S.stream_blocks = sb;
+        int r = tune_prepare<T>(S, s);
+        if (r) return r;
+        for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, L, s);
+        if (hipEventRecord(e0, s) != hipSuccess) return S7_EHIP;
+        for (int j = 0; j < K; ++j)
+            for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, L, s);
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return S7_EHIP;
+        State h;
+        if ((r = read_state(S.st, &h, s))) return r;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        *out_ms = (h.done || h.iter != K + 1) ? -1.0f : ms / (float)K;
+        char line[200];
+        std::snprintf(line, sizeof line, "single tag=%d unit=%d dims=%dx%dx%d schedule=%d lds_tile=%d xcd_run=%d "
+                      "stream_blocks=%d ms_per_iteration=%.4f", TypeTag<T>::value, jacobi, d.nx, d.ny, d.nz,
+                      L.sched, L.tile, L.xr, sb, *out_ms);
+        tune_log(line);
+        return S7_OK;
+    };
+    const int sb0 = stream_blocks_for((long long)Lo.n, 0);
+    PassLaunch bestL = forms.front();
+    float best_ms = INFINITY;
+    for (const PassLaunch& L : forms) {
+        float ms;
+        if ((rc = trial(L, sb0, &ms))) break;
+        if (ms >= 0.0f && ms < best_ms) {
+            best_ms = ms;
+            bestL = L;
+        }
+    }
+    int best_sb = sb0;
+    if (!rc && best_ms < INFINITY) {
+        for (int cap : {512, 1024}) {
             const int sb = stream_blocks_for((long long)Lo.n, cap);
-            const int id = sched * 4096 + sb;
-            if (std::find(tried.begin(), tried.end(), id) != tried.end()) continue;
-            tried.push_back(id);
-            S.stream_blocks = sb;
-            if ((rc = tune_prepare<T>(S, s))) break;
-            for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, xr, s);
-            if (hipEventRecord(e0, s) != hipSuccess) { rc = S7_EHIP; break; }
-            for (int j = 0; j < K; ++j)
-                for (int p = 0; p < kPasses; ++p) launch_pass<T>(S, p, sched, xr, s);
-            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                rc = S7_EHIP;
-                break;
-            }
-            State h;
-            if ((rc = read_state(S.st, &h, s))) break;
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (h.done || h.iter != K + 1) continue;  // the trial system stopped: no timing
-            if (ms < best_ms) {
+            if (sb == sb0) continue;
+            float ms;
+            if ((rc = trial(bestL, sb, &ms))) break;
+            if (ms >= 0.0f && ms < best_ms) {
                 best_ms = ms;
-                best[0] = sched;
-                best[1] = sb;
+                best_sb = sb;
             }
         }
-        if (rc) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -761,6 +814,16 @@ static int tune_single(s7_dims d, const Layout& Lo, int jacobi, int xr, char* ws
         set_error("autotuning trial failed");
         return rc;
     }
+    if (best_ms == INFINITY) {  // no timing: the defaults
+        s7_options def;
+        s7_default_options(&def);
+        const PassLaunch L = pass_launch(def, S);
+        bestL = PassLaunch{L.sched, xr, L.tile};
+    }
+    best[0] = bestL.sched;
+    best[1] = best_sb;
+    best[2] = bestL.tile;
+    best[3] = bestL.xr;
     tune_store(key, best);
     return S7_OK;
 }
@@ -793,6 +856,7 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
         info->iters = h.iter;
         info->outer_iters = 1;
         info->schedule = effective_schedule(o, S);
+        info->lds_tile = pass_launch(o, S).tile;
         info->rel_res_true = h.bb_true > 0 ? sqrt(h.rr_true / h.bb_true) : 0.0;
         info->t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
@@ -889,9 +953,11 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
     SysView<T> S = make_view<T>(d, Lo, o.jacobi, ws);
     int rc = start_solve<T>(cf, S, Lo, o.jacobi, s);
     if (rc) return rc;
-    return refine<T>(S, x, rtol, max_iter, o, prec, effective_schedule(o, S), info, s,
-                     [&]() { return resid_launch<T>(cf, b, x, S.d, S, o.jacobi, s); },
-                     [&](State* h) { return run_iterations<T>(S, o, s, h, info); });
+    const int rc2 = refine<T>(S, x, rtol, max_iter, o, prec, effective_schedule(o, S), info, s,
+                              [&]() { return resid_launch<T>(cf, b, x, S.d, S, o.jacobi, s); },
+                              [&](State* h) { return run_iterations<T>(S, o, s, h, info); });
+    if (info) info->lds_tile = pass_launch(o, S).tile;
+    return rc2;
 }
 
 // ============================================================== batch engine
@@ -1120,7 +1186,7 @@ int BatchEngine::tune() {
     }
     const TuneKey key{op_ == OP_9PT ? TUNE_BATCH9 : TUNE_BATCH, jobs_[0]->tag, o_.jacobi, size_bucket(total),
                       size_bucket((double)jobs_.size())};
-    int best[2];
+    int best[4] = {0, 0, 0, 0};
     if (tune_lookup(key, best)) {
         chunk_ = best[0];
         grid_cap_ = best[1];
@@ -1343,12 +1409,16 @@ int s7_bicgstab_solve(s7_dims d, const float* const coef[7], const double* b, do
     hipStream_t s = (hipStream_t)stream;
     char* w = (char*)ws;
     if (o.tune && (o.schedule == 0 || o.stream_blocks == 0)) {
-        int best[2];
+        int best[4];
         const int rc = prec == S7_FP32      ? tune_single<float>(d, Lo, o.jacobi, o.xcd_run, w, s, best)
                        : prec == S7_BF16_IR ? tune_single<bf16>(d, Lo, o.jacobi, o.xcd_run, w, s, best)
                                             : tune_single<f16>(d, Lo, o.jacobi, o.xcd_run, w, s, best);
         if (rc) return rc;
-        if (o.schedule == 0) o.schedule = best[0];
+        if (o.schedule == 0) {
+            o.schedule = best[0];
+            if (o.lds_tile == 0) o.lds_tile = best[2];
+            if (o.xcd_run == 0) o.xcd_run = best[3];
+        }
         if (o.stream_blocks == 0) o.stream_blocks = best[1];
         Lo = make_layout(d, prec, o);
     }

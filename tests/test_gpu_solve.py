@@ -481,3 +481,29 @@ def test_xcd_tile_runs_do_not_change_results(s7, sched):
     for xr in (-1, 5, 100):
         x, info = gpu_solve(s7, dims, coef, bd, rtol=1e-8, schedule=sched, xcd_run=xr)
         assert info.iters == ib.iters and np.array_equal(x, base), xr
+
+
+@pytest.mark.parametrize("tile", [2048, 8192])
+@pytest.mark.parametrize("dims", [(34, 17, 9), (128, 96, 96)])
+def test_staged_tiles_match_oracle(s7, tile, dims):
+    """The staged passes with 2048- and 8192-cell tiles (8 and 32 cells per thread)."""
+    prob, A, b = problem(dims, seed=69)
+    ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
+    x, info = gpu_solve(s7, dims, coef_dev(prob), b, rtol=1e-8, max_iter=2000, schedule=5, lds_tile=tile)
+    assert info.status == s7.OK and info.schedule == 5 and info.lds_tile == tile
+    assert rel_err(x, ref.x) <= 1e-6
+    for k in (1, 3):
+        rk = oracle.bicgstab(A, b, tol=1e-300, max_iter=k)
+        xk, ik = gpu_solve(s7, dims, coef_dev(prob), b, rtol=1e-300, max_iter=k, schedule=5, lds_tile=tile)
+        assert rel_err(xk, rk.x) <= 1e-4 and abs(ik.rel_res_rec - rk.res_rec) <= 1e-4 * rk.res_rec
+
+
+def test_staged_tile_falls_back_when_rows_are_long(s7):
+    """A tile whose LDS (tile + 2 nx floats) does not fit takes the largest default that
+    does: nx = 4096 with 8192-cell tiles runs 4096-cell ones."""
+    dims = (4096, 3, 4)
+    prob, A, b = problem(dims, seed=70)
+    ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
+    x, info = gpu_solve(s7, dims, coef_dev(prob), b, rtol=1e-8, max_iter=2000, schedule=5, lds_tile=8192)
+    assert info.status == s7.OK and info.schedule == 5 and info.lds_tile == 4096
+    assert rel_err(x, ref.x) <= 1e-6

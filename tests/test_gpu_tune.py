@@ -59,7 +59,7 @@ def test_trials_leave_caller_arrays_untouched(s7):
     assert rc == s7.NOT_CONVERGED and all(i.iters == 0 for i in infos)
     assert all(bool((x == 0.25).all()) for x in xs)
     text = path.read_text()
-    assert "s7tune1 1 " in text and "s7tune1 2 " in text
+    assert "s7tune2 1 " in text and "s7tune2 2 " in text
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -75,15 +75,14 @@ def test_tuned_single_solve(s7, prec):
     assert np.array_equal(x1, x2) and i1.iters == i2.iters
     ref = oracle.bicgstab(A, b, x0=x0, tol=1e-13, max_iter=2000)
     assert i1.status == s7.OK and rel_err(x1, ref.x) <= (1e-6 if prec == 0 else 1e-7)
-    # the choice is one of the explicit settings: some explicit run reproduces it bit for bit
-    same = False
-    for sched in (1, 2):
-        for sb in (256, 512, 1024):
-            xe, ie = solve(s7, dims, coef, b, x0, schedule=sched, stream_blocks=sb, prec=prec, rtol=rtol)
-            same = same or (np.array_equal(xe, x1) and ie.iters == i1.iters)
-    assert same
-    lines = path.read_text().split("\n")
-    assert any(l.startswith("s7tune1 1 ") for l in lines)
+    # the recorded choice (schedule, streaming split, staged tile, XCD tile order), set
+    # explicitly, reproduces the tuned solve bit for bit
+    line = [l for l in path.read_text().split("\n") if l.startswith(f"s7tune2 1 {prec} ")][-1].split()
+    sched, sb, tile, xr = (int(v) for v in line[6:10])
+    xe, ie = solve(s7, dims, coef, b, x0, schedule=sched, stream_blocks=sb, lds_tile=tile, xcd_run=xr,
+                   prec=prec, rtol=rtol)
+    assert np.array_equal(xe, x1) and ie.iters == i1.iters
+    assert i1.schedule == sched and (sched != 5 or i1.lds_tile == tile)
 
 
 def test_tuned_batched_solve(s7):
@@ -109,6 +108,28 @@ def test_tuned_batched_solve(s7):
     rc2, infos2, xs2 = run(tune=1)
     assert all(np.array_equal(a, c) for a, c in zip(xs, xs2))
     # the tuned chunk is one of the candidates: an explicit run reproduces the result
-    chunk = int([l for l in path.read_text().split("\n") if l.startswith("s7tune1 2 ")][-1].split()[6])
+    chunk = int([l for l in path.read_text().split("\n") if l.startswith("s7tune2 2 ")][-1].split()[6])
     rc3, infos3, xs3 = run(chunk_cells=chunk)
     assert all(np.array_equal(a, c) for a, c in zip(xs, xs3))
+
+
+def test_tuning_trials_are_logged(s7, tmp_path):
+    """S7_TUNE_LOG receives one line per trial: for a mesh with an even nx the staged
+    passes with tiles of 2048, 4096 and 8192 cells in both tile orders, cell pairs, and
+    single cells in three and four passes, then the streaming splits of the best."""
+    s7, path = s7
+    log = tmp_path / "trials.txt"
+    os.environ["S7_TUNE_LOG"] = str(log)
+    try:
+        dims = (96, 64, 48)  # a size class no other test tunes
+        prob, A, b = problem(dims, seed=53)
+        x, info = solve(s7, dims, coef_dev(prob), b, np.zeros(A.n), tune=1)
+    finally:
+        os.environ.pop("S7_TUNE_LOG", None)
+    assert info.status == s7.OK
+    trials = [l for l in log.read_text().split("\n") if l.startswith("single ")]
+    forms = {tuple(int(f.split("=")[1]) for f in l.split() if f.split("=")[0] in ("schedule", "lds_tile", "xcd_run"))
+             for l in trials}
+    assert {(5, t, xr) for t in (2048, 4096, 8192) for xr in (1, -1)} <= forms
+    assert {(3, 0, 0), (1, 0, 0), (2, 0, 0)} <= forms
+    assert all(float(l.split("ms_per_iteration=")[1]) > 0 for l in trials)
