@@ -77,9 +77,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(n_cells: int, kernel: str, schedule: int):
+def traffic_from_profile(n_cells: int, kernel: str, schedule: int, lds_tile: int = 0, xcd_run: int = 0):
     """HBM bytes per launch of pass `kernel` from the committed counter summary, if it was
-    taken on the same schedule and the kernel sources have not changed since."""
+    taken with the same launch parameters (schedule, staged tile, XCD tile order) and the
+    kernel sources have not changed since."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_paper600x595x1536_traffic.json")
     try:
         with open(path) as f:
@@ -87,7 +88,8 @@ def traffic_from_profile(n_cells: int, kernel: str, schedule: int):
     except (OSError, ValueError):
         return None
     if (t.get("source_hash") != kernel_source_hash() or t.get("cells") != n_cells
-            or t.get("schedule") != schedule):
+            or t.get("schedule") != schedule or t.get("lds_tile", 0) != lds_tile
+            or t.get("xcd_run", 0) != xcd_run):
         return None
     return t.get("bytes_per_launch")
 
@@ -881,6 +883,10 @@ def main():
                          "0: autotuned, or the library's default with --no-tune)")
     ap.add_argument("--no-tune", action="store_true",
                     help="fixed default launch parameters instead of autotuned ones")
+    ap.add_argument("--lds-tile", type=int, default=0, choices=(0, 2048, 4096, 8192),
+                    help="tile of the staged passes (s7_options.lds_tile; 0: tuned, or 4096 with --no-tune)")
+    ap.add_argument("--xcd-run", type=int, default=0,
+                    help="XCD tile order of the stencil passes (s7_options.xcd_run; 0: tuned, or plain with --no-tune)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-simple", action="store_true")
@@ -941,8 +947,8 @@ def main():
 
     def run(prec, iters, rtol=1e-300, profile=0):
         x.zero_()
-        o = s7.default_options(profile=profile, schedule=args.schedule,
-                               tune=0 if args.no_tune else 1)
+        o = s7.default_options(profile=profile, schedule=args.schedule, lds_tile=args.lds_tile,
+                               xcd_run=args.xcd_run, tune=0 if args.no_tune else 1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = s7.bicgstab_solve(dims, coef, b, x, rtol, iters, prec=prec, ws=ws, opt=o)
@@ -969,12 +975,12 @@ def main():
     dom_gbs = bytes32[dom] * n / (pass_ms[dom] * 1e-3) / 1e9
     iter_bytes = sum(bytes32.values()) * n
     kernel_ms_iter = sum(pass_ms.values())
-    traffic = traffic_from_profile(n, dom, sched)
+    traffic = traffic_from_profile(n, dom, sched, pinfo.lds_tile, pinfo.xcd_run if sched == 5 else 0)
     roofline = {"bound": "hbm", "kernel": KERNEL[sched][dom],
                 "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": bytes32[dom] * n,
-                "bytes_per_cell": bytes32[dom],
+                "bytes_per_cell": bytes32[dom], "lds_tile": pinfo.lds_tile, "xcd_run": pinfo.xcd_run,
                 "avg_launch_ms": round(pass_ms[dom], 4),
                 "frac_at_survey_bytes_per_cell": round(SURVEY_BYTES[dom] * n / (pass_ms[dom] * 1e-3) / 1e9
                                                        / HBM_PEAK_GBS, 4)

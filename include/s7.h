@@ -155,6 +155,9 @@ typedef struct {
                             three phases per iteration: 3 if nx is even, else 1; the
                             2D 9-point solves (single, batched, queued) report 1 */
     int32_t lds_tile;    /* schedule 5: the tile the staged passes ran with; 0 otherwise */
+    int32_t xcd_run;     /* single-system solves: the XCD tile order the stencil passes ran
+                            with (s7_options.xcd_run, or the tuned value); 0 otherwise */
+    int32_t reserved;
 } s7_info;
 
 /* Fills *opt with the defaults described above. */

@@ -51,14 +51,15 @@ class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32), ("status", C.c_int32),
                 ("reason", C.c_int32), ("rel_res_rec", C.c_double), ("rel_res_true", C.c_double),
                 ("t_ms", C.c_double), ("t_wait_ms", C.c_double), ("pass_ms", C.c_double * 4),
-                ("pass_count", C.c_int32 * 4), ("schedule", C.c_int32), ("lds_tile", C.c_int32)]
+                ("pass_count", C.c_int32 * 4), ("schedule", C.c_int32), ("lds_tile", C.c_int32),
+                ("xcd_run", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {"iters": self.iters, "outer_iters": self.outer_iters, "status": self.status,
                 "reason": self.reason, "rel_res_rec": self.rel_res_rec,
                 "rel_res_true": self.rel_res_true, "t_ms": self.t_ms, "t_wait_ms": self.t_wait_ms,
                 "pass_ms": list(self.pass_ms), "pass_count": list(self.pass_count),
-                "schedule": self.schedule, "lds_tile": self.lds_tile}
+                "schedule": self.schedule, "lds_tile": self.lds_tile, "xcd_run": self.xcd_run}
 
 
 class Request(C.Structure):

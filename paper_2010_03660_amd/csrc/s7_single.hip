@@ -857,6 +857,7 @@ static int solve_fp32(s7_dims d, const Coef7& cf, const double* b, double* x, do
         info->outer_iters = 1;
         info->schedule = effective_schedule(o, S);
         info->lds_tile = pass_launch(o, S).tile;
+        info->xcd_run = o.xcd_run;
         info->rel_res_true = h.bb_true > 0 ? sqrt(h.rr_true / h.bb_true) : 0.0;
         info->t_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
@@ -956,7 +957,10 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
     const int rc2 = refine<T>(S, x, rtol, max_iter, o, prec, effective_schedule(o, S), info, s,
                               [&]() { return resid_launch<T>(cf, b, x, S.d, S, o.jacobi, s); },
                               [&](State* h) { return run_iterations<T>(S, o, s, h, info); });
-    if (info) info->lds_tile = pass_launch(o, S).tile;
+    if (info) {
+        info->lds_tile = pass_launch(o, S).tile;
+        info->xcd_run = o.xcd_run;
+    }
     return rc2;
 }
 
