@@ -329,15 +329,15 @@ typedef struct {
     int32_t prec;         /* s7_prec */
 } s7_request_2d9;
 
-/* Bytes at the head of a queue arena that hold the engine tables (one for
- * 3D 7-point requests, one for 2D 9-point requests). */
+/* Bytes at the head of a queue arena that hold the batch engine's tables
+ * (3D 7-point and 2D 9-point requests share them). */
 size_t s7_queue_table_bytes(void);
 
 /*
  * Creates a queue over the caller's device arena (256-byte aligned), on the
  * current device.  The arena stays owned by the caller and must outlive the
  * queue.  Its head (s7_queue_table_bytes) holds the engine tables for up to
- * 1024 resident requests of each operator; the rest holds the admitted
+ * 2048 resident requests of either operator; the rest holds the admitted
  * requests' workspaces (s7_workspace_bytes of their dims and precision, or
  * s7_workspace_bytes_2d9 of their mesh).  opt->graph_iters sets the epoch: the most
  * iterations a resident request runs between two admission points; 0 (the

@@ -17,11 +17,12 @@
 //   chunk and the phase it belongs to.  Claims past the last chunk are
 //   ignored.
 // * A workgroup publishes its chunk's partial sums, then counts itself done.
-//   The workgroup completing a phase sums that system's partials in chunk
-//   order, runs the scalar step of Algorithm 1 on a private copy of the
-//   state, stores it, and opens the next phase by storing the next sequence
-//   into the claim word.  The sum order is fixed per system, so a system's
-//   iterates do not depend on the rest of the batch or on scheduling.
+//   The workgroup completing a phase sums that system's partials in unit
+//   order (one partial per 1024 cells, summed by one wavefront), runs the
+//   scalar step of Algorithm 1 on a private copy of the state, stores it, and
+//   opens the next phase by storing the next sequence into the claim word.
+//   The sum order is fixed per system, so a system's iterates depend neither
+//   on the rest of the batch, nor on scheduling, nor on the chunk size.
 // * Everything one workgroup hands to another inside the launch goes through
 //   device-scope (coherent) loads and stores: the Krylov vectors, partials,
 //   state and control words.  Each XCD's L2 is private and not coherent with
@@ -30,9 +31,9 @@
 // * Every wait is bounded.  A workgroup that finds no work spins with
 //   s_sleep.  After `spin_limit` fruitless tries it records an error and
 //   leaves, and the launch always drains.
-// * The kernel is a template on the operator: OP_7PT, the 3D 7-point
-//   stencil, or OP_9PT, the 2D 9-point stencil of section IV.  One launch
-//   holds systems of one operator.
+// * Each system names its operator: OP_7PT, the 3D 7-point stencil, or
+//   OP_9PT, the 2D 9-point stencil of section IV.  One launch may hold
+//   systems of both.
 // Included by the solver translation unit (s7_single.hip) only.
 #pragma once
 
@@ -118,7 +119,8 @@ __device__ __forceinline__ void state_store(State* dst, const State& src) {
 // ---------------------------------------------------------------- tables
 // One system of a batch.  The view is stored with FP32 element pointers and
 // re-typed by `tag` (TypeTag of the storage type); the pointer members are
-// identical in every instantiation.  Red.part holds nchunk * kMaxDots partials.
+// identical in every instantiation.  Red.part holds kMaxDots sums per unit of
+// kUnitCells cells.
 struct BCtl;
 
 enum OpKind : int { OP_7PT = 0, OP_9PT = 1 };
@@ -129,6 +131,8 @@ struct BSys {
     int nchunk;
     int tag;
     int budget;  // iterations this system may run in the launch
+    int chunk;   // cells per work item (a multiple of kUnitCells)
+    int op;      // OpKind of the system
     int pad;
     Coef7 cf;    // the caller's FP32 coefficients (residual passes)
     const double* b;
@@ -295,20 +299,61 @@ struct BGlobal {
 };
 
 // ---------------------------------------------------------------- chunk work
-// The cells of chunk c, visited kU per thread per step: thread t takes cells
-// base + 256*u + t for u < kU.  All loads of a step are issued before any
-// store.
+// Partial sums are kept per unit of kUnitCells consecutive cells of a system
+// (the last unit may be shorter): one wavefront sums a unit's products, lane l
+// taking the unit's cells (or x-adjacent pairs) l, l + 64, l + 128, ... in that
+// order, then the fixed DPP sequence of wave_reduce, and lane 63 publishes the
+// unit's sums to part[unit].  The phase's completer adds the units' sums in
+// unit order.  A system's sums therefore depend only on the system: not on
+// how many cells a work item (chunk) covers, nor on which workgroup took it,
+// so the host may size the chunks by load.  A chunk is a whole number of unit
+// groups (kUnitGroup cells, one unit per wavefront of the workgroup), except
+// at the end of a system.
+constexpr int kUnitCells = 1024;
+constexpr int kUnitGroup = kWaves * kUnitCells;
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / kWave); }
+
+// The end of a unit: its ND sums reduced over the wavefront, published by lane
+// 63 (sums j with bit j of MAXMASK set are maxima).  All 64 lanes take part.
+template <int ND, unsigned MAXMASK>
+__device__ __forceinline__ void unit_done(const double (&acc)[kMaxDots], double* part, int unit) {
+    if constexpr (ND > 0) {
+        double v[ND];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) v[j] = acc[j];
+        wave_reduce<ND, MAXMASK>(v);
+        if (lane_id() == kWave - 1) {
+#pragma unroll
+            for (int j = 0; j < ND; ++j) publish(&part[(size_t)unit * kMaxDots + j], v[j]);
+        }
+    }
+}
+
+// The units of chunk [c0, c1): wavefront w takes units w, w + kWaves, ...
+// f(u0, u1, acc) sums one unit's cells [u0, u1) into acc.
+template <int ND, unsigned MAXMASK, class F>
+__device__ __forceinline__ void over_units(int c0, int c1, double* part, F&& f) {
+    for (int u0 = c0 + wave_id() * kUnitCells; u0 < c1; u0 += kUnitGroup) {
+        double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        f(u0, min(c1, u0 + kUnitCells), acc);
+        unit_done<ND, MAXMASK>(acc, part, u0 / kUnitCells);
+    }
+}
+
+// P1 of a unit on single cells, kU per lane and step: lane l takes cells
+// base + 64 u + l for u < kU.  All loads of a step are issued before any store.
 constexpr int kU = 4;
 template <class T, bool UNIT>
 __device__ void chunk_p1_b(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += kU * kThreads) {
+    for (int base = c0; base < c1; base += kU * kWave) {
         Cell cl[kU];
         Nbr<T> pv[kU];
         Coefs<T, UNIT> k[kU];
         T rh[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int g = base + u * kThreads + (int)threadIdx.x;
+            const int g = base + u * kWave + lane_id();
             cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
             cl[u].own = g < c1;
             pv[u] = cload_nbr(S.p, cl[u]);
@@ -359,19 +404,19 @@ __device__ __forceinline__ void cload_nbr2(const T* v, const Cell& c, Nbr<float>
     v1 = Nbr<float>{ce.b, ce.a, e, s.b, nn.b, b.b, t.b};
 }
 
-// P1 of a chunk on x-adjacent cell pairs (systems with an even nx): thread t
-// takes pairs base/2 + 256*u + t for u < kUP.
+// P1 of a unit on x-adjacent cell pairs (systems with an even nx): lane l
+// takes pairs base/2 + 64 u + l for u < kUP.
 constexpr int kUP = 2;
 template <class T, bool UNIT>
 __device__ void chunk_p1_pairs(const SysView<T>& S, int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += 2 * kUP * kThreads) {
+    for (int base = c0; base < c1; base += 2 * kUP * kWave) {
         Cell cl[kUP];
         Nbr<float> p0[kUP], p1[kUP];
         Coefs<float, UNIT> k0[kUP], k1[kUP];
         F2 rh[kUP];
 #pragma unroll
         for (int u = 0; u < kUP; ++u) {
-            const int gp = base / 2 + u * kThreads + (int)threadIdx.x;
+            const int gp = base / 2 + u * kWave + lane_id();
             const bool in = 2 * gp < c1;
             cl[u] = cell2_at(in ? gp : S.n / 2 - 1, S.m, S.n);
             cl[u].own = in;
@@ -393,7 +438,7 @@ __device__ void chunk_p1_pairs(const SysView<T>& S, int c0, int c1, double (&acc
 
 // P2 of the three-phase iteration: q = r - alpha s formed in FP32 at the cell
 // and its six neighbours, y = A q stored; sums (q,y), (y,y), (q,q), (r0,q),
-// (r0,y).  Two cells per thread and step.
+// (r0,y).  Two cells per lane and step.
 __device__ __forceinline__ Nbr<float> q_of(const Nbr<float>& r, const Nbr<float>& s, float alpha) {
     return Nbr<float>{fmaT(-alpha, s.c, r.c), fmaT(-alpha, s.w, r.w), fmaT(-alpha, s.e, r.e),
                       fmaT(-alpha, s.s, r.s), fmaT(-alpha, s.n, r.n), fmaT(-alpha, s.b, r.b),
@@ -409,14 +454,14 @@ __device__ __forceinline__ void acc_p2f(double (&acc)[kMaxDots], double q, doubl
 constexpr int kUF = 2;
 template <class T, bool UNIT>
 __device__ void chunk_p2f_b(const SysView<T>& S, int c0, int c1, float alpha, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += kUF * kThreads) {
+    for (int base = c0; base < c1; base += kUF * kWave) {
         Cell cl[kUF];
         Nbr<T> rv[kUF], sv[kUF];
         Coefs<T, UNIT> k[kUF];
         T rh[kUF];
 #pragma unroll
         for (int u = 0; u < kUF; ++u) {
-            const int g = base + u * kThreads + (int)threadIdx.x;
+            const int g = base + u * kWave + lane_id();
             cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
             cl[u].own = g < c1;
             rv[u] = cload_nbr(S.r, cl[u]);
@@ -439,8 +484,8 @@ __device__ void chunk_p2f_b(const SysView<T>& S, int c0, int c1, float alpha, do
 // The same on x-adjacent cell pairs (systems with an even nx).
 template <class T, bool UNIT>
 __device__ void chunk_p2f_pairs(const SysView<T>& S, int c0, int c1, float alpha, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += 2 * kThreads) {
-        const int gp = base / 2 + (int)threadIdx.x;
+    for (int base = c0; base < c1; base += 2 * kWave) {
+        const int gp = base / 2 + lane_id();
         const bool in = 2 * gp < c1;
         Cell cl = cell2_at(in ? gp : S.n / 2 - 1, S.m, S.n);
         cl.own = in;
@@ -463,15 +508,15 @@ __device__ void chunk_p2f_pairs(const SysView<T>& S, int c0, int c1, float alpha
 
 // ---------------------------------------------------------------- staged chunk work
 // The paired P1 and P2 of a chunk with the stencil operand staged in LDS, for
-// systems with an even nx of at most kStageMaxNx.  The chunk is taken in
-// sub-tiles of kStageTile cells; each is staged with one row either side
-// (P2: q = r - alpha s formed once per cell), then its pairs read the centre
-// and the x and y neighbours from LDS and the z neighbours with coherent
-// loads.  Staging uses 16-byte loads that bypass the XCD's L2 (volatile,
-// system scope): the values were written by other workgroups of the launch.
-// Thread t visits the pairs c0/2 + 256 u + t in the order of the flat chunk
-// functions, so the sums are the same bit for bit.
-constexpr int kStageTile = 4096;
+// systems with an even nx of at most kStageMaxNx.  The chunk is taken one unit
+// group (kStageTile cells) at a time; each group is staged with one row either
+// side (P2: q = r - alpha s formed once per cell), then wavefront w sums unit w
+// of the group: its pairs read the centre and the x and y neighbours from LDS
+// and the z neighbours with coherent loads.  Staging uses 16-byte loads that
+// bypass the XCD's L2 (volatile, system scope): the values were written by
+// other workgroups of the launch.  Lane l visits the unit's pairs l, l + 64, ...
+// as the unstaged pair functions do, so the sums are the same bit for bit.
+constexpr int kStageTile = kUnitGroup;
 constexpr int kStageMaxNx = 1024;
 constexpr int kStageLds = kStageTile + 2 * kStageMaxNx + 24;  // one row and cell either side, 8-aligned
 
@@ -519,17 +564,21 @@ __device__ __forceinline__ void stage_coherent(const T* v, const T* w, float alp
 }
 
 template <class T, bool UNIT, bool P2>
-__device__ void chunk_staged(const SysView<T>& S, int c0, int c1, float alpha, float* sm, double (&acc)[kMaxDots]) {
+__device__ void chunk_staged(const SysView<T>& S, int c0, int c1, float alpha, float* sm, double* part) {
     const int nx = S.m.nx;
     for (int t0 = c0; t0 < c1; t0 += kStageTile) {
         const int t1 = min(c1, t0 + kStageTile);
         const int lo = (t0 - nx) >> 3 << 3, hi = (t1 + nx + 7) >> 3 << 3;
-        __syncthreads();  // the previous sub-tile's reads of sm are over
+        __syncthreads();  // the previous group's reads of sm are over
         stage_coherent<T>(P2 ? S.r : S.p, S.s, alpha, P2, lo, hi - lo, S.n, sm);
         __syncthreads();
-        for (int u = 0; u < kStageTile / (2 * kThreads); ++u) {
-            const int idx = t0 + 2 * (u * kThreads + (int)threadIdx.x);
-            if (idx >= t1) break;
+        const int u0 = t0 + wave_id() * kUnitCells;
+        if (u0 >= t1) continue;  // the same for the whole wavefront
+        const int u1 = min(t1, u0 + kUnitCells);
+        double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int u = 0; u < kUnitCells / (2 * kWave); ++u) {
+            const int idx = u0 + 2 * (u * kWave + lane_id());
+            if (idx >= u1) break;
             int db, dt;
             z_offsets(idx, S.m, db, dt);
             F2 vb, vt;
@@ -559,6 +608,7 @@ __device__ void chunk_staged(const SysView<T>& S, int c0, int c1, float alpha, f
                 acc[0] = fma((double)rh.b, (double)to_f32(o1), fma((double)rh.a, (double)to_f32(o0), acc[0]));
             }
         }
+        unit_done<P2 ? 5 : 1, 0u>(acc, part, u0 / kUnitCells);
     }
 }
 
@@ -569,7 +619,7 @@ __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, flo
                            float beta, double (&acc)[kMaxDots]) {
     // pairs of cells (c0 is even), then a last odd cell if c1 is odd
     const int c1e = c0 + ((c1 - c0) & ~1);
-    for (int i = c0 + 2 * (int)threadIdx.x; i < c1e; i += 2 * kThreads) {
+    for (int i = c0 + 2 * lane_id(); i < c1e; i += 2 * kWave) {
         const F2 d2 = cload2(S.d + i), p2 = cload2(S.p + i), s2 = cload2(S.s + i), y2 = cload2(S.y + i),
                  h2 = cload2(S.rhat + i);
         F2 q2 = cload2((QR ? S.r : S.q) + i);
@@ -588,7 +638,7 @@ __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, flo
         acc[0] = fma((double)h2.b, xb, fma((double)h2.a, xa, acc[0]));
         acc[1] = fma(xb, xb, fma(xa, xa, acc[1]));
     }
-    for (int i = c1e + (int)threadIdx.x; i < c1; i += kThreads) {
+    for (int i = c1e + lane_id(); i < c1; i += kWave) {
         float dv = cload(S.d + i);
         T rn, pn;
         const float sv = to_f32(cload(S.s + i));
@@ -605,7 +655,7 @@ __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, flo
 
 // X: x += scale d in FP64 (x = 0 when zero is set).
 __device__ void chunk_x_b(const SysView<float>& S, double* x, int c0, int c1, double scale, bool zero) {
-    for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads)
+    for (int i = c0 + lane_id(); i < c1; i += kWave)
         cstore(x + i, zero ? 0.0 : fma(scale, (double)cload(S.d + i), cload(x + i)));
 }
 
@@ -614,7 +664,7 @@ __device__ void chunk_x_b(const SysView<float>& S, double* x, int c0, int c1, do
 // Sums: ||b||^2, ||r||^2, max |fl32(r_s)|.
 __device__ void chunk_r_b(const SysView<float>& S, const Coef7& cf, const double* b, const double* x,
                           int c0, int c1, bool write_d, double (&acc)[kMaxDots]) {
-    for (int g = c0 + (int)threadIdx.x; g < c1; g += kThreads) {
+    for (int g = c0 + lane_id(); g < c1; g += kWave) {
         const Cell c = cell_at(g, S.m, S.n);
         const double* px = x + c.idx;
         const Nbr<double> xv{cload(px), cload(px + c.dw), cload(px + c.de), cload(px + c.ds),
@@ -636,7 +686,7 @@ __device__ void chunk_r_b(const SysView<float>& S, const Coef7& cf, const double
 // (r,r) of the rounded r, ||b||^2 unscaled.
 __device__ void chunk_s_b(const SysView<float>& S, const Coef7& cf, const double* b, const double* x,
                           int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int g = c0 + (int)threadIdx.x; g < c1; g += kThreads) {
+    for (int g = c0 + lane_id(); g < c1; g += kWave) {
         const Cell c = cell_at(g, S.m, S.n);
         const double* px = x + c.idx;
         const Nbr<double> xv{cload(px), cload(px + c.dw), cload(px + c.de), cload(px + c.ds),
@@ -663,7 +713,7 @@ __device__ void chunk_s_b(const SysView<float>& S, const Coef7& cf, const double
 // I: r = r0 = p = fl_T(d * inv_scale), d = 0; sum (r, r).
 template <class T>
 __device__ void chunk_i_b(const SysView<T>& S, int c0, int c1, float inv_scale, double (&acc)[kMaxDots]) {
-    for (int i = c0 + (int)threadIdx.x; i < c1; i += kThreads) {
+    for (int i = c0 + lane_id(); i < c1; i += kWave) {
         const T rt = from_f32<T>(cload(S.d + i) * inv_scale);
         cstore(S.r + i, rt);
         cstore(S.rhat + i, rt);
@@ -674,39 +724,53 @@ __device__ void chunk_i_b(const SysView<T>& S, int c0, int c1, float inv_scale, 
     }
 }
 
+// The iteration phases (and I) of chunk [c0, c1) of a 7-point system, with
+// each unit's sums published to part.
 template <class T>
 __device__ __forceinline__ void run_chunk(const SysView<float>& raw, int phase, int c0, int c1,
                                           float alpha, float omega, float beta, float inv_scale,
-                                          float* sm, double (&acc)[kMaxDots]) {
+                                          float* sm, double* part) {
     const SysView<T> S = as_view<T>(raw);
     if (phase == K_I) {
-        chunk_i_b<T>(S, c0, c1, inv_scale, acc);
+        over_units<1, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+            chunk_i_b<T>(S, u0, u1, inv_scale, acc);
+        });
     } else if (phase == K_P1) {
         if (S.pair_blocks > 0 && S.m.nx <= kStageMaxNx) {
-            if (S.unit) chunk_staged<T, true, false>(S, c0, c1, 0.0f, sm, acc);
-            else chunk_staged<T, false, false>(S, c0, c1, 0.0f, sm, acc);
-        } else if (S.pair_blocks > 0) {
-            if (S.unit) chunk_p1_pairs<T, true>(S, c0, c1, acc);
-            else chunk_p1_pairs<T, false>(S, c0, c1, acc);
-        } else if (S.unit) {
-            chunk_p1_b<T, true>(S, c0, c1, acc);
+            if (S.unit) chunk_staged<T, true, false>(S, c0, c1, 0.0f, sm, part);
+            else chunk_staged<T, false, false>(S, c0, c1, 0.0f, sm, part);
         } else {
-            chunk_p1_b<T, false>(S, c0, c1, acc);
+            over_units<1, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+                if (S.pair_blocks > 0) {
+                    if (S.unit) chunk_p1_pairs<T, true>(S, u0, u1, acc);
+                    else chunk_p1_pairs<T, false>(S, u0, u1, acc);
+                } else if (S.unit) {
+                    chunk_p1_b<T, true>(S, u0, u1, acc);
+                } else {
+                    chunk_p1_b<T, false>(S, u0, u1, acc);
+                }
+            });
         }
     } else if (phase == K_P2) {
         if (S.pair_blocks > 0 && S.m.nx <= kStageMaxNx) {
-            if (S.unit) chunk_staged<T, true, true>(S, c0, c1, alpha, sm, acc);
-            else chunk_staged<T, false, true>(S, c0, c1, alpha, sm, acc);
-        } else if (S.pair_blocks > 0) {
-            if (S.unit) chunk_p2f_pairs<T, true>(S, c0, c1, alpha, acc);
-            else chunk_p2f_pairs<T, false>(S, c0, c1, alpha, acc);
-        } else if (S.unit) {
-            chunk_p2f_b<T, true>(S, c0, c1, alpha, acc);
+            if (S.unit) chunk_staged<T, true, true>(S, c0, c1, alpha, sm, part);
+            else chunk_staged<T, false, true>(S, c0, c1, alpha, sm, part);
         } else {
-            chunk_p2f_b<T, false>(S, c0, c1, alpha, acc);
+            over_units<5, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+                if (S.pair_blocks > 0) {
+                    if (S.unit) chunk_p2f_pairs<T, true>(S, u0, u1, alpha, acc);
+                    else chunk_p2f_pairs<T, false>(S, u0, u1, alpha, acc);
+                } else if (S.unit) {
+                    chunk_p2f_b<T, true>(S, u0, u1, alpha, acc);
+                } else {
+                    chunk_p2f_b<T, false>(S, u0, u1, alpha, acc);
+                }
+            });
         }
     } else {
-        chunk_p3_b<T, true>(S, c0, c1, alpha, omega, beta, acc);
+        over_units<2, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+            chunk_p3_b<T, true>(S, u0, u1, alpha, omega, beta, acc);
+        });
     }
 }
 
@@ -741,18 +805,18 @@ __device__ __forceinline__ Coef9T<T> work9(const SysView<T>& S, const float* con
     return k;
 }
 
-// P1: s = A p, rounded to T; (r0, s).  Two cells per thread and step, thread t
-// taking cells base + 256*u + t; all loads of a step before any store.
+// P1 of a unit: s = A p, rounded to T; (r0, s).  Two cells per lane and step,
+// lane l taking cells base + 64 u + l; all loads of a step before any store.
 constexpr int kU9 = 2;
 template <class T, bool UNIT>
 __device__ void chunk_p1_b9(const SysView<T>& S, const Coef9T<T>& k, int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += kU9 * kThreads) {
+    for (int base = c0; base < c1; base += kU9 * kWave) {
         Cell cl[kU9];
         float pv[kU9][9];
         T rh[kU9];
 #pragma unroll
         for (int u = 0; u < kU9; ++u) {
-            const int g = base + u * kThreads + (int)threadIdx.x;
+            const int g = base + u * kWave + lane_id();
             cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
             cl[u].own = g < c1;
             cload9f(S.p, cl[u], pv[u]);
@@ -774,13 +838,13 @@ __device__ void chunk_p1_b9(const SysView<T>& S, const Coef9T<T>& k, int c0, int
 template <class T, bool UNIT>
 __device__ void chunk_p2f_b9(const SysView<T>& S, const Coef9T<T>& k, int c0, int c1, float alpha,
                              double (&acc)[kMaxDots]) {
-    for (int base = c0; base < c1; base += kU9 * kThreads) {
+    for (int base = c0; base < c1; base += kU9 * kWave) {
         Cell cl[kU9];
         float q[kU9][9];
         T rh[kU9];
 #pragma unroll
         for (int u = 0; u < kU9; ++u) {
-            const int g = base + u * kThreads + (int)threadIdx.x;
+            const int g = base + u * kWave + lane_id();
             cl[u] = cell_at(g < c1 ? g : S.n, S.m, S.n);
             cl[u].own = g < c1;
             float rv[9], sv[9];
@@ -805,7 +869,7 @@ __device__ void chunk_p2f_b9(const SysView<T>& S, const Coef9T<T>& k, int c0, in
 // masked); the rest as for the 7-point operator.
 __device__ void chunk_r_b9(const SysView<float>& S, const Coef9& cf, const double* b, const double* x,
                            int c0, int c1, bool write_d, double (&acc)[kMaxDots]) {
-    for (int g = c0 + (int)threadIdx.x; g < c1; g += kThreads) {
+    for (int g = c0 + lane_id(); g < c1; g += kWave) {
         const Cell c = cell_at(g, S.m, S.n);
         double xv[9];
         cload9d(x, c, xv);
@@ -823,7 +887,7 @@ __device__ void chunk_r_b9(const SysView<float>& S, const Coef9& cf, const doubl
 // S (FP32 jobs): r0 = b - A x0, as for the 7-point operator.
 __device__ void chunk_s_b9(const SysView<float>& S, const Coef9& cf, const double* b, const double* x,
                            int c0, int c1, double (&acc)[kMaxDots]) {
-    for (int g = c0 + (int)threadIdx.x; g < c1; g += kThreads) {
+    for (int g = c0 + lane_id(); g < c1; g += kWave) {
         const Cell c = cell_at(g, S.m, S.n);
         double xv[9];
         cload9d(x, c, xv);
@@ -846,13 +910,13 @@ __device__ void chunk_s_b9(const SysView<float>& S, const Coef9& cf, const doubl
 }
 
 // The 9-point P1 and P2 of a chunk with the operand staged in LDS (systems with
-// nx of at most kStageMaxNx): each sub-tile of kStageTile cells is staged with
-// one row and one cell either side, and all nine points of a cell are read from
-// LDS.  Thread t visits the cells c0 + 256 j + t in the order of the flat chunk
-// functions, so the sums are the same bit for bit.
+// nx of at most kStageMaxNx): each unit group is staged with one row and one
+// cell either side, and all nine points of a cell are read from LDS.  Lane l
+// of wavefront w visits the cells l, l + 64, ... of unit w of the group, as
+// the unstaged functions do, so the sums are the same bit for bit.
 template <class T, bool UNIT, bool P2>
 __device__ void chunk_staged9(const SysView<T>& S, const Coef9T<T>& k, int c0, int c1, float alpha, float* sm,
-                              double (&acc)[kMaxDots]) {
+                              double* part) {
     const int nx = S.m.nx;
     for (int t0 = c0; t0 < c1; t0 += kStageTile) {
         const int t1 = min(c1, t0 + kStageTile);
@@ -860,9 +924,13 @@ __device__ void chunk_staged9(const SysView<T>& S, const Coef9T<T>& k, int c0, i
         __syncthreads();
         stage_coherent<T>(P2 ? S.r : S.p, S.s, alpha, P2, lo, hi - lo, S.n, sm);
         __syncthreads();
-        for (int u = 0; u < kStageTile / kThreads; ++u) {
-            const int idx = t0 + u * kThreads + (int)threadIdx.x;
-            if (idx >= t1) break;
+        const int u0 = t0 + wave_id() * kUnitCells;
+        if (u0 >= t1) continue;  // the same for the whole wavefront
+        const int u1 = min(t1, u0 + kUnitCells);
+        double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int u = 0; u < kUnitCells / kWave; ++u) {
+            const int idx = u0 + u * kWave + lane_id();
+            if (idx >= u1) break;
             const int L = idx - lo;
             const float v[9] = {sm[L], sm[L - 1], sm[L + 1], sm[L - nx], sm[L + nx],
                                 sm[L - nx - 1], sm[L - nx + 1], sm[L + nx - 1], sm[L + nx + 1]};
@@ -876,30 +944,41 @@ __device__ void chunk_staged9(const SysView<T>& S, const Coef9T<T>& k, int c0, i
                 acc[0] = fma((double)to_f32(rh), (double)to_f32(o), acc[0]);
             }
         }
+        unit_done<P2 ? 5 : 1, 0u>(acc, part, u0 / kUnitCells);
     }
 }
 
 template <class T>
 __device__ __forceinline__ void run_chunk9(const SysView<float>& raw, const float* const (&wk)[2], int phase,
                                            int c0, int c1, float alpha, float omega, float beta,
-                                           float inv_scale, float* sm, double (&acc)[kMaxDots]) {
+                                           float inv_scale, float* sm, double* part) {
     const SysView<T> S = as_view<T>(raw);
     const Coef9T<T> k = work9<T>(S, wk);
     const bool staged = S.m.nx <= kStageMaxNx;
     if (phase == K_I) {
-        chunk_i_b<T>(S, c0, c1, inv_scale, acc);
+        over_units<1, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+            chunk_i_b<T>(S, u0, u1, inv_scale, acc);
+        });
     } else if (phase == K_P1) {
-        if (staged && S.unit) chunk_staged9<T, true, false>(S, k, c0, c1, 0.0f, sm, acc);
-        else if (staged) chunk_staged9<T, false, false>(S, k, c0, c1, 0.0f, sm, acc);
-        else if (S.unit) chunk_p1_b9<T, true>(S, k, c0, c1, acc);
-        else chunk_p1_b9<T, false>(S, k, c0, c1, acc);
+        if (staged && S.unit) chunk_staged9<T, true, false>(S, k, c0, c1, 0.0f, sm, part);
+        else if (staged) chunk_staged9<T, false, false>(S, k, c0, c1, 0.0f, sm, part);
+        else
+            over_units<1, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+                if (S.unit) chunk_p1_b9<T, true>(S, k, u0, u1, acc);
+                else chunk_p1_b9<T, false>(S, k, u0, u1, acc);
+            });
     } else if (phase == K_P2) {
-        if (staged && S.unit) chunk_staged9<T, true, true>(S, k, c0, c1, alpha, sm, acc);
-        else if (staged) chunk_staged9<T, false, true>(S, k, c0, c1, alpha, sm, acc);
-        else if (S.unit) chunk_p2f_b9<T, true>(S, k, c0, c1, alpha, acc);
-        else chunk_p2f_b9<T, false>(S, k, c0, c1, alpha, acc);
+        if (staged && S.unit) chunk_staged9<T, true, true>(S, k, c0, c1, alpha, sm, part);
+        else if (staged) chunk_staged9<T, false, true>(S, k, c0, c1, alpha, sm, part);
+        else
+            over_units<5, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+                if (S.unit) chunk_p2f_b9<T, true>(S, k, u0, u1, alpha, acc);
+                else chunk_p2f_b9<T, false>(S, k, u0, u1, alpha, acc);
+            });
     } else {
-        chunk_p3_b<T, true>(S, c0, c1, alpha, omega, beta, acc);
+        over_units<2, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+            chunk_p3_b<T, true>(S, u0, u1, alpha, omega, beta, acc);
+        });
     }
 }
 
@@ -971,10 +1050,10 @@ __device__ int after_resid(State& st, const double (&tot)[kMaxDots]) {
 }
 
 // ---------------------------------------------------------------- persistent kernel
-template <int OP>
+// One launch runs systems of both operators: the system's op selects its
+// phase functions.
 __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ sys, BGlobal* glob,
-                                                      int nsys, int chunk_cells,
-                                                      long long spin_limit) {
+                                                      int nsys, long long spin_limit) {
     __shared__ int sh_sys, sh_chunk, sh_last, sh_stop, sh_budget;
     __shared__ uint32_t sh_seq, sh_nseq;
     __shared__ State sh_state;
@@ -1028,59 +1107,64 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
         const BSys& B = sys[me];
         const SysView<float> S = B.S;
         const int tag = B.tag;
+        const bool op9 = __builtin_amdgcn_readfirstlane(B.op) == OP_9PT;
         const int chunk = __builtin_amdgcn_readfirstlane(sh_chunk);
         const uint32_t seq = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh_seq);
         const int kind = (int)(seq & 7u);
-        const int c0 = chunk * chunk_cells;
-        const int c1 = min(S.n, c0 + chunk_cells);
-        double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const int c0 = chunk * B.chunk;
+        const int c1 = min(S.n, c0 + B.chunk);
+        double* const part = S.red.part;
         if (kind == K_X) {
-            chunk_x_b(S, B.x, c0, c1, cload_d(&S.st->scale), cload_i(&S.st->xzero) != 0);
+            const double scale = cload_d(&S.st->scale);
+            const bool zero = cload_i(&S.st->xzero) != 0;
+            over_units<0, 0u>(c0, c1, part, [&](int u0, int u1, double (&)[kMaxDots]) {
+                chunk_x_b(S, B.x, u0, u1, scale, zero);
+            });
         } else if (kind == K_R) {
-            if constexpr (OP == OP_9PT)
-                chunk_r_b9(S, coef9_of(B.cf, B.cf9), B.b, B.x, c0, c1, cload_i(&S.st->ir) != 0, acc);
-            else
-                chunk_r_b(S, B.cf, B.b, B.x, c0, c1, cload_i(&S.st->ir) != 0, acc);
+            const bool ir = cload_i(&S.st->ir) != 0;
+            over_units<3, 4u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+                if (op9) chunk_r_b9(S, coef9_of(B.cf, B.cf9), B.b, B.x, u0, u1, ir, acc);
+                else chunk_r_b(S, B.cf, B.b, B.x, u0, u1, ir, acc);
+            });
         } else if (kind == K_S) {
-            if constexpr (OP == OP_9PT) chunk_s_b9(S, coef9_of(B.cf, B.cf9), B.b, B.x, c0, c1, acc);
-            else chunk_s_b(S, B.cf, B.b, B.x, c0, c1, acc);
+            over_units<3, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+                if (op9) chunk_s_b9(S, coef9_of(B.cf, B.cf9), B.b, B.x, u0, u1, acc);
+                else chunk_s_b(S, B.cf, B.b, B.x, u0, u1, acc);
+            });
         } else {
             const float alpha = (float)cload_d(&S.st->alpha);
             const float omega = (float)cload_d(&S.st->omega);
             const float beta = (float)cload_d(&S.st->beta);
             const float inv_scale = kind == K_I ? (float)(1.0 / cload_d(&S.st->scale)) : 1.0f;
-            if constexpr (OP == OP_9PT) {
-                if (tag == 0) run_chunk9<float>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
+            if (op9) {
+                if (tag == 0) run_chunk9<float>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, part);
                 else if (tag == 1)
-                    run_chunk9<bf16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
-                else run_chunk9<f16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
+                    run_chunk9<bf16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, part);
+                else run_chunk9<f16>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, part);
             } else {
-                if (tag == 0) run_chunk<float>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
-                else if (tag == 1) run_chunk<bf16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
-                else run_chunk<f16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, acc);
+                if (tag == 0) run_chunk<float>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, part);
+                else if (tag == 1) run_chunk<bf16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, part);
+                else run_chunk<f16>(S, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, part);
             }
         }
-        // Every thread waits until its own vector stores have reached memory: a
-        // workgroup barrier does not wait for them, and the next phase may read
-        // them from another workgroup.
+        // Every thread waits until its own vector stores (the units' sums
+        // included) have reached memory: a workgroup barrier does not wait for
+        // them, and the next phase may read them from another workgroup.  Then
+        // the chunk is counted done.
         wait_stores();
-        // publish this chunk's partials, then count the chunk done
-        double bsum[kMaxDots];
-        if (kind == K_R) block_reduce<kMaxDots, 4u>(acc, bsum);
-        else block_reduce<kMaxDots, 0u>(acc, bsum);
+        __syncthreads();
         if (threadIdx.x == 0) {
-            for (int j = 0; j < kND[kind]; ++j) publish(&S.red.part[(size_t)chunk * kMaxDots + j], bsum[j]);
-            wait_stores();
             const uint32_t t = __hip_atomic_fetch_add(gbl(&B.ctl->done_cnt), 1u, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
             sh_last = (t == (uint32_t)(B.nchunk - 1));
         }
         __syncthreads();
         if (!sh_last) continue;
-        // this workgroup completes the phase: sum the partials in chunk order
+        // this workgroup completes the phase: sum the units' sums in unit order
+        const int nunit = (S.n + kUnitCells - 1) / kUnitCells;
         double tot[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (kind == K_R) sum_range<kMaxDots, 4u, true>(S.red.part, 0, B.nchunk, tot);
-        else if (kND[kind] > 0) sum_range<kMaxDots, 0u, true>(S.red.part, 0, B.nchunk, tot);
+        if (kind == K_R) sum_range<kMaxDots, 4u, true>(part, 0, nunit, tot);
+        else if (kND[kind] > 0) sum_range<kMaxDots, 0u, true>(part, 0, nunit, tot);
         // the private state copy lives in LDS: a register copy would raise the
         // register count of the whole kernel
         state_load(S.st, sh_state);

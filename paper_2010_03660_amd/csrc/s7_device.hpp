@@ -501,19 +501,36 @@ __device__ __forceinline__ void block_reduce(double (&acc)[ND], double (&out)[ND
     }
 }
 
-// Sums src[i*ND + j] for i in [i0, i1) into out (thread 0), in a fixed order.
+// Sums src[i*ND + j] for i in [i0, i1) into out (thread 0), in a fixed order:
+// thread t adds i = i0 + t, i0 + t + 256, ... in turn, then the workgroup sum.
+// The loads of four such steps are issued before their values are added, so
+// that a long range costs about one memory round trip per four steps.
 // COHERENT: the partials were published by other workgroups of this kernel.
 template <int ND, unsigned MAXMASK, bool COHERENT>
 __device__ __forceinline__ void sum_range(const double* src, int i0, int i1, double (&out)[ND]) {
+    constexpr int kB = 4;
     double s[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) s[j] = 0.0;
-    for (int b = i0 + (int)threadIdx.x; b < i1; b += kThreads) {
+    auto ld = [&](int b, int j) {
+        const double* p = &src[(size_t)b * ND + j];
+        return COHERENT ? fetch_published(p) : *p;
+    };
+    int b = i0 + (int)threadIdx.x;
+    for (; b + (kB - 1) * kThreads < i1; b += kB * kThreads) {
+        double v[kB][ND];
 #pragma unroll
-        for (int j = 0; j < ND; ++j) {
-            const double* p = &src[(size_t)b * ND + j];
-            s[j] = comb<ND, MAXMASK>(j, s[j], COHERENT ? fetch_published(p) : *p);
-        }
+        for (int k = 0; k < kB; ++k)
+#pragma unroll
+            for (int j = 0; j < ND; ++j) v[k][j] = ld(b + k * kThreads, j);
+#pragma unroll
+        for (int k = 0; k < kB; ++k)
+#pragma unroll
+            for (int j = 0; j < ND; ++j) s[j] = comb<ND, MAXMASK>(j, s[j], v[k][j]);
+    }
+    for (; b < i1; b += kThreads) {
+#pragma unroll
+        for (int j = 0; j < ND; ++j) s[j] = comb<ND, MAXMASK>(j, s[j], ld(b, j));
     }
     block_reduce<ND, MAXMASK>(s, out);
 }

@@ -111,6 +111,7 @@ struct EngineJob {
     s7_info info;     // filled when the job is finished
     int finished;     // 1 once info is final
     void* user;       // owner's handle
+    int op = 0;       // 0: 3D 7-point, 1: 2D 9-point
     // engine-private
     int stage, tag;
     Layout lo;
@@ -124,10 +125,11 @@ struct BSys;  // one system of a persistent launch (device table entry)
 class BatchEngine {
   public:
     // use_graph: replay the persistent launch from a captured hipGraph, for
-    // callers whose resident set repeats (the batched entry point).  op: the
-    // operator of every job (0: 3D 7-point, 1: 2D 9-point).
+    // callers whose resident set repeats (the batched entry point).  Jobs of
+    // both operators (EngineJob::op) may be resident together: one persistent
+    // launch runs them all.
     BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
-                bool use_graph = false, int op = 0);
+                bool use_graph = false);
     ~BatchEngine();
     BatchEngine(const BatchEngine&) = delete;
     BatchEngine& operator=(const BatchEngine&) = delete;
@@ -158,7 +160,6 @@ class BatchEngine {
     bool graph_;
     int chunk_;     // cells per work item of the persistent kernel
     int grid_cap_;  // most workgroups of a persistent launch
-    int op_;        // the operator of every job
     double ticks_per_ms_ = 100000.0;  // device wall clock
     State* host_states_ = nullptr;  // pinned, cap_ entries
     std::vector<EngineJob*> jobs_;

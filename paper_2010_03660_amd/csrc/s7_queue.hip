@@ -20,10 +20,10 @@
 //     best on the single-system path.  A second thread solves them one at a
 //     time on its own stream, concurrently with the engine's launches.
 //   A finished request frees its workspace for the next admission.
-// * 2D 9-point requests (s7_queue_submit_2d9) share the arena, the FIFO and
-//   the large-request thread.  Small ones join a second batch engine, whose
-//   persistent kernel is the 9-point instantiation; each round of the serving
-//   thread steps the engines that have residents, one time slice each.
+// * 2D 9-point requests (s7_queue_submit_2d9) share the arena, the FIFO, the
+//   large-request thread and the batch engine: one persistent launch runs the
+//   resident requests of both operators, each system with its own phase
+//   functions.
 // * poll() never blocks; wait() blocks until the request is done.  A finished
 //   request's result is handed out once, then its ticket is released.
 #include <hip/hip_runtime.h>
@@ -45,7 +45,7 @@ using namespace s7;
 namespace {
 
 constexpr double kSliceMs = 2.0;      // target length of one persistent launch
-constexpr int kQueueCapacity = 1024;  // resident engine requests at most
+constexpr int kQueueCapacity = 2048;  // resident engine requests at most
 constexpr long long kSplitCells = 1ll << 21;
 
 double now_ms() {
@@ -114,8 +114,7 @@ struct s7_queue {
     long long split_cells;
     Arena heap;
     hipStream_t stream = nullptr, big_stream = nullptr;
-    std::unique_ptr<BatchEngine> engine;   // 3D 7-point requests
-    std::unique_ptr<BatchEngine> engine9;  // 2D 9-point requests
+    std::unique_ptr<BatchEngine> engine;  // resident requests of both operators
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done, cv_big;
@@ -183,15 +182,13 @@ struct s7_queue {
                         cv_big.notify_one();
                     } else {
                         resident.push_back(r);
-                        (r->op ? engine9 : engine)->add(&r->job);
+                        engine->add(&r->job);
                     }
                 }
                 seen = gen;
             }
             if (resident.empty()) continue;
-            int rc = S7_OK;
-            if (engine->resident() > 0) rc = engine->step(epoch_iters, kSliceMs);
-            if (rc == S7_OK && engine9->resident() > 0) rc = engine9->step(epoch_iters, kSliceMs);
+            const int rc = engine->step(epoch_iters, kSliceMs);
             std::lock_guard<std::mutex> lk(mu);
             if (rc != S7_OK) {
                 error_msg = s7_last_error();
@@ -264,7 +261,7 @@ extern "C" {
 // Two engine tables: the 7-point engine's, then the 9-point engine's.
 static size_t one_table_bytes() { return align256(engine_table_bytes(kQueueCapacity)); }
 
-size_t s7_queue_table_bytes(void) { return 2 * one_table_bytes(); }
+size_t s7_queue_table_bytes(void) { return one_table_bytes(); }
 
 int s7_queue_create(s7_queue** q, void* arena, size_t arena_bytes, const s7_options* opt) {
     clear_error();
@@ -292,8 +289,6 @@ int s7_queue_create(s7_queue** q, void* arena, size_t arena_bytes, const s7_opti
         return S7_EHIP;
     }
     Q->engine.reset(new BatchEngine((char*)arena, kQueueCapacity, o, Q->stream));
-    Q->engine9.reset(new BatchEngine((char*)arena + one_table_bytes(), kQueueCapacity, o, Q->stream,
-                                     /*use_graph=*/false, /*op=*/1));
     Q->worker = std::thread([Q] { Q->run(); });
     Q->big_worker = std::thread([Q] { Q->run_big(); });
     *q = Q;
@@ -311,6 +306,7 @@ static int enqueue(s7_queue* q, const EngineJob& job, int op, size_t bytes, uint
     std::unique_ptr<Req> r(new Req());
     r->job = job;
     r->job.ws_bytes = bytes;
+    r->job.op = op;
     r->op = op;
     r->bytes = bytes;
     r->big = (long long)job.d.nx * job.d.ny * job.d.nz >= q->split_cells;

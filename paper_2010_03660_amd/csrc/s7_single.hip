@@ -983,9 +983,9 @@ size_t engine_table_bytes(int capacity) {
 static int chunk_cells_of(const s7_options& o);
 
 BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
-                         bool use_graph, int op)
+                         bool use_graph)
     : tables_(tables), cap_(capacity), o_(o), st_(stream), graph_(use_graph),
-      chunk_(chunk_cells_of(o)), grid_cap_(1024), op_(op) {
+      chunk_(chunk_cells_of(o)), grid_cap_(1024) {
     if (hipHostMalloc((void**)&host_states_, (size_t)capacity * sizeof(State), hipHostMallocDefault) !=
         hipSuccess)
         host_states_ = nullptr;  // read_states reports it
@@ -1009,7 +1009,7 @@ int BatchEngine::add(EngineJob* j) {
         set_error("batch engine: more than %d resident systems", cap_);
         return S7_EAGAIN;
     }
-    j->lo = make_layout(j->d, j->prec, o_, op_ == OP_9PT ? (o_.jacobi ? 8 : 9) : 0);
+    j->lo = make_layout(j->d, j->prec, o_, j->op == OP_9PT ? (o_.jacobi ? 8 : 9) : 0);
     j->stage = J_NEW;
     j->tag = j->prec == S7_FP32 ? 0 : (j->prec == S7_BF16_IR ? 1 : 2);
     j->finished = 0;
@@ -1023,17 +1023,42 @@ int BatchEngine::add(EngineJob* j) {
 // round trip to memory on the system's own control words, so chunks are
 // large by default: a small system is one or two chunks, done by one
 // workgroup with no hand-off, and the batch itself supplies the parallelism.
+// A chunk is a whole number of the units whose sums the phases keep.
 static int chunk_cells_of(const s7_options& o) {
     int c = o.chunk_cells > 0 ? o.chunk_cells : 16384;
     if (c > (1 << 24)) c = 1 << 24;  // chunk start + chunk_cells stays within 32 bits
-    c = (c + kThreads - 1) / kThreads * kThreads;
+    c = (c + kUnitCells - 1) / kUnitCells * kUnitCells;
+    return c;
+}
+
+// The chunk of each system in a launch.  While the resident set has fewer
+// work items than the persistent grid has workgroups (light load), a system
+// of few chunks has its chunks halved, down to one unit group and up to
+// kShrinkChunks chunks, so that a lone system is spread over more workgroups.
+// Larger systems keep their chunks: the claims and completions of one
+// system's chunks are atomics on the same control words, which serialize.
+// The sums are kept per unit, so this changes no result.  An explicit
+// options.chunk_cells is kept as given.
+constexpr long long kShrinkChunks = 64;
+static std::vector<int> launch_chunks(const std::vector<EngineJob*>& jobs, int chunk, int grid_cap, bool adapt) {
+    std::vector<int> c(jobs.size(), chunk);
+    if (!adapt) return c;
+    long long items = 0;
+    for (const EngineJob* j : jobs) items += (long long)((j->lo.n + chunk - 1) / chunk);
+    if (items >= grid_cap) return c;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        const long long n = (long long)jobs[i]->lo.n;
+        while (c[i] >= 2 * kUnitGroup && c[i] % (2 * kUnitCells) == 0 && (n + c[i] / 2 - 1) / (c[i] / 2) <= kShrinkChunks)
+            c[i] /= 2;
+    }
     return c;
 }
 
 // The start-table entry of a new job: coefficient copies, State and control
 // words, and the first phase (the FP32 start S, or the FP64 residual R that
 // begins refinement).
-static JobStart job_entry(const EngineJob& j, const s7_options& o, int op) {
+static JobStart job_entry(const EngineJob& j, const s7_options& o) {
+    const int op = j.op;
     JobStart J{};
     SysView<float> S = make_view<float>(j.d, j.lo, o.jacobi, j.ws);  // pointer members only
     for (int a = 0; a < 7; ++a) J.cf.c[a] = j.coef[a];
@@ -1063,12 +1088,15 @@ static JobStart job_entry(const EngineJob& j, const s7_options& o, int op) {
     ((j).prec == S7_FP32 ? call<float> : ((j).prec == S7_BF16_IR ? call<bf16> : call<f16>))
 
 // The table entry of a resident job in a persistent launch.
-static BSys sys_entry(const EngineJob& j, const s7_options& o, int op, int chunk, int budget) {
+static BSys sys_entry(const EngineJob& j, const s7_options& o, int chunk, int budget) {
+    const int op = j.op;
     BSys b;
     std::memset(&b, 0, sizeof(b));
+    b.op = op;
     b.S = make_view<float>(j.d, j.lo, o.jacobi, j.ws);
     b.ctl = reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl);
     b.nchunk = (int)((j.lo.n + chunk - 1) / chunk);
+    b.chunk = chunk;
     b.tag = j.tag;
     b.budget = budget;
     for (int a = 0; a < 7; ++a) b.cf.c[a] = j.coef[a];
@@ -1086,7 +1114,8 @@ static BSys sys_entry(const EngineJob& j, const s7_options& o, int op, int chunk
     return b;
 }
 
-static void finish_job(EngineJob& j, const State& h, int op) {
+static void finish_job(EngineJob& j, const State& h) {
+    const int op = j.op;
     s7_info& inf = j.info;
     std::memset(&inf, 0, sizeof(inf));
     inf.iters = h.total;
@@ -1136,18 +1165,14 @@ int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk
     auto body = [&](hipStream_t cs) {
         hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
                            slice);
-        if (op_ == OP_9PT)
-            hipLaunchKernelGGL(k_batched<OP_9PT>, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
-                               nsys, chunk, spin_limit);
-        else
-            hipLaunchKernelGGL(k_batched<OP_7PT>, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob,
-                               nsys, chunk, spin_limit);
+        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
+                           spin_limit);
     };
     GraphRef g;  // held until the launch has completed
     if (graph_) {
         // the table is re-uploaded before every replay, so the key needs only its shape
         std::vector<uintptr_t> key = {0x53u, (uintptr_t)tables_, (uintptr_t)nsys, (uintptr_t)epoch_key,
-                                      (uintptr_t)grid, (uintptr_t)chunk, (uintptr_t)slice, (uintptr_t)op_};
+                                      (uintptr_t)grid, (uintptr_t)chunk, (uintptr_t)slice};
         int rc = cached_graph(key, body, &g);
         if (rc) return rc;
         S7_HIP(hipGraphLaunch(g->exec, st_));
@@ -1169,9 +1194,9 @@ int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk
 // A trial system in the job's workspace; the 9-point operator's two extra
 // working copies are zero (the trial is the 5-point part).
 template <class T>
-static int tune_prepare_job(const EngineJob& j, const s7_options& o, int op, hipStream_t s) {
+static int tune_prepare_job(const EngineJob& j, const s7_options& o, hipStream_t s) {
     const int rc = tune_prepare<T>(make_view<T>(j.d, j.lo, o.jacobi, j.ws), s);
-    if (rc || op != OP_9PT) return rc;
+    if (rc || j.op != OP_9PT) return rc;
     const size_t span = align256(j.lo.n * j.lo.elt);
     const int first = o.jacobi ? 1 : 0;
     S7_HIP(hipMemsetAsync(j.ws + j.lo.off_coef + (size_t)(7 - first) * span, 0, 2 * span, s));
@@ -1188,7 +1213,7 @@ int BatchEngine::tune() {
         }
         total += (double)j->lo.n;
     }
-    const TuneKey key{op_ == OP_9PT ? TUNE_BATCH9 : TUNE_BATCH, jobs_[0]->tag, o_.jacobi, size_bucket(total),
+    const TuneKey key{jobs_[0]->op == OP_9PT ? TUNE_BATCH9 : TUNE_BATCH, jobs_[0]->tag, o_.jacobi, size_bucket(total),
                       size_bucket((double)jobs_.size())};
     int best[4] = {0, 0, 0, 0};
     if (tune_lookup(key, best)) {
@@ -1211,10 +1236,10 @@ int BatchEngine::tune() {
             std::vector<BSys> table;
             long long chunks = 0;
             for (EngineJob* j : jobs_) {
-                if ((rc = S7_BY_PREC(*j, tune_prepare_job)(*j, o_, op_, st_))) break;
+                if ((rc = S7_BY_PREC(*j, tune_prepare_job)(*j, o_, st_))) break;
                 hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, st_,
                                    reinterpret_cast<BCtl*>(j->ws + j->lo.off_ctl), (int)K_P1);
-                const BSys b = sys_entry(*j, o_, op_, chunk, K);
+                const BSys b = sys_entry(*j, o_, chunk, K);
                 chunks += b.nchunk;
                 table.push_back(b);
             }
@@ -1257,7 +1282,7 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
     for (EngineJob* j : jobs_) {
         sptr.push_back(reinterpret_cast<State*>(j->ws + j->lo.off_state));
         if (j->stage != J_NEW) continue;
-        starts.push_back(job_entry(*j, o_, op_));
+        starts.push_back(job_entry(*j, o_));
         max_n = std::max(max_n, j->lo.n);
         j->stage = J_RUN;
     }
@@ -1275,8 +1300,10 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
     }
     // 2) one persistent launch over every resident job
     std::vector<BSys> table;
+    const std::vector<int> chunks = launch_chunks(jobs_, chunk_, grid_cap_, o_.chunk_cells == 0);
+    for (size_t i = 0; i < jobs_.size(); ++i)
+        table.push_back(sys_entry(*jobs_[i], o_, chunks[i], epoch_iters > 0 ? epoch_iters : (1 << 30)));
     const int chunk = chunk_;
-    for (EngineJob* j : jobs_) table.push_back(sys_entry(*j, o_, op_, chunk, epoch_iters > 0 ? epoch_iters : (1 << 30)));
     const long long slice = epoch_iters > 0 ? 0 : (long long)(slice_ms * ticks_per_ms_);
     rc = launch(table, epoch_iters, chunk, grid_cap_, slice);
     if (rc) return rc;
@@ -1286,7 +1313,7 @@ int BatchEngine::step(int epoch_iters, double slice_ms) {
     if (rc) return rc;
     std::vector<EngineJob*> keep;
     for (size_t i = 0; i < jobs_.size(); ++i) {
-        if (h[i].final) finish_job(*jobs_[i], h[i], op_);
+        if (h[i].final) finish_job(*jobs_[i], h[i]);
         else keep.push_back(jobs_[i]);
     }
     jobs_.swap(keep);
@@ -1311,10 +1338,11 @@ template <class Alone>
 static int run_batch(std::vector<EngineJob>& jobs, const std::vector<char>& big, int op, char* w,
                      const s7_options& o, hipStream_t s, s7_info* info, const char* who, Alone alone) {
     const int nsys = (int)jobs.size();
-    BatchEngine eng(w, nsys, o, s, /*use_graph=*/true, op);
+    BatchEngine eng(w, nsys, o, s, /*use_graph=*/true);
     for (int i = 0; i < nsys; ++i) {
         if (big[i]) continue;
         EngineJob& j = jobs[i];
+        j.op = op;
         const int rc = eng.add(&j);
         if (rc) return rc;
     }

@@ -2,7 +2,9 @@
 
 Each system of a batch is checked against the FP64 oracle.  Each system's result
 must not depend on the rest of the batch: solved alone through the same path, it
-comes out bit for bit the same, because its sums run in a fixed per-system order."""
+comes out bit for bit the same, because its sums run in a fixed per-system order
+(per unit of 1024 cells, each unit summed by one wavefront).  Nor may it depend on
+the work-item size (chunk_cells), which the serving loop sizes by load."""
 import numpy as np
 import pytest
 
@@ -57,7 +59,7 @@ def test_uneven_batch_matches_oracle(s7):
         assert abs(info.iters - r8.iters) <= max(3, 0.2 * r8.iters)
 
 
-@pytest.mark.parametrize("chunk", [256, 1024, 4096])
+@pytest.mark.parametrize("chunk", [1024, 4096, 16384])
 def test_alone_equals_in_mix_bitwise(s7, chunk):
     seeds = [200 + i for i in range(len(UNEVEN))]
     probs = make_batch(UNEVEN, seeds)
@@ -66,6 +68,28 @@ def test_alone_equals_in_mix_bitwise(s7, chunk):
         rc1, inf1, x1 = run_batch(s7, [UNEVEN[k]], [probs[k]], rtol=1e-8, chunk_cells=chunk)
         assert np.array_equal(x1[0], xs[k]), k
         assert inf1[0].iters == infos[k].iters
+
+
+def test_result_does_not_depend_on_chunk_size(s7):
+    """Chunks of one unit, of part of a unit group (2048 cells: two of the four
+    wavefronts idle), of one group and of several groups, and the default (chunks
+    halved by load), give the same iterates bit for bit: staged pairs (even nx up to
+    1024), unstaged pairs (nx above 1024), single cells (odd nx), FP32 and BF16+IR."""
+    shapes = [(24, 32, 48), (17, 5, 9), (1030, 6, 4), (96, 48, 24), (2, 1, 1)]
+    probs = make_batch(shapes, [300 + i for i in range(len(shapes))])
+    for prec, rtol in ((0, 1e-8), (1, 1e-10)):
+        runs = [run_batch(s7, shapes, probs, rtol=rtol, prec=prec, chunk_cells=c)
+                for c in (1024, 2048, 4096, 12288, 0)]
+        rc0, inf0, x0 = runs[0]
+        assert rc0 == s7.OK, [i.as_dict() for i in inf0]
+        for rc, infos, xs in runs[1:]:
+            assert rc == rc0
+            for k in range(len(shapes)):
+                assert np.array_equal(xs[k], x0[k]), (prec, k)
+                assert infos[k].iters == inf0[k].iters and infos[k].outer_iters == inf0[k].outer_iters
+        for (p, A, b), x in zip(probs, x0):
+            ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+            assert rel_err(x, ref.x) <= (1e-6 if prec == 0 else 1e-7)
 
 
 def test_batched_iterates_track_oracle(s7):

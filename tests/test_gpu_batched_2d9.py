@@ -66,7 +66,7 @@ def test_uneven_batch_matches_oracle(s7, jacobi):
         assert abs(info.iters - r8.iters) <= max(3, 0.2 * r8.iters)
 
 
-@pytest.mark.parametrize("chunk", [256, 4096])
+@pytest.mark.parametrize("chunk", [1024, 4096])
 def test_alone_equals_in_mix_bitwise(s7, chunk):
     probs = problems9(UNEVEN9, [500 + i for i in range(len(UNEVEN9))])
     rc, infos, xs = run9(s7, UNEVEN9, probs, rtol=1e-8, chunk_cells=chunk)
@@ -75,6 +75,26 @@ def test_alone_equals_in_mix_bitwise(s7, chunk):
         rc1, inf1, x1 = run9(s7, [UNEVEN9[k]], [probs[k]], rtol=1e-8, chunk_cells=chunk)
         assert np.array_equal(x1[0], xs[k]), k
         assert inf1[0].iters == infos[k].iters
+
+
+def test_result_does_not_depend_on_chunk_size(s7):
+    """The 9-point phases keep their sums per unit of 1024 cells too: chunk sizes
+    of one unit, two, one unit group, three groups and the load-sized default give
+    the same iterates bit for bit (staged rows up to 1024 cells, unstaged above)."""
+    shapes = [(129, 33), (300, 200), (1100, 9), (3, 1)]
+    probs = problems9(shapes, [520 + i for i in range(len(shapes))])
+    for prec, rtol in ((0, 1e-8), (1, 1e-10)):
+        runs = [run9(s7, shapes, probs, rtol=rtol, prec=prec, chunk_cells=c) for c in (1024, 2048, 4096, 12288, 0)]
+        rc0, inf0, x0 = runs[0]
+        assert rc0 == s7.OK, [i.as_dict() for i in inf0]
+        for rc, infos, xs in runs[1:]:
+            assert rc == rc0
+            for k in range(len(shapes)):
+                assert np.array_equal(xs[k], x0[k]), (prec, k)
+                assert infos[k].iters == inf0[k].iters
+        for (p, A, b), x in zip(probs, x0):
+            ref = oracle.bicgstab(A, b, tol=1e-12, max_iter=2000)
+            assert rel_err(x, ref.x) <= (1e-6 if prec == 0 else 1e-7)
 
 
 def test_batched_iterates_track_oracle(s7):

@@ -1,11 +1,11 @@
 """GPU tests of 2D 9-point requests in the request queue (section IV's operator in
 the serving form), against the FP64 oracle.
 
-2D requests share the arena, the admission order and the large-request thread
-with 3D requests and run on the queue's second batch engine.  As for 3D, a
-request's result does not depend on what else is resident: served in a mix it
-comes out bit for bit as the batched 2D call computes it alone, and a large
-mesh comes out as from the single-system 2D call."""
+2D requests share the arena, the admission order, the large-request thread and
+the batch engine with 3D requests: one persistent launch runs both operators.
+As for 3D, a request's result does not depend on what else is resident: served
+in a mix it comes out bit for bit as the batched 2D call computes it alone, and a
+large mesh comes out as from the single-system 2D call."""
 import numpy as np
 import pytest
 
@@ -55,9 +55,10 @@ def run_queue(s7, submit_all, arena_bytes, **opt):
 
 @pytest.mark.parametrize("epoch", [0, 5])
 def test_served_2d9_beside_3d_matches_oracle_and_alone(s7, epoch):
-    """2D requests in three precisions, interleaved with 3D requests, with time slices
-    (epoch 0) or 5-iteration epochs and a tight arena: each 2D result matches the oracle
-    and equals the batched 2D call on that request alone; the 3D ones match the oracle."""
+    """2D requests in three precisions, interleaved with 3D requests in the same
+    persistent launches, with time slices (epoch 0) or 5-iteration epochs and a tight
+    arena: each result matches the oracle and equals the batched call of its operator
+    on that request alone (load-sized chunks in the queue, default ones alone)."""
     import torch
     p9 = [problem9(d, 900 + i) for i, (d, pr) in enumerate(MIX9)]
     p3 = [problem(d, seed=950 + i) for i, (d, pr) in enumerate(MIX3)]
@@ -78,7 +79,7 @@ def test_served_2d9_beside_3d_matches_oracle_and_alone(s7, epoch):
                 t.append(s7.queue_submit(q, d, c3[i], b3[i], x3[i], RTOL[pr3], 2000, pr3))
         return t
     big = max(s7.workspace_bytes_2d9(nx, ny, pr) for (nx, ny), pr in MIX9)
-    out = run_queue(s7, submit_all, 3 * big + (4 << 20), graph_iters=epoch, chunk_cells=1024)
+    out = run_queue(s7, submit_all, 3 * big + (4 << 20), graph_iters=epoch)
     assert all(rc == s7.OK for rc, info in out), [info.as_dict() for rc, info in out]
     order = []
     for i in range(len(MIX9)):
@@ -93,7 +94,7 @@ def test_served_2d9_beside_3d_matches_oracle_and_alone(s7, epoch):
         assert rel_err(host(x9[i]), ref.x) <= (1e-6 if pr == 0 else 1e-7), i
         x1 = zeros(A.n)
         rc1, inf1 = s7.bicgstab_solve_batched_2d9([(nx, ny)], [c9[i]], [b9[i]], [x1], [RTOL[pr]], [2000],
-                                                  prec=pr, opt=s7.default_options(chunk_cells=1024))
+                                                  prec=pr)
         torch.cuda.synchronize()
         assert np.array_equal(host(x1), host(x9[i])), i
         assert inf1[0].iters == info.iters and inf1[0].outer_iters == info.outer_iters, i
@@ -101,6 +102,11 @@ def test_served_2d9_beside_3d_matches_oracle_and_alone(s7, epoch):
         p, A, b = p3[i]
         ref = oracle.bicgstab(A, b, tol=1e-13, max_iter=2000)
         assert rel_err(host(x3[i]), ref.x) <= (1e-6 if pr == 0 else 1e-7), i
+        x1 = zeros(A.n)
+        rc1, inf1 = s7.bicgstab_solve_batched([d], [c3[i]], [b3[i]], [x1], [RTOL[pr]], [2000], prec=pr)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(x1), host(x3[i])), i
+        assert inf1[0].iters == res[("3d", i)][1].iters, i
 
 
 def test_large_2d9_requests_take_the_single_system_path(s7):
