@@ -24,10 +24,10 @@ PREC_NAMES = {"fp32": FP32, "bf16_ir": BF16_IR, "fp16_ir": FP16_IR}
 __all__ = [
     "Dims", "Options", "Info", "Request", "lib", "default_options", "last_error", "version",
     "stencil_apply", "workspace_bytes", "bicgstab_solve", "batched_workspace_bytes",
-    "bicgstab_solve_batched", "queue_table_bytes", "queue_create", "queue_submit", "queue_poll", "queue_wait",
-    "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error", "stencil9_apply",
-    "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9", "batched_workspace_bytes_2d9",
-    "bicgstab_solve_batched_2d9", "Request2D9", "queue_submit_2d9", "workspace_bytes_pipelined",
+    "bicgstab_solve_batched", "batched_call", "queue_table_bytes", "queue_create", "queue_submit",
+    "queue_poll", "queue_wait", "queue_destroy", "generate_problem", "bandwidth_probe", "S7Error",
+    "stencil9_apply", "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9",
+    "batched_workspace_bytes_2d9", "bicgstab_solve_batched_2d9", "batched_call_2d9", "Request2D9", "queue_submit_2d9", "workspace_bytes_pipelined",
     "bicgstab_solve_pipelined", "bicgstab_solve_noalloc", "NOALLOC_WS_BYTES",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
@@ -244,9 +244,11 @@ def batched_workspace_bytes(dims_list, prec=FP32, opt: Options | None = None) ->
     return int(lib().s7_batched_workspace_bytes(n, arr, int(prec), C.byref(opt) if opt else None))
 
 
-def bicgstab_solve_batched(dims_list, coefs, bs, xs, rtols, max_iters, prec=FP32, ws=None,
-                           opt: Options | None = None, stream=None):
-    """Solves len(dims_list) systems in one persistent launch.  Returns (status, [Info])."""
+def batched_call(dims_list, coefs, bs, xs, rtols, max_iters, prec=FP32, ws=None,
+                 opt: Options | None = None, stream=None):
+    """Marshals the arguments of s7_bicgstab_solve_batched once and returns a function
+    that makes the call and returns (status, [Info]).  The arrays must stay alive and
+    in place while the function is used (for callers that repeat a batch)."""
     n = len(dims_list)
     arr = (Dims * n)(*[_dims(d) for d in dims_list])
     cp = (_vp * (7 * n))(*[_ptr(c) for cs in coefs for c in cs])
@@ -258,10 +260,20 @@ def bicgstab_solve_batched(dims_list, coefs, bs, xs, rtols, max_iters, prec=FP32
     nbytes = batched_workspace_bytes(dims_list, prec, opt)
     ws = _workspace(nbytes, ws)
     wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
-    rc = lib().s7_bicgstab_solve_batched(n, arr, cp, bp, xp, rt, mi, int(prec), _ptr(ws), wsb,
-                                         C.byref(opt) if opt else None, infos, _stream(stream))
-    _check(rc)
-    return rc, list(infos)
+    fn, wsp, ob, st = lib().s7_bicgstab_solve_batched, _ptr(ws), C.byref(opt) if opt else None, _stream(stream)
+
+    def call():
+        rc = fn(n, arr, cp, bp, xp, rt, mi, int(prec), wsp, wsb, ob, infos, st)
+        _check(rc)
+        return rc, list(infos)
+    call.keep = (arr, cp, bp, xp, rt, mi, infos, ws, opt)
+    return call
+
+
+def bicgstab_solve_batched(dims_list, coefs, bs, xs, rtols, max_iters, prec=FP32, ws=None,
+                           opt: Options | None = None, stream=None):
+    """Solves len(dims_list) systems in one persistent launch.  Returns (status, [Info])."""
+    return batched_call(dims_list, coefs, bs, xs, rtols, max_iters, prec, ws, opt, stream)()
 
 
 def queue_table_bytes() -> int:
@@ -361,10 +373,10 @@ def batched_workspace_bytes_2d9(meshes, prec=FP32, opt: Options | None = None) -
     return int(lib().s7_batched_workspace_bytes_2d9(n, nx, ny, int(prec), C.byref(opt) if opt else None))
 
 
-def bicgstab_solve_batched_2d9(meshes, coefs, bs, xs, rtols, max_iters, prec=FP32, ws=None,
-                               opt: Options | None = None, stream=None):
-    """Solves len(meshes) 2D 9-point systems in one persistent launch; meshes is a
-    list of (nx, ny), coefs a list of nine arrays each.  Returns (status, [Info])."""
+def batched_call_2d9(meshes, coefs, bs, xs, rtols, max_iters, prec=FP32, ws=None,
+                     opt: Options | None = None, stream=None):
+    """Marshals the arguments of s7_bicgstab_solve_batched_2d9 once and returns a
+    function that makes the call and returns (status, [Info]) (see batched_call)."""
     n, nx, ny = _sides(meshes)
     if any(len(cs) != 9 for cs in coefs):
         raise ValueError("need 9 coefficient arrays per system: diag, w, e, s, n, sw, se, nw, ne")
@@ -377,10 +389,21 @@ def bicgstab_solve_batched_2d9(meshes, coefs, bs, xs, rtols, max_iters, prec=FP3
     nbytes = batched_workspace_bytes_2d9(meshes, prec, opt)
     ws = _workspace(nbytes, ws)
     wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
-    rc = lib().s7_bicgstab_solve_batched_2d9(n, nx, ny, cp, bp, xp, rt, mi, int(prec), _ptr(ws), wsb,
-                                             C.byref(opt) if opt else None, infos, _stream(stream))
-    _check(rc)
-    return rc, list(infos)
+    fn, wsp, ob, st = lib().s7_bicgstab_solve_batched_2d9, _ptr(ws), C.byref(opt) if opt else None, _stream(stream)
+
+    def call():
+        rc = fn(n, nx, ny, cp, bp, xp, rt, mi, int(prec), wsp, wsb, ob, infos, st)
+        _check(rc)
+        return rc, list(infos)
+    call.keep = (nx, ny, cp, bp, xp, rt, mi, infos, ws, opt)
+    return call
+
+
+def bicgstab_solve_batched_2d9(meshes, coefs, bs, xs, rtols, max_iters, prec=FP32, ws=None,
+                               opt: Options | None = None, stream=None):
+    """Solves len(meshes) 2D 9-point systems in one persistent launch; meshes is a
+    list of (nx, ny), coefs a list of nine arrays each.  Returns (status, [Info])."""
+    return batched_call_2d9(meshes, coefs, bs, xs, rtols, max_iters, prec, ws, opt, stream)()
 
 
 def queue_submit_2d9(q: int, nx: int, ny: int, coef, b, x, rtol, max_iter, prec=FP32) -> int:

@@ -576,36 +576,52 @@ __device__ void chunk_staged(const SysView<T>& S, int c0, int c1, float alpha, f
         if (u0 >= t1) continue;  // the same for the whole wavefront
         const int u1 = min(t1, u0 + kUnitCells);
         double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int u = 0; u < kUnitCells / (2 * kWave); ++u) {
-            const int idx = u0 + 2 * (u * kWave + lane_id());
-            if (idx >= u1) break;
-            int db, dt;
-            z_offsets(idx, S.m, db, dt);
-            F2 vb, vt;
-            if (P2) {
-                const F2 rb = cload2(S.r + idx + db), sb = cload2(S.s + idx + db);
-                const F2 rt = cload2(S.r + idx + dt), st = cload2(S.s + idx + dt);
-                vb = F2{fmaT(-alpha, sb.a, rb.a), fmaT(-alpha, sb.b, rb.b)};
-                vt = F2{fmaT(-alpha, st.a, rt.a), fmaT(-alpha, st.b, rt.b)};
-            } else {
-                vb = cload2(S.p + idx + db);
-                vt = cload2(S.p + idx + dt);
+        // kSP pairs per lane and step, all their loads issued before any store;
+        // a lane past the unit's end works on the unit's first pair and keeps
+        // nothing
+        constexpr int kSP = 2;
+        for (int u = 0; u < kUnitCells / (2 * kWave); u += kSP) {
+            int idx[kSP];
+            bool own[kSP];
+            Nbr<float> v0[kSP], v1[kSP];
+            Coefs<float, UNIT> k0[kSP], k1[kSP];
+            F2 rh[kSP];
+#pragma unroll
+            for (int w = 0; w < kSP; ++w) {
+                const int i = u0 + 2 * ((u + w) * kWave + lane_id());
+                own[w] = i < u1;
+                idx[w] = own[w] ? i : u0;
+                int db, dt;
+                z_offsets(idx[w], S.m, db, dt);
+                F2 vb, vt;
+                if (P2) {
+                    const F2 rb = cload2(S.r + idx[w] + db), sb = cload2(S.s + idx[w] + db);
+                    const F2 rt = cload2(S.r + idx[w] + dt), st = cload2(S.s + idx[w] + dt);
+                    vb = F2{fmaT(-alpha, sb.a, rb.a), fmaT(-alpha, sb.b, rb.b)};
+                    vt = F2{fmaT(-alpha, st.a, rt.a), fmaT(-alpha, st.b, rt.b)};
+                } else {
+                    vb = cload2(S.p + idx[w] + db);
+                    vt = cload2(S.p + idx[w] + dt);
+                }
+                lds_nbr2(sm, idx[w] - lo, nx, vb, vt, v0[w], v1[w]);
+                load_coefs2_nt<T, UNIT>(S.c, idx[w], k0[w], k1[w]);
+                rh[w] = cload2(S.rhat + idx[w]);
             }
-            Nbr<float> v0, v1;
-            lds_nbr2(sm, idx - lo, nx, vb, vt, v0, v1);
-            Coefs<float, UNIT> k0, k1;
-            load_coefs2_nt<T, UNIT>(S.c, idx, k0, k1);
-            const F2 rh = cload2(S.rhat + idx);
-            const Cell none{};
-            const T o0 = from_f32<T>(apply7<float, float, UNIT, false>(k0, v0, none));
-            const T o1 = from_f32<T>(apply7<float, float, UNIT, false>(k1, v1, none));
-            if (P2) {
-                cstore2(S.y + idx, o0, o1);
-                acc_p2f(acc, (double)v0.c, (double)to_f32(o0), (double)rh.a);
-                acc_p2f(acc, (double)v1.c, (double)to_f32(o1), (double)rh.b);
-            } else {
-                cstore2(S.s + idx, o0, o1);
-                acc[0] = fma((double)rh.b, (double)to_f32(o1), fma((double)rh.a, (double)to_f32(o0), acc[0]));
+#pragma unroll
+            for (int w = 0; w < kSP; ++w) {
+                const Cell none{};
+                const T o0 = from_f32<T>(apply7<float, float, UNIT, false>(k0[w], v0[w], none));
+                const T o1 = from_f32<T>(apply7<float, float, UNIT, false>(k1[w], v1[w], none));
+                if (!own[w]) continue;
+                if (P2) {
+                    cstore2(S.y + idx[w], o0, o1);
+                    acc_p2f(acc, (double)v0[w].c, (double)to_f32(o0), (double)rh[w].a);
+                    acc_p2f(acc, (double)v1[w].c, (double)to_f32(o1), (double)rh[w].b);
+                } else {
+                    cstore2(S.s + idx[w], o0, o1);
+                    acc[0] = fma((double)rh[w].b, (double)to_f32(o1),
+                                 fma((double)rh[w].a, (double)to_f32(o0), acc[0]));
+                }
             }
         }
         unit_done<P2 ? 5 : 1, 0u>(acc, part, u0 / kUnitCells);
@@ -617,26 +633,43 @@ __device__ void chunk_staged(const SysView<T>& S, int c0, int c1, float alpha, f
 template <class T, bool QR>
 __device__ void chunk_p3_b(const SysView<T>& S, int c0, int c1, float alpha, float omega,
                            float beta, double (&acc)[kMaxDots]) {
-    // pairs of cells (c0 is even), then a last odd cell if c1 is odd
+    // pairs of cells (c0 is even), then a last odd cell if c1 is odd; lane l
+    // takes pairs l, l + 64, ... in that order, two per step with all loads of
+    // the step issued before any store (a second pair past the end is the
+    // first one again and keeps nothing)
     const int c1e = c0 + ((c1 - c0) & ~1);
-    for (int i = c0 + 2 * lane_id(); i < c1e; i += 2 * kWave) {
-        const F2 d2 = cload2(S.d + i), p2 = cload2(S.p + i), s2 = cload2(S.s + i), y2 = cload2(S.y + i),
-                 h2 = cload2(S.rhat + i);
-        F2 q2 = cload2((QR ? S.r : S.q) + i);
-        if (QR) {
-            q2.a = fmaT(-alpha, s2.a, q2.a);
-            q2.b = fmaT(-alpha, s2.b, q2.b);
+    for (int i0 = c0 + 2 * lane_id(); i0 < c1e; i0 += 4 * kWave) {
+        const int i1 = i0 + 2 * kWave;
+        const bool own1 = i1 < c1e;
+        const int ii[2] = {i0, own1 ? i1 : i0};
+        F2 d2[2], p2[2], s2[2], y2[2], h2[2], q2[2];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int i = ii[w];
+            d2[w] = cload2(S.d + i), p2[w] = cload2(S.p + i), s2[w] = cload2(S.s + i);
+            y2[w] = cload2(S.y + i), h2[w] = cload2(S.rhat + i);
+            q2[w] = cload2((QR ? S.r : S.q) + i);
         }
-        float da = d2.a, db = d2.b;
-        T ra, pa, rb, pb;
-        p3_math<T>(alpha, omega, beta, p2.a, s2.a, y2.a, q2.a, da, ra, pa);
-        p3_math<T>(alpha, omega, beta, p2.b, s2.b, y2.b, q2.b, db, rb, pb);
-        cstore2(S.d + i, da, db);
-        cstore2(S.r + i, ra, rb);
-        cstore2(S.p + i, pa, pb);
-        const double xa = (double)to_f32(ra), xb = (double)to_f32(rb);
-        acc[0] = fma((double)h2.b, xb, fma((double)h2.a, xa, acc[0]));
-        acc[1] = fma(xb, xb, fma(xa, xa, acc[1]));
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            if (w == 1 && !own1) break;
+            const int i = ii[w];
+            F2 q = q2[w];
+            if (QR) {
+                q.a = fmaT(-alpha, s2[w].a, q.a);
+                q.b = fmaT(-alpha, s2[w].b, q.b);
+            }
+            float da = d2[w].a, db = d2[w].b;
+            T ra, pa, rb, pb;
+            p3_math<T>(alpha, omega, beta, p2[w].a, s2[w].a, y2[w].a, q.a, da, ra, pa);
+            p3_math<T>(alpha, omega, beta, p2[w].b, s2[w].b, y2[w].b, q.b, db, rb, pb);
+            cstore2(S.d + i, da, db);
+            cstore2(S.r + i, ra, rb);
+            cstore2(S.p + i, pa, pb);
+            const double xa = (double)to_f32(ra), xb = (double)to_f32(rb);
+            acc[0] = fma((double)h2[w].b, xb, fma((double)h2[w].a, xa, acc[0]));
+            acc[1] = fma(xb, xb, fma(xa, xa, acc[1]));
+        }
     }
     for (int i = c1e + lane_id(); i < c1; i += kWave) {
         float dv = cload(S.d + i);
@@ -928,20 +961,43 @@ __device__ void chunk_staged9(const SysView<T>& S, const Coef9T<T>& k, int c0, i
         if (u0 >= t1) continue;  // the same for the whole wavefront
         const int u1 = min(t1, u0 + kUnitCells);
         double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int u = 0; u < kUnitCells / kWave; ++u) {
-            const int idx = u0 + u * kWave + lane_id();
-            if (idx >= u1) break;
-            const int L = idx - lo;
-            const float v[9] = {sm[L], sm[L - 1], sm[L + 1], sm[L - nx], sm[L + nx],
-                                sm[L - nx - 1], sm[L - nx + 1], sm[L + nx - 1], sm[L + nx + 1]};
-            const T rh = cload(S.rhat + idx);
-            const T o = from_f32<T>(apply9_work<T, UNIT>(k, idx, v));
-            if (P2) {
-                cstore(S.y + idx, o);
-                acc_p2f(acc, (double)v[0], (double)to_f32(o), (double)to_f32(rh));
-            } else {
-                cstore(S.s + idx, o);
-                acc[0] = fma((double)to_f32(rh), (double)to_f32(o), acc[0]);
+        // two cells per lane and step, their coefficient and r0 loads issued
+        // before any store; a lane past the unit's end works on the unit's
+        // first cell and keeps nothing
+        constexpr int kSC = 2;
+        for (int u = 0; u < kUnitCells / kWave; u += kSC) {
+            int idx[kSC];
+            bool own[kSC];
+            float kc[kSC][9];
+            T rh[kSC];
+#pragma unroll
+            for (int w = 0; w < kSC; ++w) {
+                const int i = u0 + (u + w) * kWave + lane_id();
+                own[w] = i < u1;
+                idx[w] = own[w] ? i : u0;
+                kc[w][0] = UNIT ? 1.0f : to_f32(ld_nt(k.c[0] + idx[w]));
+#pragma unroll
+                for (int a = 1; a < 9; ++a) kc[w][a] = to_f32(ld_nt(k.c[a] + idx[w]));
+                rh[w] = cload(S.rhat + idx[w]);
+            }
+#pragma unroll
+            for (int w = 0; w < kSC; ++w) {
+                const int L = idx[w] - lo;
+                const float v[9] = {sm[L], sm[L - 1], sm[L + 1], sm[L - nx], sm[L + nx],
+                                    sm[L - nx - 1], sm[L - nx + 1], sm[L + nx - 1], sm[L + nx + 1]};
+                // the terms in the order of apply9_work
+                float a9 = UNIT ? v[0] : kc[w][0] * v[0];
+#pragma unroll
+                for (int a = 1; a < 9; ++a) a9 = fma9(kc[w][a], v[a], a9);
+                const T o = from_f32<T>(a9);
+                if (!own[w]) continue;
+                if (P2) {
+                    cstore(S.y + idx[w], o);
+                    acc_p2f(acc, (double)v[0], (double)to_f32(o), (double)to_f32(rh[w]));
+                } else {
+                    cstore(S.s + idx[w], o);
+                    acc[0] = fma((double)to_f32(rh[w]), (double)to_f32(o), acc[0]);
+                }
             }
         }
         unit_done<P2 ? 5 : 1, 0u>(acc, part, u0 / kUnitCells);

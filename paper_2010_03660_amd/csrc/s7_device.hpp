@@ -475,9 +475,16 @@ __device__ __forceinline__ double comb(int j, double a, double b) {
 // l+128, l+192, in that order) and reduces the wavefront with DPP.  Only one
 // wavefront of the four runs the DPP sequence.  out is written in thread 0
 // only; the other threads' out is left as it was.
+// The LDS of block_reduce, one array per kernel whatever instantiations of
+// block_reduce the kernel uses.
+__device__ __forceinline__ double (*reduce_lds())[kThreads] {
+    __shared__ double sm[kMaxDots][kThreads];
+    return sm;
+}
+
 template <int ND, unsigned MAXMASK>
 __device__ __forceinline__ void block_reduce(double (&acc)[ND], double (&out)[ND]) {
-    __shared__ double sm[kMaxDots][kThreads];
+    double (*sm)[kThreads] = reduce_lds();
     __syncthreads();  // the previous use of sm is over
 #pragma unroll
     for (int j = 0; j < ND; ++j) sm[j][threadIdx.x] = acc[j];

@@ -982,13 +982,38 @@ size_t engine_table_bytes(int capacity) {
 
 static int chunk_cells_of(const s7_options& o);
 
+// Pinned host buffers for the engines' state reads, kept for the life of the
+// process: every batched call builds an engine, and pinning fresh host memory
+// for each call cost more than the call's other host work.
+static std::mutex g_pinned_mu;
+static std::vector<std::pair<size_t, void*>> g_pinned_free;
+
+static void* pinned_take(size_t bytes) {
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        for (size_t i = 0; i < g_pinned_free.size(); ++i) {
+            if (g_pinned_free[i].first >= bytes) {
+                void* p = g_pinned_free[i].second;
+                g_pinned_free.erase(g_pinned_free.begin() + (long)i);
+                return p;
+            }
+        }
+    }
+    void* p = nullptr;
+    return hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess ? p : nullptr;
+}
+
+static void pinned_give(void* p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    g_pinned_free.emplace_back(bytes, p);
+}
+
 BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStream_t stream,
                          bool use_graph)
     : tables_(tables), cap_(capacity), o_(o), st_(stream), graph_(use_graph),
       chunk_(chunk_cells_of(o)), grid_cap_(1024) {
-    if (hipHostMalloc((void**)&host_states_, (size_t)capacity * sizeof(State), hipHostMallocDefault) !=
-        hipSuccess)
-        host_states_ = nullptr;  // read_states reports it
+    host_states_ = static_cast<State*>(pinned_take((size_t)capacity * sizeof(State)));  // null: read_states reports it
     int dev = 0, khz = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
@@ -996,7 +1021,7 @@ BatchEngine::BatchEngine(char* tables, int capacity, const s7_options& o, hipStr
 }
 
 BatchEngine::~BatchEngine() {
-    if (host_states_) (void)hipHostFree(host_states_);
+    pinned_give(host_states_, (size_t)cap_ * sizeof(State));
 }
 
 static double now_ms() {
@@ -1232,7 +1257,7 @@ int BatchEngine::tune() {
     best[1] = grid_cap_;
     int rc = S7_OK;
     for (int chunk : {1024, 2048, 4096, 8192, 16384, 32768, 65536}) {
-        for (int gcap : {1024, 2048}) {
+        for (int gcap : {256, 512, 768, 1024}) {
             std::vector<BSys> table;
             long long chunks = 0;
             for (EngineJob* j : jobs_) {
@@ -1244,7 +1269,7 @@ int BatchEngine::tune() {
                 table.push_back(b);
             }
             if (rc) break;
-            if (gcap > 1024 && chunks <= 1024) continue;  // same grid as the smaller cap
+            if (gcap > 256 && chunks <= gcap / 2) continue;  // about the same grid as a smaller cap
             if (hipEventRecord(e0, st_) != hipSuccess) { rc = S7_EHIP; break; }
             if ((rc = launch(table, K, chunk, gcap))) break;
             if (hipEventRecord(e1, st_) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
@@ -1253,6 +1278,10 @@ int BatchEngine::tune() {
             }
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
+            char line[160];
+            std::snprintf(line, sizeof line, "batch op=%d tag=%d systems=%d chunk_cells=%d grid_cap=%d ms=%.4f",
+                          jobs_[0]->op, jobs_[0]->tag, (int)jobs_.size(), chunk, gcap, ms);
+            tune_log(line);
             if (ms < best_ms) {
                 best_ms = ms;
                 best[0] = chunk;
