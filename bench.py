@@ -56,8 +56,8 @@ KERNEL = {
     3: {"p1": "k_p1_pair (P1 on x-adjacent cell pairs: s = A p, (r0,s))",
         "p2": "k_p2f_pair (P2 on cell pairs: y = A q with q = r - alpha s on the fly, five dot products)",
         "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"},
-    5: {"p1": "k_p1_lds (P1, p of a 4096-cell tile and one row either side staged in LDS: s = A p, (r0,s))",
-        "p2": "k_p2f_lds (P2, q = r - alpha s of a 4096-cell tile and one row either side staged in LDS: "
+    5: {"p1": "k_p1_lds (P1, p of a tile and one row either side staged in LDS: s = A p, (r0,s))",
+        "p2": "k_p2f_lds (P2, q = r - alpha s of a tile and one row either side staged in LDS: "
               "y = A q, five dot products)",
         "p3": "k_p3 (P3: x, r, p updates, (r0,r), (r,r))"},
 }
@@ -78,20 +78,22 @@ def kernel_source_hash() -> str:
 
 
 def traffic_from_profile(n_cells: int, kernel: str, schedule: int, lds_tile: int = 0, xcd_run: int = 0):
-    """HBM bytes per launch of pass `kernel` from the committed counter summary, if it was
-    taken with the same launch parameters (schedule, staged tile, XCD tile order) and the
-    kernel sources have not changed since."""
+    """HBM bytes per launch of pass `kernel` from the committed counter summary: the
+    record of the form this run used (schedule, staged tile, XCD tile order), if the
+    kernel sources have not changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_paper600x595x1536_traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if (t.get("source_hash") != kernel_source_hash() or t.get("cells") != n_cells
-            or t.get("schedule") != schedule or t.get("lds_tile", 0) != lds_tile
-            or t.get("xcd_run", 0) != xcd_run):
+    if t.get("source_hash") != kernel_source_hash() or t.get("cells") != n_cells:
         return None
-    return t.get("bytes_per_launch")
+    for form in t.get("forms", []):
+        if (form.get("schedule") == schedule and form.get("lds_tile", 0) == lds_tile
+                and form.get("xcd_run", 0) == xcd_run):
+            return form.get("bytes_per_launch")
+    return None
 
 
 def host_cores() -> int:

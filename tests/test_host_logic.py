@@ -54,8 +54,8 @@ def test_bench_refuses_several_gpus():
 
 
 def test_traffic_is_reported_only_for_current_kernels(tmp_path, monkeypatch):
-    """bench.py reads the committed counter summary only when it was taken on the same
-    schedule, mesh and kernel sources."""
+    """bench.py reads the committed counter summary only for the form the run used
+    (schedule, staged tile, XCD tile order), on the same mesh and kernel sources."""
     sys.path.insert(0, ROOT)
     import bench
     prof = tmp_path / "profiles"
@@ -66,10 +66,14 @@ def test_traffic_is_reported_only_for_current_kernels(tmp_path, monkeypatch):
         os.makedirs(os.path.dirname(tmp_path / f), exist_ok=True)
         (tmp_path / f).write_bytes(open(os.path.join(ROOT, f), "rb").read())
     n = 548352000
-    rec = {"cells": n, "schedule": 3, "source_hash": bench.kernel_source_hash(),
-           "bytes_per_launch": 123.0}
+    rec = {"cells": n, "source_hash": bench.kernel_source_hash(),
+           "forms": [{"schedule": 3, "bytes_per_launch": 123.0},
+                     {"schedule": 5, "lds_tile": 2048, "xcd_run": -1, "bytes_per_launch": 456.0}]}
     (prof / "p2_paper600x595x1536_traffic.json").write_text(json.dumps(rec))
     assert bench.traffic_from_profile(n, "p2", 3) == 123.0
+    assert bench.traffic_from_profile(n, "p2", 5, 2048, -1) == 456.0
+    assert bench.traffic_from_profile(n, "p2", 5, 2048, 1) is None  # another tile order
+    assert bench.traffic_from_profile(n, "p2", 5, 4096, -1) is None  # another tile
     assert bench.traffic_from_profile(n, "p2", 1) is None  # another schedule
     assert bench.traffic_from_profile(n // 2, "p2", 3) is None  # another mesh
     assert bench.traffic_from_profile(n, "p1", 3) is None  # no summary
