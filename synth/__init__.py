@@ -164,9 +164,14 @@ COEF_NAMES_2D9 = ("diag", "w", "e", "s", "n", "sw", "se", "nw", "ne")
 PAPER_MESHES_2D9 = ((4800, 4800), (22800, 22800))  # the sizes section IV names
 
 
-def make_problem_2d9(nx: int, ny: int, seed: int = 0) -> Problem:
-    """Coefficients (diag, w, e, s, n, sw, se, nw, ne) and x* of the 2D 9-point recipe."""
-    cells = np.arange(nx * ny, dtype=np.int64)
+def make_problem_2d9(nx: int, ny: int, seed: int = 0, rows=None) -> Problem:
+    """Coefficients (diag, w, e, s, n, sw, se, nw, ne) and x* of the 2D 9-point recipe, on the
+    whole mesh or on the y-rows listed (every value depends only on its cell's global index)."""
+    if rows is None:
+        cells = np.arange(nx * ny, dtype=np.int64)
+    else:
+        cells = np.concatenate([np.arange(nx, dtype=np.int64) + nx * int(j) for j in rows]) if len(rows) else \
+            np.zeros(0, dtype=np.int64)
     offs = [offdiag_base(seed, aid, cells) for aid in AID_2D9]
     acc = np.zeros(cells.shape, dtype=np.float64)
     for c in offs:

@@ -174,31 +174,44 @@ def test_mixed_precision_refinement(s7, prec, dims):
     assert info.status == s7.OK and np.all(host(x0) == 0)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16_ir"])
 @pytest.mark.parametrize("side", [4800, 22800])
-def test_paper_sizes_manufactured_solution(s7, side):
-    """The two sizes section IV names, in the launch configuration the bench times."""
+def test_paper_sizes_manufactured_solution(s7, side, prec):
+    """The two sizes section IV names, in the launch configuration the bench times,
+    FP32 and BF16 storage inside FP64 refinement.  The oracle cannot hold the 22800^2
+    system, so the whole solution is checked against the manufactured x* on the device,
+    and on 21 sampled rows (0, 1, ny/2, ny-2, ny-1 and 16 seeded others) the oracle
+    computes the FP64 residual b - A x of the GPU's x (the CSR of rows j-1..j+1 is exact
+    on row j)."""
     import torch
     nx = ny = side
     n = nx * ny
+    p = s7.PREC_NAMES[prec]
+    rtol, err_bound, res_bound = (1e-8, 1e-6, 2e-6) if p == s7.FP32 else (1e-10, 1e-8, 1e-9)
     c = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(9)]
     xs = torch.empty(n, dtype=torch.float64, device="cuda")
     b = torch.empty(n, dtype=torch.float64, device="cuda")
     s7.generate_problem_2d9(nx, ny, 0, c, xs, b)
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
-    info = s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-8, 1000)
+    info = s7.bicgstab_solve_2d9(nx, ny, c, b, x, rtol, 1000, prec=p)
     torch.cuda.synchronize()
-    # FP32 storage: the true residual floors near 1e-7; with this weakly diagonally
-    # dominant operator (diag = sum |off| + 0.1, |off| >= 0.5) the error is a few times that
-    assert info.status == s7.OK and info.rel_res_true <= 1e-6
+    assert info.status == s7.OK, info.as_dict()
+    # FP32 storage: the true residual floors near 2e-7 and the error against x* sits near
+    # 6e-7 at both sizes; refinement takes both far below
     err = float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))
-    assert err <= 1e-5, err
-    # (b - A x)_i from the definition at a few sampled rows, gathered from the device
-    rows = [0, 1, nx - 1, nx, n // 2 + 17, n - nx, n - 1]
-    offs = ((0, 0), (-1, 0), (1, 0), (0, -1), (0, 1), (-1, -1), (1, -1), (-1, 1), (1, 1))
-    for r in rows:
-        i, j = r % nx, r // nx
-        acc = 0.0
-        for a, (di, dj) in enumerate(offs):
-            if 0 <= i + di < nx and 0 <= j + dj < ny:
-                acc += float(c[a][r]) * float(x[(i + di) + nx * (j + dj)])
-        assert abs(float(b[r]) - acc) <= 1e-5 * abs(float(b[r])) + 1e-5
+    assert err <= err_bound, err
+    del c, b
+    rows = synth.sample_planes(ny, 16, seed=0)
+    assert len(rows) == 21
+    for j in rows:
+        band = [q for q in (j - 1, j, j + 1) if 0 <= q < ny]
+        prob = synth.make_problem_2d9(nx, ny, seed=0, rows=band)
+        A = oracle.build_csr_2d9(nx, len(band), prob.coef)
+        kk = band.index(j)
+        r0, r1 = kk * nx, (kk + 1) * nx
+        bj = oracle.spmv_rows(A, prob.xstar, r0, r1)  # b on row j, in FP64
+        xj = host(x[band[0] * nx:(band[-1] + 1) * nx])
+        rj = bj - oracle.spmv_rows(A, xj, r0, r1)
+        rel = float(np.linalg.norm(rj) / np.linalg.norm(bj))
+        assert rel <= res_bound, (j, rel)
+        assert rel_err(xj[r0:r1], prob.xstar[r0:r1]) <= 10 * err_bound, j

@@ -127,3 +127,24 @@ def test_recipe_is_diagonally_dominant_and_seeded():
     assert all(np.array_equal(a, b) for a, b in zip(p.coef, q.coef))
     r = synth.make_problem_2d9(9, 7, seed=4)
     assert not np.array_equal(p.coef[1], r.coef[1])
+
+
+def test_row_bands_of_the_recipe_and_their_products(oracle_mod):
+    """The recipe on a band of y-rows equals those rows of the whole mesh, and the
+    9-point CSR of rows j-1..j+1 gives row j of the whole mesh's product exactly (the
+    check the paper-size GPU tests make on sampled rows)."""
+    nx, ny = 13, 9
+    full = synth.make_problem_2d9(nx, ny, seed=7)
+    A = oracle_mod.build_csr_2d9(nx, ny, full.coef)
+    v = np.random.default_rng(3).standard_normal(nx * ny)
+    Av = oracle_mod.spmv(A, v)
+    for j in (0, 1, 4, ny - 2, ny - 1):
+        band = [q for q in (j - 1, j, j + 1) if 0 <= q < ny]
+        sub = synth.make_problem_2d9(nx, ny, seed=7, rows=band)
+        lo, hi = band[0] * nx, (band[-1] + 1) * nx
+        assert all(np.array_equal(c, f[lo:hi]) for c, f in zip(sub.coef, full.coef))
+        assert np.array_equal(sub.xstar, full.xstar[lo:hi])
+        Ab = oracle_mod.build_csr_2d9(nx, len(band), sub.coef)
+        kk = band.index(j)
+        row = oracle_mod.spmv_rows(Ab, v[lo:hi], kk * nx, (kk + 1) * nx)
+        assert np.array_equal(row, Av[j * nx:(j + 1) * nx]), j
