@@ -24,8 +24,8 @@
  *
  * Memory.  Every array argument is a DEVICE pointer owned by the caller, for
  * example a PyTorch tensor.  The library allocates no device memory of its
- * own (the batch engine keeps a small pinned host buffer for reading its
- * states).  Scratch comes from a caller-provided workspace of the size that
+ * own (the batch engine reads its states through small pinned host
+ * buffers, kept for the life of the process).  Scratch comes from a caller-provided workspace of the size that
  * s7_workspace_bytes() reports, 256-byte aligned.
  *
  * Streams.  `stream` is a hipStream_t passed as void*; 0 means the null
@@ -94,8 +94,11 @@ typedef struct {
     int32_t stream_blocks;  /* workgroups of the streaming passes; 0 = auto (at most 256);
                                capped at 1024 */
     int32_t chunk_cells;    /* batched/queue: cells per work item of the persistent
-                               kernel, rounded up to a multiple of 256, at most 2^24;
-                               0 = 16384 */
+                               kernel, rounded up to a multiple of 1024, at most 2^24;
+                               0 = 16384, with the chunks of small systems halved (down
+                               to 4096 cells, up to 64 chunks) while the resident set
+                               has fewer work items than the grid has workgroups.  No
+                               result depends on it. */
     int32_t profile;        /* 1: launch without graphs, time every pass with HIP
                                events into s7_info.pass_ms */
     int32_t inner_max_iter; /* IR: inner iteration cap per outer step; 0 = 100 */
@@ -252,10 +255,11 @@ size_t s7_batched_workspace_bytes(int32_t nsys, const s7_dims *d, int32_t prec,
  * info, if not NULL, is an array of nsys and receives each system's result.
  * All systems use precision prec.  The whole of each solve runs on the
  * device: the iterations (three phases each), and the refinement steps or the
- * FP32 epilogue.  Each system's iterates depend only on that system and on
- * chunk_cells (the work-item size, which fixes its summation order), never
- * on the rest of the batch.  With opt->tune = 1 and chunk_cells = 0 the
- * work-item size and the persistent grid are autotuned per size class.
+ * FP32 epilogue.  Each system's sums are kept per unit of 1024 of its cells,
+ * so its iterates depend only on that system: not on the rest of the batch,
+ * nor on chunk_cells (the work-item size).  With opt->tune = 1 and
+ * chunk_cells = 0 the work-item size and the persistent grid are autotuned
+ * per size class.
  * A system of split_cells cells or more (default 2^21) is solved on its own
  * by the multi-kernel path of s7_bicgstab_solve, in its slice of the
  * workspace, after the shared launch; its iterates are those of
@@ -358,8 +362,9 @@ int s7_queue_submit(s7_queue *q, const s7_request *req, uint64_t *ticket);
 /*
  * The same for a 2D 9-point request (section IV's operator, solved as by
  * s7_bicgstab_solve_2d9).  It shares the arena, the admission order and the
- * tickets with 3D requests; small ones run on the queue's second batch
- * engine, meshes of split_cells cells or more on the large-request thread.
+ * tickets with 3D requests; small ones run in the same persistent launches
+ * as the 3D requests, meshes of split_cells cells or more on the
+ * large-request thread.
  * Its workspace is s7_workspace_bytes_2d9 of its mesh and precision.
  */
 int s7_queue_submit_2d9(s7_queue *q, const s7_request_2d9 *req, uint64_t *ticket);
@@ -467,9 +472,9 @@ size_t s7_batched_workspace_bytes_2d9(int32_t nsys, const int32_t *nx, const int
  * nsys: nx[s], ny[s]; coef[9*s + c], device float arrays in the order
  * {diag, w, e, s, n, sw, se, nw, ne}; b[s] and x[s], device doubles; rtol[s];
  * max_iter[s].  info, if not NULL, is an array of nsys.  Each iteration is
- * three phases (P1, P2 with the five sums, P3), one cell per thread; the
- * refinement steps or the FP32 epilogue also run on the device.  A system's
- * iterates depend only on that system and chunk_cells.  A mesh of
+ * three phases (P1, P2 with the five sums, P3); the refinement steps or the
+ * FP32 epilogue also run on the device.  A system's iterates depend only on
+ * that system.  A mesh of
  * split_cells cells or more (default 2^21) is solved alone by
  * s7_bicgstab_solve_2d9 after the shared launch.  Returns as
  * s7_bicgstab_solve_batched.
