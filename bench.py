@@ -42,6 +42,11 @@ BYTES = {
     ("16", 4): {"p1": 18, "p2a": 6, "p2b": 18, "p3": 22},
 }
 SLOT = {"p1": 0, "p2a": 1, "p2": 2, "p2b": 2, "p3": 3}
+# Bytes per cell that an FP32 solve moves once, outside its iterations (Jacobi mode): the
+# scaled coefficient copies (7 read, 6 written), r0 = b - A x0 in FP64 (7 coefficients, b,
+# x; r, r0, p, d written), x += d in FP64, and the FP64 true residual at exit.
+SETUP_BYTES_FP32 = {"coefficient copies": 28 + 24, "r0": 28 + 8 + 8 + 16, "x update": 4 + 8 + 8,
+                    "true residual": 28 + 8 + 8}
 # s7_info.schedule: 1 three passes, 2 four passes, 3 three passes on cell pairs, 5 three
 # passes with the stencil operand staged in LDS
 PASSES = {1: 3, 2: 4, 3: 3, 5: 3}
@@ -219,6 +224,9 @@ def batched_leg(s7, torch, dev):
         "seconds_min_max": [round(ts[0], 4), round(ts[-1], 4)], "timed_calls": len(ts),
         "cell_iters_per_s": round(cell_iters / dt, 1),
         "alg_GB/s": round(cell_iters * BATCH_BYTES / dt / 1e9, 1),
+        # the one-time passes of every FP32 solve counted too (start, epilogue)
+        "alg_GB/s_with_setup_bytes": round((cell_iters * BATCH_BYTES + sum(cells) * sum(SETUP_BYTES_FP32.values()))
+                                           / dt / 1e9, 1),
         "max_rel_err_vs_xstar": err,
         "serial_single_solves_s": round(dts, 4), "speedup_vs_serial": round(dts / dt, 2),
     }
@@ -1031,6 +1039,10 @@ def main():
         "hbm_frac_per_iteration": round(iter_bytes * ips / 1e9 / HBM_PEAK_GBS, 4),
         "hbm_frac_per_iteration_at_survey_bytes": round(survey_iter_bytes * ips / 1e9 / HBM_PEAK_GBS, 4),
         "hbm_frac_kernels_only": round(iter_bytes / (kernel_ms_iter * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the same timed call with the bytes of its one-time passes counted too
+        "hbm_frac_whole_call_with_setup_bytes": round((iter_bytes * args.steps
+                                                       + sum(SETUP_BYTES_FP32.values()) * n)
+                                                      / dt / 1e9 / HBM_PEAK_GBS, 4),
         "profiled_iter_per_s": round(args.steps / pdt, 3),
         "passes": passes,
         "roofline": roofline,

@@ -87,6 +87,8 @@ def test_bench_byte_accounting_matches_the_design():
     import bench
     assert sum(bench.BYTES[("f32", 3)].values()) == 112
     assert sum(bench.BYTES[("f32", 4)].values()) == 120
+    # the one-time passes of an FP32 solve: copies 52, r0 60, x update 20, true residual 44
+    assert sum(bench.SETUP_BYTES_FP32.values()) == 176
     assert sum(bench.BYTES[("16", 3)].values()) == 60
     assert sum(bench.BYTES[("16", 4)].values()) == 64
     # P1: p, r0 and 6 coefficients read, s written, 4 bytes each
