@@ -232,6 +232,61 @@ def batched_leg(s7, torch, dev):
     }
 
 
+def batched_small_leg(s7, torch, dev, nsys: int = 256, side: int = 16):
+    """Many tiny systems (256 of 16^3, seeds 3000+s, FP32 to 1e-7): one work item per
+    phase and system, so the per-phase latency of a workgroup sets the time rather than
+    bandwidth.  The batched solver (median of five calls) against a loop of single solves."""
+    dims = (side, side, side)
+    n = side ** 3
+    coefs, bs, xs, xst = [], [], [], []
+    for k in range(nsys):
+        c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(7)]
+        xx = torch.empty(n, dtype=torch.float64, device=dev)
+        bb = torch.empty(n, dtype=torch.float64, device=dev)
+        s7.generate_problem(dims, 3000 + k, 0, c, xx, bb)
+        coefs.append(c), bs.append(bb), xst.append(xx)
+        xs.append(torch.zeros(n, dtype=torch.float64, device=dev))
+    shapes = [dims] * nsys
+    ws = torch.empty(s7.batched_workspace_bytes(shapes), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    call = s7.batched_call(shapes, coefs, bs, xs, [1e-7] * nsys, [2000] * nsys, ws=ws,
+                           opt=s7.default_options(tune=1))
+
+    def batched():
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, infos = call()
+        torch.cuda.synchronize()
+        return rc, infos, time.perf_counter() - t0
+
+    batched()
+    rc, infos, ts = repeat_timed(batched)
+    dt = ts[len(ts) // 2]
+    iters = [i.iters for i in infos]
+    err = max(float(torch.linalg.vector_norm(x - xx) / torch.linalg.vector_norm(xx)) for x, xx in zip(xs, xst))
+    sws = torch.empty(s7.workspace_bytes(dims), dtype=torch.uint8, device=dev)
+    o1 = s7.default_options(tune=1)
+    s7.bicgstab_solve(dims, coefs[0], bs[0], xs[0], 1e-7, 3, ws=sws, opt=o1)
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, bb, x in zip(coefs, bs, xs):
+        s7.bicgstab_solve(dims, c, bb, x, 1e-7, 2000, ws=sws, opt=o1)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t0
+    return {
+        "workload": f"{nsys} systems of {side}^3, FP32, rtol 1e-7", "status": rc,
+        "iters_min_max": [min(iters), max(iters)], "systems_per_s": round(nsys / dt, 1),
+        "seconds": round(dt, 5), "seconds_min_max": [round(ts[0], 5), round(ts[-1], 5)],
+        "us_per_iteration_per_system": round(dt / max(iters) * 1e6, 1),
+        "max_rel_err_vs_xstar": err, "serial_single_solves_s": round(dts, 4),
+        "speedup_vs_serial": round(dts / dt, 2),
+    }
+
+
 def cube256_leg(s7, torch, dev, steps: int, warmup: int, tune: bool):
     """256^3 with the anisotropic z-slab field (the z coefficients scaled up to 10x in a
     centred slab): `steps` fixed iterations timed on the graph path (iterations/s, GFLOPS
@@ -1111,6 +1166,8 @@ def main():
     if not args.no_batched:
         print("[bench] batched: 64 uneven systems", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(s7, torch, dev)
+        print("[bench] batched: 256 systems of 16^3", file=sys.stderr, flush=True)
+        out["batched_small"] = batched_small_leg(s7, torch, dev)
         torch.cuda.empty_cache()
     if not args.no_pipelined:
         print("[bench] pipelined BiCGStab", file=sys.stderr, flush=True)
