@@ -96,7 +96,7 @@ typedef struct {
     int32_t chunk_cells;    /* batched/queue: cells per work item of the persistent
                                kernel, rounded up to a multiple of 1024, at most 2^24;
                                0 = 16384, with the chunks of small systems halved (down
-                               to 4096 cells, up to 64 chunks) while the resident set
+                               to 4096 cells, up to 32 chunks) while the resident set
                                has fewer work items than the grid has workgroups.  No
                                result depends on it. */
     int32_t profile;        /* 1: launch without graphs, time every pass with HIP

@@ -1064,7 +1064,7 @@ static int chunk_cells_of(const s7_options& o) {
 // system's chunks are atomics on the same control words, which serialize.
 // The sums are kept per unit, so this changes no result.  An explicit
 // options.chunk_cells is kept as given.
-constexpr long long kShrinkChunks = 64;
+constexpr long long kShrinkChunks = 32;
 static std::vector<int> launch_chunks(const std::vector<EngineJob*>& jobs, int chunk, int grid_cap, bool adapt) {
     std::vector<int> c(jobs.size(), chunk);
     if (!adapt) return c;
