@@ -980,6 +980,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-simple", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
+    ap.add_argument("--no-apply", action="store_true", help="skip the stencil_apply leg")
     ap.add_argument("--no-2d9", action="store_true")
     ap.add_argument("--no-pipelined", action="store_true")
     ap.add_argument("--simple-dims", type=int, nargs=3, default=[100, 400, 100])
@@ -1102,6 +1103,31 @@ def main():
         "passes": passes,
         "roofline": roofline,
     }
+
+    # ---- s7_stencil_apply alone on the same mesh: u = A v with the caller's seven
+    # FP32 coefficient arrays, 36 B per cell (7 coefficients and v read, u written)
+    if not args.no_apply:
+        print("[bench] stencil apply: 20 timed launches", file=sys.stderr, flush=True)
+        v = xs.to(torch.float32)
+        u = torch.empty_like(v)
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            s7.stencil_apply(dims, coef, v, u, stream=stream.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            s7.stencil_apply(dims, coef, v, u, stream=stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        out["stencil_apply"] = {"workload": f"u = A v, FP32, {nx}x{ny}x{nz}, the caller's 7 coefficient arrays",
+                                "avg_launch_ms": round(ms, 4), "bytes_per_cell": 36,
+                                "GB/s": round(36 * n / (ms * 1e-3) / 1e9, 1),
+                                "frac": round(36 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "form": "x-adjacent pairs, v staged in LDS (2048-cell tiles, band per XCD)"
+                                if nx % 2 == 0 and n >= (1 << 18) else "single cells",
+                                "timing": "HIP events around 20 launches on the caller's stream"}
+        del v, u
 
     # ---- one GPU's share of an 8-GPU z-slab decomposition of the same mesh:
     # the first nz/8 planes, a contiguous prefix of every array

@@ -285,6 +285,60 @@ __global__ __launch_bounds__(kThreads) void k_stencil_apply(Coef7 cf, const floa
     if (c.own) u[c.idx] = av;
 }
 
+// u = A v on x-adjacent cell pairs, v staged in LDS: a tile of TILE cells and
+// one row either side, as in the solver's staged passes; below and above come
+// from memory.  The caller's coefficients are used as given, so a neighbour
+// across a mesh face has both its coefficient and its value set to zero (the
+// staged neighbour there is another cell of the mesh): every cell's sum is the
+// flat kernel's, term by term, for finite v.
+template <int TILE>
+__global__ __launch_bounds__(kThreads) void k_apply_lds(Coef7 cf, const float* v, float* u, Mesh m, int n,
+                                                        int nblocks, int run) {
+    extern __shared__ float stage[];
+    const int tile = xcd_tile(blockIdx.x, nblocks, run);
+    const int nx = m.nx, c0 = tile * TILE, lo = lds_lo(c0, nx);
+    const int hi = (c0 + TILE + nx + 7) >> 3 << 3;
+    stage_rows<float, false>(v, nullptr, 0.0f, lo, hi - lo, n, stage);
+    __syncthreads();
+    const int plane = nx * m.ny;
+#pragma unroll 2
+    for (int q = 0; q < TILE / (2 * kThreads); ++q) {
+        const int idx = c0 + 2 * (q * kThreads + (int)threadIdx.x);
+        if (idx >= n) break;
+        const int k = div_rcp(idx, plane, m.rplane);
+        const int rem = idx - k * plane;
+        const int j = div_rcp(rem, nx, m.rnx);
+        const int i = rem - j * nx;
+        Cell f0{}, f1{};  // the faces each cell of the pair touches (nonzero: inside)
+        f0.dw = i > 0 ? -1 : 0;
+        f0.de = 1;
+        f1.dw = -1;
+        f1.de = i + 1 < nx - 1 ? 1 : 0;
+        f0.ds = f1.ds = j > 0 ? -nx : 0;
+        f0.dn = f1.dn = j < m.ny - 1 ? nx : 0;
+        f0.db = f1.db = k > 0 ? -plane : 0;
+        f0.dt = f1.dt = k < m.nz - 1 ? plane : 0;
+        const F2 vb = ld2(v + idx + f0.db), vt = ld2(v + idx + f0.dt);
+        Nbr<float> v0, v1;
+        lds_nbr2(stage, idx - lo, nx, vb, vt, v0, v1);
+        v0.w = f0.dw ? v0.w : 0.0f;
+        v1.e = f1.de ? v1.e : 0.0f;
+        v0.s = f0.ds ? v0.s : 0.0f;
+        v1.s = f0.ds ? v1.s : 0.0f;
+        v0.n = f0.dn ? v0.n : 0.0f;
+        v1.n = f0.dn ? v1.n : 0.0f;
+        v0.b = f0.db ? v0.b : 0.0f;
+        v1.b = f0.db ? v1.b : 0.0f;
+        v0.t = f0.dt ? v0.t : 0.0f;
+        v1.t = f0.dt ? v1.t : 0.0f;
+        Coefs<float, false> k0, k1;
+        load_coefs2_nt<float, false>(cf.c, idx, k0, k1);
+        const float a0 = apply7<float, float, false, true>(k0, v0, f0);
+        const float a1 = apply7<float, float, false, true>(k1, v1, f1);
+        st2_nt(u + idx, a0, a1);
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_apply_f64(Coef7 cf, const double* v, double* u,
                                                         Mesh m, int n) {
     const Cell c = cell_at(blockIdx.x * kThreads + threadIdx.x, m, n);
@@ -1425,6 +1479,8 @@ static bool coef_ok(const float* const coef[7]) {
     return true;
 }
 
+constexpr int kApplyMinCells = 1 << 18;
+
 int s7_stencil_apply(s7_dims d, const float* const coef[7], const float* v, float* u, void* stream) {
     clear_error();
     if (!dims_ok(d) || !coef_ok(coef) || !v || !u || v == u) {
@@ -1434,9 +1490,24 @@ int s7_stencil_apply(s7_dims d, const float* const coef[7], const float* v, floa
     const Mesh m = make_mesh(d.nx, d.ny, d.nz);
     const int n = d.nx * d.ny * d.nz;
     Coef7 cf;
-    for (int a = 0; a < 7; ++a) cf.c[a] = coef[a];
-    hipLaunchKernelGGL(k_stencil_apply, dim3(cell_blocks_for(n)), dim3(kThreads), 0,
-                       (hipStream_t)stream, cf, v, u, m, n);
+    bool aligned = ((uintptr_t)v & 15u) == 0 && ((uintptr_t)u & 7u) == 0;
+    for (int a = 0; a < 7; ++a) {
+        cf.c[a] = coef[a];
+        aligned = aligned && ((uintptr_t)coef[a] & 7u) == 0;
+    }
+    // The staged pairs for an even nx whose rows fit the LDS, on meshes large
+    // enough to fill the chip with 2048-cell tiles, when v allows 16-byte and
+    // the rest 8-byte accesses; single cells otherwise.
+    constexpr int kApplyTile = 2048;
+    if (d.nx % 2 == 0 && lds_fits(d.nx, kApplyTile) && n >= kApplyMinCells && aligned) {
+        const int nb = lds_blocks(n, kApplyTile);
+        const size_t lds = (size_t)lds_count(d.nx, kApplyTile) * sizeof(float);
+        hipLaunchKernelGGL((k_apply_lds<kApplyTile>), dim3(nb), dim3(kThreads), lds, (hipStream_t)stream, cf, v, u,
+                           m, n, nb, tile_run(-1, m, kApplyTile));
+    } else {
+        hipLaunchKernelGGL(k_stencil_apply, dim3(cell_blocks_for(n)), dim3(kThreads), 0,
+                           (hipStream_t)stream, cf, v, u, m, n);
+    }
     S7_CHECK_LAUNCH();
     return S7_OK;
 }

@@ -1,4 +1,8 @@
-"""GPU parity of the stencil apply and the device generator against the oracle."""
+"""GPU parity of the stencil apply and the device generator against the oracle.
+
+s7_stencil_apply takes two forms: single cells, and (even nx, at least 2^18 cells, aligned
+arrays) x-adjacent pairs with v staged in LDS in 2048-cell tiles.  Both are checked
+against the oracle's SpMV, on ragged tails and with non-finite outward coefficients."""
 import numpy as np
 import pytest
 
@@ -9,9 +13,11 @@ from tests.gpu_helpers import U32, abs_row_bound, coef_dev, dev, host
 
 pytestmark = pytest.mark.gpu
 
-# several tiles in x (62 columns each) and y (4 or 8 rows), ragged tails, z chunks
+# several tiles in x (62 columns each) and y (4 or 8 rows), ragged tails, z chunks; the
+# staged form for 200x33x65 (a ragged last tile), 130x70x40 and 1024x16x17 (long rows);
+# 4098x4x17 has rows too long for the staging LDS and takes single cells
 SHAPES = [(1, 1, 1), (2, 1, 1), (1, 1, 7), (5, 3, 2), (62, 4, 3), (63, 9, 7), (64, 17, 33),
-          (130, 70, 20), (200, 33, 65), (17, 100, 40)]
+          (130, 70, 20), (200, 33, 65), (17, 100, 40), (130, 70, 40), (1024, 16, 17), (4098, 4, 17)]
 
 
 @pytest.fixture(scope="module")
@@ -43,8 +49,8 @@ def test_stencil_apply_matches_oracle_spmv(s7, dims):
     assert np.all(np.abs(u - ref) <= bound + 1e-30), np.max(np.abs(u - ref) / bound)
 
 
-def test_outward_coefficients_are_ignored(s7):
-    dims = (70, 11, 6)
+@pytest.mark.parametrize("dims", [(70, 11, 6), (70, 64, 64)])
+def test_outward_coefficients_are_ignored(s7, dims):
     prob = synth.make_problem(*dims, seed=5)
     A = oracle.build_csr(*dims, prob.coef)
     coef = [c.copy() for c in prob.coef]
@@ -61,6 +67,21 @@ def test_outward_coefficients_are_ignored(s7):
     ref = oracle.spmv(A, v.astype(np.float64))
     bound = 8 * U32 * abs_row_bound(A, v.astype(np.float64))
     assert np.all(np.abs(u - ref) <= bound)
+
+
+def test_staged_and_single_cell_forms_agree(s7):
+    """The same apply through the staged pairs (aligned v) and through single cells (v
+    one element into a buffer, so not 16-byte aligned) gives the same values."""
+    import torch
+    dims = (200, 33, 65)
+    prob = synth.make_problem(*dims, seed=4)
+    coef = coef_dev(prob)
+    v = prob.xstar.astype(np.float32)
+    a = _apply(s7, dims, coef, dev(v))
+    buf = torch.empty(v.size + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = dev(v)
+    b = _apply(s7, dims, coef, buf[1:])
+    assert np.array_equal(a, b)
 
 
 def test_stencil_apply_deterministic(s7):
