@@ -961,10 +961,10 @@ __device__ void chunk_staged9(const SysView<T>& S, const Coef9T<T>& k, int c0, i
         if (u0 >= t1) continue;  // the same for the whole wavefront
         const int u1 = min(t1, u0 + kUnitCells);
         double acc[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        // two cells per lane and step, their coefficient and r0 loads issued
+        // four cells per lane and step, their coefficient and r0 loads issued
         // before any store; a lane past the unit's end works on the unit's
         // first cell and keeps nothing
-        constexpr int kSC = 2;
+        constexpr int kSC = 4;
         for (int u = 0; u < kUnitCells / kWave; u += kSC) {
             int idx[kSC];
             bool own[kSC];
