@@ -98,12 +98,17 @@ __device__ __forceinline__ Nbr<T> cload_nbr(const T* v, const Cell& c) {
 // to memory rather than one per word.  Called by every thread.
 constexpr int kStateWords = (int)(sizeof(State) / 4);
 static_assert(sizeof(State) % 4 == 0 && kStateWords <= kThreads, "State is copied one word per thread");
-__device__ __forceinline__ void state_load(const State* src, State& dst) {
+// state_fetch loads this thread's word; state_put stores it into the LDS copy
+// (the load may still be in flight between the two).
+__device__ __forceinline__ uint32_t state_fetch(const State* src) {
     const int w = (int)threadIdx.x;
-    if (w < kStateWords)
-        reinterpret_cast<uint32_t*>(&dst)[w] = __hip_atomic_load(
-            gbl(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(src) + w)), __ATOMIC_RELAXED,
-            __HIP_MEMORY_SCOPE_AGENT);
+    return w < kStateWords ? __hip_atomic_load(gbl(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(src) + w)),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : 0u;
+}
+__device__ __forceinline__ void state_put(uint32_t word, State& dst) {
+    const int w = (int)threadIdx.x;
+    if (w < kStateWords) reinterpret_cast<uint32_t*>(&dst)[w] = word;
     __syncthreads();
 }
 // Each thread waits until its word has reached memory.
@@ -1216,14 +1221,17 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
         }
         __syncthreads();
         if (!sh_last) continue;
-        // this workgroup completes the phase: sum the units' sums in unit order
+        // this workgroup completes the phase: sum the units' sums in unit order.
+        // The State's words are loaded first, so that they and the sums share
+        // one memory round trip.
+        const uint32_t stw = state_fetch(S.st);
         const int nunit = (S.n + kUnitCells - 1) / kUnitCells;
         double tot[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (kind == K_R) sum_range<kMaxDots, 4u, true>(part, 0, nunit, tot);
         else if (kND[kind] > 0) sum_range<kMaxDots, 0u, true>(part, 0, nunit, tot);
         // the private state copy lives in LDS: a register copy would raise the
         // register count of the whole kernel
-        state_load(S.st, sh_state);
+        state_put(stw, sh_state);
         if (threadIdx.x == 0) {
             State& st = sh_state;
             int next = K_FINAL;
