@@ -95,7 +95,6 @@ class Arena {
 struct Req {
     uint64_t ticket;
     EngineJob job;
-    int op = 0;  // 0: 3D 7-point, 1: 2D 9-point
     bool big = false;
     size_t off = 0, bytes = 0;
     double t_submit = 0, t_admit = 0;
@@ -228,7 +227,7 @@ struct s7_queue {
             const EngineJob& j = r->job;
             s7_info info;
             int rc;
-            if (r->op) {
+            if (j.op) {
                 const float* c9[9];
                 for (int a = 0; a < 7; ++a) c9[a] = j.coef[a];
                 c9[7] = j.coef9[0];
@@ -306,8 +305,7 @@ static int enqueue(s7_queue* q, const EngineJob& job, int op, size_t bytes, uint
     std::unique_ptr<Req> r(new Req());
     r->job = job;
     r->job.ws_bytes = bytes;
-    r->job.op = op;
-    r->op = op;
+    r->job.op = op;  // 0: 3D 7-point, 1: 2D 9-point
     r->bytes = bytes;
     r->big = (long long)job.d.nx * job.d.ny * job.d.nz >= q->split_cells;
     r->t_submit = now_ms();
