@@ -981,6 +981,8 @@ def main():
     ap.add_argument("--no-simple", action="store_true")
     ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--no-apply", action="store_true", help="skip the stencil_apply leg")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed calls of the headline for its median and spread (0: none)")
     ap.add_argument("--no-2d9", action="store_true")
     ap.add_argument("--no-pipelined", action="store_true")
     ap.add_argument("--simple-dims", type=int, nargs=3, default=[100, 400, 100])
@@ -1054,6 +1056,13 @@ def main():
     assert info.iters == args.steps, info.as_dict()
     ips = args.steps / dt
     sched = info.schedule  # the schedule the (tuned) solve ran
+    # the same timed call repeated: median and spread beside the one timed region above
+    rep_ips = []
+    for _ in range(args.repeats):
+        rinfo, rdt = run(s7.FP32, args.steps)
+        assert rinfo.iters == args.steps, rinfo.as_dict()
+        rep_ips.append(args.steps / rdt)
+    rep_ips.sort()
     # the same steps again without graphs, every pass bracketed by HIP events on the
     # solver's stream: the per-kernel times of the roofline
     print(f"[bench] FP32 {args.steps} iterations with per-pass HIP events", file=sys.stderr, flush=True)
@@ -1100,6 +1109,8 @@ def main():
                                                        + sum(SETUP_BYTES_FP32.values()) * n)
                                                       / dt / 1e9 / HBM_PEAK_GBS, 4),
         "profiled_iter_per_s": round(args.steps / pdt, 3),
+        "repeats": {"calls": len(rep_ips), "median_iter_per_s": round(rep_ips[len(rep_ips) // 2], 3) if rep_ips else None,
+                    "min_max_iter_per_s": [round(rep_ips[0], 3), round(rep_ips[-1], 3)] if rep_ips else None},
         "passes": passes,
         "roofline": roofline,
     }
