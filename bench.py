@@ -519,6 +519,20 @@ def stencil9_leg(s7, torch, dev, steps: int, warmup: int):
         xs = torch.empty(n, dtype=torch.float64, device=dev)
         b = torch.empty(n, dtype=torch.float64, device=dev)
         s7.generate_problem_2d9(nx, ny, 0, c, xs, b)
+        # s7_stencil9_apply alone: u = A v with the nine caller arrays, 44 B per cell
+        v = xs.to(torch.float32)
+        u = torch.empty_like(v)
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            s7.stencil9_apply(nx, ny, c, v, u, stream=stream.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            s7.stencil9_apply(nx, ny, c, v, u, stream=stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        apply_ms = e0.elapsed_time(e1) / 20
+        del v, u
         x = torch.zeros(n, dtype=torch.float64, device=dev)
         ws = torch.empty(max(s7.workspace_bytes_2d9(nx, ny, pr) for pr in (s7.FP32, s7.BF16_IR)),
                          dtype=torch.uint8, device=dev)
@@ -549,6 +563,9 @@ def stencil9_leg(s7, torch, dev, steps: int, warmup: int):
         c16 = s7.bicgstab_solve_2d9(nx, ny, c, b, x, 1e-10, 2000, prec=s7.BF16_IR, ws=ws)
         err16 = float(torch.linalg.vector_norm(x - xs) / torch.linalg.vector_norm(xs))
         out.append({"workload": f"2D 9-point, FP32, Jacobi, {nx}x{ny} ({n} cells)",
+                    "stencil9_apply": {"avg_launch_ms": round(apply_ms, 4), "bytes_per_cell": 44,
+                                       "GB/s": round(44 * n / (apply_ms * 1e-3) / 1e9, 1),
+                                       "frac": round(44 * n / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                     "bf16_ir": {"inner_iter_per_s": round(i16.iters / dt16, 2),
                                 "bytes_per_cell_inner_iteration": sum(BYTES_2D9_16.values()),
                                 "converged_rtol1e-10": {"status": c16.status, "inner_iters": c16.iters,
