@@ -302,6 +302,34 @@ int s7_bicgstab_solve_pipelined(s7_dims d, const float *const coef[7], const dou
                                 double rtol, int32_t max_iter, void *ws, size_t ws_bytes,
                                 const s7_options *opt, s7_info *info, void *stream);
 
+/* Workspace for s7_bicgstab_solve_batched_pipelined over these nsys systems
+ * (0 for invalid arguments). */
+size_t s7_batched_workspace_bytes_pipelined(int32_t nsys, const s7_dims *d, const s7_options *opt);
+
+/*
+ * The pipelined BiCGStab above for nsys independent systems in one persistent
+ * launch: the many-compact-problems use of section VIII-B with the
+ * one-reduction iteration.  In the persistent kernel each iteration is two
+ * phases, so a system's workgroups hand off twice per iteration where the
+ * classical batched solve hands off three times.  Phase A forms z at the
+ * stencil's neighbour cells and v = A z, and takes all ten sums.  Phase B forms
+ * w at the neighbour cells and t = A w, then updates r and d.  Residual
+ * replacement runs every 10 iterations, and at once after a candidate stop.
+ * The stop is verified on the FP64 true residual, as in
+ * s7_bicgstab_solve_pipelined.  FP32 storage; each system's sums are kept per
+ * unit of 1024 of its cells, so its iterates depend only on that system and
+ * not on the rest of the batch or on chunk_cells.  Arguments are as for
+ * s7_bicgstab_solve_batched with prec = S7_FP32.  Of the options it reads
+ * jacobi, chunk_cells and split_cells.  A system of split_cells cells or
+ * more is solved alone by s7_bicgstab_solve_pipelined in its slice of the
+ * workspace.  info->schedule = 4.  Returns a negative error, or else the
+ * worst status.
+ */
+int s7_bicgstab_solve_batched_pipelined(int32_t nsys, const s7_dims *d, const float *const *coef,
+                                        const double *const *b, double *const *x, const double *rtol,
+                                        const int32_t *max_iter, void *ws, size_t ws_bytes,
+                                        const s7_options *opt, s7_info *info, void *stream);
+
 /*
  * Request queue with continuous batching (serving form; section VIII-A names
  * the real-time use).  The caller supplies the device arena, which is the HBM

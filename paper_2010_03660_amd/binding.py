@@ -29,6 +29,7 @@ __all__ = [
     "stencil9_apply", "workspace_bytes_2d9", "bicgstab_solve_2d9", "generate_problem_2d9",
     "batched_workspace_bytes_2d9", "bicgstab_solve_batched_2d9", "batched_call_2d9", "Request2D9", "queue_submit_2d9", "workspace_bytes_pipelined",
     "bicgstab_solve_pipelined", "bicgstab_solve_noalloc", "NOALLOC_WS_BYTES",
+    "batched_workspace_bytes_pipelined", "bicgstab_solve_batched_pipelined", "batched_pipelined_call",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
     "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
@@ -89,6 +90,12 @@ EXPORTS = {
                                     _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info), _vp]),
     "s7_batched_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(Dims), C.c_int32,
                                                 C.POINTER(Options)]),
+    "s7_batched_workspace_bytes_pipelined": (C.c_size_t, [C.c_int32, C.POINTER(Dims), C.POINTER(Options)]),
+    "s7_bicgstab_solve_batched_pipelined": (C.c_int, [C.c_int32, C.POINTER(Dims), C.POINTER(_vp),
+                                                      C.POINTER(_vp), C.POINTER(_vp),
+                                                      C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                                      _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info),
+                                                      _vp]),
     "s7_bicgstab_solve_batched": (C.c_int, [C.c_int32, C.POINTER(Dims), C.POINTER(_vp),
                                             C.POINTER(_vp), C.POINTER(_vp),
                                             C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32,
@@ -431,3 +438,41 @@ def bicgstab_solve_pipelined(dims, coef, b, x, rtol, max_iter, ws=None, opt: Opt
                                            _stream(stream))
     _check(rc)
     return info
+
+
+def batched_workspace_bytes_pipelined(dims_list, opt: Options | None = None) -> int:
+    n = len(dims_list)
+    arr = (Dims * n)(*[_dims(d) for d in dims_list])
+    return int(lib().s7_batched_workspace_bytes_pipelined(n, arr, C.byref(opt) if opt else None))
+
+
+def batched_pipelined_call(dims_list, coefs, bs, xs, rtols, max_iters, ws=None, opt: Options | None = None,
+                           stream=None):
+    """Marshals the arguments of s7_bicgstab_solve_batched_pipelined once and returns a
+    function that makes the call and returns (status, [Info]) (see batched_call)."""
+    n = len(dims_list)
+    arr = (Dims * n)(*[_dims(d) for d in dims_list])
+    cp = (_vp * (7 * n))(*[_ptr(c) for cs in coefs for c in cs])
+    bp = (_vp * n)(*[_ptr(b) for b in bs])
+    xp = (_vp * n)(*[_ptr(x) for x in xs])
+    rt = (C.c_double * n)(*[float(r) for r in rtols])
+    mi = (C.c_int32 * n)(*[int(m) for m in max_iters])
+    infos = (Info * n)()
+    nbytes = batched_workspace_bytes_pipelined(dims_list, opt)
+    ws = _workspace(nbytes, ws)
+    wsb = ws.numel() * ws.element_size() if not isinstance(ws, int) else nbytes
+    fn, wsp, ob, st = lib().s7_bicgstab_solve_batched_pipelined, _ptr(ws), C.byref(opt) if opt else None, _stream(stream)
+
+    def call():
+        rc = fn(n, arr, cp, bp, xp, rt, mi, wsp, wsb, ob, infos, st)
+        _check(rc)
+        return rc, list(infos)
+    call.keep = (arr, cp, bp, xp, rt, mi, infos, ws, opt)
+    return call
+
+
+def bicgstab_solve_batched_pipelined(dims_list, coefs, bs, xs, rtols, max_iters, ws=None,
+                                     opt: Options | None = None, stream=None):
+    """Pipelined BiCGStab for len(dims_list) systems in one persistent launch (FP32).
+    Returns (status, [Info])."""
+    return batched_pipelined_call(dims_list, coefs, bs, xs, rtols, max_iters, ws, opt, stream)()

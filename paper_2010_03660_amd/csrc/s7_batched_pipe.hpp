@@ -1,0 +1,725 @@
+// Pipelined BiCGStab (the one-reduction variant of Cools and Vanroose, 2017)
+// for many systems in one persistent launch: the batched form of the solve in
+// s7_pipelined.hpp, on the claim-and-complete machinery of the classical
+// batched kernel (s7_batched_kernels.hpp).
+//
+// In the persistent kernel a phase boundary is a hand-off between workgroups:
+// every chunk of the phase must be done before any chunk of the next starts.
+// Of the four passes of the multi-kernel form, the two streaming ones are
+// merged into the stencil pass that follows them, by forming their output at
+// the stencil's neighbour cells from the vectors it is computed from:
+//   A  z = t + beta (z - omega v) at the cell and its six neighbours, v = A z,
+//      p, s, q, y at the cell; all ten sums of the iteration.  Its completion
+//      takes every decision of the iteration (the stop test on r_i, omega,
+//      beta, the next alpha).
+//   B  w = y - omega (t - alpha v) at the cell and its neighbours, t = A w,
+//      d += alpha p + omega q, r = q - omega y at the cell.  No sums.
+// Two hand-offs per iteration, against three for the classical P1, P2, P3.
+// A reads z and v at neighbour cells and writes new z and v; B does the same
+// for t.  So z, v and t are kept twice and the copies alternate: a phase
+// reads one copy and writes the other, and no chunk overwrites a value that
+// a neighbouring chunk of the same phase still reads.  The FP32 arithmetic of
+// every vector element is that of the multi-kernel form, term for term.
+//
+// Residual replacement every kReplace iterations, and at once after a
+// candidate stop: R (r = b - A (x + d), FP64), WS (w = A r, s = A p; x += d,
+// d = 0), TZ (t = A w, z = A s), V (v = A z and the sums (r0, r), (r0, w),
+// (r0, s), (r0, z), (r, r), which decide a candidate stop on the true
+// residual).  The start is S (r0 = b - A x0) followed by WS, TZ and V, which
+// give w_0, t_0 and alpha_0.  The end is X (x += d) and the FP64 true
+// residual, as for a classical FP32 job.  Sums are kept per unit of
+// kUnitCells cells as in the classical kernel, so a system's iterates depend
+// on nothing but the system.  FP32 storage, 7-point operator.  Included by
+// the solver translation unit (s7_single.hip) after s7_pipelined.hpp.
+#pragma once
+
+namespace s7 {
+
+// A pipelined job's control block: the State, the pipelined scalars, which
+// copy of z and v (zb) and of t (tb) is current, and the iterations since the
+// last replacement.  It sits where a classical job keeps its State, in the
+// space before the partial sums.
+struct PState {
+    State st;
+    PipeScalars ps;
+    int32_t zb, tb, since, pad;
+};
+constexpr int kPStateWords = (int)(sizeof(PState) / 4);
+static_assert(sizeof(PState) % 4 == 0 && kPStateWords <= kThreads, "PState is copied one word per thread");
+static_assert(sizeof(PState) <= (sizeof(State) + 255) / 256 * 256, "PState fits before the partial sums");
+
+// Phase kinds; a phase sequence number is (count << 4) | kind.  PK_S has the
+// value of the classical K_S, so the shared job start kernel sets it.
+enum PipeKind : int {
+    PK_A = 0, PK_B = 1, PK_R = 2, PK_WS = 3, PK_TZ = 4, PK_V = 5, PK_S = 6, PK_X = 7, PK_RF = 8, PK_FINAL = 9
+};
+static_assert((int)PK_S == (int)K_S, "the job start kernel sets the first phase");
+__host__ __device__ inline uint32_t pseq_next(uint32_t seq, int kind) {
+    return (((seq >> 4) + 1u) << 4) | (uint32_t)kind;
+}
+
+// One system of a pipelined launch.
+struct PSys {
+    SysView<float> S;  // r, r0, p, s, y, q, d, working coefficients; S.st is the PState
+    BCtl* ctl;
+    float* z[2];
+    float* v[2];
+    float* t[2];
+    float* w;
+    int nchunk;
+    int chunk;  // cells per work item (a multiple of kUnitCells)
+    Coef7 cf;   // the caller's coefficients (residual passes)
+    const double* b;
+    double* x;
+};
+
+// ---------------------------------------------------------------- unit sums
+// Up to kPD sums per unit of kUnitCells cells, reduced over the wavefront and
+// published by lane 63 (as unit_done, with a wider stride).
+constexpr int kPD = 10;
+template <int ND, unsigned MAXMASK, int NA>
+__device__ __forceinline__ void punit_done(const double (&acc)[NA], double* part, int unit) {
+    if constexpr (ND > 0) {
+        double v[ND];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) v[j] = acc[j];
+        wave_reduce<ND, MAXMASK>(v);
+        if (lane_id() == kWave - 1) {
+#pragma unroll
+            for (int j = 0; j < ND; ++j) publish(&part[(size_t)unit * kPD + j], v[j]);
+        }
+    }
+}
+
+// The units of chunk [c0, c1), wavefront w taking units w, w + kWaves, ...;
+// f(u0, u1, acc) sums one unit's cells into an acc of NA values.
+template <int NA, int ND, unsigned MAXMASK, class F>
+__device__ __forceinline__ void pover_units(int c0, int c1, double* part, F&& f) {
+    for (int u0 = c0 + wave_id() * kUnitCells; u0 < c1; u0 += kUnitGroup) {
+        double acc[NA];
+#pragma unroll
+        for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+        f(u0, min(c1, u0 + kUnitCells), acc);
+        punit_done<ND, MAXMASK>(acc, part, u0 / kUnitCells);
+    }
+}
+
+// The completer's sums over the units [0, nunit), in unit order per thread
+// (thread t adds units t, t + 256, ...), then the workgroup sum of each value;
+// the workgroup reduction takes at most five values at a time.  Result in
+// thread 0.
+template <int ND, unsigned MAXMASK>
+__device__ __forceinline__ void psum_units(const double* part, int nunit, double (&out)[kPD]) {
+    double s[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) s[j] = 0.0;
+    for (int u = (int)threadIdx.x; u < nunit; u += kThreads) {
+        double v[ND];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) v[j] = fetch_published(&part[(size_t)u * kPD + j]);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) s[j] = comb<ND, MAXMASK>(j, s[j], v[j]);
+    }
+    constexpr int L = ND < 5 ? ND : 5;
+    double a[L], oa[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) a[j] = s[j];
+    block_reduce<L, MAXMASK & 31u>(a, oa);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < L; ++j) out[j] = oa[j];
+    }
+    if constexpr (ND > 5) {
+        constexpr int H = ND - 5;
+        double b[H], ob[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) b[j] = s[5 + j];
+        block_reduce<H, (MAXMASK >> 5)>(b, ob);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int j = 0; j < H; ++j) out[5 + j] = ob[j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- chunk work
+// A of one unit.  zo, vo: the current z and v; zn, vn: the other copies, which
+// receive the new ones.  Sums: (r0, y), (r0, t), (r0, s), (r0, z), (r, r),
+// (q, y), (y, y), (q, q), (r0, q), (r0, v).
+template <bool UNIT>
+__device__ void pchunk_a(const PSys& B, const float* zo, const float* vo, float* zn, float* vn, const float* t,
+                         int u0, int u1, float a, float bt, float om, double (&acc)[kPD]) {
+    const SysView<float>& S = B.S;
+    for (int g = u0 + lane_id(); g < u1; g += kWave) {
+        const Cell c = cell_at(g, S.m, S.n);
+        const int i = c.idx;
+        const Nbr<float> tv = cload_nbr(t, c), zv = cload_nbr(zo, c), vv = cload_nbr(vo, c);
+        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
+        const float r = cload(S.r + i), w = cload(B.w + i), p0 = cload(S.p + i), s0 = cload(S.s + i);
+        const float h = cload(S.rhat + i);
+        auto zf = [&](float tt, float zz, float vx) { return fmaT(bt, fmaT(-om, vx, zz), tt); };
+        const Nbr<float> z{zf(tv.c, zv.c, vv.c), zf(tv.w, zv.w, vv.w), zf(tv.e, zv.e, vv.e), zf(tv.s, zv.s, vv.s),
+                           zf(tv.n, zv.n, vv.n), zf(tv.b, zv.b, vv.b), zf(tv.t, zv.t, vv.t)};
+        const float v = apply7<float, float, UNIT, false>(k, z, c);
+        const float p = fmaT(bt, fmaT(-om, s0, p0), r);
+        const float s = fmaT(bt, fmaT(-om, zv.c, s0), w);
+        const float q = fmaT(-a, s, r);
+        const float y = fmaT(-a, z.c, w);
+        cstore(S.p + i, p);
+        cstore(S.s + i, s);
+        cstore(zn + i, z.c);
+        cstore(vn + i, v);
+        cstore(S.q + i, q);
+        cstore(S.y + i, y);
+        const double hd = h, yd = y, qd = q, rd = r;
+        acc[0] = fma(hd, yd, acc[0]);
+        acc[1] = fma(hd, (double)tv.c, acc[1]);
+        acc[2] = fma(hd, (double)s, acc[2]);
+        acc[3] = fma(hd, (double)z.c, acc[3]);
+        acc[4] = fma(rd, rd, acc[4]);
+        acc[5] = fma(qd, yd, acc[5]);
+        acc[6] = fma(yd, yd, acc[6]);
+        acc[7] = fma(qd, qd, acc[7]);
+        acc[8] = fma(hd, qd, acc[8]);
+        acc[9] = fma(hd, (double)v, acc[9]);
+    }
+}
+
+// B of one unit, full update: to, v: the current t and v; tn receives t = A w.
+template <bool UNIT>
+__device__ void pchunk_b(const PSys& B, const float* to, const float* v, float* tn, int u0, int u1, float a,
+                         float om) {
+    const SysView<float>& S = B.S;
+    for (int g = u0 + lane_id(); g < u1; g += kWave) {
+        const Cell c = cell_at(g, S.m, S.n);
+        const int i = c.idx;
+        const Nbr<float> yv = cload_nbr(S.y, c), tv = cload_nbr(to, c), vv = cload_nbr(v, c);
+        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
+        const float q = cload(S.q + i), p = cload(S.p + i), d = cload(S.d + i);
+        auto wf = [&](float yy, float tt, float vx) { return fmaT(-om, fmaT(-a, vx, tt), yy); };
+        const Nbr<float> w{wf(yv.c, tv.c, vv.c), wf(yv.w, tv.w, vv.w), wf(yv.e, tv.e, vv.e), wf(yv.s, tv.s, vv.s),
+                           wf(yv.n, tv.n, vv.n), wf(yv.b, tv.b, vv.b), wf(yv.t, tv.t, vv.t)};
+        const float tt = apply7<float, float, UNIT, false>(k, w, c);
+        cstore(S.d + i, fmaT(om, q, fmaT(a, p, d)));
+        cstore(S.r + i, fmaT(-om, yv.c, q));
+        cstore(B.w + i, w.c);
+        cstore(tn + i, tt);
+    }
+}
+
+// B of the half-step exit: d += alpha p only.
+__device__ void pchunk_b_half(const PSys& B, int u0, int u1, float a) {
+    const SysView<float>& S = B.S;
+    for (int i = u0 + lane_id(); i < u1; i += kWave) cstore(S.d + i, fmaT(a, cload(S.p + i), cload(S.d + i)));
+}
+
+// R: r = fl32((b - A (x + d)) / diag) in FP64 with the caller's coefficients;
+// x + d is the value the next phase stores into x.
+__device__ void pchunk_r(const PSys& B, int u0, int u1) {
+    const SysView<float>& S = B.S;
+    for (int g = u0 + lane_id(); g < u1; g += kWave) {
+        const Cell c = cell_at(g, S.m, S.n);
+        const double* px = B.x + c.idx;
+        const float* pd = S.d + c.idx;
+        auto xd = [&](int o) { return cload(px + o) + (double)cload(pd + o); };
+        const Nbr<double> xv{xd(0), xd(c.dw), xd(c.de), xd(c.ds), xd(c.dn), xd(c.db), xd(c.dt)};
+        const Coefs<float, false> k = load_coefs<float, false>(B.cf.c, c.idx);
+        const double r0 = *gbl(B.b + c.idx) - apply7<double, float, false, true>(k, xv, c);
+        cstore(S.r + c.idx, (float)(S.unit ? r0 / (double)k.a[0] : r0));
+    }
+}
+
+// WS: w = A r, s = A p; x += d, d = 0.
+template <bool UNIT>
+__device__ void pchunk_ws(const PSys& B, int u0, int u1) {
+    const SysView<float>& S = B.S;
+    for (int g = u0 + lane_id(); g < u1; g += kWave) {
+        const Cell c = cell_at(g, S.m, S.n);
+        const int i = c.idx;
+        const Nbr<float> rv = cload_nbr(S.r, c), pv = cload_nbr(S.p, c);
+        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
+        const float dv = cload(S.d + i);
+        const double xv = cload(B.x + i);
+        cstore(B.w + i, apply7<float, float, UNIT, false>(k, rv, c));
+        cstore(S.s + i, apply7<float, float, UNIT, false>(k, pv, c));
+        cstore(B.x + i, xv + (double)dv);
+        cstore(S.d + i, 0.0f);
+    }
+}
+
+// TZ: t = A w, z = A s (into the current copies).
+template <bool UNIT>
+__device__ void pchunk_tz(const PSys& B, float* t, float* z, int u0, int u1) {
+    const SysView<float>& S = B.S;
+    for (int g = u0 + lane_id(); g < u1; g += kWave) {
+        const Cell c = cell_at(g, S.m, S.n);
+        const int i = c.idx;
+        const Nbr<float> wv = cload_nbr(B.w, c), sv = cload_nbr(S.s, c);
+        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
+        cstore(t + i, apply7<float, float, UNIT, false>(k, wv, c));
+        cstore(z + i, apply7<float, float, UNIT, false>(k, sv, c));
+    }
+}
+
+// V: v = A z; sums (r0, r), (r0, w), (r0, s), (r0, z), (r, r).
+template <bool UNIT>
+__device__ void pchunk_v(const PSys& B, const float* z, float* v, int u0, int u1, double (&acc)[kPD]) {
+    const SysView<float>& S = B.S;
+    for (int g = u0 + lane_id(); g < u1; g += kWave) {
+        const Cell c = cell_at(g, S.m, S.n);
+        const int i = c.idx;
+        const Nbr<float> zv = cload_nbr(z, c);
+        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
+        cstore(v + i, apply7<float, float, UNIT, false>(k, zv, c));
+        const double h = cload(S.rhat + i), r = cload(S.r + i);
+        acc[0] = fma(h, r, acc[0]);
+        acc[1] = fma(h, (double)cload(B.w + i), acc[1]);
+        acc[2] = fma(h, (double)cload(S.s + i), acc[2]);
+        acc[3] = fma(h, (double)zv.c, acc[3]);
+        acc[4] = fma(r, r, acc[4]);
+    }
+}
+
+// The phases of chunk [c0, c1) that apply the working operator.
+template <bool UNIT>
+__device__ __forceinline__ void prun_chunk(const PSys& B, int kind, int c0, int c1, int zb, int tb, float alpha,
+                                           float beta, float omega, int flag) {
+    double* const part = B.S.red.part;
+    if (kind == PK_A) {
+        pover_units<kPD, 10, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kPD]) {
+            pchunk_a<UNIT>(B, B.z[zb], B.v[zb], B.z[zb ^ 1], B.v[zb ^ 1], B.t[tb], u0, u1, alpha, beta, omega, acc);
+        });
+    } else if (kind == PK_B) {
+        pover_units<1, 0, 0u>(c0, c1, part, [&](int u0, int u1, double (&)[1]) {
+            if (flag == 2) pchunk_b<UNIT>(B, B.t[tb], B.v[zb], B.t[tb ^ 1], u0, u1, alpha, omega);
+            else pchunk_b_half(B, u0, u1, alpha);
+        });
+    } else if (kind == PK_WS) {
+        pover_units<1, 0, 0u>(c0, c1, part, [&](int u0, int u1, double (&)[1]) { pchunk_ws<UNIT>(B, u0, u1); });
+    } else if (kind == PK_TZ) {
+        pover_units<1, 0, 0u>(c0, c1, part,
+                              [&](int u0, int u1, double (&)[1]) { pchunk_tz<UNIT>(B, B.t[tb], B.z[zb], u0, u1); });
+    } else {  // PK_V
+        pover_units<kPD, 5, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kPD]) {
+            pchunk_v<UNIT>(B, B.z[zb], B.v[zb], u0, u1, acc);
+        });
+    }
+}
+
+// ---------------------------------------------------------------- control block copies
+__device__ __forceinline__ uint32_t pstate_fetch(const PState* src) {
+    const int w = (int)threadIdx.x;
+    return w < kPStateWords
+               ? __hip_atomic_load(gbl(const_cast<uint32_t*>(reinterpret_cast<const uint32_t*>(src) + w)),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+               : 0u;
+}
+__device__ __forceinline__ void pstate_put(uint32_t word, PState& dst) {
+    const int w = (int)threadIdx.x;
+    if (w < kPStateWords) reinterpret_cast<uint32_t*>(&dst)[w] = word;
+    __syncthreads();
+}
+__device__ __forceinline__ void pstate_store(PState* dst, const PState& src) {
+    const int w = (int)threadIdx.x;
+    if (w < kPStateWords) {
+        __hip_atomic_store(gbl(reinterpret_cast<uint32_t*>(dst) + w), reinterpret_cast<const uint32_t*>(&src)[w],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_stores();
+    }
+}
+
+// The decisions at the end of a phase (thread 0, on the workgroup's copy of
+// the control block).  Returns the next phase.
+__device__ int pipe_complete(PState& P, int kind, const double (&tot)[kPD]) {
+    State& st = P.st;
+    PipeScalars& ps = P.ps;
+    int next = PK_FINAL;
+    bool inner_end = false;  // the iteration has stopped: the epilogue follows
+    switch (kind) {
+        case PK_S:
+            tail_init(&st, tot[0], tot[1], st.rtol_o, st.max_total);
+            st.bb_true = tot[2];
+            st.scale = 1.0;
+            ps = PipeScalars{};
+            P.zb = P.tb = P.since = 0;
+            if (st.done) inner_end = true;
+            else next = PK_WS;
+            break;
+        case PK_R: next = PK_WS; break;
+        case PK_WS: next = PK_TZ; break;
+        case PK_TZ: next = PK_V; break;
+        case PK_V:
+            P.since = 0;
+            tail_rr(&st, &ps, reinterpret_cast<const double(&)[5]>(tot));
+            if (st.done) inner_end = true;
+            else next = PK_A;
+            break;
+        case PK_A:
+            tail_k1(&ps, reinterpret_cast<const double(&)[4]>(tot));
+            tail_k2(&st, &ps, reinterpret_cast<const double(&)[6]>(tot[4]));
+            P.zb ^= 1;
+            if (ps.flag != 0) next = PK_B;  // the update is applied, stop or not
+            else if (st.done) inner_end = true;
+            else next = PK_R;  // a candidate stop: the true residual decides
+            break;
+        case PK_B:
+            if (ps.flag == 2) P.tb ^= 1;
+            P.since += 1;
+            st.alpha = ps.alpha_next;
+            ps.flag = 0;
+            if (st.done) inner_end = true;
+            else next = (ps.verify || P.since >= kReplace) ? PK_R : PK_A;
+            break;
+        case PK_X: next = st.xzero ? PK_FINAL : PK_RF; break;
+        default:  // PK_RF
+            (void)after_resid(st, reinterpret_cast<const double(&)[kMaxDots]>(tot));
+            next = PK_FINAL;
+    }
+    if (inner_end) next = after_inner(st) == K_FINAL ? PK_FINAL : PK_X;
+    if (next == PK_FINAL) st.final = 1;
+    return next;
+}
+
+// ---------------------------------------------------------------- persistent kernel
+// Workgroups claim (system, chunk) work items as in k_batched; the last chunk
+// of a phase completes it.  A launch runs every system to its end.
+__global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restrict__ sys, BGlobal* glob, int nsys,
+                                                           long long spin_limit) {
+    __shared__ int sh_sys, sh_chunk, sh_last, sh_stop;
+    __shared__ uint32_t sh_seq, sh_nseq;
+    __shared__ PState sh_p;
+    int s = (int)(blockIdx.x % (unsigned)nsys);
+    long long idle = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            sh_sys = -1;
+            for (int tries = 0; tries < nsys; ++tries, s = (s + 1 == nsys) ? 0 : s + 1) {
+                const int act = cload_i(&sys[s].ctl->active);
+                const unsigned long long w0 =
+                    __hip_atomic_load(gbl(&sys[s].ctl->claim), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!act || (int)(w0 & 0xffffffffull) >= sys[s].nchunk) continue;
+                const unsigned long long w = __hip_atomic_fetch_add(gbl(&sys[s].ctl->claim), 1ull, __ATOMIC_RELAXED,
+                                                                    __HIP_MEMORY_SCOPE_AGENT);
+                const int c = (int)(w & 0xffffffffull);
+                if (c < sys[s].nchunk) {
+                    sh_sys = s;
+                    sh_chunk = c;
+                    sh_seq = (uint32_t)(w >> 32);
+                    break;
+                }
+            }
+            if (sh_sys == -1) {
+                const int live = cload_i(&glob->active), err = cload_i(&glob->error);
+                if (live <= 0 || err != 0) sh_sys = -2;
+            }
+        }
+        __syncthreads();
+        const int me = __builtin_amdgcn_readfirstlane(sh_sys);
+        if (me == -2) return;
+        if (me < 0) {
+            if (++idle > spin_limit) {
+                if (threadIdx.x == 0) cstore_i(&glob->error, 1);
+                return;
+            }
+            __builtin_amdgcn_s_sleep(8);
+            __syncthreads();
+            continue;
+        }
+        idle = 0;
+        const PSys& B = sys[me];
+        const SysView<float> S = B.S;
+        PState* const pst = reinterpret_cast<PState*>(S.st);
+        const int chunk = __builtin_amdgcn_readfirstlane(sh_chunk);
+        const uint32_t seq = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh_seq);
+        const int kind = (int)(seq & 15u);
+        const int c0 = chunk * B.chunk;
+        const int c1 = min(S.n, c0 + B.chunk);
+        double* const part = S.red.part;
+        if (kind == PK_S) {
+            pover_units<kMaxDots, 3, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+                chunk_s_b(S, B.cf, B.b, B.x, u0, u1, acc);
+            });
+        } else if (kind == PK_R) {
+            pover_units<1, 0, 0u>(c0, c1, part, [&](int u0, int u1, double (&)[1]) { pchunk_r(B, u0, u1); });
+        } else if (kind == PK_X) {
+            const double scale = cload_d(&S.st->scale);
+            const bool zero = cload_i(&S.st->xzero) != 0;
+            pover_units<1, 0, 0u>(c0, c1, part, [&](int u0, int u1, double (&)[1]) {
+                chunk_x_b(S, B.x, u0, u1, scale, zero);
+            });
+        } else if (kind == PK_RF) {
+            pover_units<kMaxDots, 3, 4u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
+                chunk_r_b(S, B.cf, B.b, B.x, u0, u1, false, acc);
+            });
+        } else {
+            // the scalars and copy indices this phase reads, set by the last completion
+            const int zb = __builtin_amdgcn_readfirstlane(cload_i(&pst->zb));
+            const int tb = __builtin_amdgcn_readfirstlane(cload_i(&pst->tb));
+            const int flag = __builtin_amdgcn_readfirstlane(cload_i(&pst->ps.flag));
+            const float alpha = (float)cload_d(&S.st->alpha);
+            const float beta = (float)cload_d(&S.st->beta);
+            const float omega = (float)cload_d(&S.st->omega);
+            if (S.unit) prun_chunk<true>(B, kind, c0, c1, zb, tb, alpha, beta, omega, flag);
+            else prun_chunk<false>(B, kind, c0, c1, zb, tb, alpha, beta, omega, flag);
+        }
+        // every thread's stores (the unit sums included) reach memory before the
+        // chunk is counted done
+        wait_stores();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t t =
+                __hip_atomic_fetch_add(gbl(&B.ctl->done_cnt), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh_last = (t == (uint32_t)(B.nchunk - 1));
+        }
+        __syncthreads();
+        if (!sh_last) continue;
+        // this workgroup completes the phase
+        const uint32_t pw = pstate_fetch(pst);
+        const int nunit = (S.n + kUnitCells - 1) / kUnitCells;
+        double tot[kPD] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (kind == PK_A) psum_units<10, 0u>(part, nunit, tot);
+        else if (kind == PK_V) psum_units<5, 0u>(part, nunit, tot);
+        else if (kind == PK_S) psum_units<3, 0u>(part, nunit, tot);
+        else if (kind == PK_RF) psum_units<3, 4u>(part, nunit, tot);
+        pstate_put(pw, sh_p);
+        if (threadIdx.x == 0) {
+            const int next = pipe_complete(sh_p, kind, tot);
+            sh_stop = next == PK_FINAL ? 1 : 0;
+            sh_nseq = pseq_next(seq, next == PK_FINAL ? PK_A : next);
+        }
+        __syncthreads();
+        pstate_store(pst, sh_p);
+        __syncthreads();  // every word of the control block has reached memory
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(gbl(&B.ctl->done_cnt), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t nseq = sh_nseq;
+            if (sh_stop) {
+                cstore_i(&B.ctl->active, 0);
+                __hip_atomic_store(gbl(&B.ctl->claim), ((unsigned long long)nseq << 32) | (unsigned)B.nchunk,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                wait_stores();
+                __hip_atomic_fetch_add(&glob->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                wait_stores();
+                __hip_atomic_store(gbl(&B.ctl->claim), (unsigned long long)nseq << 32, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Arms a pipelined launch: every unfinished system takes part.
+__global__ __launch_bounds__(kThreads) void k_batched_pipe_arm(const PSys* sys, BGlobal* glob, int nsys) {
+    __shared__ int count;
+    if (threadIdx.x == 0) count = 0;
+    __syncthreads();
+    for (int s = threadIdx.x; s < nsys; s += kThreads) {
+        const bool fin = sys[s].S.st->final != 0;
+        const uint32_t seq = (uint32_t)(sys[s].ctl->claim >> 32);  // rewinds the chunk counter
+        sys[s].ctl->claim = (unsigned long long)seq << 32;
+        sys[s].ctl->active = fin ? 0 : 1;
+        sys[s].ctl->budget = 0;
+        sys[s].ctl->done_cnt = 0u;
+        if (!fin) atomicAdd(&count, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        glob->active = count;
+        glob->error = 0;
+        glob->t0 = wall_clock64();
+        glob->slice = 0;
+    }
+}
+
+// ---------------------------------------------------------------- host
+// A system's slice: the classical FP32 layout (its State space holds the
+// PState), then z, v and t twice each and w.
+static size_t pipe_batch_bytes(const Layout& Lo) {
+    return align256(Lo.bytes) + 7 * align256(Lo.n * sizeof(float));
+}
+
+// Tables: [BGlobal][PSys x cap][State* x cap][State x cap][JobStart x cap].
+static size_t pt_sys() { return align256(sizeof(BGlobal)); }
+static size_t pt_sptr(int cap) { return pt_sys() + align256((size_t)cap * sizeof(PSys)); }
+static size_t pt_gather(int cap) { return pt_sptr(cap) + align256((size_t)cap * sizeof(State*)); }
+static size_t pt_jobs(int cap) { return pt_gather(cap) + align256((size_t)cap * sizeof(State)); }
+static size_t pipe_table_bytes(int cap) { return pt_jobs(cap) + align256((size_t)cap * sizeof(JobStart)); }
+
+static PSys psys_entry(const EngineJob& j, const s7_options& o, int chunk) {
+    PSys P;
+    std::memset(&P, 0, sizeof(P));
+    P.S = make_view<float>(j.d, j.lo, o.jacobi, j.ws);
+    P.ctl = reinterpret_cast<BCtl*>(j.ws + j.lo.off_ctl);
+    const size_t base = align256(j.lo.bytes), span = align256(j.lo.n * sizeof(float));
+    auto vec = [&](int k) { return reinterpret_cast<float*>(j.ws + base + (size_t)k * span); };
+    P.z[0] = vec(0), P.z[1] = vec(1), P.v[0] = vec(2), P.v[1] = vec(3), P.t[0] = vec(4), P.t[1] = vec(5);
+    P.w = vec(6);
+    P.nchunk = (int)((j.lo.n + chunk - 1) / chunk);
+    P.chunk = chunk;
+    for (int a = 0; a < 7; ++a) P.cf.c[a] = j.coef[a];
+    P.b = j.b;
+    P.x = j.x;
+    return P;
+}
+
+// Runs the jobs (workspace slices filled in) in one pipelined launch.
+static int run_pipe_batch(std::vector<EngineJob*>& jobs, char* tables, int cap, const s7_options& o,
+                          hipStream_t s) {
+    const int nsys = (int)jobs.size();
+    if (nsys == 0) return S7_OK;
+    for (EngineJob* j : jobs) {
+        // the unit sums use kPD values per unit of the classical partial space
+        const size_t nunit = (j->lo.n + kUnitCells - 1) / kUnitCells;
+        if (nunit * kPD * sizeof(double) > j->lo.off_gpart - j->lo.off_part) {
+            set_error("pipelined batch: partial space too small");
+            return S7_EHIP;
+        }
+    }
+    // 1) job starts: working coefficient copies, State, first phase S
+    std::vector<JobStart> starts;
+    std::vector<State*> sptr;
+    size_t max_n = 1;
+    for (EngineJob* j : jobs) {
+        JobStart J = job_entry(*j, o);
+        J.first = PK_S;
+        starts.push_back(J);
+        sptr.push_back(reinterpret_cast<State*>(j->ws + j->lo.off_state));
+        max_n = std::max(max_n, j->lo.n);
+    }
+    JobStart* dj = reinterpret_cast<JobStart*>(tables + pt_jobs(cap));
+    S7_HIP(hipMemcpyAsync(dj, starts.data(), starts.size() * sizeof(JobStart), hipMemcpyHostToDevice, s));
+    S7_HIP(hipMemcpyAsync(tables + pt_sptr(cap), sptr.data(), sptr.size() * sizeof(State*), hipMemcpyHostToDevice,
+                          s));
+    const int gx = (int)std::min<size_t>(128, (max_n + kThreads - 1) / kThreads);
+    for (int k = 0; k < nsys; k += 65535) {
+        const unsigned ny = (unsigned)std::min(65535, nsys - k);
+        hipLaunchKernelGGL(k_jobs_start, dim3(gx, ny), dim3(kThreads), 0, s, (const JobStart*)(dj + k));
+    }
+    S7_CHECK_LAUNCH();
+    // 2) one persistent launch runs every job to its end
+    const int grid_cap = 1024;
+    const std::vector<int> chunks = launch_chunks(jobs, chunk_cells_of(o), grid_cap, o.chunk_cells == 0);
+    std::vector<PSys> table;
+    long long total_chunks = 0;
+    for (int i = 0; i < nsys; ++i) {
+        table.push_back(psys_entry(*jobs[i], o, chunks[i]));
+        total_chunks += table.back().nchunk;
+    }
+    BGlobal* glob = reinterpret_cast<BGlobal*>(tables);
+    PSys* dsys = reinterpret_cast<PSys*>(tables + pt_sys());
+    S7_HIP(hipMemcpyAsync(dsys, table.data(), table.size() * sizeof(PSys), hipMemcpyHostToDevice, s));
+    const int grid = (int)std::max(1LL, std::min<long long>(total_chunks, grid_cap));
+    hipLaunchKernelGGL(k_batched_pipe_arm, dim3(1), dim3(kThreads), 0, s, (const PSys*)dsys, glob, nsys);
+    hipLaunchKernelGGL(k_batched_pipe, dim3(grid), dim3(kThreads), 0, s, (const PSys*)dsys, glob, nsys,
+                       (long long)5000000);
+    S7_CHECK_LAUNCH();
+    BGlobal hg;
+    S7_HIP(hipMemcpyAsync(&hg, glob, sizeof(hg), hipMemcpyDeviceToHost, s));
+    S7_HIP(hipStreamSynchronize(s));
+    if (hg.error) {
+        set_error("pipelined batched launch: a workgroup exceeded its wait bound");
+        return S7_EHIP;
+    }
+    // 3) every job's State, in one transfer
+    State* gather = reinterpret_cast<State*>(tables + pt_gather(cap));
+    hipLaunchKernelGGL(k_gather_states, dim3((nsys * (int)(sizeof(State) / 8) + kThreads - 1) / kThreads),
+                       dim3(kThreads), 0, s, (State* const*)(tables + pt_sptr(cap)), gather, nsys);
+    S7_CHECK_LAUNCH();
+    std::vector<State> h((size_t)nsys);
+    S7_HIP(hipMemcpyAsync(h.data(), gather, (size_t)nsys * sizeof(State), hipMemcpyDeviceToHost, s));
+    S7_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < nsys; ++i) {
+        if (!h[i].final) {
+            set_error("pipelined batched launch: system %d did not finish", i);
+            return S7_EHIP;
+        }
+        finish_job(*jobs[i], h[i]);
+        jobs[i]->info.schedule = 4;
+    }
+    return S7_OK;
+}
+
+}  // namespace s7
+
+extern "C" {
+
+size_t s7_batched_workspace_bytes_pipelined(int32_t nsys, const s7_dims* d, const s7_options* opt) {
+    if (nsys < 1 || !d) return 0;
+    s7_options o;
+    options_or_default(opt, o);
+    size_t total = align256(pipe_table_bytes(nsys));
+    for (int i = 0; i < nsys; ++i) {
+        if (!dims_ok(d[i])) return 0;
+        total += align256(pipe_batch_bytes(make_layout(d[i], S7_FP32, o)));
+    }
+    return total;
+}
+
+int s7_bicgstab_solve_batched_pipelined(int32_t nsys, const s7_dims* d, const float* const* coef,
+                                        const double* const* b, double* const* x, const double* rtol,
+                                        const int32_t* max_iter, void* ws, size_t ws_bytes, const s7_options* opt,
+                                        s7_info* info, void* stream) {
+    clear_error();
+    s7_options o;
+    options_or_default(opt, o);
+    if (nsys < 1 || !d || !coef || !b || !x || !rtol || !max_iter || !ws || ((uintptr_t)ws & 255u) != 0) {
+        set_error("s7_bicgstab_solve_batched_pipelined: invalid argument");
+        return S7_EINVAL;
+    }
+    for (int i = 0; i < nsys; ++i) {
+        bool ok = dims_ok(d[i]) && b[i] && x[i] && rtol[i] > 0.0 && max_iter[i] >= 0;
+        for (int a = 0; a < 7 && ok; ++a) ok = coef[7 * i + a] != nullptr;
+        if (!ok) {
+            set_error("s7_bicgstab_solve_batched_pipelined: invalid argument for system %d", i);
+            return S7_EINVAL;
+        }
+    }
+    const size_t need = s7_batched_workspace_bytes_pipelined(nsys, d, &o);
+    if (ws_bytes < need) {
+        set_error("s7_bicgstab_solve_batched_pipelined: workspace too small (%zu < %zu)", ws_bytes, need);
+        return S7_EINVAL;
+    }
+    char* w = (char*)ws;
+    const hipStream_t s = (hipStream_t)stream;
+    const long long split = split_cells_of(o);
+    std::vector<EngineJob> jobs((size_t)nsys);
+    std::vector<EngineJob*> shared;
+    size_t off = align256(pipe_table_bytes(nsys));
+    const double t0 = now_ms();
+    for (int i = 0; i < nsys; ++i) {
+        EngineJob& j = jobs[i];
+        std::memset(&j, 0, sizeof(j));
+        j.d = d[i];
+        for (int a = 0; a < 7; ++a) j.coef[a] = coef[7 * i + a];
+        j.b = b[i];
+        j.x = x[i];
+        j.rtol = rtol[i];
+        j.max_iter = max_iter[i];
+        j.prec = S7_FP32;
+        j.ws = w + off;
+        j.lo = make_layout(d[i], S7_FP32, o);
+        j.ws_bytes = pipe_batch_bytes(j.lo);
+        j.t_start_ms = t0;
+        j.op = OP_7PT;
+        off += align256(j.ws_bytes);
+        if ((long long)d[i].nx * d[i].ny * d[i].nz < split) shared.push_back(&j);
+    }
+    int rc = run_pipe_batch(shared, w, nsys, o, s);
+    if (rc) return rc;
+    int worst = S7_OK;
+    for (int i = 0; i < nsys; ++i) {
+        EngineJob& j = jobs[i];
+        if ((long long)d[i].nx * d[i].ny * d[i].nz >= split) {
+            // a large system alone, on the multi-kernel pipelined path in its slice
+            rc = s7_bicgstab_solve_pipelined(j.d, j.coef, j.b, j.x, j.rtol, j.max_iter, j.ws, j.ws_bytes, &o,
+                                             &j.info, stream);
+            if (rc < 0) return rc;
+        }
+        if (info) info[i] = j.info;
+        if (j.info.status > worst) worst = j.info.status;
+    }
+    return worst;
+}
+
+}  // extern "C"

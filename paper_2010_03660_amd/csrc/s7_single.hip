@@ -1719,3 +1719,5 @@ int s7_bicgstab_solve_batched(int32_t nsys, const s7_dims* d, const float* const
 #include "s7_stencil9.hpp"
 // Pipelined BiCGStab (one reduction per iteration), on the 7-point operator.
 #include "s7_pipelined.hpp"
+// Pipelined BiCGStab for many systems in one persistent launch.
+#include "s7_batched_pipe.hpp"
