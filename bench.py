@@ -287,6 +287,78 @@ def batched_small_leg(s7, torch, dev, nsys: int = 256, side: int = 16):
     }
 
 
+# Bytes per cell and iteration of the pipelined batched iteration (FP32, Jacobi):
+# A reads r, w, p, s, r0, the stencil operands t, z, v and six coefficients and writes
+# p, s, z, v, q, y; B reads y, t, v, q, p, d and six coefficients and writes d, r, w, t.
+# The residual replacement every 10 iterations (about 20 B per cell and iteration) is
+# not counted.
+PIPE_BATCH_BYTES = (20 + 12 + 24 + 24) + (12 + 12 + 24 + 16)
+
+
+def pipelined_batched_leg(s7, torch, dev):
+    """The pipelined BiCGStab in the persistent batched kernel (two hand-offs per
+    iteration) beside the classical batched solve (three), on the two batched workloads:
+    64 systems of uneven size (seeds 1000+s, as the batched leg) and 256 systems of 16^3
+    (seeds 3000+s), FP32 to 1e-7, each timed as the median of five calls."""
+    import synth
+    out = {}
+    shapes64, seeds64 = synth.batch_shapes(64, seed=0)
+    for key, shapes, seeds in (("64_uneven", shapes64, seeds64),
+                               ("256_of_16cubed", [(16, 16, 16)] * 256, [3000 + k for k in range(256)])):
+        coefs, bs, xs, xst = [], [], [], []
+        for d, sd in zip(shapes, seeds):
+            n = d[0] * d[1] * d[2]
+            c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(7)]
+            xx = torch.empty(n, dtype=torch.float64, device=dev)
+            bb = torch.empty(n, dtype=torch.float64, device=dev)
+            s7.generate_problem(d, sd, 0, c, xx, bb)
+            coefs.append(c), bs.append(bb), xst.append(xx)
+            xs.append(torch.zeros(n, dtype=torch.float64, device=dev))
+        cells = [d[0] * d[1] * d[2] for d in shapes]
+        ns = len(shapes)
+        wsp = torch.empty(s7.batched_workspace_bytes_pipelined(shapes), dtype=torch.uint8, device=dev)
+        wsc = torch.empty(s7.batched_workspace_bytes(shapes), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        calls = {
+            "pipelined": s7.batched_pipelined_call(shapes, coefs, bs, xs, [1e-7] * ns, [2000] * ns, ws=wsp),
+            "classical": s7.batched_call(shapes, coefs, bs, xs, [1e-7] * ns, [2000] * ns, ws=wsc,
+                                         opt=s7.default_options(tune=1)),
+        }
+        res = {}
+        for name, call in calls.items():
+            def once():
+                for x in xs:
+                    x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, infos = call()
+                torch.cuda.synchronize()
+                return rc, infos, time.perf_counter() - t0
+
+            once()  # warm-up (the classical call autotunes its size class)
+            rc, infos, ts = repeat_timed(once)
+            dt = ts[len(ts) // 2]
+            iters = [i.iters for i in infos]
+            err = max(float(torch.linalg.vector_norm(x - xx) / torch.linalg.vector_norm(xx))
+                      for x, xx in zip(xs, xst))
+            cell_iters = sum(c * k for c, k in zip(cells, iters))
+            r = {"status": rc, "seconds": round(dt, 5), "seconds_min_max": [round(ts[0], 5), round(ts[-1], 5)],
+                 "systems_per_s": round(ns / dt, 1), "iters_min_max": [min(iters), max(iters)],
+                 "iters_total": sum(iters), "max_rel_err_vs_xstar": err,
+                 "max_rel_res_true": max(i.rel_res_true for i in infos)}
+            bpc = PIPE_BATCH_BYTES if name == "pipelined" else BATCH_BYTES
+            r["alg_GB/s"] = round(cell_iters * bpc / dt / 1e9, 1)
+            r["bytes_per_cell_iter"] = bpc
+            res[name] = r
+        res["workload"] = (f"{ns} systems, FP32, rtol 1e-7, " +
+                           ("sides uniform over {24,32,48,64,96,128}" if key == "64_uneven" else "16^3 each"))
+        res["pipelined_time_over_classical"] = round(res["pipelined"]["seconds"] / res["classical"]["seconds"], 3)
+        out[key] = res
+        del coefs, bs, xs, xst, wsp, wsc, calls
+        torch.cuda.empty_cache()
+    return out
+
+
 def cube256_leg(s7, torch, dev, steps: int, warmup: int, tune: bool):
     """256^3 with the anisotropic z-slab field (the z coefficients scaled up to 10x in a
     centred slab): `steps` fixed iterations timed on the graph path (iterations/s, GFLOPS
@@ -1226,6 +1298,8 @@ def main():
     if not args.no_pipelined:
         print("[bench] pipelined BiCGStab", file=sys.stderr, flush=True)
         out["pipelined"] = pipelined_leg(s7, torch, dev, args.steps)
+        print("[bench] pipelined BiCGStab, batched", file=sys.stderr, flush=True)
+        out["pipelined_batched"] = pipelined_batched_leg(s7, torch, dev)
     if not args.no_simple:
         print("[bench] SIMPLE pattern", file=sys.stderr, flush=True)
         out["simple_pattern"] = [simple_leg(s7, torch, dev, args.simple_dims, args.simple_outer),

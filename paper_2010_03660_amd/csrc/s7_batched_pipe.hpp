@@ -143,6 +143,18 @@ __device__ __forceinline__ void psum_units(const double* part, int nunit, double
 }
 
 // ---------------------------------------------------------------- chunk work
+// The cells of step `base` of a unit [u0, u1): lane l takes cells
+// base + 64 u + l for u < kPU, so its cells come in the order l, l + 64,
+// l + 128, ... whatever kPU is.  A cell at or past u1 is replaced by u0 and
+// keeps nothing.  The loads of a step are issued before any of its stores.
+constexpr int kPU = 2;
+__device__ __forceinline__ Cell pcell(int base, int u, int u0, int u1, const Mesh& m, int n) {
+    const int g = base + u * kWave + lane_id();
+    Cell c = cell_at(g < u1 ? g : u0, m, n);
+    c.own = g < u1;
+    return c;
+}
+
 // A of one unit.  zo, vo: the current z and v; zn, vn: the other copies, which
 // receive the new ones.  Sums: (r0, y), (r0, t), (r0, s), (r0, z), (r, r),
 // (q, y), (y, y), (q, q), (r0, q), (r0, v).
@@ -150,38 +162,54 @@ template <bool UNIT>
 __device__ void pchunk_a(const PSys& B, const float* zo, const float* vo, float* zn, float* vn, const float* t,
                          int u0, int u1, float a, float bt, float om, double (&acc)[kPD]) {
     const SysView<float>& S = B.S;
-    for (int g = u0 + lane_id(); g < u1; g += kWave) {
-        const Cell c = cell_at(g, S.m, S.n);
-        const int i = c.idx;
-        const Nbr<float> tv = cload_nbr(t, c), zv = cload_nbr(zo, c), vv = cload_nbr(vo, c);
-        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
-        const float r = cload(S.r + i), w = cload(B.w + i), p0 = cload(S.p + i), s0 = cload(S.s + i);
-        const float h = cload(S.rhat + i);
-        auto zf = [&](float tt, float zz, float vx) { return fmaT(bt, fmaT(-om, vx, zz), tt); };
-        const Nbr<float> z{zf(tv.c, zv.c, vv.c), zf(tv.w, zv.w, vv.w), zf(tv.e, zv.e, vv.e), zf(tv.s, zv.s, vv.s),
-                           zf(tv.n, zv.n, vv.n), zf(tv.b, zv.b, vv.b), zf(tv.t, zv.t, vv.t)};
-        const float v = apply7<float, float, UNIT, false>(k, z, c);
-        const float p = fmaT(bt, fmaT(-om, s0, p0), r);
-        const float s = fmaT(bt, fmaT(-om, zv.c, s0), w);
-        const float q = fmaT(-a, s, r);
-        const float y = fmaT(-a, z.c, w);
-        cstore(S.p + i, p);
-        cstore(S.s + i, s);
-        cstore(zn + i, z.c);
-        cstore(vn + i, v);
-        cstore(S.q + i, q);
-        cstore(S.y + i, y);
-        const double hd = h, yd = y, qd = q, rd = r;
-        acc[0] = fma(hd, yd, acc[0]);
-        acc[1] = fma(hd, (double)tv.c, acc[1]);
-        acc[2] = fma(hd, (double)s, acc[2]);
-        acc[3] = fma(hd, (double)z.c, acc[3]);
-        acc[4] = fma(rd, rd, acc[4]);
-        acc[5] = fma(qd, yd, acc[5]);
-        acc[6] = fma(yd, yd, acc[6]);
-        acc[7] = fma(qd, qd, acc[7]);
-        acc[8] = fma(hd, qd, acc[8]);
-        acc[9] = fma(hd, (double)v, acc[9]);
+    auto zf = [&](float tt, float zz, float vx) { return fmaT(bt, fmaT(-om, vx, zz), tt); };
+    for (int base = u0; base < u1; base += kPU * kWave) {
+        Cell c[kPU];
+        Nbr<float> z[kPU];
+        Coefs<float, UNIT> k[kPU];
+        float r[kPU], w[kPU], p0[kPU], s0[kPU], h[kPU], zc[kPU], tc[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            c[u] = pcell(base, u, u0, u1, S.m, S.n);
+            const int i = c[u].idx;
+            const Nbr<float> tv = cload_nbr(t, c[u]), zv = cload_nbr(zo, c[u]), vv = cload_nbr(vo, c[u]);
+            // z = t + beta (z - omega v) at the cell and its neighbours
+            z[u] = Nbr<float>{zf(tv.c, zv.c, vv.c), zf(tv.w, zv.w, vv.w), zf(tv.e, zv.e, vv.e),
+                              zf(tv.s, zv.s, vv.s), zf(tv.n, zv.n, vv.n), zf(tv.b, zv.b, vv.b),
+                              zf(tv.t, zv.t, vv.t)};
+            zc[u] = zv.c;
+            tc[u] = tv.c;
+            k[u] = load_coefs<float, UNIT>(S.c, i);
+            r[u] = cload(S.r + i), w[u] = cload(B.w + i), p0[u] = cload(S.p + i), s0[u] = cload(S.s + i);
+            h[u] = cload(S.rhat + i);
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            if (!c[u].own) continue;
+            const int i = c[u].idx;
+            const float v = apply7<float, float, UNIT, false>(k[u], z[u], c[u]);
+            const float p = fmaT(bt, fmaT(-om, s0[u], p0[u]), r[u]);
+            const float s = fmaT(bt, fmaT(-om, zc[u], s0[u]), w[u]);
+            const float q = fmaT(-a, s, r[u]);
+            const float y = fmaT(-a, z[u].c, w[u]);
+            cstore(S.p + i, p);
+            cstore(S.s + i, s);
+            cstore(zn + i, z[u].c);
+            cstore(vn + i, v);
+            cstore(S.q + i, q);
+            cstore(S.y + i, y);
+            const double hd = h[u], yd = y, qd = q, rd = r[u];
+            acc[0] = fma(hd, yd, acc[0]);
+            acc[1] = fma(hd, (double)tc[u], acc[1]);
+            acc[2] = fma(hd, (double)s, acc[2]);
+            acc[3] = fma(hd, (double)z[u].c, acc[3]);
+            acc[4] = fma(rd, rd, acc[4]);
+            acc[5] = fma(qd, yd, acc[5]);
+            acc[6] = fma(yd, yd, acc[6]);
+            acc[7] = fma(qd, qd, acc[7]);
+            acc[8] = fma(hd, qd, acc[8]);
+            acc[9] = fma(hd, (double)v, acc[9]);
+        }
     }
 }
 
@@ -190,20 +218,35 @@ template <bool UNIT>
 __device__ void pchunk_b(const PSys& B, const float* to, const float* v, float* tn, int u0, int u1, float a,
                          float om) {
     const SysView<float>& S = B.S;
-    for (int g = u0 + lane_id(); g < u1; g += kWave) {
-        const Cell c = cell_at(g, S.m, S.n);
-        const int i = c.idx;
-        const Nbr<float> yv = cload_nbr(S.y, c), tv = cload_nbr(to, c), vv = cload_nbr(v, c);
-        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
-        const float q = cload(S.q + i), p = cload(S.p + i), d = cload(S.d + i);
-        auto wf = [&](float yy, float tt, float vx) { return fmaT(-om, fmaT(-a, vx, tt), yy); };
-        const Nbr<float> w{wf(yv.c, tv.c, vv.c), wf(yv.w, tv.w, vv.w), wf(yv.e, tv.e, vv.e), wf(yv.s, tv.s, vv.s),
-                           wf(yv.n, tv.n, vv.n), wf(yv.b, tv.b, vv.b), wf(yv.t, tv.t, vv.t)};
-        const float tt = apply7<float, float, UNIT, false>(k, w, c);
-        cstore(S.d + i, fmaT(om, q, fmaT(a, p, d)));
-        cstore(S.r + i, fmaT(-om, yv.c, q));
-        cstore(B.w + i, w.c);
-        cstore(tn + i, tt);
+    auto wf = [&](float yy, float tt, float vx) { return fmaT(-om, fmaT(-a, vx, tt), yy); };
+    for (int base = u0; base < u1; base += kPU * kWave) {
+        Cell c[kPU];
+        Nbr<float> w[kPU];
+        Coefs<float, UNIT> k[kPU];
+        float q[kPU], p[kPU], d[kPU], yc[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            c[u] = pcell(base, u, u0, u1, S.m, S.n);
+            const int i = c[u].idx;
+            const Nbr<float> yv = cload_nbr(S.y, c[u]), tv = cload_nbr(to, c[u]), vv = cload_nbr(v, c[u]);
+            // w = y - omega (t - alpha v) at the cell and its neighbours
+            w[u] = Nbr<float>{wf(yv.c, tv.c, vv.c), wf(yv.w, tv.w, vv.w), wf(yv.e, tv.e, vv.e),
+                              wf(yv.s, tv.s, vv.s), wf(yv.n, tv.n, vv.n), wf(yv.b, tv.b, vv.b),
+                              wf(yv.t, tv.t, vv.t)};
+            yc[u] = yv.c;
+            k[u] = load_coefs<float, UNIT>(S.c, i);
+            q[u] = cload(S.q + i), p[u] = cload(S.p + i), d[u] = cload(S.d + i);
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            if (!c[u].own) continue;
+            const int i = c[u].idx;
+            const float tt = apply7<float, float, UNIT, false>(k[u], w[u], c[u]);
+            cstore(S.d + i, fmaT(om, q[u], fmaT(a, p[u], d[u])));
+            cstore(S.r + i, fmaT(-om, yc[u], q[u]));
+            cstore(B.w + i, w[u].c);
+            cstore(tn + i, tt);
+        }
     }
 }
 
@@ -217,15 +260,27 @@ __device__ void pchunk_b_half(const PSys& B, int u0, int u1, float a) {
 // x + d is the value the next phase stores into x.
 __device__ void pchunk_r(const PSys& B, int u0, int u1) {
     const SysView<float>& S = B.S;
-    for (int g = u0 + lane_id(); g < u1; g += kWave) {
-        const Cell c = cell_at(g, S.m, S.n);
-        const double* px = B.x + c.idx;
-        const float* pd = S.d + c.idx;
-        auto xd = [&](int o) { return cload(px + o) + (double)cload(pd + o); };
-        const Nbr<double> xv{xd(0), xd(c.dw), xd(c.de), xd(c.ds), xd(c.dn), xd(c.db), xd(c.dt)};
-        const Coefs<float, false> k = load_coefs<float, false>(B.cf.c, c.idx);
-        const double r0 = *gbl(B.b + c.idx) - apply7<double, float, false, true>(k, xv, c);
-        cstore(S.r + c.idx, (float)(S.unit ? r0 / (double)k.a[0] : r0));
+    for (int base = u0; base < u1; base += kPU * kWave) {
+        Cell c[kPU];
+        Nbr<double> xv[kPU];
+        Coefs<float, false> k[kPU];
+        double bi[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            c[u] = pcell(base, u, u0, u1, S.m, S.n);
+            const double* px = B.x + c[u].idx;
+            const float* pd = S.d + c[u].idx;
+            auto xd = [&](int o) { return cload(px + o) + (double)cload(pd + o); };
+            xv[u] = Nbr<double>{xd(0), xd(c[u].dw), xd(c[u].de), xd(c[u].ds), xd(c[u].dn), xd(c[u].db), xd(c[u].dt)};
+            k[u] = load_coefs<float, false>(B.cf.c, c[u].idx);
+            bi[u] = *gbl(B.b + c[u].idx);
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            if (!c[u].own) continue;
+            const double r0 = bi[u] - apply7<double, float, false, true>(k[u], xv[u], c[u]);
+            cstore(S.r + c[u].idx, (float)(S.unit ? r0 / (double)k[u].a[0] : r0));
+        }
     }
 }
 
@@ -233,17 +288,30 @@ __device__ void pchunk_r(const PSys& B, int u0, int u1) {
 template <bool UNIT>
 __device__ void pchunk_ws(const PSys& B, int u0, int u1) {
     const SysView<float>& S = B.S;
-    for (int g = u0 + lane_id(); g < u1; g += kWave) {
-        const Cell c = cell_at(g, S.m, S.n);
-        const int i = c.idx;
-        const Nbr<float> rv = cload_nbr(S.r, c), pv = cload_nbr(S.p, c);
-        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
-        const float dv = cload(S.d + i);
-        const double xv = cload(B.x + i);
-        cstore(B.w + i, apply7<float, float, UNIT, false>(k, rv, c));
-        cstore(S.s + i, apply7<float, float, UNIT, false>(k, pv, c));
-        cstore(B.x + i, xv + (double)dv);
-        cstore(S.d + i, 0.0f);
+    for (int base = u0; base < u1; base += kPU * kWave) {
+        Cell c[kPU];
+        Nbr<float> rv[kPU], pv[kPU];
+        Coefs<float, UNIT> k[kPU];
+        float dv[kPU];
+        double xv[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            c[u] = pcell(base, u, u0, u1, S.m, S.n);
+            const int i = c[u].idx;
+            rv[u] = cload_nbr(S.r, c[u]), pv[u] = cload_nbr(S.p, c[u]);
+            k[u] = load_coefs<float, UNIT>(S.c, i);
+            dv[u] = cload(S.d + i);
+            xv[u] = cload(B.x + i);
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            if (!c[u].own) continue;
+            const int i = c[u].idx;
+            cstore(B.w + i, apply7<float, float, UNIT, false>(k[u], rv[u], c[u]));
+            cstore(S.s + i, apply7<float, float, UNIT, false>(k[u], pv[u], c[u]));
+            cstore(B.x + i, xv[u] + (double)dv[u]);
+            cstore(S.d + i, 0.0f);
+        }
     }
 }
 
@@ -251,13 +319,22 @@ __device__ void pchunk_ws(const PSys& B, int u0, int u1) {
 template <bool UNIT>
 __device__ void pchunk_tz(const PSys& B, float* t, float* z, int u0, int u1) {
     const SysView<float>& S = B.S;
-    for (int g = u0 + lane_id(); g < u1; g += kWave) {
-        const Cell c = cell_at(g, S.m, S.n);
-        const int i = c.idx;
-        const Nbr<float> wv = cload_nbr(B.w, c), sv = cload_nbr(S.s, c);
-        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
-        cstore(t + i, apply7<float, float, UNIT, false>(k, wv, c));
-        cstore(z + i, apply7<float, float, UNIT, false>(k, sv, c));
+    for (int base = u0; base < u1; base += kPU * kWave) {
+        Cell c[kPU];
+        Nbr<float> wv[kPU], sv[kPU];
+        Coefs<float, UNIT> k[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            c[u] = pcell(base, u, u0, u1, S.m, S.n);
+            wv[u] = cload_nbr(B.w, c[u]), sv[u] = cload_nbr(S.s, c[u]);
+            k[u] = load_coefs<float, UNIT>(S.c, c[u].idx);
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            if (!c[u].own) continue;
+            cstore(t + c[u].idx, apply7<float, float, UNIT, false>(k[u], wv[u], c[u]));
+            cstore(z + c[u].idx, apply7<float, float, UNIT, false>(k[u], sv[u], c[u]));
+        }
     }
 }
 
@@ -265,27 +342,235 @@ __device__ void pchunk_tz(const PSys& B, float* t, float* z, int u0, int u1) {
 template <bool UNIT>
 __device__ void pchunk_v(const PSys& B, const float* z, float* v, int u0, int u1, double (&acc)[kPD]) {
     const SysView<float>& S = B.S;
-    for (int g = u0 + lane_id(); g < u1; g += kWave) {
-        const Cell c = cell_at(g, S.m, S.n);
-        const int i = c.idx;
-        const Nbr<float> zv = cload_nbr(z, c);
-        const Coefs<float, UNIT> k = load_coefs<float, UNIT>(S.c, i);
-        cstore(v + i, apply7<float, float, UNIT, false>(k, zv, c));
-        const double h = cload(S.rhat + i), r = cload(S.r + i);
-        acc[0] = fma(h, r, acc[0]);
-        acc[1] = fma(h, (double)cload(B.w + i), acc[1]);
-        acc[2] = fma(h, (double)cload(S.s + i), acc[2]);
-        acc[3] = fma(h, (double)zv.c, acc[3]);
-        acc[4] = fma(r, r, acc[4]);
+    for (int base = u0; base < u1; base += kPU * kWave) {
+        Cell c[kPU];
+        Nbr<float> zv[kPU];
+        Coefs<float, UNIT> k[kPU];
+        float h[kPU], r[kPU], w[kPU], s[kPU];
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            c[u] = pcell(base, u, u0, u1, S.m, S.n);
+            const int i = c[u].idx;
+            zv[u] = cload_nbr(z, c[u]);
+            k[u] = load_coefs<float, UNIT>(S.c, i);
+            h[u] = cload(S.rhat + i), r[u] = cload(S.r + i), w[u] = cload(B.w + i), s[u] = cload(S.s + i);
+        }
+#pragma unroll
+        for (int u = 0; u < kPU; ++u) {
+            if (!c[u].own) continue;
+            cstore(v + c[u].idx, apply7<float, float, UNIT, false>(k[u], zv[u], c[u]));
+            const double hd = h[u], rd = r[u];
+            acc[0] = fma(hd, rd, acc[0]);
+            acc[1] = fma(hd, (double)w[u], acc[1]);
+            acc[2] = fma(hd, (double)s[u], acc[2]);
+            acc[3] = fma(hd, (double)zv[u].c, acc[3]);
+            acc[4] = fma(rd, rd, acc[4]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- staged A and B
+// For systems with an even nx of at most kStageMaxNx, A and B take the chunk
+// one unit group (kStageTile cells) at a time, as the classical staged passes
+// do: the group's stencil operand (z for A, w for B) is formed once per cell,
+// with one row either side, from its three vectors into LDS; then wavefront w
+// takes unit w of the group on x-adjacent cell pairs, reading the centre and
+// the x and y neighbours from LDS and forming the z neighbours from coherent
+// loads.  Lane l visits the unit's pairs l, l + 64, ... in that order.
+//
+// sm[g - lo] = f1 (f2 x2[g] + x1[g]) + x0[g] for g in [lo, lo + cnt), 0
+// outside the system (A: x0, x1, x2 = t, z, v and f1, f2 = beta, -omega; B:
+// y, t, v and -omega, -alpha).  The values were written by other workgroups
+// of the launch, so the 16-byte loads bypass the XCD's L2 (volatile, system
+// scope); two steps' loads are issued before their LDS stores.
+__device__ __forceinline__ f32x4 vload4(const float* p) {
+    return *(volatile __attribute__((address_space(1))) f32x4*)gbl(reinterpret_cast<f32x4*>(const_cast<float*>(p)));
+}
+__device__ void stage3(const float* x0, const float* x1, const float* x2, float f1, float f2, int lo, int cnt, int n,
+                       float* sm) {
+    auto comb3 = [&](float a0, float a1, float a2) { return fmaT(f1, fmaT(f2, a2, a1), a0); };
+    const int nv = cnt / 4;
+    for (int e0 = (int)threadIdx.x; e0 < nv; e0 += 2 * kThreads) {
+        float a[2][3][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = e0 + h * kThreads;
+            const int g = lo + 4 * e;
+            if (e < nv && g >= 0 && g + 4 <= n) {
+                const f32x4 u = vload4(x0 + g), v = vload4(x1 + g), w = vload4(x2 + g);
+                a[h][0][0] = u.x, a[h][0][1] = u.y, a[h][0][2] = u.z, a[h][0][3] = u.w;
+                a[h][1][0] = v.x, a[h][1][1] = v.y, a[h][1][2] = v.z, a[h][1][3] = v.w;
+                a[h][2][0] = w.x, a[h][2][1] = w.y, a[h][2][2] = w.z, a[h][2][3] = w.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool in = e < nv && g + j >= 0 && g + j < n;
+                    a[h][0][j] = in ? cload(x0 + g + j) : 0.0f;
+                    a[h][1][j] = in ? cload(x1 + g + j) : 0.0f;
+                    a[h][2][j] = in ? cload(x2 + g + j) : 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = e0 + h * kThreads;
+            if (e >= nv) break;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) sm[4 * e + j] = comb3(a[h][0][j], a[h][1][j], a[h][2][j]);
+        }
+    }
+}
+
+// The combined operand of the pair at idx + off (the cells below or above).
+__device__ __forceinline__ F2 comb3_2(const float* x0, const float* x1, const float* x2, float f1, float f2, int i) {
+    const F2 a = cload2(x0 + i), b = cload2(x1 + i), c = cload2(x2 + i);
+    return F2{fmaT(f1, fmaT(f2, c.a, b.a), a.a), fmaT(f1, fmaT(f2, c.b, b.b), a.b)};
+}
+
+// A of the chunk [c0, c1), staged (sums as pchunk_a, per unit).
+template <bool UNIT>
+__device__ void pstaged_a(const PSys& B, const float* zo, const float* vo, float* zn, float* vn, const float* t,
+                          int c0, int c1, float a, float bt, float om, float* sm, double* part) {
+    const SysView<float>& S = B.S;
+    const int nx = S.m.nx;
+    for (int t0 = c0; t0 < c1; t0 += kStageTile) {
+        const int t1 = min(c1, t0 + kStageTile);
+        const int lo = (t0 - nx) >> 3 << 3, hi = (t1 + nx + 7) >> 3 << 3;
+        __syncthreads();  // the previous group's reads of sm are over
+        stage3(t, zo, vo, bt, -om, lo, hi - lo, S.n, sm);
+        __syncthreads();
+        const int u0 = t0 + wave_id() * kUnitCells;
+        if (u0 >= t1) continue;  // the same for the whole wavefront
+        const int u1 = min(t1, u0 + kUnitCells);
+        double acc[kPD] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        constexpr int kSP = 2;  // pairs per lane and step
+        for (int u = 0; u < kUnitCells / (2 * kWave); u += kSP) {
+            int idx[kSP];
+            bool own[kSP];
+            Coefs<float, UNIT> k0[kSP], k1[kSP];
+            F2 zb[kSP], zt[kSP], r[kSP], w[kSP], p[kSP], s[kSP], h[kSP], zc[kSP], tc[kSP];
+#pragma unroll
+            for (int q = 0; q < kSP; ++q) {
+                const int i = u0 + 2 * ((u + q) * kWave + lane_id());
+                own[q] = i < u1;
+                idx[q] = own[q] ? i : u0;
+                int db, dt;
+                z_offsets(idx[q], S.m, db, dt);
+                zb[q] = comb3_2(t, zo, vo, bt, -om, idx[q] + db);
+                zt[q] = comb3_2(t, zo, vo, bt, -om, idx[q] + dt);
+                load_coefs2_nt<float, UNIT>(S.c, idx[q], k0[q], k1[q]);
+                r[q] = cload2(S.r + idx[q]), w[q] = cload2(B.w + idx[q]), p[q] = cload2(S.p + idx[q]);
+                s[q] = cload2(S.s + idx[q]), h[q] = cload2(S.rhat + idx[q]);
+                zc[q] = cload2(zo + idx[q]), tc[q] = cload2(t + idx[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < kSP; ++q) {
+                if (!own[q]) continue;
+                const int i = idx[q];
+                Nbr<float> z0, z1;
+                lds_nbr2(sm, i - lo, nx, zb[q], zt[q], z0, z1);
+                const Cell none{};
+                const float v0 = apply7<float, float, UNIT, false>(k0[q], z0, none);
+                const float v1 = apply7<float, float, UNIT, false>(k1[q], z1, none);
+                const float pa = fmaT(bt, fmaT(-om, s[q].a, p[q].a), r[q].a);
+                const float pb = fmaT(bt, fmaT(-om, s[q].b, p[q].b), r[q].b);
+                const float sa = fmaT(bt, fmaT(-om, zc[q].a, s[q].a), w[q].a);
+                const float sb = fmaT(bt, fmaT(-om, zc[q].b, s[q].b), w[q].b);
+                const float qa = fmaT(-a, sa, r[q].a), qb = fmaT(-a, sb, r[q].b);
+                const float ya = fmaT(-a, z0.c, w[q].a), yb = fmaT(-a, z1.c, w[q].b);
+                cstore2(S.p + i, pa, pb);
+                cstore2(S.s + i, sa, sb);
+                cstore2(zn + i, z0.c, z1.c);
+                cstore2(vn + i, v0, v1);
+                cstore2(S.q + i, qa, qb);
+                cstore2(S.y + i, ya, yb);
+                const float hs[2] = {h[q].a, h[q].b}, ys[2] = {ya, yb}, ts[2] = {tc[q].a, tc[q].b};
+                const float ss[2] = {sa, sb}, zs[2] = {z0.c, z1.c}, rs[2] = {r[q].a, r[q].b};
+                const float qs[2] = {qa, qb}, vs[2] = {v0, v1};
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const double hd = hs[e], yd = ys[e], qd = qs[e], rd = rs[e];
+                    acc[0] = fma(hd, yd, acc[0]);
+                    acc[1] = fma(hd, (double)ts[e], acc[1]);
+                    acc[2] = fma(hd, (double)ss[e], acc[2]);
+                    acc[3] = fma(hd, (double)zs[e], acc[3]);
+                    acc[4] = fma(rd, rd, acc[4]);
+                    acc[5] = fma(qd, yd, acc[5]);
+                    acc[6] = fma(yd, yd, acc[6]);
+                    acc[7] = fma(qd, qd, acc[7]);
+                    acc[8] = fma(hd, qd, acc[8]);
+                    acc[9] = fma(hd, (double)vs[e], acc[9]);
+                }
+            }
+        }
+        punit_done<kPD, 0u>(acc, part, u0 / kUnitCells);
+    }
+}
+
+// B of the chunk [c0, c1), full update, staged.
+template <bool UNIT>
+__device__ void pstaged_b(const PSys& B, const float* to, const float* v, float* tn, int c0, int c1, float a,
+                          float om, float* sm) {
+    const SysView<float>& S = B.S;
+    const int nx = S.m.nx;
+    for (int t0 = c0; t0 < c1; t0 += kStageTile) {
+        const int t1 = min(c1, t0 + kStageTile);
+        const int lo = (t0 - nx) >> 3 << 3, hi = (t1 + nx + 7) >> 3 << 3;
+        __syncthreads();
+        stage3(S.y, to, v, -om, -a, lo, hi - lo, S.n, sm);
+        __syncthreads();
+        const int u0 = t0 + wave_id() * kUnitCells;
+        if (u0 >= t1) continue;
+        const int u1 = min(t1, u0 + kUnitCells);
+        constexpr int kSP = 2;
+        for (int u = 0; u < kUnitCells / (2 * kWave); u += kSP) {
+            int idx[kSP];
+            bool own[kSP];
+            Coefs<float, UNIT> k0[kSP], k1[kSP];
+            F2 wb[kSP], wt[kSP], q2[kSP], p2[kSP], d2[kSP], y2[kSP];
+#pragma unroll
+            for (int q = 0; q < kSP; ++q) {
+                const int i = u0 + 2 * ((u + q) * kWave + lane_id());
+                own[q] = i < u1;
+                idx[q] = own[q] ? i : u0;
+                int db, dt;
+                z_offsets(idx[q], S.m, db, dt);
+                wb[q] = comb3_2(S.y, to, v, -om, -a, idx[q] + db);
+                wt[q] = comb3_2(S.y, to, v, -om, -a, idx[q] + dt);
+                load_coefs2_nt<float, UNIT>(S.c, idx[q], k0[q], k1[q]);
+                q2[q] = cload2(S.q + idx[q]), p2[q] = cload2(S.p + idx[q]), d2[q] = cload2(S.d + idx[q]);
+                y2[q] = cload2(S.y + idx[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < kSP; ++q) {
+                if (!own[q]) continue;
+                const int i = idx[q];
+                Nbr<float> w0, w1;
+                lds_nbr2(sm, i - lo, nx, wb[q], wt[q], w0, w1);
+                const Cell none{};
+                const float ta = apply7<float, float, UNIT, false>(k0[q], w0, none);
+                const float tb = apply7<float, float, UNIT, false>(k1[q], w1, none);
+                cstore2(S.d + i, fmaT(om, q2[q].a, fmaT(a, p2[q].a, d2[q].a)),
+                        fmaT(om, q2[q].b, fmaT(a, p2[q].b, d2[q].b)));
+                cstore2(S.r + i, fmaT(-om, y2[q].a, q2[q].a), fmaT(-om, y2[q].b, q2[q].b));
+                cstore2(B.w + i, w0.c, w1.c);
+                cstore2(tn + i, ta, tb);
+            }
+        }
     }
 }
 
 // The phases of chunk [c0, c1) that apply the working operator.
 template <bool UNIT>
 __device__ __forceinline__ void prun_chunk(const PSys& B, int kind, int c0, int c1, int zb, int tb, float alpha,
-                                           float beta, float omega, int flag) {
+                                           float beta, float omega, int flag, float* sm) {
     double* const part = B.S.red.part;
-    if (kind == PK_A) {
+    const bool staged = B.S.pair_blocks > 0 && B.S.m.nx <= kStageMaxNx;
+    if (kind == PK_A && staged) {
+        pstaged_a<UNIT>(B, B.z[zb], B.v[zb], B.z[zb ^ 1], B.v[zb ^ 1], B.t[tb], c0, c1, alpha, beta, omega, sm, part);
+    } else if (kind == PK_B && staged && flag == 2) {
+        pstaged_b<UNIT>(B, B.t[tb], B.v[zb], B.t[tb ^ 1], c0, c1, alpha, omega, sm);
+    } else if (kind == PK_A) {
         pover_units<kPD, 10, 0u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kPD]) {
             pchunk_a<UNIT>(B, B.z[zb], B.v[zb], B.z[zb ^ 1], B.v[zb ^ 1], B.t[tb], u0, u1, alpha, beta, omega, acc);
         });
@@ -388,6 +673,8 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
     __shared__ int sh_sys, sh_chunk, sh_last, sh_stop;
     __shared__ uint32_t sh_seq, sh_nseq;
     __shared__ PState sh_p;
+    // the staged phases' LDS
+    __shared__ float sh_stage[kStageLds];
     int s = (int)(blockIdx.x % (unsigned)nsys);
     long long idle = 0;
     for (;;) {
@@ -459,8 +746,8 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
             const float alpha = (float)cload_d(&S.st->alpha);
             const float beta = (float)cload_d(&S.st->beta);
             const float omega = (float)cload_d(&S.st->omega);
-            if (S.unit) prun_chunk<true>(B, kind, c0, c1, zb, tb, alpha, beta, omega, flag);
-            else prun_chunk<false>(B, kind, c0, c1, zb, tb, alpha, beta, omega, flag);
+            if (S.unit) prun_chunk<true>(B, kind, c0, c1, zb, tb, alpha, beta, omega, flag, sh_stage);
+            else prun_chunk<false>(B, kind, c0, c1, zb, tb, alpha, beta, omega, flag, sh_stage);
         }
         // every thread's stores (the unit sums included) reach memory before the
         // chunk is counted done
@@ -597,8 +884,9 @@ static int run_pipe_batch(std::vector<EngineJob*>& jobs, char* tables, int cap, 
         hipLaunchKernelGGL(k_jobs_start, dim3(gx, ny), dim3(kThreads), 0, s, (const JobStart*)(dj + k));
     }
     S7_CHECK_LAUNCH();
-    // 2) one persistent launch runs every job to its end
-    const int grid_cap = 1024;
+    // 2) one persistent launch runs every job to its end; the kernel keeps three
+    // workgroups resident per CU (its register count allows three wavefronts per SIMD)
+    const int grid_cap = 768;
     const std::vector<int> chunks = launch_chunks(jobs, chunk_cells_of(o), grid_cap, o.chunk_cells == 0);
     std::vector<PSys> table;
     long long total_chunks = 0;

@@ -19,7 +19,7 @@ from tests.gpu_helpers import coef_dev, dev, host, problem, rel_err
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(1, 1, 1), (3, 1, 2), (9, 7, 5), (33, 17, 9), (64, 48, 20), (17, 5, 9), (24, 32, 48),
+SHAPES = [(1, 1, 1), (3, 1, 2), (9, 7, 5), (33, 17, 9), (64, 48, 20), (17, 5, 9), (24, 32, 48), (1030, 6, 4),
           (80, 64, 64)]
 
 
@@ -65,9 +65,10 @@ def test_batch_matches_oracle(s7, jacobi):
             assert abs(info.iters - r8.iters) <= max(5, 0.3 * r8.iters), (d, info.iters, r8.iters)
 
 
-def test_iterates_track_oracle(s7):
-    """Three copies of one system with caps of 1, 2 and 5 iterations, in one batch."""
-    dims = (33, 17, 9)
+@pytest.mark.parametrize("dims", [(33, 17, 9), (34, 17, 9)])
+def test_iterates_track_oracle(s7, dims):
+    """Three copies of one system with caps of 1, 2 and 5 iterations, in one batch: an
+    odd nx (single cells) and an even one (the LDS-staged phases on cell pairs)."""
     prob, A, b = problem(dims, seed=4)
     ks = [1, 2, 5]
     rc, infos, xs = run(s7, [dims] * 3, [(prob, A, b)] * 3, rtol=1e-300, max_iter=ks)
@@ -81,14 +82,15 @@ def test_iterates_track_oracle(s7):
 @pytest.mark.parametrize("chunk", [1024, 4096, 16384])
 def test_alone_equals_in_mix_bitwise(s7, chunk):
     """Every system's iterates are the same bits alone and in a batch, at any work-item
-    size, and under the default load-sized chunks."""
-    shapes = [(24, 32, 48), (17, 5, 9), (96, 48, 24), (2, 1, 1), (64, 48, 20)]
+    size, and under the default load-sized chunks: staged pairs (even nx up to 1024),
+    single cells (odd nx, and even nx above 1024)."""
+    shapes = [(24, 32, 48), (17, 5, 9), (96, 48, 24), (2, 1, 1), (64, 48, 20), (1030, 6, 4)]
     probs = [problem(d, seed=70 + k) for k, d in enumerate(shapes)]
     rc, infos, xs = run(s7, shapes, probs, rtol=1e-8, chunk_cells=chunk)
     rc0, infos0, xs0 = run(s7, shapes, probs, rtol=1e-8)
     for k in range(len(shapes)):
         assert np.array_equal(xs[k], xs0[k]) and infos[k].iters == infos0[k].iters, k
-    for k in (0, 2, 4):
+    for k in (0, 2, 4, 5):
         rc1, inf1, x1 = run(s7, [shapes[k]], [probs[k]], rtol=1e-8, chunk_cells=chunk)
         assert np.array_equal(x1[0], xs[k]), k
         assert inf1[0].iters == infos[k].iters
