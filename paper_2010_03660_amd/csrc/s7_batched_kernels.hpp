@@ -1113,14 +1113,19 @@ __device__ int after_resid(State& st, const double (&tot)[kMaxDots]) {
 // ---------------------------------------------------------------- persistent kernel
 // One launch runs systems of both operators: the system's op selects its
 // phase functions.
-__global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ sys, BGlobal* glob,
-                                                      int nsys, long long spin_limit) {
+__global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ sys, const int* __restrict__ home,
+                                                      BGlobal* glob, int nsys, long long spin_limit) {
     __shared__ int sh_sys, sh_chunk, sh_last, sh_stop, sh_budget;
     __shared__ uint32_t sh_seq, sh_nseq;
     __shared__ State sh_state;
     // the staged chunk functions' LDS
     __shared__ float sh_stage[kStageLds];
-    int s = (int)(blockIdx.x % (unsigned)nsys);
+    // The search for work starts at the workgroup's home system while that
+    // system is active (systems do not become active again within a launch),
+    // then at the system where work was last found.
+    const int h0 = home[blockIdx.x];
+    bool home_live = true;
+    int s = h0;
     long long idle = 0;
     for (;;) {
         if (threadIdx.x == 0) {
@@ -1128,10 +1133,12 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
             // word are loaded together, and the launch-wide words are read only
             // when no system has work.
             sh_sys = -1;
+            if (home_live) s = h0;
             for (int tries = 0; tries < nsys; ++tries, s = (s + 1 == nsys) ? 0 : s + 1) {
                 const int act = cload_i(&sys[s].ctl->active);
                 const unsigned long long w0 =
                     __hip_atomic_load(gbl(&sys[s].ctl->claim), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!act && s == h0) home_live = false;
                 if (!act || (int)(w0 & 0xffffffffull) >= sys[s].nchunk) continue;
                 const unsigned long long w = __hip_atomic_fetch_add(
                     gbl(&sys[s].ctl->claim), 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

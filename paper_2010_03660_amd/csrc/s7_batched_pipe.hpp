@@ -668,22 +668,27 @@ __device__ int pipe_complete(PState& P, int kind, const double (&tot)[kPD]) {
 // ---------------------------------------------------------------- persistent kernel
 // Workgroups claim (system, chunk) work items as in k_batched; the last chunk
 // of a phase completes it.  A launch runs every system to its end.
-__global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restrict__ sys, BGlobal* glob, int nsys,
-                                                           long long spin_limit) {
+__global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restrict__ sys, const int* __restrict__ home,
+                                                           BGlobal* glob, int nsys, long long spin_limit) {
     __shared__ int sh_sys, sh_chunk, sh_last, sh_stop;
     __shared__ uint32_t sh_seq, sh_nseq;
     __shared__ PState sh_p;
     // the staged phases' LDS
     __shared__ float sh_stage[kStageLds];
-    int s = (int)(blockIdx.x % (unsigned)nsys);
+    // the search for work starts at the home system while it is active (as in k_batched)
+    const int h0 = home[blockIdx.x];
+    bool home_live = true;
+    int s = h0;
     long long idle = 0;
     for (;;) {
         if (threadIdx.x == 0) {
             sh_sys = -1;
+            if (home_live) s = h0;
             for (int tries = 0; tries < nsys; ++tries, s = (s + 1 == nsys) ? 0 : s + 1) {
                 const int act = cload_i(&sys[s].ctl->active);
                 const unsigned long long w0 =
                     __hip_atomic_load(gbl(&sys[s].ctl->claim), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (!act && s == h0) home_live = false;
                 if (!act || (int)(w0 & 0xffffffffull) >= sys[s].nchunk) continue;
                 const unsigned long long w = __hip_atomic_fetch_add(gbl(&sys[s].ctl->claim), 1ull, __ATOMIC_RELAXED,
                                                                     __HIP_MEMORY_SCOPE_AGENT);
@@ -826,12 +831,13 @@ static size_t pipe_batch_bytes(const Layout& Lo) {
     return align256(Lo.bytes) + 7 * align256(Lo.n * sizeof(float));
 }
 
-// Tables: [BGlobal][PSys x cap][State* x cap][State x cap][JobStart x cap].
+// Tables: [BGlobal][PSys x cap][State* x cap][State x cap][JobStart x cap][home x kMaxPersistentGrid].
 static size_t pt_sys() { return align256(sizeof(BGlobal)); }
 static size_t pt_sptr(int cap) { return pt_sys() + align256((size_t)cap * sizeof(PSys)); }
 static size_t pt_gather(int cap) { return pt_sptr(cap) + align256((size_t)cap * sizeof(State*)); }
 static size_t pt_jobs(int cap) { return pt_gather(cap) + align256((size_t)cap * sizeof(State)); }
-static size_t pipe_table_bytes(int cap) { return pt_jobs(cap) + align256((size_t)cap * sizeof(JobStart)); }
+static size_t pt_home(int cap) { return pt_jobs(cap) + align256((size_t)cap * sizeof(JobStart)); }
+static size_t pipe_table_bytes(int cap) { return pt_home(cap) + align256((size_t)kMaxPersistentGrid * sizeof(int)); }
 
 static PSys psys_entry(const EngineJob& j, const s7_options& o, int chunk) {
     PSys P;
@@ -898,9 +904,15 @@ static int run_pipe_batch(std::vector<EngineJob*>& jobs, char* tables, int cap, 
     PSys* dsys = reinterpret_cast<PSys*>(tables + pt_sys());
     S7_HIP(hipMemcpyAsync(dsys, table.data(), table.size() * sizeof(PSys), hipMemcpyHostToDevice, s));
     const int grid = (int)std::max(1LL, std::min<long long>(total_chunks, grid_cap));
+    // home systems in proportion to cell count, as for the classical kernel
+    std::vector<double> cells;
+    for (const PSys& b : table) cells.push_back((double)b.S.n);
+    const std::vector<int> home = weighted_homes(cells, grid);
+    int* dhome = reinterpret_cast<int*>(tables + pt_home(cap));
+    S7_HIP(hipMemcpyAsync(dhome, home.data(), home.size() * sizeof(int), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_batched_pipe_arm, dim3(1), dim3(kThreads), 0, s, (const PSys*)dsys, glob, nsys);
-    hipLaunchKernelGGL(k_batched_pipe, dim3(grid), dim3(kThreads), 0, s, (const PSys*)dsys, glob, nsys,
-                       (long long)5000000);
+    hipLaunchKernelGGL(k_batched_pipe, dim3(grid), dim3(kThreads), 0, s, (const PSys*)dsys, (const int*)dhome, glob,
+                       nsys, (long long)5000000);
     S7_CHECK_LAUNCH();
     BGlobal hg;
     S7_HIP(hipMemcpyAsync(&hg, glob, sizeof(hg), hipMemcpyDeviceToHost, s));

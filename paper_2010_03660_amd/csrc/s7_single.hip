@@ -1023,15 +1023,20 @@ static int solve_ir(s7_dims d, const Coef7& cf, const double* b, double* x, doub
 // runs the rest of its solve (iterations, refinement steps, epilogue).
 enum JobStage { J_NEW = 0, J_RUN = 1 };
 
-// Engine tables: [BGlobal][BSys x cap][State* x cap][State x cap][JobStart x cap].
+// Engine tables: [BGlobal][BSys x cap][State* x cap][State x cap][JobStart x cap][home x kMaxPersistentGrid].
 static size_t off_sys() { return align256(sizeof(BGlobal)); }
 static size_t off_sptr(int cap) { return off_sys() + align256((size_t)cap * sizeof(BSys)); }
 static size_t off_sgather(int cap) { return off_sptr(cap) + align256((size_t)cap * sizeof(State*)); }
 
 static size_t off_jobs(int cap) { return off_sgather(cap) + align256((size_t)cap * sizeof(State)); }
 
+static size_t off_home(int cap) { return off_jobs(cap) + align256((size_t)cap * sizeof(JobStart)); }
+
+// The most workgroups of a persistent launch (the home table's length).
+constexpr int kMaxPersistentGrid = 1024;
+
 size_t engine_table_bytes(int capacity) {
-    return off_jobs(capacity) + align256((size_t)capacity * sizeof(JobStart));
+    return off_home(capacity) + align256((size_t)kMaxPersistentGrid * sizeof(int));
 }
 
 static int chunk_cells_of(const s7_options& o);
@@ -1230,6 +1235,24 @@ int BatchEngine::read_states(std::vector<State>& h) {
     return S7_OK;
 }
 
+// Each workgroup's home system, where its search for work starts while that
+// system is active: the systems in table order, each taking a share of the
+// grid's workgroups in proportion to its cell count.  A large system thus has
+// many workgroups returning to it from the start, instead of the uniform share
+// that leaves it running alone at the end of the launch.
+static std::vector<int> weighted_homes(const std::vector<double>& cells, int grid) {
+    const int nsys = (int)cells.size();
+    std::vector<double> cum((size_t)nsys + 1, 0.0);
+    for (int i = 0; i < nsys; ++i) cum[(size_t)i + 1] = cum[(size_t)i] + cells[(size_t)i];
+    std::vector<int> home((size_t)grid);
+    for (int b = 0; b < grid; ++b) {
+        const double at = (b + 0.5) / grid * cum[(size_t)nsys];
+        const int h = (int)(std::upper_bound(cum.begin() + 1, cum.end(), at) - (cum.begin() + 1));
+        home[(size_t)b] = h < nsys ? h : nsys - 1;
+    }
+    return home;
+}
+
 int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk, int grid_cap,
                         long long slice) {
     BGlobal* glob = reinterpret_cast<BGlobal*>(tables_);
@@ -1240,12 +1263,18 @@ int BatchEngine::launch(const std::vector<BSys>& table, int epoch_key, int chunk
     for (const BSys& b : table) total_chunks += b.nchunk;
     int grid = (int)(total_chunks < grid_cap ? total_chunks : grid_cap);
     if (grid < 1) grid = 1;
+    if (grid > kMaxPersistentGrid) grid = kMaxPersistentGrid;
+    std::vector<double> cells;
+    for (const BSys& b : table) cells.push_back((double)b.S.n);
+    const std::vector<int> home = weighted_homes(cells, grid);
+    int* dhome = reinterpret_cast<int*>(tables_ + off_home(cap_));
+    S7_HIP(hipMemcpyAsync(dhome, home.data(), home.size() * sizeof(int), hipMemcpyHostToDevice, st_));
     const long long spin_limit = 5000000;
     auto body = [&](hipStream_t cs) {
         hipLaunchKernelGGL(k_batched_arm, dim3(1), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
                            slice);
-        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, glob, nsys,
-                           spin_limit);
+        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(kThreads), 0, cs, (const BSys*)dsys, (const int*)dhome,
+                           glob, nsys, spin_limit);
     };
     GraphRef g;  // held until the launch has completed
     if (graph_) {
