@@ -1115,7 +1115,7 @@ __device__ int after_resid(State& st, const double (&tot)[kMaxDots]) {
 // phase functions.
 __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ sys, const int* __restrict__ home,
                                                       BGlobal* glob, int nsys, long long spin_limit) {
-    __shared__ int sh_sys, sh_chunk, sh_last, sh_stop, sh_budget;
+    __shared__ int sh_sys, sh_chunk, sh_last, sh_stop, sh_budget, sh_direct;
     __shared__ uint32_t sh_seq, sh_nseq;
     __shared__ State sh_state;
     // the staged chunk functions' LDS
@@ -1127,8 +1127,11 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
     bool home_live = true;
     int s = h0;
     long long idle = 0;
+    if (threadIdx.x == 0) sh_direct = 0;
     for (;;) {
-        if (threadIdx.x == 0) {
+        // A one-chunk phase's completer has already taken the next phase's chunk
+        // (sh_sys, sh_chunk and sh_seq are set): no search.
+        if (threadIdx.x == 0 && !sh_direct) {
             // Each probe is a round trip to memory: the system's flag and claim
             // word are loaded together, and the launch-wide words are read only
             // when no system has work.
@@ -1221,10 +1224,16 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
         // the chunk is counted done.
         wait_stores();
         __syncthreads();
+        // a phase of one chunk is complete once its chunk is: no count
         if (threadIdx.x == 0) {
-            const uint32_t t = __hip_atomic_fetch_add(gbl(&B.ctl->done_cnt), 1u, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-            sh_last = (t == (uint32_t)(B.nchunk - 1));
+            sh_direct = 0;
+            if (B.nchunk == 1) {
+                sh_last = 1;
+            } else {
+                const uint32_t t = __hip_atomic_fetch_add(gbl(&B.ctl->done_cnt), 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                sh_last = (t == (uint32_t)(B.nchunk - 1));
+            }
         }
         __syncthreads();
         if (!sh_last) continue;
@@ -1298,6 +1307,17 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 wait_stores();
                 __hip_atomic_fetch_add(&glob->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (B.nchunk == 1) {
+                // the next phase's only chunk is taken here: the claim word is
+                // published with its chunk counter exhausted, and this workgroup
+                // goes on with the same system
+                wait_stores();
+                __hip_atomic_store(gbl(&B.ctl->claim), ((unsigned long long)nseq << 32) | 1ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                sh_sys = me;
+                sh_chunk = 0;
+                sh_seq = nseq;
+                sh_direct = 1;
             } else {
                 wait_stores();
                 __hip_atomic_store(gbl(&B.ctl->claim), (unsigned long long)nseq << 32, __ATOMIC_RELAXED,
