@@ -670,7 +670,7 @@ __device__ int pipe_complete(PState& P, int kind, const double (&tot)[kPD]) {
 // of a phase completes it.  A launch runs every system to its end.
 __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restrict__ sys, const int* __restrict__ home,
                                                            BGlobal* glob, int nsys, long long spin_limit) {
-    __shared__ int sh_sys, sh_chunk, sh_last, sh_stop;
+    __shared__ int sh_sys, sh_chunk, sh_last, sh_stop, sh_direct;
     __shared__ uint32_t sh_seq, sh_nseq;
     __shared__ PState sh_p;
     // the staged phases' LDS
@@ -680,8 +680,10 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
     bool home_live = true;
     int s = h0;
     long long idle = 0;
+    if (threadIdx.x == 0) sh_direct = 0;
     for (;;) {
-        if (threadIdx.x == 0) {
+        // a one-chunk phase's completer has already taken the next phase's chunk
+        if (threadIdx.x == 0 && !sh_direct) {
             sh_sys = -1;
             if (home_live) s = h0;
             for (int tries = 0; tries < nsys; ++tries, s = (s + 1 == nsys) ? 0 : s + 1) {
@@ -759,9 +761,14 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
         wait_stores();
         __syncthreads();
         if (threadIdx.x == 0) {
-            const uint32_t t =
-                __hip_atomic_fetch_add(gbl(&B.ctl->done_cnt), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            sh_last = (t == (uint32_t)(B.nchunk - 1));
+            sh_direct = 0;
+            if (B.nchunk == 1) {
+                sh_last = 1;  // a phase of one chunk: no count
+            } else {
+                const uint32_t t =
+                    __hip_atomic_fetch_add(gbl(&B.ctl->done_cnt), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sh_last = (t == (uint32_t)(B.nchunk - 1));
+            }
         }
         __syncthreads();
         if (!sh_last) continue;
@@ -791,6 +798,15 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 wait_stores();
                 __hip_atomic_fetch_add(&glob->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else if (B.nchunk == 1) {
+                // the next phase's only chunk is taken here (as in k_batched)
+                wait_stores();
+                __hip_atomic_store(gbl(&B.ctl->claim), ((unsigned long long)nseq << 32) | 1ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                sh_sys = me;
+                sh_chunk = 0;
+                sh_seq = nseq;
+                sh_direct = 1;
             } else {
                 wait_stores();
                 __hip_atomic_store(gbl(&B.ctl->claim), (unsigned long long)nseq << 32, __ATOMIC_RELAXED,
