@@ -1128,9 +1128,14 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
     int s = h0;
     long long idle = 0;
     if (threadIdx.x == 0) sh_direct = 0;
+    // the launch's time slice, set by the arm step
+    const long long slice = glob->slice, t_arm = glob->t0;
     for (;;) {
         // A one-chunk phase's completer has already taken the next phase's chunk
-        // (sh_sys, sh_chunk and sh_seq are set): no search.
+        // (sh_sys, sh_chunk and sh_seq are set): no search.  While it goes on
+        // so, the system is resident in the workgroup: its State's current copy
+        // is the LDS one (sh_state) and its budget is sh_budget; memory holds
+        // them again once the system stops.
         if (threadIdx.x == 0 && !sh_direct) {
             // Each probe is a round trip to memory: the system's flag and claim
             // word are loaded together, and the launch-wide words are read only
@@ -1181,18 +1186,20 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
         const bool op9 = __builtin_amdgcn_readfirstlane(B.op) == OP_9PT;
         const int chunk = __builtin_amdgcn_readfirstlane(sh_chunk);
         const uint32_t seq = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh_seq);
+        const bool res = __builtin_amdgcn_readfirstlane(sh_direct) != 0;
         const int kind = (int)(seq & 7u);
         const int c0 = chunk * B.chunk;
         const int c1 = min(S.n, c0 + B.chunk);
         double* const part = S.red.part;
+        // the State's scalars this phase reads: from the resident copy, or from memory
         if (kind == K_X) {
-            const double scale = cload_d(&S.st->scale);
-            const bool zero = cload_i(&S.st->xzero) != 0;
+            const double scale = res ? sh_state.scale : cload_d(&S.st->scale);
+            const bool zero = (res ? sh_state.xzero : cload_i(&S.st->xzero)) != 0;
             over_units<0, 0u>(c0, c1, part, [&](int u0, int u1, double (&)[kMaxDots]) {
                 chunk_x_b(S, B.x, u0, u1, scale, zero);
             });
         } else if (kind == K_R) {
-            const bool ir = cload_i(&S.st->ir) != 0;
+            const bool ir = (res ? sh_state.ir : cload_i(&S.st->ir)) != 0;
             over_units<3, 4u>(c0, c1, part, [&](int u0, int u1, double (&acc)[kMaxDots]) {
                 if (op9) chunk_r_b9(S, coef9_of(B.cf, B.cf9), B.b, B.x, u0, u1, ir, acc);
                 else chunk_r_b(S, B.cf, B.b, B.x, u0, u1, ir, acc);
@@ -1203,10 +1210,10 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
                 else chunk_s_b(S, B.cf, B.b, B.x, u0, u1, acc);
             });
         } else {
-            const float alpha = (float)cload_d(&S.st->alpha);
-            const float omega = (float)cload_d(&S.st->omega);
-            const float beta = (float)cload_d(&S.st->beta);
-            const float inv_scale = kind == K_I ? (float)(1.0 / cload_d(&S.st->scale)) : 1.0f;
+            const float alpha = (float)(res ? sh_state.alpha : cload_d(&S.st->alpha));
+            const float omega = (float)(res ? sh_state.omega : cload_d(&S.st->omega));
+            const float beta = (float)(res ? sh_state.beta : cload_d(&S.st->beta));
+            const float inv_scale = kind == K_I ? (float)(1.0 / (res ? sh_state.scale : cload_d(&S.st->scale))) : 1.0f;
             if (op9) {
                 if (tag == 0) run_chunk9<float>(S, B.wk9, kind, c0, c1, alpha, omega, beta, inv_scale, sh_stage, part);
                 else if (tag == 1)
@@ -1240,14 +1247,16 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
         // this workgroup completes the phase: sum the units' sums in unit order.
         // The State's words are loaded first, so that they and the sums share
         // one memory round trip.
-        const uint32_t stw = state_fetch(S.st);
+        // (a resident system's LDS copy is already current)
+        const uint32_t stw = res ? 0u : state_fetch(S.st);
         const int nunit = (S.n + kUnitCells - 1) / kUnitCells;
         double tot[kMaxDots] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (kind == K_R) sum_range<kMaxDots, 4u, true>(part, 0, nunit, tot);
         else if (kND[kind] > 0) sum_range<kMaxDots, 0u, true>(part, 0, nunit, tot);
         // the private state copy lives in LDS: a register copy would raise the
         // register count of the whole kernel
-        state_put(stw, sh_state);
+        if (!res) state_put(stw, sh_state);
+        else __syncthreads();
         if (threadIdx.x == 0) {
             State& st = sh_state;
             int next = K_FINAL;
@@ -1275,29 +1284,32 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
                 }
             }
             if ((kind <= K_P3 || kind == K_I || kind == K_S) && st.done) next = after_inner(st);
-            int32_t budget = cload_i(&B.ctl->budget);
+            int32_t budget = res ? sh_budget : cload_i(&B.ctl->budget);
             bool stop = next == K_FINAL;
             if (iter_done && next == K_P1) {
                 budget -= 1;
                 stop = budget <= 0;
             }
             // time slice: any phase boundary is a resumable point
-            const long long slice = __hip_atomic_load(&glob->slice, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (slice > 0 &&
-                wall_clock64() - __hip_atomic_load(&glob->t0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > slice)
-                stop = true;
+            if (slice > 0 && wall_clock64() - t_arm > slice) stop = true;
             if (next == K_FINAL) st.final = 1;
             sh_stop = stop ? 1 : 0;
             sh_budget = budget;
             sh_nseq = seq_next(seq, next == K_FINAL ? K_P1 : next);
         }
         __syncthreads();
-        state_store(S.st, sh_state);
-        __syncthreads();  // every word of the State has reached memory
+        // a system that goes on resident keeps its State in LDS only
+        const bool stay = !sh_stop && B.nchunk == 1;
+        if (!stay) {
+            state_store(S.st, sh_state);
+            __syncthreads();  // every word of the State has reached memory
+        }
         if (threadIdx.x == 0) {
-            __hip_atomic_store(gbl(&B.ctl->done_cnt), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            cstore_i(&B.ctl->budget, sh_budget);
             const uint32_t nseq = sh_nseq;
+            if (!stay) {
+                __hip_atomic_store(gbl(&B.ctl->done_cnt), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                cstore_i(&B.ctl->budget, sh_budget);
+            }
             if (sh_stop) {
                 cstore_i(&B.ctl->active, 0);
                 // Park the claim word on the phase to resume, with its chunk counter
@@ -1307,13 +1319,15 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BSys* __restrict__ s
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 wait_stores();
                 __hip_atomic_fetch_add(&glob->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if (B.nchunk == 1) {
-                // the next phase's only chunk is taken here: the claim word is
-                // published with its chunk counter exhausted, and this workgroup
-                // goes on with the same system
-                wait_stores();
-                __hip_atomic_store(gbl(&B.ctl->claim), ((unsigned long long)nseq << 32) | 1ull, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            } else if (stay) {
+                // the next phase's only chunk is taken here, and this workgroup
+                // goes on with the same system.  On the way in, the claim word is
+                // published with its chunk counter exhausted, so that no other
+                // workgroup claims the system; it is not written again until the
+                // system stops.
+                if (!res)
+                    __hip_atomic_store(gbl(&B.ctl->claim), ((unsigned long long)nseq << 32) | 1ull,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sh_sys = me;
                 sh_chunk = 0;
                 sh_seq = nseq;
