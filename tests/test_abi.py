@@ -191,3 +191,34 @@ def test_host_side_argument_checks_pipelined():
     assert rc == B.EINVAL
     rc = lib.s7_bicgstab_solve_pipelined(d, coef, 512, 768, 1e-8, 10, 1032, 1 << 30, None, C.byref(info), 0)
     assert rc == B.EINVAL  # workspace not 256-byte aligned
+
+
+def test_host_side_argument_checks_batched_pipelined():
+    """The pipelined batched call validates every system on the host before any device
+    work; its workspace is the tables plus, per system, a slice that also holds the
+    multi-kernel pipelined workspace (a large system is solved there alone)."""
+    from paper_2010_03660_amd import binding as B
+    lib = B.lib()
+    dims = (B.Dims * 2)(B.Dims(40, 30, 20), B.Dims(3, 1, 2))
+    total = lib.s7_batched_workspace_bytes_pipelined(2, dims, None)
+    singles = sum(lib.s7_workspace_bytes_pipelined(d, None) for d in (B.Dims(40, 30, 20), B.Dims(3, 1, 2)))
+    assert total > singles
+    assert lib.s7_batched_workspace_bytes_pipelined(0, dims, None) == 0
+    bad = (B.Dims * 2)(B.Dims(40, 30, 20), B.Dims(0, 1, 2))
+    assert lib.s7_batched_workspace_bytes_pipelined(2, bad, None) == 0
+    coef = (C.c_void_p * 14)(*([256] * 14))
+    bp = (C.c_void_p * 2)(512, 768)
+    xp = (C.c_void_p * 2)(1024, 1280)
+    rt = (C.c_double * 2)(1e-8, 1e-8)
+    mi = (C.c_int32 * 2)(10, 10)
+    infos = (B.Info * 2)()
+
+    def call(d=dims, coef_=coef, rt_=rt, mi_=mi, ws=4096, wsb=1 << 30):
+        return lib.s7_bicgstab_solve_batched_pipelined(2, d, coef_, bp, xp, rt_, mi_, ws, wsb, None, infos, 0)
+    assert call(bad) == B.EINVAL and "system 1" in B.last_error()
+    missing = (C.c_void_p * 14)(*([256] * 13 + [None]))
+    assert call(coef_=missing) == B.EINVAL and "system 1" in B.last_error()
+    assert call(rt_=(C.c_double * 2)(float("nan"), 1e-8)) == B.EINVAL and "system 0" in B.last_error()
+    assert call(mi_=(C.c_int32 * 2)(10, -1)) == B.EINVAL and "system 1" in B.last_error()
+    assert call(wsb=16) == B.EINVAL and "workspace" in B.last_error()
+    assert call(ws=4100) == B.EINVAL  # not 256-byte aligned
