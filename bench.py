@@ -1044,6 +1044,50 @@ def probe_leg(s7, torch, dev, counters_only: bool):
     return out
 
 
+# The P2 kernel designs of s7_p2_design_probe, in the order they are reported
+P2_DESIGNS = [("flat cell pairs", 0, 0), ("one-plane tiles, plain order", 1, 1),
+              ("one-plane tiles, band per XCD", 1, 0), ("two-plane tiles, plain order", 2, 1),
+              ("two-plane tiles, band per XCD", 2, 0), ("z-march, 8 planes", 3, 8),
+              ("z-march, 16 planes", 3, 16), ("z-march, 32 planes", 3, 32), ("z-march, 64 planes", 3, 64)]
+
+
+def p2_designs_leg(s7, torch, dev, dims, reps: int = 10):
+    """The P2 pass (q = r - alpha s on the fly, y = A q, five sums) in the kernel designs of
+    s7_p2_design_probe, on the unit-diagonal operator of the seeded recipe at `dims` with
+    random r, s, r0: ms per launch (HIP events, average of `reps` after a warm-up) and the
+    algorithmic rate at 40 B per cell.  Every design must write the same y as the first."""
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    c = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(7)]
+    s7.generate_problem(dims, 0, 0, c, None, None)
+    w = []
+    for a in range(1, 7):
+        v = (c[a] / c[0]).view(nz, ny, nx)
+        # outward links zeroed on the faces: w, e, s, n, b, t
+        [lambda t: t[:, :, 0], lambda t: t[:, :, -1], lambda t: t[:, 0, :], lambda t: t[:, -1, :],
+         lambda t: t[0], lambda t: t[-1]][a - 1](v).zero_()
+        w.append(v.reshape(-1))
+    del c
+    g = torch.Generator(device=dev).manual_seed(7)
+    r = torch.rand(n, dtype=torch.float32, device=dev, generator=g) - 0.5
+    s = torch.rand(n, dtype=torch.float32, device=dev, generator=g) - 0.5
+    rh = torch.rand(n, dtype=torch.float32, device=dev, generator=g) - 0.5
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    y0 = None
+    rows = []
+    for name, kind, param in P2_DESIGNS:
+        ms, _ = s7.p2_design_probe(kind, param, dims, w, r, s, rh, 0.37, y, reps=reps)
+        torch.cuda.synchronize()
+        if y0 is None:
+            y0 = y.clone()
+        rows.append({"design": name, "kind": kind, "param": param, "ms": round(ms, 4),
+                     "GB/s_at_40B": round(40.0 * n / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_8TBs": round(40.0 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "y_same_as_first": bool(torch.equal(y, y0))})
+    return {"workload": f"P2 designs at {nx}x{ny}x{nz}, FP32, unit diagonal", "cells": n, "reps": reps,
+            "designs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1092,6 +1136,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run one dispatch of each streaming probe on 2 GiB arrays "
                          "(calibrates the HBM byte counters)")
+    ap.add_argument("--p2-designs", action="store_true",
+                    help="only time the P2 kernel designs of s7_p2_design_probe at --dims and print one JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="only measure the streaming ceilings (copy, triad, 6-read/2-write, read-only; "
                          "cached and non-temporal) and print them as JSON")
@@ -1108,6 +1154,9 @@ def main():
     s7.lib()
     dev = torch.device("cuda:0")
 
+    if args.p2_designs:
+        print(json.dumps(p2_designs_leg(s7, torch, dev, tuple(int(v) for v in args.dims.split(",")))), flush=True)
+        return
     if args.copy_probe or args.probe:
         print(json.dumps(probe_leg(s7, torch, dev, counters_only=args.copy_probe)), flush=True)
         return

@@ -442,6 +442,37 @@ int s7_bandwidth_probe(int32_t kind, int32_t width, float *a, float *b, float *c
                        int32_t blocks, void *stream);
 
 /*
+ * P2 design probe (diagnostic).  This is the three-pass iteration's P2 of
+ * Algorithm 1 (q = r - alpha s formed on the fly, y = A q, and the sums
+ * (q,y), (y,y), (q,q), (r0,q), (r0,y)) on the stencil of section IV
+ * ("SpMV (3D)").  It is written in the kernel designs that were measured
+ * against the one the solver uses:
+ *   kind 0: flat cell pairs, every neighbour of r and s loaded from memory;
+ *   kind 1: one-plane tiles of 2048 cells, q staged in LDS with one row on
+ *           either side and the z neighbours loaded from memory (the solver's
+ *           staged form); param 1 is plain tile order, 0 is band-per-XCD order;
+ *   kind 2: two-plane tiles (planes 2k and 2k+1 staged together, so the z
+ *           neighbour between them comes from LDS); param as for kind 1;
+ *   kind 3: z-march, in which a workgroup walks param planes of one 2048-cell
+ *           in-plane tile, with q of the planes below and above in registers
+ *           and the current plane in a double-buffered LDS ring.
+ * coef: the six off-diagonal coefficients {w, e, s, n, b, t} of the
+ * unit-diagonal (Jacobi-scaled) operator, with outward links zero on the faces.
+ * r, s, rhat: device inputs; y: device output (n floats).  Every design writes
+ * the same y bit for bit.  part: device buffer of at least
+ * s7_p2_design_part_bytes() bytes, which receives five FP64 sums per workgroup
+ * (their total is the five sums).
+ * Runs one warm-up launch, then reps timed launches with HIP events on
+ * `stream`.  *ms receives the average per launch.  The call waits for the
+ * launches.  Limits: nx a multiple of 8 and at most 1024; all float arrays
+ * 16-byte aligned.  Returns S7_EINVAL otherwise.
+ */
+size_t s7_p2_design_part_bytes(int32_t kind, int32_t param, s7_dims d);
+int s7_p2_design_probe(int32_t kind, int32_t param, s7_dims d, const float *const coef[6], const float *r,
+                       const float *s, const float *rhat, float alpha, float *y, double *part,
+                       size_t part_bytes, int32_t reps, float *ms, void *stream);
+
+/*
  * The 2D 9-point operator (section IV, "SpMV (2D)"; the paper sizes it at
  * 4800 x 4800 and 22800 x 22800 meshes).  On an nx x ny mesh, cell (i,j) is
  * element i + nx*j (x fastest) and

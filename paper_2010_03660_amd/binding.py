@@ -30,6 +30,7 @@ __all__ = [
     "batched_workspace_bytes_2d9", "bicgstab_solve_batched_2d9", "batched_call_2d9", "Request2D9", "queue_submit_2d9", "workspace_bytes_pipelined",
     "bicgstab_solve_pipelined", "bicgstab_solve_noalloc", "NOALLOC_WS_BYTES",
     "batched_workspace_bytes_pipelined", "bicgstab_solve_batched_pipelined", "batched_pipelined_call",
+    "p2_design_probe",
     "OK", "NOT_CONVERGED", "BREAKDOWN", "EINVAL", "ENOMEM", "EHIP", "EAGAIN", "ENOTFOUND",
     "REASON_NONE", "REASON_RHO_ZERO", "REASON_RS_ZERO", "REASON_YY_ZERO", "REASON_NONFINITE",
     "FP32", "BF16_IR", "FP16_IR", "PREC_NAMES", "LIB_PATH", "EXPORTS",
@@ -96,6 +97,9 @@ EXPORTS = {
                                                       C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                                       _vp, C.c_size_t, C.POINTER(Options), C.POINTER(Info),
                                                       _vp]),
+    "s7_p2_design_part_bytes": (C.c_size_t, [C.c_int32, C.c_int32, Dims]),
+    "s7_p2_design_probe": (C.c_int, [C.c_int32, C.c_int32, Dims, C.POINTER(_vp), _vp, _vp, _vp, C.c_float, _vp,
+                                     _vp, C.c_size_t, C.c_int32, C.POINTER(C.c_float), _vp]),
     "s7_bicgstab_solve_batched": (C.c_int, [C.c_int32, C.POINTER(Dims), C.POINTER(_vp),
                                             C.POINTER(_vp), C.POINTER(_vp),
                                             C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int32,
@@ -476,3 +480,22 @@ def bicgstab_solve_batched_pipelined(dims_list, coefs, bs, xs, rtols, max_iters,
     """Pipelined BiCGStab for len(dims_list) systems in one persistent launch (FP32).
     Returns (status, [Info])."""
     return batched_pipelined_call(dims_list, coefs, bs, xs, rtols, max_iters, ws, opt, stream)()
+
+
+def p2_design_probe(kind: int, param: int, dims, coef6, r, s, rhat, alpha: float, y, reps: int = 10,
+                    part=None, stream=None):
+    """Times one P2 kernel design (s7_p2_design_probe); returns (ms per launch, the five
+    sums as a list).  coef6: the unit-diagonal operator's six off-diagonal arrays."""
+    import torch
+    d = _dims(dims)
+    nbytes = int(lib().s7_p2_design_part_bytes(int(kind), int(param), d))
+    if part is None:
+        part = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=r.device)
+    ms = C.c_float()
+    cp = (_vp * 6)(*[_ptr(c) for c in coef6])
+    rc = lib().s7_p2_design_probe(int(kind), int(param), d, cp, _ptr(r), _ptr(s), _ptr(rhat), float(alpha),
+                                  _ptr(y), _ptr(part), part.numel() * part.element_size(), int(reps),
+                                  C.byref(ms), _stream(stream))
+    _check(rc, allow=(OK,))
+    sums = part[: nbytes // 8].view(-1, 5).sum(dim=0).tolist()
+    return ms.value, sums

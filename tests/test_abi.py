@@ -222,3 +222,27 @@ def test_host_side_argument_checks_batched_pipelined():
     assert call(mi_=(C.c_int32 * 2)(10, -1)) == B.EINVAL and "system 1" in B.last_error()
     assert call(wsb=16) == B.EINVAL and "workspace" in B.last_error()
     assert call(ws=4100) == B.EINVAL  # not 256-byte aligned
+
+
+def test_host_side_argument_checks_p2_designs():
+    """The P2 design probe rejects unknown designs and unsupported meshes on the host."""
+    from paper_2010_03660_amd import binding as B
+    lib = B.lib()
+    d = B.Dims(64, 48, 20)
+    assert lib.s7_p2_design_part_bytes(0, 0, d) == ((64 * 48 * 20 // 2 + 255) // 256) * 5 * 8
+    assert lib.s7_p2_design_part_bytes(3, 8, d) == 2 * 3 * 5 * 8  # two in-plane tiles, three z-blocks
+    assert lib.s7_p2_design_part_bytes(9, 0, d) == 0
+    assert lib.s7_p2_design_part_bytes(0, 0, B.Dims(0, 4, 4)) == 0
+    coef = (C.c_void_p * 6)(*([256] * 6))
+    ms = C.c_float()
+
+    def call(kind, param, dims=d, part_bytes=1 << 30, reps=1):
+        return lib.s7_p2_design_probe(kind, param, dims, coef, 512, 768, 1024, 0.5, 1280, 1536, part_bytes, reps,
+                                      C.byref(ms), 0)
+    assert call(4, 0) == B.EINVAL
+    assert call(3, 0) == B.EINVAL          # z-march depth must be >= 1
+    assert call(1, 2) == B.EINVAL          # tile order: 0 or 1
+    assert call(0, 0, dims=B.Dims(36, 8, 4)) == B.EINVAL   # nx not a multiple of 8
+    assert call(0, 0, dims=B.Dims(1032, 8, 4)) == B.EINVAL  # nx above 1024
+    assert call(0, 0, part_bytes=8) == B.EINVAL and "partial" in B.last_error()
+    assert call(0, 0, reps=0) == B.EINVAL
