@@ -725,6 +725,8 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
         PState* const pst = reinterpret_cast<PState*>(S.st);
         const int chunk = __builtin_amdgcn_readfirstlane(sh_chunk);
         const uint32_t seq = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh_seq);
+        // resident (as in k_batched): the control block's current copy is sh_p
+        const bool res = __builtin_amdgcn_readfirstlane(sh_direct) != 0;
         const int kind = (int)(seq & 15u);
         const int c0 = chunk * B.chunk;
         const int c1 = min(S.n, c0 + B.chunk);
@@ -736,8 +738,8 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
         } else if (kind == PK_R) {
             pover_units<1, 0, 0u>(c0, c1, part, [&](int u0, int u1, double (&)[1]) { pchunk_r(B, u0, u1); });
         } else if (kind == PK_X) {
-            const double scale = cload_d(&S.st->scale);
-            const bool zero = cload_i(&S.st->xzero) != 0;
+            const double scale = res ? sh_p.st.scale : cload_d(&S.st->scale);
+            const bool zero = (res ? sh_p.st.xzero : cload_i(&S.st->xzero)) != 0;
             pover_units<1, 0, 0u>(c0, c1, part, [&](int u0, int u1, double (&)[1]) {
                 chunk_x_b(S, B.x, u0, u1, scale, zero);
             });
@@ -747,12 +749,12 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
             });
         } else {
             // the scalars and copy indices this phase reads, set by the last completion
-            const int zb = __builtin_amdgcn_readfirstlane(cload_i(&pst->zb));
-            const int tb = __builtin_amdgcn_readfirstlane(cload_i(&pst->tb));
-            const int flag = __builtin_amdgcn_readfirstlane(cload_i(&pst->ps.flag));
-            const float alpha = (float)cload_d(&S.st->alpha);
-            const float beta = (float)cload_d(&S.st->beta);
-            const float omega = (float)cload_d(&S.st->omega);
+            const int zb = __builtin_amdgcn_readfirstlane(res ? sh_p.zb : cload_i(&pst->zb));
+            const int tb = __builtin_amdgcn_readfirstlane(res ? sh_p.tb : cload_i(&pst->tb));
+            const int flag = __builtin_amdgcn_readfirstlane(res ? sh_p.ps.flag : cload_i(&pst->ps.flag));
+            const float alpha = (float)(res ? sh_p.st.alpha : cload_d(&S.st->alpha));
+            const float beta = (float)(res ? sh_p.st.beta : cload_d(&S.st->beta));
+            const float omega = (float)(res ? sh_p.st.omega : cload_d(&S.st->omega));
             if (S.unit) prun_chunk<true>(B, kind, c0, c1, zb, tb, alpha, beta, omega, flag, sh_stage);
             else prun_chunk<false>(B, kind, c0, c1, zb, tb, alpha, beta, omega, flag, sh_stage);
         }
@@ -772,25 +774,30 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
         }
         __syncthreads();
         if (!sh_last) continue;
-        // this workgroup completes the phase
-        const uint32_t pw = pstate_fetch(pst);
+        // this workgroup completes the phase (a resident system's LDS copy is current)
+        const uint32_t pw = res ? 0u : pstate_fetch(pst);
         const int nunit = (S.n + kUnitCells - 1) / kUnitCells;
         double tot[kPD] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (kind == PK_A) psum_units<10, 0u>(part, nunit, tot);
         else if (kind == PK_V) psum_units<5, 0u>(part, nunit, tot);
         else if (kind == PK_S) psum_units<3, 0u>(part, nunit, tot);
         else if (kind == PK_RF) psum_units<3, 4u>(part, nunit, tot);
-        pstate_put(pw, sh_p);
+        if (!res) pstate_put(pw, sh_p);
+        else __syncthreads();
         if (threadIdx.x == 0) {
             const int next = pipe_complete(sh_p, kind, tot);
             sh_stop = next == PK_FINAL ? 1 : 0;
             sh_nseq = pseq_next(seq, next == PK_FINAL ? PK_A : next);
         }
         __syncthreads();
-        pstate_store(pst, sh_p);
-        __syncthreads();  // every word of the control block has reached memory
+        // a system that goes on resident keeps its control block in LDS only
+        const bool stay = !sh_stop && B.nchunk == 1;
+        if (!stay) {
+            pstate_store(pst, sh_p);
+            __syncthreads();  // every word of the control block has reached memory
+        }
         if (threadIdx.x == 0) {
-            __hip_atomic_store(gbl(&B.ctl->done_cnt), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!stay) __hip_atomic_store(gbl(&B.ctl->done_cnt), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t nseq = sh_nseq;
             if (sh_stop) {
                 cstore_i(&B.ctl->active, 0);
@@ -798,11 +805,13 @@ __global__ __launch_bounds__(kThreads) void k_batched_pipe(const PSys* __restric
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 wait_stores();
                 __hip_atomic_fetch_add(&glob->active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else if (B.nchunk == 1) {
-                // the next phase's only chunk is taken here (as in k_batched)
-                wait_stores();
-                __hip_atomic_store(gbl(&B.ctl->claim), ((unsigned long long)nseq << 32) | 1ull, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            } else if (stay) {
+                // the next phase's only chunk is taken here (as in k_batched); the
+                // claim word, published on the way in with its counter exhausted,
+                // is not written again until the system stops
+                if (!res)
+                    __hip_atomic_store(gbl(&B.ctl->claim), ((unsigned long long)nseq << 32) | 1ull,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 sh_sys = me;
                 sh_chunk = 0;
                 sh_seq = nseq;
